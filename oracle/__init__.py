@@ -1,0 +1,237 @@
+"""CPU oracle for the direct-SCF J/K build and its nuclear gradient.
+
+TEST INFRASTRUCTURE ONLY: imported by tests/, by the smoke check and by the
+CPU-baseline leg of bench.py.  The GPU library never imports it and it never
+imports the GPU library.  See oracle.c for the equations it follows.
+
+Parity status per function (what pins it is listed in tests/test_oracle_*.py):
+  boys          pinned (mpmath 1F1 values, closed forms)
+  e_coeffs      pinned (1D overlap by exact Gauss-Hermite quadrature)
+  r_tensor      pinned (numerical derivatives of (-2a)^m F_m(a|L|^2))
+  prim_block    pinned ((ss|ss) closed form, brute-force Gaussian-transform
+                quadrature for l <= 3 on four centres, 8-fold symmetry)
+  jk / blocks   pinned (symmetry, Coulomb-metric positivity, translation and
+                rotation invariance, large-separation limit)
+  grad          pinned (central finite differences of the oracle energy,
+                zero sum over atoms, analytic two-centre derivative)
+  spherical     convention pinned by S_sph = I and rotation invariance
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from typing import Sequence, Tuple
+
+import numpy as np
+
+from . import basis as _basis
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SO = os.path.join(_HERE, "_oracle.so")
+_SRC = os.path.join(_HERE, "oracle.c")
+
+
+def build(force: bool = False) -> str:
+    """Compile oracle.c with gcc (plain -O2, OpenMP, no fast-math)."""
+    if force or not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(_SRC):
+        tmp = _SO + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", _SRC,
+                               "-o", tmp, "-lm"])
+        os.replace(tmp, _SO)
+    return _SO
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build()
+        L = ctypes.CDLL(_SO)
+        dp = ctypes.POINTER(ctypes.c_double)
+        ip = ctypes.POINTER(ctypes.c_int32)
+        L.oracle_boys.argtypes = [ctypes.c_int, ctypes.c_double, dp]
+        L.oracle_e_coeffs.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                      ctypes.c_double, ctypes.c_double, dp]
+        L.oracle_r_tensor.argtypes = [ctypes.c_int, ctypes.c_double, dp, dp]
+        L.oracle_prim_block.argtypes = [ctypes.c_int] * 4 + [dp, dp, dp]
+        bas = [ctypes.c_int32, ctypes.c_int32, ip, ip, ip, ip, dp, dp, dp]
+        L.oracle_shell_block.argtypes = bas + [ctypes.c_int] * 6 + [dp]
+        L.oracle_schwarz.argtypes = bas + [dp]
+        L.oracle_jk.argtypes = bas + [dp, ip, ip, ctypes.c_int32, dp, dp, ctypes.c_double,
+                                      ctypes.c_int, ctypes.c_int, dp, dp]
+        L.oracle_jk_blocks.argtypes = bas + [dp, ip, ip, ctypes.c_int32, dp, dp, ctypes.c_double,
+                                             ctypes.c_int, ip, ctypes.c_int, ip,
+                                             ctypes.POINTER(ctypes.c_int64), dp]
+        L.oracle_grad.argtypes = bas + [dp, ip, ip, ctypes.c_int32, dp, dp, ctypes.c_double,
+                                        ctypes.c_double, ctypes.c_double, ctypes.c_int, dp]
+        L.oracle_num_threads.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _dp(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _ip(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+
+
+# ---------------------------------------------------------------------------
+# primitives exposed for the pins
+# ---------------------------------------------------------------------------
+def boys(mmax: int, T: float) -> np.ndarray:
+    F = np.zeros(mmax + 1)
+    lib().oracle_boys(mmax, float(T), _dp(F))
+    return F
+
+
+def e_coeffs(la, lb, a, b, Ax, Bx) -> np.ndarray:
+    out = np.zeros((la + 1) * (lb + 1) * (la + lb + 1))
+    lib().oracle_e_coeffs(la, lb, a, b, Ax, Bx, _dp(out))
+    return out.reshape(la + 1, lb + 1, la + lb + 1)
+
+
+def r_tensor(Lt: int, alpha: float, L) -> np.ndarray:
+    n = Lt + 1
+    out = np.zeros(n ** 3)
+    Lv = np.ascontiguousarray(L, dtype=float)
+    lib().oracle_r_tensor(Lt, alpha, _dp(Lv), _dp(out))
+    return out.reshape(n, n, n)
+
+
+def prim_block(ls, exps, centres) -> np.ndarray:
+    """Primitive Cartesian ERI block of unnormalised monomials."""
+    la, lb, lc, ld = ls
+    nc = [(l + 1) * (l + 2) // 2 for l in ls]
+    out = np.zeros(int(np.prod(nc)))
+    e = np.ascontiguousarray(exps, float)
+    c = np.ascontiguousarray(centres, float).reshape(12)
+    lib().oracle_prim_block(la, lb, lc, ld, _dp(e), _dp(c), _dp(out))
+    return out.reshape(nc)
+
+
+# ---------------------------------------------------------------------------
+# basis marshalling
+# ---------------------------------------------------------------------------
+class OBasis:
+    """Flat arrays of one molecule for the C oracle."""
+
+    def __init__(self, mol):
+        self.mol = mol
+        sh = mol.shells
+        self.nshell = len(sh)
+        self.natom = mol.natom
+        self.atom = np.array([s.atom for s in sh], np.int32)
+        self.l = np.array([s.l for s in sh], np.int32)
+        self.nprim = np.array([len(s.exps) for s in sh], np.int32)
+        self.off = np.concatenate([[0], np.cumsum(self.nprim)[:-1]]).astype(np.int32)
+        self.exps = np.concatenate([np.asarray(s.exps, float) for s in sh])
+        self.coefs = np.concatenate([_basis.normalised_coefs(s.l, s.exps, s.coefs) for s in sh])
+        self.xyz = np.ascontiguousarray(mol.xyz, float).reshape(-1)
+        self.ao_off = np.concatenate([[0], np.cumsum(2 * self.l + 1)[:-1]]).astype(np.int32)
+        self.nbf = int(np.sum(2 * self.l + 1))
+        Ts, offs, o = [], [], 0
+        for lv in range(5):
+            T = _basis.SPH[lv]
+            Ts.append(T.reshape(-1))
+            offs.append(o)
+            o += T.size
+        self.T = np.concatenate(Ts)
+        self.Toff = np.array(offs, np.int32)
+        self._Q = None
+
+    def args(self):
+        return (self.nshell, self.natom, _ip(self.atom), _ip(self.l), _ip(self.nprim),
+                _ip(self.off), _dp(self.exps), _dp(self.coefs), _dp(self.xyz))
+
+    def shell_block(self, a, b, c, d, dcen=-1, dax=0) -> np.ndarray:
+        ls = [int(self.l[x]) for x in (a, b, c, d)]
+        nc = [(l + 1) * (l + 2) // 2 for l in ls]
+        out = np.zeros(int(np.prod(nc)))
+        lib().oracle_shell_block(*self.args(), a, b, c, d, dcen, dax, _dp(out))
+        return out.reshape(nc)
+
+    def shell_block_sph(self, a, b, c, d) -> np.ndarray:
+        blk = self.shell_block(a, b, c, d)
+        for k, x in enumerate((a, b, c, d)):
+            T = _basis.SPH[int(self.l[x])]
+            blk = np.moveaxis(np.tensordot(T, blk, axes=([1], [k])), 0, k)
+        return blk
+
+    def schwarz(self) -> np.ndarray:
+        if self._Q is None:
+            Q = np.zeros((self.nshell, self.nshell))
+            lib().oracle_schwarz(*self.args(), _dp(Q))
+            self._Q = Q
+        return self._Q
+
+
+def _sym(P):
+    P = np.ascontiguousarray(P, float)
+    return np.ascontiguousarray(0.5 * (P + P.T))
+
+
+def jk(mol, P=None, tau=None, want_j=True, want_k=True) -> Tuple[np.ndarray, np.ndarray]:
+    """Full J and K (spherical basis) by the plain definition."""
+    B = OBasis(mol)
+    P = _sym(mol.P if P is None else P)
+    tau = mol.tau_schwarz if tau is None else tau
+    Q = B.schwarz()
+    J = np.zeros((B.nbf, B.nbf))
+    K = np.zeros((B.nbf, B.nbf))
+    lib().oracle_jk(*B.args(), _dp(B.T), _ip(B.Toff), _ip(B.ao_off), B.nbf, _dp(P), _dp(Q),
+                    float(tau), int(want_j), int(want_k), _dp(J), _dp(K))
+    return J, K
+
+
+def jk_blocks(mol, jpairs: Sequence[Tuple[int, int]], kpairs: Sequence[Tuple[int, int]],
+              P=None, tau=None, basis_obj=None):
+    """Shell blocks J[a,b] and K[a,c] for sampled shell pairs."""
+    B = basis_obj or OBasis(mol)
+    P = _sym(mol.P if P is None else P)
+    tau = mol.tau_schwarz if tau is None else tau
+    Q = B.schwarz()
+    jp = np.ascontiguousarray(np.asarray(jpairs, np.int32).reshape(-1, 2))
+    kp = np.ascontiguousarray(np.asarray(kpairs, np.int32).reshape(-1, 2))
+    sizes = [(2 * B.l[x] + 1) * (2 * B.l[y] + 1) for x, y in list(jp) + list(kp)]
+    offs = np.concatenate([[0], np.cumsum(sizes)[:-1]]).astype(np.int64) if sizes else np.zeros(0, np.int64)
+    out = np.zeros(int(sum(sizes)) if sizes else 1)
+    lib().oracle_jk_blocks(*B.args(), _dp(B.T), _ip(B.Toff), _ip(B.ao_off), B.nbf, _dp(P), _dp(Q),
+                           float(tau), len(jp), _ip(jp), len(kp), _ip(kp),
+                           offs.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), _dp(out))
+    res = []
+    for t, (x, y) in enumerate(list(jp) + list(kp)):
+        nx, ny = 2 * B.l[x] + 1, 2 * B.l[y] + 1
+        res.append(out[offs[t]:offs[t] + nx * ny].reshape(nx, ny))
+    return res[:len(jp)], res[len(jp):]
+
+
+def energy(mol, J, K, P=None) -> float:
+    """E = 1/2 tr(PJ) - 1/4 tr(PK)  (SI eq. si_E_J_K)."""
+    P = _sym(mol.P if P is None else P)
+    return 0.5 * float(np.sum(P * J)) - 0.25 * float(np.sum(P * K))
+
+
+def grad(mol, P=None, tau=None, wj=1.0, wk=1.0, only_atom=-1, Q=None) -> np.ndarray:
+    """dE/dR (natom x 3) of E = wj/2 tr(PJ) - wk/4 tr(PK) at fixed P."""
+    B = OBasis(mol)
+    P = _sym(mol.P if P is None else P)
+    tau = mol.tau_schwarz if tau is None else tau
+    Q = B.schwarz() if Q is None else np.ascontiguousarray(Q, float)
+    g = np.zeros((B.natom, 3))
+    lib().oracle_grad(*B.args(), _dp(B.T), _ip(B.Toff), _ip(B.ao_off), B.nbf, _dp(P), _dp(Q),
+                      float(tau), float(wj), float(wk), int(only_atom), _dp(g))
+    return g
+
+
+def num_threads() -> int:
+    return int(lib().oracle_num_threads())
+
+
+sph_matrix = _basis.sph_matrix
+normalised_coefs = _basis.normalised_coefs
+cart_list = _basis.cart_list

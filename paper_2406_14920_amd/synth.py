@@ -1,0 +1,208 @@
+"""Seeded synthetic molecules and densities for the J/K workloads.
+
+This module only draws random numbers: atom positions, shell exponents, raw
+contraction coefficients and a random orthonormal orbital block.  It holds
+none of the integral arithmetic (no normalisation, no integrals, no screening),
+so both the CPU oracle (through the tests) and the GPU library can take their
+inputs from it without sharing any part of the method.
+
+The paper's molecules (alkanes, taxol, metal complexes with cc-pVxZ/def2 bases,
+section "Performance") are not available; these draws stand in for them with
+the same ingredients: contracted Cartesian Gaussian shells up to f on atoms at
+bonding distances (eq. contracted_basis / primtive_basis).
+
+Workloads (the recipe is spelled out in the design doc):
+  mol4    4 atoms in a 6 bohr cube, shells s3 s1 p3 p1 d1 f1            (80 sph)
+  mol40   40-atom grown cluster, shells s6 s3 s1 p3 p1 d1 f1            (840 sph)
+  tm62    2 heavy centres + 60 light atoms                              (1336 sph)
+  mol20   20-atom grown cluster (gradient workload)                      (420 sph)
+  batch64 64 grown clusters of 5..30 atoms (serving-style batch)
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from typing import List, Sequence, Tuple
+
+import numpy as np
+
+# (l, nprim) per shell
+LIGHT4_SHELLS: Tuple[Tuple[int, int], ...] = ((0, 3), (0, 1), (1, 3), (1, 1), (2, 1), (3, 1))
+LIGHT_SHELLS: Tuple[Tuple[int, int], ...] = ((0, 6), (0, 3), (0, 1), (1, 3), (1, 1), (2, 1), (3, 1))
+HEAVY_SHELLS: Tuple[Tuple[int, int], ...] = (
+    (0, 8), (0, 8), (0, 8), (1, 6), (1, 6), (2, 5), (2, 5), (2, 5), (3, 1), (3, 1))
+
+
+@dataclass
+class Shell:
+    atom: int
+    l: int
+    exps: np.ndarray    # [nprim], descending
+    coefs: np.ndarray   # [nprim], raw coefficients of normalised primitives
+
+
+@dataclass
+class Molecule:
+    name: str
+    xyz: np.ndarray                 # [natom, 3] bohr
+    shells: List[Shell]
+    P: np.ndarray                   # [nbf, nbf] symmetric density in the spherical AO basis
+    nocc: int
+    tau_schwarz: float
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def natom(self) -> int:
+        return int(self.xyz.shape[0])
+
+    @property
+    def nbf(self) -> int:
+        return int(sum(2 * s.l + 1 for s in self.shells))
+
+
+def nsph(l: int) -> int:
+    return 2 * l + 1
+
+
+def _unit(rng: np.random.Generator) -> np.ndarray:
+    v = rng.standard_normal(3)
+    return v / np.linalg.norm(v)
+
+
+def _box_positions(rng, natom, box, min_sep):
+    while True:
+        x = rng.uniform(0.0, box, size=(natom, 3))
+        d = np.linalg.norm(x[:, None, :] - x[None, :, :], axis=-1)
+        d[np.diag_indices(natom)] = np.inf
+        if d.min() >= min_sep:
+            return x
+
+
+def _grow_cluster(rng, natom, dmin=2.6, dmax=3.0, seed_xyz=None, heavy=0,
+                  heavy_dmin=3.5, heavy_dmax=3.9):
+    """Grow a cluster: each new atom is placed at distance U(dmin, dmax) from a
+    randomly chosen existing atom in a random direction and accepted if it is at
+    least dmin from every light atom and heavy_dmin from every heavy atom.
+    The first `heavy` atoms of seed_xyz are heavy centres."""
+    xyz = [np.zeros(3)] if seed_xyz is None else [np.asarray(p, float) for p in seed_xyz]
+    while len(xyz) < natom:
+        parent = int(rng.integers(len(xyz)))
+        if parent < heavy:
+            d = rng.uniform(heavy_dmin, heavy_dmax)
+        else:
+            d = rng.uniform(dmin, dmax)
+        cand = xyz[parent] + d * _unit(rng)
+        arr = np.asarray(xyz)
+        dist = np.linalg.norm(arr - cand, axis=1)
+        ok_heavy = bool(np.all(dist[:heavy] >= heavy_dmin)) if heavy else True
+        ok_light = bool(np.all(dist[heavy:] >= dmin - 1e-12))
+        if ok_heavy and ok_light:
+            xyz.append(cand)
+    return np.asarray(xyz)
+
+
+def _draw_shells(rng, atoms_shellsets: Sequence[Tuple[Tuple[int, int], ...]],
+                 ranges: Sequence[Tuple[float, float]]) -> List[Shell]:
+    """Exponents log-uniform in the atom's range (sorted descending within a
+    shell), then coefficients U(0.1, 1); exponents of all shells first."""
+    exps_all = []
+    for ia, (sset, (lo, hi)) in enumerate(zip(atoms_shellsets, ranges)):
+        for (l, n) in sset:
+            e = np.exp(rng.uniform(np.log(lo), np.log(hi), size=n))
+            exps_all.append((ia, l, np.sort(e)[::-1].copy()))
+    shells = []
+    for (ia, l, e) in exps_all:
+        c = rng.uniform(0.1, 1.0, size=e.size)
+        shells.append(Shell(atom=ia, l=l, exps=e, coefs=c))
+    return shells
+
+
+def _density(rng, nbf: int, nocc: int) -> np.ndarray:
+    """P = C C^T with C a random Euclidean-orthonormal nbf x nocc block."""
+    a = rng.standard_normal((nbf, nocc))
+    q, _ = np.linalg.qr(a)
+    P = q @ q.T
+    return 0.5 * (P + P.T)
+
+
+def _finish(name, rng, xyz, shells, tau, nocc=None, meta=None) -> Molecule:
+    nbf = int(sum(nsph(s.l) for s in shells))
+    if nocc is None:
+        nocc = max(1, int(round(nbf / 10)))
+    P = _density(rng, nbf, nocc)
+    return Molecule(name=name, xyz=xyz, shells=shells, P=P, nocc=nocc,
+                    tau_schwarz=tau, meta=dict(meta or {}))
+
+
+def mol4(seed: int = 14921) -> Molecule:
+    rng = np.random.default_rng(seed)
+    xyz = _box_positions(rng, 4, 6.0, 2.0)
+    shells = _draw_shells(rng, [LIGHT4_SHELLS] * 4, [(0.1, 1e3)] * 4)
+    return _finish("mol4", rng, xyz, shells, 1e-12, nocc=10)
+
+
+def cluster(natom: int, seed, name: str = "cluster", tau: float = 1e-11,
+            exp_range=(0.08, 5e3)) -> Molecule:
+    rng = np.random.default_rng(seed)
+    xyz = _grow_cluster(rng, natom)
+    shells = _draw_shells(rng, [LIGHT_SHELLS] * natom, [exp_range] * natom)
+    return _finish(name, rng, xyz, shells, tau)
+
+
+def mol40(seed: int = 14922) -> Molecule:
+    return cluster(40, seed, "mol40")
+
+
+def tm62(seed: int = 14923) -> Molecule:
+    rng = np.random.default_rng(seed)
+    heavy = [np.array([-2.4, 0.0, 0.0]), np.array([2.4, 0.0, 0.0])]
+    xyz = _grow_cluster(rng, 62, seed_xyz=heavy, heavy=2)
+    sets = [HEAVY_SHELLS] * 2 + [LIGHT_SHELLS] * 60
+    ranges = [(0.05, 2e5)] * 2 + [(0.08, 5e3)] * 60
+    shells = _draw_shells(rng, sets, ranges)
+    return _finish("tm62", rng, xyz, shells, 1e-11)
+
+
+def mol20(seed: int = 14924) -> Molecule:
+    return cluster(20, seed, "mol20")
+
+
+def batch64(seed: int = 14925, n: int = 64, lo: int = 5, hi: int = 30) -> List[Molecule]:
+    children = np.random.SeedSequence(seed).spawn(n)
+    mols = []
+    for i, ss in enumerate(children):
+        rng = np.random.default_rng(ss)
+        natom = int(rng.integers(lo, hi + 1))
+        xyz = _grow_cluster(rng, natom)
+        shells = _draw_shells(rng, [LIGHT_SHELLS] * natom, [(0.08, 5e3)] * natom)
+        mols.append(_finish(f"batch64[{i}]", rng, xyz, shells, 1e-11))
+    return mols
+
+
+def small_cluster(natom: int, seed: int, shellset=LIGHT_SHELLS, exp_range=(0.08, 5e3),
+                  tau: float = 1e-11, name: str = "small") -> Molecule:
+    """A grown cluster with a chosen shell set (parity tests)."""
+    rng = np.random.default_rng(seed)
+    xyz = _grow_cluster(rng, natom)
+    shells = _draw_shells(rng, [tuple(shellset)] * natom, [exp_range] * natom)
+    return _finish(name, rng, xyz, shells, tau)
+
+
+def custom(xyz, shell_specs, seed: int = 0, tau: float = 1e-12, nocc=None,
+           exp_range=(0.1, 10.0), name: str = "custom") -> Molecule:
+    """Molecule from explicit positions and (atom, l, nprim) shell specs; the
+    exponents/coefficients/density are drawn from `seed`."""
+    rng = np.random.default_rng(seed)
+    xyz = np.asarray(xyz, float).reshape(-1, 3)
+    exps_all = []
+    for (ia, l, n) in shell_specs:
+        e = np.exp(rng.uniform(np.log(exp_range[0]), np.log(exp_range[1]), size=n))
+        exps_all.append((ia, l, np.sort(e)[::-1].copy()))
+    shells = [Shell(atom=ia, l=l, exps=e, coefs=rng.uniform(0.1, 1.0, size=e.size))
+              for (ia, l, e) in exps_all]
+    nbf = int(sum(nsph(s.l) for s in shells))
+    if nocc is None:
+        nocc = max(1, nbf // 4)
+    return _finish(name, rng, xyz, shells, tau, nocc=nocc)
+
+
+WORKLOADS = {"mol4": mol4, "mol40": mol40, "tm62": tm62, "mol20": mol20}
