@@ -1,0 +1,148 @@
+/*
+ * mdjk.h -- C ABI of an MI355X (gfx950) library for direct-SCF Coulomb (J) and
+ * exchange (K) matrices and the nuclear gradient of the J/K energy, computed
+ * from contracted Gaussian electron repulsion integrals over shells up to f
+ * (l <= 3) by the McMurchie-Davidson scheme.
+ *
+ * The operations are the ones stated in arXiv 2406.14920 (Wang et al.,
+ * "Extending GPU-accelerated Gaussian integrals in the TeraChem software
+ * package to f type orbitals"):
+ *   basis functions         section "Cartesian Gaussian basis functions",
+ *                           eqs. contracted_basis, primtive_basis
+ *   ERIs                    eqs. eri_definition, eri_formula
+ *   J (J-engine)            eqs. j_definition, j_formula
+ *   K                       eqs. k_definition, k_formula
+ *   screening               eq. cauchy_schwarz_bound (pair and quartet level)
+ *   energy and gradient     SI eqs. si_E_J_K, si_dE_J, si_dE_K, si_dE_J_step1,
+ *                           si_dE_K_step1 (density held fixed)
+ *
+ * Conventions
+ *   - Units: bohr, hartree.
+ *   - Shell coefficients multiply normalised primitives; each contracted
+ *     shell is renormalised so that its x^l component has unit norm.
+ *   - AO order: shells in the order given to eri_setup.  Inside a shell,
+ *     spherical=1 (default): real solid harmonics m = -l..l, except p which is
+ *     (x, y, z); spherical=0: Cartesian components in lexicographic order
+ *     (xx, xy, xz, yy, yz, zz; xxx, xxy, ... , zzz), all carrying the x^l
+ *     normalisation.
+ *   - Matrices are nbf x nbf, row-major, FP64, in DEVICE memory (for example
+ *     the data_ptr() of a torch tensor on the GPU).
+ *   - P is read as given and used as (P + P^T)/2.  J and K are returned
+ *     symmetric.  E = 1/2 tr(PJ) - 1/4 tr(PK).
+ *   - Screening is part of the result's definition: a shell quartet (ab|cd)
+ *     enters iff Q_ab * Q_cd >= schwarz_thresh with
+ *     Q_ab = sqrt(max over Cartesian components of |(ab|ab)|); inside it a
+ *     primitive quartet enters iff q_ij * q_kl >= prim_thresh, q_ij being the
+ *     same bound for one primitive pair (with its coefficients).
+ *
+ * Calls are stream-ordered and asynchronous on opts.stream (a hipStream_t;
+ * NULL = the default stream) unless stated otherwise.  The library owns every
+ * device buffer it allocates (released by eri_destroy); it never keeps caller
+ * pointers after a call returns.  A context is not thread-safe; distinct
+ * contexts may be used from distinct threads on distinct streams.
+ *
+ * Errors: every call returns 0 on success or a negative ERI_E* code; the
+ * message of the last failure on the calling thread is in eri_last_error().
+ */
+#ifndef MDJK_H
+#define MDJK_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ERI_OK      0
+#define ERI_EINVAL (-1) /* bad argument: null pointer, l outside 0..3, nprim < 1,
+                           exponent <= 0 or not finite, atom index out of range,
+                           negative threshold, unknown precision */
+#define ERI_ENOMEM (-2) /* device or host allocation failed */
+#define ERI_EHIP   (-3) /* HIP runtime error; the message carries hipGetErrorString */
+#define ERI_ESTATE (-4) /* null/destroyed context or an inconsistent request */
+
+#define ERI_FP64  0
+#define ERI_MIXED 1
+
+typedef struct eri_ctx eri_ctx;
+
+typedef struct {
+    double xyz[3]; /* bohr */
+} eri_atom;
+
+typedef struct {
+    int32_t atom;        /* index into the atoms array */
+    int32_t l;           /* 0..3 */
+    int32_t nprim;       /* >= 1 */
+    const double *exps;  /* [nprim], > 0 (host memory, copied by eri_setup) */
+    const double *coefs; /* [nprim], coefficients of normalised primitives */
+} eri_shell;
+
+typedef struct {
+    double schwarz_thresh; /* shell-quartet threshold tau_S (>= 0) */
+    double prim_thresh;    /* primitive-quartet threshold (>= 0); 0 keeps every
+                              primitive of a kept shell quartet */
+    double mixed_thresh;   /* ERI_MIXED: quartets with Q_ab*Q_cd*max|P| below this
+                              run their primitive integrals in FP32 (>= 0) */
+    int32_t precision;     /* ERI_FP64 or ERI_MIXED */
+    int32_t spherical;     /* 1: real solid harmonics (default); 0: Cartesian */
+    void *stream;          /* hipStream_t, NULL = default stream */
+} eri_opts;
+
+typedef struct {
+    int32_t nshell, natom, nbf, nbf_cart;
+    int64_t n_pairs;             /* contracted shell pairs kept (Q_ab > 0) */
+    int64_t n_prim_pairs;        /* primitive pairs stored */
+    int64_t n_quartets;          /* unique shell quartets passing the Schwarz rule */
+    int64_t n_quartets_fp32;     /* of which run in FP32 (ERI_MIXED, last build_jk) */
+    double  eris_sph;            /* sum over kept unique quartets of prod (2l+1) */
+    double  eris_cart;           /* same with Cartesian component counts */
+    double  model_flops_k;       /* model FLOPs of one K build (unique quartets) */
+    double  model_flops_j;       /* model FLOPs of one J build (J-engine) */
+    double  last_ms;             /* device time of the last build_jk / jk_grad (ms) */
+} eri_stats_t;
+
+/* Fill opts with defaults: schwarz 1e-11, prim 1e-2*schwarz, mixed 1e-5,
+ * FP64, spherical, default stream. */
+void eri_default_opts(eri_opts *opts);
+
+/* Build a context: normalise shells, form contracted and primitive shell pairs
+ * (eq. pair_definition), compute Schwarz factors on the GPU, sort and bin the
+ * pairs into the ten angular classes and allocate every device buffer later
+ * calls need.  shells/atoms are host arrays, copied.  Synchronous.
+ * On failure *out is set to NULL. */
+int eri_setup(const eri_shell *shells, int32_t nshell, const eri_atom *atoms, int32_t natom,
+              const eri_opts *opts, eri_ctx **out);
+
+/* Number of basis functions (spherical or Cartesian, per opts.spherical). */
+int eri_nbf(const eri_ctx *ctx, int32_t *nbf);
+
+/* Move the atoms (same shells) and redo the pair/Schwarz setup.  Synchronous. */
+int eri_set_geometry(eri_ctx *ctx, const eri_atom *atoms);
+
+/* Change the precision mode (ERI_FP64 / ERI_MIXED) and mixed threshold. */
+int eri_set_precision(eri_ctx *ctx, int32_t precision, double mixed_thresh);
+
+/* J_mn = sum_ls (mn|ls) P_ls (J-engine, eq. j_formula) and
+ * K_ml = sum_ns (mn|ls) P_ns (eq. k_formula).  P, J, K: device, nbf*nbf
+ * row-major FP64.  J or K may be NULL to skip it.  Asynchronous. */
+int build_jk(eri_ctx *ctx, const double *P, double *J, double *K);
+
+/* Nuclear gradient dE/dR of E = 1/2 tr(PJ) - 1/4 tr(PK) at fixed P
+ * (SI eqs. si_dE_J, si_dE_K; the density-derivative terms are absent).
+ * grad: device [natom*3]; E: device [1] or NULL.  Asynchronous. */
+int jk_grad(eri_ctx *ctx, const double *P, double *grad, double *E);
+
+/* Counters of the context (host struct).  Synchronises the stream. */
+int eri_stats(const eri_ctx *ctx, eri_stats_t *out);
+
+/* Release the context and all its device memory.  NULL is accepted. */
+int eri_destroy(eri_ctx *ctx);
+
+/* Message of the last error on this thread ("" if none). */
+const char *eri_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MDJK_H */

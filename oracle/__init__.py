@@ -60,12 +60,14 @@ def lib():
         bas = [ctypes.c_int32, ctypes.c_int32, ip, ip, ip, ip, dp, dp, dp]
         L.oracle_shell_block.argtypes = bas + [ctypes.c_int] * 6 + [dp]
         L.oracle_schwarz.argtypes = bas + [dp]
-        L.oracle_jk.argtypes = bas + [dp, ip, ip, ctypes.c_int32, dp, dp, ctypes.c_double,
+        qp = [dp, ctypes.c_int32, ctypes.c_double]
+        L.oracle_prim_bounds.argtypes = bas + [dp]
+        L.oracle_jk.argtypes = bas + [dp, ip, ip, ctypes.c_int32, dp, dp] + qp + [ctypes.c_double,
                                       ctypes.c_int, ctypes.c_int, dp, dp]
-        L.oracle_jk_blocks.argtypes = bas + [dp, ip, ip, ctypes.c_int32, dp, dp, ctypes.c_double,
+        L.oracle_jk_blocks.argtypes = bas + [dp, ip, ip, ctypes.c_int32, dp, dp] + qp + [ctypes.c_double,
                                              ctypes.c_int, ip, ctypes.c_int, ip,
                                              ctypes.POINTER(ctypes.c_int64), dp]
-        L.oracle_grad.argtypes = bas + [dp, ip, ip, ctypes.c_int32, dp, dp, ctypes.c_double,
+        L.oracle_grad.argtypes = bas + [dp, ip, ip, ctypes.c_int32, dp, dp] + qp + [ctypes.c_double,
                                         ctypes.c_double, ctypes.c_double, ctypes.c_int, dp]
         L.oracle_num_threads.restype = ctypes.c_int
         _lib = L
@@ -143,6 +145,7 @@ class OBasis:
         self.T = np.concatenate(Ts)
         self.Toff = np.array(offs, np.int32)
         self._Q = None
+        self._qp = None
 
     def args(self):
         return (self.nshell, self.natom, _ip(self.atom), _ip(self.l), _ip(self.nprim),
@@ -162,6 +165,19 @@ class OBasis:
             blk = np.moveaxis(np.tensordot(T, blk, axes=([1], [k])), 0, k)
         return blk
 
+    def prim_bounds(self) -> np.ndarray:
+        """q_ij = |C_i C_j| sqrt(max |(ij|ij)|) for every pair of primitives."""
+        if self._qp is None:
+            n = int(self.exps.size)
+            q = np.zeros((n, n))
+            lib().oracle_prim_bounds(*self.args(), _dp(q))
+            self._qp = q
+        return self._qp
+
+    def screen_args(self, tau_prim: float):
+        q = self.prim_bounds()
+        return (_dp(q), int(q.shape[0]), float(tau_prim))
+
     def schwarz(self) -> np.ndarray:
         if self._Q is None:
             Q = np.zeros((self.nshell, self.nshell))
@@ -175,21 +191,27 @@ def _sym(P):
     return np.ascontiguousarray(0.5 * (P + P.T))
 
 
-def jk(mol, P=None, tau=None, want_j=True, want_k=True) -> Tuple[np.ndarray, np.ndarray]:
+def _tau_prim(tau, tau_prim):
+    return 1e-2 * tau if tau_prim is None else tau_prim
+
+
+def jk(mol, P=None, tau=None, want_j=True, want_k=True, tau_prim=None,
+       basis_obj=None) -> Tuple[np.ndarray, np.ndarray]:
     """Full J and K (spherical basis) by the plain definition."""
-    B = OBasis(mol)
+    B = basis_obj or OBasis(mol)
     P = _sym(mol.P if P is None else P)
     tau = mol.tau_schwarz if tau is None else tau
     Q = B.schwarz()
     J = np.zeros((B.nbf, B.nbf))
     K = np.zeros((B.nbf, B.nbf))
     lib().oracle_jk(*B.args(), _dp(B.T), _ip(B.Toff), _ip(B.ao_off), B.nbf, _dp(P), _dp(Q),
+                    *B.screen_args(_tau_prim(tau, tau_prim)),
                     float(tau), int(want_j), int(want_k), _dp(J), _dp(K))
     return J, K
 
 
 def jk_blocks(mol, jpairs: Sequence[Tuple[int, int]], kpairs: Sequence[Tuple[int, int]],
-              P=None, tau=None, basis_obj=None):
+              P=None, tau=None, basis_obj=None, tau_prim=None):
     """Shell blocks J[a,b] and K[a,c] for sampled shell pairs."""
     B = basis_obj or OBasis(mol)
     P = _sym(mol.P if P is None else P)
@@ -201,7 +223,7 @@ def jk_blocks(mol, jpairs: Sequence[Tuple[int, int]], kpairs: Sequence[Tuple[int
     offs = np.concatenate([[0], np.cumsum(sizes)[:-1]]).astype(np.int64) if sizes else np.zeros(0, np.int64)
     out = np.zeros(int(sum(sizes)) if sizes else 1)
     lib().oracle_jk_blocks(*B.args(), _dp(B.T), _ip(B.Toff), _ip(B.ao_off), B.nbf, _dp(P), _dp(Q),
-                           float(tau), len(jp), _ip(jp), len(kp), _ip(kp),
+                           *B.screen_args(_tau_prim(tau, tau_prim)), float(tau), len(jp), _ip(jp), len(kp), _ip(kp),
                            offs.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), _dp(out))
     res = []
     for t, (x, y) in enumerate(list(jp) + list(kp)):
@@ -216,15 +238,18 @@ def energy(mol, J, K, P=None) -> float:
     return 0.5 * float(np.sum(P * J)) - 0.25 * float(np.sum(P * K))
 
 
-def grad(mol, P=None, tau=None, wj=1.0, wk=1.0, only_atom=-1, Q=None) -> np.ndarray:
+def grad(mol, P=None, tau=None, wj=1.0, wk=1.0, only_atom=-1, Q=None, tau_prim=None,
+         qprim=None) -> np.ndarray:
     """dE/dR (natom x 3) of E = wj/2 tr(PJ) - wk/4 tr(PK) at fixed P."""
     B = OBasis(mol)
+    if qprim is not None:
+        B._qp = np.ascontiguousarray(qprim, float)
     P = _sym(mol.P if P is None else P)
     tau = mol.tau_schwarz if tau is None else tau
     Q = B.schwarz() if Q is None else np.ascontiguousarray(Q, float)
     g = np.zeros((B.natom, 3))
     lib().oracle_grad(*B.args(), _dp(B.T), _ip(B.Toff), _ip(B.ao_off), B.nbf, _dp(P), _dp(Q),
-                      float(tau), float(wj), float(wk), int(only_atom), _dp(g))
+                      *B.screen_args(_tau_prim(tau, tau_prim)), float(tau), float(wj), float(wk), int(only_atom), _dp(g))
     return g
 
 

@@ -23,7 +23,11 @@
  *
  * The screening rule is part of the result's definition: a shell quartet
  * (ab|cd) enters iff Q_ab * Q_cd >= tau, with Q_ab = sqrt(max over Cartesian
- * components of |(ab|ab)|) (eq. cauchy_schwarz_bound at contracted-shell level).
+ * components of |(ab|ab)|) (eq. cauchy_schwarz_bound at contracted-shell level);
+ * inside a kept shell quartet a primitive quartet enters iff q_ij * q_kl >= tau_prim,
+ * q_ij being the same bound for one primitive pair with its coefficients (the
+ * paper screens pGTO pairs by this bound, section "Data structure").  Q_ab itself
+ * is taken over every primitive.
  *
  * Build: gcc -O2 -fopenmp -shared -fPIC oracle.c -o _oracle.so -lm
  * (no -ffast-math, no FMA contraction flags).
@@ -235,13 +239,16 @@ typedef struct {
     const int32_t *atom, *l, *nprim, *off; /* per shell */
     const double *exps, *coefs;            /* per primitive; coefs are fully normalised */
     const double *xyz;                     /* [natom][3] */
+    const double *qprim;                   /* [nprim_tot][nprim_tot] primitive-pair bounds or NULL */
+    int32_t nprim_tot;
+    double tau_prim;                       /* primitive quartet kept iff q_ij q_kl >= tau_prim */
 } basis_t;
 
 static basis_t mkbasis(int32_t nshell, int32_t natom, const int32_t *atom, const int32_t *l,
                        const int32_t *nprim, const int32_t *off, const double *exps,
                        const double *coefs, const double *xyz)
 {
-    basis_t B = {nshell, natom, atom, l, nprim, off, exps, coefs, xyz};
+    basis_t B = {nshell, natom, atom, l, nprim, off, exps, coefs, xyz, NULL, 0, 0.0};
     return B;
 }
 
@@ -283,6 +290,10 @@ static void shell_block(const basis_t *B, int sa, int sb, int sc, int sd,
             for (int i2 = 0; i2 < B->nprim[sc]; ++i2)
                 for (int i3 = 0; i3 < B->nprim[sd]; ++i3) {
                     int pi[4] = {B->off[sa] + i0, B->off[sb] + i1, B->off[sc] + i2, B->off[sd] + i3};
+                    /* primitive-pair screening (pGTO pairs, section "Data structure") */
+                    if (B->qprim && B->qprim[(size_t)pi[0] * B->nprim_tot + pi[1]] *
+                                        B->qprim[(size_t)pi[2] * B->nprim_tot + pi[3]] < B->tau_prim)
+                        continue;
                     double e[4], cf = 1.0;
                     for (int k = 0; k < 4; ++k) { e[k] = B->exps[pi[k]]; cf *= B->coefs[pi[k]]; }
                     if (dcen < 0) {
@@ -424,6 +435,42 @@ void oracle_schwarz(int32_t nshell, int32_t natom, const int32_t *atom, const in
     }
 }
 
+/* Primitive-pair bounds q_ij = |C_i C_j| sqrt(max_c |(ij|ij)_c|) for every pair
+ * of primitives (any two shells), [nprim_tot][nprim_tot]. */
+void oracle_prim_bounds(int32_t nshell, int32_t natom, const int32_t *atom, const int32_t *l,
+                        const int32_t *nprim, const int32_t *off, const double *exps,
+                        const double *coefs, const double *xyz, double *qout)
+{
+    int32_t ntot = 0;
+    for (int s = 0; s < nshell; ++s) ntot += nprim[s];
+#pragma omp parallel
+    {
+        scratch_t *S = (scratch_t *)malloc(sizeof(scratch_t));
+        double *blk = (double *)malloc(sizeof(double) * 10000);
+#pragma omp for schedule(dynamic, 4)
+        for (int a = 0; a < nshell; ++a)
+            for (int b = 0; b < nshell; ++b) {
+                int na = ncart(l[a]), nb = ncart(l[b]);
+                for (int i = 0; i < nprim[a]; ++i)
+                    for (int j = 0; j < nprim[b]; ++j) {
+                        int pa = off[a] + i, pb = off[b] + j;
+                        const double *A = xyz + 3 * atom[a], *Bc = xyz + 3 * atom[b];
+                        memset(blk, 0, sizeof(double) * na * nb * na * nb);
+                        prim_block(l[a], l[b], l[a], l[b], exps[pa], exps[pb], exps[pa], exps[pb],
+                                   A, Bc, A, Bc, 1.0, blk, S);
+                        double mx = 0.0;
+                        for (int u = 0; u < na; ++u)
+                            for (int v = 0; v < nb; ++v) {
+                                double x = fabs(blk[((u * nb + v) * na + u) * nb + v]);
+                                if (x > mx) mx = x;
+                            }
+                        qout[(size_t)pa * ntot + pb] = fabs(coefs[pa] * coefs[pb]) * sqrt(mx);
+                    }
+            }
+        free(blk); free(S);
+    }
+}
+
 /* Transform a Cartesian block to the spherical basis with per-l matrices
  * T_l [2l+1][ncart(l)] (row-major, concatenated for l = 0..3 at Toff[l]). */
 static void to_sph(const int *L, const double *T, const int *Toff, const double *cart,
@@ -463,10 +510,11 @@ static void to_sph(const int *L, const double *T, const int *Toff, const double 
 void oracle_jk(int32_t nshell, int32_t natom, const int32_t *atom, const int32_t *l,
                const int32_t *nprim, const int32_t *off, const double *exps,
                const double *coefs, const double *xyz, const double *T, const int *Toff,
-               const int32_t *ao_off, int32_t nbf, const double *P, const double *Q,
+               const int32_t *ao_off, int32_t nbf, const double *P, const double *Q, const double *qprim, int32_t nprim_tot, double tau_prim,
                double tau, int want_j, int want_k, double *Jout, double *Kout)
 {
     basis_t B = mkbasis(nshell, natom, atom, l, nprim, off, exps, coefs, xyz);
+    B.qprim = qprim; B.nprim_tot = nprim_tot; B.tau_prim = tau_prim;
     memset(Jout, 0, sizeof(double) * nbf * nbf);
     memset(Kout, 0, sizeof(double) * nbf * nbf);
 #pragma omp parallel
@@ -513,11 +561,12 @@ void oracle_jk(int32_t nshell, int32_t natom, const int32_t *atom, const int32_t
 void oracle_jk_blocks(int32_t nshell, int32_t natom, const int32_t *atom, const int32_t *l,
                       const int32_t *nprim, const int32_t *off, const double *exps,
                       const double *coefs, const double *xyz, const double *T, const int *Toff,
-                      const int32_t *ao_off, int32_t nbf, const double *P, const double *Q,
+                      const int32_t *ao_off, int32_t nbf, const double *P, const double *Q, const double *qprim, int32_t nprim_tot, double tau_prim,
                       double tau, int nj, const int32_t *jpairs, int nk, const int32_t *kpairs,
                       const int64_t *out_off, double *out)
 {
     basis_t B = mkbasis(nshell, natom, atom, l, nprim, off, exps, coefs, xyz);
+    B.qprim = qprim; B.nprim_tot = nprim_tot; B.tau_prim = tau_prim;
     int ntask = nj + nk;
     for (int t = 0; t < ntask; ++t) {
         int x = (t < nj) ? jpairs[2 * t] : kpairs[2 * (t - nj)];
@@ -569,10 +618,11 @@ void oracle_jk_blocks(int32_t nshell, int32_t natom, const int32_t *atom, const 
 void oracle_grad(int32_t nshell, int32_t natom, const int32_t *atom, const int32_t *l,
                  const int32_t *nprim, const int32_t *off, const double *exps,
                  const double *coefs, const double *xyz, const double *T, const int *Toff,
-                 const int32_t *ao_off, int32_t nbf, const double *P, const double *Q,
+                 const int32_t *ao_off, int32_t nbf, const double *P, const double *Q, const double *qprim, int32_t nprim_tot, double tau_prim,
                  double tau, double wj, double wk, int only_atom, double *grad)
 {
     basis_t B = mkbasis(nshell, natom, atom, l, nprim, off, exps, coefs, xyz);
+    B.qprim = qprim; B.nprim_tot = nprim_tot; B.tau_prim = tau_prim;
     memset(grad, 0, sizeof(double) * 3 * natom);
 #pragma omp parallel
     {

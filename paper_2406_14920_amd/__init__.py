@@ -1,0 +1,77 @@
+"""MI355X-native direct-SCF J/K (and J/K energy gradient) library.
+
+    from paper_2406_14920_amd import JK, synth
+    mol = synth.mol40()
+    jk = JK.from_molecule(mol)                  # eri_setup
+    J, K = jk.jk(P)                             # build_jk, P a float64 CUDA tensor
+
+The numerical work runs in libmdjk.so (hand-written HIP for gfx950); see
+include/mdjk.h for the C ABI.  Importing this package does not load the
+library; the first call that needs it does, and raises if it is missing.
+"""
+from __future__ import annotations
+
+from typing import Optional, Tuple
+
+from . import abi  # noqa: F401  (ctypes only; loads the .so lazily)
+
+__all__ = ["abi", "JK"]
+
+
+class JK:
+    """One eri_ctx: a fixed basis/geometry, reused across builds."""
+
+    def __init__(self, shells, xyz, schwarz_thresh: float = 1e-11, prim_thresh: Optional[float] = None,
+                 precision: str = "fp64", mixed_thresh: float = 1e-5, spherical: bool = True,
+                 stream=None):
+        import torch
+        o = abi.eri_default_opts()
+        o.schwarz_thresh = float(schwarz_thresh)
+        o.prim_thresh = float(1e-2 * schwarz_thresh if prim_thresh is None else prim_thresh)
+        o.mixed_thresh = float(mixed_thresh)
+        o.precision = abi.ERI_MIXED if precision == "mixed" else abi.ERI_FP64
+        o.spherical = 1 if spherical else 0
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        o.stream = int(stream.cuda_stream)
+        self.opts = o
+        self.natom = len(xyz)
+        self.ctx = abi.eri_setup(shells, xyz, o)
+        self.nbf = abi.eri_nbf(self.ctx)
+
+    @classmethod
+    def from_molecule(cls, mol, **kw):
+        shells = [(s.atom, s.l, s.exps, s.coefs) for s in mol.shells]
+        kw.setdefault("schwarz_thresh", mol.tau_schwarz)
+        return cls(shells, mol.xyz, **kw)
+
+    def jk(self, P, want_j: bool = True, want_k: bool = True) -> Tuple:
+        import torch
+        if P.dtype != torch.float64 or not P.is_cuda or not P.is_contiguous():
+            raise ValueError("P must be a contiguous float64 CUDA tensor")
+        if P.shape != (self.nbf, self.nbf):
+            raise ValueError("P must be %d x %d" % (self.nbf, self.nbf))
+        J = torch.empty_like(P) if want_j else None
+        K = torch.empty_like(P) if want_k else None
+        with torch.cuda.stream(self.stream):
+            abi.build_jk(self.ctx, P, J, K)
+        return J, K
+
+    def set_precision(self, precision: str, mixed_thresh: Optional[float] = None):
+        abi.eri_set_precision(self.ctx, abi.ERI_MIXED if precision == "mixed" else abi.ERI_FP64,
+                              self.opts.mixed_thresh if mixed_thresh is None else mixed_thresh)
+
+    def stats(self) -> dict:
+        return abi.eri_stats(self.ctx)
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            abi.eri_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

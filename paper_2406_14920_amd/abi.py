@@ -1,0 +1,182 @@
+"""ctypes binding of libmdjk.so (include/mdjk.h) -- argument marshalling only.
+
+Every numerical step runs in the library's HIP kernels; this module converts
+Python/torch objects to the C structs and pointers of the ABI and raises on
+error codes.  If the shared library is missing it raises: there is no CPU
+fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmdjk.so")
+
+ERI_OK, ERI_EINVAL, ERI_ENOMEM, ERI_EHIP, ERI_ESTATE = 0, -1, -2, -3, -4
+ERI_FP64, ERI_MIXED = 0, 1
+_NAMES = {ERI_EINVAL: "ERI_EINVAL", ERI_ENOMEM: "ERI_ENOMEM", ERI_EHIP: "ERI_EHIP", ERI_ESTATE: "ERI_ESTATE"}
+
+
+class EriError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__("%s (%d): %s" % (_NAMES.get(code, "?"), code, msg))
+        self.code = code
+
+
+class eri_atom(ctypes.Structure):
+    _fields_ = [("xyz", ctypes.c_double * 3)]
+
+
+class eri_shell(ctypes.Structure):
+    _fields_ = [("atom", ctypes.c_int32), ("l", ctypes.c_int32), ("nprim", ctypes.c_int32),
+                ("exps", ctypes.POINTER(ctypes.c_double)), ("coefs", ctypes.POINTER(ctypes.c_double))]
+
+
+class eri_opts(ctypes.Structure):
+    _fields_ = [("schwarz_thresh", ctypes.c_double), ("prim_thresh", ctypes.c_double),
+                ("mixed_thresh", ctypes.c_double), ("precision", ctypes.c_int32),
+                ("spherical", ctypes.c_int32), ("stream", ctypes.c_void_p)]
+
+
+class eri_stats_t(ctypes.Structure):
+    _fields_ = [("nshell", ctypes.c_int32), ("natom", ctypes.c_int32), ("nbf", ctypes.c_int32),
+                ("nbf_cart", ctypes.c_int32), ("n_pairs", ctypes.c_int64), ("n_prim_pairs", ctypes.c_int64),
+                ("n_quartets", ctypes.c_int64), ("n_quartets_fp32", ctypes.c_int64),
+                ("eris_sph", ctypes.c_double), ("eris_cart", ctypes.c_double),
+                ("model_flops_k", ctypes.c_double), ("model_flops_j", ctypes.c_double),
+                ("last_ms", ctypes.c_double)]
+
+
+EXPORTS = ["eri_default_opts", "eri_setup", "eri_nbf", "eri_set_geometry", "eri_set_precision",
+           "build_jk", "jk_grad", "eri_stats", "eri_destroy", "eri_last_error"]
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load the HIP library (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError("libmdjk.so not found at %s: build it with "
+                           "`python -m paper_2406_14920_amd.build` (no CPU fallback exists)" % path)
+    L = ctypes.CDLL(path)
+    vp = ctypes.c_void_p
+    L.eri_default_opts.argtypes = [ctypes.POINTER(eri_opts)]
+    L.eri_default_opts.restype = None
+    L.eri_setup.argtypes = [ctypes.POINTER(eri_shell), ctypes.c_int32, ctypes.POINTER(eri_atom),
+                            ctypes.c_int32, ctypes.POINTER(eri_opts), ctypes.POINTER(vp)]
+    L.eri_nbf.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
+    L.eri_set_geometry.argtypes = [vp, ctypes.POINTER(eri_atom)]
+    L.eri_set_precision.argtypes = [vp, ctypes.c_int32, ctypes.c_double]
+    L.build_jk.argtypes = [vp, vp, vp, vp]
+    L.jk_grad.argtypes = [vp, vp, vp, vp]
+    L.eri_stats.argtypes = [vp, ctypes.POINTER(eri_stats_t)]
+    L.eri_destroy.argtypes = [vp]
+    L.eri_last_error.restype = ctypes.c_char_p
+    for name in EXPORTS:
+        if name not in ("eri_default_opts", "eri_last_error"):
+            getattr(L, name).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def _check(rc: int):
+    if rc != ERI_OK:
+        raise EriError(rc, load().eri_last_error().decode())
+
+
+def _ptr(x) -> Optional[int]:
+    """Device pointer of a torch tensor (or an int address), None for None."""
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    return int(x.data_ptr())
+
+
+# ---------------------------------------------------------------------------
+# ABI calls under their C names
+# ---------------------------------------------------------------------------
+def eri_default_opts() -> eri_opts:
+    o = eri_opts()
+    load().eri_default_opts(ctypes.byref(o))
+    return o
+
+
+class _ShellArrays:
+    """Keeps the ctypes shell array and the numpy buffers it points into alive."""
+
+    def __init__(self, shells):
+        self.bufs = []
+        self.arr = (eri_shell * len(shells))()
+        for k, s in enumerate(shells):
+            e = np.ascontiguousarray(s[2], dtype=np.float64)
+            c = np.ascontiguousarray(s[3], dtype=np.float64)
+            self.bufs += [e, c]
+            self.arr[k].atom = int(s[0])
+            self.arr[k].l = int(s[1])
+            self.arr[k].nprim = int(e.size)
+            self.arr[k].exps = e.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+            self.arr[k].coefs = c.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _atoms(xyz) -> ctypes.Array:
+    xyz = np.asarray(xyz, dtype=np.float64).reshape(-1, 3)
+    arr = (eri_atom * len(xyz))()
+    for i, r in enumerate(xyz):
+        arr[i].xyz[:] = [float(v) for v in r]
+    return arr
+
+
+def eri_setup(shells: Sequence, xyz, opts: Optional[eri_opts] = None) -> int:
+    """shells: sequence of (atom, l, exps, coefs); xyz: (natom, 3) bohr.
+    Returns the context handle (an int)."""
+    L = load()
+    sa = _ShellArrays(shells)
+    at = _atoms(xyz)
+    h = ctypes.c_void_p()
+    o = opts if opts is not None else eri_default_opts()
+    _check(L.eri_setup(sa.arr, len(shells), at, len(at), ctypes.byref(o), ctypes.byref(h)))
+    return int(h.value)
+
+
+def eri_nbf(ctx: int) -> int:
+    n = ctypes.c_int32()
+    _check(load().eri_nbf(ctypes.c_void_p(ctx), ctypes.byref(n)))
+    return int(n.value)
+
+
+def eri_set_geometry(ctx: int, xyz) -> None:
+    _check(load().eri_set_geometry(ctypes.c_void_p(ctx), _atoms(xyz)))
+
+
+def eri_set_precision(ctx: int, precision: int, mixed_thresh: float) -> None:
+    _check(load().eri_set_precision(ctypes.c_void_p(ctx), int(precision), float(mixed_thresh)))
+
+
+def build_jk(ctx: int, P, J, K) -> None:
+    _check(load().build_jk(ctypes.c_void_p(ctx), _ptr(P), _ptr(J), _ptr(K)))
+
+
+def jk_grad(ctx: int, P, grad, E=None) -> None:
+    _check(load().jk_grad(ctypes.c_void_p(ctx), _ptr(P), _ptr(grad), _ptr(E)))
+
+
+def eri_stats(ctx: int) -> dict:
+    s = eri_stats_t()
+    _check(load().eri_stats(ctypes.c_void_p(ctx), ctypes.byref(s)))
+    return {name: getattr(s, name) for name, _ in eri_stats_t._fields_}
+
+
+def eri_destroy(ctx: int) -> None:
+    _check(load().eri_destroy(ctypes.c_void_p(ctx)))
+
+
+def eri_last_error() -> str:
+    return load().eri_last_error().decode()

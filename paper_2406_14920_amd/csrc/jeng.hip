@@ -1,0 +1,328 @@
+// jeng.hip -- Coulomb matrix by the J-engine (eq. j_formula) in three steps:
+//   1. Hermite density of every ket primitive pair
+//        Dt_Q = (-1)^{|Q|} f sum_{cd} E^{cd}_Q D_cd                (f = 2 for c != d shells)
+//   2. Hermite J of every bra primitive pair
+//        Jh_P = sum_{kets} sum_Q R_{P+Q} Dt_Q
+//      (R carries the prefactor of eq. eri_formula and both pair factors K)
+//   3. back to Cartesian: J_ab = sum_P E^{ab}_P Jh_P, written as one
+//      triangle of the accumulator (J = Jacc + Jacc^T).
+// Step 2 depends only on the total bra / ket Hermite orders (LX, LY); low
+// orders keep R in registers (one lane per bra primitive pair), high orders
+// build R in LDS with one wavefront per bra primitive pair.
+#include "kern_args.hpp"
+#include "md_device.hpp"
+#include "wave_r.hpp"
+
+namespace md {
+
+// ---------------------------------------------------------------------------
+// 1. Hermite density: one workgroup per contracted ket pair
+// ---------------------------------------------------------------------------
+template <int LC, int LD>
+__global__ __launch_bounds__(128) void hermite_density(const CPair *__restrict__ cp, int ncp,
+                                                       const PrimPair *__restrict__ pp,
+                                                       const double *__restrict__ D, int ld,
+                                                       double *__restrict__ Dt, int dt_base)
+{
+    constexpr int NC = ncart(LC), ND = ncart(LD), LCD = LC + LD, NH = nherm(LCD);
+    constexpr int EKD = (LC + 1) * (LD + 1) * (LCD + 1);
+    __shared__ double sE[3 * EKD];
+    __shared__ double sDb[NC * ND];
+    const int c = blockIdx.x;
+    if (c >= ncp) return;
+    const CPair B = cp[c];
+    const int tid = threadIdx.x;
+    for (int o = tid; o < NC * ND; o += blockDim.x)
+        sDb[o] = D[(int64_t)(B.c1 + o / ND) * ld + B.c2 + o % ND];
+    const double f = (B.sh1 == B.sh2) ? 1.0 : 2.0;
+    for (int kp = 0; kp < B.np; ++kp) {
+        const PrimPair pk = pp[B.poff + kp];
+        if (tid < 3) {
+            const double pa = tid == 0 ? pk.PA[0] : (tid == 1 ? pk.PA[1] : pk.PA[2]);
+            const double pbb = tid == 0 ? pk.PB[0] : (tid == 1 ? pk.PB[1] : pk.PB[2]);
+            etab_lds<LC, LD>(pa, pbb, pk.o2p, sE + tid * EKD);
+        }
+        __syncthreads();
+        for (int Q = tid; Q < NH; Q += blockDim.x) {
+            const int code = c_herm.tuv[Q];
+            const int qt = code & 0xff, qu = (code >> 8) & 0xff, qv = code >> 16;
+            double acc = 0.0;
+            for (int cd = 0; cd < NC * ND; ++cd) {
+                int cx, cy, cz, dx, dy, dz;
+                cart_rt(LC, cd / ND, cx, cy, cz);
+                cart_rt(LD, cd % ND, dx, dy, dz);
+                if (qt > cx + dx || qu > cy + dy || qv > cz + dz) continue;
+                acc += sE[(cx * (LD + 1) + dx) * (LCD + 1) + qt] *
+                       sE[EKD + (cy * (LD + 1) + dy) * (LCD + 1) + qu] *
+                       sE[2 * EKD + (cz * (LD + 1) + dz) * (LCD + 1) + qv] * sDb[cd];
+            }
+            const double sg = ((qt + qu + qv) & 1) ? -1.0 : 1.0;
+            Dt[(int64_t)(B.poff + kp - dt_base) * NH + Q] = sg * f * acc;
+        }
+        __syncthreads();
+    }
+}
+
+__device__ __forceinline__ double wave_max(double v)
+{
+    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off));
+    return v;
+}
+__device__ __forceinline__ int wave_max(int v)
+{
+    for (int off = 32; off > 0; off >>= 1) v = max(v, __shfl_xor(v, off));
+    return v;
+}
+__device__ __forceinline__ double uniform_d(double v)
+{
+    const uint64_t b = __double_as_longlong(v);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)b);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(b >> 32));
+    return __longlong_as_double(((uint64_t)hi << 32) | lo);
+}
+
+// number of class-Y kets j with Qi * Q_j >= tau (Q sorted descending)
+__device__ __forceinline__ int count_kets(const double *__restrict__ Q, int n, double Qi, double tau)
+{
+    int lo = 0, hi = n;
+    while (lo < hi) {
+        int mid = (lo + hi) >> 1;
+        if (Qi * Q[mid] >= tau) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+// ---------------------------------------------------------------------------
+// 2a. Hermite J, registers: one lane per bra primitive pair
+// ---------------------------------------------------------------------------
+template <int LX, int LY>
+__global__ __launch_bounds__(64) void jeng_small(JArgs a)
+{
+    constexpr int L = LX + LY, NX = nherm(LX), NY = nherm(LY);
+    const int g = blockIdx.x * 64 + threadIdx.x;
+    const bool valid = g < a.nbp;
+    const int gi = valid ? g : a.nbp - 1;
+    const PrimPair pb = a.pp[a.pbase + gi];
+    const double Qi = valid ? a.Qbra[a.owner[gi]] : 0.0;
+    const double qi = valid ? pb.q : 0.0;
+    const int nv = valid ? count_kets(a.Qket, a.nket, Qi, a.tau) : 0;
+    const int nvmax = __builtin_amdgcn_readfirstlane(wave_max(nv));
+    const double qmax = uniform_d(wave_max(qi));
+    const int j0 = blockIdx.y * a.kchunk;
+    const int j1 = min(min(a.nket, j0 + a.kchunk), nvmax);
+
+    double Jh[NX];
+#pragma unroll
+    for (int i = 0; i < NX; ++i) Jh[i] = 0.0;
+    for (int j = j0; j < j1; ++j) {
+        const CPair B = a.ket[j];
+        for (int kp = 0; kp < B.np; ++kp) {
+            const PrimPair pk = a.pp[B.poff + kp];
+            if (qmax * pk.q < a.tau_prim) break;
+            if (j < nv && qi * pk.q >= a.tau_prim) {
+                double Fs[L + 1], X, Y, Z;
+                quartet_fs<L>(pb, pk, a.boys, Fs, X, Y, Z);
+                double R[nherm(L)];
+                r_build<L>(Fs, X, Y, Z, R);
+                const double *dt = a.Dt + (int64_t)(B.poff + kp - a.dt_base) * NY;
+                double dq[NY];
+#pragma unroll
+                for (int q = 0; q < NY; ++q) dq[q] = dt[q];
+                static_for<0, NX>([&](auto pc) {
+                    constexpr int P = decltype(pc)::value;
+                    constexpr int tp = herm_t(P), up = herm_u(P), vp = herm_v(P);
+                    double acc = Jh[P];
+                    static_for<0, NY>([&](auto qc) {
+                        constexpr int Q = decltype(qc)::value;
+                        acc += R[herm_idx(tp + herm_t(Q), up + herm_u(Q), vp + herm_v(Q))] * dq[Q];
+                    });
+                    Jh[P] = acc;
+                });
+            }
+        }
+    }
+    if (valid && j1 > j0) {
+#pragma unroll
+        for (int P = 0; P < NX; ++P) unsafeAtomicAdd(&a.Jh[(int64_t)g * NX + P], Jh[P]);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// 2b. Hermite J, LDS: one wavefront per (bra primitive pair, ket chunk)
+// ---------------------------------------------------------------------------
+template <int LX, int LY>
+__global__ __launch_bounds__(64) void jeng_wave(JArgs a)
+{
+    constexpr int L = LX + LY, L1 = L + 1, NX = nherm(LX), NY = nherm(LY);
+    constexpr int NLEV = nherm(L - 1);
+    __shared__ double sR0[L1 * L1 * L1];
+    __shared__ double sLev[2 * NLEV];
+    __shared__ double sF[L + 1];
+    const int lane = threadIdx.x;
+    const int g = blockIdx.x;
+    const PrimPair pb = a.pp[a.pbase + g];
+    const double Qi = a.Qbra[a.owner[g]];
+    const double qi = pb.q;
+    const int nv = count_kets(a.Qket, a.nket, Qi, a.tau);
+    const int j0 = blockIdx.y * a.kchunk;
+    const int j1 = min(min(a.nket, j0 + a.kchunk), nv);
+    if (j1 <= j0) return;
+
+    // lane owns P = lane and P = lane + 64
+    int pof[2];
+    bool own[2];
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+        const int P = lane + 64 * r;
+        own[r] = P < NX;
+        const int code = c_herm.tuv[own[r] ? P : 0];
+        pof[r] = ((code & 0xff) * L1 + ((code >> 8) & 0xff)) * L1 + (code >> 16);
+    }
+    double acc[2] = {0.0, 0.0};
+    for (int j = j0; j < j1; ++j) {
+        const CPair B = a.ket[j];
+        for (int kp = 0; kp < B.np; ++kp) {
+            const PrimPair pk = a.pp[B.poff + kp];
+            if (qi * pk.q < a.tau_prim) break;
+            const QuartetGeo geo = quartet_geo(pb, pk);
+            wave_boys<L>(geo, a.boys, sF, lane);
+            __syncthreads();
+            wave_recur<L>(geo, sF, sLev, sLev + NLEV, sR0, lane);
+            const double *dt = a.Dt + (int64_t)(B.poff + kp - a.dt_base) * NY;
+#pragma unroll
+            for (int r = 0; r < 2; ++r) {
+                if (!own[r]) continue;
+                const double *Rb = sR0 + pof[r];
+                double s = 0.0;
+                static_for<0, NY>([&](auto qc) {
+                    constexpr int Q = decltype(qc)::value;
+                    constexpr int qo = (herm_t(Q) * L1 + herm_u(Q)) * L1 + herm_v(Q);
+                    s += Rb[qo] * dt[Q];
+                });
+                acc[r] += s;
+            }
+            __syncthreads();
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+        if (own[r]) unsafeAtomicAdd(&a.Jh[(int64_t)g * NX + lane + 64 * r], acc[r]);
+}
+
+// ---------------------------------------------------------------------------
+// 3. Hermite J -> Cartesian J accumulator: one workgroup per contracted pair
+// ---------------------------------------------------------------------------
+template <int LA, int LB>
+__global__ __launch_bounds__(128) void hermite_to_cart(const CPair *__restrict__ cp, int ncp,
+                                                       const PrimPair *__restrict__ pp,
+                                                       const double *__restrict__ Jh, int jh_base,
+                                                       double *__restrict__ Jacc, int ld)
+{
+    constexpr int NA = ncart(LA), NB = ncart(LB), LAB = LA + LB, NH = nherm(LAB);
+    constexpr int EBD = (LA + 1) * (LB + 1) * (LAB + 1);
+    __shared__ double sE[3 * EBD];
+    const int c = blockIdx.x;
+    if (c >= ncp) return;
+    const CPair A = cp[c];
+    const int tid = threadIdx.x;
+    double acc = 0.0;
+    int ax = 0, ay = 0, az = 0, bx = 0, by = 0, bz = 0;
+    if (tid < NA * NB) {
+        cart_rt(LA, tid / NB, ax, ay, az);
+        cart_rt(LB, tid % NB, bx, by, bz);
+    }
+    for (int ip = 0; ip < A.np; ++ip) {
+        const PrimPair pb = pp[A.poff + ip];
+        if (tid < 3) {
+            const double pa = tid == 0 ? pb.PA[0] : (tid == 1 ? pb.PA[1] : pb.PA[2]);
+            const double pbb = tid == 0 ? pb.PB[0] : (tid == 1 ? pb.PB[1] : pb.PB[2]);
+            etab_lds<LA, LB>(pa, pbb, pb.o2p, sE + tid * EBD);
+        }
+        __syncthreads();
+        if (tid < NA * NB) {
+            const double *jh = Jh + (int64_t)(A.poff + ip - jh_base) * NH;
+            double s = 0.0;
+            for (int tx = 0; tx <= ax + bx; ++tx)
+                for (int ty = 0; ty <= ay + by; ++ty)
+                    for (int tz = 0; tz <= az + bz; ++tz)
+                        s += sE[(ax * (LB + 1) + bx) * (LAB + 1) + tx] *
+                             sE[EBD + (ay * (LB + 1) + by) * (LAB + 1) + ty] *
+                             sE[2 * EBD + (az * (LB + 1) + bz) * (LAB + 1) + tz] *
+                             jh[herm_idx_rt(tx, ty, tz)];
+            acc += s;
+        }
+        __syncthreads();
+    }
+    if (tid < NA * NB) {
+        const double f = (A.sh1 == A.sh2) ? 0.5 : 1.0;
+        Jacc[(int64_t)(A.c1 + tid / NB) * ld + A.c2 + tid % NB] = f * acc;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+void launch_hermite_density(int lc, int ld_, const CPair *cp, int ncp, const PrimPair *pp,
+                            const double *D, int ldd, double *Dt, int dt_base, hipStream_t st)
+{
+    if (ncp <= 0) return;
+#define MD_HD(C_, D_)                                                                         \
+    if (lc == C_ && ld_ == D_) {                                                             \
+        hipLaunchKernelGGL((hermite_density<C_, D_>), dim3(ncp), dim3(128), 0, st, cp, ncp, pp, D, \
+                           ldd, Dt, dt_base);                                                \
+        return;                                                                              \
+    }
+    MD_HD(0, 0) MD_HD(1, 0) MD_HD(1, 1) MD_HD(2, 0) MD_HD(2, 1) MD_HD(2, 2) MD_HD(3, 0) MD_HD(3, 1)
+    MD_HD(3, 2) MD_HD(3, 3)
+#undef MD_HD
+}
+
+void launch_hermite_to_cart(int la, int lb, const CPair *cp, int ncp, const PrimPair *pp,
+                            const double *Jh, int jh_base, double *Jacc, int ld, hipStream_t st)
+{
+    if (ncp <= 0) return;
+#define MD_HC(A_, B_)                                                                          \
+    if (la == A_ && lb == B_) {                                                               \
+        hipLaunchKernelGGL((hermite_to_cart<A_, B_>), dim3(ncp), dim3(128), 0, st, cp, ncp, pp, Jh, \
+                           jh_base, Jacc, ld);                                                \
+        return;                                                                               \
+    }
+    MD_HC(0, 0) MD_HC(1, 0) MD_HC(1, 1) MD_HC(2, 0) MD_HC(2, 1) MD_HC(2, 2) MD_HC(3, 0) MD_HC(3, 1)
+    MD_HC(3, 2) MD_HC(3, 3)
+#undef MD_HC
+}
+
+// total Hermite order at or below which the register path is used
+constexpr int kJengRegMaxL = 5;
+
+template <int LX, int LY>
+void jeng_launch_t(const JArgs &a, hipStream_t st)
+{
+    const int nch = (a.nket + a.kchunk - 1) / a.kchunk;
+    if (a.nbp <= 0 || nch <= 0) return;
+    if constexpr (LX + LY <= kJengRegMaxL) {
+        dim3 grid((a.nbp + 63) / 64, nch);
+        hipLaunchKernelGGL((jeng_small<LX, LY>), grid, dim3(64), 0, st, a);
+    } else {
+        dim3 grid(a.nbp, nch);
+        hipLaunchKernelGGL((jeng_wave<LX, LY>), grid, dim3(64), 0, st, a);
+    }
+}
+
+bool launch_jeng(int lx, int ly, const JArgs &a, hipStream_t st)
+{
+    bool done = false;
+    static_for<0, 7>([&](auto xc) {
+        constexpr int X = decltype(xc)::value;
+        static_for<0, 7>([&](auto yc) {
+            constexpr int Yv = decltype(yc)::value;
+            if (!done && lx == X && ly == Yv) {
+                jeng_launch_t<X, Yv>(a, st);
+                done = true;
+            }
+        });
+    });
+    return done;
+}
+
+}  // namespace md

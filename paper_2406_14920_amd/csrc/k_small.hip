@@ -1,0 +1,195 @@
+// k_small.hip -- exchange (K) for angular classes whose Cartesian block fits
+// in registers: one lane evaluates one canonical contracted shell quartet,
+// looping over its primitive quartets (eq. eri_formula with E built in-kernel),
+// accumulates the contracted Cartesian block and digests it into the four
+// exchange blocks that the 8-fold permutational symmetry (eq. 8_fold_symmetry)
+// maps it to:  K_ac += V D_bd, K_ad += V D_bc, K_bc += V D_ad, K_bd += V D_ac.
+// The caller forms K = Kacc + Kacc^T afterwards.
+#include "class_lists.hpp"
+#include "kern_args.hpp"
+#include "md_device.hpp"
+
+namespace md {
+
+template <int LA, int LB, int LC, int LD>
+__global__ __launch_bounds__(128) void k_small(KArgs a)
+{
+    constexpr int NA = ncart(LA), NB = ncart(LB), NC = ncart(LC), ND = ncart(LD);
+    constexpr int L = LA + LB + LC + LD, LAB = LA + LB;
+    constexpr int NBLK = NA * NB * NC * ND;
+
+    int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (w >= a.nwork) return;
+    int lo = 0, hi = a.nbra;
+    while (hi - lo > 1) {
+        int mid = (lo + hi) >> 1;
+        if (a.prefix[mid] <= w) lo = mid; else hi = mid;
+    }
+    const int ib = lo;
+    const int jk = (int)(w - a.prefix[ib]);
+    const CPair A = a.bra[ib];
+    const CPair B = a.ket[jk];
+
+    double V[NBLK];
+#pragma unroll
+    for (int i = 0; i < NBLK; ++i) V[i] = 0.0;
+
+    const double qk0 = a.pp[B.poff].q;
+    for (int ip = 0; ip < A.np; ++ip) {
+        const PrimPair pb = a.pp[A.poff + ip];
+        if (pb.q * qk0 < a.tau_prim) break;
+        Etab<LA, LB> Ex, Ey, Ez;
+        etab_build<LA, LB>(pb.PA[0], pb.PB[0], pb.o2p, Ex);
+        etab_build<LA, LB>(pb.PA[1], pb.PB[1], pb.o2p, Ey);
+        etab_build<LA, LB>(pb.PA[2], pb.PB[2], pb.o2p, Ez);
+        for (int kp = 0; kp < B.np; ++kp) {
+            const PrimPair pk = a.pp[B.poff + kp];
+            if (pb.q * pk.q < a.tau_prim) break;
+            double Fs[L + 1], X, Y, Z;
+            quartet_fs<L>(pb, pk, a.boys, Fs, X, Y, Z);
+            double R[nherm(L)];
+            r_build<L>(Fs, X, Y, Z, R);
+            Etab<LC, LD> Fx, Fy, Fz;
+            etab_build<LC, LD>(pk.PA[0], pk.PB[0], pk.o2p, Fx);
+            etab_build<LC, LD>(pk.PA[1], pk.PB[1], pk.o2p, Fy);
+            etab_build<LC, LD>(pk.PA[2], pk.PB[2], pk.o2p, Fz);
+            static_for<0, NC * ND>([&](auto cdc) {
+                constexpr int cd = decltype(cdc)::value;
+                constexpr int c = cd / ND, d = cd % ND;
+                constexpr int cx = cart_x(LC, c), cy = cart_y(LC, c), cz = cart_z(LC, c);
+                constexpr int dx = cart_x(LD, d), dy = cart_y(LD, d), dz = cart_z(LD, d);
+                // X_P = sum_s (-1)^{|s|} E^{cd}_s R_{P+s}   (ket half of eq. eri_formula)
+                double Xp[nherm(LAB)];
+                static_for<0, nherm(LAB)>([&](auto pc) {
+                    constexpr int P = decltype(pc)::value;
+                    constexpr int tp = herm_t(P), up = herm_u(P), vp = herm_v(P);
+                    double s = 0.0;
+                    static_for<0, cx + dx + 1>([&](auto sxc) {
+                        constexpr int sx = decltype(sxc)::value;
+                        static_for<0, cy + dy + 1>([&](auto syc) {
+                            constexpr int sy = decltype(syc)::value;
+                            const double exy = Fx.e[cx][dx][sx] * Fy.e[cy][dy][sy];
+                            static_for<0, cz + dz + 1>([&](auto szc) {
+                                constexpr int sz = decltype(szc)::value;
+                                constexpr double sg = ((sx + sy + sz) & 1) ? -1.0 : 1.0;
+                                s += sg * exy * Fz.e[cz][dz][sz] * R[herm_idx(tp + sx, up + sy, vp + sz)];
+                            });
+                        });
+                    });
+                    Xp[P] = s;
+                });
+                // (ab|cd) += sum_P E^{ab}_P X_P
+                static_for<0, NA * NB>([&](auto abc) {
+                    constexpr int ab = decltype(abc)::value;
+                    constexpr int ia = ab / NB, jb = ab % NB;
+                    constexpr int ax = cart_x(LA, ia), ay = cart_y(LA, ia), az = cart_z(LA, ia);
+                    constexpr int bx = cart_x(LB, jb), by = cart_y(LB, jb), bz = cart_z(LB, jb);
+                    double v = 0.0;
+                    static_for<0, ax + bx + 1>([&](auto txc) {
+                        constexpr int tx = decltype(txc)::value;
+                        static_for<0, ay + by + 1>([&](auto tyc) {
+                            constexpr int ty = decltype(tyc)::value;
+                            const double exy = Ex.e[ax][bx][tx] * Ey.e[ay][by][ty];
+                            static_for<0, az + bz + 1>([&](auto tzc) {
+                                constexpr int tz = decltype(tzc)::value;
+                                v += exy * Ez.e[az][bz][tz] * Xp[herm_idx(tx, ty, tz)];
+                            });
+                        });
+                    });
+                    V[ab * (NC * ND) + cd] += v;
+                });
+            });
+        }
+    }
+
+    // degeneracy of the canonical quartet
+    double s = 1.0;
+    if (A.sh1 == A.sh2) s *= 0.5;
+    if (B.sh1 == B.sh2) s *= 0.5;
+    if (a.same && ib == jk) s *= 0.5;
+
+    const double *D = a.D;
+    const int n = a.ld;
+    double *Kc = a.Kacc;
+    // K_ac += V D_bd
+    static_for<0, NA>([&](auto ic) {
+        constexpr int i = decltype(ic)::value;
+        static_for<0, NC>([&](auto kc) {
+            constexpr int k = decltype(kc)::value;
+            double acc = 0.0;
+            static_for<0, NB>([&](auto jc) {
+                constexpr int j = decltype(jc)::value;
+                static_for<0, ND>([&](auto lc) {
+                    constexpr int l = decltype(lc)::value;
+                    acc += V[((i * NB + j) * NC + k) * ND + l] * D[(int64_t)(A.c2 + j) * n + B.c2 + l];
+                });
+            });
+            unsafeAtomicAdd(&Kc[(int64_t)(A.c1 + i) * n + B.c1 + k], s * acc);
+        });
+    });
+    // K_ad += V D_bc
+    static_for<0, NA>([&](auto ic) {
+        constexpr int i = decltype(ic)::value;
+        static_for<0, ND>([&](auto lc) {
+            constexpr int l = decltype(lc)::value;
+            double acc = 0.0;
+            static_for<0, NB>([&](auto jc) {
+                constexpr int j = decltype(jc)::value;
+                static_for<0, NC>([&](auto kc) {
+                    constexpr int k = decltype(kc)::value;
+                    acc += V[((i * NB + j) * NC + k) * ND + l] * D[(int64_t)(A.c2 + j) * n + B.c1 + k];
+                });
+            });
+            unsafeAtomicAdd(&Kc[(int64_t)(A.c1 + i) * n + B.c2 + l], s * acc);
+        });
+    });
+    // K_bc += V D_ad
+    static_for<0, NB>([&](auto jc) {
+        constexpr int j = decltype(jc)::value;
+        static_for<0, NC>([&](auto kc) {
+            constexpr int k = decltype(kc)::value;
+            double acc = 0.0;
+            static_for<0, NA>([&](auto ic) {
+                constexpr int i = decltype(ic)::value;
+                static_for<0, ND>([&](auto lc) {
+                    constexpr int l = decltype(lc)::value;
+                    acc += V[((i * NB + j) * NC + k) * ND + l] * D[(int64_t)(A.c1 + i) * n + B.c2 + l];
+                });
+            });
+            unsafeAtomicAdd(&Kc[(int64_t)(A.c2 + j) * n + B.c1 + k], s * acc);
+        });
+    });
+    // K_bd += V D_ac
+    static_for<0, NB>([&](auto jc) {
+        constexpr int j = decltype(jc)::value;
+        static_for<0, ND>([&](auto lc) {
+            constexpr int l = decltype(lc)::value;
+            double acc = 0.0;
+            static_for<0, NA>([&](auto ic) {
+                constexpr int i = decltype(ic)::value;
+                static_for<0, NC>([&](auto kc) {
+                    constexpr int k = decltype(kc)::value;
+                    acc += V[((i * NB + j) * NC + k) * ND + l] * D[(int64_t)(A.c1 + i) * n + B.c1 + k];
+                });
+            });
+            unsafeAtomicAdd(&Kc[(int64_t)(A.c2 + j) * n + B.c2 + l], s * acc);
+        });
+    });
+}
+
+bool launch_k_small(int la, int lb, int lc, int ld, const KArgs &a, hipStream_t st)
+{
+    const int threads = 128;
+    const int64_t blocks = (a.nwork + threads - 1) / threads;
+    if (a.nwork <= 0) return true;
+#define MD_CASE(A_, B_, C_, D_)                                                        \
+    if (la == A_ && lb == B_ && lc == C_ && ld == D_) {                                \
+        hipLaunchKernelGGL((k_small<A_, B_, C_, D_>), dim3((unsigned)blocks), dim3(threads), 0, st, a); \
+        return true;                                                                   \
+    }
+    MD_K_SMALL_LIST(MD_CASE)
+#undef MD_CASE
+    return false;
+}
+
+}  // namespace md

@@ -1,0 +1,46 @@
+// kern_args.hpp -- argument blocks passed by value to the J/K kernels.
+#pragma once
+#include <stdint.h>
+
+#include "md_common.hpp"
+
+namespace md {
+
+// One (bra class, ket class) exchange launch over canonical shell quartets
+// (ab|cd): bra pairs of class X sorted by Q descending, ket pairs of class Y
+// sorted the same way; bra i visits kets j < prefix[i+1]-prefix[i].
+struct KArgs {
+    const CPair *bra;
+    const CPair *ket;
+    const int64_t *prefix;   // [nbra+1] cumulative ket counts
+    int64_t nwork;           // prefix[nbra]
+    int32_t nbra;
+    int32_t same;            // bra class == ket class (then j <= i)
+    const PrimPair *pp;
+    const double *boys;
+    const double *D;         // Cartesian density, ld x ld
+    double *Kacc;            // Cartesian exchange accumulator, ld x ld
+    int32_t ld;
+    double tau_prim;
+};
+
+// J-engine launch: bra primitive pairs of class X against ket contracted
+// pairs [j0, j1) of class Y.
+struct JArgs {
+    const PrimPair *pp;
+    const int32_t *owner;    // contracted pair (index inside class X) of each bra primitive pair
+    const double *Qbra;      // Q of class-X contracted pairs
+    int32_t pbase;           // first primitive pair of class X
+    int32_t nbp;             // number of class-X primitive pairs
+    const CPair *ket;        // class-Y contracted pairs
+    const double *Qket;
+    int32_t nket;
+    int32_t kchunk;          // ket contracted pairs per work item
+    const double *Dt;        // Hermite density of class-Y primitive pairs (nherm(LY) each)
+    int32_t dt_base;         // primitive pair index that Dt[0] belongs to
+    double *Jh;              // Hermite J of class-X primitive pairs (nherm(LX) each)
+    const double *boys;
+    double tau, tau_prim;
+};
+
+}  // namespace md

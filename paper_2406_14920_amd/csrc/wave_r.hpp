@@ -1,0 +1,143 @@
+// wave_r.hpp -- one 64-lane wavefront (one workgroup) builds the auxiliary
+// integrals R^0_{tuv} of a single primitive quartet in LDS (eq. R_recursion):
+// lane m <= L evaluates F_m, then the recursion runs level by level
+// (R^{n}_{...} from R^{n+1}_{...}) with the entries of a level spread over the
+// lanes.  Level 0 is written densely, sR0[(t*(L+1)+u)*(L+1)+v], so that the
+// address of R_{P+Q} is the sum of the addresses of P and Q.
+#pragma once
+#include "md_common.hpp"
+
+namespace md {
+
+// packed (t | u<<8 | v<<16) of shell-ordered Hermite indices, n <= 14
+struct HermDecode {
+    int32_t tuv[nherm(14)];
+    constexpr HermDecode() : tuv()
+    {
+        for (int k = 0; k < nherm(14); ++k) tuv[k] = herm_t(k) | (herm_u(k) << 8) | (herm_v(k) << 16);
+    }
+};
+__constant__ const HermDecode c_herm{};
+
+__device__ __forceinline__ int herm_idx_rt(int t, int u, int v)
+{
+    int n = t + u + v, s = u + v;
+    return n * (n + 1) * (n + 2) / 6 + s * (s + 1) / 2 + v;
+}
+
+// Geometry of one primitive quartet; the same on every lane.
+struct QuartetGeo {
+    double X, Y, Z, T, alpha, pref;
+};
+
+__device__ __forceinline__ QuartetGeo quartet_geo(const PrimPair &pb, const PrimPair &pk)
+{
+    QuartetGeo g;
+    double p = pb.p, q = pk.p;
+    double rpq = 1.0 / (p + q);
+    g.alpha = p * q * rpq;
+    g.X = pb.P[0] - pk.P[0];
+    g.Y = pb.P[1] - pk.P[1];
+    g.Z = pb.P[2] - pk.P[2];
+    g.T = g.alpha * (g.X * g.X + g.Y * g.Y + g.Z * g.Z);
+    g.pref = kTwoPi52 * pb.K * pk.K / (p * q) * sqrt(rpq);
+    return g;
+}
+
+// Phase 1 (no barrier inside): lane m <= L writes sF[m] = pref (-2 alpha)^m F_m.
+template <int L>
+__device__ __forceinline__ void wave_boys(const QuartetGeo &g, const double *__restrict__ btab,
+                                          double *sF, int lane)
+{
+    if (lane <= L) {
+        double F = boys_one(lane, g.T, btab);
+        double s = g.pref, m2a = -2.0 * g.alpha;
+        for (int m = 0; m < lane; ++m) s *= m2a;
+        sF[lane] = s * F;
+    }
+}
+
+// Phase 2: recursion; sF must be visible (barrier before the call).  Ends
+// with a barrier; afterwards sR0 holds the dense level-0 table.
+template <int L>
+__device__ __forceinline__ void wave_recur(const QuartetGeo &g, const double *sF, double *sLa,
+                                           double *sLb, double *sR0, int lane)
+{
+    constexpr int L1 = L + 1;
+    if constexpr (L == 0) {
+        if (lane == 0) sR0[0] = sF[0];
+        __syncthreads();
+        return;
+    } else {
+        const double *prev = sF + L;  // level L holds only (0,0,0)
+        int which = 0;
+        for (int n = L - 1; n >= 0; --n) {
+            const int cnt = nherm(L - n);
+            double *out = which ? sLb : sLa;
+            for (int k = lane; k < cnt; k += 64) {
+                const int code = c_herm.tuv[k];
+                const int t = code & 0xff, u = (code >> 8) & 0xff, v = code >> 16;
+                double val;
+                if (k == 0) {
+                    val = sF[n];
+                } else if (t > 0) {
+                    val = g.X * prev[herm_idx_rt(t - 1, u, v)];
+                    if (t > 1) val += (double)(t - 1) * prev[herm_idx_rt(t - 2, u, v)];
+                } else if (u > 0) {
+                    val = g.Y * prev[herm_idx_rt(t, u - 1, v)];
+                    if (u > 1) val += (double)(u - 1) * prev[herm_idx_rt(t, u - 2, v)];
+                } else {
+                    val = g.Z * prev[herm_idx_rt(t, u, v - 1)];
+                    if (v > 1) val += (double)(v - 1) * prev[herm_idx_rt(t, u, v - 2)];
+                }
+                if (n == 0)
+                    sR0[(t * L1 + u) * L1 + v] = val;
+                else
+                    out[k] = val;
+            }
+            __syncthreads();
+            prev = out;
+            which ^= 1;
+        }
+    }
+}
+
+// 1D Hermite coefficient table of one axis into LDS, layout [i][j][t] with
+// dims (LA+1, LB+1, LA+LB+1); E^{00}_0 = 1 (eq. E_recursion).
+template <int LA, int LB>
+__device__ __forceinline__ void etab_lds(double PA, double PB, double o2p, double *E)
+{
+    constexpr int DJ = LA + LB + 1, DI = (LB + 1) * DJ;
+    for (int i = 0; i <= LA; ++i)
+        for (int j = 0; j <= LB; ++j)
+            for (int t = 0; t < DJ; ++t) E[i * DI + j * DJ + t] = 0.0;
+    E[0] = 1.0;
+    for (int i = 0; i < LA; ++i)
+        for (int t = 0; t <= i + 1; ++t) {
+            double v = (t <= i) ? PA * E[i * DI + t] : 0.0;
+            if (t > 0) v += o2p * E[i * DI + t - 1];
+            if (t + 1 <= i) v += (double)(t + 1) * E[i * DI + t + 1];
+            E[(i + 1) * DI + t] = v;
+        }
+    for (int i = 0; i <= LA; ++i)
+        for (int j = 0; j < LB; ++j)
+            for (int t = 0; t <= i + j + 1; ++t) {
+                double v = (t <= i + j) ? PB * E[i * DI + j * DJ + t] : 0.0;
+                if (t > 0) v += o2p * E[i * DI + j * DJ + t - 1];
+                if (t + 1 <= i + j) v += (double)(t + 1) * E[i * DI + j * DJ + t + 1];
+                E[i * DI + (j + 1) * DJ + t] = v;
+            }
+}
+
+// Cartesian exponents of component c of a shell with angular momentum l (runtime).
+__device__ __forceinline__ void cart_rt(int l, int c, int &x, int &y, int &z)
+{
+    // components ordered x descending: c = (l-x)(l-x+1)/2 + (l-x-y)
+    int s = 0;
+    while ((s + 1) * (s + 2) / 2 <= c) ++s;
+    x = l - s;
+    z = c - s * (s + 1) / 2;
+    y = s - z;
+}
+
+}  // namespace md
