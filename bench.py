@@ -1,0 +1,182 @@
+#!/usr/bin/env python3
+"""Benchmark: one J+K build (one SCF iteration's Coulomb and exchange
+matrices) of the 40-atom workload (840 spherical functions, shells
+s6 s3 s1 p3 p1 d1 f1 per atom, Schwarz threshold 1e-11) on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision fp64|mixed]
+
+Prints one JSON line.  value = contracted spherical ERIs represented per
+second (sum over kept unique shell quartets of prod(2l+1), divided by the
+J+K time); ms_per_step = the J+K build time.  Inputs (P) are resident in HBM
+before the timed region; setup (pairs, Schwarz factors) is outside it.
+
+The roofline entry is for the dominant kernel of the step: its algorithmic
+FLOPs per launch (FLOP model in the design doc, primitive quartets counted by the
+library with the kernels' own screening loops) divided by its average launch
+time, taken from HIP events that the library records on its launch stream
+during the timed steps.  cpu_baseline times the CPU oracle on a bounded random
+sample of the same workload's kept shell quartets.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP64_VALU = 78.6  # TFLOP/s: 256 CU x 4 SIMD x 16 FP64 lanes x 2 FLOP x 2.4 GHz
+METRIC = "J+K build ms/iter + ERIs/s, FP32-mixed vs FP64 at ≤1e-6 max|ΔJ,ΔK|"
+
+
+def _kernel_src_hash() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2406_14920_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hip", ".hpp", ".cpp")):
+            h.update(open(os.path.join(csrc, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def _traffic(kernel_name: str, launches_per_step: int):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic_mol40.json")
+    try:
+        with open(path) as f:
+            d = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if d.get("src_hash") != _kernel_src_hash():
+        return None
+    row = d.get("kernels", {}).get(kernel_name)
+    if not row:
+        return None
+    return row.get("bytes_per_launch")
+
+
+def cpu_baseline(mol, target_s: float = 15.0):
+    """Oracle rate on a random sample of the workload's kept shell quartets."""
+    import oracle
+    B = oracle.OBasis(mol)
+    Q = B.schwarz()
+    tau = mol.tau_schwarz
+    tau_prim = 1e-2 * tau
+    B.prim_bounds()
+    n = B.nshell
+    pairs = np.array([(a, b) for a in range(n) for b in range(a + 1)], np.int32)
+    qp = Q[pairs[:, 0], pairs[:, 1]]
+    rng = np.random.default_rng(2024)
+    nsph = 2 * B.l + 1
+
+    def draw(k):
+        out = []
+        while len(out) < k:
+            i = rng.integers(len(pairs), size=4 * k)
+            j = rng.integers(len(pairs), size=4 * k)
+            ok = qp[i] * qp[j] >= tau
+            for x, y in zip(i[ok], j[ok]):
+                out.append((pairs[x, 0], pairs[x, 1], pairs[y, 0], pairs[y, 1]))
+        return np.array(out[:k], np.int32)
+
+    q = draw(200)
+    t = time.perf_counter()
+    oracle.quartet_batch(B, q, tau_prim)
+    dt = time.perf_counter() - t
+    k = int(min(2_000_000, max(400, 200 * target_s / max(dt, 1e-3))))
+    q = draw(k)
+    t = time.perf_counter()
+    oracle.quartet_batch(B, q, tau_prim)
+    dt = time.perf_counter() - t
+    eris = float(np.sum(nsph[q[:, 0]] * nsph[q[:, 1]] * nsph[q[:, 2]] * nsph[q[:, 3]]))
+    return {"value": eris / dt, "unit": "ERIs/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": "%d uniformly drawn kept shell quartets of mol40 (each evaluated once, "
+                      "spherical blocks), %.1f s" % (k, dt),
+            "sample_seconds": dt}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--profile-json", default=None, help="write the per-kernel table here")
+    a = ap.parse_args()
+    if a.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(see DESIGN.md, 'How the path would shard'); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2406_14920_amd import JK, abi, synth
+
+    mol = synth.mol40()
+    t0 = time.perf_counter()
+    jk = JK.from_molecule(mol, precision=a.precision)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    P = torch.tensor(mol.P, dtype=torch.float64, device="cuda")
+    st = jk.stats()
+    print("setup %.2fs nbf=%d quartets=%d eris_sph=%.3e flopsK=%.3e flopsJ=%.3e" % (
+        setup_s, st["nbf"], st["n_quartets"], st["eris_sph"], st["model_flops_k"], st["model_flops_j"]),
+        file=sys.stderr, flush=True)
+
+    for _ in range(a.warmup):
+        jk.jk(P)
+    torch.cuda.synchronize()
+
+    abi.eri_set_profiling(jk.ctx, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        J, K = jk.jk(P)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    prof = abi.eri_profile_read(jk.ctx)
+    abi.eri_set_profiling(jk.ctx, False)
+    ms = dt / a.steps * 1e3
+    value = st["eris_sph"] / (ms / 1e3)
+
+    prof.sort(key=lambda r: -r["ms"])
+    top = prof[0]
+    avg_ms = top["ms"] / top["launches"]
+    achieved = top["flops"] / (avg_ms * 1e-3) / 1e12
+    kern_total = sum(r["ms"] for r in prof) / a.steps
+    traffic = _traffic(top["name"], 1)
+    roof = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_VALU, "unit": "TFLOP/s",
+            "frac": achieved / PEAK_FP64_VALU, "traffic": traffic, "kernel": top["name"],
+            "kernel_avg_ms": avg_ms, "kernel_share": top["ms"] / a.steps / ms}
+    flops_total = st["model_flops_k"] + st["model_flops_j"]
+    out = {
+        "metric": METRIC, "value": value, "unit": "ERIs/s", "n_gpus": 1, "steps": a.steps,
+        "warmup": a.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64" if a.precision == "fp64" else "f32+f64",
+        "data": "synthetic (seeded 40-atom cluster, random orthonormal density)",
+        "config": {"workload": "mol40: 40 atoms, s6 s3 s1 p3 p1 d1 f1 per atom, 840 spherical bf, "
+                               "Schwarz 1e-11, primitive 1e-13", "nbf": st["nbf"],
+                   "quartets": st["n_quartets"], "precision": a.precision},
+        "path_tflops": flops_total / (ms * 1e-3) / 1e12,
+        "path_frac_fp64_peak": flops_total / (ms * 1e-3) / 1e12 / PEAK_FP64_VALU,
+        "kernel_ms_per_step": kern_total,
+        "roofline": roof,
+    }
+    if a.profile_json:
+        with open(a.profile_json, "w") as f:
+            json.dump({"steps": a.steps, "ms_per_step": ms, "kernels": prof}, f, indent=1)
+    jk.close()
+    if not a.no_cpu:
+        cb = cpu_baseline(mol)
+        out["cpu_baseline"] = {k: cb[k] for k in ("value", "unit", "cores", "kind", "sample")}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

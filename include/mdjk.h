@@ -102,6 +102,15 @@ typedef struct {
     double  last_ms;             /* device time of the last build_jk / jk_grad (ms) */
 } eri_stats_t;
 
+/* Device time of one kernel family, accumulated while profiling is on. */
+typedef struct {
+    char    name[40];       /* kernel and class, e.g. "k_wave(31|10)", "jeng_small(4,2)" */
+    int32_t launches;       /* launches accumulated */
+    double  ms;             /* summed device time (HIP events recorded on the launch stream) */
+    double  flops;          /* algorithmic FLOPs of one launch (FLOP model) */
+    int64_t prim_quartets;  /* primitive quartets one launch evaluates (0 if not applicable) */
+} eri_kernel_time;
+
 /* Fill opts with defaults: schwarz 1e-11, prim 1e-2*schwarz, mixed 1e-5,
  * FP64, spherical, default stream. */
 void eri_default_opts(eri_opts *opts);
@@ -132,6 +141,13 @@ int build_jk(eri_ctx *ctx, const double *P, double *J, double *K);
  * (SI eqs. si_dE_J, si_dE_K; the density-derivative terms are absent).
  * grad: device [natom*3]; E: device [1] or NULL.  Asynchronous. */
 int jk_grad(eri_ctx *ctx, const double *P, double *grad, double *E);
+
+/* Profiling: while on, every kernel launch of later calls is bracketed by HIP
+ * events on the launch stream; eri_profile_read synchronises, reports the
+ * accumulated per-kernel times (up to cap entries, *n set to the count) and
+ * clears them.  Profiling adds event records between launches only. */
+int eri_set_profiling(eri_ctx *ctx, int32_t on);
+int eri_profile_read(eri_ctx *ctx, eri_kernel_time *out, int32_t cap, int32_t *n);
 
 /* Counters of the context (host struct).  Synchronises the stream. */
 int eri_stats(const eri_ctx *ctx, eri_stats_t *out);

@@ -69,6 +69,8 @@ def lib():
                                              ctypes.POINTER(ctypes.c_int64), dp]
         L.oracle_grad.argtypes = bas + [dp, ip, ip, ctypes.c_int32, dp, dp] + qp + [ctypes.c_double,
                                         ctypes.c_double, ctypes.c_double, ctypes.c_int, dp]
+        L.oracle_quartet_batch.argtypes = bas + [dp, ip] + qp + [ctypes.c_int64, ip]
+        L.oracle_quartet_batch.restype = ctypes.c_double
         L.oracle_num_threads.restype = ctypes.c_int
         _lib = L
     return _lib
@@ -251,6 +253,13 @@ def grad(mol, P=None, tau=None, wj=1.0, wk=1.0, only_atom=-1, Q=None, tau_prim=N
     lib().oracle_grad(*B.args(), _dp(B.T), _ip(B.Toff), _ip(B.ao_off), B.nbf, _dp(P), _dp(Q),
                       *B.screen_args(_tau_prim(tau, tau_prim)), float(tau), float(wj), float(wk), int(only_atom), _dp(g))
     return g
+
+
+def quartet_batch(B: "OBasis", quartets, tau_prim: float) -> float:
+    """Evaluate the spherical blocks of shell quartets [(a,b,c,d), ...] (checksum)."""
+    q4 = np.ascontiguousarray(np.asarray(quartets, np.int32).reshape(-1, 4))
+    return float(lib().oracle_quartet_batch(*B.args(), _dp(B.T), _ip(B.Toff), *B.screen_args(tau_prim),
+                                            int(q4.shape[0]), _ip(q4)))
 
 
 def num_threads() -> int:

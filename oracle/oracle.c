@@ -670,6 +670,38 @@ void oracle_grad(int32_t nshell, int32_t natom, const int32_t *atom, const int32
     }
 }
 
+/* Evaluate the spherical blocks of a list of shell quartets (q4[4*i..4*i+3])
+ * in parallel; returns the sum of all block elements (a checksum).  Used to
+ * time the oracle on a sample of a workload. */
+double oracle_quartet_batch(int32_t nshell, int32_t natom, const int32_t *atom, const int32_t *l,
+                            const int32_t *nprim, const int32_t *off, const double *exps,
+                            const double *coefs, const double *xyz, const double *T, const int *Toff,
+                            const double *qprim, int32_t nprim_tot, double tau_prim,
+                            int64_t n, const int32_t *q4)
+{
+    basis_t B = mkbasis(nshell, natom, atom, l, nprim, off, exps, coefs, xyz);
+    B.qprim = qprim; B.nprim_tot = nprim_tot; B.tau_prim = tau_prim;
+    double total = 0.0;
+#pragma omp parallel reduction(+ : total)
+    {
+        scratch_t *S = (scratch_t *)malloc(sizeof(scratch_t));
+        double *blk = (double *)malloc(sizeof(double) * 10000);
+        double *sph = (double *)malloc(sizeof(double) * 10000);
+        double *w1 = (double *)malloc(sizeof(double) * 10000);
+#pragma omp for schedule(dynamic, 16)
+        for (int64_t i = 0; i < n; ++i) {
+            const int32_t *q = q4 + 4 * i;
+            int L[4] = {l[q[0]], l[q[1]], l[q[2]], l[q[3]]};
+            shell_block(&B, q[0], q[1], q[2], q[3], -1, 0, blk, S);
+            to_sph(L, T, Toff, blk, sph, w1);
+            int nn = (2 * L[0] + 1) * (2 * L[1] + 1) * (2 * L[2] + 1) * (2 * L[3] + 1);
+            for (int k = 0; k < nn; ++k) total += sph[k];
+        }
+        free(w1); free(sph); free(blk); free(S);
+    }
+    return total;
+}
+
 int oracle_num_threads(void)
 {
 #ifdef _OPENMP

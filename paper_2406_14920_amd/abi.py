@@ -51,8 +51,14 @@ class eri_stats_t(ctypes.Structure):
                 ("last_ms", ctypes.c_double)]
 
 
+class eri_kernel_time(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 40), ("launches", ctypes.c_int32), ("ms", ctypes.c_double),
+                ("flops", ctypes.c_double), ("prim_quartets", ctypes.c_int64)]
+
+
 EXPORTS = ["eri_default_opts", "eri_setup", "eri_nbf", "eri_set_geometry", "eri_set_precision",
-           "build_jk", "jk_grad", "eri_stats", "eri_destroy", "eri_last_error"]
+           "build_jk", "jk_grad", "eri_set_profiling", "eri_profile_read", "eri_stats", "eri_destroy",
+           "eri_last_error"]
 
 _lib = None
 
@@ -77,6 +83,9 @@ def load(path: str = LIB_PATH):
     L.build_jk.argtypes = [vp, vp, vp, vp]
     L.jk_grad.argtypes = [vp, vp, vp, vp]
     L.eri_stats.argtypes = [vp, ctypes.POINTER(eri_stats_t)]
+    L.eri_set_profiling.argtypes = [vp, ctypes.c_int32]
+    L.eri_profile_read.argtypes = [vp, ctypes.POINTER(eri_kernel_time), ctypes.c_int32,
+                                   ctypes.POINTER(ctypes.c_int32)]
     L.eri_destroy.argtypes = [vp]
     L.eri_last_error.restype = ctypes.c_char_p
     for name in EXPORTS:
@@ -172,6 +181,19 @@ def eri_stats(ctx: int) -> dict:
     s = eri_stats_t()
     _check(load().eri_stats(ctypes.c_void_p(ctx), ctypes.byref(s)))
     return {name: getattr(s, name) for name, _ in eri_stats_t._fields_}
+
+
+def eri_set_profiling(ctx: int, on: bool) -> None:
+    _check(load().eri_set_profiling(ctypes.c_void_p(ctx), 1 if on else 0))
+
+
+def eri_profile_read(ctx: int) -> list:
+    cap = 512
+    arr = (eri_kernel_time * cap)()
+    n = ctypes.c_int32()
+    _check(load().eri_profile_read(ctypes.c_void_p(ctx), arr, cap, ctypes.byref(n)))
+    return [{"name": arr[i].name.decode(), "launches": arr[i].launches, "ms": arr[i].ms,
+             "flops": arr[i].flops, "prim_quartets": arr[i].prim_quartets} for i in range(min(n.value, cap))]
 
 
 def eri_destroy(ctx: int) -> None:

@@ -19,6 +19,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <memory>
 #include <mutex>
 #include <numeric>
@@ -26,6 +27,7 @@
 #include <vector>
 
 #include "../../include/mdjk.h"
+#include "class_lists.hpp"
 #include "launch.hpp"
 #include "md_common.hpp"
 
@@ -64,6 +66,41 @@ constexpr int kPairClasses = 10;
 constexpr int kPairL[kPairClasses][2] = {{0, 0}, {1, 0}, {1, 1}, {2, 0}, {2, 1},
                                          {2, 2}, {3, 0}, {3, 1}, {3, 2}, {3, 3}};
 int pair_class(int la, int lb) { return la * (la + 1) / 2 + lb; }
+
+bool uses_k_pair(int la, int lb, int lc, int ld)
+{
+#define MD_IS(A_, B_, C_, D_) if (la == A_ && lb == B_ && lc == C_ && ld == D_) return true;
+    MD_K_PAIR_PART0(MD_IS) MD_K_PAIR_PART1(MD_IS) MD_K_PAIR_PART2(MD_IS) MD_K_PAIR_PART3(MD_IS)
+    MD_K_PAIR_PART4(MD_IS) MD_K_PAIR_PART5(MD_IS) MD_K_PAIR_PART6(MD_IS) MD_K_PAIR_PART7(MD_IS)
+#undef MD_IS
+    return false;
+}
+
+// ---------------------------------------------------------------------------
+// Algorithmic FLOP model (frozen before tuning; the design doc states it):
+//   Boys 3L+14, R 3(C(L+4,4)-(L+1)) + (L+1) per primitive quartet,
+//   K contraction sum_cd 2 nH(la+lb) nnz(cd) + sum_{ab,cd} 2 nnz(ab) per
+//   primitive quartet and 8 nA nB nC nD digestion per shell quartet,
+//   J-engine 2 nH(LX) nH(LY) per (bra, ket) primitive pair.
+// ---------------------------------------------------------------------------
+double binom4(int n) { return n < 4 ? 0.0 : (double)n * (n - 1) * (n - 2) * (n - 3) / 24.0; }
+double fl_boys(int L) { return 3.0 * L + 14.0; }
+double fl_r(int L) { return 3.0 * (binom4(L + 4) - (L + 1)) + (L + 1); }
+double sum_nnz(int la, int lb)
+{
+    double s = 0.0;
+    for (int a = 0; a < ncart(la); ++a)
+        for (int b = 0; b < ncart(lb); ++b) s += box_nnz(la, a, lb, b);
+    return s;
+}
+double fl_k_prim(int la, int lb, int lc, int ld)
+{
+    const int L = la + lb + lc + ld;
+    return fl_boys(L) + fl_r(L) + 2.0 * nherm(la + lb) * sum_nnz(lc, ld) +
+           2.0 * ncart(lc) * ncart(ld) * sum_nnz(la, lb);
+}
+double fl_k_digest(int la, int lb, int lc, int ld) { return 8.0 * ncart(la) * ncart(lb) * ncart(lc) * ncart(ld); }
+double fl_j_prim(int lx, int ly) { return fl_boys(lx + ly) + fl_r(lx + ly) + 2.0 * nherm(lx) * nherm(ly); }
 
 // ---------------------------------------------------------------------------
 // Boys table: F_m(i h) for m < kBoysNM.  For each grid point the top order
@@ -152,6 +189,8 @@ struct eri_ctx {
         int X, Y;
         int64_t off;    // into prefix buffer
         int64_t nwork;
+        int64_t choff;  // into chunk buffer (bra-shared kernel), -1 if unused
+        int nchunks;
     };
     std::vector<KWork> kwork;
     size_t dt_off[kPairClasses] = {}, jh_off[kPairClasses] = {};
@@ -162,13 +201,37 @@ struct eri_ctx {
     DevBuf<PrimPair> d_pp;
     DevBuf<int32_t> d_owner;
     DevBuf<int64_t> d_prefix;
+    DevBuf<int2> d_chunks;
+    DevBuf<double> d_eprod;
+    size_t eprod_off[kPairClasses] = {};
     DevBuf<double> d_boys;
     DevBuf<double> d_Pc, d_Jacc, d_Kacc, d_Dt, d_Jh;
     DevBuf<int32_t> d_soc, d_sos, d_l, d_coff, d_soff;
 
+    // primitive-quartet counts per exchange launch and per J-engine (X, Y)
+    std::vector<int64_t> kprim;
+    int64_t jprim[kPairClasses][kPairClasses] = {};
+
+    // profiling
+    struct Rec {
+        std::string name;
+        hipEvent_t a, b;
+        double flops;
+        int64_t pq;
+    };
+    struct Acc {
+        int launches = 0;
+        double ms = 0, flops = 0;
+        int64_t pq = 0;
+    };
+    bool profile = false;
+    std::vector<Rec> pending;
+    std::map<std::string, Acc> prof;
+
     // stats
     int64_t n_quartets = 0;
     double eris_sph = 0, eris_cart = 0;
+    double model_flops_k = 0, model_flops_j = 0;
     double last_ms = 0;
 };
 
@@ -345,12 +408,13 @@ void build_pairs(eri_ctx *c)
 
     // 4. exchange work lists
     std::vector<int64_t> prefix;
+    std::vector<int2> chunks;
     c->kwork.clear();
     c->n_quartets = 0;
     c->eris_sph = c->eris_cart = 0.0;
     for (int X = 0; X < kPairClasses; ++X)
         for (int Y = 0; Y <= X; ++Y) {
-            eri_ctx::KWork w{X, Y, (int64_t)prefix.size(), 0};
+            eri_ctx::KWork w{X, Y, (int64_t)prefix.size(), 0, -1, 0};
             const double *QX = c->Q.data() + c->cp_base[X];
             const double *QY = c->Q.data() + c->cp_base[Y];
             const int nX = c->ncp[X], nY = c->ncp[Y];
@@ -369,6 +433,14 @@ void build_pairs(eri_ctx *c)
                 prefix.push_back(acc);
             }
             w.nwork = acc;
+            if (uses_k_pair(kPairL[X][0], kPairL[X][1], kPairL[Y][0], kPairL[Y][1]) && acc > 0) {
+                w.choff = (int64_t)chunks.size();
+                for (int i = 0; i < nX; ++i) {
+                    const int64_t cnt = prefix[w.off + i + 1] - prefix[w.off + i];
+                    for (int64_t j0 = 0; j0 < cnt; j0 += 64) chunks.push_back(make_int2(i, (int)j0));
+                }
+                w.nchunks = (int)((int64_t)chunks.size() - w.choff);
+            }
             c->kwork.push_back(w);
             c->n_quartets += acc;
             const int la = kPairL[X][0], lb = kPairL[X][1], lc = kPairL[Y][0], ld = kPairL[Y][1];
@@ -376,6 +448,19 @@ void build_pairs(eri_ctx *c)
             c->eris_cart += (double)acc * ncart(la) * ncart(lb) * ncart(lc) * ncart(ld);
         }
     c->d_prefix.upload(prefix);
+    c->d_chunks.upload(chunks);
+
+    // Hermite products of every primitive pair (bra/ket data of the bra-shared kernel)
+    size_t ep = 0;
+    for (int X = 0; X < kPairClasses; ++X) {
+        c->eprod_off[X] = ep;
+        ep += (size_t)c->npp[X] * eprod_size(kPairL[X][0], kPairL[X][1]);
+    }
+    c->d_eprod.alloc(std::max<size_t>(ep, 1));
+    for (int X = 0; X < kPairClasses; ++X)
+        launch_eprod(kPairL[X][0], kPairL[X][1], c->d_pp.p, c->pp_base[X], c->npp[X], c->d_eprod.p + c->eprod_off[X],
+                     c->st);
+    HIPCHK(hipGetLastError());
 
     // 5. Hermite density / Hermite J storage
     size_t dt = 0;
@@ -386,6 +471,58 @@ void build_pairs(eri_ctx *c)
     }
     c->d_Dt.alloc(std::max<size_t>(dt, 1));
     c->d_Jh.alloc(std::max<size_t>(dt, 1));
+
+    // 6. primitive quartets each launch evaluates (same loops as the kernels)
+    const size_t ncount = c->kwork.size() + kPairClasses * kPairClasses;
+    DevBuf<unsigned long long> cnt;
+    cnt.alloc(ncount);
+    HIPCHK(hipMemsetAsync(cnt.p, 0, ncount * sizeof(unsigned long long), c->st));
+    for (size_t wi = 0; wi < c->kwork.size(); ++wi) {
+        const auto &w = c->kwork[wi];
+        KArgs a{};
+        a.bra = c->d_cp.p + c->cp_base[w.X];
+        a.ket = c->d_cp.p + c->cp_base[w.Y];
+        a.prefix = c->d_prefix.p + w.off;
+        a.nwork = w.nwork;
+        a.nbra = c->ncp[w.X];
+        a.pp = c->d_pp.p;
+        a.tau_prim = c->opts.prim_thresh;
+        launch_k_count(a, cnt.p + wi, c->st);
+    }
+    for (int X = 0; X < kPairClasses; ++X)
+        for (int Y = 0; Y < kPairClasses; ++Y) {
+            JArgs a{};
+            a.pp = c->d_pp.p;
+            a.owner = c->d_owner.p + c->pp_base[X];
+            a.Qbra = c->d_Q.p + c->cp_base[X];
+            a.pbase = c->pp_base[X];
+            a.nbp = c->npp[X];
+            a.ket = c->d_cp.p + c->cp_base[Y];
+            a.Qket = c->d_Q.p + c->cp_base[Y];
+            a.nket = c->ncp[Y];
+            a.tau = tau;
+            a.tau_prim = c->opts.prim_thresh;
+            launch_j_count(a, cnt.p + c->kwork.size() + X * kPairClasses + Y, c->st);
+        }
+    HIPCHK(hipGetLastError());
+    std::vector<unsigned long long> hc(ncount);
+    HIPCHK(hipStreamSynchronize(c->st));
+    HIPCHK(hipMemcpy(hc.data(), cnt.p, ncount * sizeof(unsigned long long), hipMemcpyDeviceToHost));
+    c->kprim.assign(c->kwork.size(), 0);
+    c->model_flops_k = 0.0;
+    for (size_t wi = 0; wi < c->kwork.size(); ++wi) {
+        const auto &w = c->kwork[wi];
+        c->kprim[wi] = (int64_t)hc[wi];
+        const int la = kPairL[w.X][0], lb = kPairL[w.X][1], lc = kPairL[w.Y][0], ld = kPairL[w.Y][1];
+        c->model_flops_k += (double)hc[wi] * fl_k_prim(la, lb, lc, ld) + (double)w.nwork * fl_k_digest(la, lb, lc, ld);
+    }
+    c->model_flops_j = 0.0;
+    for (int X = 0; X < kPairClasses; ++X)
+        for (int Y = 0; Y < kPairClasses; ++Y) {
+            c->jprim[X][Y] = (int64_t)hc[c->kwork.size() + X * kPairClasses + Y];
+            c->model_flops_j += (double)c->jprim[X][Y] *
+                                fl_j_prim(kPairL[X][0] + kPairL[X][1], kPairL[Y][0] + kPairL[Y][1]);
+        }
 }
 
 void build_basis(eri_ctx *c, const eri_shell *shells, const eri_atom *atoms)
@@ -452,14 +589,39 @@ ShellMap shell_map(const eri_ctx *c)
 
 bool ctx_ok(const eri_ctx *c) { return c && c->magic == 0x4d444a4b; }
 
+template <typename F>
+void timed(eri_ctx *c, const std::string &name, double flops, int64_t pq, F &&launch)
+{
+    if (!c->profile) {
+        launch();
+        return;
+    }
+    eri_ctx::Rec r{name, nullptr, nullptr, flops, pq};
+    HIPCHK(hipEventCreate(&r.a));
+    HIPCHK(hipEventCreate(&r.b));
+    HIPCHK(hipEventRecord(r.a, c->st));
+    launch();
+    HIPCHK(hipEventRecord(r.b, c->st));
+    c->pending.push_back(r);
+}
+
+std::string cls_name(const char *k, int a, int b, int cc, int d)
+{
+    char buf[40];
+    snprintf(buf, sizeof(buf), "%s(%d%d|%d%d)", k, a, b, cc, d);
+    return buf;
+}
+
 void run_j(eri_ctx *c)
 {
     hipStream_t st = c->st;
     const int nc = c->nbf_cart;
     for (int Y = 0; Y < kPairClasses; ++Y)
-        launch_hermite_density(kPairL[Y][0], kPairL[Y][1], c->d_cp.p + c->cp_base[Y], c->ncp[Y], c->d_pp.p,
-                               c->d_Pc.p, nc, c->d_Dt.p + c->dt_off[Y], c->pp_base[Y], st);
-    launch_fill_zero(c->d_Jh.p, (int64_t)c->d_Jh.n, st);
+        timed(c, cls_name("hdens", kPairL[Y][0], kPairL[Y][1], 0, 0), 0.0, 0, [&] {
+            launch_hermite_density(kPairL[Y][0], kPairL[Y][1], c->d_cp.p + c->cp_base[Y], c->ncp[Y], c->d_pp.p,
+                                   c->d_Pc.p, nc, c->d_Dt.p + c->dt_off[Y], c->pp_base[Y], st);
+        });
+    timed(c, "fill_zero", 0.0, 0, [&] { launch_fill_zero(c->d_Jh.p, (int64_t)c->d_Jh.n, st); });
     for (int X = 0; X < kPairClasses; ++X) {
         if (c->npp[X] == 0) continue;
         for (int Y = 0; Y < kPairClasses; ++Y) {
@@ -480,12 +642,18 @@ void run_j(eri_ctx *c)
             a.boys = c->d_boys.p;
             a.tau = c->opts.schwarz_thresh;
             a.tau_prim = c->opts.prim_thresh;
-            launch_jeng(kPairL[X][0] + kPairL[X][1], kPairL[Y][0] + kPairL[Y][1], a, st);
+            const int lx = kPairL[X][0] + kPairL[X][1], ly = kPairL[Y][0] + kPairL[Y][1];
+            timed(c, cls_name(lx + ly <= 5 ? "jeng_small" : "jeng_wave", kPairL[X][0], kPairL[X][1], kPairL[Y][0],
+                              kPairL[Y][1]),
+                  (double)c->jprim[X][Y] * fl_j_prim(lx, ly), c->jprim[X][Y],
+                  [&] { launch_jeng(lx, ly, a, st); });
         }
     }
     for (int X = 0; X < kPairClasses; ++X)
-        launch_hermite_to_cart(kPairL[X][0], kPairL[X][1], c->d_cp.p + c->cp_base[X], c->ncp[X], c->d_pp.p,
-                               c->d_Jh.p + c->jh_off[X], c->pp_base[X], c->d_Jacc.p, nc, st);
+        timed(c, cls_name("herm2cart", kPairL[X][0], kPairL[X][1], 0, 0), 0.0, 0, [&] {
+            launch_hermite_to_cart(kPairL[X][0], kPairL[X][1], c->d_cp.p + c->cp_base[X], c->ncp[X], c->d_pp.p,
+                                   c->d_Jh.p + c->jh_off[X], c->pp_base[X], c->d_Jacc.p, nc, st);
+        });
 }
 
 void run_k(eri_ctx *c)
@@ -507,10 +675,41 @@ void run_k(eri_ctx *c)
         a.ld = c->nbf_cart;
         a.tau_prim = c->opts.prim_thresh;
         const int la = kPairL[w.X][0], lb = kPairL[w.X][1], lc = kPairL[w.Y][0], ld = kPairL[w.Y][1];
-        bool ok = launch_k_small(la, lb, lc, ld, a, st) || launch_k_wave_0(la, lb, lc, ld, a, st) ||
-                  launch_k_wave_1(la, lb, lc, ld, a, st) || launch_k_wave_2(la, lb, lc, ld, a, st) ||
-                  launch_k_wave_3(la, lb, lc, ld, a, st) || launch_k_wave_4(la, lb, lc, ld, a, st) ||
-                  launch_k_wave_5(la, lb, lc, ld, a, st);
+        const size_t wi = &w - c->kwork.data();
+        const int64_t pq = wi < c->kprim.size() ? c->kprim[wi] : 0;
+        const double fl = (double)pq * fl_k_prim(la, lb, lc, ld) + (double)w.nwork * fl_k_digest(la, lb, lc, ld);
+        bool ok = false;
+        if (w.choff >= 0) {
+            KPArgs p;
+            p.bra = a.bra;
+            p.ket = a.ket;
+            p.chunks = c->d_chunks.p + w.choff;
+            p.prefix = a.prefix;
+            p.same = a.same;
+            p.pp = a.pp;
+            p.eprod_bra = c->d_eprod.p + c->eprod_off[w.X];
+            p.pbase_bra = c->pp_base[w.X];
+            p.eprod_ket = c->d_eprod.p + c->eprod_off[w.Y];
+            p.pbase_ket = c->pp_base[w.Y];
+            p.boys = a.boys;
+            p.D = a.D;
+            p.Kacc = a.Kacc;
+            p.ld = a.ld;
+            p.tau_prim = a.tau_prim;
+            const int nch = w.nchunks;
+            timed(c, cls_name("kp", la, lb, lc, ld), fl, pq, [&] {
+                ok = launch_k_pair_0(la, lb, lc, ld, p, nch, st) || launch_k_pair_1(la, lb, lc, ld, p, nch, st) ||
+                     launch_k_pair_2(la, lb, lc, ld, p, nch, st) || launch_k_pair_3(la, lb, lc, ld, p, nch, st) ||
+                     launch_k_pair_4(la, lb, lc, ld, p, nch, st) || launch_k_pair_5(la, lb, lc, ld, p, nch, st) ||
+                     launch_k_pair_6(la, lb, lc, ld, p, nch, st) || launch_k_pair_7(la, lb, lc, ld, p, nch, st);
+            });
+        } else
+        timed(c, cls_name("k", la, lb, lc, ld), fl, pq, [&] {
+            ok = launch_k_small(la, lb, lc, ld, a, st) || launch_k_wave_0(la, lb, lc, ld, a, st) ||
+                 launch_k_wave_1(la, lb, lc, ld, a, st) || launch_k_wave_2(la, lb, lc, ld, a, st) ||
+                 launch_k_wave_3(la, lb, lc, ld, a, st) || launch_k_wave_4(la, lb, lc, ld, a, st) ||
+                 launch_k_wave_5(la, lb, lc, ld, a, st);
+        });
         if (!ok) {
             set_err(ERI_ESTATE, "no exchange kernel for class (%d%d|%d%d)", la, lb, lc, ld);
             throw HipError{ERI_ESTATE};
@@ -647,7 +846,54 @@ int eri_stats(const eri_ctx *ctx, eri_stats_t *out)
     out->n_quartets = ctx->n_quartets;
     out->eris_sph = ctx->eris_sph;
     out->eris_cart = ctx->eris_cart;
+    out->model_flops_k = ctx->model_flops_k;
+    out->model_flops_j = ctx->model_flops_j;
     out->last_ms = ctx->last_ms;
+    return ERI_OK;
+}
+
+int eri_set_profiling(eri_ctx *ctx, int32_t on)
+{
+    if (!ctx_ok(ctx)) return set_err(ERI_ESTATE, "invalid context");
+    ctx->profile = on != 0;
+    return ERI_OK;
+}
+
+int eri_profile_read(eri_ctx *ctx, eri_kernel_time *out, int32_t cap, int32_t *n)
+{
+    if (!ctx_ok(ctx)) return set_err(ERI_ESTATE, "invalid context");
+    if (!n || (cap > 0 && !out)) return set_err(ERI_EINVAL, "null output");
+    try {
+        HIPCHK(hipStreamSynchronize(ctx->st));
+        for (auto &r : ctx->pending) {
+            float ms = 0.f;
+            HIPCHK(hipEventElapsedTime(&ms, r.a, r.b));
+            auto &acc = ctx->prof[r.name];
+            acc.launches += 1;
+            acc.ms += ms;
+            acc.flops = r.flops;
+            acc.pq = r.pq;
+            (void)hipEventDestroy(r.a);
+            (void)hipEventDestroy(r.b);
+        }
+        ctx->pending.clear();
+    } catch (const HipError &e) {
+        return e.code;
+    }
+    int k = 0;
+    for (auto &kv : ctx->prof) {
+        if (k < cap) {
+            memset(&out[k], 0, sizeof(eri_kernel_time));
+            snprintf(out[k].name, sizeof(out[k].name), "%s", kv.first.c_str());
+            out[k].launches = kv.second.launches;
+            out[k].ms = kv.second.ms;
+            out[k].flops = kv.second.flops;
+            out[k].prim_quartets = kv.second.pq;
+        }
+        ++k;
+    }
+    *n = k;
+    ctx->prof.clear();
     return ERI_OK;
 }
 
@@ -656,6 +902,10 @@ int eri_destroy(eri_ctx *ctx)
     if (!ctx) return ERI_OK;
     if (!ctx_ok(ctx)) return set_err(ERI_ESTATE, "invalid context");
     if (ctx->st) (void)hipStreamSynchronize(ctx->st); else (void)hipDeviceSynchronize();
+    for (auto &r : ctx->pending) {
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+    }
     ctx->magic = 0;
     delete ctx;
     return ERI_OK;

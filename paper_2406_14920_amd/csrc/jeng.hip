@@ -154,10 +154,9 @@ template <int LX, int LY>
 __global__ __launch_bounds__(64) void jeng_wave(JArgs a)
 {
     constexpr int L = LX + LY, L1 = L + 1, NX = nherm(LX), NY = nherm(LY);
-    constexpr int NLEV = nherm(L - 1);
     __shared__ double sR0[L1 * L1 * L1];
-    __shared__ double sLev[2 * NLEV];
     __shared__ double sF[L + 1];
+    __shared__ double sPow[3 * (L + 1)];
     const int lane = threadIdx.x;
     const int g = blockIdx.x;
     const PrimPair pb = a.pp[a.pbase + g];
@@ -186,8 +185,10 @@ __global__ __launch_bounds__(64) void jeng_wave(JArgs a)
             if (qi * pk.q < a.tau_prim) break;
             const QuartetGeo geo = quartet_geo(pb, pk);
             wave_boys<L>(geo, a.boys, sF, lane);
+            wave_powers<L>(geo, sPow, lane);
             __syncthreads();
-            wave_recur<L>(geo, sF, sLev, sLev + NLEV, sR0, lane);
+            wave_r0<L>(sF, sPow, sR0, lane);
+            __syncthreads();
             const double *dt = a.Dt + (int64_t)(B.poff + kp - a.dt_base) * NY;
 #pragma unroll
             for (int r = 0; r < 2; ++r) {

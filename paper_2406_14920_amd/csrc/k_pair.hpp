@@ -1,0 +1,218 @@
+// k_pair.hpp -- exchange (K) with the bra shared by a wavefront: one
+// workgroup (64 lanes) takes one bra contracted pair (ab| and 64 consecutive
+// kets |cd) of its work list, one ket per lane.  The bra's Hermite products
+// E^{ab}_t come precomputed from HBM through wave-uniform loads, so the
+// registers hold only what differs per lane: the auxiliary integrals R^0 of
+// the lane's primitive quartet (eq. R_recursion), the ket Hermite products,
+// and a chunk of the contracted Cartesian block
+//     (ab|cd) = sum_t E^{ab}_t sum_s (-1)^{|s|} E^{cd}_s R_{t+s}    (eq. eri_formula)
+// accumulated over the primitive quartets.  Blocks larger than the register
+// budget are produced in compile-time passes over (ab, cd) chunks, R being
+// rebuilt per pass.  Each finished chunk is digested by the lane into the
+// four exchange blocks of the 8-fold symmetry and added to the accumulator.
+#pragma once
+#include "kern_args.hpp"
+#include "md_device.hpp"
+
+namespace md {
+
+template <int LA, int LB>
+struct EprodOff {
+    static constexpr int NA = ncart(LA), NB = ncart(LB), NAB = NA * NB;
+    int off[NAB + 1];
+    constexpr EprodOff() : off()
+    {
+        int o = 0;
+        for (int ab = 0; ab < NAB; ++ab) {
+            off[ab] = o;
+            o += box_nnz(LA, ab / NB, LB, ab % NB);
+        }
+        off[NAB] = o;
+    }
+};
+
+
+template <int LA, int LB, int LC, int LD>
+struct KPairCfg {
+    static constexpr int NA = ncart(LA), NB = ncart(LB), NC = ncart(LC), ND = ncart(LD);
+    static constexpr int NAB = NA * NB, NCD = NC * ND;
+    static constexpr int L = LA + LB + LC + LD, LAB = LA + LB, LCD = LC + LD;
+    static constexpr bool XROUTE = LCD >= 2;  // precontract the ket into X_P
+    static constexpr int BUDGET0 = 120 - nherm(L) - (XROUTE ? nherm(LAB) : 0) - 12;
+    static constexpr int BUDGET = BUDGET0 < 12 ? 12 : BUDGET0;
+    static constexpr int ABCH = NAB <= BUDGET ? NAB : BUDGET;
+    static constexpr int NABP = (NAB + ABCH - 1) / ABCH;
+    static constexpr int CDCH0 = BUDGET / ABCH;
+    static constexpr int CDCH = CDCH0 < 1 ? 1 : (CDCH0 > NCD ? NCD : CDCH0);
+    static constexpr int NCDP = (NCD + CDCH - 1) / CDCH;
+};
+
+template <int LA, int LB, int LC, int LD>
+__global__ __launch_bounds__(64) void k_pair(KPArgs a)
+{
+    using C = KPairCfg<LA, LB, LC, LD>;
+    constexpr int NA = C::NA, NB = C::NB, NC = C::NC, ND = C::ND, NCD = C::NCD;
+    constexpr int L = C::L, LAB = C::LAB;
+    constexpr EprodOff<LA, LB> ob{};
+    constexpr EprodOff<LC, LD> ok{};
+    constexpr int SB = ob.off[C::NAB], SK = ok.off[NCD];
+
+    const int lane = threadIdx.x;
+    const int2 ch = a.chunks[blockIdx.x];
+    const int ib = ch.x;
+    const int cnt = (int)(a.prefix[ib + 1] - a.prefix[ib]);
+    const int jk = ch.y + lane;
+    const bool valid = jk < cnt;
+    const CPair A = a.bra[ib];
+    const CPair B = a.ket[valid ? jk : ch.y];
+    const int nkp = valid ? B.np : 0;
+    const int n = a.ld;
+    double s = 1.0;
+    if (A.sh1 == A.sh2) s *= 0.5;
+    if (B.sh1 == B.sh2) s *= 0.5;
+    if (a.same && ib == jk) s *= 0.5;
+
+    static_for<0, C::NABP * C::NCDP>([&](auto pc) {
+        constexpr int pass = decltype(pc)::value;
+        constexpr int ab0 = (pass / C::NCDP) * C::ABCH;
+        constexpr int ab1 = (ab0 + C::ABCH < C::NAB) ? ab0 + C::ABCH : C::NAB;
+        constexpr int cd0 = (pass % C::NCDP) * C::CDCH;
+        constexpr int cd1 = (cd0 + C::CDCH < NCD) ? cd0 + C::CDCH : NCD;
+        constexpr int NABc = ab1 - ab0, NCDc = cd1 - cd0;
+        double V[NABc * NCDc];
+#pragma unroll
+        for (int i = 0; i < NABc * NCDc; ++i) V[i] = 0.0;
+
+        for (int ip = 0; ip < A.np; ++ip) {
+            const PrimPair pb = a.pp[A.poff + ip];
+            const double *__restrict__ eb = a.eprod_bra + (int64_t)(A.poff + ip - a.pbase_bra) * SB;
+            for (int kp = 0; kp < nkp; ++kp) {
+                const PrimPair pk = a.pp[B.poff + kp];
+                if (pb.q * pk.q < a.tau_prim) break;
+                double Fs[L + 1], X, Y, Z;
+                quartet_fs<L>(pb, pk, a.boys, Fs, X, Y, Z);
+                double R[nherm(L)];
+                r_build<L>(Fs, X, Y, Z, R);
+                const double *__restrict__ ek = a.eprod_ket + (int64_t)(B.poff + kp - a.pbase_ket) * SK;
+                static_for<cd0, cd1>([&](auto cdc) {
+                    constexpr int cd = decltype(cdc)::value;
+                    constexpr int c = cd / ND, d = cd % ND;
+                    constexpr int nsx = cart_x(LC, c) + cart_x(LD, d) + 1;
+                    constexpr int nsy = cart_y(LC, c) + cart_y(LD, d) + 1;
+                    constexpr int nsz = cart_z(LC, c) + cart_z(LD, d) + 1;
+                    double e[nsx * nsy * nsz];
+#pragma unroll
+                    for (int q = 0; q < nsx * nsy * nsz; ++q) e[q] = ek[ok.off[cd] + q];
+                    if constexpr (C::XROUTE) {
+                        // X_P = sum_s (-1)^{|s|} E^{cd}_s R_{P+s}, then (ab|cd) = sum_t E^{ab}_t X_t
+                        double Xp[nherm(LAB)];
+                        static_for<0, nherm(LAB)>([&](auto Pc) {
+                            constexpr int P = decltype(Pc)::value;
+                            constexpr int tp = herm_t(P), up = herm_u(P), vp = herm_v(P);
+                            double x = 0.0;
+                            static_for<0, nsx * nsy * nsz>([&](auto qc) {
+                                constexpr int q = decltype(qc)::value;
+                                constexpr int sx = q / (nsy * nsz), sy = (q / nsz) % nsy, sz = q % nsz;
+                                constexpr double sg = ((sx + sy + sz) & 1) ? -1.0 : 1.0;
+                                x += sg * e[q] * R[herm_idx(tp + sx, up + sy, vp + sz)];
+                            });
+                            Xp[P] = x;
+                        });
+                        static_for<ab0, ab1>([&](auto abc) {
+                            constexpr int ab = decltype(abc)::value;
+                            constexpr int ia = ab / NB, jb = ab % NB;
+                            constexpr int mx = cart_x(LA, ia) + cart_x(LB, jb) + 1;
+                            constexpr int my = cart_y(LA, ia) + cart_y(LB, jb) + 1;
+                            constexpr int mz = cart_z(LA, ia) + cart_z(LB, jb) + 1;
+                            double v = 0.0;
+                            static_for<0, mx * my * mz>([&](auto tc) {
+                                constexpr int t = decltype(tc)::value;
+                                constexpr int tx = t / (my * mz), ty = (t / mz) % my, tz = t % mz;
+                                v += eb[ob.off[ab] + t] * Xp[herm_idx(tx, ty, tz)];
+                            });
+                            V[(ab - ab0) * NCDc + (cd - cd0)] += v;
+                        });
+                    } else {
+                        // small ket box: (ab|cd) = sum_t E^{ab}_t sum_s (-1)^{|s|} E^{cd}_s R_{t+s}
+                        static_for<ab0, ab1>([&](auto abc) {
+                            constexpr int ab = decltype(abc)::value;
+                            constexpr int ia = ab / NB, jb = ab % NB;
+                            constexpr int mx = cart_x(LA, ia) + cart_x(LB, jb) + 1;
+                            constexpr int my = cart_y(LA, ia) + cart_y(LB, jb) + 1;
+                            constexpr int mz = cart_z(LA, ia) + cart_z(LB, jb) + 1;
+                            double v = 0.0;
+                            static_for<0, mx * my * mz>([&](auto tc) {
+                                constexpr int t = decltype(tc)::value;
+                                constexpr int tx = t / (my * mz), ty = (t / mz) % my, tz = t % mz;
+                                double x = 0.0;
+                                static_for<0, nsx * nsy * nsz>([&](auto qc) {
+                                    constexpr int q = decltype(qc)::value;
+                                    constexpr int sx = q / (nsy * nsz), sy = (q / nsz) % nsy, sz = q % nsz;
+                                    constexpr double sg = ((sx + sy + sz) & 1) ? -1.0 : 1.0;
+                                    x += sg * e[q] * R[herm_idx(tx + sx, ty + sy, tz + sz)];
+                                });
+                                v += eb[ob.off[ab] + t] * x;
+                            });
+                            V[(ab - ab0) * NCDc + (cd - cd0)] += v;
+                        });
+                    }
+                });
+            }
+        }
+
+        // digest the chunk: K_ac += V D_bd, K_ad += V D_bc, K_bc += V D_ad, K_bd += V D_ac
+        if (valid) {
+            static_for<cd0, cd1>([&](auto cdc) {
+                constexpr int cd = decltype(cdc)::value;
+                constexpr int c = cd / ND, d = cd % ND;
+                static_for<0, NA>([&](auto ic) {
+                    constexpr int i = decltype(ic)::value;
+                    double t13 = 0.0, t14 = 0.0;
+                    bool any = false;
+                    static_for<0, NB>([&](auto jc) {
+                        constexpr int j = decltype(jc)::value;
+                        constexpr int ab = i * NB + j;
+                        if constexpr (ab >= ab0 && ab < ab1) {
+                            const double v = V[(ab - ab0) * NCDc + (cd - cd0)];
+                            t13 += v * a.D[(int64_t)(A.c2 + j) * n + B.c2 + d];
+                            t14 += v * a.D[(int64_t)(A.c2 + j) * n + B.c1 + c];
+                            any = true;
+                        }
+                    });
+                    if (any) {
+                        unsafeAtomicAdd(&a.Kacc[(int64_t)(A.c1 + i) * n + B.c1 + c], s * t13);
+                        unsafeAtomicAdd(&a.Kacc[(int64_t)(A.c1 + i) * n + B.c2 + d], s * t14);
+                    }
+                });
+                static_for<0, NB>([&](auto jc) {
+                    constexpr int j = decltype(jc)::value;
+                    double t23 = 0.0, t24 = 0.0;
+                    bool any = false;
+                    static_for<0, NA>([&](auto ic) {
+                        constexpr int i = decltype(ic)::value;
+                        constexpr int ab = i * NB + j;
+                        if constexpr (ab >= ab0 && ab < ab1) {
+                            const double v = V[(ab - ab0) * NCDc + (cd - cd0)];
+                            t23 += v * a.D[(int64_t)(A.c1 + i) * n + B.c2 + d];
+                            t24 += v * a.D[(int64_t)(A.c1 + i) * n + B.c1 + c];
+                            any = true;
+                        }
+                    });
+                    if (any) {
+                        unsafeAtomicAdd(&a.Kacc[(int64_t)(A.c2 + j) * n + B.c1 + c], s * t23);
+                        unsafeAtomicAdd(&a.Kacc[(int64_t)(A.c2 + j) * n + B.c2 + d], s * t24);
+                    }
+                });
+            });
+        }
+    });
+}
+
+template <int LA, int LB, int LC, int LD>
+void launch_k_pair_t(const KPArgs &a, int nchunks, hipStream_t st)
+{
+    if (nchunks <= 0) return;
+    hipLaunchKernelGGL((k_pair<LA, LB, LC, LD>), dim3((unsigned)nchunks), dim3(64), 0, st, a);
+}
+
+}  // namespace md

@@ -1,0 +1,19 @@
+// k_pair_7.hip -- instantiations of the bra-shared exchange kernel.
+#include "class_lists.hpp"
+#include "k_pair.hpp"
+
+namespace md {
+
+bool launch_k_pair_7(int la, int lb, int lc, int ld, const KPArgs &a, int nchunks, hipStream_t st)
+{
+#define MD_CASE(A_, B_, C_, D_)                                   \
+    if (la == A_ && lb == B_ && lc == C_ && ld == D_) {           \
+        launch_k_pair_t<A_, B_, C_, D_>(a, nchunks, st);          \
+        return true;                                              \
+    }
+    MD_K_PAIR_PART7(MD_CASE)
+#undef MD_CASE
+    return false;
+}
+
+}  // namespace md

@@ -110,8 +110,8 @@ __global__ __launch_bounds__(64) void k_wave(KArgs a)
     constexpr KetBoxes<LC, LD> kb{};
 
     __shared__ double sR0[C::NR0];
-    __shared__ double sLev[2 * (C::NLEV > 0 ? C::NLEV : 1)];
     __shared__ double sF[L + 1];
+    __shared__ double sPow[3 * (L + 1)];
     __shared__ double sEb[C::EB];
     __shared__ double sEk[C::EK];
     __shared__ double sEkp[C::NKP];
@@ -158,16 +158,17 @@ __global__ __launch_bounds__(64) void k_wave(KArgs a)
                 if (pb.q * pk.q < a.tau_prim) break;
                 const QuartetGeo g = quartet_geo(pb, pk);
                 wave_boys<L>(g, a.boys, sF, lane);
+                wave_powers<L>(g, sPow, lane);
                 if (lane >= 61) {  // 1D Hermite tables, bra on 61..63
                     const int ax = lane - 61;
                     const double pa = ax == 0 ? pb.PA[0] : (ax == 1 ? pb.PA[1] : pb.PA[2]);
                     const double pbb = ax == 0 ? pb.PB[0] : (ax == 1 ? pb.PB[1] : pb.PB[2]);
-                    etab_lds<LA, LB>(pa, pbb, pb.o2p, sEb + ax * EBD);
+                    etab_reg_store<LA, LB>(pa, pbb, pb.o2p, sEb + ax * EBD);
                 } else if (lane >= 58) {  // ket on 58..60
                     const int ax = lane - 58;
                     const double pa = ax == 0 ? pk.PA[0] : (ax == 1 ? pk.PA[1] : pk.PA[2]);
                     const double pbb = ax == 0 ? pk.PB[0] : (ax == 1 ? pk.PB[1] : pk.PB[2]);
-                    etab_lds<LC, LD>(pa, pbb, pk.o2p, sEk + ax * EKD);
+                    etab_reg_store<LC, LD>(pa, pbb, pk.o2p, sEk + ax * EKD);
                 }
                 __syncthreads();
                 // ket products (-1)^{|s|} E^{cd}_s, layout per cd box [sx][sy][sz]
@@ -194,7 +195,8 @@ __global__ __launch_bounds__(64) void k_wave(KArgs a)
                                 out[(sx * ny + sy) * nz + sz] = sg * Ex[sx] * Ey[sy] * Ez[sz];
                             }
                 }
-                wave_recur<L>(g, sF, sLev, sLev + C::NLEV, sR0, lane);
+                wave_r0<L>(sF, sPow, sR0, lane);
+                __syncthreads();
 
                 // contraction: lane owns bra component ab = ch*64 + lane
                 static_for<0, C::NABCH>([&](auto chc) {

@@ -43,4 +43,23 @@ struct JArgs {
     double tau, tau_prim;
 };
 
+// Bra-shared exchange launch: one workgroup per (bra pair, 64-ket chunk).
+struct KPArgs {
+    const CPair *bra;
+    const CPair *ket;
+    const int2 *chunks;      // (bra index, first ket) of every workgroup
+    const int64_t *prefix;   // cumulative ket counts of the bras
+    int32_t same;
+    const PrimPair *pp;
+    const double *eprod_bra;  // class-X products, pair g at (g - pbase_bra) * SB
+    int32_t pbase_bra;
+    const double *eprod_ket;
+    int32_t pbase_ket;
+    const double *boys;
+    const double *D;
+    double *Kacc;
+    int32_t ld;
+    double tau_prim;
+};
+
 }  // namespace md

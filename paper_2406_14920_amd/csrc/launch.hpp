@@ -14,6 +14,16 @@ struct ShellMap {
     const int32_t *sph_off;
 };
 
+bool launch_k_pair_0(int la, int lb, int lc, int ld, const KPArgs &a, int nchunks, hipStream_t st);
+bool launch_k_pair_1(int la, int lb, int lc, int ld, const KPArgs &a, int nchunks, hipStream_t st);
+bool launch_k_pair_2(int la, int lb, int lc, int ld, const KPArgs &a, int nchunks, hipStream_t st);
+bool launch_k_pair_3(int la, int lb, int lc, int ld, const KPArgs &a, int nchunks, hipStream_t st);
+bool launch_k_pair_4(int la, int lb, int lc, int ld, const KPArgs &a, int nchunks, hipStream_t st);
+bool launch_k_pair_5(int la, int lb, int lc, int ld, const KPArgs &a, int nchunks, hipStream_t st);
+bool launch_k_pair_6(int la, int lb, int lc, int ld, const KPArgs &a, int nchunks, hipStream_t st);
+bool launch_k_pair_7(int la, int lb, int lc, int ld, const KPArgs &a, int nchunks, hipStream_t st);
+void launch_eprod(int la, int lb, const PrimPair *pp, int pbase, int n, double *out, hipStream_t st);
+int eprod_size(int la, int lb);
 bool launch_k_small(int la, int lb, int lc, int ld, const KArgs &a, hipStream_t st);
 bool launch_k_wave_0(int la, int lb, int lc, int ld, const KArgs &a, hipStream_t st);
 bool launch_k_wave_1(int la, int lb, int lc, int ld, const KArgs &a, hipStream_t st);
@@ -35,5 +45,7 @@ void launch_p_to_cart(const double *P, int nbf, double *Pc, int nc, const ShellM
 void launch_acc_to_out(const double *Acc, int nc, double *Out, int nbf, const ShellMap &m, int sph,
                        hipStream_t st);
 void launch_fill_zero(double *x, int64_t n, hipStream_t st);
+void launch_k_count(const KArgs &a, unsigned long long *out, hipStream_t st);
+void launch_j_count(const JArgs &a, unsigned long long *out, hipStream_t st);
 
 }  // namespace md

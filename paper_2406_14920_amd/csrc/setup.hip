@@ -119,11 +119,11 @@ __global__ __launch_bounds__(64) void schwarz_wave(const CPair *__restrict__ cp,
                                                    const double *__restrict__ boys)
 {
     constexpr int NA = ncart(LA), NB = ncart(LB), NAB = NA * NB, LAB = LA + LB;
-    constexpr int L = 2 * LAB, L1 = L + 1, NLEV = nherm(L > 0 ? L - 1 : 0);
+    constexpr int L = 2 * LAB, L1 = L + 1;
     constexpr int EBD = (LA + 1) * (LB + 1) * (LAB + 1);
     __shared__ double sR0[L1 * L1 * L1];
-    __shared__ double sLev[2 * (NLEV > 0 ? NLEV : 1)];
     __shared__ double sF[L + 1];
+    __shared__ double sPow[3 * (L + 1)];
     __shared__ double sEb[3 * EBD];
     __shared__ double sEk[3 * EBD];
     const int lane = threadIdx.x;
@@ -149,19 +149,21 @@ __global__ __launch_bounds__(64) void schwarz_wave(const CPair *__restrict__ cp,
                 const PrimPair pk = pp[A.poff + kp];
                 const QuartetGeo g = quartet_geo(pb, pk);
                 wave_boys<L>(g, boys, sF, lane);
+                wave_powers<L>(g, sPow, lane);
                 if (lane >= 61) {
                     const int ax = lane - 61;
                     const double pa = ax == 0 ? pb.PA[0] : (ax == 1 ? pb.PA[1] : pb.PA[2]);
                     const double pbb = ax == 0 ? pb.PB[0] : (ax == 1 ? pb.PB[1] : pb.PB[2]);
-                    etab_lds<LA, LB>(pa, pbb, pb.o2p, sEb + ax * EBD);
+                    etab_reg_store<LA, LB>(pa, pbb, pb.o2p, sEb + ax * EBD);
                 } else if (lane >= 58) {
                     const int ax = lane - 58;
                     const double pa = ax == 0 ? pk.PA[0] : (ax == 1 ? pk.PA[1] : pk.PA[2]);
                     const double pbb = ax == 0 ? pk.PB[0] : (ax == 1 ? pk.PB[1] : pk.PB[2]);
-                    etab_lds<LA, LB>(pa, pbb, pk.o2p, sEk + ax * EBD);
+                    etab_reg_store<LA, LB>(pa, pbb, pk.o2p, sEk + ax * EBD);
                 }
                 __syncthreads();
-                wave_recur<L>(g, sF, sLev, sLev + NLEV, sR0, lane);
+                wave_r0<L>(sF, sPow, sR0, lane);
+                __syncthreads();
                 double pd = 0.0;
                 for (int r = 0; r < 2; ++r) {
                     if (!own[r]) continue;

@@ -6,6 +6,7 @@
 // address of R_{P+Q} is the sum of the addresses of P and Q.
 #pragma once
 #include "md_common.hpp"
+#include "md_device.hpp"
 
 namespace md {
 
@@ -127,6 +128,90 @@ __device__ __forceinline__ void etab_lds(double PA, double PB, double o2p, doubl
                 if (t + 1 <= i + j) v += (double)(t + 1) * E[i * DI + j * DJ + t + 1];
                 E[i * DI + (j + 1) * DJ + t] = v;
             }
+}
+
+
+// Closed form of the recursion (same values as eq. R_recursion): with
+// G_n = pref (-2 alpha)^n F_n and s = X^2+Y^2+Z^2, dG_n/ds = G_{n+1}/2, so
+//   R^0_{tuv} = sum_{a<=t/2, b<=u/2, c<=v/2} C_t^a C_u^b C_v^c
+//               X^{t-2a} Y^{u-2b} Z^{v-2c} G_{t+u+v-a-b-c},
+//   C_t^a = t! / (a! (t-2a)! 2^a).
+// Every entry is independent, so the lanes of a wave fill the table with one
+// barrier instead of one per recursion level.
+struct HermCoef {
+    double c[15][8];
+    constexpr HermCoef() : c()
+    {
+        for (int t = 0; t < 15; ++t) {
+            double v = 1.0;  // a = 0
+            for (int a = 0; 2 * a <= t && a < 8; ++a) {
+                c[t][a] = v;
+                v = v * (double)((t - 2 * a) * (t - 2 * a - 1)) / (2.0 * (a + 1));
+            }
+        }
+    }
+};
+__constant__ const HermCoef c_hcoef{};
+
+// Phase 1 helper: lane 0..L also stores the powers X^k, Y^k, Z^k into sPow
+// (layout [axis][L+1]); call together with wave_boys (before the barrier).
+template <int L>
+__device__ __forceinline__ void wave_powers(const QuartetGeo &g, double *sPow, int lane)
+{
+    if (lane <= L) {
+        double px = 1.0, py = 1.0, pz = 1.0;
+        for (int k = 0; k < lane; ++k) {
+            px *= g.X;
+            py *= g.Y;
+            pz *= g.Z;
+        }
+        sPow[lane] = px;
+        sPow[(L + 1) + lane] = py;
+        sPow[2 * (L + 1) + lane] = pz;
+    }
+}
+
+// Phase 2 (after the barrier that publishes sF and sPow): dense R^0 into sR0.
+// No barrier inside.
+template <int L>
+__device__ __forceinline__ void wave_r0(const double *sF, const double *sPow, double *sR0, int lane)
+{
+    constexpr int L1 = L + 1;
+    for (int k = lane; k < nherm(L); k += 64) {
+        const int code = c_herm.tuv[k];
+        const int t = code & 0xff, u = (code >> 8) & 0xff, v = code >> 16;
+        double acc = 0.0;
+        for (int a = 0; 2 * a <= t; ++a) {
+            const double ca = c_hcoef.c[t][a] * sPow[t - 2 * a];
+            for (int b = 0; 2 * b <= u; ++b) {
+                const double cab = ca * c_hcoef.c[u][b] * sPow[L1 + u - 2 * b];
+                const int n0 = t + u + v - a - b;
+                for (int c = 0; 2 * c <= v; ++c)
+                    acc += cab * c_hcoef.c[v][c] * sPow[2 * L1 + v - 2 * c] * sF[n0 - c];
+            }
+        }
+        sR0[(t * L1 + u) * L1 + v] = acc;
+    }
+}
+
+// One axis of the 1D Hermite tables computed in registers (eq. E_recursion)
+// and stored to LDS with the [i][j][t] layout of etab_lds.
+template <int LA, int LB>
+__device__ __forceinline__ void etab_reg_store(double PA, double PB, double o2p, double *E)
+{
+    constexpr int DJ = LA + LB + 1, DI = (LB + 1) * DJ;
+    Etab<LA, LB> T;
+    etab_build<LA, LB>(PA, PB, o2p, T);
+    static_for<0, LA + 1>([&](auto ic) {
+        constexpr int i = decltype(ic)::value;
+        static_for<0, LB + 1>([&](auto jc) {
+            constexpr int j = decltype(jc)::value;
+            static_for<0, DJ>([&](auto tc) {
+                constexpr int t = decltype(tc)::value;
+                E[i * DI + j * DJ + t] = (t <= i + j) ? T.e[i][j][t] : 0.0;
+            });
+        });
+    });
 }
 
 // Cartesian exponents of component c of a shell with angular momentum l (runtime).
