@@ -643,7 +643,8 @@ void run_j(eri_ctx *c)
             a.tau = c->opts.schwarz_thresh;
             a.tau_prim = c->opts.prim_thresh;
             const int lx = kPairL[X][0] + kPairL[X][1], ly = kPairL[Y][0] + kPairL[Y][1];
-            timed(c, cls_name(lx + ly <= 5 ? "jeng_small" : "jeng_wave", kPairL[X][0], kPairL[X][1], kPairL[Y][0],
+            const bool reg = lx + ly >= 6 && nherm(lx) + nherm(ly) + 4 * (lx + ly + 1) <= 116;
+            timed(c, cls_name(lx + ly <= 5 ? "jeng_small" : (reg ? "jeng_reg" : "jeng_wave"), kPairL[X][0], kPairL[X][1], kPairL[Y][0],
                               kPairL[Y][1]),
                   (double)c->jprim[X][Y] * fl_j_prim(lx, ly), c->jprim[X][Y],
                   [&] { launch_jeng(lx, ly, a, st); });

@@ -296,9 +296,17 @@ void launch_hermite_to_cart(int la, int lb, const CPair *cp, int ncp, const Prim
 // total Hermite order at or below which the register path is used
 constexpr int kJengRegMaxL = 5;
 
+bool launch_jeng_reg_0(int lx, int ly, const JArgs &a, hipStream_t st);
+bool launch_jeng_reg_1(int lx, int ly, const JArgs &a, hipStream_t st);
+bool launch_jeng_reg_2(int lx, int ly, const JArgs &a, hipStream_t st);
+bool launch_jeng_reg_3(int lx, int ly, const JArgs &a, hipStream_t st);
+
 template <int LX, int LY>
 void jeng_launch_t(const JArgs &a, hipStream_t st)
 {
+    if (launch_jeng_reg_0(LX, LY, a, st) || launch_jeng_reg_1(LX, LY, a, st) ||
+        launch_jeng_reg_2(LX, LY, a, st) || launch_jeng_reg_3(LX, LY, a, st))
+        return;
     const int nch = (a.nket + a.kchunk - 1) / a.kchunk;
     if (a.nbp <= 0 || nch <= 0) return;
     if constexpr (LX + LY <= kJengRegMaxL) {

@@ -55,4 +55,94 @@ __device__ __forceinline__ void jeng_quartet_stream(const double *G, const doubl
     });
 }
 
+template <int LX, int LY>
+__global__ __launch_bounds__(64) void jeng_reg(JArgs a)
+{
+    constexpr int L = LX + LY, NX = nherm(LX), NY = nherm(LY);
+    const int g = blockIdx.x * 64 + threadIdx.x;
+    const bool valid = g < a.nbp;
+    const int gi = valid ? g : a.nbp - 1;
+    const PrimPair pb = a.pp[a.pbase + gi];
+    const double Qi = valid ? a.Qbra[a.owner[gi]] : 0.0;
+    const double qi = valid ? pb.q : 0.0;
+    int lo = 0, hi = a.nket;
+    while (lo < hi) {
+        int mid = (lo + hi) >> 1;
+        if (Qi * a.Qket[mid] >= a.tau) lo = mid + 1; else hi = mid;
+    }
+    const int nv = valid ? lo : 0;
+    int nvmax = nv;
+    double qmax = qi;
+    for (int off = 32; off > 0; off >>= 1) {
+        nvmax = max(nvmax, __shfl_xor(nvmax, off));
+        qmax = fmax(qmax, __shfl_xor(qmax, off));
+    }
+    nvmax = __builtin_amdgcn_readfirstlane(nvmax);
+    {
+        const uint64_t bq = __double_as_longlong(qmax);
+        const uint32_t lo32 = __builtin_amdgcn_readfirstlane((uint32_t)bq);
+        const uint32_t hi32 = __builtin_amdgcn_readfirstlane((uint32_t)(bq >> 32));
+        qmax = __longlong_as_double(((uint64_t)hi32 << 32) | lo32);
+    }
+    const int j0 = blockIdx.y * a.kchunk;
+    const int j1 = min(min(a.nket, j0 + a.kchunk), nvmax);
+
+    double Jh[NX];
+#pragma unroll
+    for (int i = 0; i < NX; ++i) Jh[i] = 0.0;
+    for (int j = j0; j < j1; ++j) {
+        const CPair B = a.ket[j];
+        for (int kp = 0; kp < B.np; ++kp) {
+            const PrimPair pk = a.pp[B.poff + kp];
+            if (qmax * pk.q < a.tau_prim) break;
+            if (j < nv && qi * pk.q >= a.tau_prim) {
+                const double p = pb.p, q = pk.p, rpq = 1.0 / (p + q), alpha = p * q * rpq;
+                const double X = pb.P[0] - pk.P[0], Y = pb.P[1] - pk.P[1], Z = pb.P[2] - pk.P[2];
+                double F[L + 1];
+                boys_all<L>(alpha * (X * X + Y * Y + Z * Z), F, a.boys);
+                double G[L + 1], px[L + 1], py[L + 1], pz[L + 1];
+                double s = kTwoPi52 * pb.K * pk.K / (p * q) * sqrt(rpq);
+                const double m2a = -2.0 * alpha;
+                px[0] = py[0] = pz[0] = 1.0;
+#pragma unroll
+                for (int m = 0; m <= L; ++m) {
+                    G[m] = s * F[m];
+                    s *= m2a;
+                }
+#pragma unroll
+                for (int m = 1; m <= L; ++m) {
+                    px[m] = px[m - 1] * X;
+                    py[m] = py[m - 1] * Y;
+                    pz[m] = pz[m - 1] * Z;
+                }
+                const double *__restrict__ dt = a.Dt + (int64_t)(B.poff + kp - a.dt_base) * NY;
+                double dq[NY];
+#pragma unroll
+                for (int k = 0; k < NY; ++k) dq[k] = dt[k];
+                jeng_quartet_stream<LX, LY>(G, px, py, pz, dq, Jh);
+            }
+        }
+    }
+    if (valid && j1 > j0) {
+#pragma unroll
+        for (int P = 0; P < NX; ++P) unsafeAtomicAdd(&a.Jh[(int64_t)g * NX + P], Jh[P]);
+    }
+}
+
+// register J-engine is used where its live set (Hermite J, Hermite density,
+// Boys values and coordinate powers) stays within about 115 doubles
+__host__ __device__ constexpr bool jeng_reg_ok(int lx, int ly)
+{
+    return lx + ly >= 6 && nherm(lx) + nherm(ly) + 4 * (lx + ly + 1) <= 116;
+}
+
+template <int LX, int LY>
+void jeng_reg_launch_t(const JArgs &a, hipStream_t st)
+{
+    const int nch = (a.nket + a.kchunk - 1) / a.kchunk;
+    if (a.nbp <= 0 || nch <= 0) return;
+    dim3 grid((a.nbp + 63) / 64, nch);
+    hipLaunchKernelGGL((jeng_reg<LX, LY>), grid, dim3(64), 0, st, a);
+}
+
 }  // namespace md
