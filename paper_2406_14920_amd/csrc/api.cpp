@@ -675,6 +675,10 @@ void run_k(eri_ctx *c)
         a.Kacc = c->d_Kacc.p;
         a.ld = c->nbf_cart;
         a.tau_prim = c->opts.prim_thresh;
+        a.eprod_bra = c->d_eprod.p + c->eprod_off[w.X];
+        a.pbase_bra = c->pp_base[w.X];
+        a.eprod_ket = c->d_eprod.p + c->eprod_off[w.Y];
+        a.pbase_ket = c->pp_base[w.Y];
         const int la = kPairL[w.X][0], lb = kPairL[w.X][1], lc = kPairL[w.Y][0], ld = kPairL[w.Y][1];
         const size_t wi = &w - c->kwork.data();
         const int64_t pq = wi < c->kprim.size() ? c->kprim[wi] : 0;

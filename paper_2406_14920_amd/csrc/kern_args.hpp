@@ -22,6 +22,10 @@ struct KArgs {
     double *Kacc;            // Cartesian exchange accumulator, ld x ld
     int32_t ld;
     double tau_prim;
+    const double *eprod_bra; // Hermite products of class-X primitive pairs
+    int32_t pbase_bra;
+    const double *eprod_ket; // Hermite products of class-Y primitive pairs
+    int32_t pbase_ket;
 };
 
 // J-engine launch: bra primitive pairs of class X against ket contracted
