@@ -15,6 +15,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -208,16 +209,29 @@ struct eri_ctx {
     DevBuf<double> d_Pc, d_Jacc, d_Kacc, d_Dt, d_Jh;
     DevBuf<int32_t> d_soc, d_sos, d_l, d_coff, d_soff;
 
+    // mixed precision: single-precision Hermite products and Hermite density
+    // (built on first use after each geometry), shell-pair density bounds and
+    // Q max|D| per contracted pair (per build)
+    bool mixed_ready = false;
+    DevBuf<float> d_eprodf, d_Dtf;
+    DevBuf<double> d_Pm, d_QD;
+    bool built_mixed = false;  // last build_jk ran in the mixed mode
+    // single-precision share of the last mixed build: per exchange launch and
+    // per J-engine (X, Y): {primitive quartets, work items}; computed on demand
+    mutable bool mix_counts_ok = false;
+    mutable std::vector<std::array<int64_t, 2>> kmix;
+    mutable int64_t jmix[kPairClasses][kPairClasses][2] = {};
+
     // primitive-quartet counts per exchange launch and per J-engine (X, Y)
     std::vector<int64_t> kprim;
     int64_t jprim[kPairClasses][kPairClasses] = {};
 
-    // profiling
+    // profiling: work = {-1 none, 0 exchange launch, 1 J-engine}, idx = kwork
+    // index or X*10+Y, part = 0 whole launch, 1 double / 2 single share
     struct Rec {
         std::string name;
         hipEvent_t a, b;
-        double flops;
-        int64_t pq;
+        int work, idx, part;
     };
     struct Acc {
         int launches = 0;
@@ -405,6 +419,10 @@ void build_pairs(eri_ctx *c)
     c->d_Q.upload(c->Q);
     c->d_pp.upload(c->pp);
     c->d_owner.upload(owner);
+    c->d_QD.alloc(std::max<size_t>(c->cp.size(), 1));
+    c->mixed_ready = false;
+    c->built_mixed = false;
+    c->mix_counts_ok = false;
 
     // 4. exchange work lists
     std::vector<int64_t> prefix;
@@ -574,6 +592,20 @@ void build_basis(eri_ctx *c, const eri_shell *shells, const eri_atom *atoms)
     c->d_Pc.alloc(nc2);
     c->d_Jacc.alloc(nc2);
     c->d_Kacc.alloc(nc2);
+    c->d_Pm.alloc((size_t)c->nshell * c->nshell);
+}
+
+// Single-precision tables of the mixed mode (geometry dependent only).
+void ensure_mixed(eri_ctx *c)
+{
+    if (c->mixed_ready) return;
+    c->d_eprodf.alloc(std::max<size_t>(c->d_eprod.n, 1));
+    for (int X = 0; X < kPairClasses; ++X)
+        launch_eprod(kPairL[X][0], kPairL[X][1], c->d_pp.p, c->pp_base[X], c->npp[X],
+                     c->d_eprodf.p + c->eprod_off[X], c->st);
+    HIPCHK(hipGetLastError());
+    c->d_Dtf.alloc(std::max<size_t>(c->d_Dt.n, 1));
+    c->mixed_ready = true;
 }
 
 ShellMap shell_map(const eri_ctx *c)
@@ -590,13 +622,13 @@ ShellMap shell_map(const eri_ctx *c)
 bool ctx_ok(const eri_ctx *c) { return c && c->magic == 0x4d444a4b; }
 
 template <typename F>
-void timed(eri_ctx *c, const std::string &name, double flops, int64_t pq, F &&launch)
+void timed(eri_ctx *c, const std::string &name, int work, int idx, int part, F &&launch)
 {
     if (!c->profile) {
         launch();
         return;
     }
-    eri_ctx::Rec r{name, nullptr, nullptr, flops, pq};
+    eri_ctx::Rec r{name, nullptr, nullptr, work, idx, part};
     HIPCHK(hipEventCreate(&r.a));
     HIPCHK(hipEventCreate(&r.b));
     HIPCHK(hipEventRecord(r.a, c->st));
@@ -612,113 +644,241 @@ std::string cls_name(const char *k, int a, int b, int cc, int d)
     return buf;
 }
 
-void run_j(eri_ctx *c)
+JArgs j_args(const eri_ctx *c, int X, int Y, bool mixed)
+{
+    JArgs a{};
+    a.pp = c->d_pp.p;
+    a.owner = c->d_owner.p + c->pp_base[X];
+    a.Qbra = c->d_Q.p + c->cp_base[X];
+    a.pbase = c->pp_base[X];
+    a.nbp = c->npp[X];
+    a.ket = c->d_cp.p + c->cp_base[Y];
+    a.Qket = c->d_Q.p + c->cp_base[Y];
+    a.nket = c->ncp[Y];
+    a.kchunk = 256;
+    a.Dt = c->d_Dt.p + c->dt_off[Y];
+    a.dt_base = c->pp_base[Y];
+    a.Jh = c->d_Jh.p + c->jh_off[X];
+    a.boys = c->d_boys.p;
+    a.tau = c->opts.schwarz_thresh;
+    a.tau_prim = c->opts.prim_thresh;
+    a.mode = 0;
+    if (mixed) {
+        a.Dtf = c->d_Dtf.p + c->dt_off[Y];
+        a.tau_mix = c->opts.mixed_thresh;
+        a.QDket = c->d_QD.p + c->cp_base[Y];
+    }
+    return a;
+}
+
+bool jeng_is_reg(int lx, int ly) { return lx + ly >= 6 && nherm(lx) + nherm(ly) + 4 * (lx + ly + 1) <= 116; }
+
+void run_j(eri_ctx *c, bool mixed)
 {
     hipStream_t st = c->st;
     const int nc = c->nbf_cart;
     for (int Y = 0; Y < kPairClasses; ++Y)
-        timed(c, cls_name("hdens", kPairL[Y][0], kPairL[Y][1], 0, 0), 0.0, 0, [&] {
+        timed(c, cls_name("hdens", kPairL[Y][0], kPairL[Y][1], 0, 0), -1, 0, 0, [&] {
             launch_hermite_density(kPairL[Y][0], kPairL[Y][1], c->d_cp.p + c->cp_base[Y], c->ncp[Y], c->d_pp.p,
-                                   c->d_Pc.p, nc, c->d_Dt.p + c->dt_off[Y], c->pp_base[Y], st);
+                                   c->d_Pc.p, nc, c->d_Dt.p + c->dt_off[Y],
+                                   mixed ? c->d_Dtf.p + c->dt_off[Y] : nullptr, c->pp_base[Y], st);
         });
-    timed(c, "fill_zero", 0.0, 0, [&] { launch_fill_zero(c->d_Jh.p, (int64_t)c->d_Jh.n, st); });
+    timed(c, "fill_zero", -1, 0, 0, [&] { launch_fill_zero(c->d_Jh.p, (int64_t)c->d_Jh.n, st); });
     for (int X = 0; X < kPairClasses; ++X) {
         if (c->npp[X] == 0) continue;
         for (int Y = 0; Y < kPairClasses; ++Y) {
             if (c->ncp[Y] == 0) continue;
-            JArgs a;
-            a.pp = c->d_pp.p;
-            a.owner = c->d_owner.p + c->pp_base[X];
-            a.Qbra = c->d_Q.p + c->cp_base[X];
-            a.pbase = c->pp_base[X];
-            a.nbp = c->npp[X];
-            a.ket = c->d_cp.p + c->cp_base[Y];
-            a.Qket = c->d_Q.p + c->cp_base[Y];
-            a.nket = c->ncp[Y];
-            a.kchunk = 256;
-            a.Dt = c->d_Dt.p + c->dt_off[Y];
-            a.dt_base = c->pp_base[Y];
-            a.Jh = c->d_Jh.p + c->jh_off[X];
-            a.boys = c->d_boys.p;
-            a.tau = c->opts.schwarz_thresh;
-            a.tau_prim = c->opts.prim_thresh;
             const int lx = kPairL[X][0] + kPairL[X][1], ly = kPairL[Y][0] + kPairL[Y][1];
-            const bool reg = lx + ly >= 6 && nherm(lx) + nherm(ly) + 4 * (lx + ly + 1) <= 116;
-            timed(c, cls_name(lx + ly <= 5 ? "jeng_small" : (reg ? "jeng_reg" : "jeng_wave"), kPairL[X][0], kPairL[X][1], kPairL[Y][0],
-                              kPairL[Y][1]),
-                  (double)c->jprim[X][Y] * fl_j_prim(lx, ly), c->jprim[X][Y],
-                  [&] { launch_jeng(lx, ly, a, st); });
+            const std::string nm = cls_name(lx + ly <= 5 ? "jeng_small" : (jeng_is_reg(lx, ly) ? "jeng_reg" : "jeng_wave"),
+                                            kPairL[X][0], kPairL[X][1], kPairL[Y][0], kPairL[Y][1]);
+            JArgs a = j_args(c, X, Y, mixed);
+            for (int part = mixed ? 1 : 0; part <= (mixed ? 2 : 0); ++part) {
+                a.mode = part;
+                timed(c, part == 0 ? nm : nm + (part == 1 ? "/d" : "/s"), 1, X * kPairClasses + Y, part,
+                      [&] { launch_jeng(lx, ly, a, part == 2, st); });
+            }
         }
     }
     for (int X = 0; X < kPairClasses; ++X)
-        timed(c, cls_name("herm2cart", kPairL[X][0], kPairL[X][1], 0, 0), 0.0, 0, [&] {
+        timed(c, cls_name("herm2cart", kPairL[X][0], kPairL[X][1], 0, 0), -1, 0, 0, [&] {
             launch_hermite_to_cart(kPairL[X][0], kPairL[X][1], c->d_cp.p + c->cp_base[X], c->ncp[X], c->d_pp.p,
                                    c->d_Jh.p + c->jh_off[X], c->pp_base[X], c->d_Jacc.p, nc, st);
         });
 }
 
-void run_k(eri_ctx *c)
+KArgs k_args(const eri_ctx *c, const eri_ctx::KWork &w, bool mixed)
+{
+    KArgs a{};
+    a.bra = c->d_cp.p + c->cp_base[w.X];
+    a.ket = c->d_cp.p + c->cp_base[w.Y];
+    a.prefix = c->d_prefix.p + w.off;
+    a.nwork = w.nwork;
+    a.nbra = c->ncp[w.X];
+    a.same = w.X == w.Y;
+    a.pp = c->d_pp.p;
+    a.boys = c->d_boys.p;
+    a.D = c->d_Pc.p;
+    a.Kacc = c->d_Kacc.p;
+    a.ld = c->nbf_cart;
+    a.tau_prim = c->opts.prim_thresh;
+    a.eprod_bra = c->d_eprod.p + c->eprod_off[w.X];
+    a.pbase_bra = c->pp_base[w.X];
+    a.eprod_ket = c->d_eprod.p + c->eprod_off[w.Y];
+    a.pbase_ket = c->pp_base[w.Y];
+    a.mode = 0;
+    if (mixed) {
+        a.eprodf_bra = c->d_eprodf.p + c->eprod_off[w.X];
+        a.eprodf_ket = c->d_eprodf.p + c->eprod_off[w.Y];
+        a.tau_mix = c->opts.mixed_thresh;
+        a.Qbra = c->d_Q.p + c->cp_base[w.X];
+        a.Qket = c->d_Q.p + c->cp_base[w.Y];
+        a.Pm = c->d_Pm.p;
+        a.nsh = c->nshell;
+    }
+    return a;
+}
+
+KPArgs kp_args(const KArgs &a, const int2 *chunks)
+{
+    KPArgs p{};
+    p.bra = a.bra;
+    p.ket = a.ket;
+    p.chunks = chunks;
+    p.prefix = a.prefix;
+    p.same = a.same;
+    p.pp = a.pp;
+    p.eprod_bra = a.eprod_bra;
+    p.pbase_bra = a.pbase_bra;
+    p.eprod_ket = a.eprod_ket;
+    p.pbase_ket = a.pbase_ket;
+    p.boys = a.boys;
+    p.D = a.D;
+    p.Kacc = a.Kacc;
+    p.ld = a.ld;
+    p.tau_prim = a.tau_prim;
+    p.eprodf_bra = a.eprodf_bra;
+    p.eprodf_ket = a.eprodf_ket;
+    p.mode = a.mode;
+    p.tau_mix = a.tau_mix;
+    p.Qbra = a.Qbra;
+    p.Qket = a.Qket;
+    p.Pm = a.Pm;
+    p.nsh = a.nsh;
+    return p;
+}
+
+bool is_k_small(int la, int lb, int lc, int ld)
+{
+#define MD_IS(A_, B_, C_, D_) if (la == A_ && lb == B_ && lc == C_ && ld == D_) return true;
+    MD_K_SMALL_LIST(MD_IS)
+#undef MD_IS
+    return false;
+}
+
+void run_k(eri_ctx *c, bool mixed)
 {
     hipStream_t st = c->st;
     for (const auto &w : c->kwork) {
         if (w.nwork == 0) continue;
-        KArgs a;
-        a.bra = c->d_cp.p + c->cp_base[w.X];
-        a.ket = c->d_cp.p + c->cp_base[w.Y];
-        a.prefix = c->d_prefix.p + w.off;
-        a.nwork = w.nwork;
-        a.nbra = c->ncp[w.X];
-        a.same = w.X == w.Y;
-        a.pp = c->d_pp.p;
-        a.boys = c->d_boys.p;
-        a.D = c->d_Pc.p;
-        a.Kacc = c->d_Kacc.p;
-        a.ld = c->nbf_cart;
-        a.tau_prim = c->opts.prim_thresh;
-        a.eprod_bra = c->d_eprod.p + c->eprod_off[w.X];
-        a.pbase_bra = c->pp_base[w.X];
-        a.eprod_ket = c->d_eprod.p + c->eprod_off[w.Y];
-        a.pbase_ket = c->pp_base[w.Y];
         const int la = kPairL[w.X][0], lb = kPairL[w.X][1], lc = kPairL[w.Y][0], ld = kPairL[w.Y][1];
-        const size_t wi = &w - c->kwork.data();
-        const int64_t pq = wi < c->kprim.size() ? c->kprim[wi] : 0;
-        const double fl = (double)pq * fl_k_prim(la, lb, lc, ld) + (double)w.nwork * fl_k_digest(la, lb, lc, ld);
-        bool ok = false;
-        if (w.choff >= 0) {
-            KPArgs p;
-            p.bra = a.bra;
-            p.ket = a.ket;
-            p.chunks = c->d_chunks.p + w.choff;
-            p.prefix = a.prefix;
-            p.same = a.same;
-            p.pp = a.pp;
-            p.eprod_bra = c->d_eprod.p + c->eprod_off[w.X];
-            p.pbase_bra = c->pp_base[w.X];
-            p.eprod_ket = c->d_eprod.p + c->eprod_off[w.Y];
-            p.pbase_ket = c->pp_base[w.Y];
-            p.boys = a.boys;
-            p.D = a.D;
-            p.Kacc = a.Kacc;
-            p.ld = a.ld;
-            p.tau_prim = a.tau_prim;
-            const int nch = w.nchunks;
-            timed(c, cls_name("kp", la, lb, lc, ld), fl, pq, [&] {
-                ok = launch_k_pair_0(la, lb, lc, ld, p, nch, st) || launch_k_pair_1(la, lb, lc, ld, p, nch, st) ||
-                     launch_k_pair_2(la, lb, lc, ld, p, nch, st) || launch_k_pair_3(la, lb, lc, ld, p, nch, st) ||
-                     launch_k_pair_4(la, lb, lc, ld, p, nch, st) || launch_k_pair_5(la, lb, lc, ld, p, nch, st) ||
-                     launch_k_pair_6(la, lb, lc, ld, p, nch, st) || launch_k_pair_7(la, lb, lc, ld, p, nch, st);
-            });
-        } else
-        timed(c, cls_name("k", la, lb, lc, ld), fl, pq, [&] {
-            ok = launch_k_small(la, lb, lc, ld, a, st) || launch_k_wave_0(la, lb, lc, ld, a, st) ||
-                 launch_k_wave_1(la, lb, lc, ld, a, st) || launch_k_wave_2(la, lb, lc, ld, a, st) ||
-                 launch_k_wave_3(la, lb, lc, ld, a, st) || launch_k_wave_4(la, lb, lc, ld, a, st) ||
-                 launch_k_wave_5(la, lb, lc, ld, a, st);
-        });
-        if (!ok) {
-            set_err(ERI_ESTATE, "no exchange kernel for class (%d%d|%d%d)", la, lb, lc, ld);
-            throw HipError{ERI_ESTATE};
+        const int wi = (int)(&w - c->kwork.data());
+        KArgs a = k_args(c, w, mixed);
+        for (int part = mixed ? 1 : 0; part <= (mixed ? 2 : 0); ++part) {
+            a.mode = part;
+            const bool f32 = part == 2;
+            const char *sfx = part == 0 ? "" : (part == 1 ? "/d" : "/s");
+            bool ok = false;
+            if (w.choff >= 0) {
+                const KPArgs p = kp_args(a, c->d_chunks.p + w.choff);
+                const int nch = w.nchunks;
+                timed(c, cls_name("kp", la, lb, lc, ld) + sfx, 0, wi, part, [&] {
+                    ok = launch_k_pair_0(la, lb, lc, ld, p, nch, f32, st) || launch_k_pair_1(la, lb, lc, ld, p, nch, f32, st) ||
+                         launch_k_pair_2(la, lb, lc, ld, p, nch, f32, st) || launch_k_pair_3(la, lb, lc, ld, p, nch, f32, st) ||
+                         launch_k_pair_4(la, lb, lc, ld, p, nch, f32, st) || launch_k_pair_5(la, lb, lc, ld, p, nch, f32, st) ||
+                         launch_k_pair_6(la, lb, lc, ld, p, nch, f32, st) || launch_k_pair_7(la, lb, lc, ld, p, nch, f32, st);
+                });
+            } else {
+                timed(c, cls_name("k", la, lb, lc, ld) + sfx, 0, wi, part, [&] {
+                    ok = launch_k_small(la, lb, lc, ld, a, f32, st) || launch_k_wave_0(la, lb, lc, ld, a, f32, st) ||
+                         launch_k_wave_1(la, lb, lc, ld, a, f32, st) || launch_k_wave_2(la, lb, lc, ld, a, f32, st) ||
+                         launch_k_wave_3(la, lb, lc, ld, a, f32, st) || launch_k_wave_4(la, lb, lc, ld, a, f32, st) ||
+                         launch_k_wave_5(la, lb, lc, ld, a, f32, st);
+                });
+            }
+            if (!ok) {
+                set_err(ERI_ESTATE, "no exchange kernel for class (%d%d|%d%d)", la, lb, lc, ld);
+                throw HipError{ERI_ESTATE};
+            }
         }
+    }
+}
+
+// Single-precision share of the last mixed build (same tile rules as the
+// kernels).  Synchronous.
+void mixed_counts(const eri_ctx *c)
+{
+    if (c->mix_counts_ok) return;
+    const size_t nk = c->kwork.size();
+    const size_t n = 2 * (nk + kPairClasses * kPairClasses);
+    DevBuf<unsigned long long> cnt;
+    cnt.alloc(n);
+    HIPCHK(hipMemsetAsync(cnt.p, 0, n * sizeof(unsigned long long), c->st));
+    for (size_t wi = 0; wi < nk; ++wi) {
+        const auto &w = c->kwork[wi];
+        if (w.nwork == 0) continue;
+        KArgs a = k_args(c, w, true);
+        const int la = kPairL[w.X][0], lb = kPairL[w.X][1], lc = kPairL[w.Y][0], ld = kPairL[w.Y][1];
+        const int kind = w.choff >= 0 ? 2 : (is_k_small(la, lb, lc, ld) ? 0 : 1);
+        launch_k_count_mix(a, kind, w.choff >= 0 ? c->d_chunks.p + w.choff : nullptr, w.nchunks, cnt.p + 2 * wi,
+                           c->st);
+    }
+    for (int X = 0; X < kPairClasses; ++X)
+        for (int Y = 0; Y < kPairClasses; ++Y) {
+            if (c->npp[X] == 0 || c->ncp[Y] == 0) continue;
+            JArgs a = j_args(c, X, Y, true);
+            const int lx = kPairL[X][0] + kPairL[X][1], ly = kPairL[Y][0] + kPairL[Y][1];
+            const int per_bra = (lx + ly > 5 && !jeng_is_reg(lx, ly)) ? 1 : 0;
+            launch_j_count_mix(a, per_bra, cnt.p + 2 * (nk + X * kPairClasses + Y), c->st);
+        }
+    HIPCHK(hipGetLastError());
+    std::vector<unsigned long long> h(n);
+    HIPCHK(hipStreamSynchronize(c->st));
+    HIPCHK(hipMemcpy(h.data(), cnt.p, n * sizeof(unsigned long long), hipMemcpyDeviceToHost));
+    c->kmix.assign(nk, {0, 0});
+    for (size_t wi = 0; wi < nk; ++wi) c->kmix[wi] = {(int64_t)h[2 * wi], (int64_t)h[2 * wi + 1]};
+    for (int X = 0; X < kPairClasses; ++X)
+        for (int Y = 0; Y < kPairClasses; ++Y)
+            for (int k = 0; k < 2; ++k) c->jmix[X][Y][k] = (int64_t)h[2 * (nk + X * kPairClasses + Y) + k];
+    c->mix_counts_ok = true;
+}
+
+// Primitive quartets and model FLOPs of one profiled launch.
+void rec_work(const eri_ctx *c, const eri_ctx::Rec &r, int64_t &pq, double &flops)
+{
+    pq = 0;
+    flops = 0.0;
+    if (r.work == 0) {
+        const auto &w = c->kwork[r.idx];
+        const int la = kPairL[w.X][0], lb = kPairL[w.X][1], lc = kPairL[w.Y][0], ld = kPairL[w.Y][1];
+        int64_t p = c->kprim[r.idx], nw = w.nwork;
+        if (r.part != 0) {
+            mixed_counts(c);
+            const int64_t ps = c->kmix[r.idx][0], ns = c->kmix[r.idx][1];
+            p = r.part == 2 ? ps : p - ps;
+            nw = r.part == 2 ? ns : nw - ns;
+        }
+        pq = p;
+        flops = (double)p * fl_k_prim(la, lb, lc, ld) + (double)nw * fl_k_digest(la, lb, lc, ld);
+    } else if (r.work == 1) {
+        const int X = r.idx / kPairClasses, Y = r.idx % kPairClasses;
+        int64_t p = c->jprim[X][Y];
+        if (r.part != 0) {
+            mixed_counts(c);
+            const int64_t ps = c->jmix[X][Y][0];
+            p = r.part == 2 ? ps : p - ps;
+        }
+        pq = p;
+        flops = (double)p * fl_j_prim(kPairL[X][0] + kPairL[X][1], kPairL[Y][0] + kPairL[Y][1]);
     }
 }
 
@@ -812,15 +972,23 @@ int build_jk(eri_ctx *ctx, const double *P, double *J, double *K)
         hipStream_t st = ctx->st;
         const ShellMap m = shell_map(ctx);
         const int nc = ctx->nbf_cart;
+        const bool mixed = ctx->opts.precision == ERI_MIXED;
         launch_p_to_cart(P, ctx->nbf, ctx->d_Pc.p, nc, m, ctx->opts.spherical, st);
+        if (mixed) {
+            ensure_mixed(ctx);
+            launch_density_bounds(ctx->d_Pc.p, nc, ctx->d_l.p, ctx->d_coff.p, ctx->nshell, ctx->d_Pm.p, ctx->d_cp.p,
+                                  ctx->d_Q.p, (int)ctx->cp.size(), ctx->d_QD.p, st);
+        }
+        ctx->built_mixed = mixed;
+        ctx->mix_counts_ok = false;
         if (J) {
             launch_fill_zero(ctx->d_Jacc.p, (int64_t)nc * nc, st);
-            run_j(ctx);
+            run_j(ctx, mixed);
             launch_acc_to_out(ctx->d_Jacc.p, nc, J, ctx->nbf, m, ctx->opts.spherical, st);
         }
         if (K) {
             launch_fill_zero(ctx->d_Kacc.p, (int64_t)nc * nc, st);
-            run_k(ctx);
+            run_k(ctx, mixed);
             launch_acc_to_out(ctx->d_Kacc.p, nc, K, ctx->nbf, m, ctx->opts.spherical, st);
         }
         HIPCHK(hipGetLastError());
@@ -849,6 +1017,14 @@ int eri_stats(const eri_ctx *ctx, eri_stats_t *out)
     out->n_pairs = (int64_t)ctx->cp.size();
     out->n_prim_pairs = (int64_t)ctx->pp.size();
     out->n_quartets = ctx->n_quartets;
+    if (ctx->built_mixed) {
+        try {
+            mixed_counts(ctx);
+        } catch (const HipError &e) {
+            return e.code;
+        }
+        for (const auto &v : ctx->kmix) out->n_quartets_fp32 += v[1];
+    }
     out->eris_sph = ctx->eris_sph;
     out->eris_cart = ctx->eris_cart;
     out->model_flops_k = ctx->model_flops_k;
@@ -876,8 +1052,7 @@ int eri_profile_read(eri_ctx *ctx, eri_kernel_time *out, int32_t cap, int32_t *n
             auto &acc = ctx->prof[r.name];
             acc.launches += 1;
             acc.ms += ms;
-            acc.flops = r.flops;
-            acc.pq = r.pq;
+            rec_work(ctx, r, acc.pq, acc.flops);
             (void)hipEventDestroy(r.a);
             (void)hipEventDestroy(r.b);
         }

@@ -24,9 +24,9 @@ struct EprodLayout {
     }
 };
 
-template <int LA, int LB>
+template <int LA, int LB, typename T>
 __global__ __launch_bounds__(128) void eprod_build(const PrimPair *__restrict__ pp, int pbase, int n,
-                                                   double *__restrict__ out)
+                                                   T *__restrict__ out)
 {
     constexpr EprodLayout<LA, LB> lay{};
     constexpr int S = lay.off[lay.NAB];
@@ -37,7 +37,11 @@ __global__ __launch_bounds__(128) void eprod_build(const PrimPair *__restrict__ 
     etab_build<LA, LB>(p.PA[0], p.PB[0], p.o2p, Ex);
     etab_build<LA, LB>(p.PA[1], p.PB[1], p.o2p, Ey);
     etab_build<LA, LB>(p.PA[2], p.PB[2], p.o2p, Ez);
-    double *o = out + (int64_t)g * S;
+    T *o = out + (int64_t)g * S;
+    // single precision: K_ab E_t (2p)^{|t|/2} (scaled form, md_device.hpp)
+    double cw[LA + LB + 1];
+    cw[0] = sizeof(T) == 4 ? p.K : 1.0;
+    for (int k = 1; k <= LA + LB; ++k) cw[k] = cw[k - 1] * (sizeof(T) == 4 ? sqrt(2.0 * p.p) : 1.0);
     static_for<0, lay.NAB>([&](auto abc) {
         constexpr int ab = decltype(abc)::value;
         constexpr int a = ab / lay.NB, b = ab % lay.NB;
@@ -50,7 +54,7 @@ __global__ __launch_bounds__(128) void eprod_build(const PrimPair *__restrict__ 
                 constexpr int ty = decltype(tyc)::value;
                 static_for<0, nz>([&](auto tzc) {
                     constexpr int tz = decltype(tzc)::value;
-                    o[lay.off[ab] + (tx * ny + ty) * nz + tz] = Ex.e[ax][bx][tx] * Ey.e[ay][by][ty] * Ez.e[az][bz][tz];
+                    o[lay.off[ab] + (tx * ny + ty) * nz + tz] = (T)(Ex.e[ax][bx][tx] * Ey.e[ay][by][ty] * Ez.e[az][bz][tz] * cw[tx + ty + tz]);
                 });
             });
         });
@@ -65,18 +69,31 @@ int eprod_size(int la, int lb)
     return s;
 }
 
-void launch_eprod(int la, int lb, const PrimPair *pp, int pbase, int n, double *out, hipStream_t st)
+// The products are formed in double precision; the single-precision table
+// used by the mixed mode holds the scaled products K_ab E_t (2p)^{|t|/2}.
+template <typename T>
+void launch_eprod_t(int la, int lb, const PrimPair *pp, int pbase, int n, T *out, hipStream_t st)
 {
     if (n <= 0) return;
     const unsigned blocks = (unsigned)((n + 127) / 128);
 #define MD_EP(A_, B_)                                                                         \
     if (la == A_ && lb == B_) {                                                              \
-        hipLaunchKernelGGL((eprod_build<A_, B_>), dim3(blocks), dim3(128), 0, st, pp, pbase, n, out); \
+        hipLaunchKernelGGL((eprod_build<A_, B_, T>), dim3(blocks), dim3(128), 0, st, pp, pbase, n, out); \
         return;                                                                              \
     }
     MD_EP(0, 0) MD_EP(1, 0) MD_EP(1, 1) MD_EP(2, 0) MD_EP(2, 1) MD_EP(2, 2) MD_EP(3, 0) MD_EP(3, 1)
     MD_EP(3, 2) MD_EP(3, 3)
 #undef MD_EP
+}
+
+void launch_eprod(int la, int lb, const PrimPair *pp, int pbase, int n, double *out, hipStream_t st)
+{
+    launch_eprod_t<double>(la, lb, pp, pbase, n, out, st);
+}
+
+void launch_eprod(int la, int lb, const PrimPair *pp, int pbase, int n, float *out, hipStream_t st)
+{
+    launch_eprod_t<float>(la, lb, pp, pbase, n, out, st);
 }
 
 }  // namespace md

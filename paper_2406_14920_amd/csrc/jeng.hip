@@ -22,7 +22,8 @@ template <int LC, int LD>
 __global__ __launch_bounds__(128) void hermite_density(const CPair *__restrict__ cp, int ncp,
                                                        const PrimPair *__restrict__ pp,
                                                        const double *__restrict__ D, int ld,
-                                                       double *__restrict__ Dt, int dt_base)
+                                                       double *__restrict__ Dt, float *__restrict__ Dtf,
+                                                       int dt_base)
 {
     constexpr int NC = ncart(LC), ND = ncart(LD), LCD = LC + LD, NH = nherm(LCD);
     constexpr int EKD = (LC + 1) * (LD + 1) * (LCD + 1);
@@ -57,7 +58,14 @@ __global__ __launch_bounds__(128) void hermite_density(const CPair *__restrict__
                        sE[2 * EKD + (cz * (LD + 1) + dz) * (LCD + 1) + qv] * sDb[cd];
             }
             const double sg = ((qt + qu + qv) & 1) ? -1.0 : 1.0;
-            Dt[(int64_t)(B.poff + kp - dt_base) * NH + Q] = sg * f * acc;
+            const int64_t o = (int64_t)(B.poff + kp - dt_base) * NH + Q;
+            Dt[o] = sg * f * acc;
+            if (Dtf) {  // scaled single-precision form: K_cd Dt_Q (2q)^{|Q|/2}
+                double sc = pk.K;
+                const double c = sqrt(2.0 * pk.p);
+                for (int k = 0; k < qt + qu + qv; ++k) sc *= c;
+                Dtf[o] = (float)(sg * f * acc * sc);
+            }
         }
         __syncthreads();
     }
@@ -95,10 +103,15 @@ __device__ __forceinline__ int count_kets(const double *__restrict__ Q, int n, d
 // ---------------------------------------------------------------------------
 // 2a. Hermite J, registers: one lane per bra primitive pair
 // ---------------------------------------------------------------------------
-template <int LX, int LY>
+// In the mixed mode the precision tile is (wavefront of bra pairs, ket pair
+// j): double precision when max_wave(Q_ab) Q_cd max|D_cd| reaches the
+// threshold.  Single-precision tiles are summed per ket pair in T and added to
+// a double-precision accumulator.
+template <int LX, int LY, typename T>
 __global__ __launch_bounds__(64) void jeng_small(JArgs a)
 {
     constexpr int L = LX + LY, NX = nherm(LX), NY = nherm(LY);
+    constexpr bool F32 = sizeof(T) == 4;
     const int g = blockIdx.x * 64 + threadIdx.x;
     const bool valid = g < a.nbp;
     const int gi = valid ? g : a.nbp - 1;
@@ -108,55 +121,92 @@ __global__ __launch_bounds__(64) void jeng_small(JArgs a)
     const int nv = valid ? count_kets(a.Qket, a.nket, Qi, a.tau) : 0;
     const int nvmax = __builtin_amdgcn_readfirstlane(wave_max(nv));
     const double qmax = uniform_d(wave_max(qi));
+    const double Qw = a.mode ? uniform_d(wave_max(Qi)) : 0.0;
     const int j0 = blockIdx.y * a.kchunk;
     const int j1 = min(min(a.nket, j0 + a.kchunk), nvmax);
+    const T *__restrict__ Dt = pick<T>(a.Dt, a.Dtf);
 
-    double Jh[NX];
+    T Jt[NX];
+    double Jh[F32 ? NX : 1];
 #pragma unroll
-    for (int i = 0; i < NX; ++i) Jh[i] = 0.0;
+    for (int i = 0; i < NX; ++i) Jt[i] = T(0);
+#pragma unroll
+    for (int i = 0; i < (F32 ? NX : 1); ++i) Jh[i] = 0.0;
     for (int j = j0; j < j1; ++j) {
+        if (a.mode && (Qw * a.QDket[j] >= a.tau_mix) != (a.mode == 1)) continue;
         const CPair B = a.ket[j];
         for (int kp = 0; kp < B.np; ++kp) {
             const PrimPair pk = a.pp[B.poff + kp];
             if (qmax * pk.q < a.tau_prim) break;
             if (j < nv && qi * pk.q >= a.tau_prim) {
-                double Fs[L + 1], X, Y, Z;
-                quartet_fs<L>(pb, pk, a.boys, Fs, X, Y, Z);
-                double R[nherm(L)];
-                r_build<L>(Fs, X, Y, Z, R);
-                const double *dt = a.Dt + (int64_t)(B.poff + kp - a.dt_base) * NY;
-                double dq[NY];
-#pragma unroll
-                for (int q = 0; q < NY; ++q) dq[q] = dt[q];
+                T Fs[L + 1], X, Y, Z;
+                T rp[LY + 1];
+                if constexpr (F32) {
+                    float r;
+                    quartet_fs_scaled<L>(pb, pk, a.boys, Fs, X, Y, Z, r);
+                    powers<LY>(r, rp);
+                } else {
+                    quartet_fs<L, T>(pb, pk, a.boys, Fs, X, Y, Z);
+                }
+                T R[nherm(L)];
+                r_build<L, T>(Fs, X, Y, Z, R);
+                const T *dt = Dt + (int64_t)(B.poff + kp - a.dt_base) * NY;
+                T dq[NY];
+                static_for<0, NY>([&](auto qc) {
+                    constexpr int q = decltype(qc)::value;
+                    if constexpr (F32)
+                        dq[q] = dt[q] * rp[herm_t(q) + herm_u(q) + herm_v(q)];
+                    else
+                        dq[q] = dt[q];
+                });
                 static_for<0, NX>([&](auto pc) {
                     constexpr int P = decltype(pc)::value;
                     constexpr int tp = herm_t(P), up = herm_u(P), vp = herm_v(P);
-                    double acc = Jh[P];
+                    T acc = Jt[P];
                     static_for<0, NY>([&](auto qc) {
                         constexpr int Q = decltype(qc)::value;
                         acc += R[herm_idx(tp + herm_t(Q), up + herm_u(Q), vp + herm_v(Q))] * dq[Q];
                     });
-                    Jh[P] = acc;
+                    Jt[P] = acc;
                 });
+            }
+        }
+        if constexpr (F32) {
+#pragma unroll
+            for (int i = 0; i < NX; ++i) {
+                Jh[i] += (double)Jt[i];
+                Jt[i] = T(0);
             }
         }
     }
     if (valid && j1 > j0) {
+        // scaled form: Jh_P = K_ab (2p)^{|P|/2} times the single-precision sum
+        double cw[LX + 1];
+        cw[0] = pb.K;
+        const double c = sqrt(2.0 * pb.p);
 #pragma unroll
-        for (int P = 0; P < NX; ++P) unsafeAtomicAdd(&a.Jh[(int64_t)g * NX + P], Jh[P]);
+        for (int k = 1; k <= LX; ++k) cw[k] = cw[k - 1] * c;
+        static_for<0, NX>([&](auto pc) {
+            constexpr int P = decltype(pc)::value;
+            double v;
+            if constexpr (F32) v = Jh[P] * cw[herm_t(P) + herm_u(P) + herm_v(P)]; else v = Jt[P];
+            unsafeAtomicAdd(&a.Jh[(int64_t)g * NX + P], v);
+        });
     }
 }
 
 // ---------------------------------------------------------------------------
 // 2b. Hermite J, LDS: one wavefront per (bra primitive pair, ket chunk)
 // ---------------------------------------------------------------------------
-template <int LX, int LY>
+// Mixed mode: the tile is (bra primitive pair, ket pair j).
+template <int LX, int LY, typename T>
 __global__ __launch_bounds__(64) void jeng_wave(JArgs a)
 {
     constexpr int L = LX + LY, L1 = L + 1, NX = nherm(LX), NY = nherm(LY);
-    __shared__ double sR0[L1 * L1 * L1];
-    __shared__ double sF[L + 1];
-    __shared__ double sPow[3 * (L + 1)];
+    __shared__ T sR0[L1 * L1 * L1];
+    __shared__ T sF[L + 1];
+    __shared__ T sPow[3 * (L + 1)];
+    __shared__ T sDq[NY];  // single precision: r^|Q| times the scaled Hermite density
     const int lane = threadIdx.x;
     const int g = blockIdx.x;
     const PrimPair pb = a.pp[a.pbase + g];
@@ -177,37 +227,60 @@ __global__ __launch_bounds__(64) void jeng_wave(JArgs a)
         const int code = c_herm.tuv[own[r] ? P : 0];
         pof[r] = ((code & 0xff) * L1 + ((code >> 8) & 0xff)) * L1 + (code >> 16);
     }
+    const T *__restrict__ Dt = pick<T>(a.Dt, a.Dtf);
     double acc[2] = {0.0, 0.0};
     for (int j = j0; j < j1; ++j) {
+        if (a.mode && (Qi * a.QDket[j] >= a.tau_mix) != (a.mode == 1)) continue;
         const CPair B = a.ket[j];
         for (int kp = 0; kp < B.np; ++kp) {
             const PrimPair pk = a.pp[B.poff + kp];
             if (qi * pk.q < a.tau_prim) break;
             const QuartetGeo geo = quartet_geo(pb, pk);
-            wave_boys<L>(geo, a.boys, sF, lane);
-            wave_powers<L>(geo, sPow, lane);
+            wave_boys<L, T>(geo, a.boys, sF, lane);
+            wave_powers<L, T>(geo, sPow, lane);
+            const T *dt = Dt + (int64_t)(B.poff + kp - a.dt_base) * NY;
+            if constexpr (sizeof(T) == 4) {
+                for (int Q = lane; Q < NY; Q += 64) {
+                    const int code = c_herm.tuv[Q];
+                    const int n = (code & 0xff) + ((code >> 8) & 0xff) + (code >> 16);
+                    float w = dt[Q];
+                    const float r = (float)geo.r;
+                    for (int k = 0; k < n; ++k) w *= r;
+                    sDq[Q] = w;
+                }
+                dt = sDq;
+            }
             __syncthreads();
-            wave_r0<L>(sF, sPow, sR0, lane);
+            wave_r0<L, T>(sF, sPow, sR0, lane);
             __syncthreads();
-            const double *dt = a.Dt + (int64_t)(B.poff + kp - a.dt_base) * NY;
 #pragma unroll
             for (int r = 0; r < 2; ++r) {
                 if (!own[r]) continue;
-                const double *Rb = sR0 + pof[r];
-                double s = 0.0;
+                const T *Rb = sR0 + pof[r];
+                T s = T(0);
                 static_for<0, NY>([&](auto qc) {
                     constexpr int Q = decltype(qc)::value;
                     constexpr int qo = (herm_t(Q) * L1 + herm_u(Q)) * L1 + herm_v(Q);
                     s += Rb[qo] * dt[Q];
                 });
-                acc[r] += s;
+                acc[r] += (double)s;
             }
             __syncthreads();
         }
     }
 #pragma unroll
     for (int r = 0; r < 2; ++r)
-        if (own[r]) unsafeAtomicAdd(&a.Jh[(int64_t)g * NX + lane + 64 * r], acc[r]);
+        if (own[r]) {
+            double v = acc[r];
+            if constexpr (sizeof(T) == 4) {  // K_ab (2p)^{|P|/2} of the scaled form
+                const int code = c_herm.tuv[lane + 64 * r];
+                const int n = (code & 0xff) + ((code >> 8) & 0xff) + (code >> 16);
+                const double c = sqrt(2.0 * pb.p);
+                v *= pb.K;
+                for (int k = 0; k < n; ++k) v *= c;
+            }
+            unsafeAtomicAdd(&a.Jh[(int64_t)g * NX + lane + 64 * r], v);
+        }
 }
 
 // ---------------------------------------------------------------------------
@@ -264,13 +337,13 @@ __global__ __launch_bounds__(128) void hermite_to_cart(const CPair *__restrict__
 // launchers
 // ---------------------------------------------------------------------------
 void launch_hermite_density(int lc, int ld_, const CPair *cp, int ncp, const PrimPair *pp,
-                            const double *D, int ldd, double *Dt, int dt_base, hipStream_t st)
+                            const double *D, int ldd, double *Dt, float *Dtf, int dt_base, hipStream_t st)
 {
     if (ncp <= 0) return;
 #define MD_HD(C_, D_)                                                                         \
     if (lc == C_ && ld_ == D_) {                                                             \
         hipLaunchKernelGGL((hermite_density<C_, D_>), dim3(ncp), dim3(128), 0, st, cp, ncp, pp, D, \
-                           ldd, Dt, dt_base);                                                \
+                           ldd, Dt, Dtf, dt_base);                                                \
         return;                                                                              \
     }
     MD_HD(0, 0) MD_HD(1, 0) MD_HD(1, 1) MD_HD(2, 0) MD_HD(2, 1) MD_HD(2, 2) MD_HD(3, 0) MD_HD(3, 1)
@@ -296,29 +369,30 @@ void launch_hermite_to_cart(int la, int lb, const CPair *cp, int ncp, const Prim
 // total Hermite order at or below which the register path is used
 constexpr int kJengRegMaxL = 5;
 
-bool launch_jeng_reg_0(int lx, int ly, const JArgs &a, hipStream_t st);
-bool launch_jeng_reg_1(int lx, int ly, const JArgs &a, hipStream_t st);
-bool launch_jeng_reg_2(int lx, int ly, const JArgs &a, hipStream_t st);
-bool launch_jeng_reg_3(int lx, int ly, const JArgs &a, hipStream_t st);
+bool launch_jeng_reg_0(int lx, int ly, const JArgs &a, bool fp32, hipStream_t st);
+bool launch_jeng_reg_1(int lx, int ly, const JArgs &a, bool fp32, hipStream_t st);
+bool launch_jeng_reg_2(int lx, int ly, const JArgs &a, bool fp32, hipStream_t st);
+bool launch_jeng_reg_3(int lx, int ly, const JArgs &a, bool fp32, hipStream_t st);
 
-template <int LX, int LY>
+template <int LX, int LY, typename T>
 void jeng_launch_t(const JArgs &a, hipStream_t st)
 {
-    if (launch_jeng_reg_0(LX, LY, a, st) || launch_jeng_reg_1(LX, LY, a, st) ||
-        launch_jeng_reg_2(LX, LY, a, st) || launch_jeng_reg_3(LX, LY, a, st))
+    constexpr bool f32 = sizeof(T) == 4;
+    if (launch_jeng_reg_0(LX, LY, a, f32, st) || launch_jeng_reg_1(LX, LY, a, f32, st) ||
+        launch_jeng_reg_2(LX, LY, a, f32, st) || launch_jeng_reg_3(LX, LY, a, f32, st))
         return;
     const int nch = (a.nket + a.kchunk - 1) / a.kchunk;
     if (a.nbp <= 0 || nch <= 0) return;
     if constexpr (LX + LY <= kJengRegMaxL) {
         dim3 grid((a.nbp + 63) / 64, nch);
-        hipLaunchKernelGGL((jeng_small<LX, LY>), grid, dim3(64), 0, st, a);
+        hipLaunchKernelGGL((jeng_small<LX, LY, T>), grid, dim3(64), 0, st, a);
     } else {
         dim3 grid(a.nbp, nch);
-        hipLaunchKernelGGL((jeng_wave<LX, LY>), grid, dim3(64), 0, st, a);
+        hipLaunchKernelGGL((jeng_wave<LX, LY, T>), grid, dim3(64), 0, st, a);
     }
 }
 
-bool launch_jeng(int lx, int ly, const JArgs &a, hipStream_t st)
+bool launch_jeng(int lx, int ly, const JArgs &a, bool fp32, hipStream_t st)
 {
     bool done = false;
     static_for<0, 7>([&](auto xc) {
@@ -326,7 +400,7 @@ bool launch_jeng(int lx, int ly, const JArgs &a, hipStream_t st)
         static_for<0, 7>([&](auto yc) {
             constexpr int Yv = decltype(yc)::value;
             if (!done && lx == X && ly == Yv) {
-                jeng_launch_t<X, Yv>(a, st);
+                if (fp32) jeng_launch_t<X, Yv, float>(a, st); else jeng_launch_t<X, Yv, double>(a, st);
                 done = true;
             }
         });

@@ -18,25 +18,25 @@ __host__ __device__ constexpr double hcoef(int t, int a)
     return v;
 }
 
-template <int LX, int LY>
-__device__ __forceinline__ void jeng_quartet_stream(const double *G, const double *px, const double *py,
-                                                    const double *pz, const double *dq, double *Jh)
+template <int LX, int LY, typename T>
+__device__ __forceinline__ void jeng_quartet_stream(const T *G, const T *px, const T *py,
+                                                    const T *pz, const T *dq, T *Jh)
 {
     constexpr int L = LX + LY;
     static_for<0, nherm(L)>([&](auto Nc) {
         constexpr int N = decltype(Nc)::value;
         constexpr int t = herm_t(N), u = herm_u(N), v = herm_v(N);
-        double r = 0.0;
+        T r = T(0);
         static_for<0, t / 2 + 1>([&](auto ac) {
             constexpr int a = decltype(ac)::value;
             static_for<0, u / 2 + 1>([&](auto bc) {
                 constexpr int b = decltype(bc)::value;
-                double rz = 0.0;
+                T rz = T(0);
                 static_for<0, v / 2 + 1>([&](auto cc) {
                     constexpr int c = decltype(cc)::value;
-                    rz += hcoef(v, c) * pz[v - 2 * c] * G[t + u + v - a - b - c];
+                    rz += T(hcoef(v, c)) * pz[v - 2 * c] * G[t + u + v - a - b - c];
                 });
-                r += hcoef(t, a) * hcoef(u, b) * px[t - 2 * a] * py[u - 2 * b] * rz;
+                r += T(hcoef(t, a) * hcoef(u, b)) * px[t - 2 * a] * py[u - 2 * b] * rz;
             });
         });
         // scatter: P + Q = N, P in H(LX), Q in H(LY)
@@ -55,10 +55,13 @@ __device__ __forceinline__ void jeng_quartet_stream(const double *G, const doubl
     });
 }
 
-template <int LX, int LY>
+// Mixed mode: tile (wavefront of bra pairs, ket pair j) as in jeng_small;
+// single-precision tiles are summed per ket pair and added in double.
+template <int LX, int LY, typename T>
 __global__ __launch_bounds__(64) void jeng_reg(JArgs a)
 {
     constexpr int L = LX + LY, NX = nherm(LX), NY = nherm(LY);
+    constexpr bool F32 = sizeof(T) == 4;
     const int g = blockIdx.x * 64 + threadIdx.x;
     const bool valid = g < a.nbp;
     const int gi = valid ? g : a.nbp - 1;
@@ -72,10 +75,11 @@ __global__ __launch_bounds__(64) void jeng_reg(JArgs a)
     }
     const int nv = valid ? lo : 0;
     int nvmax = nv;
-    double qmax = qi;
+    double qmax = qi, Qw = Qi;
     for (int off = 32; off > 0; off >>= 1) {
         nvmax = max(nvmax, __shfl_xor(nvmax, off));
         qmax = fmax(qmax, __shfl_xor(qmax, off));
+        Qw = fmax(Qw, __shfl_xor(Qw, off));
     }
     nvmax = __builtin_amdgcn_readfirstlane(nvmax);
     {
@@ -87,45 +91,65 @@ __global__ __launch_bounds__(64) void jeng_reg(JArgs a)
     const int j0 = blockIdx.y * a.kchunk;
     const int j1 = min(min(a.nket, j0 + a.kchunk), nvmax);
 
-    double Jh[NX];
+    const T *__restrict__ Dt = pick<T>(a.Dt, a.Dtf);
+    T Jt[NX];
+    double Jh[F32 ? NX : 1];
 #pragma unroll
-    for (int i = 0; i < NX; ++i) Jh[i] = 0.0;
+    for (int i = 0; i < NX; ++i) Jt[i] = T(0);
+#pragma unroll
+    for (int i = 0; i < (F32 ? NX : 1); ++i) Jh[i] = 0.0;
     for (int j = j0; j < j1; ++j) {
+        if (a.mode && (Qw * a.QDket[j] >= a.tau_mix) != (a.mode == 1)) continue;
         const CPair B = a.ket[j];
         for (int kp = 0; kp < B.np; ++kp) {
             const PrimPair pk = a.pp[B.poff + kp];
             if (qmax * pk.q < a.tau_prim) break;
             if (j < nv && qi * pk.q >= a.tau_prim) {
-                const double p = pb.p, q = pk.p, rpq = 1.0 / (p + q), alpha = p * q * rpq;
-                const double X = pb.P[0] - pk.P[0], Y = pb.P[1] - pk.P[1], Z = pb.P[2] - pk.P[2];
-                double F[L + 1];
-                boys_all<L>(alpha * (X * X + Y * Y + Z * Z), F, a.boys);
-                double G[L + 1], px[L + 1], py[L + 1], pz[L + 1];
-                double s = kTwoPi52 * pb.K * pk.K / (p * q) * sqrt(rpq);
-                const double m2a = -2.0 * alpha;
-                px[0] = py[0] = pz[0] = 1.0;
-#pragma unroll
-                for (int m = 0; m <= L; ++m) {
-                    G[m] = s * F[m];
-                    s *= m2a;
+                T G[L + 1], px[L + 1], py[L + 1], pz[L + 1], Xt, Yt, Zt;
+                T rp[LY + 1];
+                if constexpr (F32) {  // scaled single-precision form (md_device.hpp)
+                    float r;
+                    quartet_fs_scaled<L>(pb, pk, a.boys, G, Xt, Yt, Zt, r);
+                    powers<LY>(r, rp);
+                } else {
+                    quartet_fs<L, T>(pb, pk, a.boys, G, Xt, Yt, Zt);
                 }
+                powers<L>(Xt, px);
+                powers<L>(Yt, py);
+                powers<L>(Zt, pz);
+                const T *__restrict__ dt = Dt + (int64_t)(B.poff + kp - a.dt_base) * NY;
+                T dq[NY];
+                static_for<0, NY>([&](auto qc) {
+                    constexpr int k = decltype(qc)::value;
+                    if constexpr (F32)
+                        dq[k] = dt[k] * rp[herm_t(k) + herm_u(k) + herm_v(k)];
+                    else
+                        dq[k] = dt[k];
+                });
+                jeng_quartet_stream<LX, LY, T>(G, px, py, pz, dq, Jt);
+            }
+        }
+        if constexpr (F32) {
 #pragma unroll
-                for (int m = 1; m <= L; ++m) {
-                    px[m] = px[m - 1] * X;
-                    py[m] = py[m - 1] * Y;
-                    pz[m] = pz[m - 1] * Z;
-                }
-                const double *__restrict__ dt = a.Dt + (int64_t)(B.poff + kp - a.dt_base) * NY;
-                double dq[NY];
-#pragma unroll
-                for (int k = 0; k < NY; ++k) dq[k] = dt[k];
-                jeng_quartet_stream<LX, LY>(G, px, py, pz, dq, Jh);
+            for (int i = 0; i < NX; ++i) {
+                Jh[i] += (double)Jt[i];
+                Jt[i] = T(0);
             }
         }
     }
     if (valid && j1 > j0) {
+        // scaled form: Jh_P = K_ab (2p)^{|P|/2} times the single-precision sum
+        double cw[LX + 1];
+        cw[0] = pb.K;
+        const double c = sqrt(2.0 * pb.p);
 #pragma unroll
-        for (int P = 0; P < NX; ++P) unsafeAtomicAdd(&a.Jh[(int64_t)g * NX + P], Jh[P]);
+        for (int k = 1; k <= LX; ++k) cw[k] = cw[k - 1] * c;
+        static_for<0, NX>([&](auto pc) {
+            constexpr int P = decltype(pc)::value;
+            double v;
+            if constexpr (F32) v = Jh[P] * cw[herm_t(P) + herm_u(P) + herm_v(P)]; else v = Jt[P];
+            unsafeAtomicAdd(&a.Jh[(int64_t)g * NX + P], v);
+        });
     }
 }
 
@@ -137,12 +161,15 @@ __host__ __device__ constexpr bool jeng_reg_ok(int lx, int ly)
 }
 
 template <int LX, int LY>
-void jeng_reg_launch_t(const JArgs &a, hipStream_t st)
+void jeng_reg_launch_t(const JArgs &a, bool fp32, hipStream_t st)
 {
     const int nch = (a.nket + a.kchunk - 1) / a.kchunk;
     if (a.nbp <= 0 || nch <= 0) return;
     dim3 grid((a.nbp + 63) / 64, nch);
-    hipLaunchKernelGGL((jeng_reg<LX, LY>), grid, dim3(64), 0, st, a);
+    if (fp32)
+        hipLaunchKernelGGL((jeng_reg<LX, LY, float>), grid, dim3(64), 0, st, a);
+    else
+        hipLaunchKernelGGL((jeng_reg<LX, LY, double>), grid, dim3(64), 0, st, a);
 }
 
 }  // namespace md

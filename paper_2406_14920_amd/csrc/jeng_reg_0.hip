@@ -3,11 +3,11 @@
 
 namespace md {
 
-bool launch_jeng_reg_0(int lx, int ly, const JArgs &a, hipStream_t st)
+bool launch_jeng_reg_0(int lx, int ly, const JArgs &a, bool fp32, hipStream_t st)
 {
-    if (lx == 3 && ly == 5) { jeng_reg_launch_t<3, 5>(a, st); return true; }
-    if (lx == 4 && ly == 3) { jeng_reg_launch_t<4, 3>(a, st); return true; }
-    if (lx == 3 && ly == 3) { jeng_reg_launch_t<3, 3>(a, st); return true; }
+    if (lx == 3 && ly == 5) { jeng_reg_launch_t<3, 5>(a, fp32, st); return true; }
+    if (lx == 4 && ly == 3) { jeng_reg_launch_t<4, 3>(a, fp32, st); return true; }
+    if (lx == 3 && ly == 3) { jeng_reg_launch_t<3, 3>(a, fp32, st); return true; }
     return false;
 }
 

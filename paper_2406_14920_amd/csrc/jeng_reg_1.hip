@@ -3,11 +3,11 @@
 
 namespace md {
 
-bool launch_jeng_reg_1(int lx, int ly, const JArgs &a, hipStream_t st)
+bool launch_jeng_reg_1(int lx, int ly, const JArgs &a, bool fp32, hipStream_t st)
 {
-    if (lx == 4 && ly == 4) { jeng_reg_launch_t<4, 4>(a, st); return true; }
-    if (lx == 5 && ly == 2) { jeng_reg_launch_t<5, 2>(a, st); return true; }
-    if (lx == 4 && ly == 2) { jeng_reg_launch_t<4, 2>(a, st); return true; }
+    if (lx == 4 && ly == 4) { jeng_reg_launch_t<4, 4>(a, fp32, st); return true; }
+    if (lx == 5 && ly == 2) { jeng_reg_launch_t<5, 2>(a, fp32, st); return true; }
+    if (lx == 4 && ly == 2) { jeng_reg_launch_t<4, 2>(a, fp32, st); return true; }
     return false;
 }
 

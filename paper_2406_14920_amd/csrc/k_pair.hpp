@@ -10,6 +10,8 @@
 // budget are produced in compile-time passes over (ab, cd) chunks, R being
 // rebuilt per pass.  Each finished chunk is digested by the lane into the
 // four exchange blocks of the 8-fold symmetry and added to the accumulator.
+// T is the arithmetic type of the primitive integrals (the digestion is in
+// double precision); in the mixed mode a workgroup is one precision tile.
 #pragma once
 #include "kern_args.hpp"
 #include "md_device.hpp"
@@ -32,13 +34,15 @@ struct EprodOff {
 };
 
 
-template <int LA, int LB, int LC, int LD>
+template <int LA, int LB, int LC, int LD, typename T = double>
 struct KPairCfg {
     static constexpr int NA = ncart(LA), NB = ncart(LB), NC = ncart(LC), ND = ncart(LD);
     static constexpr int NAB = NA * NB, NCD = NC * ND;
     static constexpr int L = LA + LB + LC + LD, LAB = LA + LB, LCD = LC + LD;
     static constexpr bool XROUTE = LCD >= 2;  // precontract the ket into X_P
-    static constexpr int BUDGET0 = 120 - nherm(L) - (XROUTE ? nherm(LAB) : 0) - 12;
+    // values of type T that fit in about 240 VGPRs next to R, X_P and addresses
+    static constexpr int NREG = sizeof(T) == 4 ? 216 : 120;
+    static constexpr int BUDGET0 = NREG - nherm(L) - (XROUTE ? nherm(LAB) : 0) - 12;
     static constexpr int BUDGET = BUDGET0 < 12 ? 12 : BUDGET0;
     static constexpr int ABCH = NAB <= BUDGET ? NAB : BUDGET;
     static constexpr int NABP = (NAB + ABCH - 1) / ABCH;
@@ -47,10 +51,10 @@ struct KPairCfg {
     static constexpr int NCDP = (NCD + CDCH - 1) / CDCH;
 };
 
-template <int LA, int LB, int LC, int LD>
+template <int LA, int LB, int LC, int LD, typename T>
 __global__ __launch_bounds__(64) void k_pair(KPArgs a)
 {
-    using C = KPairCfg<LA, LB, LC, LD>;
+    using C = KPairCfg<LA, LB, LC, LD, T>;
     constexpr int NA = C::NA, NB = C::NB, NC = C::NC, ND = C::ND, NCD = C::NCD;
     constexpr int L = C::L, LAB = C::LAB;
     constexpr EprodOff<LA, LB> ob{};
@@ -65,6 +69,11 @@ __global__ __launch_bounds__(64) void k_pair(KPArgs a)
     const bool valid = jk < cnt;
     const CPair A = a.bra[ib];
     const CPair B = a.ket[valid ? jk : ch.y];
+    if (!mix_take(a.mode, a.mode != 0 && valid &&
+                              a.Qbra[ib] * a.Qket[jk] * k_dens_bound(a.Pm, a.nsh, A, B) >= a.tau_mix))
+        return;
+    const T *__restrict__ eprod_bra = pick<T>(a.eprod_bra, a.eprodf_bra);
+    const T *__restrict__ eprod_ket = pick<T>(a.eprod_ket, a.eprodf_ket);
     const int nkp = valid ? B.np : 0;
     const int n = a.ld;
     double s = 1.0;
@@ -79,41 +88,54 @@ __global__ __launch_bounds__(64) void k_pair(KPArgs a)
         constexpr int cd0 = (pass % C::NCDP) * C::CDCH;
         constexpr int cd1 = (cd0 + C::CDCH < NCD) ? cd0 + C::CDCH : NCD;
         constexpr int NABc = ab1 - ab0, NCDc = cd1 - cd0;
-        double V[NABc * NCDc];
+        T V[NABc * NCDc];
 #pragma unroll
-        for (int i = 0; i < NABc * NCDc; ++i) V[i] = 0.0;
+        for (int i = 0; i < NABc * NCDc; ++i) V[i] = T(0);
 
         for (int ip = 0; ip < A.np; ++ip) {
             const PrimPair pb = a.pp[A.poff + ip];
-            const double *__restrict__ eb = a.eprod_bra + (int64_t)(A.poff + ip - a.pbase_bra) * SB;
+            const T *__restrict__ eb = eprod_bra + (int64_t)(A.poff + ip - a.pbase_bra) * SB;
             for (int kp = 0; kp < nkp; ++kp) {
                 const PrimPair pk = a.pp[B.poff + kp];
                 if (pb.q * pk.q < a.tau_prim) break;
-                double Fs[L + 1], X, Y, Z;
-                quartet_fs<L>(pb, pk, a.boys, Fs, X, Y, Z);
-                double R[nherm(L)];
-                r_build<L>(Fs, X, Y, Z, R);
-                const double *__restrict__ ek = a.eprod_ket + (int64_t)(B.poff + kp - a.pbase_ket) * SK;
+                T Fs[L + 1], X, Y, Z;
+                T rp[C::LCD + 1];  // r^|s| of the scaled single-precision form
+                if constexpr (sizeof(T) == 4) {
+                    float r;
+                    quartet_fs_scaled<L>(pb, pk, a.boys, Fs, X, Y, Z, r);
+                    powers<C::LCD>(r, rp);
+                } else {
+                    quartet_fs<L, T>(pb, pk, a.boys, Fs, X, Y, Z);
+                }
+                T R[nherm(L)];
+                r_build<L, T>(Fs, X, Y, Z, R);
+                const T *__restrict__ ek = eprod_ket + (int64_t)(B.poff + kp - a.pbase_ket) * SK;
                 static_for<cd0, cd1>([&](auto cdc) {
                     constexpr int cd = decltype(cdc)::value;
                     constexpr int c = cd / ND, d = cd % ND;
                     constexpr int nsx = cart_x(LC, c) + cart_x(LD, d) + 1;
                     constexpr int nsy = cart_y(LC, c) + cart_y(LD, d) + 1;
                     constexpr int nsz = cart_z(LC, c) + cart_z(LD, d) + 1;
-                    double e[nsx * nsy * nsz];
-#pragma unroll
-                    for (int q = 0; q < nsx * nsy * nsz; ++q) e[q] = ek[ok.off[cd] + q];
+                    T e[nsx * nsy * nsz];
+                    static_for<0, nsx * nsy * nsz>([&](auto qc) {
+                        constexpr int q = decltype(qc)::value;
+                        constexpr int sn = q / (nsy * nsz) + (q / nsz) % nsy + q % nsz;
+                        if constexpr (sizeof(T) == 4)
+                            e[q] = ek[ok.off[cd] + q] * rp[sn];
+                        else
+                            e[q] = ek[ok.off[cd] + q];
+                    });
                     if constexpr (C::XROUTE) {
                         // X_P = sum_s (-1)^{|s|} E^{cd}_s R_{P+s}, then (ab|cd) = sum_t E^{ab}_t X_t
-                        double Xp[nherm(LAB)];
+                        T Xp[nherm(LAB)];
                         static_for<0, nherm(LAB)>([&](auto Pc) {
                             constexpr int P = decltype(Pc)::value;
                             constexpr int tp = herm_t(P), up = herm_u(P), vp = herm_v(P);
-                            double x = 0.0;
+                            T x = T(0);
                             static_for<0, nsx * nsy * nsz>([&](auto qc) {
                                 constexpr int q = decltype(qc)::value;
                                 constexpr int sx = q / (nsy * nsz), sy = (q / nsz) % nsy, sz = q % nsz;
-                                constexpr double sg = ((sx + sy + sz) & 1) ? -1.0 : 1.0;
+                                constexpr T sg = ((sx + sy + sz) & 1) ? T(-1) : T(1);
                                 x += sg * e[q] * R[herm_idx(tp + sx, up + sy, vp + sz)];
                             });
                             Xp[P] = x;
@@ -124,7 +146,7 @@ __global__ __launch_bounds__(64) void k_pair(KPArgs a)
                             constexpr int mx = cart_x(LA, ia) + cart_x(LB, jb) + 1;
                             constexpr int my = cart_y(LA, ia) + cart_y(LB, jb) + 1;
                             constexpr int mz = cart_z(LA, ia) + cart_z(LB, jb) + 1;
-                            double v = 0.0;
+                            T v = T(0);
                             static_for<0, mx * my * mz>([&](auto tc) {
                                 constexpr int t = decltype(tc)::value;
                                 constexpr int tx = t / (my * mz), ty = (t / mz) % my, tz = t % mz;
@@ -140,15 +162,15 @@ __global__ __launch_bounds__(64) void k_pair(KPArgs a)
                             constexpr int mx = cart_x(LA, ia) + cart_x(LB, jb) + 1;
                             constexpr int my = cart_y(LA, ia) + cart_y(LB, jb) + 1;
                             constexpr int mz = cart_z(LA, ia) + cart_z(LB, jb) + 1;
-                            double v = 0.0;
+                            T v = T(0);
                             static_for<0, mx * my * mz>([&](auto tc) {
                                 constexpr int t = decltype(tc)::value;
                                 constexpr int tx = t / (my * mz), ty = (t / mz) % my, tz = t % mz;
-                                double x = 0.0;
+                                T x = T(0);
                                 static_for<0, nsx * nsy * nsz>([&](auto qc) {
                                     constexpr int q = decltype(qc)::value;
                                     constexpr int sx = q / (nsy * nsz), sy = (q / nsz) % nsy, sz = q % nsz;
-                                    constexpr double sg = ((sx + sy + sz) & 1) ? -1.0 : 1.0;
+                                    constexpr T sg = ((sx + sy + sz) & 1) ? T(-1) : T(1);
                                     x += sg * e[q] * R[herm_idx(tx + sx, ty + sy, tz + sz)];
                                 });
                                 v += eb[ob.off[ab] + t] * x;
@@ -173,7 +195,7 @@ __global__ __launch_bounds__(64) void k_pair(KPArgs a)
                         constexpr int j = decltype(jc)::value;
                         constexpr int ab = i * NB + j;
                         if constexpr (ab >= ab0 && ab < ab1) {
-                            const double v = V[(ab - ab0) * NCDc + (cd - cd0)];
+                            const double v = (double)V[(ab - ab0) * NCDc + (cd - cd0)];
                             t13 += v * a.D[(int64_t)(A.c2 + j) * n + B.c2 + d];
                             t14 += v * a.D[(int64_t)(A.c2 + j) * n + B.c1 + c];
                             any = true;
@@ -192,7 +214,7 @@ __global__ __launch_bounds__(64) void k_pair(KPArgs a)
                         constexpr int i = decltype(ic)::value;
                         constexpr int ab = i * NB + j;
                         if constexpr (ab >= ab0 && ab < ab1) {
-                            const double v = V[(ab - ab0) * NCDc + (cd - cd0)];
+                            const double v = (double)V[(ab - ab0) * NCDc + (cd - cd0)];
                             t23 += v * a.D[(int64_t)(A.c1 + i) * n + B.c2 + d];
                             t24 += v * a.D[(int64_t)(A.c1 + i) * n + B.c1 + c];
                             any = true;
@@ -209,10 +231,13 @@ __global__ __launch_bounds__(64) void k_pair(KPArgs a)
 }
 
 template <int LA, int LB, int LC, int LD>
-void launch_k_pair_t(const KPArgs &a, int nchunks, hipStream_t st)
+void launch_k_pair_t(const KPArgs &a, int nchunks, bool fp32, hipStream_t st)
 {
     if (nchunks <= 0) return;
-    hipLaunchKernelGGL((k_pair<LA, LB, LC, LD>), dim3((unsigned)nchunks), dim3(64), 0, st, a);
+    if (fp32)
+        hipLaunchKernelGGL((k_pair<LA, LB, LC, LD, float>), dim3((unsigned)nchunks), dim3(64), 0, st, a);
+    else
+        hipLaunchKernelGGL((k_pair<LA, LB, LC, LD, double>), dim3((unsigned)nchunks), dim3(64), 0, st, a);
 }
 
 }  // namespace md

@@ -4,19 +4,23 @@
 // accumulates the contracted Cartesian block and digests it into the four
 // exchange blocks that the 8-fold permutational symmetry (eq. 8_fold_symmetry)
 // maps it to:  K_ac += V D_bd, K_ad += V D_bc, K_bc += V D_ad, K_bd += V D_ac.
-// The caller forms K = Kacc + Kacc^T afterwards.
+// The caller forms K = Kacc + Kacc^T afterwards.  T is the arithmetic type of
+// the primitive integrals; the digestion and the accumulator stay in double
+// precision.  In the mixed mode a wavefront (64 consecutive quartets) is one
+// precision tile.
 #include "class_lists.hpp"
 #include "kern_args.hpp"
 #include "md_device.hpp"
 
 namespace md {
 
-template <int LA, int LB, int LC, int LD>
+template <int LA, int LB, int LC, int LD, typename T>
 __global__ __launch_bounds__(128) void k_small(KArgs a)
 {
     constexpr int NA = ncart(LA), NB = ncart(LB), NC = ncart(LC), ND = ncart(LD);
     constexpr int L = LA + LB + LC + LD, LAB = LA + LB;
     constexpr int NBLK = NA * NB * NC * ND;
+    constexpr bool F32 = sizeof(T) == 4;
 
     int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (w >= a.nwork) return;
@@ -29,49 +33,68 @@ __global__ __launch_bounds__(128) void k_small(KArgs a)
     const int jk = (int)(w - a.prefix[ib]);
     const CPair A = a.bra[ib];
     const CPair B = a.ket[jk];
+    if (!mix_take(a.mode, a.mode != 0 && a.Qbra[ib] * a.Qket[jk] * k_dens_bound(a.Pm, a.nsh, A, B) >= a.tau_mix))
+        return;
 
-    double V[NBLK];
+    T V[NBLK];
 #pragma unroll
-    for (int i = 0; i < NBLK; ++i) V[i] = 0.0;
+    for (int i = 0; i < NBLK; ++i) V[i] = T(0);
 
     const double qk0 = a.pp[B.poff].q;
     for (int ip = 0; ip < A.np; ++ip) {
         const PrimPair pb = a.pp[A.poff + ip];
         if (pb.q * qk0 < a.tau_prim) break;
-        Etab<LA, LB> Ex, Ey, Ez;
-        etab_build<LA, LB>(pb.PA[0], pb.PB[0], pb.o2p, Ex);
-        etab_build<LA, LB>(pb.PA[1], pb.PB[1], pb.o2p, Ey);
-        etab_build<LA, LB>(pb.PA[2], pb.PB[2], pb.o2p, Ez);
+        Etab<LA, LB, T> Ex, Ey, Ez;
+        etab_build<LA, LB, T>((T)pb.PA[0], (T)pb.PB[0], (T)pb.o2p, Ex);
+        etab_build<LA, LB, T>((T)pb.PA[1], (T)pb.PB[1], (T)pb.o2p, Ey);
+        etab_build<LA, LB, T>((T)pb.PA[2], (T)pb.PB[2], (T)pb.o2p, Ez);
+        float cb = 0.f;
+        if constexpr (F32) {  // scaled single-precision form (md_device.hpp)
+            cb = (float)sqrt(2.0 * pb.p);
+            etab_scale<LA, LB>(Ex, cb, (float)pb.K);
+            etab_scale<LA, LB>(Ey, cb, 1.f);
+            etab_scale<LA, LB>(Ez, cb, 1.f);
+        }
         for (int kp = 0; kp < B.np; ++kp) {
             const PrimPair pk = a.pp[B.poff + kp];
             if (pb.q * pk.q < a.tau_prim) break;
-            double Fs[L + 1], X, Y, Z;
-            quartet_fs<L>(pb, pk, a.boys, Fs, X, Y, Z);
-            double R[nherm(L)];
-            r_build<L>(Fs, X, Y, Z, R);
-            Etab<LC, LD> Fx, Fy, Fz;
-            etab_build<LC, LD>(pk.PA[0], pk.PB[0], pk.o2p, Fx);
-            etab_build<LC, LD>(pk.PA[1], pk.PB[1], pk.o2p, Fy);
-            etab_build<LC, LD>(pk.PA[2], pk.PB[2], pk.o2p, Fz);
+            T Fs[L + 1], X, Y, Z;
+            if constexpr (F32) {
+                float r;
+                quartet_fs_scaled<L>(pb, pk, a.boys, Fs, X, Y, Z, r);
+            } else {
+                quartet_fs<L, T>(pb, pk, a.boys, Fs, X, Y, Z);
+            }
+            T R[nherm(L)];
+            r_build<L, T>(Fs, X, Y, Z, R);
+            Etab<LC, LD, T> Fx, Fy, Fz;
+            etab_build<LC, LD, T>((T)pk.PA[0], (T)pk.PB[0], (T)pk.o2p, Fx);
+            etab_build<LC, LD, T>((T)pk.PA[1], (T)pk.PB[1], (T)pk.o2p, Fy);
+            etab_build<LC, LD, T>((T)pk.PA[2], (T)pk.PB[2], (T)pk.o2p, Fz);
+            if constexpr (F32) {  // ket factors carry the bra's c
+                etab_scale<LC, LD>(Fx, cb, (float)pk.K);
+                etab_scale<LC, LD>(Fy, cb, 1.f);
+                etab_scale<LC, LD>(Fz, cb, 1.f);
+            }
             static_for<0, NC * ND>([&](auto cdc) {
                 constexpr int cd = decltype(cdc)::value;
                 constexpr int c = cd / ND, d = cd % ND;
                 constexpr int cx = cart_x(LC, c), cy = cart_y(LC, c), cz = cart_z(LC, c);
                 constexpr int dx = cart_x(LD, d), dy = cart_y(LD, d), dz = cart_z(LD, d);
                 // X_P = sum_s (-1)^{|s|} E^{cd}_s R_{P+s}   (ket half of eq. eri_formula)
-                double Xp[nherm(LAB)];
+                T Xp[nherm(LAB)];
                 static_for<0, nherm(LAB)>([&](auto pc) {
                     constexpr int P = decltype(pc)::value;
                     constexpr int tp = herm_t(P), up = herm_u(P), vp = herm_v(P);
-                    double s = 0.0;
+                    T s = T(0);
                     static_for<0, cx + dx + 1>([&](auto sxc) {
                         constexpr int sx = decltype(sxc)::value;
                         static_for<0, cy + dy + 1>([&](auto syc) {
                             constexpr int sy = decltype(syc)::value;
-                            const double exy = Fx.e[cx][dx][sx] * Fy.e[cy][dy][sy];
+                            const T exy = Fx.e[cx][dx][sx] * Fy.e[cy][dy][sy];
                             static_for<0, cz + dz + 1>([&](auto szc) {
                                 constexpr int sz = decltype(szc)::value;
-                                constexpr double sg = ((sx + sy + sz) & 1) ? -1.0 : 1.0;
+                                constexpr T sg = ((sx + sy + sz) & 1) ? T(-1) : T(1);
                                 s += sg * exy * Fz.e[cz][dz][sz] * R[herm_idx(tp + sx, up + sy, vp + sz)];
                             });
                         });
@@ -84,12 +107,12 @@ __global__ __launch_bounds__(128) void k_small(KArgs a)
                     constexpr int ia = ab / NB, jb = ab % NB;
                     constexpr int ax = cart_x(LA, ia), ay = cart_y(LA, ia), az = cart_z(LA, ia);
                     constexpr int bx = cart_x(LB, jb), by = cart_y(LB, jb), bz = cart_z(LB, jb);
-                    double v = 0.0;
+                    T v = T(0);
                     static_for<0, ax + bx + 1>([&](auto txc) {
                         constexpr int tx = decltype(txc)::value;
                         static_for<0, ay + by + 1>([&](auto tyc) {
                             constexpr int ty = decltype(tyc)::value;
-                            const double exy = Ex.e[ax][bx][tx] * Ey.e[ay][by][ty];
+                            const T exy = Ex.e[ax][bx][tx] * Ey.e[ay][by][ty];
                             static_for<0, az + bz + 1>([&](auto tzc) {
                                 constexpr int tz = decltype(tzc)::value;
                                 v += exy * Ez.e[az][bz][tz] * Xp[herm_idx(tx, ty, tz)];
@@ -121,7 +144,7 @@ __global__ __launch_bounds__(128) void k_small(KArgs a)
                 constexpr int j = decltype(jc)::value;
                 static_for<0, ND>([&](auto lc) {
                     constexpr int l = decltype(lc)::value;
-                    acc += V[((i * NB + j) * NC + k) * ND + l] * D[(int64_t)(A.c2 + j) * n + B.c2 + l];
+                    acc += (double)V[((i * NB + j) * NC + k) * ND + l] * D[(int64_t)(A.c2 + j) * n + B.c2 + l];
                 });
             });
             unsafeAtomicAdd(&Kc[(int64_t)(A.c1 + i) * n + B.c1 + k], s * acc);
@@ -137,7 +160,7 @@ __global__ __launch_bounds__(128) void k_small(KArgs a)
                 constexpr int j = decltype(jc)::value;
                 static_for<0, NC>([&](auto kc) {
                     constexpr int k = decltype(kc)::value;
-                    acc += V[((i * NB + j) * NC + k) * ND + l] * D[(int64_t)(A.c2 + j) * n + B.c1 + k];
+                    acc += (double)V[((i * NB + j) * NC + k) * ND + l] * D[(int64_t)(A.c2 + j) * n + B.c1 + k];
                 });
             });
             unsafeAtomicAdd(&Kc[(int64_t)(A.c1 + i) * n + B.c2 + l], s * acc);
@@ -153,7 +176,7 @@ __global__ __launch_bounds__(128) void k_small(KArgs a)
                 constexpr int i = decltype(ic)::value;
                 static_for<0, ND>([&](auto lc) {
                     constexpr int l = decltype(lc)::value;
-                    acc += V[((i * NB + j) * NC + k) * ND + l] * D[(int64_t)(A.c1 + i) * n + B.c2 + l];
+                    acc += (double)V[((i * NB + j) * NC + k) * ND + l] * D[(int64_t)(A.c1 + i) * n + B.c2 + l];
                 });
             });
             unsafeAtomicAdd(&Kc[(int64_t)(A.c2 + j) * n + B.c1 + k], s * acc);
@@ -169,7 +192,7 @@ __global__ __launch_bounds__(128) void k_small(KArgs a)
                 constexpr int i = decltype(ic)::value;
                 static_for<0, NC>([&](auto kc) {
                     constexpr int k = decltype(kc)::value;
-                    acc += V[((i * NB + j) * NC + k) * ND + l] * D[(int64_t)(A.c1 + i) * n + B.c1 + k];
+                    acc += (double)V[((i * NB + j) * NC + k) * ND + l] * D[(int64_t)(A.c1 + i) * n + B.c1 + k];
                 });
             });
             unsafeAtomicAdd(&Kc[(int64_t)(A.c2 + j) * n + B.c2 + l], s * acc);
@@ -177,14 +200,17 @@ __global__ __launch_bounds__(128) void k_small(KArgs a)
     });
 }
 
-bool launch_k_small(int la, int lb, int lc, int ld, const KArgs &a, hipStream_t st)
+bool launch_k_small(int la, int lb, int lc, int ld, const KArgs &a, bool fp32, hipStream_t st)
 {
     const int threads = 128;
     const int64_t blocks = (a.nwork + threads - 1) / threads;
     if (a.nwork <= 0) return true;
 #define MD_CASE(A_, B_, C_, D_)                                                        \
     if (la == A_ && lb == B_ && lc == C_ && ld == D_) {                                \
-        hipLaunchKernelGGL((k_small<A_, B_, C_, D_>), dim3((unsigned)blocks), dim3(threads), 0, st, a); \
+        if (fp32)                                                                      \
+            hipLaunchKernelGGL((k_small<A_, B_, C_, D_, float>), dim3((unsigned)blocks), dim3(threads), 0, st, a); \
+        else                                                                           \
+            hipLaunchKernelGGL((k_small<A_, B_, C_, D_, double>), dim3((unsigned)blocks), dim3(threads), 0, st, a); \
         return true;                                                                   \
     }
     MD_K_SMALL_LIST(MD_CASE)

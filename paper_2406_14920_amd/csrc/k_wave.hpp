@@ -10,7 +10,10 @@
 // chunks for the largest classes) and digested into the four exchange blocks
 // of the 8-fold symmetry, which are flushed to the Cartesian accumulator.
 // A workgroup walks a contiguous range of the work list, so the bra search is
-// done once per range.
+// done once per range.  T is the arithmetic type of the primitive integrals
+// (LDS tables and the block); the density tiles, the digestion and the
+// exchange tiles are double precision.  In the mixed mode a quartet is one
+// precision tile.
 #pragma once
 #include "k_pair.hpp"
 #include "kern_args.hpp"
@@ -19,13 +22,13 @@
 
 namespace md {
 
-template <int LA, int LB, int LC, int LD>
+template <int LA, int LB, int LC, int LD, typename T = double>
 struct WaveCfg {
     static constexpr int NA = ncart(LA), NB = ncart(LB), NC = ncart(LC), ND = ncart(LD);
     static constexpr int NAB = NA * NB, NCD = NC * ND, NBLK = NAB * NCD;
     static constexpr int L = LA + LB + LC + LD, LAB = LA + LB, LCD = LC + LD, L1 = L + 1;
     static constexpr int NR0 = L1 * L1 * L1;
-    static constexpr bool STREAM = NBLK > 2048;
+    static constexpr bool STREAM = NBLK * (int)sizeof(T) > 2048 * 8;
     static constexpr int NABCH = (NAB + 63) / 64;
     static constexpr int CDCH = STREAM ? 16 : NCD;
     static constexpr int NCDCH = (NCD + CDCH - 1) / CDCH;
@@ -37,15 +40,15 @@ struct WaveCfg {
 };
 
 // Digest of a sub-block with runtime bounds (streaming mode).
-template <int NA, int NB, int NC, int ND>
-__device__ __forceinline__ void digest_rt(const double *sV, int vstride, int abb, int cdb, int ab0,
+template <int NA, int NB, int NC, int ND, typename T>
+__device__ __forceinline__ void digest_rt(const T *sV, int vstride, int abb, int cdb, int ab0,
                                           int ab1, int cd0, int cd1, const double *sD, double *sK,
                                           int lane)
 {
     const double *D13 = sD, *D14 = sD + NA * NC, *D23 = D14 + NA * ND, *D24 = D23 + NB * NC;
     double *K13 = sK, *K14 = sK + NA * NC, *K23 = K14 + NA * ND, *K24 = K23 + NB * NC;
     constexpr int O1 = NA * NC, O2 = O1 + NA * ND, O3 = O2 + NB * NC, O4 = O3 + NB * ND;
-    auto V = [&](int ab, int cd) { return sV[(cd - cdb) * vstride + (ab - abb)]; };
+    auto V = [&](int ab, int cd) { return (double)sV[(cd - cdb) * vstride + (ab - abb)]; };
     for (int o = lane; o < O4; o += 64) {
         double acc = 0.0;
         if (o < O1) {
@@ -89,8 +92,8 @@ __device__ __forceinline__ void digest_rt(const double *sV, int vstride, int abb
 }
 
 // Digest of a whole block held as sV[cd * NAB + ab]; inner sums unrolled.
-template <int NA, int NB, int NC, int ND>
-__device__ __forceinline__ void digest_full(const double *sV, const double *sD, double *sK, int lane)
+template <int NA, int NB, int NC, int ND, typename T>
+__device__ __forceinline__ void digest_full(const T *sV, const double *sD, double *sK, int lane)
 {
     constexpr int NAB = NA * NB;
     const double *D13 = sD, *D14 = sD + NA * NC, *D23 = D14 + NA * ND, *D24 = D23 + NB * NC;
@@ -100,54 +103,54 @@ __device__ __forceinline__ void digest_full(const double *sV, const double *sD, 
         double acc = 0.0;
         if (o < O1) {  // K_ac[i][k] += sum_{j,l} V[ij][kl] D_bd[j][l]
             const int i = o / NC, k = o % NC;
-            const double *v = sV + k * ND * NAB + i * NB;
+            const T *v = sV + k * ND * NAB + i * NB;
 #pragma unroll
             for (int j = 0; j < NB; ++j)
 #pragma unroll
-                for (int l = 0; l < ND; ++l) acc += v[l * NAB + j] * D24[j * ND + l];
+                for (int l = 0; l < ND; ++l) acc += (double)v[l * NAB + j] * D24[j * ND + l];
             K13[o] += acc;
         } else if (o < O2) {  // K_ad[i][l] += sum_{j,k} V[ij][kl] D_bc[j][k]
             const int r = o - O1, i = r / ND, l = r % ND;
-            const double *v = sV + l * NAB + i * NB;
+            const T *v = sV + l * NAB + i * NB;
 #pragma unroll
             for (int j = 0; j < NB; ++j)
 #pragma unroll
-                for (int k = 0; k < NC; ++k) acc += v[k * ND * NAB + j] * D23[j * NC + k];
+                for (int k = 0; k < NC; ++k) acc += (double)v[k * ND * NAB + j] * D23[j * NC + k];
             K14[r] += acc;
         } else if (o < O3) {  // K_bc[j][k] += sum_{i,l} V[ij][kl] D_ad[i][l]
             const int r = o - O2, j = r / NC, k = r % NC;
-            const double *v = sV + k * ND * NAB + j;
+            const T *v = sV + k * ND * NAB + j;
 #pragma unroll
             for (int i = 0; i < NA; ++i)
 #pragma unroll
-                for (int l = 0; l < ND; ++l) acc += v[l * NAB + i * NB] * D14[i * ND + l];
+                for (int l = 0; l < ND; ++l) acc += (double)v[l * NAB + i * NB] * D14[i * ND + l];
             K23[r] += acc;
         } else {  // K_bd[j][l] += sum_{i,k} V[ij][kl] D_ac[i][k]
             const int r = o - O3, j = r / ND, l = r % ND;
-            const double *v = sV + l * NAB + j;
+            const T *v = sV + l * NAB + j;
 #pragma unroll
             for (int i = 0; i < NA; ++i)
 #pragma unroll
-                for (int k = 0; k < NC; ++k) acc += v[k * ND * NAB + i * NB] * D13[i * NC + k];
+                for (int k = 0; k < NC; ++k) acc += (double)v[k * ND * NAB + i * NB] * D13[i * NC + k];
             K24[r] += acc;
         }
     }
 }
 
-template <int LA, int LB, int LC, int LD>
+template <int LA, int LB, int LC, int LD, typename T>
 __global__ __launch_bounds__(64) void k_wave(KArgs a)
 {
-    using C = WaveCfg<LA, LB, LC, LD>;
+    using C = WaveCfg<LA, LB, LC, LD, T>;
     constexpr int NA = C::NA, NB = C::NB, NC = C::NC, ND = C::ND;
     constexpr int NAB = C::NAB, NCD = C::NCD, L = C::L, L1 = C::L1, LCD = C::LCD;
     constexpr EprodOff<LC, LD> ok{};
 
-    __shared__ double sR0[C::NR0];
-    __shared__ double sF[L + 1];
-    __shared__ double sPow[3 * (L + 1)];
-    __shared__ double sEb[C::SB];
-    __shared__ double sEk[C::SK];
-    __shared__ double sV[C::NV];
+    __shared__ T sR0[C::NR0];
+    __shared__ T sF[L + 1];
+    __shared__ T sPow[3 * (L + 1)];
+    __shared__ T sEb[C::SB];
+    __shared__ T sEk[C::SK];
+    __shared__ T sV[C::NV];
     __shared__ double sD[C::ND_];
     __shared__ double sK[C::ND_];
 
@@ -198,6 +201,10 @@ __global__ __launch_bounds__(64) void k_wave(KArgs a)
             }
             const CPair A = a.bra[ib];
             const CPair B = a.ket[jk];
+            if (a.mode != 0) {  // uniform over the workgroup
+                const bool need = a.Qbra[ib] * a.Qket[jk] * k_dens_bound(a.Pm, a.nsh, A, B) >= a.tau_mix;
+                if (need != (a.mode == 1)) continue;
+            }
 
             // density blocks D_ac, D_ad, D_bc, D_bd and zeroed exchange tiles
             for (int o = lane; o < C::ND_; o += 64) {
@@ -210,44 +217,44 @@ __global__ __launch_bounds__(64) void k_wave(KArgs a)
                 sK[o] = 0.0;
             }
             if constexpr (!C::STREAM)
-                for (int o = lane; o < C::NV; o += 64) sV[o] = 0.0;
+                for (int o = lane; o < C::NV; o += 64) sV[o] = T(0);
             __syncthreads();
 
             const double qk0 = a.pp[B.poff].q;
             for (int ip = 0; ip < A.np; ++ip) {
                 const PrimPair pb = a.pp[A.poff + ip];
                 if (pb.q * qk0 < a.tau_prim) break;
-                const double *eb = a.eprod_bra + (int64_t)(A.poff + ip - a.pbase_bra) * C::SB;
+                const T *eb = pick<T>(a.eprod_bra, a.eprodf_bra) + (int64_t)(A.poff + ip - a.pbase_bra) * C::SB;
                 for (int kp = 0; kp < B.np; ++kp) {
                     const PrimPair pk = a.pp[B.poff + kp];
                     if (pb.q * pk.q < a.tau_prim) break;
                     const QuartetGeo g = quartet_geo(pb, pk);
-                    wave_boys<L>(g, a.boys, sF, lane);
-                    wave_powers<L>(g, sPow, lane);
-                    const double *ek = a.eprod_ket + (int64_t)(B.poff + kp - a.pbase_ket) * C::SK;
+                    wave_boys<L, T>(g, a.boys, sF, lane);
+                    wave_powers<L, T>(g, sPow, lane);
+                    const T *ek = pick<T>(a.eprod_ket, a.eprodf_ket) + (int64_t)(B.poff + kp - a.pbase_ket) * C::SK;
                     for (int o = lane; o < C::SB; o += 64) sEb[o] = eb[o];
                     for (int o = lane; o < C::SK; o += 64) sEk[o] = ek[o];
                     __syncthreads();
-                    wave_r0<L>(sF, sPow, sR0, lane);
+                    wave_r0<L, T>(sF, sPow, sR0, lane);
                     __syncthreads();
 
                     static_for<0, C::NABCH>([&](auto chc) {
                         constexpr int ch = decltype(chc)::value;
                         const int ab = ch * 64 + lane;
-                        double Y[nherm(LCD)];
+                        T Y[nherm(LCD)];
 #pragma unroll
-                        for (int q = 0; q < nherm(LCD); ++q) Y[q] = 0.0;
+                        for (int q = 0; q < nherm(LCD); ++q) Y[q] = T(0);
                         if (own[ch]) {
                             const int mx = own_m[ch][0], my = own_m[ch][1], mz = own_m[ch][2];
-                            const double *e = sEb + own_off[ch];
+                            const T *e = sEb + own_off[ch];
                             for (int tx = 0; tx < mx; ++tx)
                                 for (int ty = 0; ty < my; ++ty) {
-                                    const double *erow = e + (tx * my + ty) * mz;
-                                    const double *Rrow = sR0 + (tx * L1 + ty) * L1;
+                                    const T *erow = e + (tx * my + ty) * mz;
+                                    const T *Rrow = sR0 + (tx * L1 + ty) * L1;
 #pragma unroll 2
                                     for (int tz = 0; tz < mz; ++tz) {
-                                        const double ev = erow[tz];
-                                        const double *Rb = Rrow + tz;
+                                        const T ev = erow[tz];
+                                        const T *Rb = Rrow + tz;
                                         static_for<0, nherm(LCD)>([&](auto qc) {
                                             constexpr int Q = decltype(qc)::value;
                                             constexpr int qo = (herm_t(Q) * L1 + herm_u(Q)) * L1 + herm_v(Q);
@@ -255,6 +262,14 @@ __global__ __launch_bounds__(64) void k_wave(KArgs a)
                                         });
                                     }
                                 }
+                            if constexpr (sizeof(T) == 4) {  // ket factor r^|Q| of the scaled form
+                                T rp[LCD + 1];
+                                powers<LCD>((T)g.r, rp);
+                                static_for<0, nherm(LCD)>([&](auto qc) {
+                                    constexpr int Q = decltype(qc)::value;
+                                    Y[Q] *= rp[herm_t(Q) + herm_u(Q) + herm_v(Q)];
+                                });
+                            }
                         }
                         static_for<0, C::NCDCH>([&](auto kcc) {
                             constexpr int kc = decltype(kcc)::value;
@@ -266,11 +281,11 @@ __global__ __launch_bounds__(64) void k_wave(KArgs a)
                                 constexpr int nsx = cart_x(LC, c) + cart_x(LD, d) + 1;
                                 constexpr int nsy = cart_y(LC, c) + cart_y(LD, d) + 1;
                                 constexpr int nsz = cart_z(LC, c) + cart_z(LD, d) + 1;
-                                double v = 0.0;
+                                T v = T(0);
                                 static_for<0, nsx * nsy * nsz>([&](auto qc) {
                                     constexpr int q = decltype(qc)::value;
                                     constexpr int sx = q / (nsy * nsz), sy = (q / nsz) % nsy, sz = q % nsz;
-                                    constexpr double sg = ((sx + sy + sz) & 1) ? -1.0 : 1.0;
+                                    constexpr T sg = ((sx + sy + sz) & 1) ? T(-1) : T(1);
                                     v += sg * sEk[ok.off[cd] + q] * Y[herm_idx(sx, sy, sz)];
                                 });
                                 if constexpr (C::STREAM) {
@@ -282,7 +297,7 @@ __global__ __launch_bounds__(64) void k_wave(KArgs a)
                             if constexpr (C::STREAM) {
                                 __syncthreads();
                                 const int ab0 = ch * 64, ab1 = (ab0 + 64 < NAB) ? ab0 + 64 : NAB;
-                                digest_rt<NA, NB, NC, ND>(sV, 64, ab0, cd0, ab0, ab1, cd0, cd1, sD, sK, lane);
+                                digest_rt<NA, NB, NC, ND, T>(sV, 64, ab0, cd0, ab0, ab1, cd0, cd1, sD, sK, lane);
                                 __syncthreads();
                             }
                         });
@@ -291,7 +306,7 @@ __global__ __launch_bounds__(64) void k_wave(KArgs a)
                 }
             }
             if constexpr (!C::STREAM) {
-                digest_full<NA, NB, NC, ND>(sV, sD, sK, lane);
+                digest_full<NA, NB, NC, ND, T>(sV, sD, sK, lane);
                 __syncthreads();
             }
             double s = 1.0;
@@ -312,13 +327,16 @@ __global__ __launch_bounds__(64) void k_wave(KArgs a)
 }
 
 template <int LA, int LB, int LC, int LD>
-void launch_k_wave_t(const KArgs &a, hipStream_t st)
+void launch_k_wave_t(const KArgs &a, bool fp32, hipStream_t st)
 {
     using C = WaveCfg<LA, LB, LC, LD>;
     const int64_t ranges = (a.nwork + C::RANGE - 1) / C::RANGE;
     const int64_t blocks = ranges < 32768 ? ranges : 32768;
     if (blocks <= 0) return;
-    hipLaunchKernelGGL((k_wave<LA, LB, LC, LD>), dim3((unsigned)blocks), dim3(64), 0, st, a);
+    if (fp32)
+        hipLaunchKernelGGL((k_wave<LA, LB, LC, LD, float>), dim3((unsigned)blocks), dim3(64), 0, st, a);
+    else
+        hipLaunchKernelGGL((k_wave<LA, LB, LC, LD, double>), dim3((unsigned)blocks), dim3(64), 0, st, a);
 }
 
 }  // namespace md

@@ -26,6 +26,16 @@ struct KArgs {
     int32_t pbase_bra;
     const double *eprod_ket; // Hermite products of class-Y primitive pairs
     int32_t pbase_ket;
+    // mixed precision: single-precision copies of the products, tile mode
+    // (0 all, 1 double-precision tiles, 2 single-precision tiles), threshold,
+    // contracted Q of both classes and the shell-pair density bounds (nsh x nsh)
+    const float *eprodf_bra;
+    const float *eprodf_ket;
+    int32_t mode;
+    double tau_mix;
+    const double *Qbra, *Qket;
+    const double *Pm;
+    int32_t nsh;
 };
 
 // J-engine launch: bra primitive pairs of class X against ket contracted
@@ -45,6 +55,12 @@ struct JArgs {
     double *Jh;              // Hermite J of class-X primitive pairs (nherm(LX) each)
     const double *boys;
     double tau, tau_prim;
+    // mixed precision: single-precision Hermite density, tile mode, threshold
+    // and Q_cd max|D_cd| of every class-Y ket pair
+    const float *Dtf;
+    int32_t mode;
+    double tau_mix;
+    const double *QDket;
 };
 
 // Bra-shared exchange launch: one workgroup per (bra pair, 64-ket chunk).
@@ -64,6 +80,13 @@ struct KPArgs {
     double *Kacc;
     int32_t ld;
     double tau_prim;
+    const float *eprodf_bra;
+    const float *eprodf_ket;
+    int32_t mode;
+    double tau_mix;
+    const double *Qbra, *Qket;
+    const double *Pm;
+    int32_t nsh;
 };
 
 }  // namespace md

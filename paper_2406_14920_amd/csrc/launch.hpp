@@ -14,29 +14,30 @@ struct ShellMap {
     const int32_t *sph_off;
 };
 
-bool launch_k_pair_0(int la, int lb, int lc, int ld, const KPArgs &a, int nchunks, hipStream_t st);
-bool launch_k_pair_1(int la, int lb, int lc, int ld, const KPArgs &a, int nchunks, hipStream_t st);
-bool launch_k_pair_2(int la, int lb, int lc, int ld, const KPArgs &a, int nchunks, hipStream_t st);
-bool launch_k_pair_3(int la, int lb, int lc, int ld, const KPArgs &a, int nchunks, hipStream_t st);
-bool launch_k_pair_4(int la, int lb, int lc, int ld, const KPArgs &a, int nchunks, hipStream_t st);
-bool launch_k_pair_5(int la, int lb, int lc, int ld, const KPArgs &a, int nchunks, hipStream_t st);
-bool launch_k_pair_6(int la, int lb, int lc, int ld, const KPArgs &a, int nchunks, hipStream_t st);
-bool launch_k_pair_7(int la, int lb, int lc, int ld, const KPArgs &a, int nchunks, hipStream_t st);
+bool launch_k_pair_0(int la, int lb, int lc, int ld, const KPArgs &a, int nchunks, bool fp32, hipStream_t st);
+bool launch_k_pair_1(int la, int lb, int lc, int ld, const KPArgs &a, int nchunks, bool fp32, hipStream_t st);
+bool launch_k_pair_2(int la, int lb, int lc, int ld, const KPArgs &a, int nchunks, bool fp32, hipStream_t st);
+bool launch_k_pair_3(int la, int lb, int lc, int ld, const KPArgs &a, int nchunks, bool fp32, hipStream_t st);
+bool launch_k_pair_4(int la, int lb, int lc, int ld, const KPArgs &a, int nchunks, bool fp32, hipStream_t st);
+bool launch_k_pair_5(int la, int lb, int lc, int ld, const KPArgs &a, int nchunks, bool fp32, hipStream_t st);
+bool launch_k_pair_6(int la, int lb, int lc, int ld, const KPArgs &a, int nchunks, bool fp32, hipStream_t st);
+bool launch_k_pair_7(int la, int lb, int lc, int ld, const KPArgs &a, int nchunks, bool fp32, hipStream_t st);
 void launch_eprod(int la, int lb, const PrimPair *pp, int pbase, int n, double *out, hipStream_t st);
+void launch_eprod(int la, int lb, const PrimPair *pp, int pbase, int n, float *out, hipStream_t st);
 int eprod_size(int la, int lb);
-bool launch_k_small(int la, int lb, int lc, int ld, const KArgs &a, hipStream_t st);
-bool launch_k_wave_0(int la, int lb, int lc, int ld, const KArgs &a, hipStream_t st);
-bool launch_k_wave_1(int la, int lb, int lc, int ld, const KArgs &a, hipStream_t st);
-bool launch_k_wave_2(int la, int lb, int lc, int ld, const KArgs &a, hipStream_t st);
-bool launch_k_wave_3(int la, int lb, int lc, int ld, const KArgs &a, hipStream_t st);
-bool launch_k_wave_4(int la, int lb, int lc, int ld, const KArgs &a, hipStream_t st);
-bool launch_k_wave_5(int la, int lb, int lc, int ld, const KArgs &a, hipStream_t st);
+bool launch_k_small(int la, int lb, int lc, int ld, const KArgs &a, bool fp32, hipStream_t st);
+bool launch_k_wave_0(int la, int lb, int lc, int ld, const KArgs &a, bool fp32, hipStream_t st);
+bool launch_k_wave_1(int la, int lb, int lc, int ld, const KArgs &a, bool fp32, hipStream_t st);
+bool launch_k_wave_2(int la, int lb, int lc, int ld, const KArgs &a, bool fp32, hipStream_t st);
+bool launch_k_wave_3(int la, int lb, int lc, int ld, const KArgs &a, bool fp32, hipStream_t st);
+bool launch_k_wave_4(int la, int lb, int lc, int ld, const KArgs &a, bool fp32, hipStream_t st);
+bool launch_k_wave_5(int la, int lb, int lc, int ld, const KArgs &a, bool fp32, hipStream_t st);
 
 void launch_hermite_density(int lc, int ld, const CPair *cp, int ncp, const PrimPair *pp,
-                            const double *D, int ldd, double *Dt, int dt_base, hipStream_t st);
+                            const double *D, int ldd, double *Dt, float *Dtf, int dt_base, hipStream_t st);
 void launch_hermite_to_cart(int la, int lb, const CPair *cp, int ncp, const PrimPair *pp,
                             const double *Jh, int jh_base, double *Jacc, int ld, hipStream_t st);
-bool launch_jeng(int lx, int ly, const JArgs &a, hipStream_t st);
+bool launch_jeng(int lx, int ly, const JArgs &a, bool fp32, hipStream_t st);
 
 void launch_schwarz(int la, int lb, const CPair *cp, int ncp, PrimPair *pp, double *Q,
                     const double *boys, hipStream_t st);
@@ -45,6 +46,16 @@ void launch_p_to_cart(const double *P, int nbf, double *Pc, int nc, const ShellM
 void launch_acc_to_out(const double *Acc, int nc, double *Out, int nbf, const ShellMap &m, int sph,
                        hipStream_t st);
 void launch_fill_zero(double *x, int64_t n, hipStream_t st);
+void launch_density_bounds(const double *Pc, int nc, const int32_t *l, const int32_t *coff, int nsh,
+                           double *Pm, const CPair *cp, const double *Q, int ncp, double *QD, hipStream_t st);
+// primitive quartets (out[0]) and work items (out[1]) of the single-precision
+// share of one mixed-precision launch; kind 0 = lane-per-quartet tiles of 64,
+// 1 = one quartet per tile, 2 = bra-shared chunks
+void launch_k_count_mix(const KArgs &a, int kind, const int2 *chunks, int nchunks, unsigned long long *out,
+                        hipStream_t st);
+// primitive quartets of the single-precision share of a J-engine launch;
+// per_bra = 1 when the tile is a single bra primitive pair
+void launch_j_count_mix(const JArgs &a, int per_bra, unsigned long long *out, hipStream_t st);
 void launch_k_count(const KArgs &a, unsigned long long *out, hipStream_t st);
 void launch_j_count(const JArgs &a, unsigned long long *out, hipStream_t st);
 

@@ -236,6 +236,40 @@ void launch_acc_to_out(const double *Acc, int nc, double *Out, int nbf, const Sh
     hipLaunchKernelGGL(acc_to_out, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, Acc, nc, Out, nbf, m, sph);
 }
 
+// Density bounds of the mixed-precision rule: Pm[s1][s2] = max |P_cart| over
+// the (s1, s2) shell block, one thread per block.
+__global__ void shell_pair_pmax(const double *__restrict__ Pc, int nc, const int32_t *__restrict__ l,
+                                const int32_t *__restrict__ coff, int nsh, double *__restrict__ Pm)
+{
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)nsh * nsh) return;
+    const int s1 = (int)(idx / nsh), s2 = (int)(idx % nsh);
+    const int n1 = ncart(l[s1]), n2 = ncart(l[s2]), o1 = coff[s1], o2 = coff[s2];
+    double m = 0.0;
+    for (int i = 0; i < n1; ++i)
+        for (int j = 0; j < n2; ++j) m = fmax(m, fabs(Pc[(int64_t)(o1 + i) * nc + o2 + j]));
+    Pm[idx] = m;
+}
+
+// QD[k] = Q_k max|D| over the shell block of contracted pair k (J-engine kets).
+__global__ void pair_qd(const CPair *__restrict__ cp, const double *__restrict__ Q, int n,
+                        const double *__restrict__ Pm, int nsh, double *__restrict__ QD)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const CPair c = cp[k];
+    QD[k] = Q[k] * Pm[(int64_t)c.sh1 * nsh + c.sh2];
+}
+
+void launch_density_bounds(const double *Pc, int nc, const int32_t *l, const int32_t *coff, int nsh,
+                           double *Pm, const CPair *cp, const double *Q, int ncp, double *QD, hipStream_t st)
+{
+    const int64_t n = (int64_t)nsh * nsh;
+    hipLaunchKernelGGL(shell_pair_pmax, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, Pc, nc, l, coff, nsh, Pm);
+    if (ncp > 0)
+        hipLaunchKernelGGL(pair_qd, dim3((unsigned)((ncp + 255) / 256)), dim3(256), 0, st, cp, Q, ncp, Pm, nsh, QD);
+}
+
 void launch_fill_zero(double *x, int64_t n, hipStream_t st)
 {
     if (n <= 0) return;

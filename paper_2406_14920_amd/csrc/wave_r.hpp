@@ -27,8 +27,11 @@ __device__ __forceinline__ int herm_idx_rt(int t, int u, int v)
 }
 
 // Geometry of one primitive quartet; the same on every lane.
+// c, w, pref0 and r serve the scaled single-precision form (md_device.hpp):
+// c = sqrt(2p), w = -q/(p+q), pref0 = 2 pi^{5/2}/(pq sqrt(p+q)), r = sqrt(p/q).
 struct QuartetGeo {
     double X, Y, Z, T, alpha, pref;
+    double c, w, pref0, r;
 };
 
 __device__ __forceinline__ QuartetGeo quartet_geo(const PrimPair &pb, const PrimPair &pk)
@@ -41,20 +44,26 @@ __device__ __forceinline__ QuartetGeo quartet_geo(const PrimPair &pb, const Prim
     g.Y = pb.P[1] - pk.P[1];
     g.Z = pb.P[2] - pk.P[2];
     g.T = g.alpha * (g.X * g.X + g.Y * g.Y + g.Z * g.Z);
-    g.pref = kTwoPi52 * pb.K * pk.K / (p * q) * sqrt(rpq);
+    g.pref0 = kTwoPi52 / (p * q) * sqrt(rpq);
+    g.pref = g.pref0 * pb.K * pk.K;
+    g.c = sqrt(2.0 * p);
+    g.w = -q * rpq;
+    g.r = sqrt(p / q);
     return g;
 }
 
-// Phase 1 (no barrier inside): lane m <= L writes sF[m] = pref (-2 alpha)^m F_m.
-template <int L>
+// Phase 1 (no barrier inside): lane m <= L writes sF[m] = pref (-2 alpha)^m F_m
+// (single precision: the scaled G~_m = pref0 w^m F_m).  F_m and the scale are
+// formed in double precision; the product is stored as T.
+template <int L, typename T>
 __device__ __forceinline__ void wave_boys(const QuartetGeo &g, const double *__restrict__ btab,
-                                          double *sF, int lane)
+                                          T *sF, int lane)
 {
     if (lane <= L) {
         double F = boys_one(lane, g.T, btab);
-        double s = g.pref, m2a = -2.0 * g.alpha;
+        double s = sizeof(T) == 4 ? g.pref0 : g.pref, m2a = sizeof(T) == 4 ? g.w : -2.0 * g.alpha;
         for (int m = 0; m < lane; ++m) s *= m2a;
-        sF[lane] = s * F;
+        sF[lane] = (T)(s * F);
     }
 }
 
@@ -138,56 +147,67 @@ __device__ __forceinline__ void etab_lds(double PA, double PB, double o2p, doubl
 //   C_t^a = t! / (a! (t-2a)! 2^a).
 // Every entry is independent, so the lanes of a wave fill the table with one
 // barrier instead of one per recursion level.
+template <typename T>
 struct HermCoef {
-    double c[15][8];
+    T c[15][8];
     constexpr HermCoef() : c()
     {
         for (int t = 0; t < 15; ++t) {
             double v = 1.0;  // a = 0
             for (int a = 0; 2 * a <= t && a < 8; ++a) {
-                c[t][a] = v;
+                c[t][a] = (T)v;
                 v = v * (double)((t - 2 * a) * (t - 2 * a - 1)) / (2.0 * (a + 1));
             }
         }
     }
 };
-__constant__ const HermCoef c_hcoef{};
+__constant__ const HermCoef<double> c_hcoef{};
+__constant__ const HermCoef<float> c_hcoef_f{};
+template <typename T>
+__device__ __forceinline__ const HermCoef<T> &hcoef_table()
+{
+    if constexpr (sizeof(T) == 4) return c_hcoef_f; else return c_hcoef;
+}
 
 // Phase 1 helper: lane 0..L also stores the powers X^k, Y^k, Z^k into sPow
 // (layout [axis][L+1]); call together with wave_boys (before the barrier).
-template <int L>
-__device__ __forceinline__ void wave_powers(const QuartetGeo &g, double *sPow, int lane)
+// (single precision: powers of the scaled c X, c Y, c Z)
+template <int L, typename T>
+__device__ __forceinline__ void wave_powers(const QuartetGeo &g, T *sPow, int lane)
 {
     if (lane <= L) {
         double px = 1.0, py = 1.0, pz = 1.0;
+        const double f = sizeof(T) == 4 ? g.c : 1.0;
+        const double X = f * g.X, Y = f * g.Y, Z = f * g.Z;
         for (int k = 0; k < lane; ++k) {
-            px *= g.X;
-            py *= g.Y;
-            pz *= g.Z;
+            px *= X;
+            py *= Y;
+            pz *= Z;
         }
-        sPow[lane] = px;
-        sPow[(L + 1) + lane] = py;
-        sPow[2 * (L + 1) + lane] = pz;
+        sPow[lane] = (T)px;
+        sPow[(L + 1) + lane] = (T)py;
+        sPow[2 * (L + 1) + lane] = (T)pz;
     }
 }
 
 // Phase 2 (after the barrier that publishes sF and sPow): dense R^0 into sR0.
 // No barrier inside.
-template <int L>
-__device__ __forceinline__ void wave_r0(const double *sF, const double *sPow, double *sR0, int lane)
+template <int L, typename T>
+__device__ __forceinline__ void wave_r0(const T *sF, const T *sPow, T *sR0, int lane)
 {
     constexpr int L1 = L + 1;
+    const HermCoef<T> &hc = hcoef_table<T>();
     for (int k = lane; k < nherm(L); k += 64) {
         const int code = c_herm.tuv[k];
         const int t = code & 0xff, u = (code >> 8) & 0xff, v = code >> 16;
-        double acc = 0.0;
+        T acc = T(0);
         for (int a = 0; 2 * a <= t; ++a) {
-            const double ca = c_hcoef.c[t][a] * sPow[t - 2 * a];
+            const T ca = hc.c[t][a] * sPow[t - 2 * a];
             for (int b = 0; 2 * b <= u; ++b) {
-                const double cab = ca * c_hcoef.c[u][b] * sPow[L1 + u - 2 * b];
+                const T cab = ca * hc.c[u][b] * sPow[L1 + u - 2 * b];
                 const int n0 = t + u + v - a - b;
                 for (int c = 0; 2 * c <= v; ++c)
-                    acc += cab * c_hcoef.c[v][c] * sPow[2 * L1 + v - 2 * c] * sF[n0 - c];
+                    acc += cab * hc.c[v][c] * sPow[2 * L1 + v - 2 * c] * sF[n0 - c];
             }
         }
         sR0[(t * L1 + u) * L1 + v] = acc;
