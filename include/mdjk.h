@@ -138,9 +138,23 @@ int eri_set_precision(eri_ctx *ctx, int32_t precision, double mixed_thresh);
 int build_jk(eri_ctx *ctx, const double *P, double *J, double *K);
 
 /* Nuclear gradient dE/dR of E = 1/2 tr(PJ) - 1/4 tr(PK) at fixed P
- * (SI eqs. si_dE_J, si_dE_K; the density-derivative terms are absent).
- * grad: device [natom*3]; E: device [1] or NULL.  Asynchronous. */
+ * (SI eqs. si_E_J_K, si_dE_J, si_dE_K; the density-derivative terms are
+ * absent), in hartree/bohr, atoms in the order given to eri_setup.
+ * Coulomb part: the J-engine with the bra Hermite order raised by one and the
+ * pair derivative of SI eq. si_pair_derivative (SI eq. si_dj_formula);
+ * exchange part: derivative integrals of every canonical quartet on all four
+ * centres (the fourth by translational invariance).  Same screening as
+ * build_jk; always double precision.  Per-atom sums are formed in a fixed
+ * order, so repeated calls give identical results.
+ * P: device nbf*nbf.  grad: device [natom*3] or NULL; E: device [1] or NULL
+ * (then a double-precision J and K build is done first); not both NULL.
+ * Asynchronous. */
 int jk_grad(eri_ctx *ctx, const double *P, double *grad, double *E);
+
+/* E = 1/2 sum_ij P_ij J_ij - 1/4 sum_ij P_ij K_ij (SI eq. si_E_J_K) from
+ * device P, J, K (nbf*nbf) into device E[1]; fixed-order reduction.
+ * Asynchronous. */
+int eri_energy(eri_ctx *ctx, const double *P, const double *J, const double *K, double *E);
 
 /* Profiling: while on, every kernel launch of later calls is bracketed by HIP
  * events on the launch stream; eri_profile_read synchronises, reports the

@@ -15,7 +15,7 @@ from typing import Optional, Tuple
 
 from . import abi  # noqa: F401  (ctypes only; loads the .so lazily)
 
-__all__ = ["abi", "JK"]
+__all__ = ["abi", "JK", "JKEnergy"]
 
 
 class JK:
@@ -37,6 +37,7 @@ class JK:
         o.stream = int(stream.cuda_stream)
         self.opts = o
         self.natom = len(xyz)
+        self._xyz = [[float(v) for v in r] for r in xyz]
         self.ctx = abi.eri_setup(shells, xyz, o)
         self.nbf = abi.eri_nbf(self.ctx)
 
@@ -58,6 +59,31 @@ class JK:
             abi.build_jk(self.ctx, P, J, K)
         return J, K
 
+    def grad(self, P, energy: bool = False):
+        """dE/dR (natom x 3, hartree/bohr) of E = 1/2 tr(PJ) - 1/4 tr(PK) at
+        fixed P (jk_grad); with energy=True also E (0-dim tensor)."""
+        import torch
+        if P.dtype != torch.float64 or not P.is_cuda or not P.is_contiguous():
+            raise ValueError("P must be a contiguous float64 CUDA tensor")
+        g = torch.empty((self.natom, 3), dtype=torch.float64, device=P.device)
+        E = torch.empty((), dtype=torch.float64, device=P.device) if energy else None
+        with torch.cuda.stream(self.stream):
+            abi.jk_grad(self.ctx, P, g, E)
+        return (g, E) if energy else g
+
+    def energy(self, P, J, K):
+        """E = 1/2 <P,J> - 1/4 <P,K> on the device (eri_energy)."""
+        import torch
+        E = torch.empty((), dtype=torch.float64, device=P.device)
+        with torch.cuda.stream(self.stream):
+            abi.eri_energy(self.ctx, P, J, K, E)
+        return E
+
+    def set_geometry(self, xyz):
+        """Move the atoms (same shells); redoes pair setup (synchronous)."""
+        abi.eri_set_geometry(self.ctx, xyz)
+        self._xyz = [[float(v) for v in r] for r in xyz]
+
     def set_precision(self, precision: str, mixed_thresh: Optional[float] = None):
         abi.eri_set_precision(self.ctx, abi.ERI_MIXED if precision == "mixed" else abi.ERI_FP64,
                               self.opts.mixed_thresh if mixed_thresh is None else mixed_thresh)
@@ -75,3 +101,54 @@ class JK:
             self.close()
         except Exception:
             pass
+
+
+def _jk_energy_class():
+    import torch
+
+    class JKEnergy(torch.autograd.Function):
+        """E(coords, P) = 1/2 tr(PJ) - 1/4 tr(PK) with J, K from build_jk.
+
+        coords: (natom, 3) float64 tensor (bohr); P: (nbf, nbf) float64 CUDA
+        tensor; jk: a JK context for the same shells.  backward returns
+        dE/dcoords from jk_grad (P held fixed, SI eq. si_dE_J / si_dE_K) and
+        dE/dP = J - K/2.
+        """
+
+        @staticmethod
+        def forward(ctx, coords, P, jk):
+            xyz = coords.detach().to("cpu", torch.float64).tolist()
+            if xyz != jk._xyz:
+                jk.set_geometry(xyz)
+            J, K = jk.jk(P)
+            E = jk.energy(P, J, K)
+            ctx.jk = jk
+            ctx.coords_device = coords.device
+            ctx.save_for_backward(P, J, K)
+            return E
+
+        @staticmethod
+        def backward(ctx, gE):
+            P, J, K = ctx.saved_tensors
+            gc = gP = None
+            if ctx.needs_input_grad[0]:
+                gc = (ctx.jk.grad(P) * gE).to(ctx.coords_device)
+            if ctx.needs_input_grad[1]:
+                gP = (J - 0.5 * K) * gE
+            return gc, gP, None
+
+    return JKEnergy
+
+
+class _LazyJKEnergy:
+    """torch.autograd.Function built on first use (importing this package
+    does not import torch)."""
+    _cls = None
+
+    def __getattr__(self, name):
+        if _LazyJKEnergy._cls is None:
+            _LazyJKEnergy._cls = _jk_energy_class()
+        return getattr(_LazyJKEnergy._cls, name)
+
+
+JKEnergy = _LazyJKEnergy()

@@ -57,7 +57,7 @@ class eri_kernel_time(ctypes.Structure):
 
 
 EXPORTS = ["eri_default_opts", "eri_setup", "eri_nbf", "eri_set_geometry", "eri_set_precision",
-           "build_jk", "jk_grad", "eri_set_profiling", "eri_profile_read", "eri_stats", "eri_destroy",
+           "build_jk", "jk_grad", "eri_energy", "eri_set_profiling", "eri_profile_read", "eri_stats", "eri_destroy",
            "eri_last_error"]
 
 _lib = None
@@ -82,6 +82,7 @@ def load(path: str = LIB_PATH):
     L.eri_set_precision.argtypes = [vp, ctypes.c_int32, ctypes.c_double]
     L.build_jk.argtypes = [vp, vp, vp, vp]
     L.jk_grad.argtypes = [vp, vp, vp, vp]
+    L.eri_energy.argtypes = [vp, vp, vp, vp, vp]
     L.eri_stats.argtypes = [vp, ctypes.POINTER(eri_stats_t)]
     L.eri_set_profiling.argtypes = [vp, ctypes.c_int32]
     L.eri_profile_read.argtypes = [vp, ctypes.POINTER(eri_kernel_time), ctypes.c_int32,
@@ -175,6 +176,10 @@ def build_jk(ctx: int, P, J, K) -> None:
 
 def jk_grad(ctx: int, P, grad, E=None) -> None:
     _check(load().jk_grad(ctypes.c_void_p(ctx), _ptr(P), _ptr(grad), _ptr(E)))
+
+
+def eri_energy(ctx: int, P, J, K, E) -> None:
+    _check(load().eri_energy(ctypes.c_void_p(ctx), _ptr(P), _ptr(J), _ptr(K), _ptr(E)))
 
 
 def eri_stats(ctx: int) -> dict:

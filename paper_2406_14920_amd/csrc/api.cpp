@@ -222,6 +222,15 @@ struct eri_ctx {
     mutable std::vector<std::array<int64_t, 2>> kmix;
     mutable int64_t jmix[kPairClasses][kPairClasses][2] = {};
 
+    // gradient: Hermite J of order LX+1, per-pair Coulomb terms, exchange
+    // workgroup partials (allocated on the first jk_grad after each geometry)
+    bool grad_ready = false;
+    size_t jh1_off[kPairClasses] = {};
+    DevBuf<double> d_Jh1, d_pg, d_kpart, d_Jtmp, d_Ktmp;
+    std::vector<int> kg_blocks;   // per exchange launch
+    std::vector<int64_t> kg_off;  // first partial of each launch
+    int64_t kg_total = 0;
+
     // primitive-quartet counts per exchange launch and per J-engine (X, Y)
     std::vector<int64_t> kprim;
     int64_t jprim[kPairClasses][kPairClasses] = {};
@@ -423,6 +432,7 @@ void build_pairs(eri_ctx *c)
     c->mixed_ready = false;
     c->built_mixed = false;
     c->mix_counts_ok = false;
+    c->grad_ready = false;
 
     // 4. exchange work lists
     std::vector<int64_t> prefix;
@@ -882,6 +892,95 @@ void rec_work(const eri_ctx *c, const eri_ctx::Rec &r, int64_t &pq, double &flop
     }
 }
 
+constexpr int kKgRange = 4;      // quartets per range of the exchange-gradient kernel
+constexpr int kKgMaxBlocks = 2048;
+
+void ensure_grad(eri_ctx *c)
+{
+    if (c->grad_ready) return;
+    size_t o = 0;
+    for (int X = 0; X < kPairClasses; ++X) {
+        c->jh1_off[X] = o;
+        o += (size_t)c->npp[X] * nherm(kPairL[X][0] + kPairL[X][1] + 1);
+    }
+    c->d_Jh1.alloc(std::max<size_t>(o, 1));
+    c->d_pg.alloc(std::max<size_t>(6 * c->cp.size(), 1));
+    c->kg_blocks.assign(c->kwork.size(), 0);
+    c->kg_off.assign(c->kwork.size(), 0);
+    c->kg_total = 0;
+    for (size_t wi = 0; wi < c->kwork.size(); ++wi) {
+        const int64_t ranges = (c->kwork[wi].nwork + kKgRange - 1) / kKgRange;
+        c->kg_blocks[wi] = (int)std::min<int64_t>(ranges, kKgMaxBlocks);
+        c->kg_off[wi] = c->kg_total;
+        c->kg_total += c->kg_blocks[wi];
+    }
+    c->d_kpart.alloc(std::max<size_t>((size_t)c->kg_total * 3 * c->natom, 1));
+    c->grad_ready = true;
+}
+
+// dE/dR at fixed P (P_cart already in d_Pc).
+void run_grad(eri_ctx *c, double *grad)
+{
+    hipStream_t st = c->st;
+    const int nc = c->nbf_cart;
+    ensure_grad(c);
+    // Coulomb: Hermite density, J-engine with the bra order raised by one
+    for (int Y = 0; Y < kPairClasses; ++Y)
+        launch_hermite_density(kPairL[Y][0], kPairL[Y][1], c->d_cp.p + c->cp_base[Y], c->ncp[Y], c->d_pp.p,
+                               c->d_Pc.p, nc, c->d_Dt.p + c->dt_off[Y], nullptr, c->pp_base[Y], st);
+    launch_fill_zero(c->d_Jh1.p, (int64_t)c->d_Jh1.n, st);
+    for (int X = 0; X < kPairClasses; ++X) {
+        if (c->npp[X] == 0) continue;
+        for (int Y = 0; Y < kPairClasses; ++Y) {
+            if (c->ncp[Y] == 0) continue;
+            JArgs a = j_args(c, X, Y, false);
+            a.Jh = c->d_Jh1.p + c->jh1_off[X];
+            const int lx = kPairL[X][0] + kPairL[X][1] + 1, ly = kPairL[Y][0] + kPairL[Y][1];
+            timed(c, cls_name("jeng_grad", kPairL[X][0], kPairL[X][1], kPairL[Y][0], kPairL[Y][1]), -1, 0, 0,
+                  [&] {
+                      if (!launch_jeng(lx, ly, a, false, st)) {
+                          set_err(ERI_ESTATE, "no J-engine kernel for orders (%d,%d)", lx, ly);
+                          throw HipError{ERI_ESTATE};
+                      }
+                  });
+        }
+    }
+    for (int X = 0; X < kPairClasses; ++X) {
+        JGArgs g{};
+        g.cp = c->d_cp.p + c->cp_base[X];
+        g.ncp = c->ncp[X];
+        g.pp = c->d_pp.p;
+        g.Jh1 = c->d_Jh1.p + c->jh1_off[X];
+        g.jh_base = c->pp_base[X];
+        g.D = c->d_Pc.p;
+        g.ld = nc;
+        g.pg = c->d_pg.p + 6 * (size_t)c->cp_base[X];
+        timed(c, cls_name("jgrad", kPairL[X][0], kPairL[X][1], 0, 0), -1, 0, 0,
+              [&] { launch_jgrad(kPairL[X][0], kPairL[X][1], g, st); });
+    }
+    // exchange: every canonical quartet, all four centres
+    for (size_t wi = 0; wi < c->kwork.size(); ++wi) {
+        const auto &w = c->kwork[wi];
+        if (w.nwork == 0) continue;
+        KGArgs g{};
+        g.k = k_args(c, w, false);
+        g.partial = c->d_kpart.p + (size_t)c->kg_off[wi] * 3 * c->natom;
+        g.natom = c->natom;
+        const int la = kPairL[w.X][0], lb = kPairL[w.X][1], lc = kPairL[w.Y][0], ld = kPairL[w.Y][1];
+        const int nb = c->kg_blocks[wi];
+        bool ok = false;
+        timed(c, cls_name("kgrad", la, lb, lc, ld), -1, 0, 0, [&] {
+            ok = launch_kg_0(la, lb, lc, ld, g, nb, st) || launch_kg_1(la, lb, lc, ld, g, nb, st) ||
+                 launch_kg_2(la, lb, lc, ld, g, nb, st) || launch_kg_3(la, lb, lc, ld, g, nb, st);
+        });
+        if (!ok) {
+            set_err(ERI_ESTATE, "no exchange-gradient kernel for class (%d%d|%d%d)", la, lb, lc, ld);
+            throw HipError{ERI_ESTATE};
+        }
+    }
+    launch_grad_reduce(c->d_cp.p, (int)c->cp.size(), c->d_pg.p, c->d_kpart.p, c->kg_total, c->natom, grad, st);
+}
+
 }  // namespace
 
 extern "C" {
@@ -1001,8 +1100,48 @@ int build_jk(eri_ctx *ctx, const double *P, double *J, double *K)
 int jk_grad(eri_ctx *ctx, const double *P, double *grad, double *E)
 {
     if (!ctx_ok(ctx)) return set_err(ERI_ESTATE, "invalid context");
-    (void)P; (void)grad; (void)E;
-    return set_err(ERI_ESTATE, "jk_grad is not available in this build");
+    if (!P) return set_err(ERI_EINVAL, "P is NULL");
+    if (!grad && !E) return set_err(ERI_EINVAL, "grad and E are both NULL");
+    try {
+        hipStream_t st = ctx->st;
+        const ShellMap m = shell_map(ctx);
+        if (E) {
+            const size_t n2 = (size_t)ctx->nbf * ctx->nbf;
+            if (ctx->d_Jtmp.n != n2) {
+                ctx->d_Jtmp.alloc(n2);
+                ctx->d_Ktmp.alloc(n2);
+            }
+            const int32_t prec = ctx->opts.precision;
+            ctx->opts.precision = ERI_FP64;
+            const int rc = build_jk(ctx, P, ctx->d_Jtmp.p, ctx->d_Ktmp.p);
+            ctx->opts.precision = prec;
+            if (rc) return rc;
+            launch_energy(P, ctx->d_Jtmp.p, ctx->d_Ktmp.p, (int64_t)n2, E, st);
+        }
+        if (grad) {
+            launch_p_to_cart(P, ctx->nbf, ctx->d_Pc.p, ctx->nbf_cart, m, ctx->opts.spherical, st);
+            run_grad(ctx, grad);
+        }
+        HIPCHK(hipGetLastError());
+    } catch (const HipError &e) {
+        return e.code;
+    } catch (const std::bad_alloc &) {
+        return set_err(ERI_ENOMEM, "host allocation failed");
+    }
+    return ERI_OK;
+}
+
+int eri_energy(eri_ctx *ctx, const double *P, const double *J, const double *K, double *E)
+{
+    if (!ctx_ok(ctx)) return set_err(ERI_ESTATE, "invalid context");
+    if (!P || !J || !K || !E) return set_err(ERI_EINVAL, "null argument");
+    try {
+        launch_energy(P, J, K, (int64_t)ctx->nbf * ctx->nbf, E, ctx->st);
+        HIPCHK(hipGetLastError());
+    } catch (const HipError &e) {
+        return e.code;
+    }
+    return ERI_OK;
 }
 
 int eri_stats(const eri_ctx *ctx, eri_stats_t *out)

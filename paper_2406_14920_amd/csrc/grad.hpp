@@ -1,0 +1,286 @@
+// grad.hpp -- nuclear gradient of E = 1/2 tr(PJ) - 1/4 tr(PK) at fixed P
+// (SI eqs. si_E_J_K, si_dE_J, si_dE_K).
+//
+// Derivative of a primitive pair with respect to its first centre (the
+// content of SI eq. si_pair_derivative, written with the Gaussian identity
+// d/dA_x x_A^i e^{-a x_A^2} = 2a x_A^{i+1} e^{..} - i x_A^{i-1} e^{..}):
+//     d/dA_k (ab) = sum_t Ed^{A,k}_t Lambda_t,
+//     Ed^{A,k} = (2a E^{i_k+1, j_k} - i_k E^{i_k-1, j_k}) along k, E^{ij} along the others,
+// and, because the Hermite Gaussians depend on A and B only through P,
+//     (d/dA_k + d/dB_k)(ab) = sum_t E_t Lambda_{t+1_k}.
+// So a derivative needs the Hermite index one higher than the integral
+// (R up to L+1), and dB = (dA + dB) - dA.
+//
+// Exchange part (eq. si_dE_K over all centres of a canonical quartet,
+// weights of the 8-fold orbit): per canonical quartet
+//     W_{ab,cd} = -s (D_ac D_bd + D_ad D_bc),
+//     g_A = sum W d_A(ab|cd),  g_S = sum W (d_A + d_B)(ab|cd),  g_C = sum W d_C(ab|cd),
+//     g_B = g_S - g_A,  g_D = -g_S - g_C  (translational invariance).
+// One 64-lane workgroup per quartet: per primitive quartet R^0 up to L+1 goes
+// to LDS, the ket-contracted intermediates
+//     X^{cd}_t   = sum_s (-1)^{|s|} E^{cd}_s R_{t+s},          t in H(LAB+1)
+//     Xc^{cd,k}_t = sum_s (-1)^{|s|} Ed^{C,k}_{cd,s} R_{t+s},  t in H(LAB)
+// are built cooperatively for a chunk of ket components, and lane ab
+// contracts them with its bra coefficients and the weights.  Gradient
+// contributions are summed per workgroup in LDS by one lane in work order and
+// written as per-workgroup partials, which a final kernel adds in a fixed
+// order (deterministic).
+#pragma once
+#include "kern_args.hpp"
+#include "md_device.hpp"
+#include "wave_r.hpp"
+
+namespace md {
+
+template <int LA, int LB, int LC, int LD>
+struct KGCfg {
+    static constexpr int NA = ncart(LA), NB = ncart(LB), NC = ncart(LC), ND = ncart(LD);
+    static constexpr int NAB = NA * NB, NCD = NC * ND;
+    static constexpr int L = LA + LB + LC + LD, LAB = LA + LB, LCD = LC + LD;
+    static constexpr int L2 = L + 2;                 // dense R table side (orders up to L+1)
+    static constexpr int NR0 = L2 * L2 * L2;
+    static constexpr int NHX = nherm(LAB + 1), NHC = nherm(LAB);
+    static constexpr int CDCH = NCD < 16 ? NCD : 16;
+    static constexpr int NABCH = (NAB + 63) / 64;
+    // 1D tables [i][j][t]: bra i <= LA+1, j <= LB, t <= LAB+1; ket i <= LC+1, j <= LD, t <= LCD+1
+    static constexpr int EBJ = LAB + 2, EBI = (LB + 1) * EBJ, EBD = (LA + 2) * EBI;
+    static constexpr int EKJ = LCD + 2, EKI = (LD + 1) * EKJ, EKD = (LC + 2) * EKI;
+    static constexpr int ND_ = NA * NC + NA * ND + NB * NC + NB * ND;
+    static constexpr int RANGE = 4;
+};
+
+// Derivative coefficient along one axis: 2a E^{i+1,j}_t - i E^{i-1,j}_t.
+__device__ __forceinline__ double dcoef(const double *E, int DI, int DJ, int i, int j, int t, double a2)
+{
+    double v = a2 * E[(i + 1) * DI + j * DJ + t];
+    if (i > 0) v -= (double)i * E[(i - 1) * DI + j * DJ + t];
+    return v;
+}
+
+template <int LA, int LB, int LC, int LD>
+__global__ __launch_bounds__(64) void kg_wave(KGArgs g)
+{
+    using C = KGCfg<LA, LB, LC, LD>;
+    constexpr int NA = C::NA, NB = C::NB, NC = C::NC, ND = C::ND, NAB = C::NAB, NCD = C::NCD;
+    constexpr int L = C::L, L2 = C::L2, CDCH = C::CDCH, NHX = C::NHX, NHC = C::NHC;
+    const KArgs &a = g.k;
+
+    __shared__ double sR0[C::NR0];
+    __shared__ double sF[L + 2];
+    __shared__ double sPow[3 * (L + 2)];
+    __shared__ double sEb[3 * C::EBD];
+    __shared__ double sEk[3 * C::EKD];
+    __shared__ double sX[CDCH * NHX];
+    __shared__ double sXc[3 * CDCH * NHC];
+    __shared__ double sD[C::ND_];
+    extern __shared__ double sG[];  // natom x 3
+
+    const int lane = threadIdx.x;
+    const int na3 = 3 * g.natom;
+    for (int o = lane; o < na3; o += 64) sG[o] = 0.0;
+    // every entry finite from the start: the chunk loops below run to CDCH
+    // with zero weights past the chunk end
+    for (int o = lane; o < CDCH * NHX; o += 64) sX[o] = 0.0;
+    for (int o = lane; o < 3 * CDCH * NHC; o += 64) sXc[o] = 0.0;
+
+    const int n = a.ld;
+    for (int64_t w0 = (int64_t)blockIdx.x * C::RANGE; w0 < a.nwork; w0 += (int64_t)gridDim.x * C::RANGE) {
+        const int64_t w1 = (w0 + C::RANGE < a.nwork) ? w0 + C::RANGE : a.nwork;
+        int lo = 0, hi = a.nbra;
+        while (hi - lo > 1) {
+            int mid = (lo + hi) >> 1;
+            if (a.prefix[mid] <= w0) lo = mid; else hi = mid;
+        }
+        int ib = lo;
+        int jk = (int)(w0 - a.prefix[ib]);
+        for (int64_t w = w0; w < w1; ++w) {
+            if (w > w0) {
+                ++jk;
+                while (a.prefix[ib] + jk >= a.prefix[ib + 1]) {
+                    ++ib;
+                    jk = 0;
+                }
+            }
+            const CPair A = a.bra[ib];
+            const CPair B = a.ket[jk];
+            double sdeg = 1.0;
+            if (A.sh1 == A.sh2) sdeg *= 0.5;
+            if (B.sh1 == B.sh2) sdeg *= 0.5;
+            if (a.same && ib == jk) sdeg *= 0.5;
+
+            // density tiles D_ac, D_ad, D_bc, D_bd
+            for (int o = lane; o < C::ND_; o += 64) {
+                int row, col;
+                if (o < NA * NC) { row = A.c1 + o / NC; col = B.c1 + o % NC; }
+                else if (o < NA * NC + NA * ND) { int r = o - NA * NC; row = A.c1 + r / ND; col = B.c2 + r % ND; }
+                else if (o < NA * NC + NA * ND + NB * NC) { int r = o - NA * NC - NA * ND; row = A.c2 + r / NC; col = B.c1 + r % NC; }
+                else { int r = o - NA * NC - NA * ND - NB * NC; row = A.c2 + r / ND; col = B.c2 + r % ND; }
+                sD[o] = a.D[(int64_t)row * n + col];
+            }
+            const double *Dac = sD, *Dad = sD + NA * NC, *Dbc = Dad + NA * ND, *Dbd = Dbc + NB * NC;
+
+            double gA[3] = {0.0, 0.0, 0.0}, gS[3] = {0.0, 0.0, 0.0}, gC[3] = {0.0, 0.0, 0.0};
+            const double qk0 = a.pp[B.poff].q;
+            for (int ip = 0; ip < A.np; ++ip) {
+                const PrimPair pb = a.pp[A.poff + ip];
+                if (pb.q * qk0 < a.tau_prim) break;
+                for (int kp = 0; kp < B.np; ++kp) {
+                    const PrimPair pk = a.pp[B.poff + kp];
+                    if (pb.q * pk.q < a.tau_prim) break;
+                    const QuartetGeo geo = quartet_geo(pb, pk);
+                    wave_boys<L + 1>(geo, a.boys, sF, lane);
+                    wave_powers<L + 1>(geo, sPow, lane);
+                    if (lane >= 8 && lane < 11) {
+                        const int k = lane - 8;
+                        const double pa = k == 0 ? pb.PA[0] : (k == 1 ? pb.PA[1] : pb.PA[2]);
+                        const double pbb = k == 0 ? pb.PB[0] : (k == 1 ? pb.PB[1] : pb.PB[2]);
+                        etab_lds<LA + 1, LB>(pa, pbb, pb.o2p, sEb + k * C::EBD);
+                    } else if (lane >= 16 && lane < 19) {
+                        const int k = lane - 16;
+                        const double pa = k == 0 ? pk.PA[0] : (k == 1 ? pk.PA[1] : pk.PA[2]);
+                        const double pbb = k == 0 ? pk.PB[0] : (k == 1 ? pk.PB[1] : pk.PB[2]);
+                        etab_lds<LC + 1, LD>(pa, pbb, pk.o2p, sEk + k * C::EKD);
+                    }
+                    __syncthreads();
+                    wave_r0<L + 1>(sF, sPow, sR0, lane);
+                    __syncthreads();
+                    const double a2 = 2.0 * pb.a, c2 = 2.0 * pk.a;
+
+                    for (int cd0 = 0; cd0 < NCD; cd0 += CDCH) {
+                        const int ncd = (cd0 + CDCH < NCD) ? CDCH : NCD - cd0;
+                        // ket-contracted intermediates of this chunk
+                        for (int o = lane; o < ncd * (NHX + 3 * NHC); o += 64) {
+                            int c, t, kdir;
+                            if (o < ncd * NHX) { c = o / NHX; t = o % NHX; kdir = -1; }
+                            else { const int r = o - ncd * NHX; kdir = r / (ncd * NHC); c = (r / NHC) % ncd; t = r % NHC; }
+                            const int cd = cd0 + c;
+                            int cx, cy, cz, dx, dy, dz;
+                            cart_rt(LC, cd / ND, cx, cy, cz);
+                            cart_rt(LD, cd % ND, dx, dy, dz);
+                            const int code = c_herm.tuv[t];
+                            const int tx = code & 0xff, ty = (code >> 8) & 0xff, tz = code >> 16;
+                            const int mx = cx + dx + 1 + (kdir == 0), my = cy + dy + 1 + (kdir == 1),
+                                      mz = cz + dz + 1 + (kdir == 2);
+                            const double *Ex = sEk, *Ey = sEk + C::EKD, *Ez = sEk + 2 * C::EKD;
+                            double acc = 0.0;
+                            for (int sx = 0; sx < mx; ++sx) {
+                                const double ex = kdir == 0 ? dcoef(Ex, C::EKI, C::EKJ, cx, dx, sx, c2)
+                                                            : Ex[cx * C::EKI + dx * C::EKJ + sx];
+                                for (int sy = 0; sy < my; ++sy) {
+                                    const double ey = kdir == 1 ? dcoef(Ey, C::EKI, C::EKJ, cy, dy, sy, c2)
+                                                                : Ey[cy * C::EKI + dy * C::EKJ + sy];
+                                    const double exy = ex * ey;
+                                    for (int sz = 0; sz < mz; ++sz) {
+                                        const double ez = kdir == 2 ? dcoef(Ez, C::EKI, C::EKJ, cz, dz, sz, c2)
+                                                                    : Ez[cz * C::EKI + dz * C::EKJ + sz];
+                                        const double sg = ((sx + sy + sz) & 1) ? -1.0 : 1.0;
+                                        acc += sg * exy * ez * sR0[((tx + sx) * L2 + ty + sy) * L2 + tz + sz];
+                                    }
+                                }
+                            }
+                            if (kdir < 0) sX[c * NHX + t] = acc;
+                            else sXc[(kdir * CDCH + c) * NHC + t] = acc;
+                        }
+                        __syncthreads();
+
+                        for (int r = 0; r < C::NABCH; ++r) {
+                            const int ab = r * 64 + lane;
+                            if (ab >= NAB) continue;
+                            const int i = ab / NB, j = ab % NB;
+                            int ax, ay, az, bx, by, bz;
+                            cart_rt(LA, i, ax, ay, az);
+                            cart_rt(LB, j, bx, by, bz);
+                            double wv[CDCH];
+#pragma unroll
+                            for (int c = 0; c < CDCH; ++c) {
+                                wv[c] = 0.0;
+                                if (c < ncd) {
+                                    const int kk = (cd0 + c) / ND, ll = (cd0 + c) % ND;
+                                    wv[c] = -sdeg * (Dac[i * NC + kk] * Dbd[j * ND + ll] + Dad[i * ND + ll] * Dbc[j * NC + kk]);
+                                }
+                            }
+                            const double *Ex = sEb, *Ey = sEb + C::EBD, *Ez = sEb + 2 * C::EBD;
+                            const int ex_ = ax + bx, ey_ = ay + by, ez_ = az + bz;
+                            // d/dA: boxes extended by one along the derivative axis
+                            for (int k = 0; k < 3; ++k) {
+                                double s = 0.0;
+                                for (int tx = 0; tx <= ex_ + (k == 0); ++tx) {
+                                    const double fx = k == 0 ? dcoef(Ex, C::EBI, C::EBJ, ax, bx, tx, a2)
+                                                             : Ex[ax * C::EBI + bx * C::EBJ + tx];
+                                    for (int ty = 0; ty <= ey_ + (k == 1); ++ty) {
+                                        const double fy = k == 1 ? dcoef(Ey, C::EBI, C::EBJ, ay, by, ty, a2)
+                                                                 : Ey[ay * C::EBI + by * C::EBJ + ty];
+                                        for (int tz = 0; tz <= ez_ + (k == 2); ++tz) {
+                                            const double fz = k == 2 ? dcoef(Ez, C::EBI, C::EBJ, az, bz, tz, a2)
+                                                                     : Ez[az * C::EBI + bz * C::EBJ + tz];
+                                            const double *xr = sX + herm_idx_rt(tx, ty, tz);
+                                            double acc = 0.0;
+#pragma unroll
+                                            for (int c = 0; c < CDCH; ++c) acc += wv[c] * xr[c * NHX];
+                                            s += fx * fy * fz * acc;
+                                        }
+                                    }
+                                }
+                                gA[k] += s;
+                            }
+                            // (d/dA + d/dB) by the index shift, d/dC from Xc
+                            for (int tx = 0; tx <= ex_; ++tx)
+                                for (int ty = 0; ty <= ey_; ++ty)
+                                    for (int tz = 0; tz <= ez_; ++tz) {
+                                        const double e = Ex[ax * C::EBI + bx * C::EBJ + tx] *
+                                                         Ey[ay * C::EBI + by * C::EBJ + ty] *
+                                                         Ez[az * C::EBI + bz * C::EBJ + tz];
+                                        const int it = herm_idx_rt(tx, ty, tz);
+                                        const int sh[3] = {herm_idx_rt(tx + 1, ty, tz), herm_idx_rt(tx, ty + 1, tz),
+                                                           herm_idx_rt(tx, ty, tz + 1)};
+                                        for (int k = 0; k < 3; ++k) {
+                                            double as = 0.0, ac = 0.0;
+#pragma unroll
+                                            for (int c = 0; c < CDCH; ++c) {
+                                                as += wv[c] * sX[c * NHX + sh[k]];
+                                                ac += wv[c] * sXc[(k * CDCH + c) * NHC + it];
+                                            }
+                                            gS[k] += e * as;
+                                            gC[k] += e * ac;
+                                        }
+                                    }
+                        }
+                        __syncthreads();
+                    }
+                }
+            }
+            // wave sums (fixed butterfly), then one lane adds the four centres in order
+            double v[9] = {gA[0], gA[1], gA[2], gS[0], gS[1], gS[2], gC[0], gC[1], gC[2]};
+#pragma unroll
+            for (int q = 0; q < 9; ++q)
+                for (int off = 32; off > 0; off >>= 1) v[q] += __shfl_xor(v[q], off);
+            if (lane == 0) {
+                for (int k = 0; k < 3; ++k) {
+                    sG[3 * A.at1 + k] += v[k];
+                    sG[3 * A.at2 + k] += v[3 + k] - v[k];
+                    sG[3 * B.at1 + k] += v[6 + k];
+                    sG[3 * B.at2 + k] += -v[3 + k] - v[6 + k];
+                }
+            }
+            __syncthreads();
+        }
+    }
+    __syncthreads();
+    for (int o = lane; o < na3; o += 64) g.partial[(int64_t)blockIdx.x * na3 + o] = sG[o];
+}
+
+template <int LA, int LB, int LC, int LD>
+void launch_kg_t(const KGArgs &g, int blocks, hipStream_t st)
+{
+    if (blocks <= 0) return;
+    const size_t shm = (size_t)3 * g.natom * sizeof(double);
+    hipLaunchKernelGGL((kg_wave<LA, LB, LC, LD>), dim3((unsigned)blocks), dim3(64), shm, st, g);
+}
+
+template <int LA, int LB, int LC, int LD>
+constexpr int kg_ranges_per_block()
+{
+    return KGCfg<LA, LB, LC, LD>::RANGE;
+}
+
+}  // namespace md

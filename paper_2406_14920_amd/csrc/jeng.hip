@@ -392,15 +392,22 @@ void jeng_launch_t(const JArgs &a, hipStream_t st)
     }
 }
 
+// Bra orders up to 7 serve the gradient (the bra order raised by one), which
+// runs in double precision only.
 bool launch_jeng(int lx, int ly, const JArgs &a, bool fp32, hipStream_t st)
 {
     bool done = false;
-    static_for<0, 7>([&](auto xc) {
+    if (fp32 && lx > 6) return false;
+    static_for<0, 8>([&](auto xc) {
         constexpr int X = decltype(xc)::value;
         static_for<0, 7>([&](auto yc) {
             constexpr int Yv = decltype(yc)::value;
             if (!done && lx == X && ly == Yv) {
-                if (fp32) jeng_launch_t<X, Yv, float>(a, st); else jeng_launch_t<X, Yv, double>(a, st);
+                if constexpr (X <= 6) {
+                    if (fp32) jeng_launch_t<X, Yv, float>(a, st); else jeng_launch_t<X, Yv, double>(a, st);
+                } else {
+                    jeng_launch_t<X, Yv, double>(a, st);
+                }
                 done = true;
             }
         });

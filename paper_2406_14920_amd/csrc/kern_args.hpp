@@ -89,4 +89,24 @@ struct KPArgs {
     int32_t nsh;
 };
 
+// Exchange-gradient launch: the exchange work list plus the per-workgroup
+// gradient partials (gridDim.x x natom x 3).
+struct KGArgs {
+    KArgs k;
+    double *partial;
+    int32_t natom;
+};
+
+// Coulomb-gradient contraction over the contracted pairs of one class.
+struct JGArgs {
+    const CPair *cp;
+    int32_t ncp;
+    const PrimPair *pp;
+    const double *Jh1;   // Hermite J of order LX+1 of every class-X primitive pair
+    int32_t jh_base;     // primitive pair index that Jh1[0] belongs to
+    const double *D;     // Cartesian density
+    int32_t ld;
+    double *pg;          // [ncp][6]: dE_J/dA, dE_J/dB of each contracted pair
+};
+
 }  // namespace md

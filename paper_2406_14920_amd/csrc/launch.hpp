@@ -59,4 +59,13 @@ void launch_j_count_mix(const JArgs &a, int per_bra, unsigned long long *out, hi
 void launch_k_count(const KArgs &a, unsigned long long *out, hipStream_t st);
 void launch_j_count(const JArgs &a, unsigned long long *out, hipStream_t st);
 
+bool launch_kg_0(int la, int lb, int lc, int ld, const KGArgs &g, int blocks, hipStream_t st);
+bool launch_kg_1(int la, int lb, int lc, int ld, const KGArgs &g, int blocks, hipStream_t st);
+bool launch_kg_2(int la, int lb, int lc, int ld, const KGArgs &g, int blocks, hipStream_t st);
+bool launch_kg_3(int la, int lb, int lc, int ld, const KGArgs &g, int blocks, hipStream_t st);
+void launch_jgrad(int la, int lb, const JGArgs &g, hipStream_t st);
+void launch_grad_reduce(const CPair *cp, int ncp, const double *pg, const double *kpart, int64_t nkblocks,
+                        int natom, double *grad, hipStream_t st);
+void launch_energy(const double *P, const double *J, const double *K, int64_t n2, double *E, hipStream_t st);
+
 }  // namespace md

@@ -1,0 +1,176 @@
+"""GPU nuclear gradient of E = 1/2 tr(PJ) - 1/4 tr(PK) at fixed P (jk_grad)
+against the CPU oracle, central finite differences of the GPU energy, the
+zero-sum (translational invariance) rule, and the autograd wrapper.
+
+Bar (FP64): max|g - g_oracle| <= 1e-10 max|g_oracle| + 1e-12; |sum_A g_A| <= 1e-9;
+finite differences (h = 1e-4 bohr, no screening so that the quartet set does
+not change with the geometry) agree to 1e-7 absolute, the size of the
+central-difference truncation error h^2 E'''/6 for these systems.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2406_14920_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+RTOL = 1e-10
+
+
+def _torch():
+    import torch
+    assert torch.cuda.is_available(), "GPU test needs a GPU"
+    return torch
+
+
+def _micro():
+    xyz = [[0.0, 0.0, 0.0], [1.2, 0.3, -0.4], [-0.5, 1.1, 0.8]]
+    specs = [(0, 0, 3), (1, 0, 1), (2, 1, 2), (0, 1, 3), (1, 2, 1), (2, 2, 2), (0, 3, 1), (1, 3, 1),
+             (2, 0, 2), (0, 2, 1)]
+    return synth.custom(xyz, specs, seed=5, tau=0.0, exp_range=(0.15, 6.0), name="micro")
+
+
+def _ctx(mol, tau=None, tau_prim=None):
+    from paper_2406_14920_amd import JK
+    return JK.from_molecule(mol, schwarz_thresh=mol.tau_schwarz if tau is None else tau, prim_thresh=tau_prim)
+
+
+def _gpu_grad(mol, tau=None, tau_prim=None):
+    torch = _torch()
+    jk = _ctx(mol, tau, tau_prim)
+    P = torch.tensor(mol.P, dtype=torch.float64, device="cuda")
+    g, E = jk.grad(P, energy=True)
+    torch.cuda.synchronize()
+    out = g.cpu().numpy(), float(E.cpu())
+    jk.close()
+    return out
+
+
+def _check(g, gr, tag):
+    err = np.abs(g - gr).max()
+    scale = np.abs(gr).max()
+    print("  %s: max|dg| = %.3e  max|g| = %.3e  |sum g| = %.2e" % (tag, err, scale, np.abs(g.sum(0)).max()),
+          flush=True)
+    assert err <= RTOL * scale + 1e-12, (tag, err, scale)
+    assert np.abs(g.sum(0)).max() <= 1e-9
+
+
+def test_micro_every_class_vs_oracle():
+    mol = _micro()
+    g, E = _gpu_grad(mol, tau=0.0, tau_prim=0.0)
+    gr = oracle.grad(mol, tau=0.0, tau_prim=0.0)
+    Jr, Kr = oracle.jk(mol, tau=0.0, tau_prim=0.0)
+    Er = oracle.energy(mol, Jr, Kr)
+    print("  E = %.15f  oracle %.15f" % (E, Er), flush=True)
+    assert abs(E - Er) <= RTOL * abs(Er)
+    _check(g, gr, "micro")
+
+
+@pytest.mark.parametrize("seed", [1, 2])
+def test_clusters_default_screening_vs_oracle(seed):
+    mol = synth.small_cluster(3, seed, tau=1e-11, name="c3")
+    g, _ = _gpu_grad(mol)
+    gr = oracle.grad(mol)
+    _check(g, gr, "c3 seed %d" % seed)
+
+
+def test_mol4_vs_oracle():
+    mol = synth.mol4()
+    g, _ = _gpu_grad(mol)
+    gr = oracle.grad(mol)
+    _check(g, gr, "mol4")
+
+
+def test_finite_differences_of_gpu_energy():
+    torch = _torch()
+    mol = _micro()
+    jk = _ctx(mol, tau=0.0, tau_prim=0.0)
+    P = torch.tensor(mol.P, dtype=torch.float64, device="cuda")
+    g = jk.grad(P).cpu().numpy()
+    xyz0 = np.asarray(mol.xyz, dtype=float)
+    h = 1e-4
+    fd = np.zeros_like(g)
+    for A in range(len(xyz0)):
+        for k in range(3):
+            e = []
+            for sgn in (1.0, -1.0):
+                x = xyz0.copy()
+                x[A, k] += sgn * h
+                jk.set_geometry(x)
+                J, K = jk.jk(P)
+                e.append(float(jk.energy(P, J, K).cpu()))
+            fd[A, k] = (e[0] - e[1]) / (2 * h)
+    jk.close()
+    err = np.abs(fd - g).max()
+    print("  FD: max|fd - g| = %.3e  max|g| = %.3e" % (err, np.abs(g).max()), flush=True)
+    assert err <= 1e-7
+
+
+def test_repeat_calls_identical():
+    torch = _torch()
+    mol = synth.small_cluster(3, 3, tau=1e-11, name="c3")
+    jk = _ctx(mol)
+    P = torch.tensor(mol.P, dtype=torch.float64, device="cuda")
+    g1 = jk.grad(P).cpu().numpy()
+    g2 = jk.grad(P).cpu().numpy()
+    jk.close()
+    assert np.array_equal(g1, g2)
+
+
+def test_autograd_function():
+    torch = _torch()
+    from paper_2406_14920_amd import JKEnergy
+    mol = synth.small_cluster(3, 4, tau=1e-11, name="c3")
+    jk = _ctx(mol)
+    coords = torch.tensor(mol.xyz, dtype=torch.float64, requires_grad=True)
+    P = torch.tensor(mol.P, dtype=torch.float64, device="cuda", requires_grad=True)
+    E = JKEnergy.apply(coords, P, jk)
+    E.backward()
+    with torch.no_grad():
+        J, K = jk.jk(P.detach())
+        g = jk.grad(P.detach()).cpu()
+    assert torch.equal(coords.grad, g)  # same jk_grad call, same device-side sums
+    assert torch.allclose(P.grad, J - 0.5 * K, rtol=0, atol=1e-14 * float(J.abs().max()))
+    # E is quadratic in P: a central difference along a symmetric direction is exact up to rounding
+    rng = np.random.default_rng(7)
+    Dl = rng.standard_normal(P.shape)
+    Dl = torch.tensor(0.5 * (Dl + Dl.T), dtype=torch.float64, device="cuda")
+    eps = 1e-3
+    with torch.no_grad():
+        Ep = float(JKEnergy.apply(coords, P + eps * Dl, jk))
+        Em = float(JKEnergy.apply(coords, P - eps * Dl, jk))
+    dd = (Ep - Em) / (2 * eps)
+    an = float((P.grad * Dl).sum())
+    print("  dE/dP . D: fd %.12e  analytic %.12e" % (dd, an), flush=True)
+    assert abs(dd - an) <= 1e-9 * max(1.0, abs(an))
+    jk.close()
+
+
+def test_mol20_zero_sum_and_directional_fd():
+    """20-atom gradient workload at full size (default screening): the zero
+    sum, and a central difference of the GPU energy along a random direction
+    of all coordinates (a quartet crossing the screening threshold changes E
+    by at most about tau max|P|^2, far below the tolerance)."""
+    torch = _torch()
+    mol = synth.mol20()
+    jk = _ctx(mol)
+    P = torch.tensor(mol.P, dtype=torch.float64, device="cuda")
+    g = jk.grad(P).cpu().numpy()
+    print("  mol20 |sum g| = %.2e  max|g| = %.3e" % (np.abs(g.sum(0)).max(), np.abs(g).max()), flush=True)
+    assert np.abs(g.sum(0)).max() <= 1e-9
+    rng = np.random.default_rng(20)
+    d = rng.standard_normal(g.shape)
+    d /= np.linalg.norm(d)
+    xyz0 = np.asarray(mol.xyz, dtype=float)
+    h = 1e-4
+    e = []
+    for sgn in (1.0, -1.0):
+        jk.set_geometry(xyz0 + sgn * h * d)
+        J, K = jk.jk(P)
+        e.append(float(jk.energy(P, J, K).cpu()))
+    jk.close()
+    fd = (e[0] - e[1]) / (2 * h)
+    an = float((g * d).sum())
+    print("  directional: fd %.10e analytic %.10e" % (fd, an), flush=True)
+    assert abs(fd - an) <= 1e-6
