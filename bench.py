@@ -101,6 +101,82 @@ def cpu_baseline(mol, target_s: float = 15.0):
             "sample_seconds": dt}
 
 
+def _time(fn, steps):
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps * 1e3
+
+
+def compare_precision(jk, P, J, K, a, st):
+    """The other precision on the same context: time and max |dJ|, |dK|
+    against the double-precision result."""
+    import torch
+    other = "mixed" if a.precision == "fp64" else "fp64"
+    J0, K0 = J.clone(), K.clone()
+    jk.set_precision(other)
+    for _ in range(max(1, a.warmup)):
+        J1, K1 = jk.jk(P)
+    ms = _time(lambda: jk.jk(P), a.steps)
+    J1, K1 = jk.jk(P)
+    torch.cuda.synchronize()
+    s2 = jk.stats()
+    jk.set_precision(a.precision)
+    dJ = float((J1 - J0).abs().max())
+    dK = float((K1 - K0).abs().max())
+    mixed_st = s2 if other == "mixed" else st
+    print("compare %s: %.1f ms dJ=%.2e dK=%.2e" % (other, ms, dJ, dK), file=sys.stderr, flush=True)
+    return {"precision": other, "ms_per_step": ms, "value": st["eris_sph"] / (ms / 1e3),
+            "max_abs_dJ_vs_fp64": dJ, "max_abs_dK_vs_fp64": dK,
+            "fp32_quartet_fraction": mixed_st["n_quartets_fp32"] / max(1, st["n_quartets"]),
+            "mixed_thresh": 1e-5}
+
+
+def bench_grad(a):
+    """Nuclear gradient of the 20-atom workload (jk_grad, double precision)."""
+    import torch
+    from paper_2406_14920_amd import JK, synth
+    mol = synth.mol20()
+    jk = JK.from_molecule(mol)
+    P = torch.tensor(mol.P, dtype=torch.float64, device="cuda")
+    g = jk.grad(P)
+    ms = _time(lambda: jk.grad(P), max(1, min(a.steps, 3)))
+    g = jk.grad(P).cpu().numpy()
+    jk.close()
+    print("grad mol20: %.1f ms |sum g|=%.1e" % (ms, np.abs(g.sum(0)).max()), file=sys.stderr, flush=True)
+    return {"workload": "mol20: 20 atoms, mol40 shell set, 420 spherical bf, Schwarz 1e-11", "ms": ms,
+            "max_abs_sum_over_atoms": float(np.abs(g.sum(0)).max()), "dtype": "f64"}
+
+
+def bench_batch(a):
+    """64 molecules of 5-30 atoms built from one recorded HIP graph, against
+    the same molecules built one after another."""
+    import torch
+    from paper_2406_14920_amd import JK, Batch, synth
+    mols = synth.batch64()
+    t0 = time.perf_counter()
+    jks = [JK.from_molecule(m) for m in mols]
+    setup_s = time.perf_counter() - t0
+    Ps = [torch.tensor(m.P, dtype=torch.float64, device="cuda") for m in mols]
+    eris = sum(jk.stats()["eris_sph"] for jk in jks)
+    b = Batch(jks)
+    b.jk(Ps)
+    ms_graph = _time(lambda: b.jk(Ps), max(1, a.steps))
+    ms_seq = _time(lambda: [jk.jk(P) for jk, P in zip(jks, Ps)], max(1, min(a.steps, 3)))
+    b.close()
+    for jk in jks:
+        jk.close()
+    print("batch64: graph %.1f ms, one by one %.1f ms (setup %.1fs)" % (ms_graph, ms_seq, setup_s),
+          file=sys.stderr, flush=True)
+    return {"workload": "64 molecules of 5-30 atoms (mol40 shell set), FP64", "molecules": len(mols),
+            "nbf_range": [min(m.nbf for m in mols), max(m.nbf for m in mols)],
+            "ms_per_batch_graph": ms_graph, "ms_per_batch_one_by_one": ms_seq,
+            "eris_per_s_graph": eris / (ms_graph / 1e3), "per_molecule_latency_ms_graph": ms_graph}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -109,6 +185,8 @@ def main():
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--profile-json", default=None, help="write the per-kernel table here")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the other-precision comparison, the 20-atom gradient and the 64-molecule batch")
     a = ap.parse_args()
     if a.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -171,7 +249,12 @@ def main():
     if a.profile_json:
         with open(a.profile_json, "w") as f:
             json.dump({"steps": a.steps, "ms_per_step": ms, "kernels": prof}, f, indent=1)
+    if not a.no_extras:
+        out["compare"] = compare_precision(jk, P, J, K, a, st)
     jk.close()
+    if not a.no_extras:
+        out["grad"] = bench_grad(a)
+        out["batch64"] = bench_batch(a)
     if not a.no_cpu:
         cb = cpu_baseline(mol)
         out["cpu_baseline"] = {k: cb[k] for k in ("value", "unit", "cores", "kind", "sample")}

@@ -169,6 +169,38 @@ int eri_stats(const eri_ctx *ctx, eri_stats_t *out);
 /* Release the context and all its device memory.  NULL is accepted. */
 int eri_destroy(eri_ctx *ctx);
 
+/* Autotuner: times the candidate launch shapes (J-engine ket chunk per class
+ * pair; workgroup cap of each range-walking exchange launch) on this
+ * context's own workload -- device density P, current precision -- best of
+ * reps runs each, and keeps the fastest for later builds.  Replaces the
+ * paper's fixed rule for splitting work between kernels.  Synchronous;
+ * leaves J/K results unchanged except for the order of atomic additions. */
+int eri_autotune(eri_ctx *ctx, const double *P, int32_t reps);
+
+/* The launch shapes in use: kchunk100[10*X + Y] (may be NULL), the first
+ * cap_len exchange caps into kcap (may be NULL; 0 = default), *n_kcap = the
+ * number of exchange launches (may be NULL). */
+int eri_tuning(const eri_ctx *ctx, int32_t *kchunk100, int32_t *kcap, int32_t cap_len, int32_t *n_kcap);
+
+/* Batches of independent molecules (many contexts, uneven sizes).
+ * eri_batch_create: n >= 1 contexts on the current device, each keeping its
+ * own basis, thresholds and precision; stream = hipStream_t the batch runs
+ * on (NULL: a stream owned by the batch).  The contexts stay owned by the
+ * caller and must outlive the batch.
+ * eri_batch_build_jk: P, J, K are host arrays of n device pointers
+ * (nbf_i x nbf_i each, as in build_jk; none NULL).  The first call records
+ * every molecule's build into one HIP graph, each molecule a branch that
+ * may run concurrently with the others; later calls with the same pointers
+ * and unchanged contexts replay that graph (one launch for the whole batch).
+ * New pointers, eri_set_geometry or eri_set_precision on a member cause a
+ * new recording.  Results equal those of build_jk on each context (up to the
+ * order of floating-point atomic additions).  Asynchronous on the batch
+ * stream; profiling is suspended while recording. */
+typedef struct eri_batch eri_batch;
+int eri_batch_create(eri_ctx *const *ctxs, int32_t n, void *stream, eri_batch **out);
+int eri_batch_build_jk(eri_batch *b, const double *const *P, double *const *J, double *const *K);
+int eri_batch_destroy(eri_batch *b);
+
 /* Message of the last error on this thread ("" if none). */
 const char *eri_last_error(void);
 

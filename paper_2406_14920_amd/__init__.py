@@ -15,7 +15,7 @@ from typing import Optional, Tuple
 
 from . import abi  # noqa: F401  (ctypes only; loads the .so lazily)
 
-__all__ = ["abi", "JK", "JKEnergy"]
+__all__ = ["abi", "JK", "JKEnergy", "Batch"]
 
 
 class JK:
@@ -79,6 +79,12 @@ class JK:
             abi.eri_energy(self.ctx, P, J, K, E)
         return E
 
+    def autotune(self, P, reps: int = 2) -> dict:
+        """Pick launch shapes for this workload (eri_autotune); returns them."""
+        with __import__("torch").cuda.stream(self.stream):
+            abi.eri_autotune(self.ctx, P, reps)
+        return abi.eri_tuning(self.ctx)
+
     def set_geometry(self, xyz):
         """Move the atoms (same shells); redoes pair setup (synchronous)."""
         abi.eri_set_geometry(self.ctx, xyz)
@@ -95,6 +101,44 @@ class JK:
         if getattr(self, "ctx", None):
             abi.eri_destroy(self.ctx)
             self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Many JK contexts built together from one recorded HIP graph
+    (eri_batch_*).  Output tensors are allocated once and reused, so repeated
+    calls replay the same graph."""
+
+    def __init__(self, jks, stream=None):
+        import torch
+        self.jks = list(jks)
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        self.handle = abi.eri_batch_create([j.ctx for j in self.jks], int(stream.cuda_stream))
+        self.J = [torch.empty((j.nbf, j.nbf), dtype=torch.float64, device="cuda") for j in self.jks]
+        self.K = [torch.empty((j.nbf, j.nbf), dtype=torch.float64, device="cuda") for j in self.jks]
+
+    def jk(self, Ps):
+        """Ps: one contiguous float64 CUDA tensor per molecule.  Returns the
+        lists (J, K); their tensors are overwritten by the next call."""
+        import torch
+        for j, P in zip(self.jks, Ps):
+            if P.dtype != torch.float64 or not P.is_cuda or not P.is_contiguous() or P.shape != (j.nbf, j.nbf):
+                raise ValueError("each P must be a contiguous float64 CUDA tensor of its molecule's size")
+        with torch.cuda.stream(self.stream):
+            abi.eri_batch_build_jk(self.handle, list(Ps), self.J, self.K)
+        return self.J, self.K
+
+    def close(self):
+        if getattr(self, "handle", None):
+            abi.eri_batch_destroy(self.handle)
+            self.handle = None
 
     def __del__(self):
         try:

@@ -58,7 +58,8 @@ class eri_kernel_time(ctypes.Structure):
 
 EXPORTS = ["eri_default_opts", "eri_setup", "eri_nbf", "eri_set_geometry", "eri_set_precision",
            "build_jk", "jk_grad", "eri_energy", "eri_set_profiling", "eri_profile_read", "eri_stats", "eri_destroy",
-           "eri_last_error"]
+           "eri_last_error", "eri_batch_create", "eri_batch_build_jk", "eri_batch_destroy",
+           "eri_autotune", "eri_tuning"]
 
 _lib = None
 
@@ -88,6 +89,12 @@ def load(path: str = LIB_PATH):
     L.eri_profile_read.argtypes = [vp, ctypes.POINTER(eri_kernel_time), ctypes.c_int32,
                                    ctypes.POINTER(ctypes.c_int32)]
     L.eri_destroy.argtypes = [vp]
+    L.eri_batch_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int32, vp, ctypes.POINTER(vp)]
+    L.eri_batch_build_jk.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp)]
+    L.eri_batch_destroy.argtypes = [vp]
+    L.eri_autotune.argtypes = [vp, vp, ctypes.c_int32]
+    ip = ctypes.POINTER(ctypes.c_int32)
+    L.eri_tuning.argtypes = [vp, ip, ip, ctypes.c_int32, ip]
     L.eri_last_error.restype = ctypes.c_char_p
     for name in EXPORTS:
         if name not in ("eri_default_opts", "eri_last_error"):
@@ -203,6 +210,37 @@ def eri_profile_read(ctx: int) -> list:
 
 def eri_destroy(ctx: int) -> None:
     _check(load().eri_destroy(ctypes.c_void_p(ctx)))
+
+
+def eri_batch_create(ctxs: Sequence[int], stream=None) -> int:
+    arr = (ctypes.c_void_p * len(ctxs))(*[ctypes.c_void_p(c) for c in ctxs])
+    h = ctypes.c_void_p()
+    _check(load().eri_batch_create(arr, len(ctxs), ctypes.c_void_p(_ptr(stream) if stream is not None else None),
+                                   ctypes.byref(h)))
+    return int(h.value)
+
+
+def eri_batch_build_jk(batch: int, P: Sequence, J: Sequence, K: Sequence) -> None:
+    n = len(P)
+    mk = lambda xs: (ctypes.c_void_p * n)(*[ctypes.c_void_p(_ptr(x)) for x in xs])
+    _check(load().eri_batch_build_jk(ctypes.c_void_p(batch), mk(P), mk(J), mk(K)))
+
+
+def eri_batch_destroy(batch: int) -> None:
+    _check(load().eri_batch_destroy(ctypes.c_void_p(batch)))
+
+
+def eri_autotune(ctx: int, P, reps: int = 2) -> None:
+    _check(load().eri_autotune(ctypes.c_void_p(ctx), _ptr(P), int(reps)))
+
+
+def eri_tuning(ctx: int) -> dict:
+    kc = (ctypes.c_int32 * 100)()
+    n = ctypes.c_int32()
+    _check(load().eri_tuning(ctypes.c_void_p(ctx), kc, None, 0, ctypes.byref(n)))
+    caps = (ctypes.c_int32 * max(n.value, 1))()
+    _check(load().eri_tuning(ctypes.c_void_p(ctx), None, caps, n.value, None))
+    return {"kchunk": [kc[i] for i in range(100)], "kcap": [caps[i] for i in range(n.value)]}
 
 
 def eri_last_error() -> str:

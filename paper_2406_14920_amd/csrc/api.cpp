@@ -170,6 +170,7 @@ struct DevBuf {
 
 struct eri_ctx {
     uint32_t magic = 0x4d444a4b;
+    uint64_t gen = 0;  // bumped by every change that invalidates captured graphs
     eri_opts opts{};
     hipStream_t st = nullptr;
     int device = 0;
@@ -247,6 +248,11 @@ struct eri_ctx {
         double ms = 0, flops = 0;
         int64_t pq = 0;
     };
+    // launch-shape parameters (set by eri_autotune): J-engine ket chunk per
+    // (bra class, ket class) and workgroup cap per exchange launch
+    int kchunk[kPairClasses][kPairClasses];
+    std::vector<int> kcap;
+
     bool profile = false;
     std::vector<Rec> pending;
     std::map<std::string, Acc> prof;
@@ -477,6 +483,9 @@ void build_pairs(eri_ctx *c)
         }
     c->d_prefix.upload(prefix);
     c->d_chunks.upload(chunks);
+    for (int X = 0; X < kPairClasses; ++X)
+        for (int Y = 0; Y < kPairClasses; ++Y) c->kchunk[X][Y] = 256;
+    c->kcap.assign(c->kwork.size(), 0);
 
     // Hermite products of every primitive pair (bra/ket data of the bra-shared kernel)
     size_t ep = 0;
@@ -665,7 +674,7 @@ JArgs j_args(const eri_ctx *c, int X, int Y, bool mixed)
     a.ket = c->d_cp.p + c->cp_base[Y];
     a.Qket = c->d_Q.p + c->cp_base[Y];
     a.nket = c->ncp[Y];
-    a.kchunk = 256;
+    a.kchunk = c->kchunk[X][Y];
     a.Dt = c->d_Dt.p + c->dt_off[Y];
     a.dt_base = c->pp_base[Y];
     a.Jh = c->d_Jh.p + c->jh_off[X];
@@ -736,6 +745,7 @@ KArgs k_args(const eri_ctx *c, const eri_ctx::KWork &w, bool mixed)
     a.eprod_ket = c->d_eprod.p + c->eprod_off[w.Y];
     a.pbase_ket = c->pp_base[w.Y];
     a.mode = 0;
+    a.grid_cap = c->kcap[&w - c->kwork.data()];
     if (mixed) {
         a.eprodf_bra = c->d_eprodf.p + c->eprod_off[w.X];
         a.eprodf_ket = c->d_eprodf.p + c->eprod_off[w.Y];
@@ -1045,6 +1055,7 @@ int eri_set_geometry(eri_ctx *ctx, const eri_atom *atoms)
             for (int k = 0; k < 3; ++k) ctx->xyz[3 * i + k] = atoms[i].xyz[k];
         build_pairs(ctx);
         HIPCHK(hipStreamSynchronize(ctx->st));
+        ++ctx->gen;
     } catch (const HipError &e) {
         return e.code;
     } catch (const std::bad_alloc &) {
@@ -1058,6 +1069,7 @@ int eri_set_precision(eri_ctx *ctx, int32_t precision, double mixed_thresh)
     if (!ctx_ok(ctx)) return set_err(ERI_ESTATE, "invalid context");
     if (precision != ERI_FP64 && precision != ERI_MIXED) return set_err(ERI_EINVAL, "unknown precision %d", precision);
     if (!(mixed_thresh >= 0.0)) return set_err(ERI_EINVAL, "negative mixed threshold");
+    if (ctx->opts.precision != precision || ctx->opts.mixed_thresh != mixed_thresh) ++ctx->gen;
     ctx->opts.precision = precision;
     ctx->opts.mixed_thresh = mixed_thresh;
     return ERI_OK;
@@ -1231,5 +1243,282 @@ int eri_destroy(eri_ctx *ctx)
 }
 
 const char *eri_last_error(void) { return g_err.c_str(); }
+
+/* Autotuner: times the candidate launch shapes of every J-engine and
+ * range-walking exchange launch on this context's own workload (density P,
+ * current precision) and keeps the fastest. */
+int eri_autotune(eri_ctx *ctx, const double *P, int32_t reps)
+{
+    if (!ctx_ok(ctx)) return set_err(ERI_ESTATE, "invalid context");
+    if (!P) return set_err(ERI_EINVAL, "P is NULL");
+    if (reps < 1) reps = 1;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    const bool prof = ctx->profile;
+    ctx->profile = false;
+    try {
+        const size_t n2 = (size_t)ctx->nbf * ctx->nbf;
+        if (ctx->d_Jtmp.n != n2) {
+            ctx->d_Jtmp.alloc(n2);
+            ctx->d_Ktmp.alloc(n2);
+        }
+        int rc = build_jk(ctx, P, ctx->d_Jtmp.p, ctx->d_Ktmp.p);  // P_cart, bounds, Hermite density
+        if (rc) {
+            ctx->profile = prof;
+            return rc;
+        }
+        HIPCHK(hipEventCreate(&e0));
+        HIPCHK(hipEventCreate(&e1));
+        hipStream_t st = ctx->st;
+        const bool mixed = ctx->opts.precision == ERI_MIXED;
+        auto time_it = [&](auto &&launch) {
+            float best = 1e30f;
+            for (int r = 0; r < reps; ++r) {
+                HIPCHK(hipEventRecord(e0, st));
+                launch();
+                HIPCHK(hipEventRecord(e1, st));
+                HIPCHK(hipEventSynchronize(e1));
+                float ms = 0.f;
+                HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+                best = std::min(best, ms);
+            }
+            return best;
+        };
+        static const int kChunks[] = {64, 128, 256, 512, 1024};
+        for (int X = 0; X < kPairClasses; ++X)
+            for (int Y = 0; Y < kPairClasses; ++Y) {
+                if (ctx->npp[X] == 0 || ctx->ncp[Y] == 0) continue;
+                const int lx = kPairL[X][0] + kPairL[X][1], ly = kPairL[Y][0] + kPairL[Y][1];
+                float best = 1e30f;
+                int pick = ctx->kchunk[X][Y];
+                for (int kc : kChunks) {
+                    JArgs a = j_args(ctx, X, Y, mixed);
+                    a.kchunk = kc;
+                    const float ms = time_it([&] {
+                        for (int part = mixed ? 1 : 0; part <= (mixed ? 2 : 0); ++part) {
+                            a.mode = part;
+                            launch_jeng(lx, ly, a, part == 2, st);
+                        }
+                    });
+                    if (ms < best) {
+                        best = ms;
+                        pick = kc;
+                    }
+                }
+                ctx->kchunk[X][Y] = pick;
+            }
+        static const int kCaps[] = {1024, 4096, 16384, 32768, 131072};
+        for (size_t wi = 0; wi < ctx->kwork.size(); ++wi) {
+            const auto &w = ctx->kwork[wi];
+            const int la = kPairL[w.X][0], lb = kPairL[w.X][1], lc = kPairL[w.Y][0], ld = kPairL[w.Y][1];
+            if (w.nwork == 0 || w.choff >= 0 || is_k_small(la, lb, lc, ld)) continue;
+            float best = 1e30f;
+            int pick = ctx->kcap[wi];
+            for (int cap : kCaps) {
+                KArgs a = k_args(ctx, w, mixed);
+                a.grid_cap = cap;
+                const float ms = time_it([&] {
+                    for (int part = mixed ? 1 : 0; part <= (mixed ? 2 : 0); ++part) {
+                        a.mode = part;
+                        const bool f32 = part == 2;
+                        (void)(launch_k_wave_0(la, lb, lc, ld, a, f32, st) || launch_k_wave_1(la, lb, lc, ld, a, f32, st) ||
+                               launch_k_wave_2(la, lb, lc, ld, a, f32, st) || launch_k_wave_3(la, lb, lc, ld, a, f32, st) ||
+                               launch_k_wave_4(la, lb, lc, ld, a, f32, st) || launch_k_wave_5(la, lb, lc, ld, a, f32, st));
+                    }
+                });
+                if (ms < best) {
+                    best = ms;
+                    pick = cap;
+                }
+            }
+            ctx->kcap[wi] = pick;
+        }
+        ++ctx->gen;
+    } catch (const HipError &e) {
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        ctx->profile = prof;
+        return e.code;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    ctx->profile = prof;
+    return ERI_OK;
+}
+
+/* Current launch-shape choice (for reports): J-engine ket chunk of (X, Y)
+ * and the exchange workgroup cap of launch wi (0 = default). */
+int eri_tuning(const eri_ctx *ctx, int32_t *kchunk100, int32_t *kcap, int32_t cap_len, int32_t *n_kcap)
+{
+    if (!ctx_ok(ctx)) return set_err(ERI_ESTATE, "invalid context");
+    if (kchunk100)
+        for (int X = 0; X < kPairClasses; ++X)
+            for (int Y = 0; Y < kPairClasses; ++Y) kchunk100[X * kPairClasses + Y] = ctx->kchunk[X][Y];
+    if (n_kcap) *n_kcap = (int32_t)ctx->kcap.size();
+    if (kcap)
+        for (int32_t i = 0; i < cap_len && i < (int32_t)ctx->kcap.size(); ++i) kcap[i] = ctx->kcap[i];
+    return ERI_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Batches: the J/K builds of many contexts recorded once into a HIP graph.
+// Each molecule is a branch forked from the batch stream onto one of a few
+// streams and joined back, so independent molecules overlap on the device
+// and a whole batch costs one graph launch.  The graph is recorded on the
+// first build and again whenever the pointers or a context change.
+// ---------------------------------------------------------------------------
+struct eri_batch {
+    uint32_t magic = 0x4d4a4b42;
+    std::vector<eri_ctx *> ctxs;
+    std::vector<uint64_t> gens;
+    hipStream_t st = nullptr;      // caller's stream (graph launches)
+    bool own_stream = false;
+    std::vector<hipStream_t> lanes;  // branch streams used while recording
+    std::vector<hipEvent_t> evs;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::vector<const double *> P;
+    std::vector<double *> J, K;
+};
+
+namespace {
+
+constexpr int kBatchLanes = 8;
+
+bool batch_ok(const eri_batch *b) { return b && b->magic == 0x4d4a4b42; }
+
+void batch_release_graph(eri_batch *b)
+{
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+}
+
+// Record the batch into a graph (P/J/K pointers fixed in the nodes).
+void batch_record(eri_batch *b)
+{
+    batch_release_graph(b);
+    const size_t n = b->ctxs.size();
+    for (eri_ctx *c : b->ctxs)
+        if (c->opts.precision == ERI_MIXED) ensure_mixed(c);  // allocations stay outside the capture
+    HIPCHK(hipStreamSynchronize(b->st));
+    for (eri_ctx *c : b->ctxs) HIPCHK(hipStreamSynchronize(c->st));
+    std::vector<hipStream_t> saved(n);
+    std::vector<bool> prof(n);
+    HIPCHK(hipStreamBeginCapture(b->st, hipStreamCaptureModeThreadLocal));
+    int rc = ERI_OK;
+    try {
+        HIPCHK(hipEventRecord(b->evs[0], b->st));
+        for (size_t i = 0; i < n; ++i) {
+            eri_ctx *c = b->ctxs[i];
+            hipStream_t s = b->lanes[i % b->lanes.size()];
+            HIPCHK(hipStreamWaitEvent(s, b->evs[0], 0));
+            saved[i] = c->st;
+            prof[i] = c->profile;
+            c->st = s;
+            c->profile = false;
+            rc = build_jk(c, b->P[i], b->J[i], b->K[i]);
+            c->st = saved[i];
+            c->profile = prof[i];
+            if (rc) break;
+        }
+        if (!rc)
+            for (size_t k = 0; k < b->lanes.size() && k < n; ++k) {
+                HIPCHK(hipEventRecord(b->evs[1 + k], b->lanes[k]));
+                HIPCHK(hipStreamWaitEvent(b->st, b->evs[1 + k], 0));
+            }
+    } catch (const HipError &e) {
+        rc = e.code;
+    }
+    hipGraph_t g = nullptr;
+    const hipError_t ec = hipStreamEndCapture(b->st, &g);
+    if (rc) {
+        if (g) (void)hipGraphDestroy(g);
+        throw HipError{rc};
+    }
+    if (ec != hipSuccess) {
+        set_err(ERI_EHIP, "hipStreamEndCapture failed: %s", hipGetErrorString(ec));
+        throw HipError{ERI_EHIP};
+    }
+    b->graph = g;
+    HIPCHK(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+    for (size_t i = 0; i < n; ++i) b->gens[i] = b->ctxs[i]->gen;
+}
+
+}  // namespace
+
+extern "C" {
+
+int eri_batch_create(eri_ctx *const *ctxs, int32_t n, void *stream, eri_batch **out)
+{
+    g_err.clear();
+    if (!out) return set_err(ERI_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!ctxs || n <= 0) return set_err(ERI_EINVAL, "no contexts (n=%d)", n);
+    for (int i = 0; i < n; ++i)
+        if (!ctx_ok(ctxs[i])) return set_err(ERI_ESTATE, "context %d invalid", i);
+    std::unique_ptr<eri_batch> b(new (std::nothrow) eri_batch);
+    if (!b) return set_err(ERI_ENOMEM, "host allocation failed");
+    try {
+        b->ctxs.assign(ctxs, ctxs + n);
+        b->gens.assign(n, ~0ull);
+        if (stream) {
+            b->st = (hipStream_t)stream;
+        } else {
+            HIPCHK(hipStreamCreateWithFlags(&b->st, hipStreamNonBlocking));
+            b->own_stream = true;
+        }
+        b->lanes.resize(std::min(n, kBatchLanes));
+        for (auto &s : b->lanes) HIPCHK(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+        b->evs.resize(1 + b->lanes.size());
+        for (auto &e : b->evs) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    } catch (const HipError &e) {
+        return e.code;
+    }
+    *out = b.release();
+    return ERI_OK;
+}
+
+int eri_batch_build_jk(eri_batch *b, const double *const *P, double *const *J, double *const *K)
+{
+    if (!batch_ok(b)) return set_err(ERI_ESTATE, "invalid batch");
+    if (!P || !J || !K) return set_err(ERI_EINVAL, "null pointer array");
+    const size_t n = b->ctxs.size();
+    bool same = b->exec != nullptr && b->P.size() == n;
+    for (size_t i = 0; i < n; ++i) {
+        if (!ctx_ok(b->ctxs[i])) return set_err(ERI_ESTATE, "context %zu destroyed", i);
+        if (!P[i] || !J[i] || !K[i]) return set_err(ERI_EINVAL, "null P/J/K for molecule %zu", i);
+        if (same && (b->P[i] != P[i] || b->J[i] != J[i] || b->K[i] != K[i] || b->gens[i] != b->ctxs[i]->gen))
+            same = false;
+    }
+    try {
+        if (!same) {
+            b->P.assign(P, P + n);
+            b->J.assign(J, J + n);
+            b->K.assign(K, K + n);
+            batch_record(b);
+        }
+        HIPCHK(hipGraphLaunch(b->exec, b->st));
+    } catch (const HipError &e) {
+        return e.code;
+    }
+    return ERI_OK;
+}
+
+int eri_batch_destroy(eri_batch *b)
+{
+    if (!b) return ERI_OK;
+    if (!batch_ok(b)) return set_err(ERI_ESTATE, "invalid batch");
+    (void)hipStreamSynchronize(b->st);
+    batch_release_graph(b);
+    for (auto &e : b->evs) (void)hipEventDestroy(e);
+    for (auto &s : b->lanes) (void)hipStreamDestroy(s);
+    if (b->own_stream) (void)hipStreamDestroy(b->st);
+    b->magic = 0;
+    delete b;
+    return ERI_OK;
+}
 
 }  // extern "C"

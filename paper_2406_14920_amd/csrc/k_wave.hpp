@@ -331,7 +331,8 @@ void launch_k_wave_t(const KArgs &a, bool fp32, hipStream_t st)
 {
     using C = WaveCfg<LA, LB, LC, LD>;
     const int64_t ranges = (a.nwork + C::RANGE - 1) / C::RANGE;
-    const int64_t blocks = ranges < 32768 ? ranges : 32768;
+    const int64_t cap = a.grid_cap > 0 ? a.grid_cap : 32768;
+    const int64_t blocks = ranges < cap ? ranges : cap;
     if (blocks <= 0) return;
     if (fp32)
         hipLaunchKernelGGL((k_wave<LA, LB, LC, LD, float>), dim3((unsigned)blocks), dim3(64), 0, st, a);

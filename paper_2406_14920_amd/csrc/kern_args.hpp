@@ -36,6 +36,7 @@ struct KArgs {
     const double *Qbra, *Qket;
     const double *Pm;
     int32_t nsh;
+    int32_t grid_cap;        // workgroups of a range-walking launch (0: default)
 };
 
 // J-engine launch: bra primitive pairs of class X against ket contracted

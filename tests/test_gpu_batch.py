@@ -1,0 +1,110 @@
+"""GPU batches (one recorded HIP graph for many molecules) and the launch-shape
+autotuner: every molecule's J and K from a batch replay must equal its own
+build_jk (same kernels; only the order of floating-point atomic additions
+may differ, so the bar is 1e-13 relative), on every replay, with the
+program's own eager work and synchronisations between replays; the
+autotuner must leave results unchanged to the same bar.  The stand-alone
+builds are themselves held to the oracle by the parity tests.
+"""
+import numpy as np
+import pytest
+
+from paper_2406_14920_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+RTOL = 1e-13
+
+
+def _torch():
+    import torch
+    assert torch.cuda.is_available(), "GPU test needs a GPU"
+    return torch
+
+
+def _mols(n):
+    # uneven sizes: the first molecules of the 64-molecule batch workload
+    return synth.batch64()[:n]
+
+
+def _close(X, Xr, tag):
+    err = float((X - Xr).abs().max())
+    scale = float(Xr.abs().max())
+    assert err <= RTOL * scale, (tag, err, scale)
+
+
+def test_batch_replays_match_standalone():
+    torch = _torch()
+    from paper_2406_14920_amd import JK, Batch
+    mols = _mols(6)
+    print("  sizes:", [m.nbf for m in mols], flush=True)
+    jks = [JK.from_molecule(m) for m in mols]
+    Ps = [torch.tensor(m.P, dtype=torch.float64, device="cuda") for m in mols]
+    ref = [jk.jk(P) for jk, P in zip(jks, Ps)]
+    torch.cuda.synchronize()
+    b = Batch(jks)
+    for rep in range(3):
+        J, K = b.jk(Ps)
+        torch.cuda.synchronize()
+        for i in range(len(mols)):
+            _close(J[i], ref[i][0], "J rep %d mol %d" % (rep, i))
+            _close(K[i], ref[i][1], "K rep %d mol %d" % (rep, i))
+        # eager work of the program between replays
+        junk = torch.randn(512, 512, device="cuda", dtype=torch.float64)
+        (junk @ junk).sum().item()
+        for t in J + K:
+            t.zero_()
+        torch.cuda.synchronize()
+    b.close()
+    for jk in jks:
+        jk.close()
+
+
+def test_batch_rerecords_on_change():
+    torch = _torch()
+    from paper_2406_14920_amd import JK, Batch
+    mols = _mols(3)
+    jks = [JK.from_molecule(m) for m in mols]
+    jks[1].set_precision("mixed")
+    Ps = [torch.tensor(m.P, dtype=torch.float64, device="cuda") for m in mols]
+    b = Batch(jks)
+    J, K = b.jk(Ps)
+    torch.cuda.synchronize()
+    for i, (jk, P) in enumerate(zip(jks, Ps)):
+        Jr, Kr = jk.jk(P)
+        torch.cuda.synchronize()
+        _close(J[i], Jr, "J mixed member %d" % i)
+        _close(K[i], Kr, "K mixed member %d" % i)
+    # new density tensors (new pointers) and a moved molecule
+    Ps2 = [(P * 0.5).contiguous() for P in Ps]
+    xyz = np.asarray(mols[2].xyz) + np.array([0.0, 0.1, -0.05])
+    jks[2].set_geometry(xyz)
+    J, K = b.jk(Ps2)
+    torch.cuda.synchronize()
+    for i, (jk, P) in enumerate(zip(jks, Ps2)):
+        Jr, Kr = jk.jk(P)
+        torch.cuda.synchronize()
+        _close(J[i], Jr, "J after change %d" % i)
+        _close(K[i], Kr, "K after change %d" % i)
+    b.close()
+    for jk in jks:
+        jk.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_autotune_keeps_results(precision):
+    torch = _torch()
+    from paper_2406_14920_amd import JK
+    mol = synth.small_cluster(5, 11, tau=1e-11, name="c5")
+    jk = JK.from_molecule(mol, precision=precision)
+    P = torch.tensor(mol.P, dtype=torch.float64, device="cuda")
+    J0, K0 = jk.jk(P)
+    J0, K0 = J0.clone(), K0.clone()
+    tun = jk.autotune(P, reps=1)
+    assert set(tun["kchunk"]) <= {64, 128, 256, 512, 1024}
+    assert set(tun["kcap"]) <= {0, 1024, 4096, 16384, 32768, 131072}
+    J1, K1 = jk.jk(P)
+    torch.cuda.synchronize()
+    _close(J1, J0, "J after autotune")
+    _close(K1, K0, "K after autotune")
+    jk.close()
