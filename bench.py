@@ -185,6 +185,8 @@ def main():
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--profile-json", default=None, help="write the per-kernel table here")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
+                    help="only run a device-to-device copy of BYTES bytes five times (counter calibration) and exit")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the other-precision comparison, the 20-atom gradient and the 64-molecule batch")
     a = ap.parse_args()
@@ -194,6 +196,16 @@ def main():
         sys.exit(2)
 
     import torch
+    if a.copy_probe:
+        # a plain copy of known size: its FETCH_SIZE / WRITE_SIZE readings
+        # calibrate the HBM-traffic counters of the J/K kernels
+        src = torch.ones(a.copy_probe // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": a.copy_probe}), flush=True)
+        return
     from paper_2406_14920_amd import JK, abi, synth
 
     mol = synth.mol40()

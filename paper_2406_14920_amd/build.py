@@ -41,14 +41,37 @@ def _compile(src: str) -> str:
     return "%s %.1fs" % (src, time.time() - t)
 
 
-def build(jobs: int | None = None, verbose: bool = True) -> str:
+def _deps(path: str, seen: set) -> set:
+    """The file and every quoted #include it reaches."""
+    if path in seen or not os.path.exists(path):
+        return seen
+    seen.add(path)
+    for line in open(path):
+        line = line.strip()
+        if line.startswith("#include \""):
+            inc = line.split('"')[1]
+            _deps(os.path.normpath(os.path.join(os.path.dirname(path), inc)), seen)
+    return seen
+
+
+def _stale(src: str) -> bool:
+    """Object older than its source or one of the headers it includes."""
+    obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
+    if not os.path.exists(obj):
+        return True
+    t = os.path.getmtime(obj)
+    return any(os.path.getmtime(d) > t for d in _deps(os.path.join(CSRC, src), set()))
+
+
+def build(jobs: int | None = None, verbose: bool = True, changed_only: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
     if shutil.which(HIPCC) is None and not os.path.exists(HIPCC):
         raise RuntimeError("hipcc not found at %s" % HIPCC)
     jobs = jobs or min(16, os.cpu_count() or 4)
     t0 = time.time()
+    todo = [s for s in SOURCES if _stale(s)] if changed_only else SOURCES
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
-        for msg in ex.map(_compile, SOURCES):
+        for msg in ex.map(_compile, todo):
             if verbose:
                 print("  built", msg, flush=True)
     objs = [os.path.join(BUILD, os.path.splitext(s)[0] + ".o") for s in SOURCES]
@@ -66,9 +89,11 @@ def build(jobs: int | None = None, verbose: bool = True) -> str:
 if __name__ == "__main__":
     ap = argparse.ArgumentParser()
     ap.add_argument("--jobs", type=int, default=None)
+    ap.add_argument("--changed", action="store_true",
+                    help="recompile only objects older than their source or a header")
     a = ap.parse_args()
     try:
-        build(a.jobs)
+        build(a.jobs, changed_only=a.changed)
     except RuntimeError as e:
         print(e, file=sys.stderr)
         sys.exit(1)

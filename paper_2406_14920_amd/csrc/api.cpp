@@ -255,6 +255,10 @@ struct eri_ctx {
 
     bool profile = false;
     std::vector<Rec> pending;
+    // streams the J work and the bra-shared / small exchange launches fork
+    // onto, joined back into the context stream by events
+    hipStream_t aux[2] = {nullptr, nullptr};
+    hipEvent_t ev_fork = nullptr, ev_kzero = nullptr, ev_join[2] = {nullptr, nullptr};
     std::map<std::string, Acc> prof;
 
     // stats
@@ -641,7 +645,7 @@ ShellMap shell_map(const eri_ctx *c)
 bool ctx_ok(const eri_ctx *c) { return c && c->magic == 0x4d444a4b; }
 
 template <typename F>
-void timed(eri_ctx *c, const std::string &name, int work, int idx, int part, F &&launch)
+void timed(eri_ctx *c, hipStream_t st, const std::string &name, int work, int idx, int part, F &&launch)
 {
     if (!c->profile) {
         launch();
@@ -650,9 +654,9 @@ void timed(eri_ctx *c, const std::string &name, int work, int idx, int part, F &
     eri_ctx::Rec r{name, nullptr, nullptr, work, idx, part};
     HIPCHK(hipEventCreate(&r.a));
     HIPCHK(hipEventCreate(&r.b));
-    HIPCHK(hipEventRecord(r.a, c->st));
+    HIPCHK(hipEventRecord(r.a, st));
     launch();
-    HIPCHK(hipEventRecord(r.b, c->st));
+    HIPCHK(hipEventRecord(r.b, st));
     c->pending.push_back(r);
 }
 
@@ -692,17 +696,16 @@ JArgs j_args(const eri_ctx *c, int X, int Y, bool mixed)
 
 bool jeng_is_reg(int lx, int ly) { return lx + ly >= 6 && nherm(lx) + nherm(ly) + 4 * (lx + ly + 1) <= 116; }
 
-void run_j(eri_ctx *c, bool mixed)
+void run_j(eri_ctx *c, bool mixed, hipStream_t st)
 {
-    hipStream_t st = c->st;
     const int nc = c->nbf_cart;
     for (int Y = 0; Y < kPairClasses; ++Y)
-        timed(c, cls_name("hdens", kPairL[Y][0], kPairL[Y][1], 0, 0), -1, 0, 0, [&] {
+        timed(c, st, cls_name("hdens", kPairL[Y][0], kPairL[Y][1], 0, 0), -1, 0, 0, [&] {
             launch_hermite_density(kPairL[Y][0], kPairL[Y][1], c->d_cp.p + c->cp_base[Y], c->ncp[Y], c->d_pp.p,
                                    c->d_Pc.p, nc, c->d_Dt.p + c->dt_off[Y],
                                    mixed ? c->d_Dtf.p + c->dt_off[Y] : nullptr, c->pp_base[Y], st);
         });
-    timed(c, "fill_zero", -1, 0, 0, [&] { launch_fill_zero(c->d_Jh.p, (int64_t)c->d_Jh.n, st); });
+    timed(c, st, "fill_zero", -1, 0, 0, [&] { launch_fill_zero(c->d_Jh.p, (int64_t)c->d_Jh.n, st); });
     for (int X = 0; X < kPairClasses; ++X) {
         if (c->npp[X] == 0) continue;
         for (int Y = 0; Y < kPairClasses; ++Y) {
@@ -713,13 +716,13 @@ void run_j(eri_ctx *c, bool mixed)
             JArgs a = j_args(c, X, Y, mixed);
             for (int part = mixed ? 1 : 0; part <= (mixed ? 2 : 0); ++part) {
                 a.mode = part;
-                timed(c, part == 0 ? nm : nm + (part == 1 ? "/d" : "/s"), 1, X * kPairClasses + Y, part,
+                timed(c, st, part == 0 ? nm : nm + (part == 1 ? "/d" : "/s"), 1, X * kPairClasses + Y, part,
                       [&] { launch_jeng(lx, ly, a, part == 2, st); });
             }
         }
     }
     for (int X = 0; X < kPairClasses; ++X)
-        timed(c, cls_name("herm2cart", kPairL[X][0], kPairL[X][1], 0, 0), -1, 0, 0, [&] {
+        timed(c, st, cls_name("herm2cart", kPairL[X][0], kPairL[X][1], 0, 0), -1, 0, 0, [&] {
             launch_hermite_to_cart(kPairL[X][0], kPairL[X][1], c->d_cp.p + c->cp_base[X], c->ncp[X], c->d_pp.p,
                                    c->d_Jh.p + c->jh_off[X], c->pp_base[X], c->d_Jacc.p, nc, st);
         });
@@ -795,9 +798,9 @@ bool is_k_small(int la, int lb, int lc, int ld)
     return false;
 }
 
-void run_k(eri_ctx *c, bool mixed)
+// Range-walking wave classes on stA, bra-shared and small classes on stB.
+void run_k(eri_ctx *c, bool mixed, hipStream_t stA, hipStream_t stB)
 {
-    hipStream_t st = c->st;
     for (const auto &w : c->kwork) {
         if (w.nwork == 0) continue;
         const int la = kPairL[w.X][0], lb = kPairL[w.X][1], lc = kPairL[w.Y][0], ld = kPairL[w.Y][1];
@@ -811,14 +814,16 @@ void run_k(eri_ctx *c, bool mixed)
             if (w.choff >= 0) {
                 const KPArgs p = kp_args(a, c->d_chunks.p + w.choff);
                 const int nch = w.nchunks;
-                timed(c, cls_name("kp", la, lb, lc, ld) + sfx, 0, wi, part, [&] {
+                hipStream_t st = stB;
+                timed(c, st, cls_name("kp", la, lb, lc, ld) + sfx, 0, wi, part, [&] {
                     ok = launch_k_pair_0(la, lb, lc, ld, p, nch, f32, st) || launch_k_pair_1(la, lb, lc, ld, p, nch, f32, st) ||
                          launch_k_pair_2(la, lb, lc, ld, p, nch, f32, st) || launch_k_pair_3(la, lb, lc, ld, p, nch, f32, st) ||
                          launch_k_pair_4(la, lb, lc, ld, p, nch, f32, st) || launch_k_pair_5(la, lb, lc, ld, p, nch, f32, st) ||
                          launch_k_pair_6(la, lb, lc, ld, p, nch, f32, st) || launch_k_pair_7(la, lb, lc, ld, p, nch, f32, st);
                 });
             } else {
-                timed(c, cls_name("k", la, lb, lc, ld) + sfx, 0, wi, part, [&] {
+                hipStream_t st = is_k_small(la, lb, lc, ld) ? stB : stA;
+                timed(c, st, cls_name("k", la, lb, lc, ld) + sfx, 0, wi, part, [&] {
                     ok = launch_k_small(la, lb, lc, ld, a, f32, st) || launch_k_wave_0(la, lb, lc, ld, a, f32, st) ||
                          launch_k_wave_1(la, lb, lc, ld, a, f32, st) || launch_k_wave_2(la, lb, lc, ld, a, f32, st) ||
                          launch_k_wave_3(la, lb, lc, ld, a, f32, st) || launch_k_wave_4(la, lb, lc, ld, a, f32, st) ||
@@ -946,7 +951,7 @@ void run_grad(eri_ctx *c, double *grad)
             JArgs a = j_args(c, X, Y, false);
             a.Jh = c->d_Jh1.p + c->jh1_off[X];
             const int lx = kPairL[X][0] + kPairL[X][1] + 1, ly = kPairL[Y][0] + kPairL[Y][1];
-            timed(c, cls_name("jeng_grad", kPairL[X][0], kPairL[X][1], kPairL[Y][0], kPairL[Y][1]), -1, 0, 0,
+            timed(c, st, cls_name("jeng_grad", kPairL[X][0], kPairL[X][1], kPairL[Y][0], kPairL[Y][1]), -1, 0, 0,
                   [&] {
                       if (!launch_jeng(lx, ly, a, false, st)) {
                           set_err(ERI_ESTATE, "no J-engine kernel for orders (%d,%d)", lx, ly);
@@ -965,7 +970,7 @@ void run_grad(eri_ctx *c, double *grad)
         g.D = c->d_Pc.p;
         g.ld = nc;
         g.pg = c->d_pg.p + 6 * (size_t)c->cp_base[X];
-        timed(c, cls_name("jgrad", kPairL[X][0], kPairL[X][1], 0, 0), -1, 0, 0,
+        timed(c, st, cls_name("jgrad", kPairL[X][0], kPairL[X][1], 0, 0), -1, 0, 0,
               [&] { launch_jgrad(kPairL[X][0], kPairL[X][1], g, st); });
     }
     // exchange: every canonical quartet, all four centres
@@ -979,7 +984,7 @@ void run_grad(eri_ctx *c, double *grad)
         const int la = kPairL[w.X][0], lb = kPairL[w.X][1], lc = kPairL[w.Y][0], ld = kPairL[w.Y][1];
         const int nb = c->kg_blocks[wi];
         bool ok = false;
-        timed(c, cls_name("kgrad", la, lb, lc, ld), -1, 0, 0, [&] {
+        timed(c, st, cls_name("kgrad", la, lb, lc, ld), -1, 0, 0, [&] {
             ok = launch_kg_0(la, lb, lc, ld, g, nb, st) || launch_kg_1(la, lb, lc, ld, g, nb, st) ||
                  launch_kg_2(la, lb, lc, ld, g, nb, st) || launch_kg_3(la, lb, lc, ld, g, nb, st);
         });
@@ -1022,6 +1027,10 @@ int eri_setup(const eri_shell *shells, int32_t nshell, const eri_atom *atoms, in
     c->natom = natom;
     try {
         HIPCHK(hipGetDevice(&c->device));
+        for (auto &x : c->aux) HIPCHK(hipStreamCreateWithFlags(&x, hipStreamNonBlocking));
+        HIPCHK(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
+        HIPCHK(hipEventCreateWithFlags(&c->ev_kzero, hipEventDisableTiming));
+        for (auto &e : c->ev_join) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
         c->d_boys.upload(boys_table());
         build_basis(c.get(), shells, atoms);
         build_pairs(c.get());
@@ -1092,16 +1101,28 @@ int build_jk(eri_ctx *ctx, const double *P, double *J, double *K)
         }
         ctx->built_mixed = mixed;
         ctx->mix_counts_ok = false;
+        // J on its own stream, K split over the context stream and a second
+        // one; all accumulate with atomics, so the three run concurrently
+        HIPCHK(hipEventRecord(ctx->ev_fork, st));
         if (J) {
-            launch_fill_zero(ctx->d_Jacc.p, (int64_t)nc * nc, st);
-            run_j(ctx, mixed);
-            launch_acc_to_out(ctx->d_Jacc.p, nc, J, ctx->nbf, m, ctx->opts.spherical, st);
+            hipStream_t sJ = ctx->aux[0];
+            HIPCHK(hipStreamWaitEvent(sJ, ctx->ev_fork, 0));
+            launch_fill_zero(ctx->d_Jacc.p, (int64_t)nc * nc, sJ);
+            run_j(ctx, mixed, sJ);
+            launch_acc_to_out(ctx->d_Jacc.p, nc, J, ctx->nbf, m, ctx->opts.spherical, sJ);
+            HIPCHK(hipEventRecord(ctx->ev_join[0], sJ));
         }
         if (K) {
+            hipStream_t sK = ctx->aux[1];
             launch_fill_zero(ctx->d_Kacc.p, (int64_t)nc * nc, st);
-            run_k(ctx, mixed);
+            HIPCHK(hipEventRecord(ctx->ev_kzero, st));
+            HIPCHK(hipStreamWaitEvent(sK, ctx->ev_kzero, 0));
+            run_k(ctx, mixed, st, sK);
+            HIPCHK(hipEventRecord(ctx->ev_join[1], sK));
+            HIPCHK(hipStreamWaitEvent(st, ctx->ev_join[1], 0));
             launch_acc_to_out(ctx->d_Kacc.p, nc, K, ctx->nbf, m, ctx->opts.spherical, st);
         }
+        if (J) HIPCHK(hipStreamWaitEvent(st, ctx->ev_join[0], 0));
         HIPCHK(hipGetLastError());
     } catch (const HipError &e) {
         return e.code;
@@ -1197,6 +1218,7 @@ int eri_profile_read(eri_ctx *ctx, eri_kernel_time *out, int32_t cap, int32_t *n
     if (!n || (cap > 0 && !out)) return set_err(ERI_EINVAL, "null output");
     try {
         HIPCHK(hipStreamSynchronize(ctx->st));
+        for (auto &x : ctx->aux) HIPCHK(hipStreamSynchronize(x));
         for (auto &r : ctx->pending) {
             float ms = 0.f;
             HIPCHK(hipEventElapsedTime(&ms, r.a, r.b));
@@ -1233,6 +1255,13 @@ int eri_destroy(eri_ctx *ctx)
     if (!ctx) return ERI_OK;
     if (!ctx_ok(ctx)) return set_err(ERI_ESTATE, "invalid context");
     if (ctx->st) (void)hipStreamSynchronize(ctx->st); else (void)hipDeviceSynchronize();
+    for (auto &x : ctx->aux)
+        if (x) {
+            (void)hipStreamSynchronize(x);
+            (void)hipStreamDestroy(x);
+        }
+    for (hipEvent_t e : {ctx->ev_fork, ctx->ev_kzero, ctx->ev_join[0], ctx->ev_join[1]})
+        if (e) (void)hipEventDestroy(e);
     for (auto &r : ctx->pending) {
         (void)hipEventDestroy(r.a);
         (void)hipEventDestroy(r.b);
@@ -1404,7 +1433,10 @@ void batch_record(eri_batch *b)
     for (eri_ctx *c : b->ctxs)
         if (c->opts.precision == ERI_MIXED) ensure_mixed(c);  // allocations stay outside the capture
     HIPCHK(hipStreamSynchronize(b->st));
-    for (eri_ctx *c : b->ctxs) HIPCHK(hipStreamSynchronize(c->st));
+    for (eri_ctx *c : b->ctxs) {
+        HIPCHK(hipStreamSynchronize(c->st));
+        for (auto &x : c->aux) HIPCHK(hipStreamSynchronize(x));
+    }
     std::vector<hipStream_t> saved(n);
     std::vector<bool> prof(n);
     HIPCHK(hipStreamBeginCapture(b->st, hipStreamCaptureModeThreadLocal));

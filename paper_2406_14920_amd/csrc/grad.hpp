@@ -67,7 +67,8 @@ __global__ __launch_bounds__(64) void kg_wave(KGArgs g)
 
     __shared__ double sR0[C::NR0];
     __shared__ double sF[L + 2];
-    __shared__ double sPow[3 * (L + 2)];
+    __shared__ double sH[HPolyDims<L + 1>::N];
+    __shared__ int sHerm[nherm(L + 1)];
     __shared__ double sEb[3 * C::EBD];
     __shared__ double sEk[3 * C::EKD];
     __shared__ double sX[CDCH * NHX];
@@ -76,6 +77,7 @@ __global__ __launch_bounds__(64) void kg_wave(KGArgs g)
     extern __shared__ double sG[];  // natom x 3
 
     const int lane = threadIdx.x;
+    herm_table_lds(sHerm, nherm(L + 1), lane);
     const int na3 = 3 * g.natom;
     for (int o = lane; o < na3; o += 64) sG[o] = 0.0;
     // every entry finite from the start: the chunk loops below run to CDCH
@@ -129,7 +131,7 @@ __global__ __launch_bounds__(64) void kg_wave(KGArgs g)
                     if (pb.q * pk.q < a.tau_prim) break;
                     const QuartetGeo geo = quartet_geo(pb, pk);
                     wave_boys<L + 1>(geo, a.boys, sF, lane);
-                    wave_powers<L + 1>(geo, sPow, lane);
+                    wave_hpoly<L + 1>(geo, sH, lane);
                     if (lane >= 8 && lane < 11) {
                         const int k = lane - 8;
                         const double pa = k == 0 ? pb.PA[0] : (k == 1 ? pb.PA[1] : pb.PA[2]);
@@ -142,7 +144,7 @@ __global__ __launch_bounds__(64) void kg_wave(KGArgs g)
                         etab_lds<LC + 1, LD>(pa, pbb, pk.o2p, sEk + k * C::EKD);
                     }
                     __syncthreads();
-                    wave_r0<L + 1>(sF, sPow, sR0, lane);
+                    wave_r0h<L + 1>(sF, sH, sHerm, sR0, lane);
                     __syncthreads();
                     const double a2 = 2.0 * pb.a, c2 = 2.0 * pk.a;
 

@@ -205,9 +205,11 @@ __global__ __launch_bounds__(64) void jeng_wave(JArgs a)
     constexpr int L = LX + LY, L1 = L + 1, NX = nherm(LX), NY = nherm(LY);
     __shared__ T sR0[L1 * L1 * L1];
     __shared__ T sF[L + 1];
-    __shared__ T sPow[3 * (L + 1)];
+    __shared__ T sH[HPolyDims<L>::N];
+    __shared__ int sHerm[nherm(L)];
     __shared__ T sDq[NY];  // single precision: r^|Q| times the scaled Hermite density
     const int lane = threadIdx.x;
+    herm_table_lds(sHerm, nherm(L), lane);
     const int g = blockIdx.x;
     const PrimPair pb = a.pp[a.pbase + g];
     const double Qi = a.Qbra[a.owner[g]];
@@ -232,12 +234,13 @@ __global__ __launch_bounds__(64) void jeng_wave(JArgs a)
     for (int j = j0; j < j1; ++j) {
         if (a.mode && (Qi * a.QDket[j] >= a.tau_mix) != (a.mode == 1)) continue;
         const CPair B = a.ket[j];
+        PairLite pk = pair_lite(a.pp + B.poff);
         for (int kp = 0; kp < B.np; ++kp) {
-            const PrimPair pk = a.pp[B.poff + kp];
             if (qi * pk.q < a.tau_prim) break;
+            const PairLite pk_next = pair_lite(a.pp + B.poff + (kp + 1 < B.np ? kp + 1 : kp));
             const QuartetGeo geo = quartet_geo(pb, pk);
             wave_boys<L, T>(geo, a.boys, sF, lane);
-            wave_powers<L, T>(geo, sPow, lane);
+            wave_hpoly<L, T>(geo, sH, lane);
             const T *dt = Dt + (int64_t)(B.poff + kp - a.dt_base) * NY;
             if constexpr (sizeof(T) == 4) {
                 for (int Q = lane; Q < NY; Q += 64) {
@@ -251,7 +254,7 @@ __global__ __launch_bounds__(64) void jeng_wave(JArgs a)
                 dt = sDq;
             }
             __syncthreads();
-            wave_r0<L, T>(sF, sPow, sR0, lane);
+            wave_r0h<L, T>(sF, sH, sHerm, sR0, lane);
             __syncthreads();
 #pragma unroll
             for (int r = 0; r < 2; ++r) {
@@ -266,6 +269,7 @@ __global__ __launch_bounds__(64) void jeng_wave(JArgs a)
                 acc[r] += (double)s;
             }
             __syncthreads();
+            pk = pk_next;
         }
     }
 #pragma unroll

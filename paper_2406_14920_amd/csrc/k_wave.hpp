@@ -28,7 +28,7 @@ struct WaveCfg {
     static constexpr int NAB = NA * NB, NCD = NC * ND, NBLK = NAB * NCD;
     static constexpr int L = LA + LB + LC + LD, LAB = LA + LB, LCD = LC + LD, L1 = L + 1;
     static constexpr int NR0 = L1 * L1 * L1;
-    static constexpr bool STREAM = NBLK * (int)sizeof(T) > 2048 * 8;
+    static constexpr bool STREAM = NBLK > 2048;
     static constexpr int NABCH = (NAB + 63) / 64;
     static constexpr int CDCH = STREAM ? 16 : NCD;
     static constexpr int NCDCH = (NCD + CDCH - 1) / CDCH;
@@ -147,7 +147,8 @@ __global__ __launch_bounds__(64) void k_wave(KArgs a)
 
     __shared__ T sR0[C::NR0];
     __shared__ T sF[L + 1];
-    __shared__ T sPow[3 * (L + 1)];
+    __shared__ T sH[HPolyDims<L>::N];
+    __shared__ int sHerm[nherm(L)];
     __shared__ T sEb[C::SB];
     __shared__ T sEk[C::SK];
     __shared__ T sV[C::NV];
@@ -155,6 +156,7 @@ __global__ __launch_bounds__(64) void k_wave(KArgs a)
     __shared__ double sK[C::ND_];
 
     const int lane = threadIdx.x;
+    herm_table_lds(sHerm, nherm(L), lane);
 
     // the bra components this lane owns, their boxes and product offsets
     int own_m[C::NABCH][3], own_off[C::NABCH];
@@ -225,17 +227,19 @@ __global__ __launch_bounds__(64) void k_wave(KArgs a)
                 const PrimPair pb = a.pp[A.poff + ip];
                 if (pb.q * qk0 < a.tau_prim) break;
                 const T *eb = pick<T>(a.eprod_bra, a.eprodf_bra) + (int64_t)(A.poff + ip - a.pbase_bra) * C::SB;
+                PairLite pk = pair_lite(a.pp + B.poff);
                 for (int kp = 0; kp < B.np; ++kp) {
-                    const PrimPair pk = a.pp[B.poff + kp];
                     if (pb.q * pk.q < a.tau_prim) break;
+                    // next ket primitive pair in flight while this one is evaluated
+                    const PairLite pk_next = pair_lite(a.pp + B.poff + (kp + 1 < B.np ? kp + 1 : kp));
                     const QuartetGeo g = quartet_geo(pb, pk);
                     wave_boys<L, T>(g, a.boys, sF, lane);
-                    wave_powers<L, T>(g, sPow, lane);
+                    wave_hpoly<L, T>(g, sH, lane);
                     const T *ek = pick<T>(a.eprod_ket, a.eprodf_ket) + (int64_t)(B.poff + kp - a.pbase_ket) * C::SK;
                     for (int o = lane; o < C::SB; o += 64) sEb[o] = eb[o];
                     for (int o = lane; o < C::SK; o += 64) sEk[o] = ek[o];
                     __syncthreads();
-                    wave_r0<L, T>(sF, sPow, sR0, lane);
+                    wave_r0h<L, T>(sF, sH, sHerm, sR0, lane);
                     __syncthreads();
 
                     static_for<0, C::NABCH>([&](auto chc) {
@@ -303,6 +307,7 @@ __global__ __launch_bounds__(64) void k_wave(KArgs a)
                         });
                     });
                     __syncthreads();
+                    pk = pk_next;
                 }
             }
             if constexpr (!C::STREAM) {

@@ -52,6 +52,42 @@ __device__ __forceinline__ QuartetGeo quartet_geo(const PrimPair &pb, const Prim
     return g;
 }
 
+// The fields of a ket primitive pair that a quartet needs, loaded one by one
+// (a loop-carried copy of the whole record would live in scratch memory).
+struct PairLite {
+    double p, K, q, P0, P1, P2;
+};
+
+__device__ __forceinline__ PairLite pair_lite(const PrimPair *__restrict__ r)
+{
+    PairLite x;
+    x.p = r->p;
+    x.K = r->K;
+    x.q = r->q;
+    x.P0 = r->P[0];
+    x.P1 = r->P[1];
+    x.P2 = r->P[2];
+    return x;
+}
+
+__device__ __forceinline__ QuartetGeo quartet_geo(const PrimPair &pb, const PairLite &pk)
+{
+    QuartetGeo g;
+    double p = pb.p, q = pk.p;
+    double rpq = 1.0 / (p + q);
+    g.alpha = p * q * rpq;
+    g.X = pb.P[0] - pk.P0;
+    g.Y = pb.P[1] - pk.P1;
+    g.Z = pb.P[2] - pk.P2;
+    g.T = g.alpha * (g.X * g.X + g.Y * g.Y + g.Z * g.Z);
+    g.pref0 = kTwoPi52 / (p * q) * sqrt(rpq);
+    g.pref = g.pref0 * pb.K * pk.K;
+    g.c = sqrt(2.0 * p);
+    g.w = -q * rpq;
+    g.r = sqrt(p / q);
+    return g;
+}
+
 // Phase 1 (no barrier inside): lane m <= L writes sF[m] = pref (-2 alpha)^m F_m
 // (single precision: the scaled G~_m = pref0 w^m F_m).  F_m and the scale are
 // formed in double precision; the product is stored as T.
@@ -232,6 +268,69 @@ __device__ __forceinline__ void etab_reg_store(double PA, double PB, double o2p,
             });
         });
     });
+}
+
+// LDS-resident form of the closed form above, for the wave kernels.
+// Per quartet, lanes tabulate the per-axis factors
+//     sH[axis][t][a] = C_t^a X_axis^{t-2a},   t <= L, a <= t/2
+// (single precision: the scaled X~ = c X) in the same phase as the Boys
+// values, so that building R reads LDS only:
+//     R^0_{tuv} = sum_{a,b,c} sH[x][t][a] sH[y][u][b] sH[z][v][c] G_{t+u+v-a-b-c}.
+template <int L>
+struct HPolyDims {
+    static constexpr int H = L / 2 + 1;
+    static constexpr int N = 3 * (L + 1) * H;
+};
+
+// Hermite index decode table (t | u<<8 | v<<16 for k < n) into LDS; call once
+// at kernel start, visible after the first barrier.
+__device__ __forceinline__ void herm_table_lds(int *sHerm, int n, int lane)
+{
+    for (int k = lane; k < n; k += 64) sHerm[k] = c_herm.tuv[k];
+}
+
+// Phase 1 (no barrier inside).
+template <int L, typename T>
+__device__ __forceinline__ void wave_hpoly(const QuartetGeo &g, T *sH, int lane)
+{
+    constexpr int H = HPolyDims<L>::H;
+    const double f = sizeof(T) == 4 ? g.c : 1.0;
+    const double gx = f * g.X, gy = f * g.Y, gz = f * g.Z;  // values, not a runtime-indexed member
+    for (int i = lane; i < HPolyDims<L>::N; i += 64) {
+        const int axis = i / ((L + 1) * H), t = (i / H) % (L + 1), a = i % H;
+        if (2 * a > t) continue;
+        double x = gx;
+        if (axis == 1) x = gy;
+        if (axis == 2) x = gz;
+        double v = c_hcoef.c[t][a];
+        for (int k = 0; k < t - 2 * a; ++k) v *= x;
+        sH[i] = (T)v;
+    }
+}
+
+// Phase 2 (after the barrier that publishes sF, sH and sHerm): dense R^0
+// into sR0.  No barrier inside.
+template <int L, typename T>
+__device__ __forceinline__ void wave_r0h(const T *sF, const T *sH, const int *sHerm, T *sR0, int lane)
+{
+    constexpr int L1 = L + 1, H = HPolyDims<L>::H;
+    const T *hx = sH, *hy = sH + L1 * H, *hz = sH + 2 * L1 * H;
+    for (int k = lane; k < nherm(L); k += 64) {
+        const int code = sHerm[k];
+        const int t = code & 0xff, u = (code >> 8) & 0xff, v = code >> 16;
+        T acc = T(0);
+        for (int a = 0; 2 * a <= t; ++a) {
+            const T ha = hx[t * H + a];
+            for (int b = 0; 2 * b <= u; ++b) {
+                const T hab = ha * hy[u * H + b];
+                const int n0 = t + u + v - a - b;
+                T s = T(0);
+                for (int c = 0; 2 * c <= v; ++c) s += hz[v * H + c] * sF[n0 - c];
+                acc += hab * s;
+            }
+        }
+        sR0[(t * L1 + u) * L1 + v] = acc;
+    }
 }
 
 // Cartesian exponents of component c of a shell with angular momentum l (runtime).
