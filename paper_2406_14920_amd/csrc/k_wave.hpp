@@ -39,7 +39,9 @@ struct WaveCfg {
     static constexpr int RANGE = 8;
 };
 
-// Digest of a sub-block with runtime bounds (streaming mode).
+// Digest of a sub-block (streaming mode): V(ab, cd) = sV[(cd - cdb) * vstride
+// + (ab - abb)] for ab in [ab0, ab1), cd in [cd0, cd1); same element-wise
+// scatter with LDS atomics as digest_full.
 template <int NA, int NB, int NC, int ND, typename T>
 __device__ __forceinline__ void digest_rt(const T *sV, int vstride, int abb, int cdb, int ab0,
                                           int ab1, int cd0, int cd1, const double *sD, double *sK,
@@ -47,93 +49,39 @@ __device__ __forceinline__ void digest_rt(const T *sV, int vstride, int abb, int
 {
     const double *D13 = sD, *D14 = sD + NA * NC, *D23 = D14 + NA * ND, *D24 = D23 + NB * NC;
     double *K13 = sK, *K14 = sK + NA * NC, *K23 = K14 + NA * ND, *K24 = K23 + NB * NC;
-    constexpr int O1 = NA * NC, O2 = O1 + NA * ND, O3 = O2 + NB * NC, O4 = O3 + NB * ND;
-    auto V = [&](int ab, int cd) { return (double)sV[(cd - cdb) * vstride + (ab - abb)]; };
-    for (int o = lane; o < O4; o += 64) {
-        double acc = 0.0;
-        if (o < O1) {
-            const int i = o / NC, k = o % NC;
-            const int j0 = max(0, ab0 - i * NB), j1 = min(NB, ab1 - i * NB);
-            const int l0 = max(0, cd0 - k * ND), l1 = min(ND, cd1 - k * ND);
-            for (int j = j0; j < j1; ++j)
-                for (int l = l0; l < l1; ++l) acc += V(i * NB + j, k * ND + l) * D24[j * ND + l];
-            K13[o] += acc;
-        } else if (o < O2) {
-            const int r = o - O1, i = r / ND, l = r % ND;
-            const int j0 = max(0, ab0 - i * NB), j1 = min(NB, ab1 - i * NB);
-            for (int j = j0; j < j1; ++j)
-                for (int k = 0; k < NC; ++k) {
-                    const int cd = k * ND + l;
-                    if (cd >= cd0 && cd < cd1) acc += V(i * NB + j, cd) * D23[j * NC + k];
-                }
-            K14[r] += acc;
-        } else if (o < O3) {
-            const int r = o - O2, j = r / NC, k = r % NC;
-            const int l0 = max(0, cd0 - k * ND), l1 = min(ND, cd1 - k * ND);
-            for (int i = 0; i < NA; ++i) {
-                const int ab = i * NB + j;
-                if (ab < ab0 || ab >= ab1) continue;
-                for (int l = l0; l < l1; ++l) acc += V(ab, k * ND + l) * D14[i * ND + l];
-            }
-            K23[r] += acc;
-        } else {
-            const int r = o - O3, j = r / ND, l = r % ND;
-            for (int i = 0; i < NA; ++i) {
-                const int ab = i * NB + j;
-                if (ab < ab0 || ab >= ab1) continue;
-                for (int k = 0; k < NC; ++k) {
-                    const int cd = k * ND + l;
-                    if (cd >= cd0 && cd < cd1) acc += V(ab, cd) * D13[i * NC + k];
-                }
-            }
-            K24[r] += acc;
-        }
+    const int nab = ab1 - ab0, n = nab * (cd1 - cd0);
+    for (int e = lane; e < n; e += 64) {
+        const int ab = ab0 + e % nab, cd = cd0 + e / nab;
+        const int i = ab / NB, j = ab % NB, k = cd / ND, l = cd % ND;
+        const double v = (double)sV[(cd - cdb) * vstride + (ab - abb)];
+        atomicAdd(&K13[i * NC + k], v * D24[j * ND + l]);
+        atomicAdd(&K14[i * ND + l], v * D23[j * NC + k]);
+        atomicAdd(&K23[j * NC + k], v * D14[i * ND + l]);
+        atomicAdd(&K24[j * ND + l], v * D13[i * NC + k]);
     }
 }
 
-// Digest of a whole block held as sV[cd * NAB + ab]; inner sums unrolled.
+// Digest of a whole block held as sV[cd * NAB + ab]: every lane takes block
+// elements in turn and adds each one's four contributions
+//     K_ac[i][k] += V D_bd[j][l],  K_ad[i][l] += V D_bc[j][k],
+//     K_bc[j][k] += V D_ad[i][l],  K_bd[j][l] += V D_ac[i][k]
+// to the LDS exchange tiles with FP64 LDS atomics (the lanes of one step share
+// at most NA or NB targets, so the atomics rarely collide, and no lane waits
+// on another's branch).
 template <int NA, int NB, int NC, int ND, typename T>
 __device__ __forceinline__ void digest_full(const T *sV, const double *sD, double *sK, int lane)
 {
-    constexpr int NAB = NA * NB;
+    constexpr int NAB = NA * NB, NCD = NC * ND;
     const double *D13 = sD, *D14 = sD + NA * NC, *D23 = D14 + NA * ND, *D24 = D23 + NB * NC;
     double *K13 = sK, *K14 = sK + NA * NC, *K23 = K14 + NA * ND, *K24 = K23 + NB * NC;
-    constexpr int O1 = NA * NC, O2 = O1 + NA * ND, O3 = O2 + NB * NC, O4 = O3 + NB * ND;
-    for (int o = lane; o < O4; o += 64) {
-        double acc = 0.0;
-        if (o < O1) {  // K_ac[i][k] += sum_{j,l} V[ij][kl] D_bd[j][l]
-            const int i = o / NC, k = o % NC;
-            const T *v = sV + k * ND * NAB + i * NB;
-#pragma unroll
-            for (int j = 0; j < NB; ++j)
-#pragma unroll
-                for (int l = 0; l < ND; ++l) acc += (double)v[l * NAB + j] * D24[j * ND + l];
-            K13[o] += acc;
-        } else if (o < O2) {  // K_ad[i][l] += sum_{j,k} V[ij][kl] D_bc[j][k]
-            const int r = o - O1, i = r / ND, l = r % ND;
-            const T *v = sV + l * NAB + i * NB;
-#pragma unroll
-            for (int j = 0; j < NB; ++j)
-#pragma unroll
-                for (int k = 0; k < NC; ++k) acc += (double)v[k * ND * NAB + j] * D23[j * NC + k];
-            K14[r] += acc;
-        } else if (o < O3) {  // K_bc[j][k] += sum_{i,l} V[ij][kl] D_ad[i][l]
-            const int r = o - O2, j = r / NC, k = r % NC;
-            const T *v = sV + k * ND * NAB + j;
-#pragma unroll
-            for (int i = 0; i < NA; ++i)
-#pragma unroll
-                for (int l = 0; l < ND; ++l) acc += (double)v[l * NAB + i * NB] * D14[i * ND + l];
-            K23[r] += acc;
-        } else {  // K_bd[j][l] += sum_{i,k} V[ij][kl] D_ac[i][k]
-            const int r = o - O3, j = r / ND, l = r % ND;
-            const T *v = sV + l * NAB + j;
-#pragma unroll
-            for (int i = 0; i < NA; ++i)
-#pragma unroll
-                for (int k = 0; k < NC; ++k) acc += (double)v[k * ND * NAB + i * NB] * D13[i * NC + k];
-            K24[r] += acc;
-        }
+    for (int e = lane; e < NAB * NCD; e += 64) {
+        const int ab = e % NAB, cd = e / NAB;
+        const int i = ab / NB, j = ab % NB, k = cd / ND, l = cd % ND;
+        const double v = (double)sV[e];
+        atomicAdd(&K13[i * NC + k], v * D24[j * ND + l]);
+        atomicAdd(&K14[i * ND + l], v * D23[j * NC + k]);
+        atomicAdd(&K23[j * NC + k], v * D14[i * ND + l]);
+        atomicAdd(&K24[j * ND + l], v * D13[i * NC + k]);
     }
 }
 
