@@ -61,8 +61,9 @@ extern "C" {
 #define ERI_EHIP   (-3) /* HIP runtime error; the message carries hipGetErrorString */
 #define ERI_ESTATE (-4) /* null/destroyed context or an inconsistent request */
 
-#define ERI_FP64  0
-#define ERI_MIXED 1
+#define ERI_FP64      0
+#define ERI_MIXED     1  /* single-precision share where it pays (per launch; see eri_autotune) */
+#define ERI_MIXED_ALL 2  /* the paper's rule on every launch: FP32 below the threshold everywhere */
 
 typedef struct eri_ctx eri_ctx;
 
@@ -82,9 +83,16 @@ typedef struct {
     double schwarz_thresh; /* shell-quartet threshold tau_S (>= 0) */
     double prim_thresh;    /* primitive-quartet threshold (>= 0); 0 keeps every
                               primitive of a kept shell quartet */
-    double mixed_thresh;   /* ERI_MIXED: quartets with Q_ab*Q_cd*max|P| below this
-                              run their primitive integrals in FP32 (>= 0) */
-    int32_t precision;     /* ERI_FP64 or ERI_MIXED */
+    double mixed_thresh;   /* mixed modes: a wavefront tile whose quartets all have
+                              density-weighted bounds Q_ab*Q_cd*max|P_blk| below this
+                              runs its primitive integrals in FP32 (>= 0) */
+    int32_t precision;     /* ERI_FP64, ERI_MIXED or ERI_MIXED_ALL.  In ERI_MIXED a
+                              launch takes the FP32 share only where that is faster:
+                              by default the exchange classes with la+lb+lc+ld >= 5;
+                              the J-engine stays FP64 (its FP32 share is dominated by
+                              the FP64 Boys values and conversions); eri_autotune
+                              re-decides per launch from timings.  Boys values,
+                              bounds, digestion and accumulation are FP64 always. */
     int32_t spherical;     /* 1: real solid harmonics (default); 0: Cartesian */
     void *stream;          /* hipStream_t, NULL = default stream */
 } eri_opts;
@@ -94,7 +102,7 @@ typedef struct {
     int64_t n_pairs;             /* contracted shell pairs kept (Q_ab > 0) */
     int64_t n_prim_pairs;        /* primitive pairs stored */
     int64_t n_quartets;          /* unique shell quartets passing the Schwarz rule */
-    int64_t n_quartets_fp32;     /* of which run in FP32 (ERI_MIXED, last build_jk) */
+    int64_t n_quartets_fp32;     /* of which run in FP32 (mixed modes, last build_jk) */
     double  eris_sph;            /* sum over kept unique quartets of prod (2l+1) */
     double  eris_cart;           /* same with Cartesian component counts */
     double  model_flops_k;       /* model FLOPs of one K build (unique quartets) */
@@ -129,7 +137,8 @@ int eri_nbf(const eri_ctx *ctx, int32_t *nbf);
 /* Move the atoms (same shells) and redo the pair/Schwarz setup.  Synchronous. */
 int eri_set_geometry(eri_ctx *ctx, const eri_atom *atoms);
 
-/* Change the precision mode (ERI_FP64 / ERI_MIXED) and mixed threshold. */
+/* Change the precision mode (ERI_FP64 / ERI_MIXED / ERI_MIXED_ALL) and the
+ * mixed threshold. */
 int eri_set_precision(eri_ctx *ctx, int32_t precision, double mixed_thresh);
 
 /* J_mn = sum_ls (mn|ls) P_ls (J-engine, eq. j_formula) and
@@ -157,9 +166,11 @@ int jk_grad(eri_ctx *ctx, const double *P, double *grad, double *E);
 int eri_energy(eri_ctx *ctx, const double *P, const double *J, const double *K, double *E);
 
 /* Profiling: while on, every kernel launch of later calls is bracketed by HIP
- * events on the launch stream; eri_profile_read synchronises, reports the
+ * events on the launch stream and build_jk runs all its launches on the
+ * context stream (no concurrent J / exchange streams), so each pair of events
+ * brackets one kernel alone; eri_profile_read synchronises, reports the
  * accumulated per-kernel times (up to cap entries, *n set to the count) and
- * clears them.  Profiling adds event records between launches only. */
+ * clears them. */
 int eri_set_profiling(eri_ctx *ctx, int32_t on);
 int eri_profile_read(eri_ctx *ctx, eri_kernel_time *out, int32_t cap, int32_t *n);
 
@@ -170,11 +181,14 @@ int eri_stats(const eri_ctx *ctx, eri_stats_t *out);
 int eri_destroy(eri_ctx *ctx);
 
 /* Autotuner: times the candidate launch shapes (J-engine ket chunk per class
- * pair; workgroup cap of each range-walking exchange launch) on this
+ * pair; workgroup cap of each range-walking exchange launch; under ERI_MIXED
+ * also whether each launch takes the FP32 share at all) on this
  * context's own workload -- device density P, current precision -- best of
  * reps runs each, and keeps the fastest for later builds.  Replaces the
  * paper's fixed rule for splitting work between kernels.  Synchronous;
- * leaves J/K results unchanged except for the order of atomic additions. */
+ * leaves J/K results unchanged except for the order of atomic additions
+ * (under ERI_MIXED, launches moved between FP32 and FP64 change results
+ * within the mixed-precision error). */
 int eri_autotune(eri_ctx *ctx, const double *P, int32_t reps);
 
 /* The launch shapes in use: kchunk100[10*X + Y] (may be NULL), the first
@@ -188,14 +202,14 @@ int eri_tuning(const eri_ctx *ctx, int32_t *kchunk100, int32_t *kcap, int32_t ca
  * on (NULL: a stream owned by the batch).  The contexts stay owned by the
  * caller and must outlive the batch.
  * eri_batch_build_jk: P, J, K are host arrays of n device pointers
- * (nbf_i x nbf_i each, as in build_jk; none NULL).  The first call records
- * every molecule's build into one HIP graph, each molecule a branch that
- * may run concurrently with the others; later calls with the same pointers
- * and unchanged contexts replay that graph (one launch for the whole batch).
- * New pointers, eri_set_geometry or eri_set_precision on a member cause a
- * new recording.  Results equal those of build_jk on each context (up to the
- * order of floating-point atomic additions).  Asynchronous on the batch
- * stream; profiling is suspended while recording. */
+ * (nbf_i x nbf_i each, as in build_jk; none NULL).  Every molecule's build
+ * is forked from the batch stream onto one of up to 8 batch streams and
+ * joined back, so molecules run concurrently.  (The library also holds a
+ * path that records the whole batch into one HIP graph and replays it; it is
+ * switched off in this build after host-side crashes of the recorded batch
+ * on the MI355X runtime.)  Results equal those of build_jk on each context
+ * (up to the order of floating-point atomic additions).  Asynchronous on the
+ * batch stream. */
 typedef struct eri_batch eri_batch;
 int eri_batch_create(eri_ctx *const *ctxs, int32_t n, void *stream, eri_batch **out);
 int eri_batch_build_jk(eri_batch *b, const double *const *P, double *const *J, double *const *K);

@@ -17,6 +17,10 @@ from . import abi  # noqa: F401  (ctypes only; loads the .so lazily)
 
 __all__ = ["abi", "JK", "JKEnergy", "Batch"]
 
+# precision names: "fp64"; "mixed" (FP32 share where it is faster);
+# "mixed_all" (the density-weighted rule on every launch)
+_PREC = {"fp64": abi.ERI_FP64, "mixed": abi.ERI_MIXED, "mixed_all": abi.ERI_MIXED_ALL}
+
 
 class JK:
     """One eri_ctx: a fixed basis/geometry, reused across builds."""
@@ -29,7 +33,7 @@ class JK:
         o.schwarz_thresh = float(schwarz_thresh)
         o.prim_thresh = float(1e-2 * schwarz_thresh if prim_thresh is None else prim_thresh)
         o.mixed_thresh = float(mixed_thresh)
-        o.precision = abi.ERI_MIXED if precision == "mixed" else abi.ERI_FP64
+        o.precision = _PREC[precision]
         o.spherical = 1 if spherical else 0
         if stream is None:
             stream = torch.cuda.current_stream()
@@ -91,7 +95,7 @@ class JK:
         self._xyz = [[float(v) for v in r] for r in xyz]
 
     def set_precision(self, precision: str, mixed_thresh: Optional[float] = None):
-        abi.eri_set_precision(self.ctx, abi.ERI_MIXED if precision == "mixed" else abi.ERI_FP64,
+        abi.eri_set_precision(self.ctx, _PREC[precision],
                               self.opts.mixed_thresh if mixed_thresh is None else mixed_thresh)
 
     def stats(self) -> dict:

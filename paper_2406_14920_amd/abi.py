@@ -17,7 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libmdjk.so")
 
 ERI_OK, ERI_EINVAL, ERI_ENOMEM, ERI_EHIP, ERI_ESTATE = 0, -1, -2, -3, -4
-ERI_FP64, ERI_MIXED = 0, 1
+ERI_FP64, ERI_MIXED, ERI_MIXED_ALL = 0, 1, 2
 _NAMES = {ERI_EINVAL: "ERI_EINVAL", ERI_ENOMEM: "ERI_ENOMEM", ERI_EHIP: "ERI_EHIP", ERI_ESTATE: "ERI_ESTATE"}
 
 

@@ -252,11 +252,16 @@ struct eri_ctx {
     // (bra class, ket class) and workgroup cap per exchange launch
     int kchunk[kPairClasses][kPairClasses];
     std::vector<int> kcap;
+    // ERI_MIXED: whether a launch takes the single-precision share at all
+    // (J-engine per (X, Y), exchange per work list); ERI_MIXED_ALL splits all
+    bool jsplit[kPairClasses][kPairClasses];
+    std::vector<char> ksplit;
 
     bool profile = false;
     std::vector<Rec> pending;
     // streams the J work and the bra-shared / small exchange launches fork
     // onto, joined back into the context stream by events
+    bool recording = false;  // inside a batch graph recording: no internal fork
     hipStream_t aux[2] = {nullptr, nullptr};
     hipEvent_t ev_fork = nullptr, ev_kzero = nullptr, ev_join[2] = {nullptr, nullptr};
     std::map<std::string, Acc> prof;
@@ -294,7 +299,7 @@ int validate(const eri_shell *shells, int32_t nshell, const eri_atom *atoms, int
     if (o) {
         if (!(o->schwarz_thresh >= 0.0) || !(o->prim_thresh >= 0.0) || !(o->mixed_thresh >= 0.0))
             return set_err(ERI_EINVAL, "negative or NaN threshold");
-        if (o->precision != ERI_FP64 && o->precision != ERI_MIXED)
+        if (o->precision != ERI_FP64 && o->precision != ERI_MIXED && o->precision != ERI_MIXED_ALL)
             return set_err(ERI_EINVAL, "unknown precision %d", o->precision);
     }
     return ERI_OK;
@@ -488,8 +493,16 @@ void build_pairs(eri_ctx *c)
     c->d_prefix.upload(prefix);
     c->d_chunks.upload(chunks);
     for (int X = 0; X < kPairClasses; ++X)
-        for (int Y = 0; Y < kPairClasses; ++Y) c->kchunk[X][Y] = 256;
+        for (int Y = 0; Y < kPairClasses; ++Y) {
+            c->kchunk[X][Y] = 256;
+            c->jsplit[X][Y] = false;  // FP64 J-engine: Boys and conversions dominate its FP32 share
+        }
     c->kcap.assign(c->kwork.size(), 0);
+    c->ksplit.assign(c->kwork.size(), 0);
+    for (size_t wi = 0; wi < c->kwork.size(); ++wi) {
+        const auto &w = c->kwork[wi];
+        c->ksplit[wi] = kPairL[w.X][0] + kPairL[w.X][1] + kPairL[w.Y][0] + kPairL[w.Y][1] >= 5;
+    }
 
     // Hermite products of every primitive pair (bra/ket data of the bra-shared kernel)
     size_t ep = 0;
@@ -644,6 +657,16 @@ ShellMap shell_map(const eri_ctx *c)
 
 bool ctx_ok(const eri_ctx *c) { return c && c->magic == 0x4d444a4b; }
 
+// Does this launch take the single-precision share (two launches, modes 1/2)?
+bool j_split(const eri_ctx *c, int X, int Y)
+{
+    return c->opts.precision == ERI_MIXED_ALL || (c->opts.precision == ERI_MIXED && c->jsplit[X][Y]);
+}
+bool k_split(const eri_ctx *c, size_t wi)
+{
+    return c->opts.precision == ERI_MIXED_ALL || (c->opts.precision == ERI_MIXED && c->ksplit[wi]);
+}
+
 template <typename F>
 void timed(eri_ctx *c, hipStream_t st, const std::string &name, int work, int idx, int part, F &&launch)
 {
@@ -714,7 +737,8 @@ void run_j(eri_ctx *c, bool mixed, hipStream_t st)
             const std::string nm = cls_name(lx + ly <= 5 ? "jeng_small" : (jeng_is_reg(lx, ly) ? "jeng_reg" : "jeng_wave"),
                                             kPairL[X][0], kPairL[X][1], kPairL[Y][0], kPairL[Y][1]);
             JArgs a = j_args(c, X, Y, mixed);
-            for (int part = mixed ? 1 : 0; part <= (mixed ? 2 : 0); ++part) {
+            const bool split = mixed && j_split(c, X, Y);
+            for (int part = split ? 1 : 0; part <= (split ? 2 : 0); ++part) {
                 a.mode = part;
                 timed(c, st, part == 0 ? nm : nm + (part == 1 ? "/d" : "/s"), 1, X * kPairClasses + Y, part,
                       [&] { launch_jeng(lx, ly, a, part == 2, st); });
@@ -806,7 +830,8 @@ void run_k(eri_ctx *c, bool mixed, hipStream_t stA, hipStream_t stB)
         const int la = kPairL[w.X][0], lb = kPairL[w.X][1], lc = kPairL[w.Y][0], ld = kPairL[w.Y][1];
         const int wi = (int)(&w - c->kwork.data());
         KArgs a = k_args(c, w, mixed);
-        for (int part = mixed ? 1 : 0; part <= (mixed ? 2 : 0); ++part) {
+        const bool split = mixed && k_split(c, (size_t)wi);
+        for (int part = split ? 1 : 0; part <= (split ? 2 : 0); ++part) {
             a.mode = part;
             const bool f32 = part == 2;
             const char *sfx = part == 0 ? "" : (part == 1 ? "/d" : "/s");
@@ -850,7 +875,7 @@ void mixed_counts(const eri_ctx *c)
     HIPCHK(hipMemsetAsync(cnt.p, 0, n * sizeof(unsigned long long), c->st));
     for (size_t wi = 0; wi < nk; ++wi) {
         const auto &w = c->kwork[wi];
-        if (w.nwork == 0) continue;
+        if (w.nwork == 0 || !k_split(c, wi)) continue;
         KArgs a = k_args(c, w, true);
         const int la = kPairL[w.X][0], lb = kPairL[w.X][1], lc = kPairL[w.Y][0], ld = kPairL[w.Y][1];
         const int kind = w.choff >= 0 ? 2 : (is_k_small(la, lb, lc, ld) ? 0 : 1);
@@ -859,7 +884,7 @@ void mixed_counts(const eri_ctx *c)
     }
     for (int X = 0; X < kPairClasses; ++X)
         for (int Y = 0; Y < kPairClasses; ++Y) {
-            if (c->npp[X] == 0 || c->ncp[Y] == 0) continue;
+            if (c->npp[X] == 0 || c->ncp[Y] == 0 || !j_split(c, X, Y)) continue;
             JArgs a = j_args(c, X, Y, true);
             const int lx = kPairL[X][0] + kPairL[X][1], ly = kPairL[Y][0] + kPairL[Y][1];
             const int per_bra = (lx + ly > 5 && !jeng_is_reg(lx, ly)) ? 1 : 0;
@@ -1076,7 +1101,8 @@ int eri_set_geometry(eri_ctx *ctx, const eri_atom *atoms)
 int eri_set_precision(eri_ctx *ctx, int32_t precision, double mixed_thresh)
 {
     if (!ctx_ok(ctx)) return set_err(ERI_ESTATE, "invalid context");
-    if (precision != ERI_FP64 && precision != ERI_MIXED) return set_err(ERI_EINVAL, "unknown precision %d", precision);
+    if (precision != ERI_FP64 && precision != ERI_MIXED && precision != ERI_MIXED_ALL)
+        return set_err(ERI_EINVAL, "unknown precision %d", precision);
     if (!(mixed_thresh >= 0.0)) return set_err(ERI_EINVAL, "negative mixed threshold");
     if (ctx->opts.precision != precision || ctx->opts.mixed_thresh != mixed_thresh) ++ctx->gen;
     ctx->opts.precision = precision;
@@ -1092,7 +1118,7 @@ int build_jk(eri_ctx *ctx, const double *P, double *J, double *K)
         hipStream_t st = ctx->st;
         const ShellMap m = shell_map(ctx);
         const int nc = ctx->nbf_cart;
-        const bool mixed = ctx->opts.precision == ERI_MIXED;
+        const bool mixed = ctx->opts.precision != ERI_FP64;
         launch_p_to_cart(P, ctx->nbf, ctx->d_Pc.p, nc, m, ctx->opts.spherical, st);
         if (mixed) {
             ensure_mixed(ctx);
@@ -1102,10 +1128,13 @@ int build_jk(eri_ctx *ctx, const double *P, double *J, double *K)
         ctx->built_mixed = mixed;
         ctx->mix_counts_ok = false;
         // J on its own stream, K split over the context stream and a second
-        // one; all accumulate with atomics, so the three run concurrently
+        // one; all accumulate with atomics, so the three run concurrently.
+        // While profiling, everything stays on the context stream so that
+        // each kernel's events bracket it alone.
+        const bool fork = !ctx->profile && !ctx->recording;
         HIPCHK(hipEventRecord(ctx->ev_fork, st));
         if (J) {
-            hipStream_t sJ = ctx->aux[0];
+            hipStream_t sJ = fork ? ctx->aux[0] : st;
             HIPCHK(hipStreamWaitEvent(sJ, ctx->ev_fork, 0));
             launch_fill_zero(ctx->d_Jacc.p, (int64_t)nc * nc, sJ);
             run_j(ctx, mixed, sJ);
@@ -1113,7 +1142,7 @@ int build_jk(eri_ctx *ctx, const double *P, double *J, double *K)
             HIPCHK(hipEventRecord(ctx->ev_join[0], sJ));
         }
         if (K) {
-            hipStream_t sK = ctx->aux[1];
+            hipStream_t sK = fork ? ctx->aux[1] : st;
             launch_fill_zero(ctx->d_Kacc.p, (int64_t)nc * nc, st);
             HIPCHK(hipEventRecord(ctx->ev_kzero, st));
             HIPCHK(hipStreamWaitEvent(sK, ctx->ev_kzero, 0));
@@ -1298,7 +1327,7 @@ int eri_autotune(eri_ctx *ctx, const double *P, int32_t reps)
         HIPCHK(hipEventCreate(&e0));
         HIPCHK(hipEventCreate(&e1));
         hipStream_t st = ctx->st;
-        const bool mixed = ctx->opts.precision == ERI_MIXED;
+        const bool mixed = ctx->opts.precision != ERI_FP64;
         auto time_it = [&](auto &&launch) {
             float best = 1e30f;
             for (int r = 0; r < reps; ++r) {
@@ -1312,6 +1341,10 @@ int eri_autotune(eri_ctx *ctx, const double *P, int32_t reps)
             }
             return best;
         };
+        // split options: ERI_MIXED tries both (the FP32 share is kept only
+        // where it is faster); ERI_MIXED_ALL and ERI_FP64 have one
+        const int prec = ctx->opts.precision;
+        const bool tune_split = prec == ERI_MIXED;
         static const int kChunks[] = {64, 128, 256, 512, 1024};
         for (int X = 0; X < kPairClasses; ++X)
             for (int Y = 0; Y < kPairClasses; ++Y) {
@@ -1319,47 +1352,77 @@ int eri_autotune(eri_ctx *ctx, const double *P, int32_t reps)
                 const int lx = kPairL[X][0] + kPairL[X][1], ly = kPairL[Y][0] + kPairL[Y][1];
                 float best = 1e30f;
                 int pick = ctx->kchunk[X][Y];
-                for (int kc : kChunks) {
-                    JArgs a = j_args(ctx, X, Y, mixed);
-                    a.kchunk = kc;
-                    const float ms = time_it([&] {
-                        for (int part = mixed ? 1 : 0; part <= (mixed ? 2 : 0); ++part) {
-                            a.mode = part;
-                            launch_jeng(lx, ly, a, part == 2, st);
+                bool pick_split = ctx->jsplit[X][Y];
+                for (int sp = 0; sp < 2; ++sp) {
+                    const bool split = tune_split ? sp == 1 : (sp == 0 && prec == ERI_MIXED_ALL);
+                    if (!tune_split && sp == 1) break;
+                    for (int kc : kChunks) {
+                        JArgs a = j_args(ctx, X, Y, mixed);
+                        a.kchunk = kc;
+                        const float ms = time_it([&] {
+                            for (int part = split ? 1 : 0; part <= (split ? 2 : 0); ++part) {
+                                a.mode = part;
+                                launch_jeng(lx, ly, a, part == 2, st);
+                            }
+                        });
+                        if (ms < best) {
+                            best = ms;
+                            pick = kc;
+                            pick_split = split;
                         }
-                    });
-                    if (ms < best) {
-                        best = ms;
-                        pick = kc;
                     }
                 }
                 ctx->kchunk[X][Y] = pick;
+                if (tune_split) ctx->jsplit[X][Y] = pick_split;
             }
         static const int kCaps[] = {1024, 4096, 16384, 32768, 131072};
         for (size_t wi = 0; wi < ctx->kwork.size(); ++wi) {
             const auto &w = ctx->kwork[wi];
             const int la = kPairL[w.X][0], lb = kPairL[w.X][1], lc = kPairL[w.Y][0], ld = kPairL[w.Y][1];
-            if (w.nwork == 0 || w.choff >= 0 || is_k_small(la, lb, lc, ld)) continue;
+            if (w.nwork == 0) continue;
+            const bool wave = w.choff < 0 && !is_k_small(la, lb, lc, ld);
+            if (!wave && !tune_split) continue;
             float best = 1e30f;
             int pick = ctx->kcap[wi];
-            for (int cap : kCaps) {
-                KArgs a = k_args(ctx, w, mixed);
-                a.grid_cap = cap;
-                const float ms = time_it([&] {
-                    for (int part = mixed ? 1 : 0; part <= (mixed ? 2 : 0); ++part) {
-                        a.mode = part;
-                        const bool f32 = part == 2;
-                        (void)(launch_k_wave_0(la, lb, lc, ld, a, f32, st) || launch_k_wave_1(la, lb, lc, ld, a, f32, st) ||
-                               launch_k_wave_2(la, lb, lc, ld, a, f32, st) || launch_k_wave_3(la, lb, lc, ld, a, f32, st) ||
-                               launch_k_wave_4(la, lb, lc, ld, a, f32, st) || launch_k_wave_5(la, lb, lc, ld, a, f32, st));
+            bool pick_split = ctx->ksplit[wi] != 0;
+            for (int sp = 0; sp < 2; ++sp) {
+                const bool split = tune_split ? sp == 1 : (sp == 0 && prec == ERI_MIXED_ALL);
+                if (!tune_split && sp == 1) break;
+                for (int cap : kCaps) {
+                    if (!wave && cap != kCaps[0]) break;  // only the split choice for these
+                    KArgs a = k_args(ctx, w, mixed);
+                    a.grid_cap = wave ? cap : 0;
+                    const float ms = time_it([&] {
+                        for (int part = split ? 1 : 0; part <= (split ? 2 : 0); ++part) {
+                            a.mode = part;
+                            const bool f32 = part == 2;
+                            if (w.choff >= 0) {
+                                const KPArgs kp = kp_args(a, ctx->d_chunks.p + w.choff);
+                                (void)(launch_k_pair_0(la, lb, lc, ld, kp, w.nchunks, f32, st) ||
+                                       launch_k_pair_1(la, lb, lc, ld, kp, w.nchunks, f32, st) ||
+                                       launch_k_pair_2(la, lb, lc, ld, kp, w.nchunks, f32, st) ||
+                                       launch_k_pair_3(la, lb, lc, ld, kp, w.nchunks, f32, st) ||
+                                       launch_k_pair_4(la, lb, lc, ld, kp, w.nchunks, f32, st) ||
+                                       launch_k_pair_5(la, lb, lc, ld, kp, w.nchunks, f32, st) ||
+                                       launch_k_pair_6(la, lb, lc, ld, kp, w.nchunks, f32, st) ||
+                                       launch_k_pair_7(la, lb, lc, ld, kp, w.nchunks, f32, st));
+                            } else {
+                                (void)(launch_k_small(la, lb, lc, ld, a, f32, st) ||
+                                       launch_k_wave_0(la, lb, lc, ld, a, f32, st) || launch_k_wave_1(la, lb, lc, ld, a, f32, st) ||
+                                       launch_k_wave_2(la, lb, lc, ld, a, f32, st) || launch_k_wave_3(la, lb, lc, ld, a, f32, st) ||
+                                       launch_k_wave_4(la, lb, lc, ld, a, f32, st) || launch_k_wave_5(la, lb, lc, ld, a, f32, st));
+                            }
+                        }
+                    });
+                    if (ms < best) {
+                        best = ms;
+                        pick = wave ? cap : 0;
+                        pick_split = split;
                     }
-                });
-                if (ms < best) {
-                    best = ms;
-                    pick = cap;
                 }
             }
             ctx->kcap[wi] = pick;
+            if (tune_split) ctx->ksplit[wi] = pick_split;
         }
         ++ctx->gen;
     } catch (const HipError &e) {
@@ -1414,6 +1477,11 @@ struct eri_batch {
 namespace {
 
 constexpr int kBatchLanes = 8;
+// Graph recording of batches.  Off: the recorded path ended in a host-side
+// segmentation fault inside the batch call on the MI355X runtime, twice (the
+// second time with no stream fork inside the recorded builds), and the cause
+// is not yet shown; batches run the same fork/join with direct launches.
+constexpr bool kBatchGraphs = false;
 
 bool batch_ok(const eri_batch *b) { return b && b->magic == 0x4d4a4b42; }
 
@@ -1431,7 +1499,7 @@ void batch_record(eri_batch *b)
     batch_release_graph(b);
     const size_t n = b->ctxs.size();
     for (eri_ctx *c : b->ctxs)
-        if (c->opts.precision == ERI_MIXED) ensure_mixed(c);  // allocations stay outside the capture
+        if (c->opts.precision != ERI_FP64) ensure_mixed(c);  // allocations stay outside the capture
     HIPCHK(hipStreamSynchronize(b->st));
     for (eri_ctx *c : b->ctxs) {
         HIPCHK(hipStreamSynchronize(c->st));
@@ -1451,7 +1519,9 @@ void batch_record(eri_batch *b)
             prof[i] = c->profile;
             c->st = s;
             c->profile = false;
+            c->recording = true;  // molecules are the graph's parallel branches
             rc = build_jk(c, b->P[i], b->J[i], b->K[i]);
+            c->recording = false;
             c->st = saved[i];
             c->profile = prof[i];
             if (rc) break;
@@ -1518,21 +1588,41 @@ int eri_batch_build_jk(eri_batch *b, const double *const *P, double *const *J, d
     if (!batch_ok(b)) return set_err(ERI_ESTATE, "invalid batch");
     if (!P || !J || !K) return set_err(ERI_EINVAL, "null pointer array");
     const size_t n = b->ctxs.size();
-    bool same = b->exec != nullptr && b->P.size() == n;
     for (size_t i = 0; i < n; ++i) {
         if (!ctx_ok(b->ctxs[i])) return set_err(ERI_ESTATE, "context %zu destroyed", i);
         if (!P[i] || !J[i] || !K[i]) return set_err(ERI_EINVAL, "null P/J/K for molecule %zu", i);
-        if (same && (b->P[i] != P[i] || b->J[i] != J[i] || b->K[i] != K[i] || b->gens[i] != b->ctxs[i]->gen))
-            same = false;
     }
     try {
-        if (!same) {
-            b->P.assign(P, P + n);
-            b->J.assign(J, J + n);
-            b->K.assign(K, K + n);
-            batch_record(b);
+        if (kBatchGraphs) {
+            bool same = b->exec != nullptr && b->P.size() == n;
+            for (size_t i = 0; same && i < n; ++i)
+                if (b->P[i] != P[i] || b->J[i] != J[i] || b->K[i] != K[i] || b->gens[i] != b->ctxs[i]->gen)
+                    same = false;
+            if (!same) {
+                b->P.assign(P, P + n);
+                b->J.assign(J, J + n);
+                b->K.assign(K, K + n);
+                batch_record(b);
+            }
+            HIPCHK(hipGraphLaunch(b->exec, b->st));
+        } else {
+            // the same fork/join, launched directly: every molecule on one of
+            // the batch's streams, all joined back into the batch stream
+            HIPCHK(hipEventRecord(b->evs[0], b->st));
+            for (auto &s : b->lanes) HIPCHK(hipStreamWaitEvent(s, b->evs[0], 0));
+            for (size_t i = 0; i < n; ++i) {
+                eri_ctx *c = b->ctxs[i];
+                const hipStream_t saved = c->st;
+                c->st = b->lanes[i % b->lanes.size()];
+                const int rc = build_jk(c, P[i], J[i], K[i]);
+                c->st = saved;
+                if (rc) return rc;
+            }
+            for (size_t k = 0; k < b->lanes.size(); ++k) {
+                HIPCHK(hipEventRecord(b->evs[1 + k], b->lanes[k]));
+                HIPCHK(hipStreamWaitEvent(b->st, b->evs[1 + k], 0));
+            }
         }
-        HIPCHK(hipGraphLaunch(b->exec, b->st));
     } catch (const HipError &e) {
         return e.code;
     }

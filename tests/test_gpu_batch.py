@@ -1,5 +1,5 @@
-"""GPU batches (one recorded HIP graph for many molecules) and the launch-shape
-autotuner: every molecule's J and K from a batch replay must equal its own
+"""GPU batches of many molecules and the launch-shape autotuner: every
+molecule's J and K from a batch must equal its own
 build_jk (same kernels; only the order of floating-point atomic additions
 may differ, so the bar is 1e-13 relative), on every replay, with the
 program's own eager work and synchronisations between replays; the
@@ -33,6 +33,12 @@ def _close(X, Xr, tag):
     assert err <= RTOL * scale, (tag, err, scale)
 
 
+GRAPH_SKIP = ("batch graph recording is switched off: the recorded batch ended in a host-side segmentation "
+              "fault inside eri_batch_build_jk on the MI355X runtime (twice, also without the per-context stream "
+              "fork inside the recording) and the cause is not yet shown; kept for when it is re-enabled")
+
+
+@pytest.mark.skip(reason=GRAPH_SKIP)
 def test_batch_replays_match_standalone():
     torch = _torch()
     from paper_2406_14920_amd import JK, Batch
@@ -60,6 +66,7 @@ def test_batch_replays_match_standalone():
         jk.close()
 
 
+@pytest.mark.skip(reason=GRAPH_SKIP)
 def test_batch_rerecords_on_change():
     torch = _torch()
     from paper_2406_14920_amd import JK, Batch
@@ -91,7 +98,33 @@ def test_batch_rerecords_on_change():
         jk.close()
 
 
-@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_batch_direct_launches_match_standalone():
+    """Batches as they run now: every molecule's build launched on one of the
+    batch's streams, joined back; repeated calls with eager work between."""
+    torch = _torch()
+    from paper_2406_14920_amd import JK, Batch
+    mols = _mols(6)
+    print("  sizes:", [m.nbf for m in mols], flush=True)
+    jks = [JK.from_molecule(m) for m in mols]
+    jks[2].set_precision("mixed")
+    Ps = [torch.tensor(m.P, dtype=torch.float64, device="cuda") for m in mols]
+    ref = [tuple(t.clone() for t in jk.jk(P)) for jk, P in zip(jks, Ps)]
+    torch.cuda.synchronize()
+    b = Batch(jks)
+    for rep in range(2):
+        J, K = b.jk(Ps)
+        torch.cuda.synchronize()
+        for i in range(len(mols)):
+            _close(J[i], ref[i][0], "J rep %d mol %d" % (rep, i))
+            _close(K[i], ref[i][1], "K rep %d mol %d" % (rep, i))
+        junk = torch.randn(256, 256, device="cuda", dtype=torch.float64)
+        (junk @ junk).sum().item()
+    b.close()
+    for jk in jks:
+        jk.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed", "mixed_all"])
 def test_autotune_keeps_results(precision):
     torch = _torch()
     from paper_2406_14920_amd import JK
@@ -105,6 +138,11 @@ def test_autotune_keeps_results(precision):
     assert set(tun["kcap"]) <= {0, 1024, 4096, 16384, 32768, 131072}
     J1, K1 = jk.jk(P)
     torch.cuda.synchronize()
-    _close(J1, J0, "J after autotune")
-    _close(K1, K0, "K after autotune")
+    if precision == "mixed":
+        # the tuner may move launches between the FP32 share and FP64: both
+        # results are mixed results, held to the mixed bar against each other
+        assert float((J1 - J0).abs().max()) <= 1e-6 and float((K1 - K0).abs().max()) <= 1e-6
+    else:
+        _close(J1, J0, "J after autotune")
+        _close(K1, K0, "K after autotune")
     jk.close()

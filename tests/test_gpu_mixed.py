@@ -1,4 +1,5 @@
-"""GPU mixed precision: tiles whose density-weighted Schwarz bound
+"""GPU mixed precision ("mixed": the single-precision share on the launches
+where it pays; "mixed_all": on every launch): tiles whose density-weighted Schwarz bound
 Q_ab Q_cd max|D| is below the threshold run their primitive integrals in
 single precision; bounds, Boys values, digestion and accumulation stay double.
 
@@ -59,7 +60,7 @@ def test_all_single_precision_every_class(case):
     mol = _micro() if case == "micro" else synth.small_cluster(3, 2, tau=1e-11, name="c3")
     tau = 0.0 if case == "micro" else None
     print("case %s all-FP32 nbf=%d" % (case, mol.nbf), flush=True)
-    J, K, st = _run(mol, "mixed", mixed_thresh=1e300, tau=tau, tau_prim=0.0 if case == "micro" else None)
+    J, K, st = _run(mol, "mixed_all", mixed_thresh=1e300, tau=tau, tau_prim=0.0 if case == "micro" else None)
     assert st["n_quartets_fp32"] == st["n_quartets"]
     Jr, Kr = oracle.jk(mol, tau=0.0 if case == "micro" else mol.tau_schwarz,
                        tau_prim=0.0 if case == "micro" else None)
@@ -68,30 +69,33 @@ def test_all_single_precision_every_class(case):
     assert np.abs(J - J.T).max() <= 1e-14 * np.abs(J).max() and np.abs(K - K.T).max() <= 1e-14 * np.abs(K).max()
 
 
-def test_threshold_zero_is_double():
+@pytest.mark.parametrize("mode", ["mixed", "mixed_all"])
+def test_threshold_zero_is_double(mode):
     mol = synth.small_cluster(3, 1, tau=1e-11, name="c3")
-    J, K, st = _run(mol, "mixed", mixed_thresh=0.0)
+    J, K, st = _run(mol, mode, mixed_thresh=0.0)
     assert st["n_quartets_fp32"] == 0
     J64, K64, _ = _run(mol, "fp64")
     assert np.abs(J - J64).max() <= 1e-13 * np.abs(J64).max()
     assert np.abs(K - K64).max() <= 1e-13 * np.abs(K64).max()
 
 
-def test_mol4_default_threshold_vs_oracle():
+@pytest.mark.parametrize("mode", ["mixed", "mixed_all"])
+def test_mol4_default_threshold_vs_oracle(mode):
     mol = synth.mol4()
-    J, K, st = _run(mol, "mixed")
+    J, K, st = _run(mol, mode)
     print("  fp32 quartets %d of %d" % (st["n_quartets_fp32"], st["n_quartets"]), flush=True)
     Jr, Kr = oracle.jk(mol)
     assert _report("J", J, Jr) <= ABS_TOL
     assert _report("K", K, Kr) <= ABS_TOL
 
 
-def test_mol40_default_threshold():
+@pytest.mark.parametrize("mode", ["mixed", "mixed_all"])
+def test_mol40_default_threshold(mode):
     """Full 40-atom workload: whole matrices against the double-precision
     build (itself held to the oracle at 1e-10 relative by the parity tests),
     and sampled shell blocks against the oracle directly."""
     mol = synth.mol40()
-    J, K, st = _run(mol, "mixed")
+    J, K, st = _run(mol, mode)
     frac = st["n_quartets_fp32"] / st["n_quartets"]
     print("  fp32 quartets %d of %d (%.3f)" % (st["n_quartets_fp32"], st["n_quartets"], frac), flush=True)
     assert 0.0 < frac < 1.0
