@@ -34,6 +34,8 @@ struct WaveCfg {
     static constexpr int NCDCH = (NCD + CDCH - 1) / CDCH;
     static constexpr int NV = STREAM ? 64 * CDCH : NBLK;
     static constexpr int SB = EprodOff<LA, LB>().off[NAB];
+    // 1D Hermite tables of the bra [i][j][t] per axis (products formed on the fly)
+    static constexpr int EDJ = LAB + 1, EDI = (LB + 1) * EDJ, EBD = (LA + 1) * EDI;
     static constexpr int SK = EprodOff<LC, LD>().off[NCD];
     static constexpr int ND_ = NA * NC + NA * ND + NB * NC + NB * ND;
     static constexpr int RANGE = 8;
@@ -97,7 +99,7 @@ __global__ __launch_bounds__(64) void k_wave(KArgs a)
     __shared__ T sF[L + 1];
     __shared__ T sH[HPolyDims<L>::N];
     __shared__ int sHerm[nherm(L)];
-    __shared__ T sEb[C::SB];
+    __shared__ T sE1[3 * C::EBD];
     __shared__ T sEk[C::SK];
     __shared__ T sV[C::NV];
     __shared__ double sD[C::ND_];
@@ -106,20 +108,13 @@ __global__ __launch_bounds__(64) void k_wave(KArgs a)
     const int lane = threadIdx.x;
     herm_table_lds(sHerm, nherm(L), lane);
 
-    // the bra components this lane owns, their boxes and product offsets
-    int own_m[C::NABCH][3], own_off[C::NABCH];
+    // the bra components this lane owns: their boxes and 1D table offsets
+    int own_m[C::NABCH][3], own_off[C::NABCH][3];
     bool own[C::NABCH];
 #pragma unroll
     for (int r = 0; r < C::NABCH; ++r) {
         const int ab = r * 64 + lane;
         own[r] = ab < NAB;
-        int off = 0;
-        for (int e = 0; e < (own[r] ? ab : 0); ++e) {
-            int x1, y1, z1, x2, y2, z2;
-            cart_rt(LA, e / NB, x1, y1, z1);
-            cart_rt(LB, e % NB, x2, y2, z2);
-            off += (x1 + x2 + 1) * (y1 + y2 + 1) * (z1 + z2 + 1);
-        }
         int ax = 0, ay = 0, az = 0, bx = 0, by = 0, bz = 0;
         if (own[r]) {
             cart_rt(LA, ab / NB, ax, ay, az);
@@ -128,7 +123,9 @@ __global__ __launch_bounds__(64) void k_wave(KArgs a)
         own_m[r][0] = ax + bx + 1;
         own_m[r][1] = ay + by + 1;
         own_m[r][2] = az + bz + 1;
-        own_off[r] = off;
+        own_off[r][0] = ax * C::EDI + bx * C::EDJ;
+        own_off[r][1] = C::EBD + ay * C::EDI + by * C::EDJ;
+        own_off[r][2] = 2 * C::EBD + az * C::EDI + bz * C::EDJ;
     }
 
     const int n = a.ld;
@@ -174,7 +171,16 @@ __global__ __launch_bounds__(64) void k_wave(KArgs a)
             for (int ip = 0; ip < A.np; ++ip) {
                 const PrimPair pb = a.pp[A.poff + ip];
                 if (pb.q * qk0 < a.tau_prim) break;
-                const T *eb = pick<T>(a.eprod_bra, a.eprodf_bra) + (int64_t)(A.poff + ip - a.pbase_bra) * C::SB;
+                // bra 1D tables once per bra primitive (their previous readers
+                // finished at the last barrier of the previous ket loop); the
+                // single-precision form folds K_ab (2p)^{t/2} in (md_device.hpp)
+                if (lane < 3) {
+                    const double pa = lane == 0 ? pb.PA[0] : (lane == 1 ? pb.PA[1] : pb.PA[2]);
+                    const double pbb = lane == 0 ? pb.PB[0] : (lane == 1 ? pb.PB[1] : pb.PB[2]);
+                    const bool f32 = sizeof(T) == 4;
+                    etab_store_scaled<LA, LB, T>(pa, pbb, pb.o2p, (f32 && lane == 0) ? pb.K : 1.0,
+                                                 f32 ? sqrt(2.0 * pb.p) : 1.0, sE1 + lane * C::EBD);
+                }
                 PairLite pk = pair_lite(a.pp + B.poff);
                 for (int kp = 0; kp < B.np; ++kp) {
                     if (pb.q * pk.q < a.tau_prim) break;
@@ -184,7 +190,6 @@ __global__ __launch_bounds__(64) void k_wave(KArgs a)
                     wave_boys<L, T>(g, a.boys, sF, lane);
                     wave_hpoly<L, T>(g, sH, lane);
                     const T *ek = pick<T>(a.eprod_ket, a.eprodf_ket) + (int64_t)(B.poff + kp - a.pbase_ket) * C::SK;
-                    for (int o = lane; o < C::SB; o += 64) sEb[o] = eb[o];
                     for (int o = lane; o < C::SK; o += 64) sEk[o] = ek[o];
                     __syncthreads();
                     wave_r0h<L, T>(sF, sH, sHerm, sR0, lane);
@@ -198,14 +203,15 @@ __global__ __launch_bounds__(64) void k_wave(KArgs a)
                         for (int q = 0; q < nherm(LCD); ++q) Y[q] = T(0);
                         if (own[ch]) {
                             const int mx = own_m[ch][0], my = own_m[ch][1], mz = own_m[ch][2];
-                            const T *e = sEb + own_off[ch];
-                            for (int tx = 0; tx < mx; ++tx)
+                            const T *Ex = sE1 + own_off[ch][0], *Ey = sE1 + own_off[ch][1], *Ez = sE1 + own_off[ch][2];
+                            for (int tx = 0; tx < mx; ++tx) {
+                                const T ex = Ex[tx];
                                 for (int ty = 0; ty < my; ++ty) {
-                                    const T *erow = e + (tx * my + ty) * mz;
+                                    const T exy = ex * Ey[ty];
                                     const T *Rrow = sR0 + (tx * L1 + ty) * L1;
 #pragma unroll 2
                                     for (int tz = 0; tz < mz; ++tz) {
-                                        const T ev = erow[tz];
+                                        const T ev = exy * Ez[tz];
                                         const T *Rb = Rrow + tz;
                                         static_for<0, nherm(LCD)>([&](auto qc) {
                                             constexpr int Q = decltype(qc)::value;
@@ -214,6 +220,7 @@ __global__ __launch_bounds__(64) void k_wave(KArgs a)
                                         });
                                     }
                                 }
+                            }
                             if constexpr (sizeof(T) == 4) {  // ket factor r^|Q| of the scaled form
                                 T rp[LCD + 1];
                                 powers<LCD>((T)g.r, rp);

@@ -333,6 +333,30 @@ __device__ __forceinline__ void wave_r0h(const T *sF, const T *sH, const int *sH
     }
 }
 
+// One axis of the 1D Hermite tables built in registers (eq. E_recursion, in
+// double) and stored to LDS as T with the [i][j][t] layout of etab_lds minus
+// the padding: dims (LA+1, LB+1, LA+LB+1), entries multiplied by k c^t.
+template <int LA, int LB, typename T>
+__device__ __forceinline__ void etab_store_scaled(double PA, double PB, double o2p, double k, double c, T *E)
+{
+    constexpr int DJ = LA + LB + 1, DI = (LB + 1) * DJ;
+    Etab<LA, LB> Tb;
+    etab_build<LA, LB>(PA, PB, o2p, Tb);
+    double w[LA + LB + 1];
+    w[0] = k;
+    for (int t = 1; t <= LA + LB; ++t) w[t] = w[t - 1] * c;
+    static_for<0, LA + 1>([&](auto ic) {
+        constexpr int i = decltype(ic)::value;
+        static_for<0, LB + 1>([&](auto jc) {
+            constexpr int j = decltype(jc)::value;
+            static_for<0, DJ>([&](auto tc) {
+                constexpr int t = decltype(tc)::value;
+                E[i * DI + j * DJ + t] = (T)((t <= i + j) ? Tb.e[i][j][t] * w[t] : 0.0);
+            });
+        });
+    });
+}
+
 // Cartesian exponents of component c of a shell with angular momentum l (runtime).
 __device__ __forceinline__ void cart_rt(int l, int c, int &x, int &y, int &z)
 {
