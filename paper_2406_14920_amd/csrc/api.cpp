@@ -949,7 +949,11 @@ void ensure_grad(eri_ctx *c)
     c->kg_off.assign(c->kwork.size(), 0);
     c->kg_total = 0;
     for (size_t wi = 0; wi < c->kwork.size(); ++wi) {
-        const int64_t ranges = (c->kwork[wi].nwork + kKgRange - 1) / kKgRange;
+        const auto &w = c->kwork[wi];
+        // small classes: a lane per quartet (64 per workgroup step); others a
+        // workgroup per kKgRange quartets
+        const int per = is_k_small(kPairL[w.X][0], kPairL[w.X][1], kPairL[w.Y][0], kPairL[w.Y][1]) ? 64 : kKgRange;
+        const int64_t ranges = (w.nwork + per - 1) / per;
         c->kg_blocks[wi] = (int)std::min<int64_t>(ranges, kKgMaxBlocks);
         c->kg_off[wi] = c->kg_total;
         c->kg_total += c->kg_blocks[wi];

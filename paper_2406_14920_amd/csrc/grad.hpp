@@ -26,6 +26,7 @@
 // written as per-workgroup partials, which a final kernel adds in a fixed
 // order (deterministic).
 #pragma once
+#include "class_lists.hpp"
 #include "kern_args.hpp"
 #include "md_device.hpp"
 #include "wave_r.hpp"
@@ -283,6 +284,275 @@ template <int LA, int LB, int LC, int LD>
 constexpr int kg_ranges_per_block()
 {
     return KGCfg<LA, LB, LC, LD>::RANGE;
+}
+
+}  // namespace md
+
+namespace md {
+
+// ---------------------------------------------------------------------------
+// Exchange gradient for the small classes: one lane per canonical quartet,
+// every table in registers (the same sums as kg_wave, unrolled at compile
+// time).  The 64 lanes of a wavefront stage their twelve centre terms in LDS
+// and lanes owning (atom, axis) entries add them in lane order, so the
+// per-workgroup partials are deterministic.
+// ---------------------------------------------------------------------------
+template <int LA, int LB, int LC, int LD>
+__global__ __launch_bounds__(64) void kg_small(KGArgs g)
+{
+    constexpr int NA = ncart(LA), NB = ncart(LB), NC = ncart(LC), ND = ncart(LD);
+    constexpr int L = LA + LB + LC + LD, LAB = LA + LB;
+    const KArgs &a = g.k;
+    __shared__ double sT[64][13];  // 12 centre terms + valid flag per lane
+    __shared__ int sAt[64][4];
+    extern __shared__ double sG[];  // natom x 3
+    const int lane = threadIdx.x;
+    const int na3 = 3 * g.natom;
+    for (int o = lane; o < na3; o += 64) sG[o] = 0.0;
+
+    for (int64_t wbase = (int64_t)blockIdx.x * 64; wbase < a.nwork; wbase += (int64_t)gridDim.x * 64) {
+        const int64_t w = wbase + lane;
+        double v[12];
+#pragma unroll
+        for (int q = 0; q < 12; ++q) v[q] = 0.0;
+        int at[4] = {0, 0, 0, 0};
+        const bool valid = w < a.nwork;
+        if (valid) {
+            int lo = 0, hi = a.nbra;
+            while (hi - lo > 1) {
+                int mid = (lo + hi) >> 1;
+                if (a.prefix[mid] <= w) lo = mid; else hi = mid;
+            }
+            const int ib = lo, jk = (int)(w - a.prefix[lo]);
+            const CPair A = a.bra[ib], B = a.ket[jk];
+            at[0] = A.at1; at[1] = A.at2; at[2] = B.at1; at[3] = B.at2;
+            double sdeg = 1.0;
+            if (A.sh1 == A.sh2) sdeg *= 0.5;
+            if (B.sh1 == B.sh2) sdeg *= 0.5;
+            if (a.same && ib == jk) sdeg *= 0.5;
+            const int n = a.ld;
+            // weights W_{ab,cd} = -s (D_ac D_bd + D_ad D_bc)
+            double W[NA * NB * NC * ND];
+            static_for<0, NA * NB * NC * ND>([&](auto ec) {
+                constexpr int e = decltype(ec)::value;
+                constexpr int i = e / (NB * NC * ND), j = (e / (NC * ND)) % NB, k = (e / ND) % NC, l = e % ND;
+                W[e] = -sdeg * (a.D[(int64_t)(A.c1 + i) * n + B.c1 + k] * a.D[(int64_t)(A.c2 + j) * n + B.c2 + l] +
+                                a.D[(int64_t)(A.c1 + i) * n + B.c2 + l] * a.D[(int64_t)(A.c2 + j) * n + B.c1 + k]);
+            });
+            double gA[3] = {0, 0, 0}, gS[3] = {0, 0, 0}, gC[3] = {0, 0, 0};
+            const double qk0 = a.pp[B.poff].q;
+            for (int ip = 0; ip < A.np; ++ip) {
+                const PrimPair pb = a.pp[A.poff + ip];
+                if (pb.q * qk0 < a.tau_prim) break;
+                Etab<LA + 1, LB> Ex, Ey, Ez;
+                etab_build<LA + 1, LB>(pb.PA[0], pb.PB[0], pb.o2p, Ex);
+                etab_build<LA + 1, LB>(pb.PA[1], pb.PB[1], pb.o2p, Ey);
+                etab_build<LA + 1, LB>(pb.PA[2], pb.PB[2], pb.o2p, Ez);
+                const double a2 = 2.0 * pb.a;
+                for (int kp = 0; kp < B.np; ++kp) {
+                    const PrimPair pk = a.pp[B.poff + kp];
+                    if (pb.q * pk.q < a.tau_prim) break;
+                    double Fs[L + 2], X, Y, Z;
+                    quartet_fs<L + 1, double>(pb, pk, a.boys, Fs, X, Y, Z);
+                    double R[nherm(L + 1)];
+                    r_build<L + 1, double>(Fs, X, Y, Z, R);
+                    Etab<LC + 1, LD> Fx, Fy, Fz;
+                    etab_build<LC + 1, LD>(pk.PA[0], pk.PB[0], pk.o2p, Fx);
+                    etab_build<LC + 1, LD>(pk.PA[1], pk.PB[1], pk.o2p, Fy);
+                    etab_build<LC + 1, LD>(pk.PA[2], pk.PB[2], pk.o2p, Fz);
+                    const double c2 = 2.0 * pk.a;
+                    static_for<0, NC * ND>([&](auto cdc) {
+                        constexpr int cd = decltype(cdc)::value;
+                        constexpr int c = cd / ND, d = cd % ND;
+                        constexpr int cx = cart_x(LC, c), cy = cart_y(LC, c), cz = cart_z(LC, c);
+                        constexpr int dx = cart_x(LD, d), dy = cart_y(LD, d), dz = cart_z(LD, d);
+                        // X_t = sum_s (-1)^|s| E^{cd}_s R_{t+s}, t in H(LAB+1)
+                        double Xt[nherm(LAB + 1)];
+                        static_for<0, nherm(LAB + 1)>([&](auto pc) {
+                            constexpr int P = decltype(pc)::value;
+                            constexpr int tp = herm_t(P), up = herm_u(P), vp = herm_v(P);
+                            double s = 0.0;
+                            static_for<0, cx + dx + 1>([&](auto sxc) {
+                                constexpr int sx = decltype(sxc)::value;
+                                static_for<0, cy + dy + 1>([&](auto syc) {
+                                    constexpr int sy = decltype(syc)::value;
+                                    static_for<0, cz + dz + 1>([&](auto szc) {
+                                        constexpr int sz = decltype(szc)::value;
+                                        constexpr double sg = ((sx + sy + sz) & 1) ? -1.0 : 1.0;
+                                        s += sg * Fx.e[cx][dx][sx] * Fy.e[cy][dy][sy] * Fz.e[cz][dz][sz] *
+                                             R[herm_idx(tp + sx, up + sy, vp + sz)];
+                                    });
+                                });
+                            });
+                            Xt[P] = s;
+                        });
+                        // Xc^k_t = sum_s (-1)^|s| Ed^{C,k}_s R_{t+s}, t in H(LAB)
+                        double Xc[3][nherm(LAB)];
+                        static_for<0, 3>([&](auto kc) {
+                            constexpr int k = decltype(kc)::value;
+                            static_for<0, nherm(LAB)>([&](auto pc) {
+                                constexpr int P = decltype(pc)::value;
+                                constexpr int tp = herm_t(P), up = herm_u(P), vp = herm_v(P);
+                                double s = 0.0;
+                                static_for<0, cx + dx + 1 + (k == 0)>([&](auto sxc) {
+                                    constexpr int sx = decltype(sxc)::value;
+                                    double ex;
+                                    if constexpr (k == 0) {
+                                        ex = c2 * Fx.e[cx + 1][dx][sx];
+                                        if constexpr (cx > 0 && sx <= cx - 1 + dx) ex -= (double)cx * Fx.e[cx - 1][dx][sx];
+                                    } else {
+                                        ex = Fx.e[cx][dx][sx];
+                                    }
+                                    static_for<0, cy + dy + 1 + (k == 1)>([&](auto syc) {
+                                        constexpr int sy = decltype(syc)::value;
+                                        double ey;
+                                        if constexpr (k == 1) {
+                                            ey = c2 * Fy.e[cy + 1][dy][sy];
+                                            if constexpr (cy > 0 && sy <= cy - 1 + dy) ey -= (double)cy * Fy.e[cy - 1][dy][sy];
+                                        } else {
+                                            ey = Fy.e[cy][dy][sy];
+                                        }
+                                        static_for<0, cz + dz + 1 + (k == 2)>([&](auto szc) {
+                                            constexpr int sz = decltype(szc)::value;
+                                            double ez;
+                                            if constexpr (k == 2) {
+                                                ez = c2 * Fz.e[cz + 1][dz][sz];
+                                                if constexpr (cz > 0 && sz <= cz - 1 + dz) ez -= (double)cz * Fz.e[cz - 1][dz][sz];
+                                            } else {
+                                                ez = Fz.e[cz][dz][sz];
+                                            }
+                                            constexpr double sg = ((sx + sy + sz) & 1) ? -1.0 : 1.0;
+                                            s += sg * ex * ey * ez * R[herm_idx(tp + sx, up + sy, vp + sz)];
+                                        });
+                                    });
+                                });
+                                Xc[k][P] = s;
+                            });
+                        });
+                        // bra side with the weights
+                        static_for<0, NA * NB>([&](auto abc) {
+                            constexpr int ab = decltype(abc)::value;
+                            constexpr int i = ab / NB, j = ab % NB;
+                            constexpr int ax = cart_x(LA, i), ay = cart_y(LA, i), az = cart_z(LA, i);
+                            constexpr int bx = cart_x(LB, j), by = cart_y(LB, j), bz = cart_z(LB, j);
+                            const double w = W[ab * (NC * ND) + cd];
+                            // dA_k: coefficient boxes extended along k
+                            static_for<0, 3>([&](auto kc) {
+                                constexpr int k = decltype(kc)::value;
+                                double s = 0.0;
+                                static_for<0, ax + bx + 1 + (k == 0)>([&](auto txc) {
+                                    constexpr int tx = decltype(txc)::value;
+                                    double fx;
+                                    if constexpr (k == 0) {
+                                        fx = a2 * Ex.e[ax + 1][bx][tx];
+                                        if constexpr (ax > 0 && tx <= ax - 1 + bx) fx -= (double)ax * Ex.e[ax - 1][bx][tx];
+                                    } else {
+                                        fx = Ex.e[ax][bx][tx];
+                                    }
+                                    static_for<0, ay + by + 1 + (k == 1)>([&](auto tyc) {
+                                        constexpr int ty = decltype(tyc)::value;
+                                        double fy;
+                                        if constexpr (k == 1) {
+                                            fy = a2 * Ey.e[ay + 1][by][ty];
+                                            if constexpr (ay > 0 && ty <= ay - 1 + by) fy -= (double)ay * Ey.e[ay - 1][by][ty];
+                                        } else {
+                                            fy = Ey.e[ay][by][ty];
+                                        }
+                                        static_for<0, az + bz + 1 + (k == 2)>([&](auto tzc) {
+                                            constexpr int tz = decltype(tzc)::value;
+                                            double fz;
+                                            if constexpr (k == 2) {
+                                                fz = a2 * Ez.e[az + 1][bz][tz];
+                                                if constexpr (az > 0 && tz <= az - 1 + bz) fz -= (double)az * Ez.e[az - 1][bz][tz];
+                                            } else {
+                                                fz = Ez.e[az][bz][tz];
+                                            }
+                                            s += fx * fy * fz * Xt[herm_idx(tx, ty, tz)];
+                                        });
+                                    });
+                                });
+                                gA[k] += w * s;
+                            });
+                            // (dA + dB) by the index shift, dC from Xc
+                            static_for<0, ax + bx + 1>([&](auto txc) {
+                                constexpr int tx = decltype(txc)::value;
+                                static_for<0, ay + by + 1>([&](auto tyc) {
+                                    constexpr int ty = decltype(tyc)::value;
+                                    static_for<0, az + bz + 1>([&](auto tzc) {
+                                        constexpr int tz = decltype(tzc)::value;
+                                        const double e = w * Ex.e[ax][bx][tx] * Ey.e[ay][by][ty] * Ez.e[az][bz][tz];
+                                        gS[0] += e * Xt[herm_idx(tx + 1, ty, tz)];
+                                        gS[1] += e * Xt[herm_idx(tx, ty + 1, tz)];
+                                        gS[2] += e * Xt[herm_idx(tx, ty, tz + 1)];
+                                        gC[0] += e * Xc[0][herm_idx(tx, ty, tz)];
+                                        gC[1] += e * Xc[1][herm_idx(tx, ty, tz)];
+                                        gC[2] += e * Xc[2][herm_idx(tx, ty, tz)];
+                                    });
+                                });
+                            });
+                        });
+                    });
+                }
+            }
+            for (int k = 0; k < 3; ++k) {
+                v[k] = gA[k];
+                v[3 + k] = gS[k] - gA[k];
+                v[6 + k] = gC[k];
+                v[9 + k] = -gS[k] - gC[k];
+            }
+        }
+        // stage and add in lane order (deterministic)
+#pragma unroll
+        for (int q = 0; q < 12; ++q) sT[lane][q] = v[q];
+        sT[lane][12] = valid ? 1.0 : 0.0;
+        for (int c = 0; c < 4; ++c) sAt[lane][c] = at[c];
+        __syncthreads();
+        for (int o = lane; o < na3; o += 64) {
+            const int atom = o / 3, k = o % 3;
+            double acc = 0.0;
+            for (int l = 0; l < 64; ++l) {
+                if (sT[l][12] == 0.0) continue;
+                for (int c = 0; c < 4; ++c)
+                    if (sAt[l][c] == atom) acc += sT[l][3 * c + k];
+            }
+            sG[o] += acc;
+        }
+        __syncthreads();
+    }
+    for (int o = lane; o < na3; o += 64) g.partial[(int64_t)blockIdx.x * na3 + o] = sG[o];
+}
+
+template <int LA, int LB, int LC, int LD>
+void launch_kg_small_t(const KGArgs &g, int blocks, hipStream_t st)
+{
+    if (blocks <= 0) return;
+    const size_t shm = (size_t)3 * g.natom * sizeof(double);
+    hipLaunchKernelGGL((kg_small<LA, LB, LC, LD>), dim3((unsigned)blocks), dim3(64), shm, st, g);
+}
+
+}  // namespace md
+
+namespace md {
+
+// the lane-per-quartet kernel serves the classes the energy path serves the
+// same way (all their blocks fit in registers)
+template <int LA, int LB, int LC, int LD>
+constexpr bool kg_use_small()
+{
+    bool r = false;
+#define MD_IS(A_, B_, C_, D_) r = r || (LA == A_ && LB == B_ && LC == C_ && LD == D_);
+    MD_K_SMALL_LIST(MD_IS)
+#undef MD_IS
+    return r;
+}
+
+template <int LA, int LB, int LC, int LD>
+void launch_kg_any(const KGArgs &g, int blocks, hipStream_t st)
+{
+    if constexpr (kg_use_small<LA, LB, LC, LD>())
+        launch_kg_small_t<LA, LB, LC, LD>(g, blocks, st);
+    else
+        launch_kg_t<LA, LB, LC, LD>(g, blocks, st);
 }
 
 }  // namespace md

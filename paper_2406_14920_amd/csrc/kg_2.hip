@@ -8,7 +8,7 @@ bool launch_kg_2(int la, int lb, int lc, int ld, const KGArgs &g, int blocks, hi
 {
 #define MD_CASE(A_, B_, C_, D_)                                   \
     if (la == A_ && lb == B_ && lc == C_ && ld == D_) {           \
-        launch_kg_t<A_, B_, C_, D_>(g, blocks, st);               \
+        launch_kg_any<A_, B_, C_, D_>(g, blocks, st);               \
         return true;                                              \
     }
     MD_KG_PART2(MD_CASE)
