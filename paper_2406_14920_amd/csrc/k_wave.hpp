@@ -202,22 +202,31 @@ __global__ __launch_bounds__(64) void k_wave(KArgs a)
 #pragma unroll
                         for (int q = 0; q < nherm(LCD); ++q) Y[q] = T(0);
                         if (own[ch]) {
+                            // the lane's box (tx, ty, tz) walked in one flat loop whose
+                            // trip count is the chunk's largest box, the same for every
+                            // lane (nested per-lane loops would run the union of all
+                            // lanes' boxes)
+                            constexpr int BMAX = box_max(LA, LB, ch * 64, ch * 64 + 64);
                             const int mx = own_m[ch][0], my = own_m[ch][1], mz = own_m[ch][2];
+                            const int nbox = mx * my * mz;
                             const T *Ex = sE1 + own_off[ch][0], *Ey = sE1 + own_off[ch][1], *Ez = sE1 + own_off[ch][2];
-                            for (int tx = 0; tx < mx; ++tx) {
-                                const T ex = Ex[tx];
-                                for (int ty = 0; ty < my; ++ty) {
-                                    const T exy = ex * Ey[ty];
-                                    const T *Rrow = sR0 + (tx * L1 + ty) * L1;
+                            int tx = 0, ty = 0, tz = 0;
 #pragma unroll 2
-                                    for (int tz = 0; tz < mz; ++tz) {
-                                        const T ev = exy * Ez[tz];
-                                        const T *Rb = Rrow + tz;
-                                        static_for<0, nherm(LCD)>([&](auto qc) {
-                                            constexpr int Q = decltype(qc)::value;
-                                            constexpr int qo = (herm_t(Q) * L1 + herm_u(Q)) * L1 + herm_v(Q);
-                                            Y[Q] += ev * Rb[qo];
-                                        });
+                            for (int st = 0; st < BMAX; ++st) {
+                                if (st < nbox) {
+                                    const T ev = Ex[tx] * Ey[ty] * Ez[tz];
+                                    const T *Rb = sR0 + (tx * L1 + ty) * L1 + tz;
+                                    static_for<0, nherm(LCD)>([&](auto qc) {
+                                        constexpr int Q = decltype(qc)::value;
+                                        constexpr int qo = (herm_t(Q) * L1 + herm_u(Q)) * L1 + herm_v(Q);
+                                        Y[Q] += ev * Rb[qo];
+                                    });
+                                }
+                                if (++tz == mz) {
+                                    tz = 0;
+                                    if (++ty == my) {
+                                        ty = 0;
+                                        ++tx;
                                     }
                                 }
                             }

@@ -72,6 +72,18 @@ __host__ __device__ constexpr int box_nnz(int la, int ca, int lb, int cb)
            (cart_z(la, ca) + cart_z(lb, cb) + 1);
 }
 
+// largest box over the pair components ab in [ab0, ab1) (components ab = i NB + j)
+__host__ __device__ constexpr int box_max(int la, int lb, int ab0, int ab1)
+{
+    const int nb = ncart(lb), nab = ncart(la) * nb;
+    int m = 0;
+    for (int ab = ab0; ab < ab1 && ab < nab; ++ab) {
+        const int v = box_nnz(la, ab / nb, lb, ab % nb);
+        if (v > m) m = v;
+    }
+    return m;
+}
+
 // ---------------------------------------------------------------------------
 // Pair records (HBM, array-of-structures, 128 B per primitive pair)
 // ---------------------------------------------------------------------------
