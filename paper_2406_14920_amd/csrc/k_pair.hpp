@@ -40,8 +40,12 @@ struct KPairCfg {
     static constexpr int NAB = NA * NB, NCD = NC * ND;
     static constexpr int L = LA + LB + LC + LD, LAB = LA + LB, LCD = LC + LD;
     static constexpr bool XROUTE = LCD >= 2;  // precontract the ket into X_P
-    // values of type T that fit in about 240 VGPRs next to R, X_P and addresses
-    static constexpr int NREG = sizeof(T) == 4 ? 216 : 120;
+    // register budget (values of type T) for R, X_P and the block chunk.  One
+    // wave per SIMD is the occupancy anyway, so the budget reaches into the
+    // accumulation registers: fewer passes over the primitive quartets beat
+    // the extra register moves and the few spills (budgets 120..300 were
+    // timed per class; (fd|ps) in FP64 is fastest with the smaller one)
+    static constexpr int NREG = sizeof(T) == 4 ? 300 : ((LA == 3 && LB == 2 && LC == 1 && LD == 0) ? 160 : 240);
     static constexpr int BUDGET0 = NREG - nherm(L) - (XROUTE ? nherm(LAB) : 0) - 12;
     static constexpr int BUDGET = BUDGET0 < 12 ? 12 : BUDGET0;
     static constexpr int ABCH = NAB <= BUDGET ? NAB : BUDGET;
@@ -182,48 +186,101 @@ __global__ __launch_bounds__(64) void k_pair(KPArgs a)
             }
         }
 
-        // digest the chunk: K_ac += V D_bd, K_ad += V D_bc, K_bc += V D_ad, K_bd += V D_ac
+        // digest the chunk: K_ac += V D_bd, K_ad += V D_bc, K_bc += V D_ad, K_bd += V D_ac.
+        // Every density element the chunk touches is loaded once, and every
+        // exchange element gets one atomic with the chunk's sum over the other
+        // two indices (instead of one load and one atomic per block element).
         if (valid) {
-            static_for<cd0, cd1>([&](auto cdc) {
-                constexpr int cd = decltype(cdc)::value;
-                constexpr int c = cd / ND, d = cd % ND;
-                static_for<0, NA>([&](auto ic) {
-                    constexpr int i = decltype(ic)::value;
-                    double t13 = 0.0, t14 = 0.0;
+            constexpr int i0 = ab0 / NB, i1 = (ab1 - 1) / NB;
+            constexpr int j0 = i0 < i1 ? 0 : ab0 % NB, j1 = i0 < i1 ? NB - 1 : (ab1 - 1) % NB;
+            constexpr int c0 = cd0 / ND, c1 = (cd1 - 1) / ND;
+            constexpr int d0 = c0 < c1 ? 0 : cd0 % ND, d1 = c0 < c1 ? ND - 1 : (cd1 - 1) % ND;
+            constexpr int ni = i1 - i0 + 1, nj = j1 - j0 + 1, nc = c1 - c0 + 1, nd = d1 - d0 + 1;
+            const double *__restrict__ D = a.D;
+            double Dac[ni * nc], Dad[ni * nd], Dbc[nj * nc], Dbd[nj * nd];
+            static_for<0, ni>([&](auto ic) {
+                constexpr int i = decltype(ic)::value;
+                const double *row = D + (int64_t)(A.c1 + i0 + i) * n;
+                static_for<0, nc>([&](auto cc) { Dac[i * nc + cc] = row[B.c1 + c0 + cc]; });
+                static_for<0, nd>([&](auto dc) { Dad[i * nd + dc] = row[B.c2 + d0 + dc]; });
+            });
+            static_for<0, nj>([&](auto jc) {
+                constexpr int j = decltype(jc)::value;
+                const double *row = D + (int64_t)(A.c2 + j0 + j) * n;
+                static_for<0, nc>([&](auto cc) { Dbc[j * nc + cc] = row[B.c1 + c0 + cc]; });
+                static_for<0, nd>([&](auto dc) { Dbd[j * nd + dc] = row[B.c2 + d0 + dc]; });
+            });
+            // block element (i0+i, j0+j | c0+c, d0+d) if it lies in the chunk
+            auto vget = [&](auto ic, auto jc, auto cc, auto dc, double &v) -> bool {
+                constexpr int ab = (i0 + decltype(ic)::value) * NB + j0 + decltype(jc)::value;
+                constexpr int cd = (c0 + decltype(cc)::value) * ND + d0 + decltype(dc)::value;
+                if constexpr (ab >= ab0 && ab < ab1 && cd >= cd0 && cd < cd1) {
+                    v = (double)V[(ab - ab0) * NCDc + (cd - cd0)];
+                    return true;
+                } else {
+                    return false;
+                }
+            };
+            static_for<0, ni>([&](auto ic) {
+                constexpr int i = decltype(ic)::value;
+                static_for<0, nc>([&](auto cc) {  // K_ac[i][c] = sum_{j,d} V D_bd[j][d]
+                    double t = 0.0;
                     bool any = false;
-                    static_for<0, NB>([&](auto jc) {
-                        constexpr int j = decltype(jc)::value;
-                        constexpr int ab = i * NB + j;
-                        if constexpr (ab >= ab0 && ab < ab1) {
-                            const double v = (double)V[(ab - ab0) * NCDc + (cd - cd0)];
-                            t13 += v * a.D[(int64_t)(A.c2 + j) * n + B.c2 + d];
-                            t14 += v * a.D[(int64_t)(A.c2 + j) * n + B.c1 + c];
-                            any = true;
-                        }
+                    static_for<0, nj>([&](auto jc) {
+                        static_for<0, nd>([&](auto dc) {
+                            double v;
+                            if (vget(ic, jc, cc, dc, v)) {
+                                t += v * Dbd[decltype(jc)::value * nd + decltype(dc)::value];
+                                any = true;
+                            }
+                        });
                     });
-                    if (any) {
-                        unsafeAtomicAdd(&a.Kacc[(int64_t)(A.c1 + i) * n + B.c1 + c], s * t13);
-                        unsafeAtomicAdd(&a.Kacc[(int64_t)(A.c1 + i) * n + B.c2 + d], s * t14);
-                    }
+                    if (any) unsafeAtomicAdd(&a.Kacc[(int64_t)(A.c1 + i0 + i) * n + B.c1 + c0 + cc], s * t);
                 });
-                static_for<0, NB>([&](auto jc) {
-                    constexpr int j = decltype(jc)::value;
-                    double t23 = 0.0, t24 = 0.0;
+                static_for<0, nd>([&](auto dc) {  // K_ad[i][d] = sum_{j,c} V D_bc[j][c]
+                    double t = 0.0;
                     bool any = false;
-                    static_for<0, NA>([&](auto ic) {
-                        constexpr int i = decltype(ic)::value;
-                        constexpr int ab = i * NB + j;
-                        if constexpr (ab >= ab0 && ab < ab1) {
-                            const double v = (double)V[(ab - ab0) * NCDc + (cd - cd0)];
-                            t23 += v * a.D[(int64_t)(A.c1 + i) * n + B.c2 + d];
-                            t24 += v * a.D[(int64_t)(A.c1 + i) * n + B.c1 + c];
-                            any = true;
-                        }
+                    static_for<0, nj>([&](auto jc) {
+                        static_for<0, nc>([&](auto cc) {
+                            double v;
+                            if (vget(ic, jc, cc, dc, v)) {
+                                t += v * Dbc[decltype(jc)::value * nc + decltype(cc)::value];
+                                any = true;
+                            }
+                        });
                     });
-                    if (any) {
-                        unsafeAtomicAdd(&a.Kacc[(int64_t)(A.c2 + j) * n + B.c1 + c], s * t23);
-                        unsafeAtomicAdd(&a.Kacc[(int64_t)(A.c2 + j) * n + B.c2 + d], s * t24);
-                    }
+                    if (any) unsafeAtomicAdd(&a.Kacc[(int64_t)(A.c1 + i0 + i) * n + B.c2 + d0 + dc], s * t);
+                });
+            });
+            static_for<0, nj>([&](auto jc) {
+                constexpr int j = decltype(jc)::value;
+                static_for<0, nc>([&](auto cc) {  // K_bc[j][c] = sum_{i,d} V D_ad[i][d]
+                    double t = 0.0;
+                    bool any = false;
+                    static_for<0, ni>([&](auto ic) {
+                        static_for<0, nd>([&](auto dc) {
+                            double v;
+                            if (vget(ic, jc, cc, dc, v)) {
+                                t += v * Dad[decltype(ic)::value * nd + decltype(dc)::value];
+                                any = true;
+                            }
+                        });
+                    });
+                    if (any) unsafeAtomicAdd(&a.Kacc[(int64_t)(A.c2 + j0 + j) * n + B.c1 + c0 + cc], s * t);
+                });
+                static_for<0, nd>([&](auto dc) {  // K_bd[j][d] = sum_{i,c} V D_ac[i][c]
+                    double t = 0.0;
+                    bool any = false;
+                    static_for<0, ni>([&](auto ic) {
+                        static_for<0, nc>([&](auto cc) {
+                            double v;
+                            if (vget(ic, jc, cc, dc, v)) {
+                                t += v * Dac[decltype(ic)::value * nc + decltype(cc)::value];
+                                any = true;
+                            }
+                        });
+                    });
+                    if (any) unsafeAtomicAdd(&a.Kacc[(int64_t)(A.c2 + j0 + j) * n + B.c2 + d0 + dc], s * t);
                 });
             });
         }
