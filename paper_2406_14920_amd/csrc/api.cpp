@@ -103,6 +103,22 @@ double fl_k_prim(int la, int lb, int lc, int ld)
 double fl_k_digest(int la, int lb, int lc, int ld) { return 8.0 * ncart(la) * ncart(lb) * ncart(lc) * ncart(ld); }
 double fl_j_prim(int lx, int ly) { return fl_boys(lx + ly) + fl_r(lx + ly) + 2.0 * nherm(lx) * nherm(ly); }
 
+bool jeng_is_reg(int lx, int ly) { return lx + ly >= 6 && nherm(lx) + nherm(ly) + 4 * (lx + ly + 1) <= 116; }
+
+// Default ket chunk of a J-engine launch: the largest power of two in
+// [8, 256] that still gives the launch at least 16384 workgroups (one per
+// bra primitive pair, or per 64 of them, times the ket chunks), so that the
+// classes with few bra primitive pairs fill the 256 CUs instead of running
+// long ket loops on a few hundred waves.
+int jeng_default_chunk(int lx, int ly, int npp, int ncp)
+{
+    const bool per_pair = lx + ly > 5 && !jeng_is_reg(lx, ly);
+    const int64_t nx = per_pair ? npp : (npp + 63) / 64;
+    int kc = 256;
+    while (kc > 8 && nx * ((ncp + kc - 1) / kc) < 16384) kc /= 2;
+    return kc;
+}
+
 // ---------------------------------------------------------------------------
 // Boys table: F_m(i h) for m < kBoysNM.  For each grid point the top order
 // (m = 60) is summed from its Kummer series e^{-T} sum_k (2T)^k/(2m+1)...(2m+2k+1)
@@ -494,7 +510,8 @@ void build_pairs(eri_ctx *c)
     c->d_chunks.upload(chunks);
     for (int X = 0; X < kPairClasses; ++X)
         for (int Y = 0; Y < kPairClasses; ++Y) {
-            c->kchunk[X][Y] = 256;
+            c->kchunk[X][Y] = jeng_default_chunk(kPairL[X][0] + kPairL[X][1], kPairL[Y][0] + kPairL[Y][1],
+                                                 c->npp[X], c->ncp[Y]);
             c->jsplit[X][Y] = false;  // FP64 J-engine: Boys and conversions dominate its FP32 share
         }
     c->kcap.assign(c->kwork.size(), 0);
@@ -717,7 +734,6 @@ JArgs j_args(const eri_ctx *c, int X, int Y, bool mixed)
     return a;
 }
 
-bool jeng_is_reg(int lx, int ly) { return lx + ly >= 6 && nherm(lx) + nherm(ly) + 4 * (lx + ly + 1) <= 116; }
 
 void run_j(eri_ctx *c, bool mixed, hipStream_t st)
 {
@@ -1349,7 +1365,7 @@ int eri_autotune(eri_ctx *ctx, const double *P, int32_t reps)
         // where it is faster); ERI_MIXED_ALL and ERI_FP64 have one
         const int prec = ctx->opts.precision;
         const bool tune_split = prec == ERI_MIXED;
-        static const int kChunks[] = {64, 128, 256, 512, 1024};
+        static const int kChunks[] = {8, 16, 32, 64, 128, 256, 512, 1024};
         for (int X = 0; X < kPairClasses; ++X)
             for (int Y = 0; Y < kPairClasses; ++Y) {
                 if (ctx->npp[X] == 0 || ctx->ncp[Y] == 0) continue;

@@ -134,7 +134,7 @@ def test_autotune_keeps_results(precision):
     J0, K0 = jk.jk(P)
     J0, K0 = J0.clone(), K0.clone()
     tun = jk.autotune(P, reps=1)
-    assert set(tun["kchunk"]) <= {64, 128, 256, 512, 1024}
+    assert set(tun["kchunk"]) <= {8, 16, 32, 64, 128, 256, 512, 1024}
     assert set(tun["kcap"]) <= {0, 1024, 4096, 16384, 32768, 131072}
     J1, K1 = jk.jk(P)
     torch.cuda.synchronize()
