@@ -38,7 +38,12 @@ struct WaveCfg {
     static constexpr int EDJ = LAB + 1, EDI = (LB + 1) * EDJ, EBD = (LA + 1) * EDI;
     static constexpr int SK = EprodOff<LC, LD>().off[NCD];
     static constexpr int ND_ = NA * NC + NA * ND + NB * NC + NB * ND;
-    static constexpr int RANGE = 8;
+    // quartets per range: the heaviest classes have the fewest quartets, so
+    // they take short ranges to give the launch enough workgroups
+    static constexpr int RANGE = L >= 11 ? 1 : (L == 10 ? 2 : 8);
+    // ket-first form (k_wave_x) where it was measured faster: blocks in LDS
+    // with at most 10 ket components (larger ket blocks cost it occupancy)
+    static constexpr bool KETFIRST = !STREAM && NCD <= 10;
 };
 
 // Digest of a sub-block (streaming mode): V(ab, cd) = sV[(cd - cdb) * vstride
@@ -295,6 +300,237 @@ __global__ __launch_bounds__(64) void k_wave(KArgs a)
     }
 }
 
+// Ket-first form for the classes whose block fits in LDS.  Per primitive
+// quartet, for each ket component cd (a compile-time round in which every
+// lane takes the same path), lane k owning the bra Hermite index t forms
+//     X_t(cd) += sum_{s in box(cd)} (-1)^{|s|} E^{cd}_s R_{t+s}
+// and keeps the sum in registers over the ket primitive pairs.  After the
+// ket primitives of one bra primitive pair, the lanes owning bra components
+// ab apply the bra transform once:
+//     V(ab, cd) += sum_{t in box(ab)} E^{ab}_t X_t(cd)
+// (eq. eri_formula with the two Hermite sums in the other order), so the
+// bra transform runs per bra primitive pair instead of per primitive quartet.
+template <int LA, int LB, int LC, int LD, typename T>
+__global__ __launch_bounds__(64) void k_wave_x(KArgs a)
+{
+    using C = WaveCfg<LA, LB, LC, LD, T>;
+    constexpr int NA = C::NA, NB = C::NB, NC = C::NC, ND = C::ND;
+    constexpr int NAB = C::NAB, NCD = C::NCD, L = C::L, L1 = C::L1, LAB = C::LAB, LCD = C::LCD;
+    constexpr int NHAB = nherm(LAB), TCH = (NHAB + 63) / 64;
+    constexpr EprodOff<LC, LD> ok{};
+    static_assert(C::KETFIRST, "ket-first form: whole block in LDS, small ket block");
+
+    // R^0 lives during the ket loop, X only between its end and the bra
+    // transform (separated by barriers), so they share one buffer
+    constexpr int NRX = C::NR0 > NCD * NHAB ? C::NR0 : NCD * NHAB;
+    __shared__ T sRX[NRX];
+    T *const sR0 = sRX;
+    T *const sX = sRX;
+    __shared__ T sF[L + 1];
+    __shared__ T sH[HPolyDims<L>::N];
+    __shared__ int sHerm[nherm(L)];
+    __shared__ T sE1[3 * C::EBD];
+    __shared__ T sEk[C::SK];
+    __shared__ T sV[C::NBLK];
+    __shared__ double sD[C::ND_];
+    __shared__ double sK[C::ND_];
+
+    const int lane = threadIdx.x;
+    herm_table_lds(sHerm, nherm(L), lane);
+
+    // bra Hermite indices this lane owns in the ket rounds
+    int tof[TCH];
+    bool town[TCH];
+#pragma unroll
+    for (int r = 0; r < TCH; ++r) {
+        const int t = r * 64 + lane;
+        town[r] = t < NHAB;
+        const int code = c_herm.tuv[town[r] ? t : 0];
+        tof[r] = ((code & 0xff) * L1 + ((code >> 8) & 0xff)) * L1 + (code >> 16);
+    }
+    // bra components this lane owns in the bra transform
+    int own_m[C::NABCH][3], own_off[C::NABCH][3];
+    bool own[C::NABCH];
+#pragma unroll
+    for (int r = 0; r < C::NABCH; ++r) {
+        const int ab = r * 64 + lane;
+        own[r] = ab < NAB;
+        int ax = 0, ay = 0, az = 0, bx = 0, by = 0, bz = 0;
+        if (own[r]) {
+            cart_rt(LA, ab / NB, ax, ay, az);
+            cart_rt(LB, ab % NB, bx, by, bz);
+        }
+        own_m[r][0] = ax + bx + 1;
+        own_m[r][1] = ay + by + 1;
+        own_m[r][2] = az + bz + 1;
+        own_off[r][0] = ax * C::EDI + bx * C::EDJ;
+        own_off[r][1] = C::EBD + ay * C::EDI + by * C::EDJ;
+        own_off[r][2] = 2 * C::EBD + az * C::EDI + bz * C::EDJ;
+    }
+
+    const int n = a.ld;
+    for (int64_t w0 = (int64_t)blockIdx.x * C::RANGE; w0 < a.nwork; w0 += (int64_t)gridDim.x * C::RANGE) {
+        const int64_t w1 = (w0 + C::RANGE < a.nwork) ? w0 + C::RANGE : a.nwork;
+        int lo = 0, hi = a.nbra;
+        while (hi - lo > 1) {
+            int mid = (lo + hi) >> 1;
+            if (a.prefix[mid] <= w0) lo = mid; else hi = mid;
+        }
+        int ib = lo;
+        int jk = (int)(w0 - a.prefix[ib]);
+        for (int64_t w = w0; w < w1; ++w) {
+            if (w > w0) {
+                ++jk;
+                while (a.prefix[ib] + jk >= a.prefix[ib + 1]) {
+                    ++ib;
+                    jk = 0;
+                }
+            }
+            const CPair A = a.bra[ib];
+            const CPair B = a.ket[jk];
+            if (a.mode != 0) {  // uniform over the workgroup
+                const bool need = a.Qbra[ib] * a.Qket[jk] * k_dens_bound(a.Pm, a.nsh, A, B) >= a.tau_mix;
+                if (need != (a.mode == 1)) continue;
+            }
+
+            for (int o = lane; o < C::ND_; o += 64) {
+                int row, col;
+                if (o < NA * NC) { row = A.c1 + o / NC; col = B.c1 + o % NC; }
+                else if (o < NA * NC + NA * ND) { int r = o - NA * NC; row = A.c1 + r / ND; col = B.c2 + r % ND; }
+                else if (o < NA * NC + NA * ND + NB * NC) { int r = o - NA * NC - NA * ND; row = A.c2 + r / NC; col = B.c1 + r % NC; }
+                else { int r = o - NA * NC - NA * ND - NB * NC; row = A.c2 + r / ND; col = B.c2 + r % ND; }
+                sD[o] = a.D[(int64_t)row * n + col];
+                sK[o] = 0.0;
+            }
+            for (int o = lane; o < C::NBLK; o += 64) sV[o] = T(0);
+            __syncthreads();
+
+            const double qk0 = a.pp[B.poff].q;
+            for (int ip = 0; ip < A.np; ++ip) {
+                const PrimPair pb = a.pp[A.poff + ip];
+                if (pb.q * qk0 < a.tau_prim) break;
+                // bra 1D tables of this bra primitive pair (read again only by
+                // the bra transform below, after the ket loop's last barrier)
+                if (lane < 3) {
+                    const double pa = lane == 0 ? pb.PA[0] : (lane == 1 ? pb.PA[1] : pb.PA[2]);
+                    const double pbb = lane == 0 ? pb.PB[0] : (lane == 1 ? pb.PB[1] : pb.PB[2]);
+                    const bool f32 = sizeof(T) == 4;
+                    etab_store_scaled<LA, LB, T>(pa, pbb, pb.o2p, (f32 && lane == 0) ? pb.K : 1.0,
+                                                 f32 ? sqrt(2.0 * pb.p) : 1.0, sE1 + lane * C::EBD);
+                }
+                T X[TCH][NCD];
+#pragma unroll
+                for (int r = 0; r < TCH; ++r)
+#pragma unroll
+                    for (int cd = 0; cd < NCD; ++cd) X[r][cd] = T(0);
+
+                PairLite pk = pair_lite(a.pp + B.poff);
+                for (int kp = 0; kp < B.np; ++kp) {
+                    if (pb.q * pk.q < a.tau_prim) break;
+                    const PairLite pk_next = pair_lite(a.pp + B.poff + (kp + 1 < B.np ? kp + 1 : kp));
+                    const QuartetGeo g = quartet_geo(pb, pk);
+                    wave_boys<L, T>(g, a.boys, sF, lane);
+                    wave_hpoly<L, T>(g, sH, lane);
+                    const T *ek = pick<T>(a.eprod_ket, a.eprodf_ket) + (int64_t)(B.poff + kp - a.pbase_ket) * C::SK;
+                    for (int o = lane; o < C::SK; o += 64) sEk[o] = ek[o];
+                    __syncthreads();
+                    wave_r0h<L, T>(sF, sH, sHerm, sR0, lane);
+                    __syncthreads();
+
+                    T rp[LCD + 1];  // r^|s| of the scaled single-precision form
+                    if constexpr (sizeof(T) == 4) powers<LCD>((T)g.r, rp);
+                    static_for<0, NCD>([&](auto cdc) {
+                        constexpr int cd = decltype(cdc)::value;
+                        constexpr int c = cd / ND, d = cd % ND;
+                        constexpr int nsx = cart_x(LC, c) + cart_x(LD, d) + 1;
+                        constexpr int nsy = cart_y(LC, c) + cart_y(LD, d) + 1;
+                        constexpr int nsz = cart_z(LC, c) + cart_z(LD, d) + 1;
+                        T e[nsx * nsy * nsz];
+                        static_for<0, nsx * nsy * nsz>([&](auto qc) {
+                            constexpr int q = decltype(qc)::value;
+                            constexpr int sx = q / (nsy * nsz), sy = (q / nsz) % nsy, sz = q % nsz;
+                            constexpr T sg = ((sx + sy + sz) & 1) ? T(-1) : T(1);
+                            if constexpr (sizeof(T) == 4)
+                                e[q] = sg * rp[sx + sy + sz] * sEk[ok.off[cd] + q];
+                            else
+                                e[q] = sg * sEk[ok.off[cd] + q];
+                        });
+#pragma unroll
+                        for (int r = 0; r < TCH; ++r) {
+                            if (!town[r]) continue;
+                            const T *Rb = sR0 + tof[r];
+                            T x = T(0);
+                            static_for<0, nsx * nsy * nsz>([&](auto qc) {
+                                constexpr int q = decltype(qc)::value;
+                                constexpr int sx = q / (nsy * nsz), sy = (q / nsz) % nsy, sz = q % nsz;
+                                x += e[q] * Rb[(sx * L1 + sy) * L1 + sz];
+                            });
+                            X[r][cd] += x;
+                        }
+                    });
+                    __syncthreads();
+                    pk = pk_next;
+                }
+
+                // bra transform of this bra primitive pair
+#pragma unroll
+                for (int r = 0; r < TCH; ++r)
+                    if (town[r])
+#pragma unroll
+                        for (int cd = 0; cd < NCD; ++cd) sX[cd * NHAB + r * 64 + lane] = X[r][cd];
+                __syncthreads();
+                static_for<0, C::NABCH>([&](auto chc) {
+                    constexpr int ch = decltype(chc)::value;
+                    const int ab = ch * 64 + lane;
+                    if (own[ch]) {
+                        constexpr int BMAX = box_max(LA, LB, ch * 64, ch * 64 + 64);
+                        const int mx = own_m[ch][0], my = own_m[ch][1], mz = own_m[ch][2];
+                        const int nbox = mx * my * mz;
+                        const T *Ex = sE1 + own_off[ch][0], *Ey = sE1 + own_off[ch][1], *Ez = sE1 + own_off[ch][2];
+                        T v[NCD];
+#pragma unroll
+                        for (int cd = 0; cd < NCD; ++cd) v[cd] = T(0);
+                        int tx = 0, ty = 0, tz = 0;
+                        for (int st = 0; st < BMAX; ++st) {
+                            if (st < nbox) {
+                                const T ev = Ex[tx] * Ey[ty] * Ez[tz];
+                                const T *xr = sX + herm_idx_rt(tx, ty, tz);
+#pragma unroll
+                                for (int cd = 0; cd < NCD; ++cd) v[cd] += ev * xr[cd * NHAB];
+                            }
+                            if (++tz == mz) {
+                                tz = 0;
+                                if (++ty == my) {
+                                    ty = 0;
+                                    ++tx;
+                                }
+                            }
+                        }
+#pragma unroll
+                        for (int cd = 0; cd < NCD; ++cd) sV[cd * NAB + ab] += v[cd];
+                    }
+                });
+                __syncthreads();
+            }
+            digest_full<NA, NB, NC, ND, T>(sV, sD, sK, lane);
+            __syncthreads();
+            double s = 1.0;
+            if (A.sh1 == A.sh2) s *= 0.5;
+            if (B.sh1 == B.sh2) s *= 0.5;
+            if (a.same && ib == jk) s *= 0.5;
+            for (int o = lane; o < C::ND_; o += 64) {
+                int row, col;
+                if (o < NA * NC) { row = A.c1 + o / NC; col = B.c1 + o % NC; }
+                else if (o < NA * NC + NA * ND) { int r = o - NA * NC; row = A.c1 + r / ND; col = B.c2 + r % ND; }
+                else if (o < NA * NC + NA * ND + NB * NC) { int r = o - NA * NC - NA * ND; row = A.c2 + r / NC; col = B.c1 + r % NC; }
+                else { int r = o - NA * NC - NA * ND - NB * NC; row = A.c2 + r / ND; col = B.c2 + r % ND; }
+                unsafeAtomicAdd(&a.Kacc[(int64_t)row * n + col], s * sK[o]);
+            }
+            __syncthreads();
+        }
+    }
+}
+
 template <int LA, int LB, int LC, int LD>
 void launch_k_wave_t(const KArgs &a, bool fp32, hipStream_t st)
 {
@@ -303,10 +539,17 @@ void launch_k_wave_t(const KArgs &a, bool fp32, hipStream_t st)
     const int64_t cap = a.grid_cap > 0 ? a.grid_cap : 32768;
     const int64_t blocks = ranges < cap ? ranges : cap;
     if (blocks <= 0) return;
-    if (fp32)
-        hipLaunchKernelGGL((k_wave<LA, LB, LC, LD, float>), dim3((unsigned)blocks), dim3(64), 0, st, a);
-    else
-        hipLaunchKernelGGL((k_wave<LA, LB, LC, LD, double>), dim3((unsigned)blocks), dim3(64), 0, st, a);
+    if constexpr (!C::KETFIRST) {
+        if (fp32)
+            hipLaunchKernelGGL((k_wave<LA, LB, LC, LD, float>), dim3((unsigned)blocks), dim3(64), 0, st, a);
+        else
+            hipLaunchKernelGGL((k_wave<LA, LB, LC, LD, double>), dim3((unsigned)blocks), dim3(64), 0, st, a);
+    } else {
+        if (fp32)
+            hipLaunchKernelGGL((k_wave_x<LA, LB, LC, LD, float>), dim3((unsigned)blocks), dim3(64), 0, st, a);
+        else
+            hipLaunchKernelGGL((k_wave_x<LA, LB, LC, LD, double>), dim3((unsigned)blocks), dim3(64), 0, st, a);
+    }
 }
 
 }  // namespace md
