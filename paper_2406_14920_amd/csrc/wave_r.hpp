@@ -308,29 +308,54 @@ __device__ __forceinline__ void wave_hpoly(const QuartetGeo &g, T *sH, int lane)
     }
 }
 
+// largest number of closed-form terms (a, b, c) over the Hermite indices
+// k in [k0, k1): (t/2 + 1)(u/2 + 1)(v/2 + 1)
+__host__ __device__ constexpr int r0_terms_max(int k0, int k1)
+{
+    int m = 0;
+    for (int k = k0; k < k1; ++k) {
+        const int v = (herm_t(k) / 2 + 1) * (herm_u(k) / 2 + 1) * (herm_v(k) / 2 + 1);
+        if (v > m) m = v;
+    }
+    return m;
+}
+
 // Phase 2 (after the barrier that publishes sF, sH and sHerm): dense R^0
-// into sR0.  No barrier inside.
+// into sR0.  No barrier inside.  Each lane walks the (a, b, c) terms of its
+// entry in one flat loop whose trip count is the round's largest term
+// count, the same for every lane (nested per-lane loops would run the union
+// of all lanes' term boxes).
 template <int L, typename T>
 __device__ __forceinline__ void wave_r0h(const T *sF, const T *sH, const int *sHerm, T *sR0, int lane)
 {
-    constexpr int L1 = L + 1, H = HPolyDims<L>::H;
+    constexpr int L1 = L + 1, H = HPolyDims<L>::H, NH = nherm(L);
     const T *hx = sH, *hy = sH + L1 * H, *hz = sH + 2 * L1 * H;
-    for (int k = lane; k < nherm(L); k += 64) {
-        const int code = sHerm[k];
-        const int t = code & 0xff, u = (code >> 8) & 0xff, v = code >> 16;
-        T acc = T(0);
-        for (int a = 0; 2 * a <= t; ++a) {
-            const T ha = hx[t * H + a];
-            for (int b = 0; 2 * b <= u; ++b) {
-                const T hab = ha * hy[u * H + b];
-                const int n0 = t + u + v - a - b;
-                T s = T(0);
-                for (int c = 0; 2 * c <= v; ++c) s += hz[v * H + c] * sF[n0 - c];
-                acc += hab * s;
+    static_for<0, (NH + 63) / 64>([&](auto rc) {
+        constexpr int r = decltype(rc)::value;
+        constexpr int TM = r0_terms_max(r * 64, (r * 64 + 64 < NH) ? r * 64 + 64 : NH);
+        const int k = r * 64 + lane;
+        if (k < NH) {
+            const int code = sHerm[k];
+            const int t = code & 0xff, u = (code >> 8) & 0xff, v = code >> 16;
+            const int nb = u / 2 + 1, nc = v / 2 + 1, nterm = (t / 2 + 1) * nb * nc;
+            const T *px = hx + t * H, *py = hy + u * H, *pz = hz + v * H;
+            const T *pf = sF + t + u + v;
+            T acc = T(0);
+            int a = 0, b = 0, c = 0;
+#pragma unroll 2
+            for (int st = 0; st < TM; ++st) {
+                if (st < nterm) acc += px[a] * py[b] * pz[c] * pf[-(a + b + c)];
+                if (++c == nc) {
+                    c = 0;
+                    if (++b == nb) {
+                        b = 0;
+                        ++a;
+                    }
+                }
             }
+            sR0[(t * L1 + u) * L1 + v] = acc;
         }
-        sR0[(t * L1 + u) * L1 + v] = acc;
-    }
+    });
 }
 
 // One axis of the 1D Hermite tables built in registers (eq. E_recursion, in
