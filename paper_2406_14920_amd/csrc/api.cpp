@@ -995,6 +995,9 @@ void run_grad(eri_ctx *c, double *grad)
             if (c->ncp[Y] == 0) continue;
             JArgs a = j_args(c, X, Y, false);
             a.Jh = c->d_Jh1.p + c->jh1_off[X];
+            // one ket chunk: every Jh1 element gets exactly one addition per
+            // launch, so repeated gradients are bitwise identical
+            a.kchunk = c->ncp[Y];
             const int lx = kPairL[X][0] + kPairL[X][1] + 1, ly = kPairL[Y][0] + kPairL[Y][1];
             timed(c, st, cls_name("jeng_grad", kPairL[X][0], kPairL[X][1], kPairL[Y][0], kPairL[Y][1]), -1, 0, 0,
                   [&] {
