@@ -78,20 +78,21 @@ def cpu_baseline(mol, target_s: float = 15.0):
     nsph = 2 * B.l + 1
 
     def draw(k):
-        out = []
-        while len(out) < k:
+        out, have = [], 0
+        while have < k:
             i = rng.integers(len(pairs), size=4 * k)
             j = rng.integers(len(pairs), size=4 * k)
             ok = qp[i] * qp[j] >= tau
-            for x, y in zip(i[ok], j[ok]):
-                out.append((pairs[x, 0], pairs[x, 1], pairs[y, 0], pairs[y, 1]))
-        return np.array(out[:k], np.int32)
+            blk = np.concatenate([pairs[i[ok]], pairs[j[ok]]], axis=1)
+            out.append(blk)
+            have += len(blk)
+        return np.ascontiguousarray(np.concatenate(out)[:k], np.int32)
 
-    q = draw(200)
+    q = draw(20000)  # pilot run sizes the sample to about target_s
     t = time.perf_counter()
     oracle.quartet_batch(B, q, tau_prim)
     dt = time.perf_counter() - t
-    k = int(min(2_000_000, max(400, 200 * target_s / max(dt, 1e-3))))
+    k = int(min(40_000_000, max(20000, 20000 * target_s / max(dt, 1e-3))))
     q = draw(k)
     t = time.perf_counter()
     oracle.quartet_batch(B, q, tau_prim)
