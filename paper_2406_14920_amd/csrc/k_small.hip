@@ -131,73 +131,82 @@ __global__ __launch_bounds__(128) void k_small(KArgs a)
     if (B.sh1 == B.sh2) s *= 0.5;
     if (a.same && ib == jk) s *= 0.5;
 
-    const double *D = a.D;
+    // Each density element is loaded once: the loads could not otherwise be
+    // hoisted past the atomics, and every block element would reload two.
+    const double *__restrict__ D = a.D;
     const int n = a.ld;
     double *Kc = a.Kacc;
-    // K_ac += V D_bd
-    static_for<0, NA>([&](auto ic) {
-        constexpr int i = decltype(ic)::value;
-        static_for<0, NC>([&](auto kc) {
-            constexpr int k = decltype(kc)::value;
-            double acc = 0.0;
-            static_for<0, NB>([&](auto jc) {
-                constexpr int j = decltype(jc)::value;
-                static_for<0, ND>([&](auto lc) {
-                    constexpr int l = decltype(lc)::value;
-                    acc += (double)V[((i * NB + j) * NC + k) * ND + l] * D[(int64_t)(A.c2 + j) * n + B.c2 + l];
-                });
-            });
-            unsafeAtomicAdd(&Kc[(int64_t)(A.c1 + i) * n + B.c1 + k], s * acc);
+    {  // K_ac += V D_bd and K_ad += V D_bc (density rows of the second bra shell)
+        double Dbd[NB * ND], Dbc[NB * NC];
+        static_for<0, NB>([&](auto jc) {
+            constexpr int j = decltype(jc)::value;
+            const double *row = D + (int64_t)(A.c2 + j) * n;
+            static_for<0, ND>([&](auto lc) { Dbd[j * ND + lc] = row[B.c2 + lc]; });
+            static_for<0, NC>([&](auto kc) { Dbc[j * NC + kc] = row[B.c1 + kc]; });
         });
-    });
-    // K_ad += V D_bc
-    static_for<0, NA>([&](auto ic) {
-        constexpr int i = decltype(ic)::value;
-        static_for<0, ND>([&](auto lc) {
-            constexpr int l = decltype(lc)::value;
-            double acc = 0.0;
+        static_for<0, NA>([&](auto ic) {
+            constexpr int i = decltype(ic)::value;
+            static_for<0, NC>([&](auto kc) {
+                constexpr int k = decltype(kc)::value;
+                double acc = 0.0;
+                static_for<0, NB>([&](auto jc) {
+                    constexpr int j = decltype(jc)::value;
+                    static_for<0, ND>([&](auto lc) {
+                        constexpr int l = decltype(lc)::value;
+                        acc += (double)V[((i * NB + j) * NC + k) * ND + l] * Dbd[j * ND + l];
+                    });
+                });
+                unsafeAtomicAdd(&Kc[(int64_t)(A.c1 + i) * n + B.c1 + k], s * acc);
+            });
+            static_for<0, ND>([&](auto lc) {
+                constexpr int l = decltype(lc)::value;
+                double acc = 0.0;
+                static_for<0, NB>([&](auto jc) {
+                    constexpr int j = decltype(jc)::value;
+                    static_for<0, NC>([&](auto kc) {
+                        constexpr int k = decltype(kc)::value;
+                        acc += (double)V[((i * NB + j) * NC + k) * ND + l] * Dbc[j * NC + k];
+                    });
+                });
+                unsafeAtomicAdd(&Kc[(int64_t)(A.c1 + i) * n + B.c2 + l], s * acc);
+            });
+        });
+    }
+    {  // K_bc += V D_ad and K_bd += V D_ac, one density row of the first bra shell at a time
+        double acc_bc[NB * NC], acc_bd[NB * ND];
+#pragma unroll
+        for (int o = 0; o < NB * NC; ++o) acc_bc[o] = 0.0;
+#pragma unroll
+        for (int o = 0; o < NB * ND; ++o) acc_bd[o] = 0.0;
+        static_for<0, NA>([&](auto ic) {
+            constexpr int i = decltype(ic)::value;
+            const double *row = D + (int64_t)(A.c1 + i) * n;
+            double Dad[ND], Dac[NC];
+            static_for<0, ND>([&](auto lc) { Dad[lc] = row[B.c2 + lc]; });
+            static_for<0, NC>([&](auto kc) { Dac[kc] = row[B.c1 + kc]; });
             static_for<0, NB>([&](auto jc) {
                 constexpr int j = decltype(jc)::value;
                 static_for<0, NC>([&](auto kc) {
                     constexpr int k = decltype(kc)::value;
-                    acc += (double)V[((i * NB + j) * NC + k) * ND + l] * D[(int64_t)(A.c2 + j) * n + B.c1 + k];
+                    static_for<0, ND>([&](auto lc) {
+                        constexpr int l = decltype(lc)::value;
+                        const double v = (double)V[((i * NB + j) * NC + k) * ND + l];
+                        acc_bc[j * NC + k] += v * Dad[l];
+                        acc_bd[j * ND + l] += v * Dac[k];
+                    });
                 });
             });
-            unsafeAtomicAdd(&Kc[(int64_t)(A.c1 + i) * n + B.c2 + l], s * acc);
         });
-    });
-    // K_bc += V D_ad
-    static_for<0, NB>([&](auto jc) {
-        constexpr int j = decltype(jc)::value;
-        static_for<0, NC>([&](auto kc) {
-            constexpr int k = decltype(kc)::value;
-            double acc = 0.0;
-            static_for<0, NA>([&](auto ic) {
-                constexpr int i = decltype(ic)::value;
-                static_for<0, ND>([&](auto lc) {
-                    constexpr int l = decltype(lc)::value;
-                    acc += (double)V[((i * NB + j) * NC + k) * ND + l] * D[(int64_t)(A.c1 + i) * n + B.c2 + l];
-                });
+        static_for<0, NB>([&](auto jc) {
+            constexpr int j = decltype(jc)::value;
+            static_for<0, NC>([&](auto kc) {
+                unsafeAtomicAdd(&Kc[(int64_t)(A.c2 + j) * n + B.c1 + kc], s * acc_bc[j * NC + kc]);
             });
-            unsafeAtomicAdd(&Kc[(int64_t)(A.c2 + j) * n + B.c1 + k], s * acc);
-        });
-    });
-    // K_bd += V D_ac
-    static_for<0, NB>([&](auto jc) {
-        constexpr int j = decltype(jc)::value;
-        static_for<0, ND>([&](auto lc) {
-            constexpr int l = decltype(lc)::value;
-            double acc = 0.0;
-            static_for<0, NA>([&](auto ic) {
-                constexpr int i = decltype(ic)::value;
-                static_for<0, NC>([&](auto kc) {
-                    constexpr int k = decltype(kc)::value;
-                    acc += (double)V[((i * NB + j) * NC + k) * ND + l] * D[(int64_t)(A.c1 + i) * n + B.c1 + k];
-                });
+            static_for<0, ND>([&](auto lc) {
+                unsafeAtomicAdd(&Kc[(int64_t)(A.c2 + j) * n + B.c2 + lc], s * acc_bd[j * ND + lc]);
             });
-            unsafeAtomicAdd(&Kc[(int64_t)(A.c2 + j) * n + B.c2 + l], s * acc);
         });
-    });
+    }
 }
 
 bool launch_k_small(int la, int lb, int lc, int ld, const KArgs &a, bool fp32, hipStream_t st)
