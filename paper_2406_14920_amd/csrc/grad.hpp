@@ -51,6 +51,22 @@ struct KGCfg {
 };
 
 // Derivative coefficient along one axis: 2a E^{i+1,j}_t - i E^{i-1,j}_t.
+// largest Hermite box of a pair class with one axis extended by one (the
+// derivative boxes), over all components and axes
+__host__ __device__ constexpr int box_max_ext(int la, int lb)
+{
+    int m = 0;
+    for (int ca = 0; ca < ncart(la); ++ca)
+        for (int cb = 0; cb < ncart(lb); ++cb) {
+            const int nx = cart_x(la, ca) + cart_x(lb, cb) + 1, ny = cart_y(la, ca) + cart_y(lb, cb) + 1,
+                      nz = cart_z(la, ca) + cart_z(lb, cb) + 1;
+            const int v = (nx + 1) * ny * nz > nx * (ny + 1) * nz ? (nx + 1) * ny * nz : nx * (ny + 1) * nz;
+            const int w = v > nx * ny * (nz + 1) ? v : nx * ny * (nz + 1);
+            if (w > m) m = w;
+        }
+    return m;
+}
+
 __device__ __forceinline__ double dcoef(const double *E, int DI, int DJ, int i, int j, int t, double a2)
 {
     double v = a2 * E[(i + 1) * DI + j * DJ + t];
@@ -166,18 +182,27 @@ __global__ __launch_bounds__(64) void kg_wave(KGArgs g)
                                       mz = cz + dz + 1 + (kdir == 2);
                             const double *Ex = sEk, *Ey = sEk + C::EKD, *Ez = sEk + 2 * C::EKD;
                             double acc = 0.0;
-                            for (int sx = 0; sx < mx; ++sx) {
-                                const double ex = kdir == 0 ? dcoef(Ex, C::EKI, C::EKJ, cx, dx, sx, c2)
-                                                            : Ex[cx * C::EKI + dx * C::EKJ + sx];
-                                for (int sy = 0; sy < my; ++sy) {
+                            // one flat loop over the (possibly extended) ket box, trip
+                            // count the class's largest box for every lane
+                            constexpr int KBM = box_max_ext(LC, LD);
+                            const int nbox = mx * my * mz;
+                            int sx = 0, sy = 0, sz = 0;
+                            for (int st = 0; st < KBM; ++st) {
+                                if (st < nbox) {
+                                    const double ex = kdir == 0 ? dcoef(Ex, C::EKI, C::EKJ, cx, dx, sx, c2)
+                                                                : Ex[cx * C::EKI + dx * C::EKJ + sx];
                                     const double ey = kdir == 1 ? dcoef(Ey, C::EKI, C::EKJ, cy, dy, sy, c2)
                                                                 : Ey[cy * C::EKI + dy * C::EKJ + sy];
-                                    const double exy = ex * ey;
-                                    for (int sz = 0; sz < mz; ++sz) {
-                                        const double ez = kdir == 2 ? dcoef(Ez, C::EKI, C::EKJ, cz, dz, sz, c2)
-                                                                    : Ez[cz * C::EKI + dz * C::EKJ + sz];
-                                        const double sg = ((sx + sy + sz) & 1) ? -1.0 : 1.0;
-                                        acc += sg * exy * ez * sR0[((tx + sx) * L2 + ty + sy) * L2 + tz + sz];
+                                    const double ez = kdir == 2 ? dcoef(Ez, C::EKI, C::EKJ, cz, dz, sz, c2)
+                                                                : Ez[cz * C::EKI + dz * C::EKJ + sz];
+                                    const double sg = ((sx + sy + sz) & 1) ? -1.0 : 1.0;
+                                    acc += sg * ex * ey * ez * sR0[((tx + sx) * L2 + ty + sy) * L2 + tz + sz];
+                                }
+                                if (++sz == mz) {
+                                    sz = 0;
+                                    if (++sy == my) {
+                                        sy = 0;
+                                        ++sx;
                                     }
                                 }
                             }
@@ -204,32 +229,45 @@ __global__ __launch_bounds__(64) void kg_wave(KGArgs g)
                             }
                             const double *Ex = sEb, *Ey = sEb + C::EBD, *Ez = sEb + 2 * C::EBD;
                             const int ex_ = ax + bx, ey_ = ay + by, ez_ = az + bz;
-                            // d/dA: boxes extended by one along the derivative axis
+                            // d/dA: boxes extended by one along the derivative axis, each
+                            // walked in one flat loop of the class's largest extended box
+                            constexpr int BBM = box_max_ext(LA, LB);
                             for (int k = 0; k < 3; ++k) {
                                 double s = 0.0;
-                                for (int tx = 0; tx <= ex_ + (k == 0); ++tx) {
-                                    const double fx = k == 0 ? dcoef(Ex, C::EBI, C::EBJ, ax, bx, tx, a2)
-                                                             : Ex[ax * C::EBI + bx * C::EBJ + tx];
-                                    for (int ty = 0; ty <= ey_ + (k == 1); ++ty) {
+                                const int mx = ex_ + 1 + (k == 0), my = ey_ + 1 + (k == 1), mz = ez_ + 1 + (k == 2);
+                                const int nbox = mx * my * mz;
+                                int tx = 0, ty = 0, tz = 0;
+                                for (int st = 0; st < BBM; ++st) {
+                                    if (st < nbox) {
+                                        const double fx = k == 0 ? dcoef(Ex, C::EBI, C::EBJ, ax, bx, tx, a2)
+                                                                 : Ex[ax * C::EBI + bx * C::EBJ + tx];
                                         const double fy = k == 1 ? dcoef(Ey, C::EBI, C::EBJ, ay, by, ty, a2)
                                                                  : Ey[ay * C::EBI + by * C::EBJ + ty];
-                                        for (int tz = 0; tz <= ez_ + (k == 2); ++tz) {
-                                            const double fz = k == 2 ? dcoef(Ez, C::EBI, C::EBJ, az, bz, tz, a2)
-                                                                     : Ez[az * C::EBI + bz * C::EBJ + tz];
-                                            const double *xr = sX + herm_idx_rt(tx, ty, tz);
-                                            double acc = 0.0;
+                                        const double fz = k == 2 ? dcoef(Ez, C::EBI, C::EBJ, az, bz, tz, a2)
+                                                                 : Ez[az * C::EBI + bz * C::EBJ + tz];
+                                        const double *xr = sX + herm_idx_rt(tx, ty, tz);
+                                        double acc = 0.0;
 #pragma unroll
-                                            for (int c = 0; c < CDCH; ++c) acc += wv[c] * xr[c * NHX];
-                                            s += fx * fy * fz * acc;
+                                        for (int c = 0; c < CDCH; ++c) acc += wv[c] * xr[c * NHX];
+                                        s += fx * fy * fz * acc;
+                                    }
+                                    if (++tz == mz) {
+                                        tz = 0;
+                                        if (++ty == my) {
+                                            ty = 0;
+                                            ++tx;
                                         }
                                     }
                                 }
                                 gA[k] += s;
                             }
                             // (d/dA + d/dB) by the index shift, d/dC from Xc
-                            for (int tx = 0; tx <= ex_; ++tx)
-                                for (int ty = 0; ty <= ey_; ++ty)
-                                    for (int tz = 0; tz <= ez_; ++tz) {
+                            {
+                                constexpr int BM = box_max(LA, LB, 0, NAB);
+                                const int mx = ex_ + 1, my = ey_ + 1, mz = ez_ + 1, nbox = mx * my * mz;
+                                int tx = 0, ty = 0, tz = 0;
+                                for (int st = 0; st < BM; ++st) {
+                                    if (st < nbox) {
                                         const double e = Ex[ax * C::EBI + bx * C::EBJ + tx] *
                                                          Ey[ay * C::EBI + by * C::EBJ + ty] *
                                                          Ez[az * C::EBI + bz * C::EBJ + tz];
@@ -247,6 +285,15 @@ __global__ __launch_bounds__(64) void kg_wave(KGArgs g)
                                             gC[k] += e * ac;
                                         }
                                     }
+                                    if (++tz == mz) {
+                                        tz = 0;
+                                        if (++ty == my) {
+                                            ty = 0;
+                                            ++tx;
+                                        }
+                                    }
+                                }
+                            }
                         }
                         __syncthreads();
                     }
