@@ -13,7 +13,8 @@
 // done once per range.  T is the arithmetic type of the primitive integrals
 // (LDS tables and the block); the density tiles, the digestion and the
 // exchange tiles are double precision.  In the mixed mode a quartet is one
-// precision tile.
+// precision tile.  Most classes use the ket-first form k_wave_x below; this
+// bra-first kernel serves the rest (KETFIRST in WaveCfg).
 #pragma once
 #include "k_pair.hpp"
 #include "kern_args.hpp"
@@ -41,9 +42,10 @@ struct WaveCfg {
     // quartets per range: the heaviest classes have the fewest quartets, so
     // they take short ranges to give the launch enough workgroups
     static constexpr int RANGE = L >= 11 ? 1 : (L == 10 ? 2 : 8);
-    // ket-first form (k_wave_x) where it was measured faster: blocks in LDS
-    // with at most 10 ket components (larger ket blocks cost it occupancy)
-    static constexpr bool KETFIRST = !STREAM && NCD <= 10;
+    // ket-first form (k_wave_x) where it was measured faster: a lane's X
+    // accumulators (bra Hermite rounds x ket components) fit in registers,
+    // and the bra Hermite set (35+ indices for la + lb >= 4) fills the lanes
+    static constexpr bool KETFIRST = LAB >= 4 && ((nherm(LAB) + 63) / 64) * NCD <= 72;
 };
 
 // Digest of a sub-block (streaming mode): V(ab, cd) = sV[(cd - cdb) * vstride
@@ -310,6 +312,8 @@ __global__ __launch_bounds__(64) void k_wave(KArgs a)
 //     V(ab, cd) += sum_{t in box(ab)} E^{ab}_t X_t(cd)
 // (eq. eri_formula with the two Hermite sums in the other order), so the
 // bra transform runs per bra primitive pair instead of per primitive quartet.
+// The lane then digests its block row at once (digestion is linear in the
+// block), so no block buffer is needed and large blocks fit too.
 template <int LA, int LB, int LC, int LD, typename T>
 __global__ __launch_bounds__(64) void k_wave_x(KArgs a)
 {
@@ -318,7 +322,7 @@ __global__ __launch_bounds__(64) void k_wave_x(KArgs a)
     constexpr int NAB = C::NAB, NCD = C::NCD, L = C::L, L1 = C::L1, LAB = C::LAB, LCD = C::LCD;
     constexpr int NHAB = nherm(LAB), TCH = (NHAB + 63) / 64;
     constexpr EprodOff<LC, LD> ok{};
-    static_assert(C::KETFIRST, "ket-first form: whole block in LDS, small ket block");
+    static_assert(C::KETFIRST, "ket-first form: X of a lane fits in registers");
 
     // R^0 lives during the ket loop, X only between its end and the bra
     // transform (separated by barriers), so they share one buffer
@@ -331,7 +335,6 @@ __global__ __launch_bounds__(64) void k_wave_x(KArgs a)
     __shared__ int sHerm[nherm(L)];
     __shared__ T sE1[3 * C::EBD];
     __shared__ T sEk[C::SK];
-    __shared__ T sV[C::NBLK];
     __shared__ double sD[C::ND_];
     __shared__ double sK[C::ND_];
 
@@ -402,7 +405,6 @@ __global__ __launch_bounds__(64) void k_wave_x(KArgs a)
                 sD[o] = a.D[(int64_t)row * n + col];
                 sK[o] = 0.0;
             }
-            for (int o = lane; o < C::NBLK; o += 64) sV[o] = T(0);
             __syncthreads();
 
             const double qk0 = a.pp[B.poff].q;
@@ -506,14 +508,49 @@ __global__ __launch_bounds__(64) void k_wave_x(KArgs a)
                                 }
                             }
                         }
+                        // digest this bra primitive pair's block row ab directly
+                        // (digestion is linear in the block): per exchange element
+                        // one LDS atomic with the row's sum over the other index
+                        const int i = ab / NB, j = ab % NB;
+                        const double *D13 = sD, *D14 = sD + NA * NC, *D23 = D14 + NA * ND, *D24 = D23 + NB * NC;
+                        double *K13 = sK, *K14 = sK + NA * NC, *K23 = K14 + NA * ND, *K24 = K23 + NB * NC;
+                        double d13[NC], d23[NC], d14[ND], d24[ND];
 #pragma unroll
-                        for (int cd = 0; cd < NCD; ++cd) sV[cd * NAB + ab] += v[cd];
+                        for (int k = 0; k < NC; ++k) {
+                            d13[k] = D13[i * NC + k];
+                            d23[k] = D23[j * NC + k];
+                        }
+#pragma unroll
+                        for (int l = 0; l < ND; ++l) {
+                            d14[l] = D14[i * ND + l];
+                            d24[l] = D24[j * ND + l];
+                        }
+#pragma unroll
+                        for (int k = 0; k < NC; ++k) {
+                            double t13 = 0.0, t23 = 0.0;
+#pragma unroll
+                            for (int l = 0; l < ND; ++l) {
+                                t13 += (double)v[k * ND + l] * d24[l];
+                                t23 += (double)v[k * ND + l] * d14[l];
+                            }
+                            atomicAdd(&K13[i * NC + k], t13);
+                            atomicAdd(&K23[j * NC + k], t23);
+                        }
+#pragma unroll
+                        for (int l = 0; l < ND; ++l) {
+                            double t14 = 0.0, t24 = 0.0;
+#pragma unroll
+                            for (int k = 0; k < NC; ++k) {
+                                t14 += (double)v[k * ND + l] * d23[k];
+                                t24 += (double)v[k * ND + l] * d13[k];
+                            }
+                            atomicAdd(&K14[i * ND + l], t14);
+                            atomicAdd(&K24[j * ND + l], t24);
+                        }
                     }
                 });
                 __syncthreads();
             }
-            digest_full<NA, NB, NC, ND, T>(sV, sD, sK, lane);
-            __syncthreads();
             double s = 1.0;
             if (A.sh1 == A.sh2) s *= 0.5;
             if (B.sh1 == B.sh2) s *= 0.5;
