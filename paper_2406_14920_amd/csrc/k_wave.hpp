@@ -330,7 +330,10 @@ __global__ __launch_bounds__(64) void k_wave_x(KArgs a)
     __shared__ T sRX[NRX];
     T *const sR0 = sRX;
     T *const sX = sRX;
-    __shared__ T sF[L + 1];
+    // geometry and scaled Boys values of a batch of ket primitive pairs
+    constexpr int NBAT = 64 / (L + 1);
+    __shared__ T sFb[NBAT * (L + 1)];
+    __shared__ double sGeo[NBAT * 6];
     __shared__ T sH[HPolyDims<L>::N];
     __shared__ int sHerm[nherm(L)];
     __shared__ T sE1[3 * C::EBD];
@@ -426,52 +429,87 @@ __global__ __launch_bounds__(64) void k_wave_x(KArgs a)
 #pragma unroll
                     for (int cd = 0; cd < NCD; ++cd) X[r][cd] = T(0);
 
-                PairLite pk = pair_lite(a.pp + B.poff);
-                for (int kp = 0; kp < B.np; ++kp) {
-                    if (pb.q * pk.q < a.tau_prim) break;
-                    const PairLite pk_next = pair_lite(a.pp + B.poff + (kp + 1 < B.np ? kp + 1 : kp));
-                    const QuartetGeo g = quartet_geo(pb, pk);
-                    wave_boys<L, T>(g, a.boys, sF, lane);
-                    wave_hpoly<L, T>(g, sH, lane);
-                    const T *ek = pick<T>(a.eprod_ket, a.eprodf_ket) + (int64_t)(B.poff + kp - a.pbase_ket) * C::SK;
-                    for (int o = lane; o < C::SK; o += 64) sEk[o] = ek[o];
+                bool screened = false;
+                for (int kb = 0; kb < B.np && !screened; kb += NBAT) {
+                    // one pass for a batch of ket primitive pairs: lane o owns
+                    // (kp, m) = (kb + o / (L + 1), o % (L + 1)) and forms
+                    // pref (-2 alpha)^m F_m (scaled form: pref0 w^m F_m); the
+                    // m = 0 lane also keeps the pair's geometry
+                    {
+                        const int kq = kb + lane / (L + 1), m = lane % (L + 1);
+                        if (lane < NBAT * (L + 1) && kq < B.np) {
+                            const PairLite pq = pair_lite(a.pp + B.poff + kq);
+                            const QuartetGeo gq = quartet_geo(pb, pq);
+                            const double F = boys_one(m, gq.T, a.boys);
+                            double sc = sizeof(T) == 4 ? gq.pref0 : gq.pref;
+                            const double m2a = sizeof(T) == 4 ? gq.w : -2.0 * gq.alpha;
+                            for (int k = 0; k < m; ++k) sc *= m2a;
+                            sFb[(kq - kb) * (L + 1) + m] = (T)(sc * F);
+                            if (m == 0) {
+                                double *o = sGeo + (kq - kb) * 6;
+                                o[0] = gq.X;
+                                o[1] = gq.Y;
+                                o[2] = gq.Z;
+                                o[3] = gq.c;
+                                o[4] = gq.r;
+                                o[5] = pq.q;
+                            }
+                        }
+                    }
                     __syncthreads();
-                    wave_r0h<L, T>(sF, sH, sHerm, sR0, lane);
-                    __syncthreads();
+                    const int ke = (kb + NBAT < B.np) ? kb + NBAT : B.np;
+                    for (int kp = kb; kp < ke; ++kp) {
+                        const double *gk = sGeo + (kp - kb) * 6;
+                        if (pb.q * gk[5] < a.tau_prim) {  // uniform: the pairs are sorted by q
+                            screened = true;
+                            break;
+                        }
+                        QuartetGeo g;
+                        g.X = gk[0];
+                        g.Y = gk[1];
+                        g.Z = gk[2];
+                        g.c = gk[3];
+                        g.r = gk[4];
+                        wave_hpoly<L, T>(g, sH, lane);
+                        const T *ek = pick<T>(a.eprod_ket, a.eprodf_ket) + (int64_t)(B.poff + kp - a.pbase_ket) * C::SK;
+                        for (int o = lane; o < C::SK; o += 64) sEk[o] = ek[o];
+                        __syncthreads();
+                        wave_r0h<L, T>(sFb + (kp - kb) * (L + 1), sH, sHerm, sR0, lane);
+                        __syncthreads();
 
-                    T rp[LCD + 1];  // r^|s| of the scaled single-precision form
-                    if constexpr (sizeof(T) == 4) powers<LCD>((T)g.r, rp);
-                    static_for<0, NCD>([&](auto cdc) {
-                        constexpr int cd = decltype(cdc)::value;
-                        constexpr int c = cd / ND, d = cd % ND;
-                        constexpr int nsx = cart_x(LC, c) + cart_x(LD, d) + 1;
-                        constexpr int nsy = cart_y(LC, c) + cart_y(LD, d) + 1;
-                        constexpr int nsz = cart_z(LC, c) + cart_z(LD, d) + 1;
-                        T e[nsx * nsy * nsz];
-                        static_for<0, nsx * nsy * nsz>([&](auto qc) {
-                            constexpr int q = decltype(qc)::value;
-                            constexpr int sx = q / (nsy * nsz), sy = (q / nsz) % nsy, sz = q % nsz;
-                            constexpr T sg = ((sx + sy + sz) & 1) ? T(-1) : T(1);
-                            if constexpr (sizeof(T) == 4)
-                                e[q] = sg * rp[sx + sy + sz] * sEk[ok.off[cd] + q];
-                            else
-                                e[q] = sg * sEk[ok.off[cd] + q];
-                        });
-#pragma unroll
-                        for (int r = 0; r < TCH; ++r) {
-                            if (!town[r]) continue;
-                            const T *Rb = sR0 + tof[r];
-                            T x = T(0);
+                        T rp[LCD + 1];  // r^|s| of the scaled single-precision form
+                        if constexpr (sizeof(T) == 4) powers<LCD>((T)g.r, rp);
+                        static_for<0, NCD>([&](auto cdc) {
+                            constexpr int cd = decltype(cdc)::value;
+                            constexpr int c = cd / ND, d = cd % ND;
+                            constexpr int nsx = cart_x(LC, c) + cart_x(LD, d) + 1;
+                            constexpr int nsy = cart_y(LC, c) + cart_y(LD, d) + 1;
+                            constexpr int nsz = cart_z(LC, c) + cart_z(LD, d) + 1;
+                            T e[nsx * nsy * nsz];
                             static_for<0, nsx * nsy * nsz>([&](auto qc) {
                                 constexpr int q = decltype(qc)::value;
                                 constexpr int sx = q / (nsy * nsz), sy = (q / nsz) % nsy, sz = q % nsz;
-                                x += e[q] * Rb[(sx * L1 + sy) * L1 + sz];
+                                constexpr T sg = ((sx + sy + sz) & 1) ? T(-1) : T(1);
+                                if constexpr (sizeof(T) == 4)
+                                    e[q] = sg * rp[sx + sy + sz] * sEk[ok.off[cd] + q];
+                                else
+                                    e[q] = sg * sEk[ok.off[cd] + q];
                             });
-                            X[r][cd] += x;
-                        }
-                    });
-                    __syncthreads();
-                    pk = pk_next;
+    #pragma unroll
+                            for (int r = 0; r < TCH; ++r) {
+                                if (!town[r]) continue;
+                                const T *Rb = sR0 + tof[r];
+                                T x = T(0);
+                                static_for<0, nsx * nsy * nsz>([&](auto qc) {
+                                    constexpr int q = decltype(qc)::value;
+                                    constexpr int sx = q / (nsy * nsz), sy = (q / nsz) % nsy, sz = q % nsz;
+                                    x += e[q] * Rb[(sx * L1 + sy) * L1 + sz];
+                                });
+                                X[r][cd] += x;
+                            }
+                        });
+                        __syncthreads();
+                    }
                 }
 
                 // bra transform of this bra primitive pair
