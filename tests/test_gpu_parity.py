@@ -83,6 +83,23 @@ def test_j_only_and_k_only():
     _check(K, Kr, "K only")
 
 
+def test_heavy_contractions_vs_oracle():
+    """A heavy centre (s8 s8 p6 p6 d5 d5 f1) and two light atoms: ket pairs of
+    up to 64 primitive pairs, so the exchange kernels walk their ket
+    primitive loops in several batches and stop inside a batch on the
+    primitive screen; default screening."""
+    xyz = [[0.0, 0.0, 0.0], [3.6, 0.4, -0.3], [-1.2, 3.4, 0.8]]
+    specs = [(0, 0, 8), (0, 0, 8), (0, 1, 6), (0, 1, 6), (0, 2, 5), (0, 2, 5), (0, 3, 1),
+             (1, 0, 6), (1, 0, 3), (1, 1, 3), (1, 2, 1), (1, 3, 1),
+             (2, 0, 6), (2, 1, 3), (2, 2, 1), (2, 3, 1)]
+    mol = synth.custom(xyz, specs, seed=11, tau=1e-12, exp_range=(0.08, 60.0), name="heavy3")
+    print("case heavy3 nbf=%d" % mol.nbf, flush=True)
+    J, K, _ = _gpu_jk(mol)
+    Jr, Kr = oracle.jk(mol)
+    _check(J, Jr, "heavy3 J")
+    _check(K, Kr, "heavy3 K")
+
+
 def test_edge_single_s_shell():
     mol = synth.custom([[0.0, 0.0, 0.0]], [(0, 0, 1)], seed=3, tau=0.0)
     J, K, _ = _gpu_jk(mol, tau=0.0, tau_prim=0.0)
