@@ -326,7 +326,10 @@ __global__ __launch_bounds__(64) void k_wave_x(KArgs a)
 
     // R^0 lives during the ket loop, X only between its end and the bra
     // transform (separated by barriers), so they share one buffer
-    constexpr int NRX = C::NR0 > NCD * NHAB ? C::NR0 : NCD * NHAB;
+    // R^0 at t ST + u SU + v; the t stride is padded by two off the power of
+    // two so that lanes whose indices differ only in t hit different LDS banks
+    constexpr int SU = L1, ST = L1 * L1 + 2, NR0P = L1 * ST;
+    constexpr int NRX = NR0P > NCD * NHAB ? NR0P : NCD * NHAB;
     __shared__ T sRX[NRX];
     T *const sR0 = sRX;
     T *const sX = sRX;
@@ -352,7 +355,7 @@ __global__ __launch_bounds__(64) void k_wave_x(KArgs a)
         const int t = r * 64 + lane;
         town[r] = t < NHAB;
         const int code = c_herm.tuv[town[r] ? t : 0];
-        tof[r] = ((code & 0xff) * L1 + ((code >> 8) & 0xff)) * L1 + (code >> 16);
+        tof[r] = (code & 0xff) * ST + ((code >> 8) & 0xff) * SU + (code >> 16);
     }
     // bra components this lane owns in the bra transform
     int own_m[C::NABCH][3], own_off[C::NABCH][3];
@@ -474,7 +477,7 @@ __global__ __launch_bounds__(64) void k_wave_x(KArgs a)
                         const T *ek = pick<T>(a.eprod_ket, a.eprodf_ket) + (int64_t)(B.poff + kp - a.pbase_ket) * C::SK;
                         for (int o = lane; o < C::SK; o += 64) sEk[o] = ek[o];
                         __syncthreads();
-                        wave_r0h<L, T>(sFb + (kp - kb) * (L + 1), sH, sHerm, sR0, lane);
+                        wave_r0h<L, T, ST, SU>(sFb + (kp - kb) * (L + 1), sH, sHerm, sR0, lane);
                         __syncthreads();
 
                         T rp[LCD + 1];  // r^|s| of the scaled single-precision form
@@ -503,7 +506,7 @@ __global__ __launch_bounds__(64) void k_wave_x(KArgs a)
                                 static_for<0, nsx * nsy * nsz>([&](auto qc) {
                                     constexpr int q = decltype(qc)::value;
                                     constexpr int sx = q / (nsy * nsz), sy = (q / nsz) % nsy, sz = q % nsz;
-                                    x += e[q] * Rb[(sx * L1 + sy) * L1 + sz];
+                                    x += e[q] * Rb[sx * ST + sy * SU + sz];
                                 });
                                 X[r][cd] += x;
                             }

@@ -321,11 +321,11 @@ __host__ __device__ constexpr int r0_terms_max(int k0, int k1)
 }
 
 // Phase 2 (after the barrier that publishes sF, sH and sHerm): dense R^0
-// into sR0.  No barrier inside.  Each lane walks the (a, b, c) terms of its
+// into sR0 at t ST + u SU + v (by default the cube (L+1)^3).  No barrier inside.  Each lane walks the (a, b, c) terms of its
 // entry in one flat loop whose trip count is the round's largest term
 // count, the same for every lane (nested per-lane loops would run the union
 // of all lanes' term boxes).
-template <int L, typename T>
+template <int L, typename T, int ST = (L + 1) * (L + 1), int SU = L + 1>
 __device__ __forceinline__ void wave_r0h(const T *sF, const T *sH, const int *sHerm, T *sR0, int lane)
 {
     constexpr int L1 = L + 1, H = HPolyDims<L>::H, NH = nherm(L);
@@ -353,7 +353,7 @@ __device__ __forceinline__ void wave_r0h(const T *sF, const T *sH, const int *sH
                     }
                 }
             }
-            sR0[(t * L1 + u) * L1 + v] = acc;
+            sR0[t * ST + u * SU + v] = acc;
         }
     });
 }
