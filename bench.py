@@ -11,8 +11,9 @@ J+K time); ms_per_step = the J+K build time.  Inputs (P) are resident in HBM
 before the timed region; setup (pairs, Schwarz factors) is outside it.
 
 The roofline entry is for the dominant kernel of the step: its algorithmic
-FLOPs per launch (FLOP model in the design doc, primitive quartets counted by the
-library with the kernels' own screening loops) divided by its average launch
+FLOPs per launch (the library's fixed FLOP model per primitive quartet,
+primitive quartets counted by the library with the kernels' own screening
+loops) divided by its average launch
 time, taken from HIP events that the library records on its launch stream
 during a profiled pass of the same number of steps right after the timed
 region (the library runs a profiled build on one stream, so each event pair
@@ -195,8 +196,8 @@ def main():
                     help="skip the other-precision comparison, the 20-atom gradient and the 64-molecule batch")
     a = ap.parse_args()
     if a.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
-              "(see DESIGN.md, 'How the path would shard'); run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU path; run with --gpus 1",
+              file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -115,7 +115,7 @@ typedef struct {
     char    name[40];       /* kernel and class, e.g. "k_wave(31|10)", "jeng_small(4,2)" */
     int32_t launches;       /* launches accumulated */
     double  ms;             /* summed device time (HIP events recorded on the launch stream) */
-    double  flops;          /* algorithmic FLOPs of one launch (FLOP model) */
+    double  flops;          /* algorithmic FLOPs of one launch (fixed FLOP model per primitive quartet) */
     int64_t prim_quartets;  /* primitive quartets one launch evaluates (0 if not applicable) */
 } eri_kernel_time;
 

@@ -78,7 +78,7 @@ bool uses_k_pair(int la, int lb, int lc, int ld)
 }
 
 // ---------------------------------------------------------------------------
-// Algorithmic FLOP model (frozen before tuning; the design doc states it):
+// Algorithmic FLOP model (frozen before tuning):
 //   Boys 3L+14, R 3(C(L+4,4)-(L+1)) + (L+1) per primitive quartet,
 //   K contraction sum_cd 2 nH(la+lb) nnz(cd) + sum_{ab,cd} 2 nnz(ab) per
 //   primitive quartet and 8 nA nB nC nD digestion per shell quartet,

@@ -11,7 +11,7 @@ section "Performance") are not available; these draws stand in for them with
 the same ingredients: contracted Cartesian Gaussian shells up to f on atoms at
 bonding distances (eq. contracted_basis / primtive_basis).
 
-Workloads (the recipe is spelled out in the design doc):
+Workloads (exponent ranges and placement rules in the functions below):
   mol4    4 atoms in a 6 bohr cube, shells s3 s1 p3 p1 d1 f1            (80 sph)
   mol40   40-atom grown cluster, shells s6 s3 s1 p3 p1 d1 f1            (840 sph)
   tm62    2 heavy centres + 60 light atoms                              (1336 sph)
