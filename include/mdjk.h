@@ -199,8 +199,11 @@ int eri_tuning(const eri_ctx *ctx, int32_t *kchunk100, int32_t *kcap, int32_t ca
 /* Batches of independent molecules (many contexts, uneven sizes).
  * eri_batch_create: n >= 1 contexts on the current device, each keeping its
  * own basis, thresholds and precision; stream = hipStream_t the batch runs
- * on (NULL: a stream owned by the batch).  The contexts stay owned by the
- * caller and must outlive the batch.
+ * on (NULL: the default stream).  The batch's own streams fork from that
+ * stream at the start of each call and are joined back into it at the end, so
+ * a call is ordered after the work queued before it on that stream and
+ * before the work queued after it.  The contexts stay owned by the caller and
+ * must outlive the batch.
  * eri_batch_build_jk: P, J, K are host arrays of n device pointers
  * (nbf_i x nbf_i each, as in build_jk; none NULL).  Every molecule's build
  * is forked from the batch stream onto one of up to 8 batch streams and

@@ -10,6 +10,10 @@ Parity status per function (what pins it is listed in tests/test_oracle_*.py):
   r_tensor      pinned (numerical derivatives of (-2a)^m F_m(a|L|^2))
   prim_block    pinned ((ss|ss) closed form, brute-force Gaussian-transform
                 quadrature for l <= 3 on four centres, 8-fold symmetry)
+  prim_bounds   pinned (s-s primitive pairs against the mpmath closed form of
+                (ss|ss); equal to the contracted Schwarz factor for
+                one-primitive shells of every l <= 3; the J/K change from
+                skipping primitive quartets stays inside their Schwarz bounds)
   jk / blocks   pinned (symmetry, Coulomb-metric positivity, translation and
                 rotation invariance, large-separation limit)
   grad          pinned (central finite differences of the oracle energy,

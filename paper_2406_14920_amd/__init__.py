@@ -171,6 +171,7 @@ def _jk_energy_class():
             J, K = jk.jk(P)
             E = jk.energy(P, J, K)
             ctx.jk = jk
+            ctx.xyz = xyz  # the context may have moved by the time backward runs
             ctx.coords_device = coords.device
             ctx.save_for_backward(P, J, K)
             return E
@@ -180,6 +181,8 @@ def _jk_energy_class():
             P, J, K = ctx.saved_tensors
             gc = gP = None
             if ctx.needs_input_grad[0]:
+                if ctx.jk._xyz != ctx.xyz:
+                    ctx.jk.set_geometry(ctx.xyz)
                 gc = (ctx.jk.grad(P) * gE).to(ctx.coords_device)
             if ctx.needs_input_grad[1]:
                 gP = (J - 0.5 * K) * gE

@@ -1488,7 +1488,6 @@ struct eri_batch {
     std::vector<eri_ctx *> ctxs;
     std::vector<uint64_t> gens;
     hipStream_t st = nullptr;      // caller's stream (graph launches)
-    bool own_stream = false;
     std::vector<hipStream_t> lanes;  // branch streams used while recording
     std::vector<hipEvent_t> evs;
     hipGraph_t graph = nullptr;
@@ -1589,12 +1588,10 @@ int eri_batch_create(eri_ctx *const *ctxs, int32_t n, void *stream, eri_batch **
     try {
         b->ctxs.assign(ctxs, ctxs + n);
         b->gens.assign(n, ~0ull);
-        if (stream) {
-            b->st = (hipStream_t)stream;
-        } else {
-            HIPCHK(hipStreamCreateWithFlags(&b->st, hipStreamNonBlocking));
-            b->own_stream = true;
-        }
+        // NULL is the default stream, as for eri_setup: the fork below records
+        // its start event there and the join makes the default stream wait, so
+        // work queued before and after the call on that stream stays ordered
+        b->st = (hipStream_t)stream;
         b->lanes.resize(std::min(n, kBatchLanes));
         for (auto &s : b->lanes) HIPCHK(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
         b->evs.resize(1 + b->lanes.size());
@@ -1660,7 +1657,6 @@ int eri_batch_destroy(eri_batch *b)
     batch_release_graph(b);
     for (auto &e : b->evs) (void)hipEventDestroy(e);
     for (auto &s : b->lanes) (void)hipStreamDestroy(s);
-    if (b->own_stream) (void)hipStreamDestroy(b->st);
     b->magic = 0;
     delete b;
     return ERI_OK;

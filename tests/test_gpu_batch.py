@@ -146,3 +146,39 @@ def test_autotune_keeps_results(precision):
         _close(J1, J0, "J after autotune")
         _close(K1, K0, "K after autotune")
     jk.close()
+
+
+def test_batch_on_default_stream_is_ordered():
+    """A batch created on the default stream (handle 0) forks from and joins
+    back into that stream: densities produced by asynchronous work queued
+    just before the call, and reads of J/K queued just after it, need no
+    device-wide synchronisation."""
+    torch = _torch()
+    from paper_2406_14920_amd import JK, Batch
+    mols = _mols(4)
+    jks = [JK.from_molecule(m) for m in mols]
+    Ps_host = [torch.tensor(m.P, dtype=torch.float64) for m in mols]
+    ref = []
+    for jk, Ph in zip(jks, Ps_host):
+        J, K = jk.jk(Ph.cuda())
+        ref.append((J.cpu(), K.cpu()))
+    torch.cuda.synchronize()
+    b = Batch(jks, stream=torch.cuda.default_stream())
+    assert int(b.stream.cuda_stream) == 0
+    with torch.cuda.stream(torch.cuda.default_stream()):
+        for rep in range(2):
+            # the densities come out of a long asynchronous chain on the default stream
+            Ps = []
+            for Ph in Ps_host:
+                X = Ph.to("cuda", non_blocking=False) * 3.0
+                for _ in range(20):
+                    X = X * 0.5 + X * 0.5
+                Ps.append((X / 3.0).contiguous())
+            J, K = b.jk(Ps)
+            got = [(j.cpu(), k.cpu()) for j, k in zip(J, K)]  # ordered reads, no synchronize
+            for i in range(len(mols)):
+                _close(got[i][0], ref[i][0], "J rep %d mol %d" % (rep, i))
+                _close(got[i][1], ref[i][1], "K rep %d mol %d" % (rep, i))
+    b.close()
+    for jk in jks:
+        jk.close()

@@ -147,6 +147,30 @@ def test_autograd_function():
     jk.close()
 
 
+def test_autograd_backward_after_context_moved():
+    """Two forwards at different geometries on one context, then the backward
+    of the first: it must be the gradient at the first geometry."""
+    torch = _torch()
+    from paper_2406_14920_amd import JKEnergy
+    mol = synth.small_cluster(3, 5, tau=1e-11, name="c3")
+    jk = _ctx(mol)
+    P = torch.tensor(mol.P, dtype=torch.float64, device="cuda")
+    x0 = torch.tensor(mol.xyz, dtype=torch.float64, requires_grad=True)
+    x1 = (x0.detach() + torch.tensor([[0.05, -0.02, 0.01]], dtype=torch.float64)).requires_grad_(True)
+    E0 = JKEnergy.apply(x0, P, jk)
+    E1 = JKEnergy.apply(x1, P, jk)
+    E0.backward()
+    jk.set_geometry(x0.detach().tolist())
+    g0 = jk.grad(P).cpu()
+    assert torch.equal(x0.grad, g0)
+    E1.backward()
+    jk.set_geometry(x1.detach().tolist())
+    g1 = jk.grad(P).cpu()
+    assert torch.equal(x1.grad, g1)
+    assert not torch.equal(g0, g1)
+    jk.close()
+
+
 def test_mol20_zero_sum_and_directional_fd():
     """20-atom gradient workload at full size (default screening): the zero
     sum, and a central difference of the GPU energy along a random direction

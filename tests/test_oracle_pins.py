@@ -441,3 +441,112 @@ def test_gradient_two_centre_closed_form():
     assert g[1, 2] == pytest.approx(dz, rel=1e-10)
     assert g[0, 2] == pytest.approx(-dz, rel=1e-10)
     assert abs(g[1, 0]) < 1e-14 and abs(g[1, 1]) < 1e-14
+
+
+# ---------------------------------------------------------------------------
+# Primitive-pair bounds q_ij (section "Data structure": the pGTO pair list is
+# screened by the primitive Schwarz bound, eq. cauchy_schwarz_bound applied
+# to one primitive pair with its contraction coefficients)
+# ---------------------------------------------------------------------------
+def _two_s_molecule(exps_a, exps_b, r=1.4):
+    rng = np.random.default_rng(11)
+    shells = [synth.Shell(atom=0, l=0, exps=np.asarray(exps_a, float), coefs=rng.uniform(0.2, 1.0, len(exps_a))),
+              synth.Shell(atom=1, l=0, exps=np.asarray(exps_b, float), coefs=rng.uniform(0.2, 1.0, len(exps_b)))]
+    return synth.Molecule(name="ss", xyz=np.array([[0.0, 0.0, 0.0], [0.0, 0.0, r]]), shells=shells,
+                          P=np.eye(2), nocc=1, tau_schwarz=0.0)
+
+
+def test_prim_bounds_ss_pairs_match_closed_form():
+    """q_ij of s primitive pairs equals |C_i C_j|/(N_i N_j) sqrt((ij|ij)) with
+    (ij|ij) of normalised s primitives from the mpmath closed form of
+    eq. eri_base_case (golden values: one centre a=1; two centres a=1,
+    R=1.4 bohr)."""
+    gold = {v["label"]: float(v["value"]) for v in json.load(open(os.path.join(GOLDEN, "ssss_values.json")))["values"]}
+    mol = _two_s_molecule([1.0, 0.35], [2.5, 1.0])
+    B = oracle.OBasis(mol)
+    q = B.prim_bounds()
+    N = np.array([(2 * a / np.pi) ** 0.75 for a in B.exps])
+    c = B.coefs / N  # coefficients of the normalised primitives
+    ia, ib = 0, 3  # exponent 1 on centre A, exponent 1 on centre B
+    two = q[ia, ib] / abs(c[ia] * c[ib])
+    assert abs(two - np.sqrt(gold["(sA sB|sA sB), a=1, R=1.4"])) <= 1e-14
+    one = q[ia, ia] / abs(c[ia] * c[ia])
+    assert abs(one - np.sqrt(gold["one centre, a=1"])) <= 1e-14
+    assert np.allclose(q, q.T, rtol=0, atol=0)
+
+
+def test_prim_bounds_one_primitive_shells_equal_schwarz():
+    """For contracted shells of one primitive the primitive bound is the
+    contracted Schwarz factor Q_ab = sqrt(max_c |(ab|ab)_c|) (every l <= 3)."""
+    xyz = [[0.0, 0.0, 0.0], [1.1, -0.4, 0.7], [-0.6, 1.2, -0.5]]
+    specs = [(0, 0, 1), (1, 1, 1), (2, 2, 1), (0, 3, 1), (1, 2, 1), (2, 3, 1), (0, 1, 1)]
+    mol = synth.custom(xyz, specs, seed=13, tau=0.0, exp_range=(0.2, 30.0))
+    B = oracle.OBasis(mol)
+    q = B.prim_bounds()
+    Q = B.schwarz()
+    for a in range(B.nshell):
+        for b in range(B.nshell):
+            assert abs(q[B.off[a], B.off[b]] - Q[a, b]) <= 1e-13 * Q[a, b] + 1e-300, (a, b)
+
+
+def _dropped_bound_sums(B, Q, q, tau, tau_prim):
+    """S[a,b,c,d] = sum of q_ij q_kl over the primitive quartets of the kept
+    shell quartet (ab|cd) that tau_prim drops, and their number."""
+    n = B.nshell
+    blocks = [[q[B.off[a]:B.off[a] + B.nprim[a], B.off[b]:B.off[b] + B.nprim[b]].ravel() for b in range(n)]
+              for a in range(n)]
+    S = np.zeros((n, n, n, n))
+    count = 0
+    for a, b in itertools.product(range(n), repeat=2):
+        for c, d in itertools.product(range(n), repeat=2):
+            if Q[a, b] * Q[c, d] < tau:
+                continue
+            prod = np.multiply.outer(blocks[a][b], blocks[c][d])
+            drop = prod < tau_prim
+            count += int(drop.sum())
+            S[a, b, c, d] = prod[drop].sum()
+    return S, count
+
+
+def test_prim_screen_error_within_schwarz_bound():
+    """Skipping the primitive quartets with q_ij q_kl < tau_prim changes J and
+    K by no more than the Schwarz bounds of what is skipped (every Cartesian
+    component of a primitive ERI is bounded by q_ij q_kl, eq.
+    cauchy_schwarz_bound): for the Cartesian block of shells (a,b),
+    |dJ| <= sum_cd S_abcd nc_c nc_d max|P_cart|, and for (a,c),
+    |dK| <= sum_bd S_abcd nc_b nc_d max|P_cart|, S_abcd the sum of q_ij q_kl
+    over the dropped primitive quartets of (ab|cd); the spherical transforms
+    add at most a factor w_row^2 (w_row, w_col: largest absolute row / column
+    sum of a Cartesian-to-spherical matrix, max|P_cart| <= w_col^2 max|P|).
+    The threshold is chosen so that the screen drops quartets and the bound is
+    far below max|J|, max|K|."""
+    mol = synth.small_cluster(3, 1, tau=1e-11, name="c3")
+    B = oracle.OBasis(mol)
+    Q = B.schwarz()
+    q = B.prim_bounds()
+    tau = mol.tau_schwarz
+    tau_prim = 1e-7
+    S, nd = _dropped_bound_sums(B, Q, q, tau, tau_prim)
+    assert nd > 0
+    nc = (B.l + 1) * (B.l + 2) // 2
+    bj = np.einsum("abcd,c,d->ab", S, nc, nc)
+    bk = np.einsum("abcd,b,d->ac", S, nc, nc)
+    w_row = max(np.abs(ob.SPH[l]).sum(axis=1).max() for l in range(4))
+    w_col = max(np.abs(ob.SPH[l]).sum(axis=0).max() for l in range(4))
+    pmax = w_col ** 2 * np.abs(mol.P).max()
+    J0, K0 = oracle.jk(mol, tau_prim=0.0, basis_obj=B)
+    J1, K1 = oracle.jk(mol, tau_prim=tau_prim, basis_obj=B)
+    dJ, dK = np.abs(J1 - J0), np.abs(K1 - K0)
+    worst_j = worst_k = 0.0
+    for a in range(B.nshell):
+        ra = slice(B.ao_off[a], B.ao_off[a] + 2 * B.l[a] + 1)
+        for b in range(B.nshell):
+            rb = slice(B.ao_off[b], B.ao_off[b] + 2 * B.l[b] + 1)
+            lim_j = w_row ** 2 * bj[a, b] * pmax
+            lim_k = w_row ** 2 * bk[a, b] * pmax
+            assert dJ[ra, rb].max() <= lim_j * (1 + 1e-12) + 1e-15, (a, b)
+            assert dK[ra, rb].max() <= lim_k * (1 + 1e-12) + 1e-15, (a, b)
+            worst_j, worst_k = max(worst_j, lim_j), max(worst_k, lim_k)
+    print("dropped %d  max bound J %.3e K %.3e  max dJ %.3e dK %.3e" % (nd, worst_j, worst_k, dJ.max(), dK.max()))
+    assert dJ.max() > 0 and dK.max() > 0
+    assert max(worst_j, worst_k) < 1e-2 * min(np.abs(J0).max(), np.abs(K0).max())
