@@ -19,6 +19,9 @@ Parity status per function (what pins it is listed in tests/test_oracle_*.py):
   grad          pinned (central finite differences of the oracle energy,
                 zero sum over atoms, analytic two-centre derivative)
   spherical     convention pinned by S_sph = I and rotation invariance
+  omega > 0     pinned (erf(omega r)/r blocks against the Gaussian-transform
+                quadrature cut at t = omega and an mpmath closed form of the
+                attenuated (ss|ss); the large-omega limit is the 1/r result)
 """
 from __future__ import annotations
 
@@ -76,8 +79,27 @@ def lib():
         L.oracle_quartet_batch.argtypes = bas + [dp, ip] + qp + [ctypes.c_int64, ip]
         L.oracle_quartet_batch.restype = ctypes.c_double
         L.oracle_num_threads.restype = ctypes.c_int
+        L.oracle_set_omega.argtypes = [ctypes.c_double]
+        L.oracle_set_omega.restype = None
+        L.oracle_get_omega.restype = ctypes.c_double
         _lib = L
     return _lib
+
+
+class _Omega:
+    """Context: the two-electron operator erf(omega r)/r (omega > 0) or 1/r
+    (omega = 0) for the oracle calls inside it (eqs. eri_longrange_definition,
+    eri_longrange_formula)."""
+
+    def __init__(self, omega: float):
+        self.omega = float(omega)
+
+    def __enter__(self):
+        self.saved = lib().oracle_get_omega()
+        lib().oracle_set_omega(self.omega)
+
+    def __exit__(self, *exc):
+        lib().oracle_set_omega(self.saved)
 
 
 def _dp(a):
@@ -111,14 +133,16 @@ def r_tensor(Lt: int, alpha: float, L) -> np.ndarray:
     return out.reshape(n, n, n)
 
 
-def prim_block(ls, exps, centres) -> np.ndarray:
-    """Primitive Cartesian ERI block of unnormalised monomials."""
+def prim_block(ls, exps, centres, omega: float = 0.0) -> np.ndarray:
+    """Primitive Cartesian ERI block of unnormalised monomials (operator
+    erf(omega r)/r if omega > 0, else 1/r)."""
     la, lb, lc, ld = ls
     nc = [(l + 1) * (l + 2) // 2 for l in ls]
     out = np.zeros(int(np.prod(nc)))
     e = np.ascontiguousarray(exps, float)
     c = np.ascontiguousarray(centres, float).reshape(12)
-    lib().oracle_prim_block(la, lb, lc, ld, _dp(e), _dp(c), _dp(out))
+    with _Omega(omega):
+        lib().oracle_prim_block(la, lb, lc, ld, _dp(e), _dp(c), _dp(out))
     return out.reshape(nc)
 
 
@@ -176,7 +200,8 @@ class OBasis:
         if self._qp is None:
             n = int(self.exps.size)
             q = np.zeros((n, n))
-            lib().oracle_prim_bounds(*self.args(), _dp(q))
+            with _Omega(0.0):  # screening bounds of 1/r, whatever the operator
+                lib().oracle_prim_bounds(*self.args(), _dp(q))
             self._qp = q
         return self._qp
 
@@ -187,7 +212,8 @@ class OBasis:
     def schwarz(self) -> np.ndarray:
         if self._Q is None:
             Q = np.zeros((self.nshell, self.nshell))
-            lib().oracle_schwarz(*self.args(), _dp(Q))
+            with _Omega(0.0):
+                lib().oracle_schwarz(*self.args(), _dp(Q))
             self._Q = Q
         return self._Q
 
@@ -202,22 +228,24 @@ def _tau_prim(tau, tau_prim):
 
 
 def jk(mol, P=None, tau=None, want_j=True, want_k=True, tau_prim=None,
-       basis_obj=None) -> Tuple[np.ndarray, np.ndarray]:
-    """Full J and K (spherical basis) by the plain definition."""
+       basis_obj=None, omega: float = 0.0) -> Tuple[np.ndarray, np.ndarray]:
+    """Full J and K (spherical basis) by the plain definition; operator
+    erf(omega r)/r if omega > 0 (screening by the 1/r bounds)."""
     B = basis_obj or OBasis(mol)
     P = _sym(mol.P if P is None else P)
     tau = mol.tau_schwarz if tau is None else tau
     Q = B.schwarz()
     J = np.zeros((B.nbf, B.nbf))
     K = np.zeros((B.nbf, B.nbf))
-    lib().oracle_jk(*B.args(), _dp(B.T), _ip(B.Toff), _ip(B.ao_off), B.nbf, _dp(P), _dp(Q),
-                    *B.screen_args(_tau_prim(tau, tau_prim)),
-                    float(tau), int(want_j), int(want_k), _dp(J), _dp(K))
+    sa = B.screen_args(_tau_prim(tau, tau_prim))
+    with _Omega(omega):
+        lib().oracle_jk(*B.args(), _dp(B.T), _ip(B.Toff), _ip(B.ao_off), B.nbf, _dp(P), _dp(Q),
+                        *sa, float(tau), int(want_j), int(want_k), _dp(J), _dp(K))
     return J, K
 
 
 def jk_blocks(mol, jpairs: Sequence[Tuple[int, int]], kpairs: Sequence[Tuple[int, int]],
-              P=None, tau=None, basis_obj=None, tau_prim=None):
+              P=None, tau=None, basis_obj=None, tau_prim=None, omega: float = 0.0):
     """Shell blocks J[a,b] and K[a,c] for sampled shell pairs."""
     B = basis_obj or OBasis(mol)
     P = _sym(mol.P if P is None else P)
@@ -228,9 +256,11 @@ def jk_blocks(mol, jpairs: Sequence[Tuple[int, int]], kpairs: Sequence[Tuple[int
     sizes = [(2 * B.l[x] + 1) * (2 * B.l[y] + 1) for x, y in list(jp) + list(kp)]
     offs = np.concatenate([[0], np.cumsum(sizes)[:-1]]).astype(np.int64) if sizes else np.zeros(0, np.int64)
     out = np.zeros(int(sum(sizes)) if sizes else 1)
-    lib().oracle_jk_blocks(*B.args(), _dp(B.T), _ip(B.Toff), _ip(B.ao_off), B.nbf, _dp(P), _dp(Q),
-                           *B.screen_args(_tau_prim(tau, tau_prim)), float(tau), len(jp), _ip(jp), len(kp), _ip(kp),
-                           offs.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), _dp(out))
+    sa = B.screen_args(_tau_prim(tau, tau_prim))
+    with _Omega(omega):
+        lib().oracle_jk_blocks(*B.args(), _dp(B.T), _ip(B.Toff), _ip(B.ao_off), B.nbf, _dp(P), _dp(Q),
+                               *sa, float(tau), len(jp), _ip(jp), len(kp), _ip(kp),
+                               offs.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), _dp(out))
     res = []
     for t, (x, y) in enumerate(list(jp) + list(kp)):
         nx, ny = 2 * B.l[x] + 1, 2 * B.l[y] + 1
@@ -245,7 +275,7 @@ def energy(mol, J, K, P=None) -> float:
 
 
 def grad(mol, P=None, tau=None, wj=1.0, wk=1.0, only_atom=-1, Q=None, tau_prim=None,
-         qprim=None) -> np.ndarray:
+         qprim=None, omega: float = 0.0) -> np.ndarray:
     """dE/dR (natom x 3) of E = wj/2 tr(PJ) - wk/4 tr(PK) at fixed P."""
     B = OBasis(mol)
     if qprim is not None:
@@ -254,8 +284,10 @@ def grad(mol, P=None, tau=None, wj=1.0, wk=1.0, only_atom=-1, Q=None, tau_prim=N
     tau = mol.tau_schwarz if tau is None else tau
     Q = B.schwarz() if Q is None else np.ascontiguousarray(Q, float)
     g = np.zeros((B.natom, 3))
-    lib().oracle_grad(*B.args(), _dp(B.T), _ip(B.Toff), _ip(B.ao_off), B.nbf, _dp(P), _dp(Q),
-                      *B.screen_args(_tau_prim(tau, tau_prim)), float(tau), float(wj), float(wk), int(only_atom), _dp(g))
+    sa = B.screen_args(_tau_prim(tau, tau_prim))
+    with _Omega(omega):
+        lib().oracle_grad(*B.args(), _dp(B.T), _ip(B.Toff), _ip(B.ao_off), B.nbf, _dp(P), _dp(Q),
+                          *sa, float(tau), float(wj), float(wk), int(only_atom), _dp(g))
     return g
 
 

@@ -21,6 +21,10 @@
  *     si_dE_K_step1) by differentiating every basis function centre:
  *     d/dA_x [(x-A_x)^i e^{-a(x-A_x)^2}] = 2a (x-A_x)^{i+1} e - i (x-A_x)^{i-1} e.
  *
+ * The range-separated operator erf(omega r)/r (eqs. eri_longrange_definition,
+ * eri_longrange_formula) replaces 1/r when oracle_set_omega(omega > 0) is in
+ * effect; the screening bounds are always those of 1/r (see oracle/__init__.py).
+ *
  * The screening rule is part of the result's definition: a shell quartet
  * (ab|cd) enters iff Q_ab * Q_cd >= tau, with Q_ab = sqrt(max over Cartesian
  * components of |(ab|ab)|) (eq. cauchy_schwarz_bound at contracted-shell level);
@@ -172,6 +176,16 @@ typedef struct {
     double H[2 * OR_MAXL + 2][2 * OR_MAXL + 2][2 * OR_MAXL + 2];
 } scratch_t;
 
+/* Two-electron operator: omega = 0 is the Coulomb operator 1/r of eq.
+ * eri_formula; omega > 0 is the long-range operator erf(omega r)/r of eq.
+ * eri_longrange_definition, whose integrals (eq. eri_longrange_formula) take
+ * the prefactor 2 pi^{5/2} omega / (pq sqrt(pq + p omega^2 + q omega^2)) and
+ * R^0 at the exponent pq omega^2 / (pq + p omega^2 + q omega^2).  Set before
+ * a parallel call and left unchanged during it. */
+static double g_omega = 0.0;
+void oracle_set_omega(double omega) { g_omega = omega; }
+double oracle_get_omega(void) { return g_omega; }
+
 static void prim_block(int la, int lb, int lc, int ld,
                        double a, double b, double c, double d,
                        const double *A, const double *B, const double *C, const double *D,
@@ -184,8 +198,15 @@ static void prim_block(int la, int lb, int lc, int ld,
         Q[k] = (c * C[k] + d * D[k]) / q;
         PQ[k] = P[k] - Q[k];
     }
-    double alpha = p * q / (p + q);
-    double pref = scale * 2.0 * pow(OR_PI, 2.5) / (p * q * sqrt(p + q));
+    double alpha, pref;
+    if (g_omega > 0.0) { /* eq. eri_longrange_formula */
+        double w2 = g_omega * g_omega, den = p * q + p * w2 + q * w2;
+        alpha = p * q * w2 / den;
+        pref = scale * 2.0 * pow(OR_PI, 2.5) * g_omega / (p * q * sqrt(den));
+    } else {             /* eq. eri_formula */
+        alpha = p * q / (p + q);
+        pref = scale * 2.0 * pow(OR_PI, 2.5) / (p * q * sqrt(p + q));
+    }
     for (int k = 0; k < 3; ++k) {
         e_coeffs(la, lb, a, b, A[k], B[k], S->Eab[k]);
         e_coeffs(lc, ld, c, d, C[k], D[k], S->Ecd[k]);

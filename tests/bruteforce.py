@@ -8,6 +8,7 @@ integrals of polynomials (one per Cartesian axis).  Each 2D integral is done
 exactly by tensor Gauss-Hermite quadrature after completing the square; the
 remaining 1D integral over t is mapped to u in [0,1) by t = sqrt(rho) u/sqrt(1-u^2)
 (rho = pq/(p+q)), where the integrand is smooth, and done by Gauss-Legendre.
+The long-range operator erf(omega r)/r is the same transform cut at t = omega.
 
 Used only by the oracle pins.
 """
@@ -41,14 +42,20 @@ def _axis_integral(i, j, k, l, a, b, c, d, A, B, C, D, t):
     return np.exp(c0) / np.prod(np.diag(R)) * np.sum(w * f)
 
 
-def eri_monomial(ijk_a, ijk_b, ijk_c, ijk_d, a, b, c, d, A, B, C, D):
-    """(ab|cd) of unnormalised monomial Gaussians x^i y^j z^k e^{-a r^2}."""
+def eri_monomial(ijk_a, ijk_b, ijk_c, ijk_d, a, b, c, d, A, B, C, D, omega=None):
+    """(ab|cd) of unnormalised monomial Gaussians x^i y^j z^k e^{-a r^2}.
+    With omega, the operator is erf(omega r)/r = (2/sqrt(pi)) int_0^omega
+    exp(-t^2 r^2) dt: the same integrand over t in [0, omega] (Gauss-Legendre
+    on the finite interval)."""
     p, q = a + b, c + d
     rho = p * q / (p + q)
     total = 0.0
     for u, wu in zip(_GL_U, _GL_WU):
-        t = np.sqrt(rho) * u / np.sqrt(1.0 - u * u)
-        dt = np.sqrt(rho) * (1.0 - u * u) ** -1.5
+        if omega is None:
+            t = np.sqrt(rho) * u / np.sqrt(1.0 - u * u)
+            dt = np.sqrt(rho) * (1.0 - u * u) ** -1.5
+        else:
+            t, dt = omega * u, omega
         prod = 1.0
         for ax in range(3):
             prod *= _axis_integral(ijk_a[ax], ijk_b[ax], ijk_c[ax], ijk_d[ax],

@@ -384,21 +384,24 @@ def test_screening_rule_is_applied():
 # ---------------------------------------------------------------------------
 # Gradient (SI eqs. si_E_J_K, si_dE_J_step1, si_dE_K_step1)
 # ---------------------------------------------------------------------------
-def _energy(mol, P):
-    J, K = oracle.jk(mol, P=P, tau=0.0)
+def _energy(mol, P, omega=0.0):
+    J, K = oracle.jk(mol, P=P, tau=0.0, omega=omega)
     return oracle.energy(mol, J, K, P=P)
 
 
-def test_gradient_vs_finite_differences(tiny):
+@pytest.mark.parametrize("omega", [0.0, 0.6])
+def test_gradient_vs_finite_differences(tiny, omega):
+    """Central differences of the oracle energy; omega > 0: the erf(omega r)/r
+    energy (eq. eri_longrange_formula) and its gradient."""
     P = tiny.P
-    g = oracle.grad(tiny, tau=0.0)
+    g = oracle.grad(tiny, tau=0.0, omega=omega)
     h = 1e-4
     specs = [(s.atom, s.l, len(s.exps)) for s in tiny.shells]
     for (A, ax) in [(0, 0), (1, 2), (2, 1)]:
         xp = np.array(tiny.xyz, float); xp[A, ax] += h
         xm = np.array(tiny.xyz, float); xm[A, ax] -= h
-        Ep = _energy(synth.custom(xp, specs, seed=21, tau=0.0), P)
-        Em = _energy(synth.custom(xm, specs, seed=21, tau=0.0), P)
+        Ep = _energy(synth.custom(xp, specs, seed=21, tau=0.0), P, omega)
+        Em = _energy(synth.custom(xm, specs, seed=21, tau=0.0), P, omega)
         fd = (Ep - Em) / (2 * h)
         assert g[A, ax] == pytest.approx(fd, rel=1e-6, abs=1e-8)
     assert np.abs(g.sum(axis=0)).max() < 1e-11
@@ -550,3 +553,78 @@ def test_prim_screen_error_within_schwarz_bound():
     print("dropped %d  max bound J %.3e K %.3e  max dJ %.3e dK %.3e" % (nd, worst_j, worst_k, dJ.max(), dK.max()))
     assert dJ.max() > 0 and dK.max() > 0
     assert max(worst_j, worst_k) < 1e-2 * min(np.abs(J0).max(), np.abs(K0).max())
+
+
+# ---------------------------------------------------------------------------
+# Long-range operator erf(omega r)/r (eqs. eri_longrange_definition,
+# eri_longrange_formula)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("ls,seed,omega", [((0, 0, 0, 0), 11, 0.4), ((1, 1, 1, 0), 12, 0.7),
+                                           ((2, 1, 0, 2), 13, 1.3), ((3, 0, 2, 1), 14, 0.33),
+                                           ((3, 3, 2, 2), 15, 2.5)])
+def test_longrange_prim_block_vs_bruteforce(ls, seed, omega):
+    """Every (sampled) Cartesian component of an erf(omega r)/r primitive block
+    against the Gaussian transform of the operator, (2/sqrt(pi)) int_0^omega
+    exp(-t^2 r^2) dt, integrated by quadrature (no Boys function involved)."""
+    rng = np.random.default_rng(seed)
+    ex = np.exp(rng.uniform(np.log(0.2), np.log(4.0), 4))
+    cen = rng.uniform(-1.2, 1.2, (4, 3))
+    blk = oracle.prim_block(ls, ex, cen.reshape(-1), omega=omega)
+    full = oracle.prim_block(ls, ex, cen.reshape(-1))
+    assert not np.allclose(blk, full)
+    cl = [oracle.cart_list(l) for l in ls]
+    idx_all = list(itertools.product(*[range(len(c)) for c in cl]))
+    if len(idx_all) > 30:
+        pick = rng.choice(len(idx_all), 30, replace=False)
+        idx_all = [idx_all[i] for i in pick]
+    scale = np.abs(blk).max()
+    for idx in idx_all:
+        ref = bf.eri_monomial(cl[0][idx[0]], cl[1][idx[1]], cl[2][idx[2]], cl[3][idx[3]],
+                              *ex, *cen, omega=omega)
+        assert abs(blk[idx] - ref) <= 1e-10 * scale, (idx, blk[idx], ref)
+
+
+def test_longrange_ssss_closed_form():
+    """(ss|erf(omega r)/r|ss) of unnormalised s Gaussians by the Gaussian
+    transform done in closed form per t: the t-slice is
+    (pi/(t^2+q))^{3/2} (pi/(p+mu))^{3/2} exp(-p mu/(p+mu) |P-Q|^2) with
+    mu = t^2 q/(t^2+q), integrated over t in [0, omega] by mpmath."""
+    mp.mp.dps = 30
+    rng = np.random.default_rng(21)
+    for _ in range(4):
+        a, b, c, d = np.exp(rng.uniform(np.log(0.1), np.log(8.0), 4))
+        A, B, C, D = rng.uniform(-1.5, 1.5, (4, 3))
+        omega = float(np.exp(rng.uniform(np.log(0.1), np.log(5.0))))
+        p, q = a + b, c + d
+        P = (a * A + b * B) / p
+        Q = (c * C + d * D) / q
+        kab = mp.e ** (-a * b / p * float(np.sum((A - B) ** 2)))
+        kcd = mp.e ** (-c * d / q * float(np.sum((C - D) ** 2)))
+        R2 = float(np.sum((P - Q) ** 2))
+
+        def slice_(t):
+            mu = t * t * q / (t * t + q)
+            return (mp.pi / (t * t + q)) ** 1.5 * (mp.pi / (p + mu)) ** 1.5 * mp.e ** (-p * mu / (p + mu) * R2)
+
+        ref = float(2 / mp.sqrt(mp.pi) * kab * kcd * mp.quad(slice_, [0, omega]))
+        v = oracle.prim_block((0, 0, 0, 0), [a, b, c, d], np.concatenate([A, B, C, D]), omega=omega).ravel()[0]
+        assert v == pytest.approx(ref, rel=1e-12), (omega, v, ref)
+
+
+def test_longrange_large_omega_is_coulomb_and_jk_consistent():
+    """As omega grows the long-range operator becomes 1/r: J and K at
+    omega = 1e7 equal the Coulomb ones to rounding; at finite omega they are
+    smaller in the Coulomb-metric sense (E_J decreases: the kernel's Fourier
+    transform 4 pi/k^2 exp(-k^2/(4 omega^2)) is pointwise below 4 pi/k^2)."""
+    mol = synth.custom([[0, 0, 0], [1.1, 0.3, -0.2], [-0.4, 1.0, 0.9]],
+                       [(0, 3, 1), (1, 2, 2), (2, 1, 1), (1, 0, 3), (0, 0, 2)], seed=23, tau=0.0)
+    J0, K0 = oracle.jk(mol, tau=0.0, tau_prim=0.0)
+    J1, K1 = oracle.jk(mol, tau=0.0, tau_prim=0.0, omega=1e7)
+    assert np.abs(J1 - J0).max() <= 1e-12 * np.abs(J0).max()
+    assert np.abs(K1 - K0).max() <= 1e-12 * np.abs(K0).max()
+    Jw, Kw = oracle.jk(mol, tau=0.0, tau_prim=0.0, omega=0.5)
+    P = 0.5 * (mol.P + mol.P.T)
+    ej0, ejw = float(np.sum(P * J0)), float(np.sum(P * Jw))
+    assert 0.0 < ejw < ej0
+    assert np.abs(Jw - Jw.T).max() <= 1e-14 * np.abs(Jw).max()
+    assert np.abs(Kw - Kw.T).max() <= 1e-14 * np.abs(Kw).max()
