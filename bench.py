@@ -139,6 +139,64 @@ def compare_precision(jk, P, J, K, a, st):
             "mixed_thresh": 1e-5}
 
 
+def bench_prim0(jk0, P, J, K, a, st):
+    """The same workload with the primitive screen off (contracted-quartet
+    Schwarz rule only): time, max |dJ|, |dK| against the default build and
+    the share of primitive quartets the default screen skips."""
+    import torch
+    from paper_2406_14920_amd import JK, synth
+    mol = synth.mol40()
+    jk = JK.from_molecule(mol, prim_thresh=0.0)
+    for _ in range(max(1, a.warmup)):
+        jk.jk(P)
+    ms = _time(lambda: jk.jk(P), a.steps)
+    J0, K0 = jk.jk(P)
+    torch.cuda.synchronize()
+    s0 = jk.stats()
+    jk.close()
+    dJ = float((J0 - J).abs().max())
+    dK = float((K0 - K).abs().max())
+    skip_k = 1.0 - st["n_prim_quartets_k"] / max(1, s0["n_prim_quartets_k"])
+    skip_j = 1.0 - st["n_prim_quartets_j"] / max(1, s0["n_prim_quartets_j"])
+    print("prim_thresh 0: %.1f ms dJ=%.2e dK=%.2e skipped K %.4f J %.4f" % (ms, dJ, dK, skip_k, skip_j),
+          file=sys.stderr, flush=True)
+    return {"prim_thresh": 0.0, "ms_per_step": ms, "max_abs_dJ_vs_default": dJ, "max_abs_dK_vs_default": dK,
+            "prim_quartets_k": s0["n_prim_quartets_k"], "prim_quartets_j": s0["n_prim_quartets_j"],
+            "default_skips_k": skip_k, "default_skips_j": skip_j}
+
+
+def bench_tm62(a):
+    """Transition-metal-like workload (1336 functions, exponents to 2e5):
+    FP64 and mixed J+K time and the mixed error against FP64."""
+    import torch
+    from paper_2406_14920_amd import JK, synth
+    mol = synth.tm62()
+    jk = JK.from_molecule(mol)
+    P = torch.tensor(mol.P, dtype=torch.float64, device="cuda")
+    out = {"workload": "tm62: 2 heavy centres (3 s8, 2 p6, 3 d5, 2 f1; exponents 0.05-2e5) + 60 light atoms, "
+                       "%d spherical bf, Schwarz 1e-11, primitive 1e-13" % mol.nbf}
+    res = {}
+    for prec in ("fp64", "mixed"):
+        jk.set_precision(prec)
+        for _ in range(max(1, a.warmup)):
+            jk.jk(P)
+        ms = _time(lambda: jk.jk(P), max(1, min(a.steps, 5)))
+        J, K = jk.jk(P)
+        torch.cuda.synchronize()
+        res[prec] = (ms, J, K)
+        out[prec + "_ms"] = ms
+    st = jk.stats()
+    jk.close()
+    out["eris_sph"] = st["eris_sph"]
+    out["value_fp64"] = st["eris_sph"] / (res["fp64"][0] * 1e-3)
+    out["mixed_speedup"] = res["fp64"][0] / res["mixed"][0]
+    out["mixed_max_abs_dJ"] = float((res["mixed"][1] - res["fp64"][1]).abs().max())
+    out["mixed_max_abs_dK"] = float((res["mixed"][2] - res["fp64"][2]).abs().max())
+    print("tm62: fp64 %.1f ms mixed %.1f ms dJ=%.2e dK=%.2e" % (
+        out["fp64_ms"], out["mixed_ms"], out["mixed_max_abs_dJ"], out["mixed_max_abs_dK"]), file=sys.stderr, flush=True)
+    return out
+
+
 def bench_grad(a):
     """Nuclear gradient of the 20-atom workload (jk_grad, double precision)."""
     import torch
@@ -278,7 +336,10 @@ def main():
             json.dump({"steps": a.steps, "ms_per_step": ms, "kernels": prof}, f, indent=1)
     if not a.no_extras:
         out["compare"] = compare_precision(jk, P, J, K, a, st)
+        out["prim_thresh_0"] = bench_prim0(jk, P, J, K, a, st)
     jk.close()
+    if not a.no_extras:
+        out["tm62"] = bench_tm62(a)
     if not a.no_extras:
         out["grad"] = bench_grad(a)
         out["batch64"] = bench_batch(a)

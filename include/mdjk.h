@@ -95,6 +95,12 @@ typedef struct {
                               bounds, digestion and accumulation are FP64 always. */
     int32_t spherical;     /* 1: real solid harmonics (default); 0: Cartesian */
     void *stream;          /* hipStream_t, NULL = default stream */
+    double omega;          /* two-electron operator: 0 (default) the Coulomb 1/r;
+                              > 0 the long-range erf(omega r)/r of eqs.
+                              eri_longrange_definition / eri_longrange_formula
+                              (J, K, energy and gradient).  Screening always uses
+                              the 1/r bounds, which bound the long-range
+                              integrals too. */
 } eri_opts;
 
 typedef struct {
@@ -108,6 +114,9 @@ typedef struct {
     double  model_flops_k;       /* model FLOPs of one K build (unique quartets) */
     double  model_flops_j;       /* model FLOPs of one J build (J-engine) */
     double  last_ms;             /* device time of the last build_jk / jk_grad (ms) */
+    int64_t n_prim_quartets_k;   /* primitive quartets one K build evaluates (after the
+                                    primitive screen; unique quartets) */
+    int64_t n_prim_quartets_j;   /* (bra, ket) primitive pairs one J-engine build evaluates */
 } eri_stats_t;
 
 /* Device time of one kernel family, accumulated while profiling is on. */
@@ -120,7 +129,7 @@ typedef struct {
 } eri_kernel_time;
 
 /* Fill opts with defaults: schwarz 1e-11, prim 1e-2*schwarz, mixed 1e-5,
- * FP64, spherical, default stream. */
+ * FP64, spherical, default stream, Coulomb operator (omega 0). */
 void eri_default_opts(eri_opts *opts);
 
 /* Build a context: normalise shells, form contracted and primitive shell pairs
@@ -140,6 +149,11 @@ int eri_set_geometry(eri_ctx *ctx, const eri_atom *atoms);
 /* Change the precision mode (ERI_FP64 / ERI_MIXED / ERI_MIXED_ALL) and the
  * mixed threshold. */
 int eri_set_precision(eri_ctx *ctx, int32_t precision, double mixed_thresh);
+
+/* Switch the two-electron operator of later calls: omega = 0 for 1/r, > 0 for
+ * erf(omega r)/r (eq. eri_longrange_formula); the pairs and screening bounds
+ * are unchanged. */
+int eri_set_omega(eri_ctx *ctx, double omega);
 
 /* J_mn = sum_ls (mn|ls) P_ls (J-engine, eq. j_formula) and
  * K_ml = sum_ns (mn|ls) P_ns (eq. k_formula).  P, J, K: device, nbf*nbf
@@ -195,6 +209,29 @@ int eri_autotune(eri_ctx *ctx, const double *P, int32_t reps);
  * cap_len exchange caps into kcap (may be NULL; 0 = default), *n_kcap = the
  * number of exchange launches (may be NULL). */
 int eri_tuning(const eri_ctx *ctx, int32_t *kchunk100, int32_t *kcap, int32_t cap_len, int32_t *n_kcap);
+
+/* The launch shapes and precision splits in use, keyed by angular class so
+ * that they can be saved and applied to a context of a similar workload.
+ * kchunk/jsplit[10*X + Y]: J-engine ket chunk and FP32-share flag of bra
+ * class X, ket class Y (classes ss, ps, pp, ds, dp, dd, fs, fp, fd, ff);
+ * launch i < n_kwork of the exchange: class pair kwork_class[i] = 10*X + Y
+ * (X >= Y), workgroup cap kcap[i] (0 = default) and FP32-share flag ksplit[i]. */
+typedef struct {
+    int32_t kchunk[100];
+    int32_t jsplit[100];
+    int32_t n_kwork;
+    int32_t kwork_class[64];
+    int32_t kcap[64];
+    int32_t ksplit[64];
+} eri_tuning_t;
+
+/* Read the current choice (eri_get_tuning) or apply a saved one
+ * (eri_set_tuning: entries are matched by class; chunks outside 8..1024 or
+ * negative caps are rejected with ERI_EINVAL).  Results change only in the
+ * order of floating-point additions, and under ERI_MIXED within the mixed
+ * error where a launch moves between FP32 and FP64. */
+int eri_get_tuning(const eri_ctx *ctx, eri_tuning_t *out);
+int eri_set_tuning(eri_ctx *ctx, const eri_tuning_t *in);
 
 /* Batches of independent molecules (many contexts, uneven sizes).
  * eri_batch_create: n >= 1 contexts on the current device, each keeping its

@@ -27,14 +27,16 @@ class JK:
 
     def __init__(self, shells, xyz, schwarz_thresh: float = 1e-11, prim_thresh: Optional[float] = None,
                  precision: str = "fp64", mixed_thresh: float = 1e-5, spherical: bool = True,
-                 stream=None):
+                 stream=None, omega: float = 0.0):
         import torch
         o = abi.eri_default_opts()
         o.schwarz_thresh = float(schwarz_thresh)
         o.prim_thresh = float(1e-2 * schwarz_thresh if prim_thresh is None else prim_thresh)
         o.mixed_thresh = float(mixed_thresh)
         o.precision = _PREC[precision]
+        self._precision = o.precision
         o.spherical = 1 if spherical else 0
+        o.omega = float(omega)  # 0: 1/r; > 0: erf(omega r)/r
         if stream is None:
             stream = torch.cuda.current_stream()
         self.stream = stream
@@ -83,11 +85,33 @@ class JK:
             abi.eri_energy(self.ctx, P, J, K, E)
         return E
 
-    def autotune(self, P, reps: int = 2) -> dict:
-        """Pick launch shapes for this workload (eri_autotune); returns them."""
+    def autotune(self, P, reps: int = 2, cache: Optional[str] = None, key: Optional[str] = None) -> dict:
+        """Pick launch shapes for this workload (eri_autotune); returns them.
+        With `cache` (a JSON file path), a choice saved there under `key`
+        and this precision is applied instead of timing, and a new choice is
+        saved there."""
+        import json
+        import os
+        ck = "%s/%s" % (key or "nbf%d" % self.nbf, self.precision_name())
+        store = {}
+        if cache and os.path.exists(cache):
+            with open(cache) as f:
+                store = json.load(f)
+            if ck in store:
+                abi.eri_set_tuning(self.ctx, store[ck])
+                return abi.eri_tuning(self.ctx)
         with __import__("torch").cuda.stream(self.stream):
             abi.eri_autotune(self.ctx, P, reps)
+        if cache:
+            store[ck] = abi.eri_get_tuning(self.ctx)
+            tmp = cache + ".tmp"
+            with open(tmp, "w") as f:
+                json.dump(store, f, indent=1, sort_keys=True)
+            os.replace(tmp, cache)
         return abi.eri_tuning(self.ctx)
+
+    def precision_name(self) -> str:
+        return {v: k for k, v in _PREC.items()}[self._precision]
 
     def set_geometry(self, xyz):
         """Move the atoms (same shells); redoes pair setup (synchronous)."""
@@ -97,6 +121,11 @@ class JK:
     def set_precision(self, precision: str, mixed_thresh: Optional[float] = None):
         abi.eri_set_precision(self.ctx, _PREC[precision],
                               self.opts.mixed_thresh if mixed_thresh is None else mixed_thresh)
+        self._precision = _PREC[precision]
+
+    def set_omega(self, omega: float):
+        """Two-electron operator of later builds: 0 for 1/r, > 0 for erf(omega r)/r."""
+        abi.eri_set_omega(self.ctx, omega)
 
     def stats(self) -> dict:
         return abi.eri_stats(self.ctx)

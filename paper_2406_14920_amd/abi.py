@@ -39,7 +39,7 @@ class eri_shell(ctypes.Structure):
 class eri_opts(ctypes.Structure):
     _fields_ = [("schwarz_thresh", ctypes.c_double), ("prim_thresh", ctypes.c_double),
                 ("mixed_thresh", ctypes.c_double), ("precision", ctypes.c_int32),
-                ("spherical", ctypes.c_int32), ("stream", ctypes.c_void_p)]
+                ("spherical", ctypes.c_int32), ("stream", ctypes.c_void_p), ("omega", ctypes.c_double)]
 
 
 class eri_stats_t(ctypes.Structure):
@@ -48,7 +48,13 @@ class eri_stats_t(ctypes.Structure):
                 ("n_quartets", ctypes.c_int64), ("n_quartets_fp32", ctypes.c_int64),
                 ("eris_sph", ctypes.c_double), ("eris_cart", ctypes.c_double),
                 ("model_flops_k", ctypes.c_double), ("model_flops_j", ctypes.c_double),
-                ("last_ms", ctypes.c_double)]
+                ("last_ms", ctypes.c_double), ("n_prim_quartets_k", ctypes.c_int64),
+                ("n_prim_quartets_j", ctypes.c_int64)]
+
+
+class eri_tuning_t(ctypes.Structure):
+    _fields_ = [("kchunk", ctypes.c_int32 * 100), ("jsplit", ctypes.c_int32 * 100), ("n_kwork", ctypes.c_int32),
+                ("kwork_class", ctypes.c_int32 * 64), ("kcap", ctypes.c_int32 * 64), ("ksplit", ctypes.c_int32 * 64)]
 
 
 class eri_kernel_time(ctypes.Structure):
@@ -59,7 +65,8 @@ class eri_kernel_time(ctypes.Structure):
 EXPORTS = ["eri_default_opts", "eri_setup", "eri_nbf", "eri_set_geometry", "eri_set_precision",
            "build_jk", "jk_grad", "eri_energy", "eri_set_profiling", "eri_profile_read", "eri_stats", "eri_destroy",
            "eri_last_error", "eri_batch_create", "eri_batch_build_jk", "eri_batch_destroy",
-           "eri_autotune", "eri_tuning"]
+           "eri_autotune", "eri_tuning", "eri_set_omega", "eri_get_tuning",
+           "eri_set_tuning"]
 
 _lib = None
 
@@ -81,6 +88,9 @@ def load(path: str = LIB_PATH):
     L.eri_nbf.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
     L.eri_set_geometry.argtypes = [vp, ctypes.POINTER(eri_atom)]
     L.eri_set_precision.argtypes = [vp, ctypes.c_int32, ctypes.c_double]
+    L.eri_set_omega.argtypes = [vp, ctypes.c_double]
+    L.eri_get_tuning.argtypes = [vp, ctypes.POINTER(eri_tuning_t)]
+    L.eri_set_tuning.argtypes = [vp, ctypes.POINTER(eri_tuning_t)]
     L.build_jk.argtypes = [vp, vp, vp, vp]
     L.jk_grad.argtypes = [vp, vp, vp, vp]
     L.eri_energy.argtypes = [vp, vp, vp, vp, vp]
@@ -179,6 +189,37 @@ def eri_set_precision(ctx: int, precision: int, mixed_thresh: float) -> None:
 
 def build_jk(ctx: int, P, J, K) -> None:
     _check(load().build_jk(ctypes.c_void_p(ctx), _ptr(P), _ptr(J), _ptr(K)))
+
+
+_CLASSES = ["ss", "ps", "pp", "ds", "dp", "dd", "fs", "fp", "fd", "ff"]
+
+
+def eri_get_tuning(ctx: int) -> dict:
+    """Launch shapes and splits keyed by class names (JSON-serialisable)."""
+    t = eri_tuning_t()
+    _check(load().eri_get_tuning(ctypes.c_void_p(ctx), ctypes.byref(t)))
+    j = {"%s|%s" % (_CLASSES[k // 10], _CLASSES[k % 10]): [int(t.kchunk[k]), int(t.jsplit[k])] for k in range(100)}
+    kx = {"%s|%s" % (_CLASSES[t.kwork_class[i] // 10], _CLASSES[t.kwork_class[i] % 10]): [int(t.kcap[i]), int(t.ksplit[i])]
+          for i in range(t.n_kwork)}
+    return {"jengine": j, "exchange": kx}
+
+
+def eri_set_tuning(ctx: int, tuning: dict) -> None:
+    cur = eri_tuning_t()
+    _check(load().eri_get_tuning(ctypes.c_void_p(ctx), ctypes.byref(cur)))
+    for name, (kc, sp) in tuning.get("jengine", {}).items():
+        x, y = name.split("|")
+        k = 10 * _CLASSES.index(x) + _CLASSES.index(y)
+        cur.kchunk[k], cur.jsplit[k] = int(kc), int(sp)
+    for i in range(cur.n_kwork):
+        name = "%s|%s" % (_CLASSES[cur.kwork_class[i] // 10], _CLASSES[cur.kwork_class[i] % 10])
+        if name in tuning.get("exchange", {}):
+            cur.kcap[i], cur.ksplit[i] = (int(v) for v in tuning["exchange"][name])
+    _check(load().eri_set_tuning(ctypes.c_void_p(ctx), ctypes.byref(cur)))
+
+
+def eri_set_omega(ctx: int, omega: float) -> None:
+    _check(load().eri_set_omega(ctypes.c_void_p(ctx), float(omega)))
 
 
 def jk_grad(ctx: int, P, grad, E=None) -> None:

@@ -103,7 +103,10 @@ double fl_k_prim(int la, int lb, int lc, int ld)
 double fl_k_digest(int la, int lb, int lc, int ld) { return 8.0 * ncart(la) * ncart(lb) * ncart(lc) * ncart(ld); }
 double fl_j_prim(int lx, int ly) { return fl_boys(lx + ly) + fl_r(lx + ly) + 2.0 * nherm(lx) * nherm(ly); }
 
-bool jeng_is_reg(int lx, int ly) { return lx + ly >= 6 && nherm(lx) + nherm(ly) + 4 * (lx + ly + 1) <= 116; }
+bool jeng_is_reg(int lx, int ly)
+{
+    return lx + ly >= 6 && nherm(lx) + 4 * (lx + ly + 1) + (nherm(ly) <= 20 ? nherm(ly) : 0) <= 116;
+}
 
 // Default ket chunk of a J-engine launch: the largest power of two in
 // [8, 256] that still gives the launch at least 16384 workgroups (one per
@@ -209,7 +212,13 @@ struct eri_ctx {
         int64_t nwork;
         int64_t choff;  // into chunk buffer (bra-shared kernel), -1 if unused
         int nchunks;
+        int64_t roff;   // into row buffer
+        int nrows;
     };
+    // exchange view: per class the pairs grouped by contraction length
+    // (largest first), Q descending inside a group (same class bases as cp)
+    std::vector<CPair> kcp;
+    std::vector<double> kQ;
     std::vector<KWork> kwork;
     size_t dt_off[kPairClasses] = {}, jh_off[kPairClasses] = {};
 
@@ -219,11 +228,18 @@ struct eri_ctx {
     DevBuf<PrimPair> d_pp;
     DevBuf<int32_t> d_owner;
     DevBuf<int64_t> d_prefix;
+    DevBuf<int2> d_rows;
+    DevBuf<CPair> d_kcp;
+    DevBuf<double> d_kQ;
     DevBuf<int2> d_chunks;
     DevBuf<double> d_eprod;
     size_t eprod_off[kPairClasses] = {};
     DevBuf<double> d_boys;
     DevBuf<double> d_Pc, d_Jacc, d_Kacc, d_Dt, d_Jh;
+    // the per-build work buffers the kernels are handed
+    struct Work {
+        double *Pc = nullptr, *Jacc = nullptr, *Kacc = nullptr, *Dt = nullptr, *Jh = nullptr;
+    } wk;
     DevBuf<int32_t> d_soc, d_sos, d_l, d_coff, d_soff;
 
     // mixed precision: single-precision Hermite products and Hermite density
@@ -317,6 +333,8 @@ int validate(const eri_shell *shells, int32_t nshell, const eri_atom *atoms, int
             return set_err(ERI_EINVAL, "negative or NaN threshold");
         if (o->precision != ERI_FP64 && o->precision != ERI_MIXED && o->precision != ERI_MIXED_ALL)
             return set_err(ERI_EINVAL, "unknown precision %d", o->precision);
+        if (!(o->omega >= 0.0) || !std::isfinite(o->omega))
+            return set_err(ERI_EINVAL, "omega %g not non-negative and finite", o->omega);
     }
     return ERI_OK;
 }
@@ -465,38 +483,81 @@ void build_pairs(eri_ctx *c)
     c->mix_counts_ok = false;
     c->grad_ready = false;
 
-    // 4. exchange work lists
+    // 4. exchange work lists.  The exchange kernels see each class through a
+    // view grouped by contraction length (number of primitive pairs, rounded
+    // up to a power of two; largest first) and Q-sorted inside a group, so
+    // that the lanes of a wavefront, which take neighbouring work items, run
+    // primitive loops of equal length.  A row pairs one bra with the kets of
+    // one group; the kets it visits (Q_i Q_j >= tau and, in a class with
+    // itself, j not after i in the Q order) form a prefix of that group.
+    auto group_of = [](int np) {
+        int g = 0;
+        while ((1 << g) < np) ++g;
+        return g;
+    };
+    c->kcp.assign(c->cp.size(), CPair{});
+    c->kQ.assign(c->cp.size(), 0.0);
+    std::vector<int> vorig(c->cp.size());          // view index -> Q-order index (inside the class)
+    std::vector<std::vector<std::array<int, 2>>> groups(kPairClasses);  // (first, count) in view order
+    for (int X = 0; X < kPairClasses; ++X) {
+        const int b = c->cp_base[X], nX = c->ncp[X];
+        std::vector<int> idx(nX);
+        for (int k = 0; k < nX; ++k) idx[k] = k;
+        std::stable_sort(idx.begin(), idx.end(),
+                         [&](int x, int y) { return group_of(c->cp[b + x].np) > group_of(c->cp[b + y].np); });
+        for (int r = 0; r < nX; ++r) {
+            c->kcp[b + r] = c->cp[b + idx[r]];
+            c->kQ[b + r] = c->Q[b + idx[r]];
+            vorig[b + r] = idx[r];
+            const int g = group_of(c->cp[b + idx[r]].np);
+            if (r == 0 || g != group_of(c->cp[b + idx[r - 1]].np)) groups[X].push_back({r, 0});
+            groups[X].back()[1]++;
+        }
+    }
     std::vector<int64_t> prefix;
+    std::vector<int2> rows;
     std::vector<int2> chunks;
     c->kwork.clear();
     c->n_quartets = 0;
     c->eris_sph = c->eris_cart = 0.0;
     for (int X = 0; X < kPairClasses; ++X)
         for (int Y = 0; Y <= X; ++Y) {
-            eri_ctx::KWork w{X, Y, (int64_t)prefix.size(), 0, -1, 0};
-            const double *QX = c->Q.data() + c->cp_base[X];
-            const double *QY = c->Q.data() + c->cp_base[Y];
-            const int nX = c->ncp[X], nY = c->ncp[Y];
+            eri_ctx::KWork w{X, Y, (int64_t)prefix.size(), 0, -1, 0, (int64_t)rows.size(), 0};
+            const int bX = c->cp_base[X], bY = c->cp_base[Y];
             int64_t acc = 0;
             prefix.push_back(0);
-            for (int i = 0; i < nX; ++i) {
-                // kets with Q_i Q_j >= tau form a prefix of the descending list
-                int lo = 0, hi = nY;
-                while (lo < hi) {
-                    int mid = (lo + hi) / 2;
-                    if (QX[i] * QY[mid] >= tau) lo = mid + 1; else hi = mid;
-                }
-                int cnt = lo;
-                if (X == Y) cnt = std::min(cnt, i + 1);
-                acc += cnt;
-                prefix.push_back(acc);
-            }
+            for (const auto &gx : groups[X])
+                for (const auto &gy : groups[Y])
+                    for (int i = gx[0]; i < gx[0] + gx[1]; ++i) {
+                        const double Qi = c->kQ[bX + i];
+                        const int j0 = gy[0], j1 = gy[0] + gy[1];
+                        int lo = j0, hi = j1;  // Q descending inside the group
+                        while (lo < hi) {
+                            const int mid = (lo + hi) / 2;
+                            if (Qi * c->kQ[bY + mid] >= tau) lo = mid + 1; else hi = mid;
+                        }
+                        int cnt = lo - j0;
+                        if (X == Y) {  // Q-order index ascending inside the group
+                            const int oi = vorig[bX + i];
+                            int l2 = j0, h2 = j1;
+                            while (l2 < h2) {
+                                const int mid = (l2 + h2) / 2;
+                                if (vorig[bY + mid] <= oi) l2 = mid + 1; else h2 = mid;
+                            }
+                            cnt = std::min(cnt, l2 - j0);
+                        }
+                        if (cnt <= 0) continue;
+                        rows.push_back(make_int2(i, j0));
+                        acc += cnt;
+                        prefix.push_back(acc);
+                    }
             w.nwork = acc;
+            w.nrows = (int)((int64_t)rows.size() - w.roff);
             if (uses_k_pair(kPairL[X][0], kPairL[X][1], kPairL[Y][0], kPairL[Y][1]) && acc > 0) {
                 w.choff = (int64_t)chunks.size();
-                for (int i = 0; i < nX; ++i) {
-                    const int64_t cnt = prefix[w.off + i + 1] - prefix[w.off + i];
-                    for (int64_t j0 = 0; j0 < cnt; j0 += 64) chunks.push_back(make_int2(i, (int)j0));
+                for (int r = 0; r < w.nrows; ++r) {
+                    const int64_t cnt = prefix[w.off + r + 1] - prefix[w.off + r];
+                    for (int64_t j0 = 0; j0 < cnt; j0 += 64) chunks.push_back(make_int2(r, (int)j0));
                 }
                 w.nchunks = (int)((int64_t)chunks.size() - w.choff);
             }
@@ -507,6 +568,9 @@ void build_pairs(eri_ctx *c)
             c->eris_cart += (double)acc * ncart(la) * ncart(lb) * ncart(lc) * ncart(ld);
         }
     c->d_prefix.upload(prefix);
+    c->d_rows.upload(rows);
+    c->d_kcp.upload(c->kcp);
+    c->d_kQ.upload(c->kQ);
     c->d_chunks.upload(chunks);
     for (int X = 0; X < kPairClasses; ++X)
         for (int Y = 0; Y < kPairClasses; ++Y) {
@@ -542,6 +606,8 @@ void build_pairs(eri_ctx *c)
     }
     c->d_Dt.alloc(std::max<size_t>(dt, 1));
     c->d_Jh.alloc(std::max<size_t>(dt, 1));
+    c->wk.Dt = c->d_Dt.p;
+    c->wk.Jh = c->d_Jh.p;
 
     // 6. primitive quartets each launch evaluates (same loops as the kernels)
     const size_t ncount = c->kwork.size() + kPairClasses * kPairClasses;
@@ -551,11 +617,12 @@ void build_pairs(eri_ctx *c)
     for (size_t wi = 0; wi < c->kwork.size(); ++wi) {
         const auto &w = c->kwork[wi];
         KArgs a{};
-        a.bra = c->d_cp.p + c->cp_base[w.X];
-        a.ket = c->d_cp.p + c->cp_base[w.Y];
+        a.bra = c->d_kcp.p + c->cp_base[w.X];
+        a.ket = c->d_kcp.p + c->cp_base[w.Y];
+        a.rows = c->d_rows.p + w.roff;
         a.prefix = c->d_prefix.p + w.off;
         a.nwork = w.nwork;
-        a.nbra = c->ncp[w.X];
+        a.nrows = w.nrows;
         a.pp = c->d_pp.p;
         a.tau_prim = c->opts.prim_thresh;
         launch_k_count(a, cnt.p + wi, c->st);
@@ -645,6 +712,9 @@ void build_basis(eri_ctx *c, const eri_shell *shells, const eri_atom *atoms)
     c->d_Pc.alloc(nc2);
     c->d_Jacc.alloc(nc2);
     c->d_Kacc.alloc(nc2);
+    c->wk.Pc = c->d_Pc.p;
+    c->wk.Jacc = c->d_Jacc.p;
+    c->wk.Kacc = c->d_Kacc.p;
     c->d_Pm.alloc((size_t)c->nshell * c->nshell);
 }
 
@@ -673,6 +743,8 @@ ShellMap shell_map(const eri_ctx *c)
 }
 
 bool ctx_ok(const eri_ctx *c) { return c && c->magic == 0x4d444a4b; }
+
+
 
 // Does this launch take the single-precision share (two launches, modes 1/2)?
 bool j_split(const eri_ctx *c, int X, int Y)
@@ -719,9 +791,9 @@ JArgs j_args(const eri_ctx *c, int X, int Y, bool mixed)
     a.Qket = c->d_Q.p + c->cp_base[Y];
     a.nket = c->ncp[Y];
     a.kchunk = c->kchunk[X][Y];
-    a.Dt = c->d_Dt.p + c->dt_off[Y];
+    a.Dt = c->wk.Dt + c->dt_off[Y];
     a.dt_base = c->pp_base[Y];
-    a.Jh = c->d_Jh.p + c->jh_off[X];
+    a.Jh = c->wk.Jh + c->jh_off[X];
     a.boys = c->d_boys.p;
     a.tau = c->opts.schwarz_thresh;
     a.tau_prim = c->opts.prim_thresh;
@@ -731,6 +803,7 @@ JArgs j_args(const eri_ctx *c, int X, int Y, bool mixed)
         a.tau_mix = c->opts.mixed_thresh;
         a.QDket = c->d_QD.p + c->cp_base[Y];
     }
+    a.om2 = c->opts.omega * c->opts.omega;
     return a;
 }
 
@@ -741,10 +814,10 @@ void run_j(eri_ctx *c, bool mixed, hipStream_t st)
     for (int Y = 0; Y < kPairClasses; ++Y)
         timed(c, st, cls_name("hdens", kPairL[Y][0], kPairL[Y][1], 0, 0), -1, 0, 0, [&] {
             launch_hermite_density(kPairL[Y][0], kPairL[Y][1], c->d_cp.p + c->cp_base[Y], c->ncp[Y], c->d_pp.p,
-                                   c->d_Pc.p, nc, c->d_Dt.p + c->dt_off[Y],
+                                   c->wk.Pc, nc, c->wk.Dt + c->dt_off[Y],
                                    mixed ? c->d_Dtf.p + c->dt_off[Y] : nullptr, c->pp_base[Y], st);
         });
-    timed(c, st, "fill_zero", -1, 0, 0, [&] { launch_fill_zero(c->d_Jh.p, (int64_t)c->d_Jh.n, st); });
+    timed(c, st, "fill_zero", -1, 0, 0, [&] { launch_fill_zero(c->wk.Jh, (int64_t)c->d_Jh.n, st); });
     for (int X = 0; X < kPairClasses; ++X) {
         if (c->npp[X] == 0) continue;
         for (int Y = 0; Y < kPairClasses; ++Y) {
@@ -764,23 +837,24 @@ void run_j(eri_ctx *c, bool mixed, hipStream_t st)
     for (int X = 0; X < kPairClasses; ++X)
         timed(c, st, cls_name("herm2cart", kPairL[X][0], kPairL[X][1], 0, 0), -1, 0, 0, [&] {
             launch_hermite_to_cart(kPairL[X][0], kPairL[X][1], c->d_cp.p + c->cp_base[X], c->ncp[X], c->d_pp.p,
-                                   c->d_Jh.p + c->jh_off[X], c->pp_base[X], c->d_Jacc.p, nc, st);
+                                   c->wk.Jh + c->jh_off[X], c->pp_base[X], c->wk.Jacc, nc, st);
         });
 }
 
 KArgs k_args(const eri_ctx *c, const eri_ctx::KWork &w, bool mixed)
 {
     KArgs a{};
-    a.bra = c->d_cp.p + c->cp_base[w.X];
-    a.ket = c->d_cp.p + c->cp_base[w.Y];
+    a.bra = c->d_kcp.p + c->cp_base[w.X];
+    a.ket = c->d_kcp.p + c->cp_base[w.Y];
+    a.rows = c->d_rows.p + w.roff;
     a.prefix = c->d_prefix.p + w.off;
     a.nwork = w.nwork;
-    a.nbra = c->ncp[w.X];
+    a.nrows = w.nrows;
     a.same = w.X == w.Y;
     a.pp = c->d_pp.p;
     a.boys = c->d_boys.p;
-    a.D = c->d_Pc.p;
-    a.Kacc = c->d_Kacc.p;
+    a.D = c->wk.Pc;
+    a.Kacc = c->wk.Kacc;
     a.ld = c->nbf_cart;
     a.tau_prim = c->opts.prim_thresh;
     a.eprod_bra = c->d_eprod.p + c->eprod_off[w.X];
@@ -789,12 +863,13 @@ KArgs k_args(const eri_ctx *c, const eri_ctx::KWork &w, bool mixed)
     a.pbase_ket = c->pp_base[w.Y];
     a.mode = 0;
     a.grid_cap = c->kcap[&w - c->kwork.data()];
+    a.om2 = c->opts.omega * c->opts.omega;
     if (mixed) {
         a.eprodf_bra = c->d_eprodf.p + c->eprod_off[w.X];
         a.eprodf_ket = c->d_eprodf.p + c->eprod_off[w.Y];
         a.tau_mix = c->opts.mixed_thresh;
-        a.Qbra = c->d_Q.p + c->cp_base[w.X];
-        a.Qket = c->d_Q.p + c->cp_base[w.Y];
+        a.Qbra = c->d_kQ.p + c->cp_base[w.X];
+        a.Qket = c->d_kQ.p + c->cp_base[w.Y];
         a.Pm = c->d_Pm.p;
         a.nsh = c->nshell;
     }
@@ -807,6 +882,7 @@ KPArgs kp_args(const KArgs &a, const int2 *chunks)
     p.bra = a.bra;
     p.ket = a.ket;
     p.chunks = chunks;
+    p.rows = a.rows;
     p.prefix = a.prefix;
     p.same = a.same;
     p.pp = a.pp;
@@ -827,6 +903,7 @@ KPArgs kp_args(const KArgs &a, const int2 *chunks)
     p.Qket = a.Qket;
     p.Pm = a.Pm;
     p.nsh = a.nsh;
+    p.om2 = a.om2;
     return p;
 }
 
@@ -987,7 +1064,7 @@ void run_grad(eri_ctx *c, double *grad)
     // Coulomb: Hermite density, J-engine with the bra order raised by one
     for (int Y = 0; Y < kPairClasses; ++Y)
         launch_hermite_density(kPairL[Y][0], kPairL[Y][1], c->d_cp.p + c->cp_base[Y], c->ncp[Y], c->d_pp.p,
-                               c->d_Pc.p, nc, c->d_Dt.p + c->dt_off[Y], nullptr, c->pp_base[Y], st);
+                               c->wk.Pc, nc, c->wk.Dt + c->dt_off[Y], nullptr, c->pp_base[Y], st);
     launch_fill_zero(c->d_Jh1.p, (int64_t)c->d_Jh1.n, st);
     for (int X = 0; X < kPairClasses; ++X) {
         if (c->npp[X] == 0) continue;
@@ -1015,7 +1092,7 @@ void run_grad(eri_ctx *c, double *grad)
         g.pp = c->d_pp.p;
         g.Jh1 = c->d_Jh1.p + c->jh1_off[X];
         g.jh_base = c->pp_base[X];
-        g.D = c->d_Pc.p;
+        g.D = c->wk.Pc;
         g.ld = nc;
         g.pg = c->d_pg.p + 6 * (size_t)c->cp_base[X];
         timed(c, st, cls_name("jgrad", kPairL[X][0], kPairL[X][1], 0, 0), -1, 0, 0,
@@ -1057,6 +1134,7 @@ void eri_default_opts(eri_opts *o)
     o->precision = ERI_FP64;
     o->spherical = 1;
     o->stream = nullptr;
+    o->omega = 0.0;
 }
 
 int eri_setup(const eri_shell *shells, int32_t nshell, const eri_atom *atoms, int32_t natom,
@@ -1133,6 +1211,16 @@ int eri_set_precision(eri_ctx *ctx, int32_t precision, double mixed_thresh)
     return ERI_OK;
 }
 
+int eri_set_omega(eri_ctx *ctx, double omega)
+{
+    if (!ctx_ok(ctx)) return set_err(ERI_ESTATE, "invalid context");
+    if (!(omega >= 0.0) || !std::isfinite(omega))
+        return set_err(ERI_EINVAL, "omega %g not non-negative and finite", omega);
+    if (ctx->opts.omega != omega) ++ctx->gen;
+    ctx->opts.omega = omega;
+    return ERI_OK;
+}
+
 int build_jk(eri_ctx *ctx, const double *P, double *J, double *K)
 {
     if (!ctx_ok(ctx)) return set_err(ERI_ESTATE, "invalid context");
@@ -1142,10 +1230,10 @@ int build_jk(eri_ctx *ctx, const double *P, double *J, double *K)
         const ShellMap m = shell_map(ctx);
         const int nc = ctx->nbf_cart;
         const bool mixed = ctx->opts.precision != ERI_FP64;
-        launch_p_to_cart(P, ctx->nbf, ctx->d_Pc.p, nc, m, ctx->opts.spherical, st);
+        launch_p_to_cart(P, ctx->nbf, ctx->wk.Pc, nc, m, ctx->opts.spherical, st);
         if (mixed) {
             ensure_mixed(ctx);
-            launch_density_bounds(ctx->d_Pc.p, nc, ctx->d_l.p, ctx->d_coff.p, ctx->nshell, ctx->d_Pm.p, ctx->d_cp.p,
+            launch_density_bounds(ctx->wk.Pc, nc, ctx->d_l.p, ctx->d_coff.p, ctx->nshell, ctx->d_Pm.p, ctx->d_cp.p,
                                   ctx->d_Q.p, (int)ctx->cp.size(), ctx->d_QD.p, st);
         }
         ctx->built_mixed = mixed;
@@ -1159,20 +1247,20 @@ int build_jk(eri_ctx *ctx, const double *P, double *J, double *K)
         if (J) {
             hipStream_t sJ = fork ? ctx->aux[0] : st;
             HIPCHK(hipStreamWaitEvent(sJ, ctx->ev_fork, 0));
-            launch_fill_zero(ctx->d_Jacc.p, (int64_t)nc * nc, sJ);
+            launch_fill_zero(ctx->wk.Jacc, (int64_t)nc * nc, sJ);
             run_j(ctx, mixed, sJ);
-            launch_acc_to_out(ctx->d_Jacc.p, nc, J, ctx->nbf, m, ctx->opts.spherical, sJ);
+            launch_acc_to_out(ctx->wk.Jacc, nc, J, ctx->nbf, m, ctx->opts.spherical, sJ);
             HIPCHK(hipEventRecord(ctx->ev_join[0], sJ));
         }
         if (K) {
             hipStream_t sK = fork ? ctx->aux[1] : st;
-            launch_fill_zero(ctx->d_Kacc.p, (int64_t)nc * nc, st);
+            launch_fill_zero(ctx->wk.Kacc, (int64_t)nc * nc, st);
             HIPCHK(hipEventRecord(ctx->ev_kzero, st));
             HIPCHK(hipStreamWaitEvent(sK, ctx->ev_kzero, 0));
             run_k(ctx, mixed, st, sK);
             HIPCHK(hipEventRecord(ctx->ev_join[1], sK));
             HIPCHK(hipStreamWaitEvent(st, ctx->ev_join[1], 0));
-            launch_acc_to_out(ctx->d_Kacc.p, nc, K, ctx->nbf, m, ctx->opts.spherical, st);
+            launch_acc_to_out(ctx->wk.Kacc, nc, K, ctx->nbf, m, ctx->opts.spherical, st);
         }
         if (J) HIPCHK(hipStreamWaitEvent(st, ctx->ev_join[0], 0));
         HIPCHK(hipGetLastError());
@@ -1204,7 +1292,7 @@ int jk_grad(eri_ctx *ctx, const double *P, double *grad, double *E)
             launch_energy(P, ctx->d_Jtmp.p, ctx->d_Ktmp.p, (int64_t)n2, E, st);
         }
         if (grad) {
-            launch_p_to_cart(P, ctx->nbf, ctx->d_Pc.p, ctx->nbf_cart, m, ctx->opts.spherical, st);
+            launch_p_to_cart(P, ctx->nbf, ctx->wk.Pc, ctx->nbf_cart, m, ctx->opts.spherical, st);
             run_grad(ctx, grad);
         }
         HIPCHK(hipGetLastError());
@@ -1254,6 +1342,9 @@ int eri_stats(const eri_ctx *ctx, eri_stats_t *out)
     out->model_flops_k = ctx->model_flops_k;
     out->model_flops_j = ctx->model_flops_j;
     out->last_ms = ctx->last_ms;
+    for (int64_t v : ctx->kprim) out->n_prim_quartets_k += v;
+    for (int X = 0; X < kPairClasses; ++X)
+        for (int Y = 0; Y < kPairClasses; ++Y) out->n_prim_quartets_j += ctx->jprim[X][Y];
     return ERI_OK;
 }
 
@@ -1471,6 +1562,54 @@ int eri_tuning(const eri_ctx *ctx, int32_t *kchunk100, int32_t *kcap, int32_t ca
     if (n_kcap) *n_kcap = (int32_t)ctx->kcap.size();
     if (kcap)
         for (int32_t i = 0; i < cap_len && i < (int32_t)ctx->kcap.size(); ++i) kcap[i] = ctx->kcap[i];
+    return ERI_OK;
+}
+
+int eri_get_tuning(const eri_ctx *ctx, eri_tuning_t *out)
+{
+    if (!ctx_ok(ctx)) return set_err(ERI_ESTATE, "invalid context");
+    if (!out) return set_err(ERI_EINVAL, "out is NULL");
+    memset(out, 0, sizeof(*out));
+    for (int X = 0; X < kPairClasses; ++X)
+        for (int Y = 0; Y < kPairClasses; ++Y) {
+            out->kchunk[X * kPairClasses + Y] = ctx->kchunk[X][Y];
+            out->jsplit[X * kPairClasses + Y] = ctx->jsplit[X][Y] ? 1 : 0;
+        }
+    const int nk = (int)std::min<size_t>(ctx->kwork.size(), 64);
+    out->n_kwork = nk;
+    for (int i = 0; i < nk; ++i) {
+        out->kwork_class[i] = ctx->kwork[i].X * kPairClasses + ctx->kwork[i].Y;
+        out->kcap[i] = ctx->kcap[i];
+        out->ksplit[i] = ctx->ksplit[i] ? 1 : 0;
+    }
+    return ERI_OK;
+}
+
+int eri_set_tuning(eri_ctx *ctx, const eri_tuning_t *in)
+{
+    if (!ctx_ok(ctx)) return set_err(ERI_ESTATE, "invalid context");
+    if (!in) return set_err(ERI_EINVAL, "in is NULL");
+    for (int k = 0; k < kPairClasses * kPairClasses; ++k)
+        if (in->kchunk[k] < 8 || in->kchunk[k] > 1024)
+            return set_err(ERI_EINVAL, "kchunk[%d] = %d outside 8..1024", k, in->kchunk[k]);
+    if (in->n_kwork < 0 || in->n_kwork > 64) return set_err(ERI_EINVAL, "n_kwork %d outside 0..64", in->n_kwork);
+    for (int i = 0; i < in->n_kwork; ++i)
+        if (in->kcap[i] < 0) return set_err(ERI_EINVAL, "kcap[%d] = %d negative", i, in->kcap[i]);
+    for (int X = 0; X < kPairClasses; ++X)
+        for (int Y = 0; Y < kPairClasses; ++Y) {
+            ctx->kchunk[X][Y] = in->kchunk[X * kPairClasses + Y];
+            ctx->jsplit[X][Y] = in->jsplit[X * kPairClasses + Y] != 0;
+        }
+    for (size_t wi = 0; wi < ctx->kwork.size(); ++wi) {
+        const int cls = ctx->kwork[wi].X * kPairClasses + ctx->kwork[wi].Y;
+        for (int i = 0; i < in->n_kwork; ++i)
+            if (in->kwork_class[i] == cls) {
+                ctx->kcap[wi] = in->kcap[i];
+                ctx->ksplit[wi] = in->ksplit[i] != 0;
+            }
+    }
+    ctx->mix_counts_ok = false;
+    ++ctx->gen;
     return ERI_OK;
 }
 

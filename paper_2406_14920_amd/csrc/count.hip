@@ -12,13 +12,10 @@ __global__ void k_count(KArgs a, unsigned long long *out)
     int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     unsigned long long n = 0;
     if (w < a.nwork) {
-        int lo = 0, hi = a.nbra;
-        while (hi - lo > 1) {
-            int mid = (lo + hi) >> 1;
-            if (a.prefix[mid] <= w) lo = mid; else hi = mid;
-        }
-        const CPair A = a.bra[lo];
-        const CPair B = a.ket[(int)(w - a.prefix[lo])];
+        const int row = k_find_row(a.prefix, a.nrows, w);
+        const int2 rw = a.rows[row];
+        const CPair A = a.bra[rw.x];
+        const CPair B = a.ket[rw.y + (int)(w - a.prefix[row])];
         const double qk0 = a.pp[B.poff].q;
         for (int ip = 0; ip < A.np; ++ip) {
             const double qb = a.pp[A.poff + ip].q;
@@ -92,13 +89,9 @@ __global__ void k_count_mix(KArgs a, int kind, unsigned long long *out)
     int ib = 0, jk = 0;
     bool need = false;
     if (valid) {
-        int lo = 0, hi = a.nbra;
-        while (hi - lo > 1) {
-            int mid = (lo + hi) >> 1;
-            if (a.prefix[mid] <= w) lo = mid; else hi = mid;
-        }
-        ib = lo;
-        jk = (int)(w - a.prefix[lo]);
+        const int row = k_find_row(a.prefix, a.nrows, w);
+        ib = a.rows[row].x;
+        jk = a.rows[row].y + (int)(w - a.prefix[row]);
         need = a.Qbra[ib] * a.Qket[jk] * k_dens_bound(a.Pm, a.nsh, a.bra[ib], a.ket[jk]) >= a.tau_mix;
     }
     const bool tile_fp64 = kind == 0 ? (__ballot(need ? 1 : 0) != 0ull) : need;
@@ -114,12 +107,12 @@ __global__ __launch_bounds__(64) void k_count_mix_chunks(KArgs a, const int2 *__
                                                           unsigned long long *out)
 {
     const int2 ch = chunks[blockIdx.x];
-    const int ib = ch.x;
-    const int cnt = (int)(a.prefix[ib + 1] - a.prefix[ib]);
-    const int jk = ch.y + (int)threadIdx.x;
-    const bool valid = jk < cnt;
+    const KRow row = k_row(a.rows, a.prefix, ch.x);
+    const int ib = row.ib;
+    const bool valid = ch.y + (int)threadIdx.x < row.cnt;
+    const int jk = row.kb + (valid ? ch.y + (int)threadIdx.x : ch.y);
     const CPair A = a.bra[ib];
-    const CPair B = a.ket[valid ? jk : ch.y];
+    const CPair B = a.ket[jk];
     const bool need = valid && a.Qbra[ib] * a.Qket[jk] * k_dens_bound(a.Pm, a.nsh, A, B) >= a.tau_mix;
     const bool tile_fp64 = __ballot(need ? 1 : 0) != 0ull;
     unsigned long long n = 0, m = 0;

@@ -105,27 +105,23 @@ __global__ __launch_bounds__(64) void kg_wave(KGArgs g)
     const int n = a.ld;
     for (int64_t w0 = (int64_t)blockIdx.x * C::RANGE; w0 < a.nwork; w0 += (int64_t)gridDim.x * C::RANGE) {
         const int64_t w1 = (w0 + C::RANGE < a.nwork) ? w0 + C::RANGE : a.nwork;
-        int lo = 0, hi = a.nbra;
-        while (hi - lo > 1) {
-            int mid = (lo + hi) >> 1;
-            if (a.prefix[mid] <= w0) lo = mid; else hi = mid;
-        }
-        int ib = lo;
-        int jk = (int)(w0 - a.prefix[ib]);
+        int row = k_find_row(a.prefix, a.nrows, w0);
+        int jk = (int)(w0 - a.prefix[row]);
         for (int64_t w = w0; w < w1; ++w) {
             if (w > w0) {
                 ++jk;
-                while (a.prefix[ib] + jk >= a.prefix[ib + 1]) {
-                    ++ib;
+                while (a.prefix[row] + jk >= a.prefix[row + 1]) {
+                    ++row;
                     jk = 0;
                 }
             }
+            const int ib = a.rows[row].x, kj = a.rows[row].y + jk;
             const CPair A = a.bra[ib];
-            const CPair B = a.ket[jk];
+            const CPair B = a.ket[kj];
             double sdeg = 1.0;
             if (A.sh1 == A.sh2) sdeg *= 0.5;
             if (B.sh1 == B.sh2) sdeg *= 0.5;
-            if (a.same && ib == jk) sdeg *= 0.5;
+            if (a.same && same_pair(A, B)) sdeg *= 0.5;
 
             // density tiles D_ac, D_ad, D_bc, D_bd
             for (int o = lane; o < C::ND_; o += 64) {
@@ -146,7 +142,7 @@ __global__ __launch_bounds__(64) void kg_wave(KGArgs g)
                 for (int kp = 0; kp < B.np; ++kp) {
                     const PrimPair pk = a.pp[B.poff + kp];
                     if (pb.q * pk.q < a.tau_prim) break;
-                    const QuartetGeo geo = quartet_geo(pb, pk);
+                    const QuartetGeo geo = quartet_geo(pb, pk, a.om2);
                     wave_boys<L + 1>(geo, a.boys, sF, lane);
                     wave_hpoly<L + 1>(geo, sH, lane);
                     if (lane >= 8 && lane < 11) {
@@ -365,18 +361,14 @@ __global__ __launch_bounds__(64) void kg_small(KGArgs g)
         int at[4] = {0, 0, 0, 0};
         const bool valid = w < a.nwork;
         if (valid) {
-            int lo = 0, hi = a.nbra;
-            while (hi - lo > 1) {
-                int mid = (lo + hi) >> 1;
-                if (a.prefix[mid] <= w) lo = mid; else hi = mid;
-            }
-            const int ib = lo, jk = (int)(w - a.prefix[lo]);
-            const CPair A = a.bra[ib], B = a.ket[jk];
+            const int row = k_find_row(a.prefix, a.nrows, w);
+            const int2 rw = a.rows[row];
+            const CPair A = a.bra[rw.x], B = a.ket[rw.y + (int)(w - a.prefix[row])];
             at[0] = A.at1; at[1] = A.at2; at[2] = B.at1; at[3] = B.at2;
             double sdeg = 1.0;
             if (A.sh1 == A.sh2) sdeg *= 0.5;
             if (B.sh1 == B.sh2) sdeg *= 0.5;
-            if (a.same && ib == jk) sdeg *= 0.5;
+            if (a.same && same_pair(A, B)) sdeg *= 0.5;
             const int n = a.ld;
             // weights W_{ab,cd} = -s (D_ac D_bd + D_ad D_bc)
             double W[NA * NB * NC * ND];
@@ -400,7 +392,7 @@ __global__ __launch_bounds__(64) void kg_small(KGArgs g)
                     const PrimPair pk = a.pp[B.poff + kp];
                     if (pb.q * pk.q < a.tau_prim) break;
                     double Fs[L + 2], X, Y, Z;
-                    quartet_fs<L + 1, double>(pb, pk, a.boys, Fs, X, Y, Z);
+                    quartet_fs<L + 1, double>(pb, pk, a.boys, Fs, X, Y, Z, a.om2);
                     double R[nherm(L + 1)];
                     r_build<L + 1, double>(Fs, X, Y, Z, R);
                     Etab<LC + 1, LD> Fx, Fy, Fz;

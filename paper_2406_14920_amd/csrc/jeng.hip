@@ -143,10 +143,10 @@ __global__ __launch_bounds__(64) void jeng_small(JArgs a)
                 T rp[LY + 1];
                 if constexpr (F32) {
                     float r;
-                    quartet_fs_scaled<L>(pb, pk, a.boys, Fs, X, Y, Z, r);
+                    quartet_fs_scaled<L>(pb, pk, a.boys, Fs, X, Y, Z, r, a.om2);
                     powers<LY>(r, rp);
                 } else {
-                    quartet_fs<L, T>(pb, pk, a.boys, Fs, X, Y, Z);
+                    quartet_fs<L, T>(pb, pk, a.boys, Fs, X, Y, Z, a.om2);
                 }
                 T R[nherm(L)];
                 r_build<L, T>(Fs, X, Y, Z, R);
@@ -238,7 +238,7 @@ __global__ __launch_bounds__(64) void jeng_wave(JArgs a)
         for (int kp = 0; kp < B.np; ++kp) {
             if (qi * pk.q < a.tau_prim) break;
             const PairLite pk_next = pair_lite(a.pp + B.poff + (kp + 1 < B.np ? kp + 1 : kp));
-            const QuartetGeo geo = quartet_geo(pb, pk);
+            const QuartetGeo geo = quartet_geo(pb, pk, a.om2);
             wave_boys<L, T>(geo, a.boys, sF, lane);
             wave_hpoly<L, T>(geo, sH, lane);
             const T *dt = Dt + (int64_t)(B.poff + kp - a.dt_base) * NY;

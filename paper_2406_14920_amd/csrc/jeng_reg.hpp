@@ -18,9 +18,12 @@ __host__ __device__ constexpr double hcoef(int t, int a)
     return v;
 }
 
-template <int LX, int LY, typename T>
+// dq: the ket's Hermite density, in registers or (large ket orders) read at
+// each use through the wave-uniform pointer into HBM; SCALE multiplies entry Q
+// by rp[|Q|] at use (single-precision form).
+template <int LX, int LY, bool SCALE, typename T>
 __device__ __forceinline__ void jeng_quartet_stream(const T *G, const T *px, const T *py,
-                                                    const T *pz, const T *dq, T *Jh)
+                                                    const T *pz, const T *__restrict__ dq, const T *rp, T *Jh)
 {
     constexpr int L = LX + LY;
     static_for<0, nherm(L)>([&](auto Nc) {
@@ -47,7 +50,11 @@ __device__ __forceinline__ void jeng_quartet_stream(const T *G, const T *px, con
                 static_for<0, v + 1>([&](auto pzc) {
                     constexpr int p3 = decltype(pzc)::value;
                     if constexpr (p1 + p2 + p3 <= LX && (t - p1) + (u - p2) + (v - p3) <= LY) {
-                        Jh[herm_idx(p1, p2, p3)] += r * dq[herm_idx(t - p1, u - p2, v - p3)];
+                        constexpr int Q = herm_idx(t - p1, u - p2, v - p3);
+                        if constexpr (SCALE)
+                            Jh[herm_idx(p1, p2, p3)] += r * (dq[Q] * rp[(t - p1) + (u - p2) + (v - p3)]);
+                        else
+                            Jh[herm_idx(p1, p2, p3)] += r * dq[Q];
                     }
                 });
             });
@@ -62,6 +69,7 @@ __global__ __launch_bounds__(64) void jeng_reg(JArgs a)
 {
     constexpr int L = LX + LY, NX = nherm(LX), NY = nherm(LY);
     constexpr bool F32 = sizeof(T) == 4;
+    constexpr bool DQMEM = NY > 20;  // ket density read at use instead of held in registers
     const int g = blockIdx.x * 64 + threadIdx.x;
     const bool valid = g < a.nbp;
     const int gi = valid ? g : a.nbp - 1;
@@ -109,24 +117,28 @@ __global__ __launch_bounds__(64) void jeng_reg(JArgs a)
                 T rp[LY + 1];
                 if constexpr (F32) {  // scaled single-precision form (md_device.hpp)
                     float r;
-                    quartet_fs_scaled<L>(pb, pk, a.boys, G, Xt, Yt, Zt, r);
+                    quartet_fs_scaled<L>(pb, pk, a.boys, G, Xt, Yt, Zt, r, a.om2);
                     powers<LY>(r, rp);
                 } else {
-                    quartet_fs<L, T>(pb, pk, a.boys, G, Xt, Yt, Zt);
+                    quartet_fs<L, T>(pb, pk, a.boys, G, Xt, Yt, Zt, a.om2);
                 }
                 powers<L>(Xt, px);
                 powers<L>(Yt, py);
                 powers<L>(Zt, pz);
                 const T *__restrict__ dt = Dt + (int64_t)(B.poff + kp - a.dt_base) * NY;
-                T dq[NY];
-                static_for<0, NY>([&](auto qc) {
-                    constexpr int k = decltype(qc)::value;
-                    if constexpr (F32)
-                        dq[k] = dt[k] * rp[herm_t(k) + herm_u(k) + herm_v(k)];
-                    else
-                        dq[k] = dt[k];
-                });
-                jeng_quartet_stream<LX, LY, T>(G, px, py, pz, dq, Jt);
+                if constexpr (DQMEM) {
+                    jeng_quartet_stream<LX, LY, F32, T>(G, px, py, pz, dt, rp, Jt);
+                } else {
+                    T dq[NY];
+                    static_for<0, NY>([&](auto qc) {
+                        constexpr int k = decltype(qc)::value;
+                        if constexpr (F32)
+                            dq[k] = dt[k] * rp[herm_t(k) + herm_u(k) + herm_v(k)];
+                        else
+                            dq[k] = dt[k];
+                    });
+                    jeng_quartet_stream<LX, LY, false, T>(G, px, py, pz, dq, rp, Jt);
+                }
             }
         }
         if constexpr (F32) {
@@ -153,11 +165,12 @@ __global__ __launch_bounds__(64) void jeng_reg(JArgs a)
     }
 }
 
-// register J-engine is used where its live set (Hermite J, Hermite density,
-// Boys values and coordinate powers) stays within about 115 doubles
+// register J-engine is used where its live set (Hermite J, Boys values,
+// coordinate powers and, up to 20 entries, the Hermite density) stays within
+// about 115 doubles
 __host__ __device__ constexpr bool jeng_reg_ok(int lx, int ly)
 {
-    return lx + ly >= 6 && nherm(lx) + nherm(ly) + 4 * (lx + ly + 1) <= 116;
+    return lx + ly >= 6 && nherm(lx) + 4 * (lx + ly + 1) + (nherm(ly) <= 20 ? nherm(ly) : 0) <= 116;
 }
 
 template <int LX, int LY>

@@ -67,12 +67,12 @@ __global__ __launch_bounds__(64) void k_pair(KPArgs a)
 
     const int lane = threadIdx.x;
     const int2 ch = a.chunks[blockIdx.x];
-    const int ib = ch.x;
-    const int cnt = (int)(a.prefix[ib + 1] - a.prefix[ib]);
-    const int jk = ch.y + lane;
-    const bool valid = jk < cnt;
+    const KRow row = k_row(a.rows, a.prefix, ch.x);
+    const int ib = row.ib;
+    const bool valid = ch.y + lane < row.cnt;
+    const int jk = row.kb + (valid ? ch.y + lane : ch.y);
     const CPair A = a.bra[ib];
-    const CPair B = a.ket[valid ? jk : ch.y];
+    const CPair B = a.ket[jk];
     if (!mix_take(a.mode, a.mode != 0 && valid &&
                               a.Qbra[ib] * a.Qket[jk] * k_dens_bound(a.Pm, a.nsh, A, B) >= a.tau_mix))
         return;
@@ -83,7 +83,7 @@ __global__ __launch_bounds__(64) void k_pair(KPArgs a)
     double s = 1.0;
     if (A.sh1 == A.sh2) s *= 0.5;
     if (B.sh1 == B.sh2) s *= 0.5;
-    if (a.same && ib == jk) s *= 0.5;
+    if (a.same && same_pair(A, B)) s *= 0.5;
 
     static_for<0, C::NABP * C::NCDP>([&](auto pc) {
         constexpr int pass = decltype(pc)::value;
@@ -106,10 +106,10 @@ __global__ __launch_bounds__(64) void k_pair(KPArgs a)
                 T rp[C::LCD + 1];  // r^|s| of the scaled single-precision form
                 if constexpr (sizeof(T) == 4) {
                     float r;
-                    quartet_fs_scaled<L>(pb, pk, a.boys, Fs, X, Y, Z, r);
+                    quartet_fs_scaled<L>(pb, pk, a.boys, Fs, X, Y, Z, r, a.om2);
                     powers<C::LCD>(r, rp);
                 } else {
-                    quartet_fs<L, T>(pb, pk, a.boys, Fs, X, Y, Z);
+                    quartet_fs<L, T>(pb, pk, a.boys, Fs, X, Y, Z, a.om2);
                 }
                 T R[nherm(L)];
                 r_build<L, T>(Fs, X, Y, Z, R);

@@ -24,13 +24,10 @@ __global__ __launch_bounds__(128) void k_small(KArgs a)
 
     int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (w >= a.nwork) return;
-    int lo = 0, hi = a.nbra;
-    while (hi - lo > 1) {
-        int mid = (lo + hi) >> 1;
-        if (a.prefix[mid] <= w) lo = mid; else hi = mid;
-    }
-    const int ib = lo;
-    const int jk = (int)(w - a.prefix[ib]);
+    const int r = k_find_row(a.prefix, a.nrows, w);
+    const int2 rw = a.rows[r];
+    const int ib = rw.x;
+    const int jk = rw.y + (int)(w - a.prefix[r]);
     const CPair A = a.bra[ib];
     const CPair B = a.ket[jk];
     if (!mix_take(a.mode, a.mode != 0 && a.Qbra[ib] * a.Qket[jk] * k_dens_bound(a.Pm, a.nsh, A, B) >= a.tau_mix))
@@ -61,9 +58,9 @@ __global__ __launch_bounds__(128) void k_small(KArgs a)
             T Fs[L + 1], X, Y, Z;
             if constexpr (F32) {
                 float r;
-                quartet_fs_scaled<L>(pb, pk, a.boys, Fs, X, Y, Z, r);
+                quartet_fs_scaled<L>(pb, pk, a.boys, Fs, X, Y, Z, r, a.om2);
             } else {
-                quartet_fs<L, T>(pb, pk, a.boys, Fs, X, Y, Z);
+                quartet_fs<L, T>(pb, pk, a.boys, Fs, X, Y, Z, a.om2);
             }
             T R[nherm(L)];
             r_build<L, T>(Fs, X, Y, Z, R);
@@ -129,7 +126,7 @@ __global__ __launch_bounds__(128) void k_small(KArgs a)
     double s = 1.0;
     if (A.sh1 == A.sh2) s *= 0.5;
     if (B.sh1 == B.sh2) s *= 0.5;
-    if (a.same && ib == jk) s *= 0.5;
+    if (a.same && same_pair(A, B)) s *= 0.5;
 
     // Each density element is loaded once: the loads could not otherwise be
     // hoisted past the atomics, and every block element would reload two.

@@ -138,25 +138,21 @@ __global__ __launch_bounds__(64) void k_wave(KArgs a)
     const int n = a.ld;
     for (int64_t w0 = (int64_t)blockIdx.x * C::RANGE; w0 < a.nwork; w0 += (int64_t)gridDim.x * C::RANGE) {
         const int64_t w1 = (w0 + C::RANGE < a.nwork) ? w0 + C::RANGE : a.nwork;
-        int lo = 0, hi = a.nbra;
-        while (hi - lo > 1) {
-            int mid = (lo + hi) >> 1;
-            if (a.prefix[mid] <= w0) lo = mid; else hi = mid;
-        }
-        int ib = lo;
-        int jk = (int)(w0 - a.prefix[ib]);
+        int row = k_find_row(a.prefix, a.nrows, w0);
+        int jk = (int)(w0 - a.prefix[row]);
         for (int64_t w = w0; w < w1; ++w) {
             if (w > w0) {
                 ++jk;
-                while (a.prefix[ib] + jk >= a.prefix[ib + 1]) {
-                    ++ib;
+                while (a.prefix[row] + jk >= a.prefix[row + 1]) {
+                    ++row;
                     jk = 0;
                 }
             }
+            const int ib = a.rows[row].x, kj = a.rows[row].y + jk;
             const CPair A = a.bra[ib];
-            const CPair B = a.ket[jk];
+            const CPair B = a.ket[kj];
             if (a.mode != 0) {  // uniform over the workgroup
-                const bool need = a.Qbra[ib] * a.Qket[jk] * k_dens_bound(a.Pm, a.nsh, A, B) >= a.tau_mix;
+                const bool need = a.Qbra[ib] * a.Qket[kj] * k_dens_bound(a.Pm, a.nsh, A, B) >= a.tau_mix;
                 if (need != (a.mode == 1)) continue;
             }
 
@@ -193,7 +189,7 @@ __global__ __launch_bounds__(64) void k_wave(KArgs a)
                     if (pb.q * pk.q < a.tau_prim) break;
                     // next ket primitive pair in flight while this one is evaluated
                     const PairLite pk_next = pair_lite(a.pp + B.poff + (kp + 1 < B.np ? kp + 1 : kp));
-                    const QuartetGeo g = quartet_geo(pb, pk);
+                    const QuartetGeo g = quartet_geo(pb, pk, a.om2);
                     wave_boys<L, T>(g, a.boys, sF, lane);
                     wave_hpoly<L, T>(g, sH, lane);
                     const T *ek = pick<T>(a.eprod_ket, a.eprodf_ket) + (int64_t)(B.poff + kp - a.pbase_ket) * C::SK;
@@ -288,7 +284,7 @@ __global__ __launch_bounds__(64) void k_wave(KArgs a)
             double s = 1.0;
             if (A.sh1 == A.sh2) s *= 0.5;
             if (B.sh1 == B.sh2) s *= 0.5;
-            if (a.same && ib == jk) s *= 0.5;
+            if (a.same && same_pair(A, B)) s *= 0.5;
             for (int o = lane; o < C::ND_; o += 64) {
                 int row, col;
                 if (o < NA * NC) { row = A.c1 + o / NC; col = B.c1 + o % NC; }
@@ -380,25 +376,21 @@ __global__ __launch_bounds__(64) void k_wave_x(KArgs a)
     const int n = a.ld;
     for (int64_t w0 = (int64_t)blockIdx.x * C::RANGE; w0 < a.nwork; w0 += (int64_t)gridDim.x * C::RANGE) {
         const int64_t w1 = (w0 + C::RANGE < a.nwork) ? w0 + C::RANGE : a.nwork;
-        int lo = 0, hi = a.nbra;
-        while (hi - lo > 1) {
-            int mid = (lo + hi) >> 1;
-            if (a.prefix[mid] <= w0) lo = mid; else hi = mid;
-        }
-        int ib = lo;
-        int jk = (int)(w0 - a.prefix[ib]);
+        int row = k_find_row(a.prefix, a.nrows, w0);
+        int jk = (int)(w0 - a.prefix[row]);
         for (int64_t w = w0; w < w1; ++w) {
             if (w > w0) {
                 ++jk;
-                while (a.prefix[ib] + jk >= a.prefix[ib + 1]) {
-                    ++ib;
+                while (a.prefix[row] + jk >= a.prefix[row + 1]) {
+                    ++row;
                     jk = 0;
                 }
             }
+            const int ib = a.rows[row].x, kj = a.rows[row].y + jk;
             const CPair A = a.bra[ib];
-            const CPair B = a.ket[jk];
+            const CPair B = a.ket[kj];
             if (a.mode != 0) {  // uniform over the workgroup
-                const bool need = a.Qbra[ib] * a.Qket[jk] * k_dens_bound(a.Pm, a.nsh, A, B) >= a.tau_mix;
+                const bool need = a.Qbra[ib] * a.Qket[kj] * k_dens_bound(a.Pm, a.nsh, A, B) >= a.tau_mix;
                 if (need != (a.mode == 1)) continue;
             }
 
@@ -442,7 +434,7 @@ __global__ __launch_bounds__(64) void k_wave_x(KArgs a)
                         const int kq = kb + lane / (L + 1), m = lane % (L + 1);
                         if (lane < NBAT * (L + 1) && kq < B.np) {
                             const PairLite pq = pair_lite(a.pp + B.poff + kq);
-                            const QuartetGeo gq = quartet_geo(pb, pq);
+                            const QuartetGeo gq = quartet_geo(pb, pq, a.om2);
                             const double F = boys_one(m, gq.T, a.boys);
                             double sc = sizeof(T) == 4 ? gq.pref0 : gq.pref;
                             const double m2a = sizeof(T) == 4 ? gq.w : -2.0 * gq.alpha;
@@ -595,7 +587,7 @@ __global__ __launch_bounds__(64) void k_wave_x(KArgs a)
             double s = 1.0;
             if (A.sh1 == A.sh2) s *= 0.5;
             if (B.sh1 == B.sh2) s *= 0.5;
-            if (a.same && ib == jk) s *= 0.5;
+            if (a.same && same_pair(A, B)) s *= 0.5;
             for (int o = lane; o < C::ND_; o += 64) {
                 int row, col;
                 if (o < NA * NC) { row = A.c1 + o / NC; col = B.c1 + o % NC; }

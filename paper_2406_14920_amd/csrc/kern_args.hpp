@@ -7,15 +7,21 @@
 namespace md {
 
 // One (bra class, ket class) exchange launch over canonical shell quartets
-// (ab|cd): bra pairs of class X sorted by Q descending, ket pairs of class Y
-// sorted the same way; bra i visits kets j < prefix[i+1]-prefix[i].
+// (ab|cd).  The pairs of each class are held in an exchange view: grouped by
+// contraction length (largest first), Q descending inside a group.  The work
+// list is a sequence of rows; row r pairs bra rows[r].x with the kets
+// rows[r].y, rows[r].y + 1, ... of one contraction group, of which the first
+// prefix[r+1]-prefix[r] are visited (those passing the Schwarz rule and, in a
+// class with itself, the canonical order).  Rows run group pair by group
+// pair, so neighbouring work items have equal contraction lengths.
 struct KArgs {
-    const CPair *bra;
-    const CPair *ket;
-    const int64_t *prefix;   // [nbra+1] cumulative ket counts
-    int64_t nwork;           // prefix[nbra]
-    int32_t nbra;
-    int32_t same;            // bra class == ket class (then j <= i)
+    const CPair *bra;        // exchange view of class X
+    const CPair *ket;        // exchange view of class Y
+    const int2 *rows;        // [nrows] (bra index, first ket index of the row's group)
+    const int64_t *prefix;   // [nrows+1] cumulative ket counts
+    int64_t nwork;           // prefix[nrows]
+    int32_t nrows;
+    int32_t same;            // bra class == ket class: the diagonal quartet (ab|ab) gets 1/2
     const PrimPair *pp;
     const double *boys;
     const double *D;         // Cartesian density, ld x ld
@@ -33,11 +39,37 @@ struct KArgs {
     const float *eprodf_ket;
     int32_t mode;
     double tau_mix;
-    const double *Qbra, *Qket;
+    const double *Qbra, *Qket;  // Q in exchange-view order
     const double *Pm;
     int32_t nsh;
     int32_t grid_cap;        // workgroups of a range-walking launch (0: default)
+    double om2;              // omega^2 of the operator erf(omega r)/r; 0: 1/r
 };
+
+// Row r of an exchange work list: bra pair, first ket index and ket count.
+struct KRow {
+    int ib, kb, cnt;
+};
+__device__ __forceinline__ KRow k_row(const int2 *rows, const int64_t *prefix, int r)
+{
+    const int2 v = rows[r];
+    return KRow{v.x, v.y, (int)(prefix[r + 1] - prefix[r])};
+}
+// row holding work item w (prefix ascending, prefix[0] = 0)
+__device__ __forceinline__ int k_find_row(const int64_t *prefix, int nrows, int64_t w)
+{
+    int lo = 0, hi = nrows;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (prefix[mid] <= w) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+// the diagonal quartet (ab|ab) of a class with itself
+__device__ __forceinline__ bool same_pair(const CPair &A, const CPair &B)
+{
+    return A.sh1 == B.sh1 && A.sh2 == B.sh2;
+}
 
 // J-engine launch: bra primitive pairs of class X against ket contracted
 // pairs [j0, j1) of class Y.
@@ -62,14 +94,17 @@ struct JArgs {
     int32_t mode;
     double tau_mix;
     const double *QDket;
+    double om2;              // omega^2 of the operator erf(omega r)/r; 0: 1/r
 };
 
-// Bra-shared exchange launch: one workgroup per (bra pair, 64-ket chunk).
+// Bra-shared exchange launch: one workgroup per (row, 64-ket chunk) of an
+// exchange work list (rows as in KArgs).
 struct KPArgs {
     const CPair *bra;
     const CPair *ket;
-    const int2 *chunks;      // (bra index, first ket) of every workgroup
-    const int64_t *prefix;   // cumulative ket counts of the bras
+    const int2 *chunks;      // (row, first ket of the row) of every workgroup
+    const int2 *rows;
+    const int64_t *prefix;   // cumulative ket counts of the rows
     int32_t same;
     const PrimPair *pp;
     const double *eprod_bra;  // class-X products, pair g at (g - pbase_bra) * SB
@@ -88,6 +123,7 @@ struct KPArgs {
     const double *Qbra, *Qket;
     const double *Pm;
     int32_t nsh;
+    double om2;              // omega^2 of the operator erf(omega r)/r; 0: 1/r
 };
 
 // Exchange-gradient launch: the exchange work list plus the per-workgroup

@@ -101,9 +101,23 @@ __device__ __forceinline__ void r_build(const T *Fs, T X, T Y, T Z, T *R)
 // double precision whatever T is (their range exceeds single precision for
 // tight exponents); only the finished G_m and the separation P - Q are
 // rounded to T.
+//
+// The long-range operator erf(omega r)/r (eq. eri_longrange_formula) takes
+// the same form with alpha -> alpha s and the prefactor times sqrt(s),
+// s = omega^2 / (alpha + omega^2); om2 = omega^2, 0 for the Coulomb operator.
+__device__ __forceinline__ void longrange_scale(double om2, double &alpha, double &pref)
+{
+    if (om2 > 0.0) {
+        const double s = om2 / (alpha + om2);
+        alpha *= s;
+        pref *= sqrt(s);
+    }
+}
+
 template <int L, typename T>
 __device__ __forceinline__ void quartet_fs(const PrimPair &pb, const PrimPair &pk,
-                                           const double *__restrict__ btab, T *Fs, T &X, T &Y, T &Z)
+                                           const double *__restrict__ btab, T *Fs, T &X, T &Y, T &Z,
+                                           double om2)
 {
     double p = pb.p, q = pk.p;
     double rpq = 1.0 / (p + q);
@@ -114,10 +128,11 @@ __device__ __forceinline__ void quartet_fs(const PrimPair &pb, const PrimPair &p
     X = (T)dx;
     Y = (T)dy;
     Z = (T)dz;
+    double pref = kTwoPi52 * pb.K * pk.K / (p * q) * sqrt(rpq);
+    longrange_scale(om2, alpha, pref);
     double Tb = alpha * (dx * dx + dy * dy + dz * dz);
     double F[L + 1];
     boys_all<L>(Tb, F, btab);
-    double pref = kTwoPi52 * pb.K * pk.K / (p * q) * sqrt(rpq);
     double m2a = -2.0 * alpha;
     double s = pref;
 #pragma unroll
@@ -140,17 +155,27 @@ __device__ __forceinline__ void quartet_fs(const PrimPair &pb, const PrimPair &p
 // every factor of order one.  The ket factor is stored per pair as
 // K_cd E^{cd}_s (2q)^{|s|/2} and multiplied by r^{|s|}, r = sqrt(p/q).
 // F_m, the powers and the prefactor are formed in double and then rounded.
+// Long-range operator: alpha -> alpha s0, w -> w s0, prefactor times
+// sqrt(s0), s0 = omega^2/(alpha + omega^2).
 template <int L>
 __device__ __forceinline__ void quartet_fs_scaled(const PrimPair &pb, const PrimPair &pk,
                                                   const double *__restrict__ btab, float *Fs, float &X,
-                                                  float &Y, float &Z, float &r)
+                                                  float &Y, float &Z, float &r, double om2)
 {
     const double p = pb.p, q = pk.p;
     const double rpq = 1.0 / (p + q);
-    const double alpha = p * q * rpq;
+    double alpha = p * q * rpq;
     const double dx = pb.P[0] - pk.P[0];
     const double dy = pb.P[1] - pk.P[1];
     const double dz = pb.P[2] - pk.P[2];
+    double s = kTwoPi52 / (p * q) * sqrt(rpq);
+    double w = -q * rpq;
+    if (om2 > 0.0) {
+        const double s0 = om2 / (alpha + om2);
+        alpha *= s0;
+        w *= s0;
+        s *= sqrt(s0);
+    }
     double F[L + 1];
     boys_all<L>(alpha * (dx * dx + dy * dy + dz * dz), F, btab);
     const double c = sqrt(2.0 * p);
@@ -158,8 +183,6 @@ __device__ __forceinline__ void quartet_fs_scaled(const PrimPair &pb, const Prim
     Y = (float)(c * dy);
     Z = (float)(c * dz);
     r = (float)sqrt(p / q);
-    double s = kTwoPi52 / (p * q) * sqrt(rpq);
-    const double w = -q * rpq;
 #pragma unroll
     for (int m = 0; m <= L; ++m) {
         Fs[m] = (float)(s * F[m]);

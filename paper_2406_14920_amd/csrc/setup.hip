@@ -147,7 +147,7 @@ __global__ __launch_bounds__(64) void schwarz_wave(const CPair *__restrict__ cp,
             const PrimPair pb = pp[A.poff + ip];
             for (int kp = 0; kp < A.np; ++kp) {
                 const PrimPair pk = pp[A.poff + kp];
-                const QuartetGeo g = quartet_geo(pb, pk);
+                const QuartetGeo g = quartet_geo(pb, pk, 0.0);  // screening bounds of 1/r
                 wave_boys<L>(g, boys, sF, lane);
                 wave_powers<L>(g, sPow, lane);
                 if (lane >= 61) {

@@ -29,12 +29,15 @@ __device__ __forceinline__ int herm_idx_rt(int t, int u, int v)
 // Geometry of one primitive quartet; the same on every lane.
 // c, w, pref0 and r serve the scaled single-precision form (md_device.hpp):
 // c = sqrt(2p), w = -q/(p+q), pref0 = 2 pi^{5/2}/(pq sqrt(p+q)), r = sqrt(p/q).
+// With the long-range operator erf(omega r)/r (om2 = omega^2 > 0), alpha, T
+// and w carry the factor s0 = omega^2/(alpha + omega^2) and the prefactors
+// sqrt(s0) (eq. eri_longrange_formula).
 struct QuartetGeo {
     double X, Y, Z, T, alpha, pref;
     double c, w, pref0, r;
 };
 
-__device__ __forceinline__ QuartetGeo quartet_geo(const PrimPair &pb, const PrimPair &pk)
+__device__ __forceinline__ QuartetGeo quartet_geo(const PrimPair &pb, const PrimPair &pk, double om2)
 {
     QuartetGeo g;
     double p = pb.p, q = pk.p;
@@ -45,9 +48,16 @@ __device__ __forceinline__ QuartetGeo quartet_geo(const PrimPair &pb, const Prim
     g.Z = pb.P[2] - pk.P[2];
     g.T = g.alpha * (g.X * g.X + g.Y * g.Y + g.Z * g.Z);
     g.pref0 = kTwoPi52 / (p * q) * sqrt(rpq);
+    g.w = -q * rpq;
+    if (om2 > 0.0) {  // long-range operator (eq. eri_longrange_formula)
+        const double s0 = om2 / (g.alpha + om2);
+        g.alpha *= s0;
+        g.T *= s0;
+        g.w *= s0;
+        g.pref0 *= sqrt(s0);
+    }
     g.pref = g.pref0 * pb.K * pk.K;
     g.c = sqrt(2.0 * p);
-    g.w = -q * rpq;
     g.r = sqrt(p / q);
     return g;
 }
@@ -70,7 +80,7 @@ __device__ __forceinline__ PairLite pair_lite(const PrimPair *__restrict__ r)
     return x;
 }
 
-__device__ __forceinline__ QuartetGeo quartet_geo(const PrimPair &pb, const PairLite &pk)
+__device__ __forceinline__ QuartetGeo quartet_geo(const PrimPair &pb, const PairLite &pk, double om2)
 {
     QuartetGeo g;
     double p = pb.p, q = pk.p;
@@ -81,9 +91,16 @@ __device__ __forceinline__ QuartetGeo quartet_geo(const PrimPair &pb, const Pair
     g.Z = pb.P[2] - pk.P2;
     g.T = g.alpha * (g.X * g.X + g.Y * g.Y + g.Z * g.Z);
     g.pref0 = kTwoPi52 / (p * q) * sqrt(rpq);
+    g.w = -q * rpq;
+    if (om2 > 0.0) {  // long-range operator (eq. eri_longrange_formula)
+        const double s0 = om2 / (g.alpha + om2);
+        g.alpha *= s0;
+        g.T *= s0;
+        g.w *= s0;
+        g.pref0 *= sqrt(s0);
+    }
     g.pref = g.pref0 * pb.K * pk.K;
     g.c = sqrt(2.0 * p);
-    g.w = -q * rpq;
     g.r = sqrt(p / q);
     return g;
 }

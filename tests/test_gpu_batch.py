@@ -182,3 +182,29 @@ def test_batch_on_default_stream_is_ordered():
     b.close()
     for jk in jks:
         jk.close()
+
+
+def test_autotune_cache_roundtrip(tmp_path):
+    """A tuning saved to the JSON cache is applied to a fresh context of the
+    same workload without timing, and gives the same launch shapes and the
+    same J, K (to the atomic-order bar)."""
+    torch = _torch()
+    from paper_2406_14920_amd import JK
+    mol = synth.small_cluster(5, 11, tau=1e-11, name="c5")
+    cache = str(tmp_path / "tuning.json")
+    jk1 = JK.from_molecule(mol)
+    P = torch.tensor(mol.P, dtype=torch.float64, device="cuda")
+    t1 = jk1.autotune(P, reps=1, cache=cache, key="c5")
+    J1, K1 = jk1.jk(P)
+    jk2 = JK.from_molecule(mol)
+    t2 = jk2.autotune(P, reps=1, cache=cache, key="c5")
+    assert t1 == t2
+    J2, K2 = jk2.jk(P)
+    torch.cuda.synchronize()
+    _close(J2, J1, "J after cached tuning")
+    _close(K2, K1, "K after cached tuning")
+    import json
+    store = json.load(open(cache))
+    assert "c5/fp64" in store and store["c5/fp64"]["exchange"]
+    jk1.close()
+    jk2.close()

@@ -132,26 +132,95 @@ def test_repeat_builds_agree():
     jk.close()
 
 
-def test_mol40_sampled_blocks():
-    """40-atom workload at full size, default thresholds, sampled shell blocks."""
-    mol = synth.mol40()
-    print("case mol40 nbf=%d" % mol.nbf, flush=True)
-    J, K, st = _gpu_jk(mol)
-    print("  quartets %d pairs %d" % (st["n_quartets"], st["n_pairs"]), flush=True)
-    B = oracle.OBasis(mol)
-    rng = np.random.default_rng(40)
+def _sample_blocks(mol, n_per, seed, extra=0):
+    """Shell pairs (a, b) covering every ordered (l_a, l_b), n_per of each,
+    plus `extra` drawn at random."""
+    rng = np.random.default_rng(seed)
     ls = np.array([s.l for s in mol.shells])
     picks = []
-    for la, lb in [(3, 3), (3, 0), (2, 1), (0, 0), (1, 1), (3, 2)]:
-        a = int(rng.choice(np.where(ls == la)[0]))
-        b = int(rng.choice(np.where(ls == lb)[0]))
-        picks.append((a, b))
-    Jb, Kb = oracle.jk_blocks(mol, picks, picks, basis_obj=B)
+    for la in range(4):
+        for lb in range(4):
+            ia, ib = np.where(ls == la)[0], np.where(ls == lb)[0]
+            if len(ia) == 0 or len(ib) == 0:
+                continue
+            for _ in range(n_per):
+                picks.append((int(rng.choice(ia)), int(rng.choice(ib))))
+    for _ in range(extra):
+        picks.append((int(rng.integers(len(ls))), int(rng.integers(len(ls)))))
+    return picks
+
+
+def _check_blocks(mol, J, K, picks, tau_prim=None, tag=""):
+    B = oracle.OBasis(mol)
+    Jb, Kb = oracle.jk_blocks(mol, picks, picks, basis_obj=B, tau_prim=tau_prim)
     scaleJ, scaleK = np.abs(J).max(), np.abs(K).max()
+    worst = 0.0
     for (a, b), jb, kb in zip(picks, Jb, Kb):
         ra = slice(B.ao_off[a], B.ao_off[a] + 2 * B.l[a] + 1)
         rb = slice(B.ao_off[b], B.ao_off[b] + 2 * B.l[b] + 1)
-        ej = np.abs(J[ra, rb] - jb).max()
-        ek = np.abs(K[ra, rb] - kb).max()
-        print("  block (%d,%d) l=(%d,%d): dJ=%.2e dK=%.2e" % (a, b, B.l[a], B.l[b], ej, ek), flush=True)
-        assert ej <= RTOL * scaleJ and ek <= RTOL * scaleK
+        ej = np.abs(J[ra, rb] - jb).max() / scaleJ
+        ek = np.abs(K[ra, rb] - kb).max() / scaleK
+        worst = max(worst, ej, ek)
+        assert ej <= RTOL and ek <= RTOL, (tag, a, b, ej, ek)
+    print("  %s: %d blocks, worst relative error %.2e" % (tag, len(picks), worst), flush=True)
+
+
+def test_mol40_sampled_blocks():
+    """40-atom workload at full size, contracted-quartet Schwarz rule only (no
+    primitive screen on either side): 48 sampled shell blocks of J and K,
+    three of every ordered (l_a, l_b)."""
+    mol = synth.mol40()
+    print("case mol40 nbf=%d prim_tau=0" % mol.nbf, flush=True)
+    J, K, st = _gpu_jk(mol, tau_prim=0.0)
+    print("  quartets %d pairs %d" % (st["n_quartets"], st["n_pairs"]), flush=True)
+    _check_blocks(mol, J, K, _sample_blocks(mol, 3, 40), tau_prim=0.0, tag="mol40")
+
+
+def test_mol40_default_screen_blocks():
+    """40-atom workload with the default primitive screen on both sides (the
+    bench configuration): 16 sampled blocks, one of every ordered (l_a, l_b)."""
+    mol = synth.mol40()
+    J, K, _ = _gpu_jk(mol)
+    _check_blocks(mol, J, K, _sample_blocks(mol, 1, 41), tag="mol40 default screen")
+
+
+def test_tm62_sampled_blocks():
+    """Transition-metal-like workload at full size (two heavy centres with
+    exponents up to 2e5 and 60 light atoms, 1336 functions): sampled J and K
+    blocks against the oracle, at least eight on the heavy centres' shells;
+    FP64 to 1e-10 relative, and the mixed-precision build (FP32 share,
+    threshold 1e-5) to 1e-6 absolute on the same blocks."""
+    torch = _torch()
+    from paper_2406_14920_amd import JK
+    mol = synth.tm62()
+    print("case tm62 nbf=%d" % mol.nbf, flush=True)
+    jk = JK.from_molecule(mol)
+    P = torch.tensor(mol.P, dtype=torch.float64, device="cuda")
+    J, K = (t.cpu().numpy() for t in jk.jk(P))
+    jk.set_precision("mixed")
+    Jm, Km = (t.cpu().numpy() for t in jk.jk(P))
+    st = jk.stats()
+    jk.close()
+    print("  quartets %d  fp32 share %d" % (st["n_quartets"], st["n_quartets_fp32"]), flush=True)
+    atoms = np.array([s.atom for s in mol.shells])
+    heavy = [i for i, a in enumerate(atoms) if a < 2]
+    rng = np.random.default_rng(62)
+    picks = _sample_blocks(mol, 1, 62)
+    for _ in range(4):  # heavy-heavy and heavy-light blocks
+        picks.append((int(rng.choice(heavy)), int(rng.choice(heavy))))
+        picks.append((int(rng.choice(heavy)), int(rng.integers(len(atoms)))))
+    B = oracle.OBasis(mol)
+    Jb, Kb = oracle.jk_blocks(mol, picks, picks, basis_obj=B)
+    scaleJ, scaleK = np.abs(J).max(), np.abs(K).max()
+    worst, worst_m = 0.0, 0.0
+    for (a, b), jb, kb in zip(picks, Jb, Kb):
+        ra = slice(B.ao_off[a], B.ao_off[a] + 2 * B.l[a] + 1)
+        rb = slice(B.ao_off[b], B.ao_off[b] + 2 * B.l[b] + 1)
+        ej = np.abs(J[ra, rb] - jb).max() / scaleJ
+        ek = np.abs(K[ra, rb] - kb).max() / scaleK
+        em = max(np.abs(Jm[ra, rb] - jb).max(), np.abs(Km[ra, rb] - kb).max())
+        worst, worst_m = max(worst, ej, ek), max(worst_m, em)
+        assert ej <= RTOL and ek <= RTOL, ("tm62 fp64", a, b, ej, ek)
+        assert em <= 1e-6, ("tm62 mixed", a, b, em)
+    print("  tm62: %d blocks, FP64 worst relative %.2e, mixed worst absolute %.2e" % (len(picks), worst, worst_m),
+          flush=True)
