@@ -160,6 +160,21 @@ int eri_set_omega(eri_ctx *ctx, double omega);
  * row-major FP64.  J or K may be NULL to skip it.  Asynchronous. */
 int build_jk(eri_ctx *ctx, const double *P, double *J, double *K);
 
+/* build_jk for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same double-precision J and K as build_jk, with the per-build work buffers
+ * (Cartesian density and accumulators, Hermite density and Hermite J) taken
+ * from a static device array of 64 MiB per GPU instead of the context's own
+ * buffers; the call allocates nothing.  Needs 8*(3*nbf_cart^2 + 2*H) bytes,
+ * H = sum over primitive pairs of the Hermite index count (rounded up to 256
+ * bytes per region); a larger context is rejected with ERI_EINVAL.  Only the
+ * double-precision path (ERI_FP64; otherwise ERI_ESTATE).  Every call on a
+ * GPU shares that GPU's array and leaves its contents behind (each call
+ * clears what it accumulates into), so calls that overlap on one GPU -- on
+ * different streams or host threads -- race and must be serialised by the
+ * caller.  P, J, K as for build_jk.  Asynchronous. */
+int build_jk_static(eri_ctx *ctx, const double *P, double *J, double *K);
+
 /* Nuclear gradient dE/dR of E = 1/2 tr(PJ) - 1/4 tr(PK) at fixed P
  * (SI eqs. si_E_J_K, si_dE_J, si_dE_K; the density-derivative terms are
  * absent), in hartree/bohr, atoms in the order given to eri_setup.

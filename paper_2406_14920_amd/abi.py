@@ -65,7 +65,7 @@ class eri_kernel_time(ctypes.Structure):
 EXPORTS = ["eri_default_opts", "eri_setup", "eri_nbf", "eri_set_geometry", "eri_set_precision",
            "build_jk", "jk_grad", "eri_energy", "eri_set_profiling", "eri_profile_read", "eri_stats", "eri_destroy",
            "eri_last_error", "eri_batch_create", "eri_batch_build_jk", "eri_batch_destroy",
-           "eri_autotune", "eri_tuning", "eri_set_omega", "eri_get_tuning",
+           "eri_autotune", "eri_tuning", "build_jk_static", "eri_set_omega", "eri_get_tuning",
            "eri_set_tuning"]
 
 _lib = None
@@ -92,6 +92,7 @@ def load(path: str = LIB_PATH):
     L.eri_get_tuning.argtypes = [vp, ctypes.POINTER(eri_tuning_t)]
     L.eri_set_tuning.argtypes = [vp, ctypes.POINTER(eri_tuning_t)]
     L.build_jk.argtypes = [vp, vp, vp, vp]
+    L.build_jk_static.argtypes = [vp, vp, vp, vp]
     L.jk_grad.argtypes = [vp, vp, vp, vp]
     L.eri_energy.argtypes = [vp, vp, vp, vp, vp]
     L.eri_stats.argtypes = [vp, ctypes.POINTER(eri_stats_t)]
@@ -220,6 +221,12 @@ def eri_set_tuning(ctx: int, tuning: dict) -> None:
 
 def eri_set_omega(ctx: int, omega: float) -> None:
     _check(load().eri_set_omega(ctypes.c_void_p(ctx), float(omega)))
+
+
+def build_jk_static(ctx: int, P, J, K) -> None:
+    """build_jk with the work buffers in the library's static device array
+    (allocates nothing; double precision only)."""
+    _check(load().build_jk_static(ctypes.c_void_p(ctx), _ptr(P), _ptr(J), _ptr(K)))
 
 
 def jk_grad(ctx: int, P, grad, E=None) -> None:

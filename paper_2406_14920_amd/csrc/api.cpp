@@ -236,7 +236,8 @@ struct eri_ctx {
     size_t eprod_off[kPairClasses] = {};
     DevBuf<double> d_boys;
     DevBuf<double> d_Pc, d_Jacc, d_Kacc, d_Dt, d_Jh;
-    // the per-build work buffers the kernels are handed
+    // the per-build work buffers the kernels are handed: the context's own
+    // (above), or regions of the static scratch array during build_jk_static
     struct Work {
         double *Pc = nullptr, *Jacc = nullptr, *Kacc = nullptr, *Dt = nullptr, *Jh = nullptr;
     } wk;
@@ -744,7 +745,44 @@ ShellMap shell_map(const eri_ctx *c)
 
 bool ctx_ok(const eri_ctx *c) { return c && c->magic == 0x4d444a4b; }
 
+// ---------------------------------------------------------------------------
+// Static scratch of the allocation-free build (build_jk_static): the Cartesian
+// density and accumulators and the Hermite density / Hermite J of one build,
+// carved from a file-scope device array.  Each GPU holds its own copy; its
+// address is looked up once per device (at eri_setup, with that device
+// current) and kept, since the array's name is not a device address in host
+// code.
+// ---------------------------------------------------------------------------
+constexpr size_t kScratchDoubles = size_t(8) << 20;  // 64 MiB per device
+constexpr int kMaxDevices = 64;
+__device__ __align__(256) double scratch[kScratchDoubles];
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[kMaxDevices] = {};
 
+// Address of this device's scratch array (the device must be current).
+double *scratch_address(int dev)
+{
+    if (dev < 0 || dev >= kMaxDevices) {
+        set_err(ERI_ESTATE, "device %d outside the %d devices the scratch table covers", dev, kMaxDevices);
+        throw HipError{ERI_ESTATE};
+    }
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        HIPCHK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        g_scratch_ptr[dev] = (double *)ptr;
+    }
+    return g_scratch_ptr[dev];
+}
+
+// Doubles of scratch one build of this context needs (each region rounded up
+// to 256 bytes).
+size_t scratch_need(const eri_ctx *c)
+{
+    auto r = [](size_t n) { return (n + 31) / 32 * 32; };
+    const size_t nc2 = (size_t)c->nbf_cart * c->nbf_cart;
+    return 3 * r(nc2) + 2 * r(c->d_Dt.n);
+}
 
 // Does this launch take the single-precision share (two launches, modes 1/2)?
 bool j_split(const eri_ctx *c, int X, int Y)
@@ -1153,6 +1191,7 @@ int eri_setup(const eri_shell *shells, int32_t nshell, const eri_atom *atoms, in
     c->natom = natom;
     try {
         HIPCHK(hipGetDevice(&c->device));
+        (void)scratch_address(c->device);  // once per device: the scratch array's address
         for (auto &x : c->aux) HIPCHK(hipStreamCreateWithFlags(&x, hipStreamNonBlocking));
         HIPCHK(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
         HIPCHK(hipEventCreateWithFlags(&c->ev_kzero, hipEventDisableTiming));
@@ -1268,6 +1307,37 @@ int build_jk(eri_ctx *ctx, const double *P, double *J, double *K)
         return e.code;
     }
     return ERI_OK;
+}
+
+int build_jk_static(eri_ctx *ctx, const double *P, double *J, double *K)
+{
+    if (!ctx_ok(ctx)) return set_err(ERI_ESTATE, "invalid context");
+    if (!P) return set_err(ERI_EINVAL, "P is NULL");
+    if (ctx->opts.precision != ERI_FP64)
+        return set_err(ERI_ESTATE, "build_jk_static runs the double-precision path only (precision %d)",
+                       ctx->opts.precision);
+    const size_t need = scratch_need(ctx);
+    if (need > kScratchDoubles)
+        return set_err(ERI_EINVAL, "build_jk_static: this context needs %zu bytes of scratch, more than the "
+                                   "%zu-byte static array (nbf_cart %d)",
+                       need * sizeof(double), kScratchDoubles * sizeof(double), ctx->nbf_cart);
+    double *base = nullptr;
+    try {
+        base = scratch_address(ctx->device);
+    } catch (const HipError &e) {
+        return e.code;
+    }
+    auto r = [](size_t n) { return (n + 31) / 32 * 32; };
+    const size_t nc2 = (size_t)ctx->nbf_cart * ctx->nbf_cart;
+    const eri_ctx::Work own = ctx->wk;
+    ctx->wk.Pc = base;
+    ctx->wk.Jacc = base + r(nc2);
+    ctx->wk.Kacc = base + 2 * r(nc2);
+    ctx->wk.Dt = base + 3 * r(nc2);
+    ctx->wk.Jh = base + 3 * r(nc2) + r(ctx->d_Dt.n);
+    const int rc = build_jk(ctx, P, J, K);
+    ctx->wk = own;
+    return rc;
 }
 
 int jk_grad(eri_ctx *ctx, const double *P, double *grad, double *E)

@@ -60,6 +60,9 @@ def test_null_context_is_a_state_error():
     with pytest.raises(abi.EriError) as e:
         abi.build_jk(0, 1, 2, 3)
     assert e.value.code == abi.ERI_ESTATE
+    with pytest.raises(abi.EriError) as e:
+        abi.build_jk_static(0, 1, 2, 3)
+    assert e.value.code == abi.ERI_ESTATE
     abi.eri_destroy(0)  # NULL is accepted
 
 
