@@ -231,7 +231,7 @@ struct eri_ctx {
     DevBuf<int2> d_rows;
     DevBuf<CPair> d_kcp;
     DevBuf<double> d_kQ;
-    DevBuf<int2> d_chunks;
+    DevBuf<int4> d_chunks;
     DevBuf<double> d_eprod;
     size_t eprod_off[kPairClasses] = {};
     DevBuf<double> d_boys;
@@ -485,17 +485,27 @@ void build_pairs(eri_ctx *c)
     c->grad_ready = false;
 
     // 4. exchange work lists.  The exchange kernels see each class through a
-    // view grouped by contraction length (number of primitive pairs, rounded
-    // up to a power of two; largest first) and Q-sorted inside a group, so
-    // that the lanes of a wavefront, which take neighbouring work items, run
-    // primitive loops of equal length.  A row pairs one bra with the kets of
-    // one group; the kets it visits (Q_i Q_j >= tau and, in a class with
-    // itself, j not after i in the Q order) form a prefix of that group.
-    auto group_of = [](int np) {
+    // view grouped by contraction length and by the pair's first shell (the
+    // shell c of a ket (cd|)), Q-sorted inside a group.  A row pairs one bra with the kets of one
+    // group; the kets it visits (Q_i Q_j >= tau and, in a class with itself,
+    // j not after i in the Q order) form a prefix of the group.  Rows run bra
+    // by bra, so neighbouring work items share the bra and, inside a row, the
+    // shell c: their exchange contributions K_ac and K_bc go to the same
+    // elements and are summed before one atomic addition per element.
+    // Groups are keyed by (contraction length, first shell): the length (the
+    // number of primitive pairs rounded up to a power of two, largest first)
+    // keeps the primitive loops of neighbouring lanes equally long, the shell
+    // gives the shared exchange elements.
+    auto np_group = [](int np) {
         int g = 0;
         while ((1 << g) < np) ++g;
         return g;
     };
+    auto key_less = [&](const CPair &x, const CPair &y) {
+        const int gx = np_group(x.np), gy = np_group(y.np);
+        return gx != gy ? gx > gy : x.sh1 < y.sh1;
+    };
+    auto key_same = [&](const CPair &x, const CPair &y) { return np_group(x.np) == np_group(y.np) && x.sh1 == y.sh1; };
     c->kcp.assign(c->cp.size(), CPair{});
     c->kQ.assign(c->cp.size(), 0.0);
     std::vector<int> vorig(c->cp.size());          // view index -> Q-order index (inside the class)
@@ -504,20 +514,18 @@ void build_pairs(eri_ctx *c)
         const int b = c->cp_base[X], nX = c->ncp[X];
         std::vector<int> idx(nX);
         for (int k = 0; k < nX; ++k) idx[k] = k;
-        std::stable_sort(idx.begin(), idx.end(),
-                         [&](int x, int y) { return group_of(c->cp[b + x].np) > group_of(c->cp[b + y].np); });
+        std::stable_sort(idx.begin(), idx.end(), [&](int x, int y) { return key_less(c->cp[b + x], c->cp[b + y]); });
         for (int r = 0; r < nX; ++r) {
             c->kcp[b + r] = c->cp[b + idx[r]];
             c->kQ[b + r] = c->Q[b + idx[r]];
             vorig[b + r] = idx[r];
-            const int g = group_of(c->cp[b + idx[r]].np);
-            if (r == 0 || g != group_of(c->cp[b + idx[r - 1]].np)) groups[X].push_back({r, 0});
+            if (r == 0 || !key_same(c->cp[b + idx[r]], c->cp[b + idx[r - 1]])) groups[X].push_back({r, 0});
             groups[X].back()[1]++;
         }
     }
     std::vector<int64_t> prefix;
     std::vector<int2> rows;
-    std::vector<int2> chunks;
+    std::vector<int4> chunks;
     c->kwork.clear();
     c->n_quartets = 0;
     c->eris_sph = c->eris_cart = 0.0;
@@ -525,43 +533,53 @@ void build_pairs(eri_ctx *c)
         for (int Y = 0; Y <= X; ++Y) {
             eri_ctx::KWork w{X, Y, (int64_t)prefix.size(), 0, -1, 0, (int64_t)rows.size(), 0};
             const int bX = c->cp_base[X], bY = c->cp_base[Y];
+            const bool kp = uses_k_pair(kPairL[X][0], kPairL[X][1], kPairL[Y][0], kPairL[Y][1]);
+            if (kp) w.choff = (int64_t)chunks.size();
             int64_t acc = 0;
             prefix.push_back(0);
-            for (const auto &gx : groups[X])
-                for (const auto &gy : groups[Y])
-                    for (int i = gx[0]; i < gx[0] + gx[1]; ++i) {
-                        const double Qi = c->kQ[bX + i];
-                        const int j0 = gy[0], j1 = gy[0] + gy[1];
-                        int lo = j0, hi = j1;  // Q descending inside the group
-                        while (lo < hi) {
-                            const int mid = (lo + hi) / 2;
-                            if (Qi * c->kQ[bY + mid] >= tau) lo = mid + 1; else hi = mid;
-                        }
-                        int cnt = lo - j0;
-                        if (X == Y) {  // Q-order index ascending inside the group
-                            const int oi = vorig[bX + i];
-                            int l2 = j0, h2 = j1;
-                            while (l2 < h2) {
-                                const int mid = (l2 + h2) / 2;
-                                if (vorig[bY + mid] <= oi) l2 = mid + 1; else h2 = mid;
-                            }
-                            cnt = std::min(cnt, l2 - j0);
-                        }
-                        if (cnt <= 0) continue;
-                        rows.push_back(make_int2(i, j0));
-                        acc += cnt;
-                        prefix.push_back(acc);
+            for (int i = 0; i < c->ncp[X]; ++i) {
+                const double Qi = c->kQ[bX + i];
+                const int oi = vorig[bX + i];
+                const int r_first = (int)((int64_t)rows.size() - w.roff);
+                const int64_t w_first = acc;
+                for (const auto &gy : groups[Y]) {
+                    const int j0 = gy[0], j1 = gy[0] + gy[1];
+                    int lo = j0, hi = j1;  // Q descending inside the group
+                    while (lo < hi) {
+                        const int mid = (lo + hi) / 2;
+                        if (Qi * c->kQ[bY + mid] >= tau) lo = mid + 1; else hi = mid;
                     }
+                    int cnt = lo - j0;
+                    if (X == Y) {  // Q-order index ascending inside the group
+                        int l2 = j0, h2 = j0 + cnt;
+                        while (l2 < h2) {
+                            const int mid = (l2 + h2) / 2;
+                            if (vorig[bY + mid] <= oi) l2 = mid + 1; else h2 = mid;
+                        }
+                        cnt = l2 - j0;
+                    }
+                    if (cnt <= 0) continue;
+                    rows.push_back(make_int2(i, j0));
+                    acc += cnt;
+                    prefix.push_back(acc);
+                }
+                // bra-shared chunks: 64 consecutive work items of this bra
+                // (first row, offset in it, items, rows spanned)
+                if (kp) {
+                    const int r_end = (int)((int64_t)rows.size() - w.roff);
+                    int r = r_first;
+                    for (int64_t s0 = w_first; s0 < acc; s0 += 64) {
+                        const int64_t s1 = std::min<int64_t>(s0 + 64, acc);
+                        while (prefix[w.off + r + 1] <= s0) ++r;
+                        int r1 = r;
+                        while (r1 + 1 < r_end && prefix[w.off + r1 + 1] < s1) ++r1;
+                        chunks.push_back(make_int4(r, (int)(s0 - prefix[w.off + r]), (int)(s1 - s0), r1 - r + 1));
+                    }
+                }
+            }
             w.nwork = acc;
             w.nrows = (int)((int64_t)rows.size() - w.roff);
-            if (uses_k_pair(kPairL[X][0], kPairL[X][1], kPairL[Y][0], kPairL[Y][1]) && acc > 0) {
-                w.choff = (int64_t)chunks.size();
-                for (int r = 0; r < w.nrows; ++r) {
-                    const int64_t cnt = prefix[w.off + r + 1] - prefix[w.off + r];
-                    for (int64_t j0 = 0; j0 < cnt; j0 += 64) chunks.push_back(make_int2(r, (int)j0));
-                }
-                w.nchunks = (int)((int64_t)chunks.size() - w.choff);
-            }
+            if (kp) w.nchunks = (int)((int64_t)chunks.size() - w.choff);
             c->kwork.push_back(w);
             c->n_quartets += acc;
             const int la = kPairL[X][0], lb = kPairL[X][1], lc = kPairL[Y][0], ld = kPairL[Y][1];
@@ -914,7 +932,7 @@ KArgs k_args(const eri_ctx *c, const eri_ctx::KWork &w, bool mixed)
     return a;
 }
 
-KPArgs kp_args(const KArgs &a, const int2 *chunks)
+KPArgs kp_args(const KArgs &a, const int4 *chunks)
 {
     KPArgs p{};
     p.bra = a.bra;

@@ -103,14 +103,18 @@ __global__ void k_count_mix(KArgs a, int kind, unsigned long long *out)
     wave_add2(n, m, out);
 }
 
-__global__ __launch_bounds__(64) void k_count_mix_chunks(KArgs a, const int2 *__restrict__ chunks,
+__global__ __launch_bounds__(64) void k_count_mix_chunks(KArgs a, const int4 *__restrict__ chunks,
                                                           unsigned long long *out)
 {
-    const int2 ch = chunks[blockIdx.x];
-    const KRow row = k_row(a.rows, a.prefix, ch.x);
-    const int ib = row.ib;
-    const bool valid = ch.y + (int)threadIdx.x < row.cnt;
-    const int jk = row.kb + (valid ? ch.y + (int)threadIdx.x : ch.y);
+    const int4 ch = chunks[blockIdx.x];
+    const int lane = (int)threadIdx.x;
+    const bool valid = lane < ch.z;
+    const int64_t wl = a.prefix[ch.x] + ch.y + (valid ? lane : 0);
+    int r = ch.x;
+    for (int k = 1; k < ch.w; ++k)
+        if (a.prefix[ch.x + k] <= wl) r = ch.x + k;
+    const int ib = a.rows[ch.x].x;
+    const int jk = a.rows[r].y + (int)(wl - a.prefix[r]);
     const CPair A = a.bra[ib];
     const CPair B = a.ket[jk];
     const bool need = valid && a.Qbra[ib] * a.Qket[jk] * k_dens_bound(a.Pm, a.nsh, A, B) >= a.tau_mix;
@@ -148,7 +152,7 @@ __global__ void j_count_mix(JArgs a, int per_bra, unsigned long long *out)
     wave_add2(n, m, out);
 }
 
-void launch_k_count_mix(const KArgs &a, int kind, const int2 *chunks, int nchunks, unsigned long long *out,
+void launch_k_count_mix(const KArgs &a, int kind, const int4 *chunks, int nchunks, unsigned long long *out,
                         hipStream_t st)
 {
     if (a.nwork <= 0) return;

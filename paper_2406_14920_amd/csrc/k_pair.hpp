@@ -1,6 +1,6 @@
 // k_pair.hpp -- exchange (K) with the bra shared by a wavefront: one
-// workgroup (64 lanes) takes one bra contracted pair (ab| and 64 consecutive
-// kets |cd) of its work list, one ket per lane.  The bra's Hermite products
+// workgroup (64 lanes) takes one bra contracted pair (ab| and up to 64
+// consecutive kets |cd) of its work list, one ket per lane.  The bra's Hermite products
 // E^{ab}_t come precomputed from HBM through wave-uniform loads, so the
 // registers hold only what differs per lane: the auxiliary integrals R^0 of
 // the lane's primitive quartet (eq. R_recursion), the ket Hermite products,
@@ -9,7 +9,9 @@
 // accumulated over the primitive quartets.  Blocks larger than the register
 // budget are produced in compile-time passes over (ab, cd) chunks, R being
 // rebuilt per pass.  Each finished chunk is digested by the lane into the
-// four exchange blocks of the 8-fold symmetry and added to the accumulator.
+// four exchange blocks of the 8-fold symmetry and added to the accumulator;
+// the K_ac and K_bc terms of lanes in one work-list row (same ket shell c)
+// are summed across those lanes first.
 // T is the arithmetic type of the primitive integrals (the digestion is in
 // double precision); in the mixed mode a workgroup is one precision tile.
 #pragma once
@@ -66,13 +68,17 @@ __global__ __launch_bounds__(64) void k_pair(KPArgs a)
     constexpr int SB = ob.off[C::NAB], SK = ok.off[NCD];
 
     const int lane = threadIdx.x;
-    const int2 ch = a.chunks[blockIdx.x];
-    const KRow row = k_row(a.rows, a.prefix, ch.x);
-    const int ib = row.ib;
-    const bool valid = ch.y + lane < row.cnt;
-    const int jk = row.kb + (valid ? ch.y + lane : ch.y);
+    const int4 ch = a.chunks[blockIdx.x];
+    const bool valid = lane < ch.z;
+    const int64_t wl = a.prefix[ch.x] + ch.y + (valid ? lane : 0);  // the lane's work item
+    int r = ch.x;
+    for (int k = 1; k < ch.w; ++k)
+        if (a.prefix[ch.x + k] <= wl) r = ch.x + k;
+    const int ib = a.rows[ch.x].x;
+    const int jk = a.rows[r].y + (int)(wl - a.prefix[r]);
     const CPair A = a.bra[ib];
     const CPair B = a.ket[jk];
+    const SegLinks links = seg_links(valid ? r : -1 - lane);
     if (!mix_take(a.mode, a.mode != 0 && valid &&
                               a.Qbra[ib] * a.Qket[jk] * k_dens_bound(a.Pm, a.nsh, A, B) >= a.tau_mix))
         return;
@@ -190,7 +196,7 @@ __global__ __launch_bounds__(64) void k_pair(KPArgs a)
         // Every density element the chunk touches is loaded once, and every
         // exchange element gets one atomic with the chunk's sum over the other
         // two indices (instead of one load and one atomic per block element).
-        if (valid) {
+        {
             constexpr int i0 = ab0 / NB, i1 = (ab1 - 1) / NB;
             constexpr int j0 = i0 < i1 ? 0 : ab0 % NB, j1 = i0 < i1 ? NB - 1 : (ab1 - 1) % NB;
             constexpr int c0 = cd0 / ND, c1 = (cd1 - 1) / ND;
@@ -235,7 +241,10 @@ __global__ __launch_bounds__(64) void k_pair(KPArgs a)
                             }
                         });
                     });
-                    if (any) unsafeAtomicAdd(&a.Kacc[(int64_t)(A.c1 + i0 + i) * n + B.c1 + c0 + cc], s * t);
+                    if (any) {  // K_ac: shared by the lanes of a row
+                        const double v = seg_sum(s * t, links);
+                        if (valid && links.head) unsafeAtomicAdd(&a.Kacc[(int64_t)(A.c1 + i0 + i) * n + B.c1 + c0 + cc], v);
+                    }
                 });
                 static_for<0, nd>([&](auto dc) {  // K_ad[i][d] = sum_{j,c} V D_bc[j][c]
                     double t = 0.0;
@@ -249,7 +258,7 @@ __global__ __launch_bounds__(64) void k_pair(KPArgs a)
                             }
                         });
                     });
-                    if (any) unsafeAtomicAdd(&a.Kacc[(int64_t)(A.c1 + i0 + i) * n + B.c2 + d0 + dc], s * t);
+                    if (any && valid) unsafeAtomicAdd(&a.Kacc[(int64_t)(A.c1 + i0 + i) * n + B.c2 + d0 + dc], s * t);
                 });
             });
             static_for<0, nj>([&](auto jc) {
@@ -266,7 +275,10 @@ __global__ __launch_bounds__(64) void k_pair(KPArgs a)
                             }
                         });
                     });
-                    if (any) unsafeAtomicAdd(&a.Kacc[(int64_t)(A.c2 + j0 + j) * n + B.c1 + c0 + cc], s * t);
+                    if (any) {  // K_bc: shared by the lanes of a row
+                        const double v = seg_sum(s * t, links);
+                        if (valid && links.head) unsafeAtomicAdd(&a.Kacc[(int64_t)(A.c2 + j0 + j) * n + B.c1 + c0 + cc], v);
+                    }
                 });
                 static_for<0, nd>([&](auto dc) {  // K_bd[j][d] = sum_{i,c} V D_ac[i][c]
                     double t = 0.0;
@@ -280,7 +292,7 @@ __global__ __launch_bounds__(64) void k_pair(KPArgs a)
                             }
                         });
                     });
-                    if (any) unsafeAtomicAdd(&a.Kacc[(int64_t)(A.c2 + j0 + j) * n + B.c2 + d0 + dc], s * t);
+                    if (any && valid) unsafeAtomicAdd(&a.Kacc[(int64_t)(A.c2 + j0 + j) * n + B.c2 + d0 + dc], s * t);
                 });
             });
         }

@@ -4,6 +4,9 @@
 // accumulates the contracted Cartesian block and digests it into the four
 // exchange blocks that the 8-fold permutational symmetry (eq. 8_fold_symmetry)
 // maps it to:  K_ac += V D_bd, K_ad += V D_bc, K_bc += V D_ad, K_bd += V D_ac.
+// Neighbouring lanes of one work-list row share the bra and the ket shell c,
+// so their K_ac and K_bc terms are summed across the lanes before one atomic
+// addition per element.
 // The caller forms K = Kacc + Kacc^T afterwards.  T is the arithmetic type of
 // the primitive integrals; the digestion and the accumulator stay in double
 // precision.  In the mixed mode a wavefront (64 consecutive quartets) is one
@@ -22,23 +25,28 @@ __global__ __launch_bounds__(128) void k_small(KArgs a)
     constexpr int NBLK = NA * NB * NC * ND;
     constexpr bool F32 = sizeof(T) == 4;
 
-    int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (w >= a.nwork) return;
-    const int r = k_find_row(a.prefix, a.nrows, w);
+    // every lane of a wavefront stays to the end (the digestion sums across
+    // lanes); lanes past the work list evaluate nothing
+    const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool valid = w < a.nwork;
+    const int64_t wc = valid ? w : a.nwork - 1;
+    const int r = k_find_row(a.prefix, a.nrows, wc);
     const int2 rw = a.rows[r];
     const int ib = rw.x;
-    const int jk = rw.y + (int)(w - a.prefix[r]);
+    const int jk = rw.y + (int)(wc - a.prefix[r]);
     const CPair A = a.bra[ib];
     const CPair B = a.ket[jk];
-    if (!mix_take(a.mode, a.mode != 0 && a.Qbra[ib] * a.Qket[jk] * k_dens_bound(a.Pm, a.nsh, A, B) >= a.tau_mix))
-        return;
+    if (!mix_take(a.mode, a.mode != 0 && valid &&
+                              a.Qbra[ib] * a.Qket[jk] * k_dens_bound(a.Pm, a.nsh, A, B) >= a.tau_mix))
+        return;  // uniform over the wavefront
+    const int nbp = valid ? A.np : 0;
 
     T V[NBLK];
 #pragma unroll
     for (int i = 0; i < NBLK; ++i) V[i] = T(0);
 
     const double qk0 = a.pp[B.poff].q;
-    for (int ip = 0; ip < A.np; ++ip) {
+    for (int ip = 0; ip < nbp; ++ip) {
         const PrimPair pb = a.pp[A.poff + ip];
         if (pb.q * qk0 < a.tau_prim) break;
         Etab<LA, LB, T> Ex, Ey, Ez;
@@ -130,10 +138,14 @@ __global__ __launch_bounds__(128) void k_small(KArgs a)
 
     // Each density element is loaded once: the loads could not otherwise be
     // hoisted past the atomics, and every block element would reload two.
+    // K_ac and K_bc of the lanes of one row (same bra, same ket shell c) are
+    // summed across those lanes and added once by the row's first lane;
+    // K_ad and K_bd are added by every lane.
     const double *__restrict__ D = a.D;
     const int n = a.ld;
     double *Kc = a.Kacc;
-    {  // K_ac += V D_bd and K_ad += V D_bc (density rows of the second bra shell)
+    double kac[NA * NC], kad[NA * ND], kbc[NB * NC], kbd[NB * ND];
+    {  // K_ac = V D_bd and K_ad = V D_bc (density rows of the second bra shell)
         double Dbd[NB * ND], Dbc[NB * NC];
         static_for<0, NB>([&](auto jc) {
             constexpr int j = decltype(jc)::value;
@@ -153,7 +165,7 @@ __global__ __launch_bounds__(128) void k_small(KArgs a)
                         acc += (double)V[((i * NB + j) * NC + k) * ND + l] * Dbd[j * ND + l];
                     });
                 });
-                unsafeAtomicAdd(&Kc[(int64_t)(A.c1 + i) * n + B.c1 + k], s * acc);
+                kac[i * NC + k] = s * acc;
             });
             static_for<0, ND>([&](auto lc) {
                 constexpr int l = decltype(lc)::value;
@@ -165,16 +177,15 @@ __global__ __launch_bounds__(128) void k_small(KArgs a)
                         acc += (double)V[((i * NB + j) * NC + k) * ND + l] * Dbc[j * NC + k];
                     });
                 });
-                unsafeAtomicAdd(&Kc[(int64_t)(A.c1 + i) * n + B.c2 + l], s * acc);
+                kad[i * ND + l] = s * acc;
             });
         });
     }
-    {  // K_bc += V D_ad and K_bd += V D_ac, one density row of the first bra shell at a time
-        double acc_bc[NB * NC], acc_bd[NB * ND];
+    {  // K_bc = V D_ad and K_bd = V D_ac, one density row of the first bra shell at a time
 #pragma unroll
-        for (int o = 0; o < NB * NC; ++o) acc_bc[o] = 0.0;
+        for (int o = 0; o < NB * NC; ++o) kbc[o] = 0.0;
 #pragma unroll
-        for (int o = 0; o < NB * ND; ++o) acc_bd[o] = 0.0;
+        for (int o = 0; o < NB * ND; ++o) kbd[o] = 0.0;
         static_for<0, NA>([&](auto ic) {
             constexpr int i = decltype(ic)::value;
             const double *row = D + (int64_t)(A.c1 + i) * n;
@@ -188,20 +199,32 @@ __global__ __launch_bounds__(128) void k_small(KArgs a)
                     static_for<0, ND>([&](auto lc) {
                         constexpr int l = decltype(lc)::value;
                         const double v = (double)V[((i * NB + j) * NC + k) * ND + l];
-                        acc_bc[j * NC + k] += v * Dad[l];
-                        acc_bd[j * ND + l] += v * Dac[k];
+                        kbc[j * NC + k] += v * Dad[l];
+                        kbd[j * ND + l] += v * Dac[k];
                     });
                 });
             });
         });
-        static_for<0, NB>([&](auto jc) {
-            constexpr int j = decltype(jc)::value;
-            static_for<0, NC>([&](auto kc) {
-                unsafeAtomicAdd(&Kc[(int64_t)(A.c2 + j) * n + B.c1 + kc], s * acc_bc[j * NC + kc]);
-            });
-            static_for<0, ND>([&](auto lc) {
-                unsafeAtomicAdd(&Kc[(int64_t)(A.c2 + j) * n + B.c2 + lc], s * acc_bd[j * ND + lc]);
-            });
+    }
+    const SegLinks links = seg_links(valid ? r : -1 - (int)(threadIdx.x & 63));
+    static_for<0, NA * NC>([&](auto oc) {
+        constexpr int o = decltype(oc)::value;
+        const double v = seg_sum(kac[o], links);
+        if (valid && links.head) unsafeAtomicAdd(&Kc[(int64_t)(A.c1 + o / NC) * n + B.c1 + o % NC], v);
+    });
+    static_for<0, NB * NC>([&](auto oc) {
+        constexpr int o = decltype(oc)::value;
+        const double v = seg_sum(s * kbc[o], links);
+        if (valid && links.head) unsafeAtomicAdd(&Kc[(int64_t)(A.c2 + o / NC) * n + B.c1 + o % NC], v);
+    });
+    if (valid) {
+        static_for<0, NA * ND>([&](auto oc) {
+            constexpr int o = decltype(oc)::value;
+            unsafeAtomicAdd(&Kc[(int64_t)(A.c1 + o / ND) * n + B.c2 + o % ND], kad[o]);
+        });
+        static_for<0, NB * ND>([&](auto oc) {
+            constexpr int o = decltype(oc)::value;
+            unsafeAtomicAdd(&Kc[(int64_t)(A.c2 + o / ND) * n + B.c2 + o % ND], s * kbd[o]);
         });
     }
 }

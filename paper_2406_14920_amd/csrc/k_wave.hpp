@@ -8,7 +8,9 @@
 //     (ab|cd) = sum_{s in box(cd)} (-1)^{|s|} E^{cd}_s Y_s  (eq. eri_formula)
 // The block is accumulated over primitive quartets in LDS (or streamed in
 // chunks for the largest classes) and digested into the four exchange blocks
-// of the 8-fold symmetry, which are flushed to the Cartesian accumulator.
+// of the 8-fold symmetry, which are flushed to the Cartesian accumulator:
+// K_ad and K_bd after every quartet, K_ac and K_bc (the same elements for all
+// quartets of a work-list row) after the row's last quartet in the range.
 // A workgroup walks a contiguous range of the work list, so the bra search is
 // done once per range.  T is the arithmetic type of the primitive integrals
 // (LDS tables and the block); the density tiles, the digestion and the
@@ -54,7 +56,7 @@ struct WaveCfg {
 template <int NA, int NB, int NC, int ND, typename T>
 __device__ __forceinline__ void digest_rt(const T *sV, int vstride, int abb, int cdb, int ab0,
                                           int ab1, int cd0, int cd1, const double *sD, double *sK,
-                                          int lane)
+                                          int lane, double s)
 {
     const double *D13 = sD, *D14 = sD + NA * NC, *D23 = D14 + NA * ND, *D24 = D23 + NB * NC;
     double *K13 = sK, *K14 = sK + NA * NC, *K23 = K14 + NA * ND, *K24 = K23 + NB * NC;
@@ -62,7 +64,7 @@ __device__ __forceinline__ void digest_rt(const T *sV, int vstride, int abb, int
     for (int e = lane; e < n; e += 64) {
         const int ab = ab0 + e % nab, cd = cd0 + e / nab;
         const int i = ab / NB, j = ab % NB, k = cd / ND, l = cd % ND;
-        const double v = (double)sV[(cd - cdb) * vstride + (ab - abb)];
+        const double v = s * (double)sV[(cd - cdb) * vstride + (ab - abb)];
         atomicAdd(&K13[i * NC + k], v * D24[j * ND + l]);
         atomicAdd(&K14[i * ND + l], v * D23[j * NC + k]);
         atomicAdd(&K23[j * NC + k], v * D14[i * ND + l]);
@@ -78,7 +80,7 @@ __device__ __forceinline__ void digest_rt(const T *sV, int vstride, int abb, int
 // at most NA or NB targets, so the atomics rarely collide, and no lane waits
 // on another's branch).
 template <int NA, int NB, int NC, int ND, typename T>
-__device__ __forceinline__ void digest_full(const T *sV, const double *sD, double *sK, int lane)
+__device__ __forceinline__ void digest_full(const T *sV, const double *sD, double *sK, int lane, double s)
 {
     constexpr int NAB = NA * NB, NCD = NC * ND;
     const double *D13 = sD, *D14 = sD + NA * NC, *D23 = D14 + NA * ND, *D24 = D23 + NB * NC;
@@ -86,11 +88,34 @@ __device__ __forceinline__ void digest_full(const T *sV, const double *sD, doubl
     for (int e = lane; e < NAB * NCD; e += 64) {
         const int ab = e % NAB, cd = e / NAB;
         const int i = ab / NB, j = ab % NB, k = cd / ND, l = cd % ND;
-        const double v = (double)sV[e];
+        const double v = s * (double)sV[e];
         atomicAdd(&K13[i * NC + k], v * D24[j * ND + l]);
         atomicAdd(&K14[i * ND + l], v * D23[j * NC + k]);
         atomicAdd(&K23[j * NC + k], v * D14[i * ND + l]);
         atomicAdd(&K24[j * ND + l], v * D13[i * NC + k]);
+    }
+}
+
+// Add the LDS exchange tiles of a quartet to the accumulator: K_ad and K_bd
+// always, K_ac and K_bc (shared by the quartets of one work-list row: same
+// bra, same ket shell c) only after the row's last quartet.  Each element is
+// read, cleared and added by one lane; exact zeros are not added.
+template <int NA, int NB, int NC, int ND>
+__device__ __forceinline__ void flush_tiles(double *sK, const CPair &A, const CPair &B, double *__restrict__ Kacc,
+                                            int n, bool row_end, int lane)
+{
+    constexpr int ND_ = NA * NC + NA * ND + NB * NC + NB * ND;
+    for (int o = lane; o < ND_; o += 64) {
+        int row, col;
+        bool shared;
+        if (o < NA * NC) { row = A.c1 + o / NC; col = B.c1 + o % NC; shared = true; }
+        else if (o < NA * NC + NA * ND) { int r = o - NA * NC; row = A.c1 + r / ND; col = B.c2 + r % ND; shared = false; }
+        else if (o < NA * NC + NA * ND + NB * NC) { int r = o - NA * NC - NA * ND; row = A.c2 + r / NC; col = B.c1 + r % NC; shared = true; }
+        else { int r = o - NA * NC - NA * ND - NB * NC; row = A.c2 + r / ND; col = B.c2 + r % ND; shared = false; }
+        if (shared && !row_end) continue;
+        const double v = sK[o];
+        sK[o] = 0.0;
+        if (v != 0.0) unsafeAtomicAdd(&Kacc[(int64_t)row * n + col], v);
     }
 }
 
@@ -114,6 +139,7 @@ __global__ __launch_bounds__(64) void k_wave(KArgs a)
 
     const int lane = threadIdx.x;
     herm_table_lds(sHerm, nherm(L), lane);
+    for (int o = lane; o < C::ND_; o += 64) sK[o] = 0.0;  // cleared again by every flush
 
     // the bra components this lane owns: their boxes and 1D table offsets
     int own_m[C::NABCH][3], own_off[C::NABCH][3];
@@ -151,12 +177,20 @@ __global__ __launch_bounds__(64) void k_wave(KArgs a)
             const int ib = a.rows[row].x, kj = a.rows[row].y + jk;
             const CPair A = a.bra[ib];
             const CPair B = a.ket[kj];
+            // last quartet of its row inside this range: K_ac, K_bc are flushed after it
+            const bool row_end = w + 1 == w1 || a.prefix[row] + jk + 1 >= a.prefix[row + 1];
+            bool take = true;
             if (a.mode != 0) {  // uniform over the workgroup
                 const bool need = a.Qbra[ib] * a.Qket[kj] * k_dens_bound(a.Pm, a.nsh, A, B) >= a.tau_mix;
-                if (need != (a.mode == 1)) continue;
+                take = need == (a.mode == 1);
             }
+            if (take) {
+            double s = 1.0;
+            if (A.sh1 == A.sh2) s *= 0.5;
+            if (B.sh1 == B.sh2) s *= 0.5;
+            if (a.same && same_pair(A, B)) s *= 0.5;
 
-            // density blocks D_ac, D_ad, D_bc, D_bd and zeroed exchange tiles
+            // density blocks D_ac, D_ad, D_bc, D_bd
             for (int o = lane; o < C::ND_; o += 64) {
                 int row, col;
                 if (o < NA * NC) { row = A.c1 + o / NC; col = B.c1 + o % NC; }
@@ -164,7 +198,6 @@ __global__ __launch_bounds__(64) void k_wave(KArgs a)
                 else if (o < NA * NC + NA * ND + NB * NC) { int r = o - NA * NC - NA * ND; row = A.c2 + r / NC; col = B.c1 + r % NC; }
                 else { int r = o - NA * NC - NA * ND - NB * NC; row = A.c2 + r / ND; col = B.c2 + r % ND; }
                 sD[o] = a.D[(int64_t)row * n + col];
-                sK[o] = 0.0;
             }
             if constexpr (!C::STREAM)
                 for (int o = lane; o < C::NV; o += 64) sV[o] = T(0);
@@ -268,7 +301,7 @@ __global__ __launch_bounds__(64) void k_wave(KArgs a)
                             if constexpr (C::STREAM) {
                                 __syncthreads();
                                 const int ab0 = ch * 64, ab1 = (ab0 + 64 < NAB) ? ab0 + 64 : NAB;
-                                digest_rt<NA, NB, NC, ND, T>(sV, 64, ab0, cd0, ab0, ab1, cd0, cd1, sD, sK, lane);
+                                digest_rt<NA, NB, NC, ND, T>(sV, 64, ab0, cd0, ab0, ab1, cd0, cd1, sD, sK, lane, s);
                                 __syncthreads();
                             }
                         });
@@ -278,21 +311,11 @@ __global__ __launch_bounds__(64) void k_wave(KArgs a)
                 }
             }
             if constexpr (!C::STREAM) {
-                digest_full<NA, NB, NC, ND, T>(sV, sD, sK, lane);
+                digest_full<NA, NB, NC, ND, T>(sV, sD, sK, lane, s);
                 __syncthreads();
             }
-            double s = 1.0;
-            if (A.sh1 == A.sh2) s *= 0.5;
-            if (B.sh1 == B.sh2) s *= 0.5;
-            if (a.same && same_pair(A, B)) s *= 0.5;
-            for (int o = lane; o < C::ND_; o += 64) {
-                int row, col;
-                if (o < NA * NC) { row = A.c1 + o / NC; col = B.c1 + o % NC; }
-                else if (o < NA * NC + NA * ND) { int r = o - NA * NC; row = A.c1 + r / ND; col = B.c2 + r % ND; }
-                else if (o < NA * NC + NA * ND + NB * NC) { int r = o - NA * NC - NA * ND; row = A.c2 + r / NC; col = B.c1 + r % NC; }
-                else { int r = o - NA * NC - NA * ND - NB * NC; row = A.c2 + r / ND; col = B.c2 + r % ND; }
-                unsafeAtomicAdd(&a.Kacc[(int64_t)row * n + col], s * sK[o]);
-            }
+            }  // take
+            flush_tiles<NA, NB, NC, ND>(sK, A, B, a.Kacc, n, row_end, lane);
             __syncthreads();
         }
     }
@@ -342,6 +365,7 @@ __global__ __launch_bounds__(64) void k_wave_x(KArgs a)
 
     const int lane = threadIdx.x;
     herm_table_lds(sHerm, nherm(L), lane);
+    for (int o = lane; o < C::ND_; o += 64) sK[o] = 0.0;  // cleared again by every flush
 
     // bra Hermite indices this lane owns in the ket rounds
     int tof[TCH];
@@ -389,10 +413,18 @@ __global__ __launch_bounds__(64) void k_wave_x(KArgs a)
             const int ib = a.rows[row].x, kj = a.rows[row].y + jk;
             const CPair A = a.bra[ib];
             const CPair B = a.ket[kj];
+            // last quartet of its row inside this range: K_ac, K_bc are flushed after it
+            const bool row_end = w + 1 == w1 || a.prefix[row] + jk + 1 >= a.prefix[row + 1];
+            bool take = true;
             if (a.mode != 0) {  // uniform over the workgroup
                 const bool need = a.Qbra[ib] * a.Qket[kj] * k_dens_bound(a.Pm, a.nsh, A, B) >= a.tau_mix;
-                if (need != (a.mode == 1)) continue;
+                take = need == (a.mode == 1);
             }
+            if (take) {
+            double s = 1.0;
+            if (A.sh1 == A.sh2) s *= 0.5;
+            if (B.sh1 == B.sh2) s *= 0.5;
+            if (a.same && same_pair(A, B)) s *= 0.5;
 
             for (int o = lane; o < C::ND_; o += 64) {
                 int row, col;
@@ -401,7 +433,6 @@ __global__ __launch_bounds__(64) void k_wave_x(KArgs a)
                 else if (o < NA * NC + NA * ND + NB * NC) { int r = o - NA * NC - NA * ND; row = A.c2 + r / NC; col = B.c1 + r % NC; }
                 else { int r = o - NA * NC - NA * ND - NB * NC; row = A.c2 + r / ND; col = B.c2 + r % ND; }
                 sD[o] = a.D[(int64_t)row * n + col];
-                sK[o] = 0.0;
             }
             __syncthreads();
 
@@ -566,8 +597,8 @@ __global__ __launch_bounds__(64) void k_wave_x(KArgs a)
                                 t13 += (double)v[k * ND + l] * d24[l];
                                 t23 += (double)v[k * ND + l] * d14[l];
                             }
-                            atomicAdd(&K13[i * NC + k], t13);
-                            atomicAdd(&K23[j * NC + k], t23);
+                            atomicAdd(&K13[i * NC + k], s * t13);
+                            atomicAdd(&K23[j * NC + k], s * t23);
                         }
 #pragma unroll
                         for (int l = 0; l < ND; ++l) {
@@ -577,25 +608,15 @@ __global__ __launch_bounds__(64) void k_wave_x(KArgs a)
                                 t14 += (double)v[k * ND + l] * d23[k];
                                 t24 += (double)v[k * ND + l] * d13[k];
                             }
-                            atomicAdd(&K14[i * ND + l], t14);
-                            atomicAdd(&K24[j * ND + l], t24);
+                            atomicAdd(&K14[i * ND + l], s * t14);
+                            atomicAdd(&K24[j * ND + l], s * t24);
                         }
                     }
                 });
                 __syncthreads();
             }
-            double s = 1.0;
-            if (A.sh1 == A.sh2) s *= 0.5;
-            if (B.sh1 == B.sh2) s *= 0.5;
-            if (a.same && same_pair(A, B)) s *= 0.5;
-            for (int o = lane; o < C::ND_; o += 64) {
-                int row, col;
-                if (o < NA * NC) { row = A.c1 + o / NC; col = B.c1 + o % NC; }
-                else if (o < NA * NC + NA * ND) { int r = o - NA * NC; row = A.c1 + r / ND; col = B.c2 + r % ND; }
-                else if (o < NA * NC + NA * ND + NB * NC) { int r = o - NA * NC - NA * ND; row = A.c2 + r / NC; col = B.c1 + r % NC; }
-                else { int r = o - NA * NC - NA * ND - NB * NC; row = A.c2 + r / ND; col = B.c2 + r % ND; }
-                unsafeAtomicAdd(&a.Kacc[(int64_t)row * n + col], s * sK[o]);
-            }
+            }  // take
+            flush_tiles<NA, NB, NC, ND>(sK, A, B, a.Kacc, n, row_end, lane);
             __syncthreads();
         }
     }

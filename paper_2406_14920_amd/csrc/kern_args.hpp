@@ -46,6 +46,9 @@ struct KArgs {
     double om2;              // omega^2 of the operator erf(omega r)/r; 0: 1/r
 };
 
+// The rows of an exchange work list run bra by bra and, inside a bra, group
+// by group: the items of one row share the bra (ab| and the ket shell c, so
+// their K_ac and K_bc contributions go to the same elements.
 // Row r of an exchange work list: bra pair, first ket index and ket count.
 struct KRow {
     int ib, kb, cnt;
@@ -65,6 +68,40 @@ __device__ __forceinline__ int k_find_row(const int64_t *prefix, int nrows, int6
     }
     return lo;
 }
+// Segmented sums over a wavefront.  The lanes that share a key (the work-list
+// row: one bra and one ket shell c) are contiguous; seg_links gives, per
+// doubling step k, whether lane + 2^k holds the same key, and seg_sum then
+// leaves in the first lane of every run the sum over the run (a downward
+// Hillis-Steele scan cut at key changes).  Every lane of the wavefront must
+// take part.
+struct SegLinks {
+    uint32_t same;  // bit k: lane + 2^k is in this lane's run
+    bool head;      // first lane of its run
+};
+__device__ __forceinline__ SegLinks seg_links(int key)
+{
+    const int lane = threadIdx.x & 63;
+    SegLinks L{0u, true};
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        const int off = 1 << k;
+        const int ko = __shfl_down(key, off);
+        if (lane + off < 64 && ko == key) L.same |= 1u << k;
+    }
+    const int kp = __shfl_up(key, 1);
+    L.head = lane == 0 || kp != key;
+    return L;
+}
+__device__ __forceinline__ double seg_sum(double v, const SegLinks &L)
+{
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        const double o = __shfl_down(v, 1 << k);
+        if (L.same & (1u << k)) v += o;
+    }
+    return v;
+}
+
 // the diagonal quartet (ab|ab) of a class with itself
 __device__ __forceinline__ bool same_pair(const CPair &A, const CPair &B)
 {
@@ -97,12 +134,12 @@ struct JArgs {
     double om2;              // omega^2 of the operator erf(omega r)/r; 0: 1/r
 };
 
-// Bra-shared exchange launch: one workgroup per (row, 64-ket chunk) of an
-// exchange work list (rows as in KArgs).
+// Bra-shared exchange launch: one workgroup per chunk of up to 64
+// consecutive work items of one bra (rows as in KArgs).
 struct KPArgs {
     const CPair *bra;
     const CPair *ket;
-    const int2 *chunks;      // (row, first ket of the row) of every workgroup
+    const int4 *chunks;      // (first row, offset of the first item in it, items, rows spanned)
     const int2 *rows;
     const int64_t *prefix;   // cumulative ket counts of the rows
     int32_t same;

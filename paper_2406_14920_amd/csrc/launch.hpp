@@ -51,7 +51,7 @@ void launch_density_bounds(const double *Pc, int nc, const int32_t *l, const int
 // primitive quartets (out[0]) and work items (out[1]) of the single-precision
 // share of one mixed-precision launch; kind 0 = lane-per-quartet tiles of 64,
 // 1 = one quartet per tile, 2 = bra-shared chunks
-void launch_k_count_mix(const KArgs &a, int kind, const int2 *chunks, int nchunks, unsigned long long *out,
+void launch_k_count_mix(const KArgs &a, int kind, const int4 *chunks, int nchunks, unsigned long long *out,
                         hipStream_t st);
 // primitive quartets of the single-precision share of a J-engine launch;
 // per_bra = 1 when the tile is a single bra primitive pair
