@@ -18,6 +18,11 @@ Parity status per function (what pins it is listed in tests/test_oracle_*.py):
                 rotation invariance, large-separation limit)
   grad          pinned (central finite differences of the oracle energy,
                 zero sum over atoms, analytic two-centre derivative)
+  vmatrix       pinned ((s|1/r_C|s) closed form of eq. v1e_base_case with
+                mpmath erf; blocks up to (f|f) against a Gaussian-transform
+                quadrature; far-field limit q S/|P-C|)
+  vgrad         pinned (central differences of E_V in atom and charge
+                positions; atom and charge derivatives sum to zero)
   spherical     convention pinned by S_sph = I and rotation invariance
   omega > 0     pinned (erf(omega r)/r blocks against the Gaussian-transform
                 quadrature cut at t = omega and an mpmath closed form of the
@@ -79,6 +84,9 @@ def lib():
         L.oracle_quartet_batch.argtypes = bas + [dp, ip] + qp + [ctypes.c_int64, ip]
         L.oracle_quartet_batch.restype = ctypes.c_double
         L.oracle_num_threads.restype = ctypes.c_int
+        L.oracle_vmatrix.argtypes = bas + [dp, ip, ip, ctypes.c_int32, ctypes.c_int32, dp, dp]
+        L.oracle_vgrad.argtypes = bas + [dp, ip, ip, ctypes.c_int32, ctypes.c_int32, dp, dp, dp, dp]
+        L.oracle_prim_vblock.argtypes = [ctypes.c_int, ctypes.c_int, dp, dp, ctypes.c_int32, dp, dp]
         L.oracle_set_omega.argtypes = [ctypes.c_double]
         L.oracle_set_omega.restype = None
         L.oracle_get_omega.restype = ctypes.c_double
@@ -266,6 +274,45 @@ def jk_blocks(mol, jpairs: Sequence[Tuple[int, int]], kpairs: Sequence[Tuple[int
         nx, ny = 2 * B.l[x] + 1, 2 * B.l[y] + 1
         res.append(out[offs[t]:offs[t] + nx * ny].reshape(nx, ny))
     return res[:len(jp)], res[len(jp):]
+
+
+def _charges(charges):
+    c = np.ascontiguousarray(np.asarray(charges, float).reshape(-1, 4))
+    return c, int(c.shape[0])
+
+
+def prim_vblock(ls, exps, centres, charges) -> np.ndarray:
+    """Primitive Cartesian block of sum_C q_C/|r - C| between unnormalised
+    monomial Gaussians (charges: rows x, y, z, q)."""
+    la, lb = ls
+    c, n = _charges(charges)
+    out = np.zeros(((la + 1) * (la + 2) // 2) * ((lb + 1) * (lb + 2) // 2))
+    e = np.ascontiguousarray(exps, float)
+    x = np.ascontiguousarray(centres, float).reshape(6)
+    lib().oracle_prim_vblock(la, lb, _dp(e), _dp(x), n, _dp(c), _dp(out))
+    return out.reshape((la + 1) * (la + 2) // 2, (lb + 1) * (lb + 2) // 2)
+
+
+def vmatrix(mol, charges, basis_obj=None) -> np.ndarray:
+    """V_mn = sum_C q_C int m n / |r - C| (spherical basis), eqs. v1e_definition,
+    v1e_formula; charges: rows x, y, z, q (nuclei: q = -Z)."""
+    B = basis_obj or OBasis(mol)
+    c, n = _charges(charges)
+    V = np.zeros((B.nbf, B.nbf))
+    lib().oracle_vmatrix(*B.args(), _dp(B.T), _ip(B.Toff), _ip(B.ao_off), B.nbf, n, _dp(c), _dp(V))
+    return V
+
+
+def vgrad(mol, charges, P=None, basis_obj=None):
+    """dE_V/dR of E_V = sum P_mn V_mn at fixed P: (per atom carrying basis
+    functions, per charge position), SI eqs. si_v1e_derivative_A/B/C."""
+    B = basis_obj or OBasis(mol)
+    c, n = _charges(charges)
+    P = _sym(mol.P if P is None else P)
+    ga = np.zeros((B.natom, 3))
+    gc = np.zeros((max(n, 1), 3))
+    lib().oracle_vgrad(*B.args(), _dp(B.T), _ip(B.Toff), _ip(B.ao_off), B.nbf, n, _dp(c), _dp(P), _dp(ga), _dp(gc))
+    return ga, gc[:n]
 
 
 def energy(mol, J, K, P=None) -> float:

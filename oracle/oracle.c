@@ -492,6 +492,226 @@ void oracle_prim_bounds(int32_t nshell, int32_t natom, const int32_t *atom, cons
     }
 }
 
+/* ------------------------------------------------------------------------ */
+/* Point-charge potential (nuclear attraction and QM/MM charges):            */
+/* V_mn = sum_C q_C int m(r) n(r) / |r - C| (eqs. v1e_definition,            */
+/* v1e_summation_over_C), by eq. v1e_formula:                                */
+/*   V_mnC = q_C C_m C_n (2 pi/p) sum_t E^{mn}_t R^0_t(p, P - C).            */
+/* ------------------------------------------------------------------------ */
+
+/* Cartesian block of one primitive pair summed over the charges (chg[4k..4k+3]
+ * = x, y, z, q), times scale, added to out[ia*nb+ib].  dcharge >= 0: instead
+ * the derivative with respect to the position of charge dcharge along axis dax,
+ * d/dC_x R^0_{tuv}(p, P - C) = -R^0_{t+1,u,v} (SI eq. si_v1e_derivative_C). */
+static void prim_vblock(int la, int lb, double a, double b, const double *A, const double *B,
+                        int ncharge, const double *chg, int dcharge, int dax, double scale,
+                        double *out, scratch_t *S)
+{
+    double p = a + b, P[3];
+    for (int k = 0; k < 3; ++k) {
+        P[k] = (a * A[k] + b * B[k]) / p;
+        e_coeffs(la, lb, a, b, A[k], B[k], S->Eab[k]);
+    }
+    int ca[64][3], cb[64][3];
+    cart_list(la, ca);
+    cart_list(lb, cb);
+    int na = ncart(la), nb = ncart(lb);
+    int c0 = dcharge >= 0 ? dcharge : 0, c1 = dcharge >= 0 ? dcharge + 1 : ncharge;
+    int Lt = la + lb + (dcharge >= 0 ? 1 : 0);
+    for (int c = c0; c < c1; ++c) {
+        const double *C = chg + 4 * c;
+        double PC[3] = {P[0] - C[0], P[1] - C[1], P[2] - C[2]};
+        r_tensor(Lt, p, PC, &S->R0, &S->work);
+        double pref = scale * C[3] * 2.0 * OR_PI / p;
+        int sh[3] = {0, 0, 0};
+        if (dcharge >= 0) {
+            sh[dax] = 1;
+            pref = -pref;
+        }
+        for (int ia = 0; ia < na; ++ia)
+            for (int ib = 0; ib < nb; ++ib) {
+                const int *i = ca[ia], *j = cb[ib];
+                double v = 0.0;
+                for (int tx = 0; tx <= i[0] + j[0]; ++tx)
+                    for (int ty = 0; ty <= i[1] + j[1]; ++ty)
+                        for (int tz = 0; tz <= i[2] + j[2]; ++tz)
+                            v += S->Eab[0][i[0]][j[0]][tx] * S->Eab[1][i[1]][j[1]][ty] *
+                                 S->Eab[2][i[2]][j[2]][tz] * S->R0.v[tx + sh[0]][ty + sh[1]][tz + sh[2]];
+                out[ia * nb + ib] += pref * v;
+            }
+    }
+}
+
+/* Contracted Cartesian block of shells (sa, sb).  dcen 0/1: derivative with
+ * respect to the centre of sa / sb along dax, by differentiating the basis
+ * function, d/dA_x [(x-A_x)^i e^{-a(x-A_x)^2}] = 2a (x-A_x)^{i+1} e - i (x-A_x)^{i-1} e
+ * (every charge); dcen 2: derivative with respect to charge dcharge. */
+static void shell_vblock(const basis_t *B, int sa, int sb, int ncharge, const double *chg, int dcen,
+                         int dax, int dcharge, double *out, scratch_t *S)
+{
+    int L[2] = {B->l[sa], B->l[sb]};
+    int n[2] = {ncart(L[0]), ncart(L[1])};
+    const double *X[2] = {B->xyz + 3 * B->atom[sa], B->xyz + 3 * B->atom[sb]};
+    memset(out, 0, sizeof(double) * n[0] * n[1]);
+    int cl[2][64][3];
+    cart_list(L[0], cl[0]);
+    cart_list(L[1], cl[1]);
+    double tmp[15 * 15];
+    for (int i0 = 0; i0 < B->nprim[sa]; ++i0)
+        for (int i1 = 0; i1 < B->nprim[sb]; ++i1) {
+            int pi[2] = {B->off[sa] + i0, B->off[sb] + i1};
+            double e[2] = {B->exps[pi[0]], B->exps[pi[1]]};
+            double cf = B->coefs[pi[0]] * B->coefs[pi[1]];
+            if (dcen < 0 || dcen == 2) {
+                prim_vblock(L[0], L[1], e[0], e[1], X[0], X[1], ncharge, chg, dcen == 2 ? dcharge : -1, dax, cf,
+                            out, S);
+                continue;
+            }
+            /* + 2 e (x-A)^{i+1} */
+            int Lp[2] = {L[0], L[1]};
+            Lp[dcen] += 1;
+            int np[2] = {ncart(Lp[0]), ncart(Lp[1])};
+            int clp[64][3];
+            cart_list(Lp[dcen], clp);
+            memset(tmp, 0, sizeof(double) * np[0] * np[1]);
+            prim_vblock(Lp[0], Lp[1], e[0], e[1], X[0], X[1], ncharge, chg, -1, 0, cf * 2.0 * e[dcen], tmp, S);
+            for (int a0 = 0; a0 < n[0]; ++a0)
+                for (int a1 = 0; a1 < n[1]; ++a1) {
+                    int idx[2] = {a0, a1}, cc[3];
+                    for (int k = 0; k < 3; ++k) cc[k] = cl[dcen][idx[dcen]][k];
+                    cc[dax] += 1;
+                    int slot = -1;
+                    for (int q = 0; q < np[dcen]; ++q)
+                        if (clp[q][0] == cc[0] && clp[q][1] == cc[1] && clp[q][2] == cc[2]) slot = q;
+                    int j[2] = {a0, a1};
+                    j[dcen] = slot;
+                    out[a0 * n[1] + a1] += tmp[j[0] * np[1] + j[1]];
+                }
+            /* - i (x-A)^{i-1} */
+            if (L[dcen] > 0) {
+                int Lm[2] = {L[0], L[1]};
+                Lm[dcen] -= 1;
+                int nm[2] = {ncart(Lm[0]), ncart(Lm[1])};
+                int clm[64][3];
+                cart_list(Lm[dcen], clm);
+                memset(tmp, 0, sizeof(double) * nm[0] * nm[1]);
+                prim_vblock(Lm[0], Lm[1], e[0], e[1], X[0], X[1], ncharge, chg, -1, 0, cf, tmp, S);
+                for (int a0 = 0; a0 < n[0]; ++a0)
+                    for (int a1 = 0; a1 < n[1]; ++a1) {
+                        int idx[2] = {a0, a1}, cc[3];
+                        for (int k = 0; k < 3; ++k) cc[k] = cl[dcen][idx[dcen]][k];
+                        int pw = cc[dax];
+                        if (pw == 0) continue;
+                        cc[dax] -= 1;
+                        int slot = -1;
+                        for (int q = 0; q < nm[dcen]; ++q)
+                            if (clm[q][0] == cc[0] && clm[q][1] == cc[1] && clm[q][2] == cc[2]) slot = q;
+                        int j[2] = {a0, a1};
+                        j[dcen] = slot;
+                        out[a0 * n[1] + a1] -= pw * tmp[j[0] * nm[1] + j[1]];
+                    }
+            }
+        }
+}
+
+/* Spherical (or Cartesian if T == NULL) 2-index block from a Cartesian one. */
+static void vblock_sph(int la, int lb, const double *T, const int *Toff, const double *cart, double *sph)
+{
+    int na = ncart(la), nb = ncart(lb), sa = 2 * la + 1, sb = 2 * lb + 1;
+    const double *Ta = T + Toff[la], *Tb = T + Toff[lb];
+    for (int i = 0; i < sa; ++i)
+        for (int j = 0; j < sb; ++j) {
+            double v = 0.0;
+            for (int x = 0; x < na; ++x)
+                for (int y = 0; y < nb; ++y) v += Ta[i * na + x] * Tb[j * nb + y] * cart[x * nb + y];
+            sph[i * sb + j] = v;
+        }
+}
+
+/* V (spherical, nbf x nbf) over every ordered shell pair. */
+void oracle_vmatrix(int32_t nshell, int32_t natom, const int32_t *atom, const int32_t *l,
+                    const int32_t *nprim, const int32_t *off, const double *exps, const double *coefs,
+                    const double *xyz, const double *T, const int *Toff, const int32_t *ao_off, int32_t nbf,
+                    int32_t ncharge, const double *chg, double *V)
+{
+    basis_t B = mkbasis(nshell, natom, atom, l, nprim, off, exps, coefs, xyz);
+    memset(V, 0, sizeof(double) * nbf * nbf);
+#pragma omp parallel
+    {
+        scratch_t *S = (scratch_t *)malloc(sizeof(scratch_t));
+        double blk[256], sph[64];
+#pragma omp for schedule(dynamic, 1)
+        for (int a = 0; a < nshell; ++a)
+            for (int b = 0; b < nshell; ++b) {
+                shell_vblock(&B, a, b, ncharge, chg, -1, 0, -1, blk, S);
+                vblock_sph(l[a], l[b], T, Toff, blk, sph);
+                int sa = 2 * l[a] + 1, sb = 2 * l[b] + 1;
+                for (int i = 0; i < sa; ++i)
+                    for (int j = 0; j < sb; ++j) V[(ao_off[a] + i) * nbf + ao_off[b] + j] = sph[i * sb + j];
+            }
+        free(S);
+    }
+}
+
+/* E_V = sum_mn P_mn V_mn and its derivatives at fixed P: with respect to the
+ * atoms carrying the basis functions (gatom[natom][3], every ordered shell
+ * pair, both centres) and to the charge positions (gchg[ncharge][3]). */
+void oracle_vgrad(int32_t nshell, int32_t natom, const int32_t *atom, const int32_t *l,
+                  const int32_t *nprim, const int32_t *off, const double *exps, const double *coefs,
+                  const double *xyz, const double *T, const int *Toff, const int32_t *ao_off, int32_t nbf,
+                  int32_t ncharge, const double *chg, const double *P, double *gatom, double *gchg)
+{
+    basis_t B = mkbasis(nshell, natom, atom, l, nprim, off, exps, coefs, xyz);
+    memset(gatom, 0, sizeof(double) * 3 * natom);
+    memset(gchg, 0, sizeof(double) * 3 * ncharge);
+#pragma omp parallel
+    {
+        scratch_t *S = (scratch_t *)malloc(sizeof(scratch_t));
+        double blk[256], sph[64];
+        double *ga = (double *)calloc(3 * natom, sizeof(double));
+        double *gc = (double *)calloc(3 * (ncharge > 0 ? ncharge : 1), sizeof(double));
+#pragma omp for schedule(dynamic, 1)
+        for (int a = 0; a < nshell; ++a)
+            for (int b = 0; b < nshell; ++b) {
+                int sa = 2 * l[a] + 1, sb = 2 * l[b] + 1;
+                for (int cen = 0; cen < 2; ++cen)
+                    for (int ax = 0; ax < 3; ++ax) {
+                        shell_vblock(&B, a, b, ncharge, chg, cen, ax, -1, blk, S);
+                        vblock_sph(l[a], l[b], T, Toff, blk, sph);
+                        double g = 0.0;
+                        for (int i = 0; i < sa; ++i)
+                            for (int j = 0; j < sb; ++j) g += P[(ao_off[a] + i) * nbf + ao_off[b] + j] * sph[i * sb + j];
+                        ga[3 * atom[cen == 0 ? a : b] + ax] += g;
+                    }
+                for (int c = 0; c < ncharge; ++c)
+                    for (int ax = 0; ax < 3; ++ax) {
+                        shell_vblock(&B, a, b, ncharge, chg, 2, ax, c, blk, S);
+                        vblock_sph(l[a], l[b], T, Toff, blk, sph);
+                        double g = 0.0;
+                        for (int i = 0; i < sa; ++i)
+                            for (int j = 0; j < sb; ++j) g += P[(ao_off[a] + i) * nbf + ao_off[b] + j] * sph[i * sb + j];
+                        gc[3 * c + ax] += g;
+                    }
+            }
+#pragma omp critical
+        {
+            for (int i = 0; i < 3 * natom; ++i) gatom[i] += ga[i];
+            for (int i = 0; i < 3 * ncharge; ++i) gchg[i] += gc[i];
+        }
+        free(ga); free(gc); free(S);
+    }
+}
+
+/* One primitive Cartesian block of V for the pins (unnormalised monomials). */
+void oracle_prim_vblock(int la, int lb, const double *exps2, const double *centres6, int32_t ncharge,
+                        const double *chg, double *out)
+{
+    scratch_t *S = (scratch_t *)malloc(sizeof(scratch_t));
+    memset(out, 0, sizeof(double) * ncart(la) * ncart(lb));
+    prim_vblock(la, lb, exps2[0], exps2[1], centres6, centres6 + 3, ncharge, chg, -1, 0, 1.0, out, S);
+    free(S);
+}
+
 /* Transform a Cartesian block to the spherical basis with per-l matrices
  * T_l [2l+1][ncart(l)] (row-major, concatenated for l = 0..3 at Toff[l]). */
 static void to_sph(const int *L, const double *T, const int *Toff, const double *cart,

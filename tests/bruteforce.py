@@ -62,3 +62,30 @@ def eri_monomial(ijk_a, ijk_b, ijk_c, ijk_d, a, b, c, d, A, B, C, D, omega=None)
                                    a, b, c, d, A[ax], B[ax], C[ax], D[ax], t)
         total += wu * dt * prod
     return 2.0 / np.sqrt(np.pi) * total
+
+
+def _axis_potential(i, j, a, b, A, B, C, t):
+    """int (x-A)^i (x-B)^j e^{-a(x-A)^2 - b(x-B)^2 - t^2 (x-C)^2} dx, exact by
+    Gauss-Hermite after completing the square."""
+    e = a + b + t * t
+    m = (a * A + b * B + t * t * C) / e
+    c0 = -(a * A * A + b * B * B + t * t * C * C) + e * m * m
+    x = m + _GH_X / np.sqrt(e)
+    f = (x - A) ** i * (x - B) ** j
+    return np.exp(c0) / np.sqrt(e) * np.sum(_GH_W * f)
+
+
+def potential_monomial(ijk_a, ijk_b, a, b, A, B, C):
+    """int x^i.. e^{-a r_A^2} x^j.. e^{-b r_B^2} / |r - C| dr of unnormalised
+    monomial Gaussians, by the Gaussian transform of 1/r; the t integral is
+    mapped to u in [0, 1) by t = sqrt(p) u / sqrt(1 - u^2)."""
+    p = a + b
+    total = 0.0
+    for u, wu in zip(_GL_U, _GL_WU):
+        t = np.sqrt(p) * u / np.sqrt(1.0 - u * u)
+        dt = np.sqrt(p) * (1.0 - u * u) ** -1.5
+        prod = 1.0
+        for ax in range(3):
+            prod *= _axis_potential(ijk_a[ax], ijk_b[ax], a, b, A[ax], B[ax], C[ax], t)
+        total += wu * dt * prod
+    return 2.0 / np.sqrt(np.pi) * total

@@ -628,3 +628,96 @@ def test_longrange_large_omega_is_coulomb_and_jk_consistent():
     assert 0.0 < ejw < ej0
     assert np.abs(Jw - Jw.T).max() <= 1e-14 * np.abs(Jw).max()
     assert np.abs(Kw - Kw.T).max() <= 1e-14 * np.abs(Kw).max()
+
+
+
+# ---------------------------------------------------------------------------
+# Point-charge potential V (eqs. v1e_definition, v1e_base_case, v1e_formula)
+# and its derivatives (SI eqs. si_v1e_derivative_A/B/C)
+# ---------------------------------------------------------------------------
+def test_potential_ss_closed_form():
+    """(s|q/|r-C||s) of unnormalised s Gaussians = q K_ab (2 pi/p) F_0(p|P-C|^2)
+    with F_0(T) = sqrt(pi/T) erf(sqrt T)/2 in mpmath (eq. v1e_base_case)."""
+    mp.mp.dps = 30
+    rng = np.random.default_rng(31)
+    for _ in range(5):
+        a, b = np.exp(rng.uniform(np.log(0.1), np.log(20.0), 2))
+        A, B, C = rng.uniform(-2.0, 2.0, (3, 3))
+        q = float(rng.uniform(-3, 3))
+        p = a + b
+        P = (a * A + b * B) / p
+        T = mp.mpf(p * float(np.sum((P - C) ** 2)))
+        F0 = mp.sqrt(mp.pi / T) * mp.erf(mp.sqrt(T)) / 2
+        ref = float(q * mp.e ** (-a * b / p * float(np.sum((A - B) ** 2))) * 2 * mp.pi / p * F0)
+        v = oracle.prim_vblock((0, 0), [a, b], np.concatenate([A, B]), [[*C, q]])[0, 0]
+        assert v == pytest.approx(ref, rel=1e-13)
+
+
+@pytest.mark.parametrize("ls,seed", [((1, 0), 1), ((1, 1), 2), ((2, 1), 3), ((3, 2), 4), ((3, 3), 5)])
+def test_potential_block_vs_bruteforce(ls, seed):
+    """Every Cartesian component of a primitive potential block (two charges)
+    against the Gaussian-transform quadrature of the defining integral."""
+    rng = np.random.default_rng(seed + 40)
+    ex = np.exp(rng.uniform(np.log(0.2), np.log(4.0), 2))
+    cen = rng.uniform(-1.2, 1.2, (2, 3))
+    chg = np.concatenate([rng.uniform(-2, 2, (2, 3)), rng.uniform(-2, 2, (2, 1))], axis=1)
+    blk = oracle.prim_vblock(ls, ex, cen.reshape(-1), chg)
+    cl = [oracle.cart_list(l) for l in ls]
+    scale = np.abs(blk).max()
+    for ia, ca in enumerate(cl[0]):
+        for ib, cb in enumerate(cl[1]):
+            ref = sum(q * bf.potential_monomial(ca, cb, ex[0], ex[1], cen[0], cen[1], C)
+                      for C, q in zip(chg[:, :3], chg[:, 3]))
+            assert abs(blk[ia, ib] - ref) <= 1e-11 * scale, (ia, ib, blk[ia, ib], ref)
+
+
+def test_potential_far_field():
+    """A charge far away sees the pair's charge: V_mn -> q S_mn / |R| with the
+    overlap S_mn of the normalised s functions (closed form)."""
+    mol = synth.custom([[0, 0, 0], [0.9, -0.3, 0.4]], [(0, 0, 2), (1, 0, 1)], seed=6, tau=0.0)
+    B = oracle.OBasis(mol)
+    R = np.array([3e5, -2e5, 1e5])  # dipole terms ~ |d|/|R| ~ 1e-6
+    V = oracle.vmatrix(mol, [[*R, 0.7]], basis_obj=B)
+    S = np.zeros((2, 2))
+    for a in range(2):
+        for b in range(2):
+            for i in range(B.nprim[a]):
+                for j in range(B.nprim[b]):
+                    ea, eb = B.exps[B.off[a] + i], B.exps[B.off[b] + j]
+                    XA, XB = B.xyz[3 * B.atom[a]:3 * B.atom[a] + 3], B.xyz[3 * B.atom[b]:3 * B.atom[b] + 3]
+                    S[a, b] += (B.coefs[B.off[a] + i] * B.coefs[B.off[b] + j] * (np.pi / (ea + eb)) ** 1.5
+                                * np.exp(-ea * eb / (ea + eb) * np.sum((XA - XB) ** 2)))
+    assert np.allclose(V, 0.7 * S / np.linalg.norm(R), rtol=1e-5, atol=0)
+
+
+def test_potential_gradient_fd_and_invariance():
+    """dE_V/dR for E_V = sum P V against central differences in atom and
+    charge coordinates, and the sum over atoms and charges vanishing."""
+    xyz = [[0.0, 0.0, 0.0], [1.2, 0.3, -0.4], [-0.5, 1.1, 0.8]]
+    specs = [(0, 0, 2), (1, 1, 1), (2, 2, 1), (0, 3, 1), (1, 0, 2)]
+    mol = synth.custom(xyz, specs, seed=33, tau=0.0)
+    rng = np.random.default_rng(33)
+    chg = np.concatenate([rng.uniform(-3, 3, (4, 3)), rng.uniform(-2, 2, (4, 1))], axis=1)
+    P = 0.5 * (mol.P + mol.P.T)
+    ga, gc = oracle.vgrad(mol, chg, P=P)
+    total = ga.sum(0) + gc.sum(0)
+    assert np.abs(total).max() <= 1e-11 * max(1.0, np.abs(ga).max())
+
+    def ev(x, c):
+        m = synth.custom(x, specs, seed=33, tau=0.0)
+        return float(np.sum(P * oracle.vmatrix(m, c)))
+
+    h = 1e-4
+    x0 = np.array(xyz)
+    for A, k in [(0, 0), (1, 2), (2, 1)]:
+        xp, xm = x0.copy(), x0.copy()
+        xp[A, k] += h
+        xm[A, k] -= h
+        fd = (ev(xp, chg) - ev(xm, chg)) / (2 * h)
+        assert ga[A, k] == pytest.approx(fd, rel=1e-6, abs=1e-8)
+    for c, k in [(0, 1), (3, 2)]:
+        cp_, cm_ = chg.copy(), chg.copy()
+        cp_[c, k] += h
+        cm_[c, k] -= h
+        fd = (ev(x0, cp_) - ev(x0, cm_)) / (2 * h)
+        assert gc[c, k] == pytest.approx(fd, rel=1e-6, abs=1e-8)
