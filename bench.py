@@ -213,6 +213,45 @@ def bench_grad(a):
             "max_abs_sum_over_atoms": float(np.abs(g.sum(0)).max()), "dtype": "f64"}
 
 
+def bench_potential(a, n_mm: int = 20000):
+    """Point-charge potential V and its gradient on mol40 with its 40 nuclei
+    plus n_mm QM/MM-style embedding charges (the paper's nuclear-attraction
+    study uses a QM region inside many thousands of point charges)."""
+    import torch
+    from paper_2406_14920_amd import JK, abi, synth
+    mol = synth.mol40()
+    chg = np.concatenate([synth.nuclei(mol, seed=1), synth.point_charges(mol, n_mm, seed=2)])
+    jk = JK.from_molecule(mol)
+    c = torch.tensor(chg, dtype=torch.float64, device="cuda")
+    P = torch.tensor(0.5 * (mol.P + mol.P.T), dtype=torch.float64, device="cuda")
+    jk.potential(c)
+    jk.potential_grad(c, P)
+    steps = max(1, min(a.steps, 5))
+    ms_v = _time(lambda: jk.potential(c), steps)
+    ms_g = _time(lambda: jk.potential_grad(c, P), steps)
+    abi.eri_set_profiling(jk.ctx, True)
+    jk.potential(c)
+    jk.potential_grad(c, P)
+    torch.cuda.synchronize()
+    prof = abi.eri_profile_read(jk.ctx)
+    abi.eri_set_profiling(jk.ctx, False)
+    jk.close()
+    vh = [r for r in prof if r["name"].startswith("vh(")]
+    pair_charge = sum(r["prim_quartets"] for r in vh)
+    fl = sum(r["flops"] for r in vh)
+    kms = sum(r["ms"] for r in vh)
+    top = max(vh, key=lambda r: r["ms"])
+    ach = top["flops"] / (top["ms"] / top["launches"] * 1e-3) / 1e12
+    print("potential mol40 + %d charges: V %.2f ms (%.2f TFLOP/s over the V kernels), gradient %.2f ms" % (
+        n_mm, ms_v, fl / (kms * 1e-3) / 1e12, ms_g), file=sys.stderr, flush=True)
+    return {"workload": "mol40 (840 spherical bf) with its 40 nuclei + %d embedding point charges" % n_mm,
+            "charges": int(chg.shape[0]), "dtype": "f64", "V_ms": ms_v, "grad_ms": ms_g,
+            "pair_charge_terms": int(pair_charge), "pair_charge_terms_per_s": pair_charge / (ms_v * 1e-3),
+            "V_kernels_tflops": fl / (kms * 1e-3) / 1e12,
+            "V_kernels_frac_fp64_peak": fl / (kms * 1e-3) / 1e12 / PEAK_FP64_VALU,
+            "top_kernel": top["name"], "top_kernel_tflops": ach}
+
+
 def bench_batch(a):
     """64 molecules of 5-30 atoms built as one batch (molecules on concurrent
     streams), against the same molecules built one after another."""
@@ -342,6 +381,7 @@ def main():
         out["tm62"] = bench_tm62(a)
     if not a.no_extras:
         out["grad"] = bench_grad(a)
+        out["potential"] = bench_potential(a)
         out["batch64"] = bench_batch(a)
     if not a.no_cpu:
         cb = cpu_baseline(mol)

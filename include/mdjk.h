@@ -189,6 +189,33 @@ int build_jk_static(eri_ctx *ctx, const double *P, double *J, double *K);
  * Asynchronous. */
 int jk_grad(eri_ctx *ctx, const double *P, double *grad, double *E);
 
+/* Point-charge potential matrix V_mn = sum_C q_C int m(r) n(r) / |r - C|
+ * (eqs. v1e_definition, v1e_summation_over_C; nuclear attraction with
+ * q_C = -Z_C, or embedding charges of a QM/MM calculation), by eq.
+ * v1e_formula: per primitive pair the Hermite potential
+ * K_ab (2 pi/p) sum_C q_C R^0_t(p, P - C) (one lane per primitive pair, all
+ * charges), then the pair's E coefficients.  Always the 1/r operator and
+ * double precision, whatever eri_set_omega / eri_set_precision chose; no
+ * primitive cut-off; the shell pairs are those the context keeps (pairs that
+ * fail the Schwarz rule against every pair are absent, as in build_jk).
+ * charges: device [ncharge][4] = x, y, z (bohr), q; ncharge >= 0 (0 gives
+ * V = 0).  V: device nbf*nbf row-major, overwritten.  Asynchronous; the
+ * context's work buffers are shared with build_jk on the same stream. */
+int eri_potential(eri_ctx *ctx, const double *charges, int32_t ncharge, double *V);
+
+/* Derivatives of E_V = sum_mn P_mn V_mn at fixed P (SI eqs.
+ * si_v1e_derivative_A, si_v1e_derivative_B, si_v1e_derivative_C): with
+ * respect to the atoms that carry the basis functions (the pair derivative of
+ * SI eq. si_pair_derivative with the Hermite potential of order la+lb+1) and
+ * to the charge positions (-q_C sum_t Dh_t R^0_{t+1_k}, Dh the pair's Hermite
+ * density).  A nucleus that carries basis functions and a charge gets both
+ * terms: the caller adds gatom[A] and gchg[C] for it.  Sums are formed in a
+ * fixed order: repeated calls give identical results.
+ * P: device nbf*nbf, symmetric.  gatom: device [natom*3] or NULL; gchg:
+ * device [ncharge*3] or NULL; both overwritten.  Asynchronous. */
+int eri_potential_grad(eri_ctx *ctx, const double *charges, int32_t ncharge, const double *P,
+                       double *gatom, double *gchg);
+
 /* E = 1/2 sum_ij P_ij J_ij - 1/4 sum_ij P_ij K_ij (SI eq. si_E_J_K) from
  * device P, J, K (nbf*nbf) into device E[1]; fixed-order reduction.
  * Asynchronous. */

@@ -77,6 +77,39 @@ class JK:
             abi.jk_grad(self.ctx, P, g, E)
         return (g, E) if energy else g
 
+    def _charges(self, charges):
+        import torch
+        if charges.dtype != torch.float64 or not charges.is_cuda or not charges.is_contiguous():
+            raise ValueError("charges must be a contiguous float64 CUDA tensor")
+        if charges.dim() != 2 or charges.shape[1] != 4:
+            raise ValueError("charges must be n x 4 (x, y, z, q)")
+        return charges, int(charges.shape[0])
+
+    def potential(self, charges):
+        """V_mn = sum_C q_C (m|1/|r - C||n) (eri_potential); charges: n x 4
+        float64 CUDA tensor of x, y, z (bohr), q (nuclei: q = -Z)."""
+        import torch
+        c, n = self._charges(charges)
+        V = torch.empty((self.nbf, self.nbf), dtype=torch.float64, device=c.device)
+        with torch.cuda.stream(self.stream):
+            abi.eri_potential(self.ctx, c, n, V)
+        return V
+
+    def potential_grad(self, charges, P):
+        """(dE_V/dR_atoms (natom x 3), dE_V/dR_charges (n x 3)) of
+        E_V = sum P_mn V_mn at fixed P (eri_potential_grad)."""
+        import torch
+        c, n = self._charges(charges)
+        if P.dtype != torch.float64 or not P.is_cuda or not P.is_contiguous():
+            raise ValueError("P must be a contiguous float64 CUDA tensor")
+        if P.shape != (self.nbf, self.nbf):
+            raise ValueError("P must be %d x %d" % (self.nbf, self.nbf))
+        ga = torch.empty((self.natom, 3), dtype=torch.float64, device=P.device)
+        gc = torch.empty((n, 3), dtype=torch.float64, device=P.device)
+        with torch.cuda.stream(self.stream):
+            abi.eri_potential_grad(self.ctx, c, n, P, ga, gc if n > 0 else None)
+        return ga, gc
+
     def energy(self, P, J, K):
         """E = 1/2 <P,J> - 1/4 <P,K> on the device (eri_energy)."""
         import torch

@@ -66,7 +66,7 @@ EXPORTS = ["eri_default_opts", "eri_setup", "eri_nbf", "eri_set_geometry", "eri_
            "build_jk", "jk_grad", "eri_energy", "eri_set_profiling", "eri_profile_read", "eri_stats", "eri_destroy",
            "eri_last_error", "eri_batch_create", "eri_batch_build_jk", "eri_batch_destroy",
            "eri_autotune", "eri_tuning", "build_jk_static", "eri_set_omega", "eri_get_tuning",
-           "eri_set_tuning"]
+           "eri_set_tuning", "eri_potential", "eri_potential_grad"]
 
 _lib = None
 
@@ -95,6 +95,8 @@ def load(path: str = LIB_PATH):
     L.build_jk_static.argtypes = [vp, vp, vp, vp]
     L.jk_grad.argtypes = [vp, vp, vp, vp]
     L.eri_energy.argtypes = [vp, vp, vp, vp, vp]
+    L.eri_potential.argtypes = [vp, vp, ctypes.c_int32, vp]
+    L.eri_potential_grad.argtypes = [vp, vp, ctypes.c_int32, vp, vp, vp]
     L.eri_stats.argtypes = [vp, ctypes.POINTER(eri_stats_t)]
     L.eri_set_profiling.argtypes = [vp, ctypes.c_int32]
     L.eri_profile_read.argtypes = [vp, ctypes.POINTER(eri_kernel_time), ctypes.c_int32,
@@ -231,6 +233,16 @@ def build_jk_static(ctx: int, P, J, K) -> None:
 
 def jk_grad(ctx: int, P, grad, E=None) -> None:
     _check(load().jk_grad(ctypes.c_void_p(ctx), _ptr(P), _ptr(grad), _ptr(E)))
+
+
+def eri_potential(ctx: int, charges, ncharge: int, V) -> None:
+    """V = sum_C q_C (m|1/|r-C||n); charges: device [ncharge][4] x, y, z, q."""
+    _check(load().eri_potential(ctypes.c_void_p(ctx), _ptr(charges), int(ncharge), _ptr(V)))
+
+
+def eri_potential_grad(ctx: int, charges, ncharge: int, P, gatom, gchg) -> None:
+    _check(load().eri_potential_grad(ctypes.c_void_p(ctx), _ptr(charges), int(ncharge), _ptr(P), _ptr(gatom),
+                                     _ptr(gchg)))
 
 
 def eri_energy(ctx: int, P, J, K, E) -> None:

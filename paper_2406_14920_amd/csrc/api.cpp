@@ -102,6 +102,11 @@ double fl_k_prim(int la, int lb, int lc, int ld)
 }
 double fl_k_digest(int la, int lb, int lc, int ld) { return 8.0 * ncart(la) * ncart(lb) * ncart(lc) * ncart(ld); }
 double fl_j_prim(int lx, int ly) { return fl_boys(lx + ly) + fl_r(lx + ly) + 2.0 * nherm(lx) * nherm(ly); }
+// one (primitive pair, point charge) term of the Hermite potential of order L:
+// distance and Boys argument, Boys, the scaled R^m_000, R, the accumulation
+double fl_v(int L) { return 8.0 + fl_boys(L) + fl_r(L) + 2.0 * (L + 1) + nherm(L); }
+// one (primitive pair, charge) term of the charge derivative at pair order L
+double fl_vg(int L) { return 8.0 + fl_boys(L + 1) + fl_r(L + 1) + 2.0 * (L + 2) + 7.0 * nherm(L); }
 
 bool jeng_is_reg(int lx, int ly)
 {
@@ -258,9 +263,11 @@ struct eri_ctx {
 
     // gradient: Hermite J of order LX+1, per-pair Coulomb terms, exchange
     // workgroup partials (allocated on the first jk_grad after each geometry)
-    bool grad_ready = false;
+    bool grad_ready = false, jh1_ready = false;
     size_t jh1_off[kPairClasses] = {};
-    DevBuf<double> d_Jh1, d_pg, d_kpart, d_Jtmp, d_Ktmp;
+    DevBuf<double> d_vpart;  // charge-gradient partials of eri_potential_grad
+    DevBuf<double> d_Jh1, d_pg, d_kpart, d_Jtmp, d_Ktmp, d_jhpart;
+    int gchunk[kPairClasses][kPairClasses] = {};  // J-engine ket chunk of the gradient launches
     std::vector<int> kg_blocks;   // per exchange launch
     std::vector<int64_t> kg_off;  // first partial of each launch
     int64_t kg_total = 0;
@@ -483,6 +490,7 @@ void build_pairs(eri_ctx *c)
     c->built_mixed = false;
     c->mix_counts_ok = false;
     c->grad_ready = false;
+    c->jh1_ready = false;
 
     // 4. exchange work lists.  The exchange kernels see each class through a
     // view grouped by contraction length and by the pair's first shell (the
@@ -1078,15 +1086,22 @@ void rec_work(const eri_ctx *c, const eri_ctx::Rec &r, int64_t &pq, double &flop
         }
         pq = p;
         flops = (double)p * fl_j_prim(kPairL[X][0] + kPairL[X][1], kPairL[Y][0] + kPairL[Y][1]);
+    } else if (r.work == 2 || r.work == 3) {  // potential: idx = X * 16 + order, part = charges
+        const int X = r.idx / 16, L = r.idx % 16;
+        pq = (int64_t)c->npp[X] * r.part;
+        flops = (double)pq * (r.work == 2 ? fl_v(L) : fl_vg(L));
     }
 }
 
 constexpr int kKgRange = 4;      // quartets per range of the exchange-gradient kernel
+constexpr int kGradChunks = 32;  // most ket chunks of a gradient J-engine launch
 constexpr int kKgMaxBlocks = 2048;
 
-void ensure_grad(eri_ctx *c)
+// Hermite arrays of order la+lb+1 of every primitive pair and the per-pair
+// centre terms: the Coulomb and the potential gradients.
+void ensure_jh1(eri_ctx *c)
 {
-    if (c->grad_ready) return;
+    if (c->jh1_ready) return;
     size_t o = 0;
     for (int X = 0; X < kPairClasses; ++X) {
         c->jh1_off[X] = o;
@@ -1094,6 +1109,26 @@ void ensure_grad(eri_ctx *c)
     }
     c->d_Jh1.alloc(std::max<size_t>(o, 1));
     c->d_pg.alloc(std::max<size_t>(6 * c->cp.size(), 1));
+    c->jh1_ready = true;
+}
+
+void ensure_grad(eri_ctx *c)
+{
+    if (c->grad_ready) return;
+    ensure_jh1(c);
+    // per-chunk Hermite J of one gradient J-engine launch (at most kGradChunks
+    // ket chunks), reduced in chunk order
+    size_t part = 1;
+    for (int X = 0; X < kPairClasses; ++X)
+        for (int Y = 0; Y < kPairClasses; ++Y) {
+            const int ncp = c->ncp[Y];
+            int kc = std::max(c->kchunk[X][Y], (ncp + kGradChunks - 1) / kGradChunks);
+            kc = std::max(kc, 1);
+            c->gchunk[X][Y] = kc;
+            const size_t nch = (size_t)((ncp + kc - 1) / kc);
+            part = std::max(part, nch * (size_t)c->npp[X] * nherm(kPairL[X][0] + kPairL[X][1] + 1));
+        }
+    c->d_jhpart.alloc(part);
     c->kg_blocks.assign(c->kwork.size(), 0);
     c->kg_off.assign(c->kwork.size(), 0);
     c->kg_total = 0;
@@ -1127,17 +1162,20 @@ void run_grad(eri_ctx *c, double *grad)
         for (int Y = 0; Y < kPairClasses; ++Y) {
             if (c->ncp[Y] == 0) continue;
             JArgs a = j_args(c, X, Y, false);
-            a.Jh = c->d_Jh1.p + c->jh1_off[X];
-            // one ket chunk: every Jh1 element gets exactly one addition per
-            // launch, so repeated gradients are bitwise identical
-            a.kchunk = c->ncp[Y];
+            // every ket chunk stores its sums; they are added to Jh1 in chunk
+            // order, so repeated gradients are bitwise identical
+            a.kchunk = c->gchunk[X][Y];
+            const int nch = (c->ncp[Y] + a.kchunk - 1) / a.kchunk;
             const int lx = kPairL[X][0] + kPairL[X][1] + 1, ly = kPairL[Y][0] + kPairL[Y][1];
+            a.Jh = c->d_jhpart.p;
+            a.jh_part = (int64_t)c->npp[X] * nherm(lx);
             timed(c, st, cls_name("jeng_grad", kPairL[X][0], kPairL[X][1], kPairL[Y][0], kPairL[Y][1]), -1, 0, 0,
                   [&] {
                       if (!launch_jeng(lx, ly, a, false, st)) {
                           set_err(ERI_ESTATE, "no J-engine kernel for orders (%d,%d)", lx, ly);
                           throw HipError{ERI_ESTATE};
                       }
+                      launch_jh_reduce(c->d_jhpart.p, nch, a.jh_part, c->d_Jh1.p + c->jh1_off[X], a.jh_part, st);
                   });
         }
     }
@@ -1175,6 +1213,108 @@ void run_grad(eri_ctx *c, double *grad)
         }
     }
     launch_grad_reduce(c->d_cp.p, (int)c->cp.size(), c->d_pg.p, c->d_kpart.p, c->kg_total, c->natom, grad, st);
+}
+
+// V = sum_C q_C (m|1/|r - C||n): Hermite potential of every primitive pair
+// (order la+lb), the J-engine's Hermite-to-Cartesian step, one triangle of
+// the accumulator (V = Acc + Acc^T), then the output basis.
+constexpr int64_t kVPartDoubles = 8 << 20;  // most charge-split partials of one potential launch
+
+// charge splits of each class's Hermite potential of order la+lb+extra, and
+// the partial buffer they need
+void potential_plan(eri_ctx *c, int nchg, int extra, int *ns)
+{
+    size_t need = 1;
+    for (int X = 0; X < kPairClasses; ++X) {
+        const int L = kPairL[X][0] + kPairL[X][1] + extra;
+        ns[X] = potential_splits(c->npp[X], nchg, L, kVPartDoubles);
+        if (ns[X] > 1) need = std::max(need, (size_t)ns[X] * c->npp[X] * nherm(L));
+    }
+    if (c->d_vpart.n < need) c->d_vpart.alloc(need);
+}
+
+void run_potential(eri_ctx *c, const double *chg, int nchg, double *V)
+{
+    hipStream_t st = c->st;
+    const int nc = c->nbf_cart;
+    int ns[kPairClasses];
+    potential_plan(c, nchg, 0, ns);
+    launch_fill_zero(c->wk.Jacc, (int64_t)nc * nc, st);
+    for (int X = 0; X < kPairClasses; ++X) {
+        if (c->npp[X] == 0) continue;
+        const int la = kPairL[X][0], lb = kPairL[X][1];
+        double *vh = c->wk.Jh + c->jh_off[X];
+        timed(c, st, cls_name("vh", la, lb, 0, 0), 2, X * 16 + la + lb, nchg, [&] {
+            if (!launch_vh(la + lb, c->d_pp.p, c->pp_base[X], c->npp[X], chg, nchg, c->d_boys.p, vh,
+                           c->d_vpart.p, ns[X], st)) {
+                set_err(ERI_ESTATE, "no potential kernel for order %d", la + lb);
+                throw HipError{ERI_ESTATE};
+            }
+        });
+        launch_hermite_to_cart(la, lb, c->d_cp.p + c->cp_base[X], c->ncp[X], c->d_pp.p, vh, c->pp_base[X],
+                               c->wk.Jacc, nc, st);
+    }
+    launch_acc_to_out(c->wk.Jacc, nc, V, c->nbf, shell_map(c), c->opts.spherical, st);
+}
+
+// dE_V/dR at fixed P (P_cart already in wk.Pc).  Atoms: the Hermite potential
+// of order la+lb+1 through the Coulomb gradient's pair-derivative kernel;
+// charges: the Hermite density against R of order la+lb+1.
+void run_potential_grad(eri_ctx *c, const double *chg, int nchg, double *gatom, double *gchg)
+{
+    hipStream_t st = c->st;
+    const int nc = c->nbf_cart;
+    if (gatom) {
+        ensure_jh1(c);
+        int ns[kPairClasses];
+        potential_plan(c, nchg, 1, ns);
+        for (int X = 0; X < kPairClasses; ++X) {
+            if (c->npp[X] == 0) continue;
+            const int la = kPairL[X][0], lb = kPairL[X][1];
+            double *vh = c->d_Jh1.p + c->jh1_off[X];
+            timed(c, st, cls_name("vh1", la, lb, 0, 0), 2, X * 16 + la + lb + 1, nchg, [&] {
+                if (!launch_vh(la + lb + 1, c->d_pp.p, c->pp_base[X], c->npp[X], chg, nchg, c->d_boys.p, vh,
+                               c->d_vpart.p, ns[X], st)) {
+                    set_err(ERI_ESTATE, "no potential kernel for order %d", la + lb + 1);
+                    throw HipError{ERI_ESTATE};
+                }
+            });
+            JGArgs g{};
+            g.cp = c->d_cp.p + c->cp_base[X];
+            g.ncp = c->ncp[X];
+            g.pp = c->d_pp.p;
+            g.Jh1 = vh;
+            g.jh_base = c->pp_base[X];
+            g.D = c->wk.Pc;
+            g.ld = nc;
+            g.pg = c->d_pg.p + 6 * (size_t)c->cp_base[X];
+            launch_jgrad(la, lb, g, st);
+        }
+        launch_grad_reduce(c->d_cp.p, (int)c->cp.size(), c->d_pg.p, nullptr, 0, c->natom, gatom, st);
+    }
+    if (gchg && nchg > 0) {
+        launch_fill_zero(gchg, 3 * (int64_t)nchg, st);
+        // pair splits per class: enough workgroups (64 charges each) to fill
+        // the chip, at least 16 pairs per split
+        const int groups = (nchg + 63) / 64;
+        const int nshare = std::max(1, std::min(64, (4096 + groups - 1) / groups));
+        const size_t need = (size_t)nshare * 3 * nchg;
+        if (c->d_vpart.n < need) c->d_vpart.alloc(need);
+        for (int X = 0; X < kPairClasses; ++X) {
+            if (c->npp[X] == 0) continue;
+            const int la = kPairL[X][0], lb = kPairL[X][1];
+            launch_hermite_density(la, lb, c->d_cp.p + c->cp_base[X], c->ncp[X], c->d_pp.p, c->wk.Pc, nc,
+                                   c->wk.Dt + c->dt_off[X], nullptr, c->pp_base[X], st);
+            const int ns = std::max(1, std::min(nshare, (c->npp[X] + 15) / 16));
+            timed(c, st, cls_name("vgrad_chg", la, lb, 0, 0), 3, X * 16 + la + lb, nchg, [&] {
+                if (!launch_vgrad_charge(la + lb, c->d_pp.p, c->pp_base[X], c->npp[X], c->wk.Dt + c->dt_off[X],
+                                         chg, nchg, c->d_boys.p, c->d_vpart.p, ns, gchg, st)) {
+                    set_err(ERI_ESTATE, "no charge-gradient kernel for order %d", la + lb);
+                    throw HipError{ERI_ESTATE};
+                }
+            });
+        }
+    }
 }
 
 }  // namespace
@@ -1383,6 +1523,43 @@ int jk_grad(eri_ctx *ctx, const double *P, double *grad, double *E)
             launch_p_to_cart(P, ctx->nbf, ctx->wk.Pc, ctx->nbf_cart, m, ctx->opts.spherical, st);
             run_grad(ctx, grad);
         }
+        HIPCHK(hipGetLastError());
+    } catch (const HipError &e) {
+        return e.code;
+    } catch (const std::bad_alloc &) {
+        return set_err(ERI_ENOMEM, "host allocation failed");
+    }
+    return ERI_OK;
+}
+
+int eri_potential(eri_ctx *ctx, const double *charges, int32_t ncharge, double *V)
+{
+    if (!ctx_ok(ctx)) return set_err(ERI_ESTATE, "invalid context");
+    if (!V) return set_err(ERI_EINVAL, "V is NULL");
+    if (ncharge < 0) return set_err(ERI_EINVAL, "ncharge %d negative", ncharge);
+    if (ncharge > 0 && !charges) return set_err(ERI_EINVAL, "charges is NULL");
+    try {
+        run_potential(ctx, charges, ncharge, V);
+        HIPCHK(hipGetLastError());
+    } catch (const HipError &e) {
+        return e.code;
+    } catch (const std::bad_alloc &) {
+        return set_err(ERI_ENOMEM, "host allocation failed");
+    }
+    return ERI_OK;
+}
+
+int eri_potential_grad(eri_ctx *ctx, const double *charges, int32_t ncharge, const double *P, double *gatom,
+                       double *gchg)
+{
+    if (!ctx_ok(ctx)) return set_err(ERI_ESTATE, "invalid context");
+    if (!P) return set_err(ERI_EINVAL, "P is NULL");
+    if (!gatom && !gchg) return set_err(ERI_EINVAL, "gatom and gchg are both NULL");
+    if (ncharge < 0) return set_err(ERI_EINVAL, "ncharge %d negative", ncharge);
+    if (ncharge > 0 && !charges) return set_err(ERI_EINVAL, "charges is NULL");
+    try {
+        launch_p_to_cart(P, ctx->nbf, ctx->wk.Pc, ctx->nbf_cart, shell_map(ctx), ctx->opts.spherical, ctx->st);
+        run_potential_grad(ctx, charges, ncharge, gatom, gchg);
         HIPCHK(hipGetLastError());
     } catch (const HipError &e) {
         return e.code;

@@ -179,7 +179,7 @@ __global__ __launch_bounds__(64) void jeng_small(JArgs a)
             }
         }
     }
-    if (valid && j1 > j0) {
+    if (valid && (j1 > j0 || a.jh_part > 0)) {
         // scaled form: Jh_P = K_ab (2p)^{|P|/2} times the single-precision sum
         double cw[LX + 1];
         cw[0] = pb.K;
@@ -190,7 +190,10 @@ __global__ __launch_bounds__(64) void jeng_small(JArgs a)
             constexpr int P = decltype(pc)::value;
             double v;
             if constexpr (F32) v = Jh[P] * cw[herm_t(P) + herm_u(P) + herm_v(P)]; else v = Jt[P];
-            unsafeAtomicAdd(&a.Jh[(int64_t)g * NX + P], v);
+            if (a.jh_part > 0)
+                a.Jh[(int64_t)blockIdx.y * a.jh_part + (int64_t)g * NX + P] = v;
+            else
+                unsafeAtomicAdd(&a.Jh[(int64_t)g * NX + P], v);
         });
     }
 }
@@ -217,7 +220,7 @@ __global__ __launch_bounds__(64) void jeng_wave(JArgs a)
     const int nv = count_kets(a.Qket, a.nket, Qi, a.tau);
     const int j0 = blockIdx.y * a.kchunk;
     const int j1 = min(min(a.nket, j0 + a.kchunk), nv);
-    if (j1 <= j0) return;
+    if (j1 <= j0 && a.jh_part == 0) return;  // (per-chunk stores still write their zeros)
 
     // lane owns P = lane and P = lane + 64
     int pof[2];
@@ -283,8 +286,29 @@ __global__ __launch_bounds__(64) void jeng_wave(JArgs a)
                 v *= pb.K;
                 for (int k = 0; k < n; ++k) v *= c;
             }
-            unsafeAtomicAdd(&a.Jh[(int64_t)g * NX + lane + 64 * r], v);
+            if (a.jh_part > 0)
+                a.Jh[(int64_t)blockIdx.y * a.jh_part + (int64_t)g * NX + lane + 64 * r] = v;
+            else
+                unsafeAtomicAdd(&a.Jh[(int64_t)g * NX + lane + 64 * r], v);
         }
+}
+
+// out[i] += sum over the chunks c = 0, 1, ... of part[c * stride + i], in that
+// order (the gradient's Hermite J: repeatable sums with many ket chunks)
+__global__ void jh_reduce(const double *__restrict__ part, int nch, int64_t stride, double *__restrict__ out,
+                          int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double s = out[i];
+    for (int c = 0; c < nch; ++c) s += part[(int64_t)c * stride + i];
+    out[i] = s;
+}
+
+void launch_jh_reduce(const double *part, int nch, int64_t stride, double *out, int64_t n, hipStream_t st)
+{
+    if (n <= 0 || nch <= 0) return;
+    hipLaunchKernelGGL(jh_reduce, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, part, nch, stride, out, n);
 }
 
 // ---------------------------------------------------------------------------

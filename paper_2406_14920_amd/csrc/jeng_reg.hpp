@@ -149,7 +149,7 @@ __global__ __launch_bounds__(64) void jeng_reg(JArgs a)
             }
         }
     }
-    if (valid && j1 > j0) {
+    if (valid && (j1 > j0 || a.jh_part > 0)) {
         // scaled form: Jh_P = K_ab (2p)^{|P|/2} times the single-precision sum
         double cw[LX + 1];
         cw[0] = pb.K;
@@ -160,7 +160,10 @@ __global__ __launch_bounds__(64) void jeng_reg(JArgs a)
             constexpr int P = decltype(pc)::value;
             double v;
             if constexpr (F32) v = Jh[P] * cw[herm_t(P) + herm_u(P) + herm_v(P)]; else v = Jt[P];
-            unsafeAtomicAdd(&a.Jh[(int64_t)g * NX + P], v);
+            if (a.jh_part > 0)
+                a.Jh[(int64_t)blockIdx.y * a.jh_part + (int64_t)g * NX + P] = v;
+            else
+                unsafeAtomicAdd(&a.Jh[(int64_t)g * NX + P], v);
         });
     }
 }

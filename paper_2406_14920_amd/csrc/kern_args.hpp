@@ -132,6 +132,10 @@ struct JArgs {
     double tau_mix;
     const double *QDket;
     double om2;              // omega^2 of the operator erf(omega r)/r; 0: 1/r
+    // > 0: each ket chunk (blockIdx.y) stores its sums with plain stores at
+    // Jh + chunk * jh_part (zeros where it has no kets), for a fixed-order
+    // reduction over the chunks; 0: atomic additions into Jh
+    int64_t jh_part;
 };
 
 // Bra-shared exchange launch: one workgroup per chunk of up to 64

@@ -38,6 +38,7 @@ void launch_hermite_density(int lc, int ld, const CPair *cp, int ncp, const Prim
 void launch_hermite_to_cart(int la, int lb, const CPair *cp, int ncp, const PrimPair *pp,
                             const double *Jh, int jh_base, double *Jacc, int ld, hipStream_t st);
 bool launch_jeng(int lx, int ly, const JArgs &a, bool fp32, hipStream_t st);
+void launch_jh_reduce(const double *part, int nch, int64_t stride, double *out, int64_t n, hipStream_t st);
 
 void launch_schwarz(int la, int lb, const CPair *cp, int ncp, PrimPair *pp, double *Q,
                     const double *boys, hipStream_t st);
@@ -67,5 +68,16 @@ void launch_jgrad(int la, int lb, const JGArgs &g, hipStream_t st);
 void launch_grad_reduce(const CPair *cp, int ncp, const double *pg, const double *kpart, int64_t nkblocks,
                         int natom, double *grad, hipStream_t st);
 void launch_energy(const double *P, const double *J, const double *K, int64_t n2, double *E, hipStream_t st);
+
+// point-charge potential (potential.hip); chg holds [n][4] = x, y, z, q
+// Hermite potential of order L of npp primitive pairs into Vh [npp][nherm(L)];
+// with nsplit > 1 the charges are split over nsplit launches' worth of
+// workgroups whose sums go to part [nsplit][npp][nherm(L)] and are reduced in
+// order.  potential_splits picks nsplit within cap_doubles of part.
+int potential_splits(int npp, int nchg, int L, int64_t cap_doubles);
+bool launch_vh(int L, const PrimPair *pp, int pbase, int npp, const double *chg, int nchg, const double *btab,
+               double *Vh, double *part, int nsplit, hipStream_t st);
+bool launch_vgrad_charge(int L, const PrimPair *pp, int pbase, int npp, const double *Dt, const double *chg,
+                         int nchg, const double *btab, double *part, int nshare, double *gchg, hipStream_t st);
 
 }  // namespace md

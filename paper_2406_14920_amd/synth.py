@@ -206,3 +206,27 @@ def custom(xyz, shell_specs, seed: int = 0, tau: float = 1e-12, nocc=None,
 
 
 WORKLOADS = {"mol4": mol4, "mol40": mol40, "tm62": tm62, "mol20": mol20}
+
+
+def nuclei(mol: Molecule, seed: int = 0) -> np.ndarray:
+    """Nuclear point charges of the atoms, rows x, y, z, q with q = -Z and Z
+    drawn from {1, 6, 7, 8} (the synthetic atoms carry no element)."""
+    rng = np.random.default_rng(seed)
+    Z = rng.choice(np.array([1.0, 6.0, 7.0, 8.0]), size=mol.natom)
+    return np.concatenate([mol.xyz, -Z[:, None]], axis=1)
+
+
+def point_charges(mol: Molecule, n: int, seed: int = 0, rmin: float = 2.0, pad: float = 8.0) -> np.ndarray:
+    """n embedding point charges (QM/MM style), rows x, y, z, q: uniform in the
+    atoms' bounding box widened by `pad` bohr, none closer than `rmin` bohr to
+    an atom, q uniform in [-1, 1]."""
+    rng = np.random.default_rng(seed)
+    lo = mol.xyz.min(axis=0) - pad
+    hi = mol.xyz.max(axis=0) + pad
+    out = np.zeros((0, 3))
+    while out.shape[0] < n:
+        x = rng.uniform(lo, hi, size=(max(64, 2 * (n - out.shape[0])), 3))
+        d2 = ((x[:, None, :] - mol.xyz[None, :, :]) ** 2).sum(-1).min(axis=1)
+        out = np.concatenate([out, x[d2 >= rmin * rmin]], axis=0)
+    q = rng.uniform(-1.0, 1.0, size=n)
+    return np.concatenate([out[:n], q[:, None]], axis=1)
