@@ -87,6 +87,8 @@ def lib():
         L.oracle_vmatrix.argtypes = bas + [dp, ip, ip, ctypes.c_int32, ctypes.c_int32, dp, dp]
         L.oracle_vgrad.argtypes = bas + [dp, ip, ip, ctypes.c_int32, ctypes.c_int32, dp, dp, dp, dp]
         L.oracle_prim_vblock.argtypes = [ctypes.c_int, ctypes.c_int, dp, dp, ctypes.c_int32, dp, dp]
+        L.oracle_st.argtypes = bas + [dp, ip, ip, ctypes.c_int32, dp, dp]
+        L.oracle_prim_stblock.argtypes = [ctypes.c_int, ctypes.c_int, dp, dp, dp, dp]
         L.oracle_set_omega.argtypes = [ctypes.c_double]
         L.oracle_set_omega.restype = None
         L.oracle_get_omega.restype = ctypes.c_double
@@ -313,6 +315,87 @@ def vgrad(mol, charges, P=None, basis_obj=None):
     gc = np.zeros((max(n, 1), 3))
     lib().oracle_vgrad(*B.args(), _dp(B.T), _ip(B.Toff), _ip(B.ao_off), B.nbf, n, _dp(c), _dp(P), _dp(ga), _dp(gc))
     return ga, gc[:n]
+
+
+def prim_stblock(ls, exps, centres):
+    """Primitive Cartesian overlap and kinetic blocks between unnormalised
+    monomial Gaussians (eqs. overlap_formula, kinetic_formula)."""
+    la, lb = ls
+    n = ((la + 1) * (la + 2) // 2, (lb + 1) * (lb + 2) // 2)
+    S = np.zeros(n[0] * n[1])
+    T = np.zeros(n[0] * n[1])
+    e = np.ascontiguousarray(exps, float)
+    x = np.ascontiguousarray(centres, float).reshape(6)
+    lib().oracle_prim_stblock(la, lb, _dp(e), _dp(x), _dp(S), _dp(T))
+    return S.reshape(n), T.reshape(n)
+
+
+def st(mol, basis_obj=None):
+    """Overlap S and kinetic energy T (spherical basis) over every ordered
+    shell pair (eqs. overlap_definition, kinetic_definition)."""
+    B = basis_obj or OBasis(mol)
+    S = np.zeros((B.nbf, B.nbf))
+    T = np.zeros((B.nbf, B.nbf))
+    lib().oracle_st(*B.args(), _dp(B.T), _ip(B.Toff), _ip(B.ao_off), B.nbf, _dp(S), _dp(T))
+    return S, T
+
+
+def nuclear_repulsion(charges) -> float:
+    """sum over pairs of point charges q_A q_B / |A - B|."""
+    c = np.asarray(charges, float).reshape(-1, 4)
+    e = 0.0
+    for i in range(c.shape[0]):
+        for j in range(i):
+            e += c[i, 3] * c[j, 3] / np.linalg.norm(c[i, :3] - c[j, :3])
+    return e
+
+
+def rhf(mol, nuclei, nocc: int, conv: float = 1e-10, max_iter: int = 200, basis_obj=None, tau=None,
+        tau_prim=None):
+    """Closed-shell Hartree-Fock energy: F = T + V + J(P) - K(P)/2 with the
+    total density P = 2 C_occ C_occ^T (J, K by eqs. j_definition and
+    k_definition; V of the nuclei q = -Z by eq. v1e_definition), solved in the
+    canonically orthogonalised basis (overlap eigenvalues below 1e-8 dropped)
+    with Pulay's commutator extrapolation, from the core-Hamiltonian guess.
+    Returns (E_total, P, iterations)."""
+    B = basis_obj or OBasis(mol)
+    S, T = st(mol, basis_obj=B)
+    H = T + vmatrix(mol, nuclei, basis_obj=B)
+    s, U = np.linalg.eigh(S)
+    keep = s > 1e-8
+    X = U[:, keep] / np.sqrt(s[keep])
+    enuc = nuclear_repulsion(nuclei)
+
+    def density(F):
+        e, C = np.linalg.eigh(X.T @ F @ X)
+        Co = X @ C[:, :nocc]
+        return 2.0 * Co @ Co.T
+
+    P = density(H)
+    Fs, errs = [], []
+    E_old = None
+    for it in range(1, max_iter + 1):
+        J, K = jk(mol, P=P, basis_obj=B, tau=tau, tau_prim=tau_prim)
+        F = H + J - 0.5 * K
+        E = 0.5 * float(np.sum(P * (H + F))) + enuc
+        err = X.T @ (F @ P @ S - S @ P @ F) @ X
+        Fs.append(F)
+        errs.append(err)
+        Fs, errs = Fs[-8:], errs[-8:]
+        if E_old is not None and abs(E - E_old) < conv and np.abs(err).max() < 1e-7:
+            return E, P, it
+        E_old = E
+        n = len(Fs)
+        Bm = -np.ones((n + 1, n + 1))
+        Bm[n, n] = 0.0
+        for i in range(n):
+            for j in range(n):
+                Bm[i, j] = float(np.sum(errs[i] * errs[j]))
+        rhs = np.zeros(n + 1)
+        rhs[n] = -1.0
+        c = np.linalg.lstsq(Bm, rhs, rcond=None)[0][:n]
+        P = density(sum(ci * Fi for ci, Fi in zip(c, Fs)))
+    raise RuntimeError("rhf: no convergence in %d iterations" % max_iter)
 
 
 def energy(mol, J, K, P=None) -> float:

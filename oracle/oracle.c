@@ -951,3 +951,79 @@ int oracle_num_threads(void)
     return 1;
 #endif
 }
+
+/* ------------------------------------------------------------------------ */
+/* Overlap and kinetic energy (eqs. overlap_definition, overlap_formula,    */
+/* kinetic_definition, kinetic_formula): with the one-direction Hermite      */
+/* coefficients E (whose E^{00}_0 carries that direction's factor of K_AB)   */
+/*   S = C (pi/p)^{3/2} E^x_0 E^y_0 E^z_0,                                   */
+/*   T = C (pi/p)^{3/2} sum_k t_k prod_{other} E_0,                          */
+/*   t_k = -j(j-1)/2 E^{i,j-2}_0 + (2j+1) b E^{i,j}_0 - 2 b^2 E^{i,j+2}_0.    */
+/* ------------------------------------------------------------------------ */
+static void prim_stblock(int la, int lb, double a, double b, const double *A, const double *B, double scale,
+                         double *S, double *T, scratch_t *W)
+{
+    double p = a + b;
+    for (int k = 0; k < 3; ++k) e_coeffs(la, lb + 2, a, b, A[k], B[k], W->Eab[k]);
+    int ca[64][3], cb[64][3];
+    cart_list(la, ca);
+    cart_list(lb, cb);
+    int na = ncart(la), nb = ncart(lb);
+    double pref = scale * pow(OR_PI / p, 1.5);
+    for (int ia = 0; ia < na; ++ia)
+        for (int ib = 0; ib < nb; ++ib) {
+            double sk[3], tk[3];
+            for (int k = 0; k < 3; ++k) {
+                int i = ca[ia][k], j = cb[ib][k];
+                sk[k] = W->Eab[k][i][j][0];
+                double t = (2 * j + 1) * b * W->Eab[k][i][j][0] - 2.0 * b * b * W->Eab[k][i][j + 2][0];
+                if (j >= 2) t -= 0.5 * j * (j - 1) * W->Eab[k][i][j - 2][0];
+                tk[k] = t;
+            }
+            S[ia * nb + ib] += pref * sk[0] * sk[1] * sk[2];
+            T[ia * nb + ib] += pref * (tk[0] * sk[1] * sk[2] + sk[0] * tk[1] * sk[2] + sk[0] * sk[1] * tk[2]);
+        }
+}
+
+/* S and T (spherical, nbf x nbf) over every ordered shell pair. */
+void oracle_st(int32_t nshell, int32_t natom, const int32_t *atom, const int32_t *l, const int32_t *nprim,
+               const int32_t *off, const double *exps, const double *coefs, const double *xyz, const double *Tsph,
+               const int *Toff, const int32_t *ao_off, int32_t nbf, double *S, double *T)
+{
+    basis_t B = mkbasis(nshell, natom, atom, l, nprim, off, exps, coefs, xyz);
+#pragma omp parallel
+    {
+        scratch_t *W = (scratch_t *)malloc(sizeof(scratch_t));
+        double sb[256], tb[256], sph[64];
+#pragma omp for schedule(dynamic, 1)
+        for (int a = 0; a < nshell; ++a)
+            for (int b = 0; b < nshell; ++b) {
+                int n = ncart(l[a]) * ncart(l[b]);
+                memset(sb, 0, sizeof(double) * n);
+                memset(tb, 0, sizeof(double) * n);
+                for (int i = 0; i < nprim[a]; ++i)
+                    for (int j = 0; j < nprim[b]; ++j)
+                        prim_stblock(l[a], l[b], exps[off[a] + i], exps[off[b] + j], xyz + 3 * atom[a],
+                                     xyz + 3 * atom[b], B.coefs[off[a] + i] * B.coefs[off[b] + j], sb, tb, W);
+                int na = 2 * l[a] + 1, nb = 2 * l[b] + 1;
+                vblock_sph(l[a], l[b], Tsph, Toff, sb, sph);
+                for (int x = 0; x < na; ++x)
+                    for (int y = 0; y < nb; ++y) S[(ao_off[a] + x) * nbf + ao_off[b] + y] = sph[x * nb + y];
+                vblock_sph(l[a], l[b], Tsph, Toff, tb, sph);
+                for (int x = 0; x < na; ++x)
+                    for (int y = 0; y < nb; ++y) T[(ao_off[a] + x) * nbf + ao_off[b] + y] = sph[x * nb + y];
+            }
+        free(W);
+    }
+}
+
+/* One primitive Cartesian S and T block for the pins (unnormalised monomials). */
+void oracle_prim_stblock(int la, int lb, const double *exps2, const double *centres6, double *S, double *T)
+{
+    scratch_t *W = (scratch_t *)malloc(sizeof(scratch_t));
+    memset(S, 0, sizeof(double) * ncart(la) * ncart(lb));
+    memset(T, 0, sizeof(double) * ncart(la) * ncart(lb));
+    prim_stblock(la, lb, exps2[0], exps2[1], centres6, centres6 + 3, 1.0, S, T, W);
+    free(W);
+}
+

@@ -89,3 +89,28 @@ def potential_monomial(ijk_a, ijk_b, a, b, A, B, C):
             prod *= _axis_potential(ijk_a[ax], ijk_b[ax], a, b, A[ax], B[ax], C[ax], t)
         total += wu * dt * prod
     return 2.0 / np.sqrt(np.pi) * total
+
+
+def _axis_st(i, j, a, b, A, B):
+    """One-direction overlap int f_a f_b and derivative product
+    int f_a' f_b' of f_a = (x-A)^i e^{-a(x-A)^2}, f_b = (x-B)^j e^{-b(x-B)^2},
+    with the derivatives written out as polynomials, by Gauss-Hermite
+    quadrature about the product centre."""
+    p = a + b
+    P = (a * A + b * B) / p
+    c0 = -a * b / p * (A - B) ** 2
+    x = P + _GH_X / np.sqrt(p)
+    fa, fb = (x - A) ** i, (x - B) ** j
+    dfa = (i * (x - A) ** (i - 1) if i > 0 else 0.0) - 2.0 * a * (x - A) ** (i + 1)
+    dfb = (j * (x - B) ** (j - 1) if j > 0 else 0.0) - 2.0 * b * (x - B) ** (j + 1)
+    f = np.exp(c0) / np.sqrt(p)
+    return f * np.sum(_GH_W * fa * fb), f * np.sum(_GH_W * dfa * dfb)
+
+
+def overlap_kinetic_monomial(ijk_a, ijk_b, a, b, A, B):
+    """S = int a b and T = -1/2 int a lap(b) = 1/2 int grad(a).grad(b) of
+    unnormalised monomial Gaussians (integration by parts; no recurrence)."""
+    s, d = zip(*[_axis_st(ijk_a[k], ijk_b[k], a, b, A[k], B[k]) for k in range(3)])
+    S = s[0] * s[1] * s[2]
+    T = 0.5 * (d[0] * s[1] * s[2] + s[0] * d[1] * s[2] + s[0] * s[1] * d[2])
+    return S, T

@@ -721,3 +721,110 @@ def test_potential_gradient_fd_and_invariance():
         cm_[c, k] -= h
         fd = (ev(x0, cp_) - ev(x0, cm_)) / (2 * h)
         assert gc[c, k] == pytest.approx(fd, rel=1e-6, abs=1e-8)
+
+
+# ---------------------------------------------------------------------------
+# Overlap and kinetic energy (eqs. overlap_formula, kinetic_formula) and the
+# closed-shell SCF built on them
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("ls,seed", [((0, 0), 1), ((1, 0), 2), ((0, 2), 3), ((1, 1), 4), ((2, 3), 5),
+                                     ((3, 2), 6), ((3, 3), 7)])
+def test_overlap_kinetic_block_vs_bruteforce(ls, seed):
+    """Every Cartesian component of primitive S and T blocks against
+    quadrature of the defining integrals (T through 1/2 grad.grad)."""
+    rng = np.random.default_rng(seed + 70)
+    ex = np.exp(rng.uniform(np.log(0.2), np.log(6.0), 2))
+    cen = rng.uniform(-1.2, 1.2, (2, 3))
+    S, T = oracle.prim_stblock(ls, ex, cen.reshape(-1))
+    cl = [oracle.cart_list(l) for l in ls]
+    ss, ts = np.abs(S).max(), np.abs(T).max()
+    for ia, ca in enumerate(cl[0]):
+        for ib, cb in enumerate(cl[1]):
+            rs, rt = bf.overlap_kinetic_monomial(ca, cb, ex[0], ex[1], cen[0], cen[1])
+            assert abs(S[ia, ib] - rs) <= 1e-13 * ss, (ia, ib)
+            assert abs(T[ia, ib] - rt) <= 1e-12 * ts, (ia, ib, T[ia, ib], rt)
+
+
+def test_kinetic_ss_closed_form():
+    """(s|T|s) = mu (3 - 2 mu R^2) (pi/p)^{3/2} e^{-mu R^2}, mu = ab/p."""
+    rng = np.random.default_rng(77)
+    for _ in range(5):
+        a, b = np.exp(rng.uniform(np.log(0.1), np.log(20.0), 2))
+        A, B = rng.uniform(-2.0, 2.0, (2, 3))
+        p, mu, R2 = a + b, a * b / (a + b), float(np.sum((A - B) ** 2))
+        S, T = oracle.prim_stblock((0, 0), [a, b], np.concatenate([A, B]))
+        s_ref = (np.pi / p) ** 1.5 * np.exp(-mu * R2)
+        assert S[0, 0] == pytest.approx(s_ref, rel=1e-14)
+        assert T[0, 0] == pytest.approx(mu * (3.0 - 2.0 * mu * R2) * s_ref, rel=1e-13, abs=1e-15)
+
+
+def test_overlap_is_unit_on_the_diagonal_and_kinetic_positive():
+    """Normalised spherical functions: S_ii = 1; T is symmetric positive
+    definite (a kinetic energy)."""
+    mol = synth.small_cluster(3, seed=5, tau=0.0)
+    S, T = oracle.st(mol)
+    assert np.allclose(np.diag(S), 1.0, atol=1e-12)
+    assert np.abs(S - S.T).max() <= 1e-14 and np.abs(T - T.T).max() <= 1e-12 * np.abs(T).max()
+    assert np.linalg.eigvalsh(T).min() > 0.0
+
+
+def _h2_minimal(R=1.4, seed=0):
+    xyz = [[0.0, 0.0, 0.0], [0.0, 0.0, R]]
+    mol = synth.custom(xyz, [(0, 0, 3), (1, 0, 3)], seed=seed, tau=0.0, exp_range=(0.15, 4.0))
+    mol.shells[1].exps = mol.shells[0].exps.copy()     # the same function on both atoms
+    mol.shells[1].coefs = mol.shells[0].coefs.copy()
+    nuc = np.array([[0.0, 0.0, 0.0, 1.0], [0.0, 0.0, R, 1.0]])
+    return mol, nuc
+
+
+def test_rhf_symmetric_two_centre_minimal_basis():
+    """Two identical s functions on two unit charges, two electrons: the
+    occupied orbital is fixed by symmetry, (phi1 + phi2)/sqrt(2 + 2 S12), so
+    the converged RHF energy equals sum P (H + F)/2 + 1/R at that density
+    (the nuclei enter V with q = -Z)."""
+    mol, nuc = _h2_minimal()
+    nucq = nuc.copy()
+    nucq[:, 3] = -1.0
+    E, P, it = oracle.rhf(mol, nucq, nocc=1)
+    S, T = oracle.st(mol)
+    H = T + oracle.vmatrix(mol, nucq)
+    c = np.array([1.0, 1.0]) / np.sqrt(2.0 + 2.0 * S[0, 1])
+    Pref = 2.0 * np.outer(c, c)
+    J, K = oracle.jk(mol, P=Pref)
+    Eref = 0.5 * np.sum(Pref * (2 * H + J - 0.5 * K)) + 1.0 / 1.4
+    assert np.abs(P - Pref).max() <= 1e-8
+    assert E == pytest.approx(Eref, abs=1e-10)
+
+
+def test_rhf_energy_is_stationary_minimum():
+    """At convergence, rotating the occupied orbitals into the virtual space
+    by a small angle raises the energy quadratically (first order zero)."""
+    mol = synth.small_cluster(2, seed=8, tau=0.0, shellset=((0, 3), (0, 1), (1, 2), (2, 1)))
+    nuc = np.concatenate([mol.xyz, -np.array([[3.0], [3.0]])], axis=1)
+    E, P, _ = oracle.rhf(mol, nuc, nocc=3)
+    S, T = oracle.st(mol)
+    H = T + oracle.vmatrix(mol, nuc)
+    enuc = oracle.nuclear_repulsion(nuc)
+    s, U = np.linalg.eigh(S)
+    X = U / np.sqrt(s)
+    J, K = oracle.jk(mol, P=P)
+    e, C = np.linalg.eigh(X.T @ (H + J - 0.5 * K) @ X)
+    C = X @ C
+
+    def energy_of(Cocc):
+        Pn = 2.0 * Cocc @ Cocc.T
+        Jn, Kn = oracle.jk(mol, P=Pn)
+        return 0.5 * np.sum(Pn * (2 * H + Jn - 0.5 * Kn)) + enuc
+
+    assert energy_of(C[:, :3]) == pytest.approx(E, abs=1e-9)
+    rng = np.random.default_rng(1)
+    kappa = rng.standard_normal((C.shape[1] - 3, 3))
+    d = []
+    for h in (1e-3, 2e-3):
+        Co = C[:, :3] + h * C[:, 3:] @ kappa
+        # re-orthonormalise in the S metric
+        w, V = np.linalg.eigh(Co.T @ S @ Co)
+        Co = Co @ V @ np.diag(w ** -0.5) @ V.T
+        d.append(energy_of(Co) - E)
+    assert d[0] > 0 and d[1] > 0
+    assert d[1] / d[0] == pytest.approx(4.0, rel=0.05)
