@@ -23,6 +23,9 @@ Parity status per function (what pins it is listed in tests/test_oracle_*.py):
                 quadrature; far-field limit q S/|P-C|)
   vgrad         pinned (central differences of E_V in atom and charge
                 positions; atom and charge derivatives sum to zero)
+  ao_values,    pinned (sum_g w_g m n over a product Gauss-Legendre box grid
+  grid_density, against the overlap S; gradients against central
+  xc_matrix     differences; sum_g w_g grad(m n) over the box grid vanishes)
   spherical     convention pinned by S_sph = I and rotation invariance
   omega > 0     pinned (erf(omega r)/r blocks against the Gaussian-transform
                 quadrature cut at t = omega and an mpmath closed form of the
@@ -396,6 +399,72 @@ def rhf(mol, nuclei, nocc: int, conv: float = 1e-10, max_iter: int = 200, basis_
         c = np.linalg.lstsq(Bm, rhs, rcond=None)[0][:n]
         P = density(sum(ci * Fi for ci, Fi in zip(c, Fs)))
     raise RuntimeError("rhf: no convergence in %d iterations" % max_iter)
+
+
+def ao_values(mol, pts, deriv: bool = False, basis_obj=None):
+    """Basis functions at points (spherical basis, nbf x npts) and, with
+    deriv, their gradients (3 x nbf x npts): every contracted Cartesian
+    Gaussian sum_k c_k x_A^i y_A^j z_A^l e^{-a_k |r - A|^2} (eqs.
+    contracted_basis, primtive_basis) written out at each point, then the
+    spherical transform; d/dx x_A^i e^{-a r_A^2} = i x_A^{i-1} e - 2a x_A^{i+1} e."""
+    B = basis_obj or OBasis(mol)
+    pts = np.asarray(pts, float).reshape(-1, 3)
+    n = pts.shape[0]
+    chi = np.zeros((B.nbf, n))
+    dchi = np.zeros((3, B.nbf, n)) if deriv else None
+    for s in range(B.nshell):
+        l, at, o, npr = int(B.l[s]), int(B.atom[s]), int(B.off[s]), int(B.nprim[s])
+        d = pts - B.xyz[3 * at:3 * at + 3]
+        r2 = np.sum(d * d, axis=1)
+        g = np.zeros(n)
+        gp = np.zeros(n)  # d g / d(r^2) times 2: the radial factor of the derivative
+        for k in range(npr):
+            ek = np.exp(-B.exps[o + k] * r2) * B.coefs[o + k]
+            g += ek
+            gp += -2.0 * B.exps[o + k] * ek
+        comps = _basis.cart_list(l)
+        cart = np.array([d[:, 0] ** i * d[:, 1] ** j * d[:, 2] ** m * g for (i, j, m) in comps])
+        T = _basis.SPH[l]
+        a0 = int(B.ao_off[s])
+        chi[a0:a0 + 2 * l + 1] = T @ cart
+        if deriv:
+            for ax in range(3):
+                rows = []
+                for c in comps:
+                    pw = list(c)
+                    mono = np.prod([d[:, q] ** pw[q] for q in range(3)], axis=0)
+                    lower = 0.0
+                    if pw[ax] > 0:
+                        pm = list(pw)
+                        pm[ax] -= 1
+                        lower = pw[ax] * np.prod([d[:, q] ** pm[q] for q in range(3)], axis=0) * g
+                    rows.append(lower + mono * d[:, ax] * gp)
+                dchi[ax, a0:a0 + 2 * l + 1] = T @ np.array(rows)
+    return (chi, dchi) if deriv else chi
+
+
+def grid_density(mol, P, pts, basis_obj=None):
+    """rho(r_g) = sum P_mn m(r_g) n(r_g) and its gradient (eqs. xc_density_0,
+    xc_density_1) at every point: (npts,), (npts, 3)."""
+    chi, dchi = ao_values(mol, pts, deriv=True, basis_obj=basis_obj)
+    Ps = _sym(P)
+    Pc = Ps @ chi
+    rho = np.sum(chi * Pc, axis=0)
+    grad = 2.0 * np.einsum("kmg,mg->gk", dchi, Pc)
+    return rho, grad
+
+
+def xc_matrix(mol, pts, v0, v1=None, basis_obj=None):
+    """V_mn = sum_g v0_g m(r_g) n(r_g) + sum_g v1_g . grad(m n)(r_g)
+    (eqs. xc_grid_sum_0, xc_grid_sum_1, the weights folded into v0, v1)."""
+    chi, dchi = ao_values(mol, pts, deriv=True, basis_obj=basis_obj)
+    V = (chi * np.asarray(v0, float)[None, :]) @ chi.T
+    if v1 is not None:
+        v1 = np.asarray(v1, float).reshape(-1, 3)
+        for k in range(3):
+            W = (dchi[k] * v1[None, :, k]) @ chi.T
+            V += W + W.T
+    return V
 
 
 def energy(mol, J, K, P=None) -> float:

@@ -828,3 +828,67 @@ def test_rhf_energy_is_stationary_minimum():
         d.append(energy_of(Co) - E)
     assert d[0] > 0 and d[1] > 0
     assert d[1] / d[0] == pytest.approx(4.0, rel=0.05)
+
+
+# ---------------------------------------------------------------------------
+# Basis functions on grid points, density and the exchange-correlation matrix
+# sums (eqs. xc_density_0, xc_density_1, xc_grid_sum_0, xc_grid_sum_1)
+# ---------------------------------------------------------------------------
+def _box_grid(mol, n=90, pad=7.0):
+    lo, hi = mol.xyz.min(0) - pad, mol.xyz.max(0) + pad
+    axes, wts = [], []
+    for k in range(3):
+        x, w = np.polynomial.legendre.leggauss(n)
+        axes.append(0.5 * (hi[k] - lo[k]) * x + 0.5 * (hi[k] + lo[k]))
+        wts.append(0.5 * (hi[k] - lo[k]) * w)
+    X, Y, Z = np.meshgrid(*axes, indexing="ij")
+    W = wts[0][:, None, None] * wts[1][None, :, None] * wts[2][None, None, :]
+    return np.stack([X.ravel(), Y.ravel(), Z.ravel()], 1), W.ravel()
+
+
+def _soft_mol():
+    xyz = [[0.0, 0.0, 0.0], [1.3, 0.4, -0.5]]
+    specs = [(0, 0, 2), (0, 1, 1), (1, 2, 1), (1, 3, 1), (0, 1, 2), (1, 0, 1)]
+    return synth.custom(xyz, specs, seed=41, tau=0.0, exp_range=(0.25, 1.2))
+
+
+def test_ao_values_integrate_to_the_overlap():
+    mol = _soft_mol()
+    pts, w = _box_grid(mol)
+    chi = oracle.ao_values(mol, pts)
+    S = (chi * w[None, :]) @ chi.T
+    Sr, _ = oracle.st(mol)
+    assert np.abs(S - Sr).max() <= 1e-9
+
+
+def test_ao_and_density_gradients_vs_central_differences():
+    mol = _soft_mol()
+    rng = np.random.default_rng(4)
+    pts = rng.uniform(-1.5, 2.5, (7, 3))
+    chi, dchi = oracle.ao_values(mol, pts, deriv=True)
+    P = 0.5 * (mol.P + mol.P.T)
+    rho, grad = oracle.grid_density(mol, P, pts)
+    assert np.allclose(rho, np.einsum("mg,mn,ng->g", chi, P, chi), rtol=1e-13, atol=0)
+    h = 1e-5
+    for k in range(3):
+        e = np.zeros(3)
+        e[k] = h
+        fd = (oracle.ao_values(mol, pts + e) - oracle.ao_values(mol, pts - e)) / (2 * h)
+        assert np.abs(fd - dchi[k]).max() <= 1e-7 * np.abs(dchi).max()
+        rp, _ = oracle.grid_density(mol, P, pts + e)
+        rm, _ = oracle.grid_density(mol, P, pts - e)
+        assert np.abs((rp - rm) / (2 * h) - grad[:, k]).max() <= 1e-7 * np.abs(grad).max()
+
+
+def test_xc_matrix_weight_sum_and_total_derivative():
+    """With v0 = w the matrix is sum_g w m n (the overlap on the box grid);
+    with v1 = w e (a constant direction) it is the integral of a total
+    derivative, zero up to the quadrature error."""
+    mol = _soft_mol()
+    pts, w = _box_grid(mol, n=70)
+    Sr, _ = oracle.st(mol)
+    V0 = oracle.xc_matrix(mol, pts, w)
+    assert np.abs(V0 - Sr).max() <= 1e-7
+    v1 = w[:, None] * np.array([0.3, -0.7, 0.5])[None, :]
+    V1 = oracle.xc_matrix(mol, pts, np.zeros_like(w), v1)
+    assert np.abs(V1).max() <= 1e-7 and np.abs(V1 - V1.T).max() <= 1e-14
