@@ -252,6 +252,75 @@ def bench_potential(a, n_mm: int = 20000):
             "top_kernel": top["name"], "top_kernel_tflops": ach}
 
 
+def bench_scf(a):
+    """Closed-shell SCF of mol40 with nuclei (Z in {1, 6, 7, 8}): every
+    iteration a full double-precision J/K build, against the dynamic scheme
+    (mixed precision with a threshold following the orbital gradient,
+    incremental builds under the density-weighted screen, double precision at
+    the end)."""
+    import torch
+    from paper_2406_14920_amd import JK, scf, synth
+    mol = synth.mol40()
+    nuc = synth.nuclei(mol, seed=3, even=True)
+    nocc = int(round(-nuc[:, 3].sum())) // 2
+    jk = JK.from_molecule(mol)
+    be = scf.GPUBackend(jk, nuc)
+    out = {"workload": "mol40 closed-shell SCF, %d electrons, 840 spherical bf, level shift 0.3" % (2 * nocc)}
+    for mode in ("fp64", "dynamic"):
+        t0 = time.perf_counter()
+        r = scf.rhf(be, nuc, nocc, mode=mode, max_iter=50, conv=1e-8, grad_conv=1e-5, level_shift=0.3)
+        wall = time.perf_counter() - t0
+        out[mode] = {"energy": r.energy, "converged": r.converged, "iterations": len(r.iterations),
+                     "build_ms_total": r.build_ms, "wall_s": wall,
+                     "mixed_iterations": sum(1 for it in r.iterations if it.precision != "fp64"),
+                     "incremental_iterations": sum(1 for it in r.iterations if it.incremental),
+                     "errors": [float("%.2e" % it.error) for it in r.iterations],
+                     "build_ms": [round(it.build_ms, 1) for it in r.iterations]}
+        print("scf %s: E %.10f converged %s, %d iterations, J/K builds %.0f ms, wall %.1f s" % (
+            mode, r.energy, r.converged, len(r.iterations), r.build_ms, wall), file=sys.stderr, flush=True)
+    jk.close()
+    out["energy_diff"] = out["dynamic"]["energy"] - out["fp64"]["energy"]
+    out["build_speedup"] = out["fp64"]["build_ms_total"] / max(out["dynamic"]["build_ms_total"], 1e-9)
+    return out
+
+
+def bench_grid(a):
+    """Exchange-correlation grid step on mol40 with its atom-centred grid:
+    density and gradient at every point, a functional's potential (Slater
+    exchange for v0 and a gradient term of the same scaling for v1; the paper
+    evaluates the functional outside the GPU kernels and names none), then
+    the matrix sums."""
+    import torch
+    from paper_2406_14920_amd import JK, synth
+    mol = synth.mol40()
+    pts, w = synth.molecular_grid(mol)
+    jk = JK.from_molecule(mol)
+    P = torch.tensor(0.5 * (mol.P + mol.P.T), dtype=torch.float64, device="cuda")
+    pt = torch.tensor(pts, dtype=torch.float64, device="cuda")
+    wt = torch.tensor(w, dtype=torch.float64, device="cuda")
+
+    def potential(rho, grad):
+        r = torch.clamp(rho, min=1e-14)
+        v0 = -(3.0 / np.pi) ** (1.0 / 3.0) * r ** (1.0 / 3.0) * wt
+        v1 = (-0.0042 * grad / r[:, None] ** (4.0 / 3.0)) * wt[:, None]
+        return v0.contiguous(), v1.contiguous()
+
+    rho, grad = jk.grid_density(P, pt)
+    v0, v1 = potential(rho, grad)
+    jk.grid_matrix(pt, v0, v1)
+    steps = max(1, min(a.steps, 5))
+    ms_rho = _time(lambda: jk.grid_density(P, pt), steps)
+    ms_mat = _time(lambda: jk.grid_matrix(pt, v0, v1), steps)
+    n_el = float(torch.sum(wt * rho))
+    jk.close()
+    print("grid mol40: %d points, density+gradient %.2f ms, matrix %.2f ms, electrons %.6f (tr PS check)" % (
+        pts.shape[0], ms_rho, ms_mat, n_el), file=sys.stderr, flush=True)
+    return {"workload": "mol40 (840 spherical bf), atom-centred grid 40 radial x 11 x 22 angular per atom, "
+                        "Becke partition", "points": int(pts.shape[0]), "dtype": "f64",
+            "density_gradient_ms": ms_rho, "matrix_ms": ms_mat,
+            "points_per_s_density": pts.shape[0] / (ms_rho * 1e-3), "integrated_electrons": n_el}
+
+
 def bench_batch(a):
     """64 molecules of 5-30 atoms built as one batch (molecules on concurrent
     streams), against the same molecules built one after another."""
@@ -382,6 +451,8 @@ def main():
     if not a.no_extras:
         out["grad"] = bench_grad(a)
         out["potential"] = bench_potential(a)
+        out["scf"] = bench_scf(a)
+        out["grid"] = bench_grid(a)
         out["batch64"] = bench_batch(a)
     if not a.no_cpu:
         cb = cpu_baseline(mol)

@@ -15,6 +15,13 @@
  *   screening               eq. cauchy_schwarz_bound (pair and quartet level)
  *   energy and gradient     SI eqs. si_E_J_K, si_dE_J, si_dE_K, si_dE_J_step1,
  *                           si_dE_K_step1 (density held fixed)
+ *   long-range operator     eqs. eri_longrange_definition, eri_longrange_formula
+ *   one-electron integrals  eqs. overlap_formula, kinetic_formula, v1e_formula
+ *                           (point charges: nuclei or QM/MM embedding) and SI
+ *                           eqs. si_v1e_derivative_A/B/C
+ *   density-weighted screen eq. kernel_upperbound (incremental builds)
+ *   grid density, XC sums   eqs. xc_density_0, xc_density_1, xc_grid_sum_0,
+ *                           xc_grid_sum_1, pair_derivative
  *
  * Conventions
  *   - Units: bohr, hartree.
@@ -160,6 +167,50 @@ int eri_set_omega(eri_ctx *ctx, double omega);
  * row-major FP64.  J or K may be NULL to skip it.  Asynchronous. */
 int build_jk(eri_ctx *ctx, const double *P, double *J, double *K);
 
+/* Density-weighted screen of later build_jk / build_jk_static calls (the
+ * paper's density-weighted Schwarz bound, eq. kernel_upperbound and section
+ * "Performance"): K skips a contracted quartet whose Q_ab Q_cd times the
+ * largest |P| over the four Cartesian density blocks its digestion reads is
+ * below tau; J skips a (bra wavefront, ket pair) tile whose largest Q_ab
+ * times Q_cd max|P_cd| is below tau.  Each skipped term is bounded by its
+ * bound, so incremental builds on a density change dP (J(P + dP) =
+ * J(P) + J(dP)) skip most of the work as dP shrinks.  tau = 0 (default) turns
+ * it off.  Gradients and potentials ignore it. */
+int eri_set_density_screen(eri_ctx *ctx, double tau);
+
+/* Overlap S_mn (eqs. overlap_definition, overlap_formula) and kinetic energy
+ * T_mn (eqs. kinetic_definition, kinetic_formula) of the context's basis:
+ * one workgroup per contracted shell pair, a thread per Cartesian component,
+ * the pair's E coefficients with the ket index raised by two in LDS.  Pairs
+ * that fail the Schwarz rule against every pair are absent, as in build_jk.
+ * S, T: device nbf*nbf row-major, overwritten; either may be NULL, not both.
+ * Asynchronous. */
+int eri_one_electron(eri_ctx *ctx, double *S, double *T);
+
+/* Electron density and its gradient at grid points (eqs. xc_density_0,
+ * xc_density_1, with the pair derivative of eq. pair_derivative):
+ * rho(r) = sum_mn P_mn m(r) n(r).  One lane per point; the contracted pairs
+ * are walked per 64-point block, skipping every pair whose bounding sphere
+ * (all points where one of its primitives has p |r - P|^2 <= 100) misses the
+ * block's sphere, and inside a pair every such primitive.  Points should be
+ * ordered so that consecutive points lie close together (atom by atom, shell
+ * by shell), which keeps the block spheres small.  Deterministic.
+ * P: device nbf*nbf, symmetric.  pts: device [npts][3] (bohr).  rho: device
+ * [npts], overwritten; grad: device [npts][3] or NULL, overwritten.
+ * npts = 0 is a no-op (pts, rho may then be NULL).  Asynchronous. */
+int eri_grid_density(eri_ctx *ctx, const double *P, const double *pts, int64_t npts, double *rho, double *grad);
+
+/* Grid sums of the exchange-correlation matrix (eqs. xc_grid_sum_0,
+ * xc_grid_sum_1): V_mn = sum_g v0_g m(r_g) n(r_g) + sum_g v1_g . grad(m n)(r_g),
+ * the quadrature weights folded into v0 and v1 by the caller (v0 = w de/drho,
+ * v1 = w de/d(grad rho) of the functional, evaluated outside the library as
+ * in the paper).  One wavefront per contracted pair over the point blocks
+ * whose spheres meet the pair's (same cut-off as eri_grid_density), sums
+ * reduced in a fixed order: deterministic.  pts: device [npts][3]; v0: device
+ * [npts]; v1: device [npts][3] or NULL (no gradient term); V: device nbf*nbf,
+ * overwritten (V = 0 for npts = 0).  Asynchronous. */
+int eri_grid_matrix(eri_ctx *ctx, const double *pts, int64_t npts, const double *v0, const double *v1, double *V);
+
 /* build_jk for callers that cannot allocate device memory (code under HIP
  * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
  * same double-precision J and K as build_jk, with the per-build work buffers
@@ -237,7 +288,11 @@ int eri_stats(const eri_ctx *ctx, eri_stats_t *out);
 int eri_destroy(eri_ctx *ctx);
 
 /* Autotuner: times the candidate launch shapes (J-engine ket chunk per class
- * pair; workgroup cap of each range-walking exchange launch; under ERI_MIXED
+ * pair; workgroup cap of each range-walking exchange launch; the ket
+ * grouping of each lane-per-quartet exchange launch -- by the first ket
+ * shell c or by the second shell d, the latter being the ordering the paper
+ * calls inverted (section "Performance", closing remarks on the K
+ * algorithm), chosen per angular class; under ERI_MIXED
  * also whether each launch takes the FP32 share at all) on this
  * context's own workload -- device density P, current precision -- best of
  * reps runs each, and keeps the fastest for later builds.  Replaces the
@@ -257,7 +312,10 @@ int eri_tuning(const eri_ctx *ctx, int32_t *kchunk100, int32_t *kcap, int32_t ca
  * kchunk/jsplit[10*X + Y]: J-engine ket chunk and FP32-share flag of bra
  * class X, ket class Y (classes ss, ps, pp, ds, dp, dd, fs, fp, fd, ff);
  * launch i < n_kwork of the exchange: class pair kwork_class[i] = 10*X + Y
- * (X >= Y), workgroup cap kcap[i] (0 = default) and FP32-share flag ksplit[i]. */
+ * (X >= Y), workgroup cap kcap[i] (0 = default), FP32-share flag ksplit[i]
+ * and ket grouping kinv[i] (0: by the first ket shell, whose exchange targets
+ * K_ac, K_bc the items of a row share; 1: by the second, sharing K_ad, K_bd;
+ * only lane-per-quartet launches take 1, others keep 0). */
 typedef struct {
     int32_t kchunk[100];
     int32_t jsplit[100];
@@ -265,6 +323,7 @@ typedef struct {
     int32_t kwork_class[64];
     int32_t kcap[64];
     int32_t ksplit[64];
+    int32_t kinv[64];
 } eri_tuning_t;
 
 /* Read the current choice (eri_get_tuning) or apply a saved one

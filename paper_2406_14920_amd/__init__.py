@@ -77,6 +77,50 @@ class JK:
             abi.jk_grad(self.ctx, P, g, E)
         return (g, E) if energy else g
 
+    def one_electron(self):
+        """(S, T): overlap and kinetic energy matrices (eri_one_electron)."""
+        import torch
+        S = torch.empty((self.nbf, self.nbf), dtype=torch.float64, device="cuda")
+        T = torch.empty_like(S)
+        with torch.cuda.stream(self.stream):
+            abi.eri_one_electron(self.ctx, S, T)
+        return S, T
+
+    def _points(self, pts):
+        import torch
+        if pts.dtype != torch.float64 or not pts.is_cuda or not pts.is_contiguous():
+            raise ValueError("points must be a contiguous float64 CUDA tensor")
+        if pts.dim() != 2 or pts.shape[1] != 3:
+            raise ValueError("points must be n x 3")
+        return int(pts.shape[0])
+
+    def grid_density(self, P, pts, gradient: bool = True):
+        """(rho (n,), grad rho (n, 3) or None) at the points (eri_grid_density)."""
+        import torch
+        n = self._points(pts)
+        rho = torch.empty(n, dtype=torch.float64, device=pts.device)
+        grad = torch.empty((n, 3), dtype=torch.float64, device=pts.device) if gradient else None
+        with torch.cuda.stream(self.stream):
+            abi.eri_grid_density(self.ctx, P, pts, n, rho, grad)
+        return rho, grad
+
+    def grid_matrix(self, pts, v0, v1=None):
+        """V_mn = sum_g v0_g m n + v1_g . grad(m n) (eri_grid_matrix)."""
+        import torch
+        n = self._points(pts)
+        for name, v, shp in (("v0", v0, (n,)), ("v1", v1, (n, 3))):
+            if v is not None and (v.dtype != torch.float64 or not v.is_cuda or not v.is_contiguous()
+                                  or tuple(v.shape) != shp):
+                raise ValueError("%s must be a contiguous float64 CUDA tensor of shape %s" % (name, shp))
+        V = torch.empty((self.nbf, self.nbf), dtype=torch.float64, device=pts.device)
+        with torch.cuda.stream(self.stream):
+            abi.eri_grid_matrix(self.ctx, pts, n, v0, v1, V)
+        return V
+
+    def set_density_screen(self, tau: float):
+        """Density-weighted screen of later builds (0: off)."""
+        abi.eri_set_density_screen(self.ctx, tau)
+
     def _charges(self, charges):
         import torch
         if charges.dtype != torch.float64 or not charges.is_cuda or not charges.is_contiguous():

@@ -54,7 +54,8 @@ class eri_stats_t(ctypes.Structure):
 
 class eri_tuning_t(ctypes.Structure):
     _fields_ = [("kchunk", ctypes.c_int32 * 100), ("jsplit", ctypes.c_int32 * 100), ("n_kwork", ctypes.c_int32),
-                ("kwork_class", ctypes.c_int32 * 64), ("kcap", ctypes.c_int32 * 64), ("ksplit", ctypes.c_int32 * 64)]
+                ("kwork_class", ctypes.c_int32 * 64), ("kcap", ctypes.c_int32 * 64), ("ksplit", ctypes.c_int32 * 64),
+                ("kinv", ctypes.c_int32 * 64)]
 
 
 class eri_kernel_time(ctypes.Structure):
@@ -66,7 +67,8 @@ EXPORTS = ["eri_default_opts", "eri_setup", "eri_nbf", "eri_set_geometry", "eri_
            "build_jk", "jk_grad", "eri_energy", "eri_set_profiling", "eri_profile_read", "eri_stats", "eri_destroy",
            "eri_last_error", "eri_batch_create", "eri_batch_build_jk", "eri_batch_destroy",
            "eri_autotune", "eri_tuning", "build_jk_static", "eri_set_omega", "eri_get_tuning",
-           "eri_set_tuning", "eri_potential", "eri_potential_grad"]
+           "eri_set_tuning", "eri_potential", "eri_potential_grad", "eri_set_density_screen",
+           "eri_one_electron", "eri_grid_density", "eri_grid_matrix"]
 
 _lib = None
 
@@ -96,6 +98,10 @@ def load(path: str = LIB_PATH):
     L.jk_grad.argtypes = [vp, vp, vp, vp]
     L.eri_energy.argtypes = [vp, vp, vp, vp, vp]
     L.eri_potential.argtypes = [vp, vp, ctypes.c_int32, vp]
+    L.eri_set_density_screen.argtypes = [vp, ctypes.c_double]
+    L.eri_one_electron.argtypes = [vp, vp, vp]
+    L.eri_grid_density.argtypes = [vp, vp, vp, ctypes.c_int64, vp, vp]
+    L.eri_grid_matrix.argtypes = [vp, vp, ctypes.c_int64, vp, vp, vp]
     L.eri_potential_grad.argtypes = [vp, vp, ctypes.c_int32, vp, vp, vp]
     L.eri_stats.argtypes = [vp, ctypes.POINTER(eri_stats_t)]
     L.eri_set_profiling.argtypes = [vp, ctypes.c_int32]
@@ -202,8 +208,8 @@ def eri_get_tuning(ctx: int) -> dict:
     t = eri_tuning_t()
     _check(load().eri_get_tuning(ctypes.c_void_p(ctx), ctypes.byref(t)))
     j = {"%s|%s" % (_CLASSES[k // 10], _CLASSES[k % 10]): [int(t.kchunk[k]), int(t.jsplit[k])] for k in range(100)}
-    kx = {"%s|%s" % (_CLASSES[t.kwork_class[i] // 10], _CLASSES[t.kwork_class[i] % 10]): [int(t.kcap[i]), int(t.ksplit[i])]
-          for i in range(t.n_kwork)}
+    kx = {"%s|%s" % (_CLASSES[t.kwork_class[i] // 10], _CLASSES[t.kwork_class[i] % 10]):
+          [int(t.kcap[i]), int(t.ksplit[i]), int(t.kinv[i])] for i in range(t.n_kwork)}
     return {"jengine": j, "exchange": kx}
 
 
@@ -217,7 +223,10 @@ def eri_set_tuning(ctx: int, tuning: dict) -> None:
     for i in range(cur.n_kwork):
         name = "%s|%s" % (_CLASSES[cur.kwork_class[i] // 10], _CLASSES[cur.kwork_class[i] % 10])
         if name in tuning.get("exchange", {}):
-            cur.kcap[i], cur.ksplit[i] = (int(v) for v in tuning["exchange"][name])
+            vals = [int(v) for v in tuning["exchange"][name]]
+            cur.kcap[i], cur.ksplit[i] = vals[0], vals[1]
+            if len(vals) > 2:
+                cur.kinv[i] = vals[2]
     _check(load().eri_set_tuning(ctypes.c_void_p(ctx), ctypes.byref(cur)))
 
 
@@ -233,6 +242,23 @@ def build_jk_static(ctx: int, P, J, K) -> None:
 
 def jk_grad(ctx: int, P, grad, E=None) -> None:
     _check(load().jk_grad(ctypes.c_void_p(ctx), _ptr(P), _ptr(grad), _ptr(E)))
+
+
+def eri_set_density_screen(ctx: int, tau: float) -> None:
+    _check(load().eri_set_density_screen(ctypes.c_void_p(ctx), float(tau)))
+
+
+def eri_one_electron(ctx: int, S, T) -> None:
+    """Overlap S and kinetic energy T (device nbf x nbf; either may be None)."""
+    _check(load().eri_one_electron(ctypes.c_void_p(ctx), _ptr(S), _ptr(T)))
+
+
+def eri_grid_density(ctx: int, P, pts, npts: int, rho, grad=None) -> None:
+    _check(load().eri_grid_density(ctypes.c_void_p(ctx), _ptr(P), _ptr(pts), int(npts), _ptr(rho), _ptr(grad)))
+
+
+def eri_grid_matrix(ctx: int, pts, npts: int, v0, v1, V) -> None:
+    _check(load().eri_grid_matrix(ctypes.c_void_p(ctx), _ptr(pts), int(npts), _ptr(v0), _ptr(v1), _ptr(V)))
 
 
 def eri_potential(ctx: int, charges, ncharge: int, V) -> None:

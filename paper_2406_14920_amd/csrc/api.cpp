@@ -29,6 +29,7 @@
 
 #include "../../include/mdjk.h"
 #include "class_lists.hpp"
+#include "grid.hpp"
 #include "launch.hpp"
 #include "md_common.hpp"
 
@@ -220,11 +221,18 @@ struct eri_ctx {
         int64_t roff;   // into row buffer
         int nrows;
     };
-    // exchange view: per class the pairs grouped by contraction length
-    // (largest first), Q descending inside a group (same class bases as cp)
-    std::vector<CPair> kcp;
-    std::vector<double> kQ;
+    // exchange views: per class the pairs grouped by contraction length
+    // (largest first) and by one shell -- view 0 the first shell c, view 1
+    // the second shell d -- Q descending inside a group (same class bases as
+    // cp); vorig maps a view index to the Q-order index inside the class,
+    // kgroups lists each class's groups (first, count) in view order
+    std::vector<CPair> kcp[2];
+    std::vector<double> kQ[2];
+    std::vector<int> vorig[2];
+    std::vector<std::vector<std::array<int, 2>>> kgroups[2];
     std::vector<KWork> kwork;
+    std::vector<int> kinv;  // per exchange launch: the view its kets come from
+    double tau_dens = 0.0;  // density-weighted screen of build_jk (0: off)
     size_t dt_off[kPairClasses] = {}, jh_off[kPairClasses] = {};
 
     // device
@@ -234,8 +242,8 @@ struct eri_ctx {
     DevBuf<int32_t> d_owner;
     DevBuf<int64_t> d_prefix;
     DevBuf<int2> d_rows;
-    DevBuf<CPair> d_kcp;
-    DevBuf<double> d_kQ;
+    DevBuf<CPair> d_kcp[2];
+    DevBuf<double> d_kQ[2];
     DevBuf<int4> d_chunks;
     DevBuf<double> d_eprod;
     size_t eprod_off[kPairClasses] = {};
@@ -266,6 +274,11 @@ struct eri_ctx {
     bool grad_ready = false, jh1_ready = false;
     size_t jh1_off[kPairClasses] = {};
     DevBuf<double> d_vpart;  // charge-gradient partials of eri_potential_grad
+    // grid integrals: atom positions, bounding sphere of every contracted pair
+    // (J order), bounding spheres of the current call's point blocks
+    bool grid_ready = false;
+    DevBuf<double> d_xyz;
+    DevBuf<double4> d_psph, d_bsph;
     DevBuf<double> d_Jh1, d_pg, d_kpart, d_Jtmp, d_Ktmp, d_jhpart;
     int gchunk[kPairClasses][kPairClasses] = {};  // J-engine ket chunk of the gradient launches
     std::vector<int> kg_blocks;   // per exchange launch
@@ -388,6 +401,152 @@ void make_prim_pair(PrimPair &r, double a, double b, double ca, double cb, const
     r.pad = 0.0;
 }
 
+// The exchange kernels see each class through a view grouped by
+// contraction length and by one shell of the pair, Q-sorted inside a group.
+// A row of a work list pairs one bra with the kets of one group; the kets it
+// visits (Q_i Q_j >= tau and, in a class with itself, j not after i in the Q
+// order) form a prefix of the group.  Rows run bra by bra, so neighbouring
+// work items share the bra and, inside a row, the grouping shell: with view 0
+// (grouped by the first shell c of a ket (cd|)) their exchange contributions
+// K_ac and K_bc go to the same elements, with view 1 (grouped by d) K_ad and
+// K_bd do, and the kernels sum those across the lanes before one atomic
+// addition per element (view 1 is what the paper calls the inverted
+// ordering).  The length (the number of primitive pairs rounded up to a power
+// of two, largest first) keeps the primitive loops of neighbouring lanes
+// equally long.
+void build_views(eri_ctx *c)
+{
+    auto np_group = [](int np) {
+        int g = 0;
+        while ((1 << g) < np) ++g;
+        return g;
+    };
+    for (int v = 0; v < 2; ++v) {
+        auto sh = [v](const CPair &x) { return v == 0 ? x.sh1 : x.sh2; };
+        auto key_less = [&](const CPair &x, const CPair &y) {
+            const int gx = np_group(x.np), gy = np_group(y.np);
+            return gx != gy ? gx > gy : sh(x) < sh(y);
+        };
+        auto key_same = [&](const CPair &x, const CPair &y) {
+            return np_group(x.np) == np_group(y.np) && sh(x) == sh(y);
+        };
+        c->kcp[v].assign(c->cp.size(), CPair{});
+        c->kQ[v].assign(c->cp.size(), 0.0);
+        c->vorig[v].assign(c->cp.size(), 0);
+        c->kgroups[v].assign(kPairClasses, {});
+        for (int X = 0; X < kPairClasses; ++X) {
+            const int b = c->cp_base[X], nX = c->ncp[X];
+            std::vector<int> idx(nX);
+            for (int k = 0; k < nX; ++k) idx[k] = k;
+            std::stable_sort(idx.begin(), idx.end(),
+                             [&](int x, int y) { return key_less(c->cp[b + x], c->cp[b + y]); });
+            for (int r = 0; r < nX; ++r) {
+                c->kcp[v][b + r] = c->cp[b + idx[r]];
+                c->kQ[v][b + r] = c->Q[b + idx[r]];
+                c->vorig[v][b + r] = idx[r];
+                if (r == 0 || !key_same(c->cp[b + idx[r]], c->cp[b + idx[r - 1]])) c->kgroups[v][X].push_back({r, 0});
+                c->kgroups[v][X].back()[1]++;
+            }
+        }
+        c->d_kcp[v].upload(c->kcp[v]);
+        c->d_kQ[v].upload(c->kQ[v]);
+    }
+}
+
+bool is_k_small(int la, int lb, int lc, int ld)
+{
+#define MD_IS(A_, B_, C_, D_) if (la == A_ && lb == B_ && lc == C_ && ld == D_) return true;
+    MD_K_SMALL_LIST(MD_IS)
+#undef MD_IS
+    return false;
+}
+
+// Whether an exchange launch may take its kets from view 1 (the kernels with
+// a lane per work item; the LDS kernels keep per-row tiles of K_ac and K_bc).
+bool kinv_ok(int X, int Y)
+{
+    const int la = kPairL[X][0], lb = kPairL[X][1], lc = kPairL[Y][0], ld = kPairL[Y][1];
+    return uses_k_pair(la, lb, lc, ld) || is_k_small(la, lb, lc, ld);
+}
+
+// Exchange work lists of every launch (X >= Y) from the view each one uses.
+void build_kwork(eri_ctx *c)
+{
+    const double tau = c->opts.schwarz_thresh;
+    std::vector<int64_t> prefix;
+    std::vector<int2> rows;
+    std::vector<int4> chunks;
+    c->kwork.clear();
+    c->n_quartets = 0;
+    c->eris_sph = c->eris_cart = 0.0;
+    for (int X = 0; X < kPairClasses; ++X)
+        for (int Y = 0; Y <= X; ++Y) {
+            const int v = c->kinv[c->kwork.size()] && kinv_ok(X, Y) ? 1 : 0;
+            c->kinv[c->kwork.size()] = v;
+            const std::vector<double> &kQ = c->kQ[v];
+            const std::vector<int> &vorig = c->vorig[v];
+            eri_ctx::KWork w{X, Y, (int64_t)prefix.size(), 0, -1, 0, (int64_t)rows.size(), 0};
+            const int bX = c->cp_base[X], bY = c->cp_base[Y];
+            const bool kp = uses_k_pair(kPairL[X][0], kPairL[X][1], kPairL[Y][0], kPairL[Y][1]);
+            if (kp) w.choff = (int64_t)chunks.size();
+            int64_t acc = 0;
+            prefix.push_back(0);
+            for (int i = 0; i < c->ncp[X]; ++i) {
+                const double Qi = kQ[bX + i];
+                const int oi = vorig[bX + i];
+                const int r_first = (int)((int64_t)rows.size() - w.roff);
+                const int64_t w_first = acc;
+                for (const auto &gy : c->kgroups[v][Y]) {
+                    const int j0 = gy[0], j1 = gy[0] + gy[1];
+                    int lo = j0, hi = j1;  // Q descending inside the group
+                    while (lo < hi) {
+                        const int mid = (lo + hi) / 2;
+                        if (Qi * kQ[bY + mid] >= tau) lo = mid + 1; else hi = mid;
+                    }
+                    int cnt = lo - j0;
+                    if (X == Y) {  // Q-order index ascending inside the group
+                        int l2 = j0, h2 = j0 + cnt;
+                        while (l2 < h2) {
+                            const int mid = (l2 + h2) / 2;
+                            if (vorig[bY + mid] <= oi) l2 = mid + 1; else h2 = mid;
+                        }
+                        cnt = l2 - j0;
+                    }
+                    if (cnt <= 0) continue;
+                    rows.push_back(make_int2(i, j0));
+                    acc += cnt;
+                    prefix.push_back(acc);
+                }
+                // bra-shared chunks: 64 consecutive work items of this bra
+                // (first row, offset in it, items, rows spanned)
+                if (kp) {
+                    const int r_end = (int)((int64_t)rows.size() - w.roff);
+                    int r = r_first;
+                    for (int64_t s0 = w_first; s0 < acc; s0 += 64) {
+                        const int64_t s1 = std::min<int64_t>(s0 + 64, acc);
+                        while (prefix[w.off + r + 1] <= s0) ++r;
+                        int r1 = r;
+                        while (r1 + 1 < r_end && prefix[w.off + r1 + 1] < s1) ++r1;
+                        chunks.push_back(make_int4(r, (int)(s0 - prefix[w.off + r]), (int)(s1 - s0), r1 - r + 1));
+                    }
+                }
+            }
+            w.nwork = acc;
+            w.nrows = (int)((int64_t)rows.size() - w.roff);
+            if (kp) w.nchunks = (int)((int64_t)chunks.size() - w.choff);
+            c->kwork.push_back(w);
+            c->n_quartets += acc;
+            const int la = kPairL[X][0], lb = kPairL[X][1], lc = kPairL[Y][0], ld = kPairL[Y][1];
+            c->eris_sph += (double)acc * nsph(la) * nsph(lb) * nsph(lc) * nsph(ld);
+            c->eris_cart += (double)acc * ncart(la) * ncart(lb) * ncart(lc) * ncart(ld);
+        }
+    c->d_prefix.upload(prefix);
+    c->d_rows.upload(rows);
+    c->d_chunks.upload(chunks);
+    c->mix_counts_ok = false;
+    ++c->gen;
+}
+
 // Build pairs, run the Schwarz kernels, sort, build the work lists.
 void build_pairs(eri_ctx *c)
 {
@@ -491,114 +650,12 @@ void build_pairs(eri_ctx *c)
     c->mix_counts_ok = false;
     c->grad_ready = false;
     c->jh1_ready = false;
+    c->grid_ready = false;
 
-    // 4. exchange work lists.  The exchange kernels see each class through a
-    // view grouped by contraction length and by the pair's first shell (the
-    // shell c of a ket (cd|)), Q-sorted inside a group.  A row pairs one bra with the kets of one
-    // group; the kets it visits (Q_i Q_j >= tau and, in a class with itself,
-    // j not after i in the Q order) form a prefix of the group.  Rows run bra
-    // by bra, so neighbouring work items share the bra and, inside a row, the
-    // shell c: their exchange contributions K_ac and K_bc go to the same
-    // elements and are summed before one atomic addition per element.
-    // Groups are keyed by (contraction length, first shell): the length (the
-    // number of primitive pairs rounded up to a power of two, largest first)
-    // keeps the primitive loops of neighbouring lanes equally long, the shell
-    // gives the shared exchange elements.
-    auto np_group = [](int np) {
-        int g = 0;
-        while ((1 << g) < np) ++g;
-        return g;
-    };
-    auto key_less = [&](const CPair &x, const CPair &y) {
-        const int gx = np_group(x.np), gy = np_group(y.np);
-        return gx != gy ? gx > gy : x.sh1 < y.sh1;
-    };
-    auto key_same = [&](const CPair &x, const CPair &y) { return np_group(x.np) == np_group(y.np) && x.sh1 == y.sh1; };
-    c->kcp.assign(c->cp.size(), CPair{});
-    c->kQ.assign(c->cp.size(), 0.0);
-    std::vector<int> vorig(c->cp.size());          // view index -> Q-order index (inside the class)
-    std::vector<std::vector<std::array<int, 2>>> groups(kPairClasses);  // (first, count) in view order
-    for (int X = 0; X < kPairClasses; ++X) {
-        const int b = c->cp_base[X], nX = c->ncp[X];
-        std::vector<int> idx(nX);
-        for (int k = 0; k < nX; ++k) idx[k] = k;
-        std::stable_sort(idx.begin(), idx.end(), [&](int x, int y) { return key_less(c->cp[b + x], c->cp[b + y]); });
-        for (int r = 0; r < nX; ++r) {
-            c->kcp[b + r] = c->cp[b + idx[r]];
-            c->kQ[b + r] = c->Q[b + idx[r]];
-            vorig[b + r] = idx[r];
-            if (r == 0 || !key_same(c->cp[b + idx[r]], c->cp[b + idx[r - 1]])) groups[X].push_back({r, 0});
-            groups[X].back()[1]++;
-        }
-    }
-    std::vector<int64_t> prefix;
-    std::vector<int2> rows;
-    std::vector<int4> chunks;
-    c->kwork.clear();
-    c->n_quartets = 0;
-    c->eris_sph = c->eris_cart = 0.0;
-    for (int X = 0; X < kPairClasses; ++X)
-        for (int Y = 0; Y <= X; ++Y) {
-            eri_ctx::KWork w{X, Y, (int64_t)prefix.size(), 0, -1, 0, (int64_t)rows.size(), 0};
-            const int bX = c->cp_base[X], bY = c->cp_base[Y];
-            const bool kp = uses_k_pair(kPairL[X][0], kPairL[X][1], kPairL[Y][0], kPairL[Y][1]);
-            if (kp) w.choff = (int64_t)chunks.size();
-            int64_t acc = 0;
-            prefix.push_back(0);
-            for (int i = 0; i < c->ncp[X]; ++i) {
-                const double Qi = c->kQ[bX + i];
-                const int oi = vorig[bX + i];
-                const int r_first = (int)((int64_t)rows.size() - w.roff);
-                const int64_t w_first = acc;
-                for (const auto &gy : groups[Y]) {
-                    const int j0 = gy[0], j1 = gy[0] + gy[1];
-                    int lo = j0, hi = j1;  // Q descending inside the group
-                    while (lo < hi) {
-                        const int mid = (lo + hi) / 2;
-                        if (Qi * c->kQ[bY + mid] >= tau) lo = mid + 1; else hi = mid;
-                    }
-                    int cnt = lo - j0;
-                    if (X == Y) {  // Q-order index ascending inside the group
-                        int l2 = j0, h2 = j0 + cnt;
-                        while (l2 < h2) {
-                            const int mid = (l2 + h2) / 2;
-                            if (vorig[bY + mid] <= oi) l2 = mid + 1; else h2 = mid;
-                        }
-                        cnt = l2 - j0;
-                    }
-                    if (cnt <= 0) continue;
-                    rows.push_back(make_int2(i, j0));
-                    acc += cnt;
-                    prefix.push_back(acc);
-                }
-                // bra-shared chunks: 64 consecutive work items of this bra
-                // (first row, offset in it, items, rows spanned)
-                if (kp) {
-                    const int r_end = (int)((int64_t)rows.size() - w.roff);
-                    int r = r_first;
-                    for (int64_t s0 = w_first; s0 < acc; s0 += 64) {
-                        const int64_t s1 = std::min<int64_t>(s0 + 64, acc);
-                        while (prefix[w.off + r + 1] <= s0) ++r;
-                        int r1 = r;
-                        while (r1 + 1 < r_end && prefix[w.off + r1 + 1] < s1) ++r1;
-                        chunks.push_back(make_int4(r, (int)(s0 - prefix[w.off + r]), (int)(s1 - s0), r1 - r + 1));
-                    }
-                }
-            }
-            w.nwork = acc;
-            w.nrows = (int)((int64_t)rows.size() - w.roff);
-            if (kp) w.nchunks = (int)((int64_t)chunks.size() - w.choff);
-            c->kwork.push_back(w);
-            c->n_quartets += acc;
-            const int la = kPairL[X][0], lb = kPairL[X][1], lc = kPairL[Y][0], ld = kPairL[Y][1];
-            c->eris_sph += (double)acc * nsph(la) * nsph(lb) * nsph(lc) * nsph(ld);
-            c->eris_cart += (double)acc * ncart(la) * ncart(lb) * ncart(lc) * ncart(ld);
-        }
-    c->d_prefix.upload(prefix);
-    c->d_rows.upload(rows);
-    c->d_kcp.upload(c->kcp);
-    c->d_kQ.upload(c->kQ);
-    c->d_chunks.upload(chunks);
+    // 4. exchange views and work lists (build_views, build_kwork)
+    build_views(c);
+    c->kinv.assign((size_t)kPairClasses * (kPairClasses + 1) / 2, 0);
+    build_kwork(c);
     for (int X = 0; X < kPairClasses; ++X)
         for (int Y = 0; Y < kPairClasses; ++Y) {
             c->kchunk[X][Y] = jeng_default_chunk(kPairL[X][0] + kPairL[X][1], kPairL[Y][0] + kPairL[Y][1],
@@ -644,8 +701,8 @@ void build_pairs(eri_ctx *c)
     for (size_t wi = 0; wi < c->kwork.size(); ++wi) {
         const auto &w = c->kwork[wi];
         KArgs a{};
-        a.bra = c->d_kcp.p + c->cp_base[w.X];
-        a.ket = c->d_kcp.p + c->cp_base[w.Y];
+        a.bra = c->d_kcp[c->kinv[wi]].p + c->cp_base[w.X];
+        a.ket = c->d_kcp[c->kinv[wi]].p + c->cp_base[w.Y];
         a.rows = c->d_rows.p + w.roff;
         a.prefix = c->d_prefix.p + w.off;
         a.nwork = w.nwork;
@@ -865,7 +922,10 @@ JArgs j_args(const eri_ctx *c, int X, int Y, bool mixed)
     if (mixed) {
         a.Dtf = c->d_Dtf.p + c->dt_off[Y];
         a.tau_mix = c->opts.mixed_thresh;
+    }
+    if (mixed || c->tau_dens > 0.0) {
         a.QDket = c->d_QD.p + c->cp_base[Y];
+        a.tau_dens = c->tau_dens;
     }
     a.om2 = c->opts.omega * c->opts.omega;
     return a;
@@ -908,8 +968,10 @@ void run_j(eri_ctx *c, bool mixed, hipStream_t st)
 KArgs k_args(const eri_ctx *c, const eri_ctx::KWork &w, bool mixed)
 {
     KArgs a{};
-    a.bra = c->d_kcp.p + c->cp_base[w.X];
-    a.ket = c->d_kcp.p + c->cp_base[w.Y];
+    const int v = c->kinv[&w - c->kwork.data()];
+    a.inv = v;
+    a.bra = c->d_kcp[v].p + c->cp_base[w.X];
+    a.ket = c->d_kcp[v].p + c->cp_base[w.Y];
     a.rows = c->d_rows.p + w.roff;
     a.prefix = c->d_prefix.p + w.off;
     a.nwork = w.nwork;
@@ -932,10 +994,13 @@ KArgs k_args(const eri_ctx *c, const eri_ctx::KWork &w, bool mixed)
         a.eprodf_bra = c->d_eprodf.p + c->eprod_off[w.X];
         a.eprodf_ket = c->d_eprodf.p + c->eprod_off[w.Y];
         a.tau_mix = c->opts.mixed_thresh;
-        a.Qbra = c->d_kQ.p + c->cp_base[w.X];
-        a.Qket = c->d_kQ.p + c->cp_base[w.Y];
+    }
+    if (mixed || c->tau_dens > 0.0) {  // density-weighted bounds of the quartets
+        a.Qbra = c->d_kQ[v].p + c->cp_base[w.X];
+        a.Qket = c->d_kQ[v].p + c->cp_base[w.Y];
         a.Pm = c->d_Pm.p;
         a.nsh = c->nshell;
+        a.tau_dens = c->tau_dens;
     }
     return a;
 }
@@ -968,16 +1033,11 @@ KPArgs kp_args(const KArgs &a, const int4 *chunks)
     p.Pm = a.Pm;
     p.nsh = a.nsh;
     p.om2 = a.om2;
+    p.tau_dens = a.tau_dens;
+    p.inv = a.inv;
     return p;
 }
 
-bool is_k_small(int la, int lb, int lc, int ld)
-{
-#define MD_IS(A_, B_, C_, D_) if (la == A_ && lb == B_ && lc == C_ && ld == D_) return true;
-    MD_K_SMALL_LIST(MD_IS)
-#undef MD_IS
-    return false;
-}
 
 // Range-walking wave classes on stA, bra-shared and small classes on stB.
 void run_k(eri_ctx *c, bool mixed, hipStream_t stA, hipStream_t stB)
@@ -1418,6 +1478,37 @@ int eri_set_omega(eri_ctx *ctx, double omega)
     return ERI_OK;
 }
 
+int eri_set_density_screen(eri_ctx *ctx, double tau)
+{
+    if (!ctx_ok(ctx)) return set_err(ERI_ESTATE, "invalid context");
+    if (!(tau >= 0.0) || !std::isfinite(tau)) return set_err(ERI_EINVAL, "density screen %g not non-negative", tau);
+    ctx->tau_dens = tau;
+    ++ctx->gen;
+    return ERI_OK;
+}
+
+int eri_one_electron(eri_ctx *ctx, double *S, double *T)
+{
+    if (!ctx_ok(ctx)) return set_err(ERI_ESTATE, "invalid context");
+    if (!S && !T) return set_err(ERI_EINVAL, "S and T are both NULL");
+    try {
+        hipStream_t st = ctx->st;
+        const int nc = ctx->nbf_cart;
+        launch_fill_zero(ctx->wk.Jacc, (int64_t)nc * nc, st);
+        launch_fill_zero(ctx->wk.Kacc, (int64_t)nc * nc, st);
+        for (int X = 0; X < kPairClasses; ++X)
+            launch_st_pair(kPairL[X][0], kPairL[X][1], ctx->d_cp.p + ctx->cp_base[X], ctx->ncp[X], ctx->d_pp.p,
+                           ctx->wk.Jacc, ctx->wk.Kacc, nc, st);
+        const ShellMap m = shell_map(ctx);
+        if (S) launch_acc_to_out(ctx->wk.Jacc, nc, S, ctx->nbf, m, ctx->opts.spherical, st);
+        if (T) launch_acc_to_out(ctx->wk.Kacc, nc, T, ctx->nbf, m, ctx->opts.spherical, st);
+        HIPCHK(hipGetLastError());
+    } catch (const HipError &e) {
+        return e.code;
+    }
+    return ERI_OK;
+}
+
 int build_jk(eri_ctx *ctx, const double *P, double *J, double *K)
 {
     if (!ctx_ok(ctx)) return set_err(ERI_ESTATE, "invalid context");
@@ -1428,8 +1519,8 @@ int build_jk(eri_ctx *ctx, const double *P, double *J, double *K)
         const int nc = ctx->nbf_cart;
         const bool mixed = ctx->opts.precision != ERI_FP64;
         launch_p_to_cart(P, ctx->nbf, ctx->wk.Pc, nc, m, ctx->opts.spherical, st);
-        if (mixed) {
-            ensure_mixed(ctx);
+        if (mixed) ensure_mixed(ctx);
+        if (mixed || ctx->tau_dens > 0.0) {
             launch_density_bounds(ctx->wk.Pc, nc, ctx->d_l.p, ctx->d_coff.p, ctx->nshell, ctx->d_Pm.p, ctx->d_cp.p,
                                   ctx->d_Q.p, (int)ctx->cp.size(), ctx->d_QD.p, st);
         }
@@ -1532,6 +1623,46 @@ int jk_grad(eri_ctx *ctx, const double *P, double *grad, double *E)
     return ERI_OK;
 }
 
+// Bounding sphere of every contracted pair: all points where one of its
+// primitives has p |r - P|^2 <= kGridCut.
+void ensure_grid(eri_ctx *c)
+{
+    if (c->grid_ready) return;
+    std::vector<double4> sph(std::max<size_t>(c->cp.size(), 1));
+    for (size_t k = 0; k < c->cp.size(); ++k) {
+        const CPair &A = c->cp[k];
+        double cx = 0.0, cy = 0.0, cz = 0.0;
+        for (int i = 0; i < A.np; ++i) {
+            const PrimPair &q = c->pp[A.poff + i];
+            cx += q.P[0];
+            cy += q.P[1];
+            cz += q.P[2];
+        }
+        cx /= A.np;
+        cy /= A.np;
+        cz /= A.np;
+        double r = 0.0;
+        for (int i = 0; i < A.np; ++i) {
+            const PrimPair &q = c->pp[A.poff + i];
+            const double d = std::sqrt((q.P[0] - cx) * (q.P[0] - cx) + (q.P[1] - cy) * (q.P[1] - cy) +
+                                       (q.P[2] - cz) * (q.P[2] - cz));
+            r = std::max(r, d + std::sqrt(kGridCut / q.p));
+        }
+        sph[k] = make_double4(cx, cy, cz, r * (1.0 + 1e-12) + 1e-12);
+    }
+    c->d_psph.upload(sph);
+    c->d_xyz.upload(c->xyz);
+    c->grid_ready = true;
+}
+
+void grid_prepare(eri_ctx *c, const double *pts, int64_t npts)
+{
+    ensure_grid(c);
+    const size_t nblk = (size_t)((npts + 63) / 64);
+    if (c->d_bsph.n < nblk) c->d_bsph.alloc(nblk);
+    launch_grid_blocks(pts, npts, c->d_bsph.p, c->st);
+}
+
 int eri_potential(eri_ctx *ctx, const double *charges, int32_t ncharge, double *V)
 {
     if (!ctx_ok(ctx)) return set_err(ERI_ESTATE, "invalid context");
@@ -1560,6 +1691,64 @@ int eri_potential_grad(eri_ctx *ctx, const double *charges, int32_t ncharge, con
     try {
         launch_p_to_cart(P, ctx->nbf, ctx->wk.Pc, ctx->nbf_cart, shell_map(ctx), ctx->opts.spherical, ctx->st);
         run_potential_grad(ctx, charges, ncharge, gatom, gchg);
+        HIPCHK(hipGetLastError());
+    } catch (const HipError &e) {
+        return e.code;
+    } catch (const std::bad_alloc &) {
+        return set_err(ERI_ENOMEM, "host allocation failed");
+    }
+    return ERI_OK;
+}
+
+int eri_grid_density(eri_ctx *ctx, const double *P, const double *pts, int64_t npts, double *rho, double *grad)
+{
+    if (!ctx_ok(ctx)) return set_err(ERI_ESTATE, "invalid context");
+    if (!P) return set_err(ERI_EINVAL, "P is NULL");
+    if (npts < 0) return set_err(ERI_EINVAL, "npts %lld negative", (long long)npts);
+    if (npts == 0) return ERI_OK;
+    if (!pts || !rho) return set_err(ERI_EINVAL, "pts or rho is NULL");
+    try {
+        hipStream_t st = ctx->st;
+        const int nc = ctx->nbf_cart;
+        launch_p_to_cart(P, ctx->nbf, ctx->wk.Pc, nc, shell_map(ctx), ctx->opts.spherical, st);
+        grid_prepare(ctx, pts, npts);
+        launch_fill_zero(rho, npts, st);
+        if (grad) launch_fill_zero(grad, 3 * npts, st);
+        for (int X = 0; X < kPairClasses; ++X)
+            timed(ctx, st, cls_name("grid_rho", kPairL[X][0], kPairL[X][1], 0, 0), -1, 0, 0, [&] {
+                launch_grid_rho(kPairL[X][0], kPairL[X][1], ctx->d_cp.p + ctx->cp_base[X], ctx->ncp[X], ctx->d_pp.p,
+                                ctx->d_psph.p + ctx->cp_base[X], ctx->d_xyz.p, ctx->wk.Pc, nc, pts, npts,
+                                ctx->d_bsph.p, rho, grad, st);
+            });
+        HIPCHK(hipGetLastError());
+    } catch (const HipError &e) {
+        return e.code;
+    } catch (const std::bad_alloc &) {
+        return set_err(ERI_ENOMEM, "host allocation failed");
+    }
+    return ERI_OK;
+}
+
+int eri_grid_matrix(eri_ctx *ctx, const double *pts, int64_t npts, const double *v0, const double *v1, double *V)
+{
+    if (!ctx_ok(ctx)) return set_err(ERI_ESTATE, "invalid context");
+    if (!V) return set_err(ERI_EINVAL, "V is NULL");
+    if (npts < 0) return set_err(ERI_EINVAL, "npts %lld negative", (long long)npts);
+    if (npts > 0 && (!pts || !v0)) return set_err(ERI_EINVAL, "pts or v0 is NULL");
+    try {
+        hipStream_t st = ctx->st;
+        const int nc = ctx->nbf_cart;
+        launch_fill_zero(ctx->wk.Jacc, (int64_t)nc * nc, st);
+        if (npts > 0) {
+            grid_prepare(ctx, pts, npts);
+            for (int X = 0; X < kPairClasses; ++X)
+                timed(ctx, st, cls_name("grid_vmat", kPairL[X][0], kPairL[X][1], 0, 0), -1, 0, 0, [&] {
+                    launch_grid_vmat(kPairL[X][0], kPairL[X][1], ctx->d_cp.p + ctx->cp_base[X], ctx->ncp[X],
+                                     ctx->d_pp.p, ctx->d_psph.p + ctx->cp_base[X], ctx->d_xyz.p, pts, npts,
+                                     ctx->d_bsph.p, v0, v1, ctx->wk.Jacc, nc, st);
+                });
+        }
+        launch_acc_to_out(ctx->wk.Jacc, nc, V, ctx->nbf, shell_map(ctx), ctx->opts.spherical, st);
         HIPCHK(hipGetLastError());
     } catch (const HipError &e) {
         return e.code;
@@ -1754,6 +1943,52 @@ int eri_autotune(eri_ctx *ctx, const double *P, int32_t reps)
                 ctx->kchunk[X][Y] = pick;
                 if (tune_split) ctx->jsplit[X][Y] = pick_split;
             }
+        // one exchange launch as build_jk runs it (its current split choice)
+        auto launch_k = [&](const eri_ctx::KWork &w, KArgs a, bool split) {
+            const int la = kPairL[w.X][0], lb = kPairL[w.X][1], lc = kPairL[w.Y][0], ld = kPairL[w.Y][1];
+            for (int part = split ? 1 : 0; part <= (split ? 2 : 0); ++part) {
+                a.mode = part;
+                const bool f32 = part == 2;
+                if (w.choff >= 0) {
+                    const KPArgs kp = kp_args(a, ctx->d_chunks.p + w.choff);
+                    (void)(launch_k_pair_0(la, lb, lc, ld, kp, w.nchunks, f32, st) ||
+                           launch_k_pair_1(la, lb, lc, ld, kp, w.nchunks, f32, st) ||
+                           launch_k_pair_2(la, lb, lc, ld, kp, w.nchunks, f32, st) ||
+                           launch_k_pair_3(la, lb, lc, ld, kp, w.nchunks, f32, st) ||
+                           launch_k_pair_4(la, lb, lc, ld, kp, w.nchunks, f32, st) ||
+                           launch_k_pair_5(la, lb, lc, ld, kp, w.nchunks, f32, st) ||
+                           launch_k_pair_6(la, lb, lc, ld, kp, w.nchunks, f32, st) ||
+                           launch_k_pair_7(la, lb, lc, ld, kp, w.nchunks, f32, st));
+                } else {
+                    (void)(launch_k_small(la, lb, lc, ld, a, f32, st) ||
+                           launch_k_wave_0(la, lb, lc, ld, a, f32, st) || launch_k_wave_1(la, lb, lc, ld, a, f32, st) ||
+                           launch_k_wave_2(la, lb, lc, ld, a, f32, st) || launch_k_wave_3(la, lb, lc, ld, a, f32, st) ||
+                           launch_k_wave_4(la, lb, lc, ld, a, f32, st) || launch_k_wave_5(la, lb, lc, ld, a, f32, st));
+                }
+            }
+        };
+        // exchange variant of every lane-per-item launch: kets grouped by
+        // their first shell (view 0) or by their second (view 1, the paper's
+        // inverted ordering), whichever is faster on this workload
+        {
+            const size_t nw = ctx->kwork.size();
+            std::vector<float> tv[2];
+            HIPCHK(hipStreamSynchronize(st));
+            for (int v = 0; v < 2; ++v) {
+                for (size_t wi = 0; wi < nw; ++wi) ctx->kinv[wi] = v;
+                build_kwork(ctx);
+                tv[v].assign(nw, 1e30f);
+                for (size_t wi = 0; wi < nw; ++wi) {
+                    const auto &w = ctx->kwork[wi];
+                    if (w.nwork == 0 || !kinv_ok(w.X, w.Y)) continue;
+                    const KArgs a = k_args(ctx, w, mixed);
+                    const bool split = mixed && (prec == ERI_MIXED_ALL || ctx->ksplit[wi]);
+                    tv[v][wi] = time_it([&] { launch_k(w, a, split); });
+                }
+            }
+            for (size_t wi = 0; wi < nw; ++wi) ctx->kinv[wi] = tv[1][wi] < tv[0][wi] ? 1 : 0;
+            build_kwork(ctx);
+        }
         static const int kCaps[] = {1024, 4096, 16384, 32768, 131072};
         for (size_t wi = 0; wi < ctx->kwork.size(); ++wi) {
             const auto &w = ctx->kwork[wi];
@@ -1771,28 +2006,7 @@ int eri_autotune(eri_ctx *ctx, const double *P, int32_t reps)
                     if (!wave && cap != kCaps[0]) break;  // only the split choice for these
                     KArgs a = k_args(ctx, w, mixed);
                     a.grid_cap = wave ? cap : 0;
-                    const float ms = time_it([&] {
-                        for (int part = split ? 1 : 0; part <= (split ? 2 : 0); ++part) {
-                            a.mode = part;
-                            const bool f32 = part == 2;
-                            if (w.choff >= 0) {
-                                const KPArgs kp = kp_args(a, ctx->d_chunks.p + w.choff);
-                                (void)(launch_k_pair_0(la, lb, lc, ld, kp, w.nchunks, f32, st) ||
-                                       launch_k_pair_1(la, lb, lc, ld, kp, w.nchunks, f32, st) ||
-                                       launch_k_pair_2(la, lb, lc, ld, kp, w.nchunks, f32, st) ||
-                                       launch_k_pair_3(la, lb, lc, ld, kp, w.nchunks, f32, st) ||
-                                       launch_k_pair_4(la, lb, lc, ld, kp, w.nchunks, f32, st) ||
-                                       launch_k_pair_5(la, lb, lc, ld, kp, w.nchunks, f32, st) ||
-                                       launch_k_pair_6(la, lb, lc, ld, kp, w.nchunks, f32, st) ||
-                                       launch_k_pair_7(la, lb, lc, ld, kp, w.nchunks, f32, st));
-                            } else {
-                                (void)(launch_k_small(la, lb, lc, ld, a, f32, st) ||
-                                       launch_k_wave_0(la, lb, lc, ld, a, f32, st) || launch_k_wave_1(la, lb, lc, ld, a, f32, st) ||
-                                       launch_k_wave_2(la, lb, lc, ld, a, f32, st) || launch_k_wave_3(la, lb, lc, ld, a, f32, st) ||
-                                       launch_k_wave_4(la, lb, lc, ld, a, f32, st) || launch_k_wave_5(la, lb, lc, ld, a, f32, st));
-                            }
-                        }
-                    });
+                    const float ms = time_it([&] { launch_k(w, a, split); });
                     if (ms < best) {
                         best = ms;
                         pick = wave ? cap : 0;
@@ -1846,6 +2060,7 @@ int eri_get_tuning(const eri_ctx *ctx, eri_tuning_t *out)
         out->kwork_class[i] = ctx->kwork[i].X * kPairClasses + ctx->kwork[i].Y;
         out->kcap[i] = ctx->kcap[i];
         out->ksplit[i] = ctx->ksplit[i] ? 1 : 0;
+        out->kinv[i] = ctx->kinv[i];
     }
     return ERI_OK;
 }
@@ -1858,20 +2073,36 @@ int eri_set_tuning(eri_ctx *ctx, const eri_tuning_t *in)
         if (in->kchunk[k] < 8 || in->kchunk[k] > 1024)
             return set_err(ERI_EINVAL, "kchunk[%d] = %d outside 8..1024", k, in->kchunk[k]);
     if (in->n_kwork < 0 || in->n_kwork > 64) return set_err(ERI_EINVAL, "n_kwork %d outside 0..64", in->n_kwork);
-    for (int i = 0; i < in->n_kwork; ++i)
+    for (int i = 0; i < in->n_kwork; ++i) {
         if (in->kcap[i] < 0) return set_err(ERI_EINVAL, "kcap[%d] = %d negative", i, in->kcap[i]);
+        if (in->kinv[i] != 0 && in->kinv[i] != 1) return set_err(ERI_EINVAL, "kinv[%d] = %d not 0 or 1", i, in->kinv[i]);
+    }
     for (int X = 0; X < kPairClasses; ++X)
         for (int Y = 0; Y < kPairClasses; ++Y) {
             ctx->kchunk[X][Y] = in->kchunk[X * kPairClasses + Y];
             ctx->jsplit[X][Y] = in->jsplit[X * kPairClasses + Y] != 0;
         }
+    bool views_changed = false;
     for (size_t wi = 0; wi < ctx->kwork.size(); ++wi) {
         const int cls = ctx->kwork[wi].X * kPairClasses + ctx->kwork[wi].Y;
         for (int i = 0; i < in->n_kwork; ++i)
             if (in->kwork_class[i] == cls) {
                 ctx->kcap[wi] = in->kcap[i];
                 ctx->ksplit[wi] = in->ksplit[i] != 0;
+                const int v = in->kinv[i] && kinv_ok(ctx->kwork[wi].X, ctx->kwork[wi].Y) ? 1 : 0;
+                views_changed |= v != ctx->kinv[wi];
+                ctx->kinv[wi] = v;
             }
+    }
+    if (views_changed) {
+        try {
+            HIPCHK(hipStreamSynchronize(ctx->st));  // the old lists may still be read
+            build_kwork(ctx);
+        } catch (const HipError &e) {
+            return e.code;
+        } catch (const std::bad_alloc &) {
+            return set_err(ERI_ENOMEM, "host allocation failed");
+        }
     }
     ctx->mix_counts_ok = false;
     ++ctx->gen;

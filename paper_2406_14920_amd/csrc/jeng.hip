@@ -121,7 +121,7 @@ __global__ __launch_bounds__(64) void jeng_small(JArgs a)
     const int nv = valid ? count_kets(a.Qket, a.nket, Qi, a.tau) : 0;
     const int nvmax = __builtin_amdgcn_readfirstlane(wave_max(nv));
     const double qmax = uniform_d(wave_max(qi));
-    const double Qw = a.mode ? uniform_d(wave_max(Qi)) : 0.0;
+    const double Qw = (a.mode || a.tau_dens > 0.0) ? uniform_d(wave_max(Qi)) : 0.0;
     const int j0 = blockIdx.y * a.kchunk;
     const int j1 = min(min(a.nket, j0 + a.kchunk), nvmax);
     const T *__restrict__ Dt = pick<T>(a.Dt, a.Dtf);
@@ -134,6 +134,7 @@ __global__ __launch_bounds__(64) void jeng_small(JArgs a)
     for (int i = 0; i < (F32 ? NX : 1); ++i) Jh[i] = 0.0;
     for (int j = j0; j < j1; ++j) {
         if (a.mode && (Qw * a.QDket[j] >= a.tau_mix) != (a.mode == 1)) continue;
+        if (a.tau_dens > 0.0 && Qw * a.QDket[j] < a.tau_dens) continue;  // density-weighted screen
         const CPair B = a.ket[j];
         for (int kp = 0; kp < B.np; ++kp) {
             const PrimPair pk = a.pp[B.poff + kp];
@@ -236,6 +237,7 @@ __global__ __launch_bounds__(64) void jeng_wave(JArgs a)
     double acc[2] = {0.0, 0.0};
     for (int j = j0; j < j1; ++j) {
         if (a.mode && (Qi * a.QDket[j] >= a.tau_mix) != (a.mode == 1)) continue;
+        if (a.tau_dens > 0.0 && Qi * a.QDket[j] < a.tau_dens) continue;  // density-weighted screen
         const CPair B = a.ket[j];
         PairLite pk = pair_lite(a.pp + B.poff);
         for (int kp = 0; kp < B.np; ++kp) {

@@ -108,6 +108,7 @@ __global__ __launch_bounds__(64) void jeng_reg(JArgs a)
     for (int i = 0; i < (F32 ? NX : 1); ++i) Jh[i] = 0.0;
     for (int j = j0; j < j1; ++j) {
         if (a.mode && (Qw * a.QDket[j] >= a.tau_mix) != (a.mode == 1)) continue;
+        if (a.tau_dens > 0.0 && Qw * a.QDket[j] < a.tau_dens) continue;  // density-weighted screen
         const CPair B = a.ket[j];
         for (int kp = 0; kp < B.np; ++kp) {
             const PrimPair pk = a.pp[B.poff + kp];

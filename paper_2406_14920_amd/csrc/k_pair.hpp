@@ -10,8 +10,9 @@
 // budget are produced in compile-time passes over (ab, cd) chunks, R being
 // rebuilt per pass.  Each finished chunk is digested by the lane into the
 // four exchange blocks of the 8-fold symmetry and added to the accumulator;
-// the K_ac and K_bc terms of lanes in one work-list row (same ket shell c)
-// are summed across those lanes first.
+// the K_ac and K_bc terms of lanes in one work-list row (same ket shell c;
+// K_ad and K_bd when the kets are grouped by d) are summed across those lanes
+// first.  A density-weighted screen may skip lanes.
 // T is the arithmetic type of the primitive integrals (the digestion is in
 // double precision); in the mixed mode a workgroup is one precision tile.
 #pragma once
@@ -79,12 +80,25 @@ __global__ __launch_bounds__(64) void k_pair(KPArgs a)
     const CPair A = a.bra[ib];
     const CPair B = a.ket[jk];
     const SegLinks links = seg_links(valid ? r : -1 - lane);
-    if (!mix_take(a.mode, a.mode != 0 && valid &&
-                              a.Qbra[ib] * a.Qket[jk] * k_dens_bound(a.Pm, a.nsh, A, B) >= a.tau_mix))
-        return;
+    const double bound =
+        (a.mode != 0 || a.tau_dens > 0.0) ? a.Qbra[ib] * a.Qket[jk] * k_dens_bound(a.Pm, a.nsh, A, B) : 0.0;
+    const bool live = valid && (a.tau_dens <= 0.0 || bound >= a.tau_dens);  // else the lane adds zeros
+    if (!mix_take(a.mode, a.mode != 0 && live && bound >= a.tau_mix)) return;
     const T *__restrict__ eprod_bra = pick<T>(a.eprod_bra, a.eprodf_bra);
     const T *__restrict__ eprod_ket = pick<T>(a.eprod_ket, a.eprodf_ket);
-    const int nkp = valid ? B.np : 0;
+    const int nkp = live ? B.np : 0;
+    // K_ac, K_bc (kets grouped by c) or K_ad, K_bd (grouped by d) are shared
+    // by the lanes of a row: summed across them, added by the row's first
+    // lane; the other two blocks are added by every live lane
+    auto put = [&](bool shared, double v, double *dst) {
+        if (shared) {
+            const double u = seg_sum(v, links);
+            if (valid && links.head) unsafeAtomicAdd(dst, u);
+        } else if (live) {
+            unsafeAtomicAdd(dst, v);
+        }
+    };
+    const bool by_c = a.inv == 0;
     const int n = a.ld;
     double s = 1.0;
     if (A.sh1 == A.sh2) s *= 0.5;
@@ -241,10 +255,7 @@ __global__ __launch_bounds__(64) void k_pair(KPArgs a)
                             }
                         });
                     });
-                    if (any) {  // K_ac: shared by the lanes of a row
-                        const double v = seg_sum(s * t, links);
-                        if (valid && links.head) unsafeAtomicAdd(&a.Kacc[(int64_t)(A.c1 + i0 + i) * n + B.c1 + c0 + cc], v);
-                    }
+                    if (any) put(by_c, s * t, &a.Kacc[(int64_t)(A.c1 + i0 + i) * n + B.c1 + c0 + cc]);
                 });
                 static_for<0, nd>([&](auto dc) {  // K_ad[i][d] = sum_{j,c} V D_bc[j][c]
                     double t = 0.0;
@@ -258,7 +269,7 @@ __global__ __launch_bounds__(64) void k_pair(KPArgs a)
                             }
                         });
                     });
-                    if (any && valid) unsafeAtomicAdd(&a.Kacc[(int64_t)(A.c1 + i0 + i) * n + B.c2 + d0 + dc], s * t);
+                    if (any) put(!by_c, s * t, &a.Kacc[(int64_t)(A.c1 + i0 + i) * n + B.c2 + d0 + dc]);
                 });
             });
             static_for<0, nj>([&](auto jc) {
@@ -275,10 +286,7 @@ __global__ __launch_bounds__(64) void k_pair(KPArgs a)
                             }
                         });
                     });
-                    if (any) {  // K_bc: shared by the lanes of a row
-                        const double v = seg_sum(s * t, links);
-                        if (valid && links.head) unsafeAtomicAdd(&a.Kacc[(int64_t)(A.c2 + j0 + j) * n + B.c1 + c0 + cc], v);
-                    }
+                    if (any) put(by_c, s * t, &a.Kacc[(int64_t)(A.c2 + j0 + j) * n + B.c1 + c0 + cc]);
                 });
                 static_for<0, nd>([&](auto dc) {  // K_bd[j][d] = sum_{i,c} V D_ac[i][c]
                     double t = 0.0;
@@ -292,7 +300,7 @@ __global__ __launch_bounds__(64) void k_pair(KPArgs a)
                             }
                         });
                     });
-                    if (any && valid) unsafeAtomicAdd(&a.Kacc[(int64_t)(A.c2 + j0 + j) * n + B.c2 + d0 + dc], s * t);
+                    if (any) put(!by_c, s * t, &a.Kacc[(int64_t)(A.c2 + j0 + j) * n + B.c2 + d0 + dc]);
                 });
             });
         }

@@ -4,9 +4,10 @@
 // accumulates the contracted Cartesian block and digests it into the four
 // exchange blocks that the 8-fold permutational symmetry (eq. 8_fold_symmetry)
 // maps it to:  K_ac += V D_bd, K_ad += V D_bc, K_bc += V D_ad, K_bd += V D_ac.
-// Neighbouring lanes of one work-list row share the bra and the ket shell c,
-// so their K_ac and K_bc terms are summed across the lanes before one atomic
-// addition per element.
+// Neighbouring lanes of one work-list row share the bra and one ket shell
+// (c, or d in the grouping that the paper calls inverted), so their K_ac and
+// K_bc (or K_ad and K_bd) terms are summed across the lanes before one
+// atomic addition per element.  A density-weighted screen may skip lanes.
 // The caller forms K = Kacc + Kacc^T afterwards.  T is the arithmetic type of
 // the primitive integrals; the digestion and the accumulator stay in double
 // precision.  In the mixed mode a wavefront (64 consecutive quartets) is one
@@ -36,10 +37,13 @@ __global__ __launch_bounds__(128) void k_small(KArgs a)
     const int jk = rw.y + (int)(wc - a.prefix[r]);
     const CPair A = a.bra[ib];
     const CPair B = a.ket[jk];
-    if (!mix_take(a.mode, a.mode != 0 && valid &&
-                              a.Qbra[ib] * a.Qket[jk] * k_dens_bound(a.Pm, a.nsh, A, B) >= a.tau_mix))
-        return;  // uniform over the wavefront
-    const int nbp = valid ? A.np : 0;
+    // a live lane evaluates its quartet; the others (past the work list, or
+    // below the density-weighted screen) contribute zeros
+    const double bound =
+        (a.mode != 0 || a.tau_dens > 0.0) ? a.Qbra[ib] * a.Qket[jk] * k_dens_bound(a.Pm, a.nsh, A, B) : 0.0;
+    const bool live = valid && (a.tau_dens <= 0.0 || bound >= a.tau_dens);
+    if (!mix_take(a.mode, a.mode != 0 && live && bound >= a.tau_mix)) return;  // uniform over the wavefront
+    const int nbp = live ? A.np : 0;
 
     T V[NBLK];
 #pragma unroll
@@ -206,26 +210,53 @@ __global__ __launch_bounds__(128) void k_small(KArgs a)
             });
         });
     }
+    // The two blocks whose targets the lanes of a row share (K_ac, K_bc when
+    // the kets are grouped by c; K_ad, K_bd when grouped by d) are summed
+    // across those lanes and added by the row's first lane (a skipped lane
+    // adds zeros, so it may lead its row); the other two by every live lane.
     const SegLinks links = seg_links(valid ? r : -1 - (int)(threadIdx.x & 63));
-    static_for<0, NA * NC>([&](auto oc) {
-        constexpr int o = decltype(oc)::value;
-        const double v = seg_sum(kac[o], links);
-        if (valid && links.head) unsafeAtomicAdd(&Kc[(int64_t)(A.c1 + o / NC) * n + B.c1 + o % NC], v);
-    });
-    static_for<0, NB * NC>([&](auto oc) {
-        constexpr int o = decltype(oc)::value;
-        const double v = seg_sum(s * kbc[o], links);
-        if (valid && links.head) unsafeAtomicAdd(&Kc[(int64_t)(A.c2 + o / NC) * n + B.c1 + o % NC], v);
-    });
-    if (valid) {
+    if (!a.inv) {
+        static_for<0, NA * NC>([&](auto oc) {
+            constexpr int o = decltype(oc)::value;
+            const double v = seg_sum(kac[o], links);
+            if (valid && links.head) unsafeAtomicAdd(&Kc[(int64_t)(A.c1 + o / NC) * n + B.c1 + o % NC], v);
+        });
+        static_for<0, NB * NC>([&](auto oc) {
+            constexpr int o = decltype(oc)::value;
+            const double v = seg_sum(s * kbc[o], links);
+            if (valid && links.head) unsafeAtomicAdd(&Kc[(int64_t)(A.c2 + o / NC) * n + B.c1 + o % NC], v);
+        });
+        if (live) {
+            static_for<0, NA * ND>([&](auto oc) {
+                constexpr int o = decltype(oc)::value;
+                unsafeAtomicAdd(&Kc[(int64_t)(A.c1 + o / ND) * n + B.c2 + o % ND], kad[o]);
+            });
+            static_for<0, NB * ND>([&](auto oc) {
+                constexpr int o = decltype(oc)::value;
+                unsafeAtomicAdd(&Kc[(int64_t)(A.c2 + o / ND) * n + B.c2 + o % ND], s * kbd[o]);
+            });
+        }
+    } else {
         static_for<0, NA * ND>([&](auto oc) {
             constexpr int o = decltype(oc)::value;
-            unsafeAtomicAdd(&Kc[(int64_t)(A.c1 + o / ND) * n + B.c2 + o % ND], kad[o]);
+            const double v = seg_sum(kad[o], links);
+            if (valid && links.head) unsafeAtomicAdd(&Kc[(int64_t)(A.c1 + o / ND) * n + B.c2 + o % ND], v);
         });
         static_for<0, NB * ND>([&](auto oc) {
             constexpr int o = decltype(oc)::value;
-            unsafeAtomicAdd(&Kc[(int64_t)(A.c2 + o / ND) * n + B.c2 + o % ND], s * kbd[o]);
+            const double v = seg_sum(s * kbd[o], links);
+            if (valid && links.head) unsafeAtomicAdd(&Kc[(int64_t)(A.c2 + o / ND) * n + B.c2 + o % ND], v);
         });
+        if (live) {
+            static_for<0, NA * NC>([&](auto oc) {
+                constexpr int o = decltype(oc)::value;
+                unsafeAtomicAdd(&Kc[(int64_t)(A.c1 + o / NC) * n + B.c1 + o % NC], kac[o]);
+            });
+            static_for<0, NB * NC>([&](auto oc) {
+                constexpr int o = decltype(oc)::value;
+                unsafeAtomicAdd(&Kc[(int64_t)(A.c2 + o / NC) * n + B.c1 + o % NC], s * kbc[o]);
+            });
+        }
     }
 }
 

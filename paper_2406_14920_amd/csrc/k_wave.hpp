@@ -180,9 +180,10 @@ __global__ __launch_bounds__(64) void k_wave(KArgs a)
             // last quartet of its row inside this range: K_ac, K_bc are flushed after it
             const bool row_end = w + 1 == w1 || a.prefix[row] + jk + 1 >= a.prefix[row + 1];
             bool take = true;
-            if (a.mode != 0) {  // uniform over the workgroup
-                const bool need = a.Qbra[ib] * a.Qket[kj] * k_dens_bound(a.Pm, a.nsh, A, B) >= a.tau_mix;
-                take = need == (a.mode == 1);
+            if (a.mode != 0 || a.tau_dens > 0.0) {  // uniform over the workgroup
+                const double bound = a.Qbra[ib] * a.Qket[kj] * k_dens_bound(a.Pm, a.nsh, A, B);
+                if (a.mode != 0) take = (bound >= a.tau_mix) == (a.mode == 1);
+                if (bound < a.tau_dens) take = false;  // density-weighted screen
             }
             if (take) {
             double s = 1.0;
@@ -416,9 +417,10 @@ __global__ __launch_bounds__(64) void k_wave_x(KArgs a)
             // last quartet of its row inside this range: K_ac, K_bc are flushed after it
             const bool row_end = w + 1 == w1 || a.prefix[row] + jk + 1 >= a.prefix[row + 1];
             bool take = true;
-            if (a.mode != 0) {  // uniform over the workgroup
-                const bool need = a.Qbra[ib] * a.Qket[kj] * k_dens_bound(a.Pm, a.nsh, A, B) >= a.tau_mix;
-                take = need == (a.mode == 1);
+            if (a.mode != 0 || a.tau_dens > 0.0) {  // uniform over the workgroup
+                const double bound = a.Qbra[ib] * a.Qket[kj] * k_dens_bound(a.Pm, a.nsh, A, B);
+                if (a.mode != 0) take = (bound >= a.tau_mix) == (a.mode == 1);
+                if (bound < a.tau_dens) take = false;  // density-weighted screen
             }
             if (take) {
             double s = 1.0;

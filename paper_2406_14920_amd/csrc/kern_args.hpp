@@ -44,6 +44,14 @@ struct KArgs {
     int32_t nsh;
     int32_t grid_cap;        // workgroups of a range-walking launch (0: default)
     double om2;              // omega^2 of the operator erf(omega r)/r; 0: 1/r
+    // > 0: a quartet whose density-weighted bound Q_ab Q_cd max|D| (the four
+    // blocks its digestion reads) is below tau_dens is skipped (Qbra, Qket,
+    // Pm, nsh set)
+    double tau_dens;
+    // 0: kets grouped by their first shell c (the items of a row share the
+    // K_ac, K_bc targets, which are summed across lanes first); 1: grouped by
+    // the second shell d (K_ad, K_bd shared).  Lane-per-item kernels only.
+    int32_t inv;
 };
 
 // The rows of an exchange work list run bra by bra and, inside a bra, group
@@ -132,6 +140,9 @@ struct JArgs {
     double tau_mix;
     const double *QDket;
     double om2;              // omega^2 of the operator erf(omega r)/r; 0: 1/r
+    // > 0: a ket pair whose Q_ab Q_cd max|D_cd| (Q_ab the wavefront's largest)
+    // is below tau_dens is skipped (Qbra, QDket set)
+    double tau_dens;
     // > 0: each ket chunk (blockIdx.y) stores its sums with plain stores at
     // Jh + chunk * jh_part (zeros where it has no kets), for a fixed-order
     // reduction over the chunks; 0: atomic additions into Jh
@@ -165,6 +176,8 @@ struct KPArgs {
     const double *Pm;
     int32_t nsh;
     double om2;              // omega^2 of the operator erf(omega r)/r; 0: 1/r
+    double tau_dens;         // as in KArgs
+    int32_t inv;             // as in KArgs
 };
 
 // Exchange-gradient launch: the exchange work list plus the per-workgroup

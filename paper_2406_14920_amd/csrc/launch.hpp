@@ -69,6 +69,18 @@ void launch_grad_reduce(const CPair *cp, int ncp, const double *pg, const double
                         int natom, double *grad, hipStream_t st);
 void launch_energy(const double *P, const double *J, const double *K, int64_t n2, double *E, hipStream_t st);
 
+// grid.hip: bounding spheres of 64-point blocks; density (and gradient, if
+// grad) added into rho/grad; the matrix sums of one pair class
+void launch_grid_blocks(const double *pts, int64_t npts, double4 *bsph, hipStream_t st);
+void launch_grid_rho(int la, int lb, const CPair *cp, int ncp, const PrimPair *pp, const double4 *psph,
+                     const double *xyz, const double *D, int ld, const double *pts, int64_t npts,
+                     const double4 *bsph, double *rho, double *grad, hipStream_t st);
+void launch_grid_vmat(int la, int lb, const CPair *cp, int ncp, const PrimPair *pp, const double4 *psph,
+                      const double *xyz, const double *pts, int64_t npts, const double4 *bsph, const double *v0,
+                      const double *v1, double *Vacc, int ld, hipStream_t st);
+// overlap and kinetic energy of one pair class into the accumulators (potential.hip)
+void launch_st_pair(int la, int lb, const CPair *cp, int ncp, const PrimPair *pp, double *Sacc, double *Tacc, int ld,
+                    hipStream_t st);
 // point-charge potential (potential.hip); chg holds [n][4] = x, y, z, q
 // Hermite potential of order L of npp primitive pairs into Vh [npp][nherm(L)];
 // with nsplit > 1 the charges are split over nsplit launches' worth of

@@ -1,4 +1,5 @@
-// potential.hip -- point-charge potential V_mn = sum_C q_C int m(r) n(r) / |r - C|
+// potential.hip -- one-electron integrals: overlap S, kinetic energy T and the
+// point-charge potential V_mn = sum_C q_C int m(r) n(r) / |r - C|
 // (nuclear attraction with q_C = -Z_C, or any point charges such as QM/MM
 // embedding charges; eqs. v1e_definition, v1e_summation_over_C) and the
 // derivatives of E_V = sum_mn P_mn V_mn (SI eqs. si_v1e_derivative_A/B/C).
@@ -23,8 +24,83 @@
 #include "kern_args.hpp"
 #include "launch.hpp"
 #include "md_device.hpp"
+#include "wave_r.hpp"
 
 namespace md {
+
+// Overlap and kinetic energy of one contracted pair, thread per Cartesian
+// component (eqs. overlap_formula, kinetic_formula): with the one-direction
+// Hermite coefficients E (E^{00}_0 = 1; K_ab kept apart) per primitive pair
+//     S_ab += K_ab (pi/p)^{3/2} E^x_0 E^y_0 E^z_0,
+//     T_ab += K_ab (pi/p)^{3/2} sum_k t_k prod_{other} E_0,
+//     t_k = (2j+1) b E^{i,j}_0 - 2 b^2 E^{i,j+2}_0 - j(j-1)/2 E^{i,j-2}_0,
+// written as one triangle of the accumulators (X = Acc + Acc^T).
+template <int LA, int LB>
+__global__ __launch_bounds__(128) void st_pair(const CPair *__restrict__ cp, int ncp,
+                                               const PrimPair *__restrict__ pp, double *__restrict__ Sacc,
+                                               double *__restrict__ Tacc, int ld)
+{
+    constexpr int NA = ncart(LA), NB = ncart(LB), LB2 = LB + 2;
+    constexpr int DJ = LA + LB2 + 1, DI = (LB2 + 1) * DJ, EBD = (LA + 1) * DI;
+    __shared__ double sE[3 * EBD];
+    const int c = blockIdx.x;
+    if (c >= ncp) return;
+    const CPair A = cp[c];
+    const int tid = threadIdx.x;
+    int ia[3] = {0, 0, 0}, jb[3] = {0, 0, 0};
+    if (tid < NA * NB) {
+        cart_rt(LA, tid / NB, ia[0], ia[1], ia[2]);
+        cart_rt(LB, tid % NB, jb[0], jb[1], jb[2]);
+    }
+    double sacc = 0.0, tacc = 0.0;
+    for (int ip = 0; ip < A.np; ++ip) {
+        const PrimPair pb = pp[A.poff + ip];
+        if (tid < 3) {
+            const double pa = tid == 0 ? pb.PA[0] : (tid == 1 ? pb.PA[1] : pb.PA[2]);
+            const double pbb = tid == 0 ? pb.PB[0] : (tid == 1 ? pb.PB[1] : pb.PB[2]);
+            etab_lds<LA, LB2>(pa, pbb, pb.o2p, sE + tid * EBD);
+        }
+        __syncthreads();
+        if (tid < NA * NB) {
+            const double b = pb.b;
+            double sk[3], tk[3];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                const double *E = sE + k * EBD + ia[k] * DI;
+                const int j = jb[k];
+                sk[k] = E[j * DJ];
+                double t = (2 * j + 1) * b * E[j * DJ] - 2.0 * b * b * E[(j + 2) * DJ];
+                if (j >= 2) t -= 0.5 * j * (j - 1) * E[(j - 2) * DJ];
+                tk[k] = t;
+            }
+            const double r = kPi / pb.p;
+            const double pref = pb.K * r * sqrt(r);
+            sacc += pref * sk[0] * sk[1] * sk[2];
+            tacc += pref * (tk[0] * sk[1] * sk[2] + sk[0] * tk[1] * sk[2] + sk[0] * sk[1] * tk[2]);
+        }
+        __syncthreads();
+    }
+    if (tid < NA * NB) {
+        const double f = (A.sh1 == A.sh2) ? 0.5 : 1.0;
+        const int64_t o = (int64_t)(A.c1 + tid / NB) * ld + A.c2 + tid % NB;
+        Sacc[o] = f * sacc;
+        Tacc[o] = f * tacc;
+    }
+}
+
+void launch_st_pair(int la, int lb, const CPair *cp, int ncp, const PrimPair *pp, double *Sacc, double *Tacc, int ld,
+                    hipStream_t st)
+{
+    if (ncp <= 0) return;
+#define MD_ST(A_, B_)                                                                                    \
+    if (la == A_ && lb == B_) {                                                                          \
+        hipLaunchKernelGGL((st_pair<A_, B_>), dim3((unsigned)ncp), dim3(128), 0, st, cp, ncp, pp, Sacc, Tacc, ld); \
+        return;                                                                                          \
+    }
+    MD_ST(0, 0) MD_ST(1, 0) MD_ST(1, 1) MD_ST(2, 0) MD_ST(2, 1) MD_ST(2, 2) MD_ST(3, 0) MD_ST(3, 1)
+    MD_ST(3, 2) MD_ST(3, 3)
+#undef MD_ST
+}
 
 // R^0_t(p, P - C) times K_ab (2 pi/p) q for one primitive pair and one charge
 template <int L>

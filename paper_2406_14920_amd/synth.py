@@ -208,11 +208,15 @@ def custom(xyz, shell_specs, seed: int = 0, tau: float = 1e-12, nocc=None,
 WORKLOADS = {"mol4": mol4, "mol40": mol40, "tm62": tm62, "mol20": mol20}
 
 
-def nuclei(mol: Molecule, seed: int = 0) -> np.ndarray:
+def nuclei(mol: Molecule, seed: int = 0, even: bool = False) -> np.ndarray:
     """Nuclear point charges of the atoms, rows x, y, z, q with q = -Z and Z
-    drawn from {1, 6, 7, 8} (the synthetic atoms carry no element)."""
+    drawn from {1, 6, 7, 8} (the synthetic atoms carry no element); with
+    even=True the first atom's Z moves by one where needed so that the
+    electron count sum Z is even (closed shell)."""
     rng = np.random.default_rng(seed)
     Z = rng.choice(np.array([1.0, 6.0, 7.0, 8.0]), size=mol.natom)
+    if even and int(Z.sum()) % 2:
+        Z[0] += 1.0 if Z[0] in (1.0, 6.0) else -1.0
     return np.concatenate([mol.xyz, -Z[:, None]], axis=1)
 
 
@@ -230,3 +234,45 @@ def point_charges(mol: Molecule, n: int, seed: int = 0, rmin: float = 2.0, pad: 
         out = np.concatenate([out, x[d2 >= rmin * rmin]], axis=0)
     q = rng.uniform(-1.0, 1.0, size=n)
     return np.concatenate([out[:n], q[:, None]], axis=1)
+
+
+def molecular_grid(mol: Molecule, nrad: int = 40, ntheta: int = 11, nphi: int = 22, rm: float = 1.0):
+    """Atom-centred integration grid (the paper's molecular grids are not
+    specified): per atom, nrad radial nodes of Gauss-Chebyshev quadrature of
+    the second kind mapped by r = rm (1 + x) / (1 - x), times ntheta
+    Gauss-Legendre nodes in cos(theta) and nphi equally spaced phi, with
+    Becke's fuzzy-cell partition (three iterations of f(u) = 1.5u - 0.5u^3) for
+    the weights.  Points come atom by atom and radial shell by radial shell,
+    so neighbouring points lie close together.  Returns (points [n, 3],
+    weights [n]).  Geometry only: no random numbers and none of the integral
+    arithmetic."""
+    k = np.arange(1, nrad + 1)
+    x = np.cos(k * np.pi / (nrad + 1))
+    wx = np.pi / (nrad + 1) * np.sin(k * np.pi / (nrad + 1)) ** 2 / np.sqrt(1.0 - x * x)
+    r = rm * (1.0 + x) / (1.0 - x)
+    wr = wx * 2.0 * rm / (1.0 - x) ** 2 * r * r
+    ct, wt = np.polynomial.legendre.leggauss(ntheta)
+    st = np.sqrt(1.0 - ct * ct)
+    ph = 2.0 * np.pi * np.arange(nphi) / nphi
+    dirs = np.stack([(st[:, None] * np.cos(ph)[None, :]).ravel(), (st[:, None] * np.sin(ph)[None, :]).ravel(),
+                     np.repeat(ct, nphi)], axis=1)
+    wa = np.repeat(wt, nphi) * (2.0 * np.pi / nphi)
+    xyz = mol.xyz
+    nat = mol.natom
+    R = np.linalg.norm(xyz[:, None, :] - xyz[None, :, :], axis=-1) + np.eye(nat)
+    pts, wts = [], []
+    for a in range(nat):
+        p = (xyz[a][None, None, :] + r[:, None, None] * dirs[None, :, :]).reshape(-1, 3)
+        w = (wr[:, None] * wa[None, :]).ravel()
+        d = np.linalg.norm(p[:, None, :] - xyz[None, :, :], axis=-1)      # [n, nat]
+        cell = np.empty((p.shape[0], nat))
+        for A in range(nat):
+            s = (d[:, A:A + 1] - d) / R[A][None, :]                       # mu_AB, [n, B]
+            for _ in range(3):
+                s = s * (1.5 - 0.5 * s * s)
+            s = 0.5 * (1.0 - s)
+            s[:, A] = 1.0
+            cell[:, A] = np.prod(s, axis=1)
+        pts.append(p)
+        wts.append(w * cell[:, a] / np.sum(cell, axis=1))
+    return np.concatenate(pts, 0), np.concatenate(wts, 0)

@@ -138,9 +138,10 @@ def test_autotune_keeps_results(precision):
     assert set(tun["kcap"]) <= {0, 1024, 4096, 16384, 32768, 131072}
     J1, K1 = jk.jk(P)
     torch.cuda.synchronize()
-    if precision == "mixed":
-        # the tuner may move launches between the FP32 share and FP64: both
-        # results are mixed results, held to the mixed bar against each other
+    if precision != "fp64":
+        # the tuner may move launches between the FP32 share and FP64, and a
+        # change of ket grouping changes which quartets share a precision
+        # tile: both results are mixed results, held to the mixed bar
         assert float((J1 - J0).abs().max()) <= 1e-6 and float((K1 - K0).abs().max()) <= 1e-6
     else:
         _close(J1, J0, "J after autotune")
