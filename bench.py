@@ -165,6 +165,41 @@ def bench_prim0(jk0, P, J, K, a, st):
             "default_skips_k": skip_k, "default_skips_j": skip_j}
 
 
+def bench_tuned(jk, P, J, K, a):
+    """The autotuner on the headline workload, per precision: launch shapes,
+    FP32 shares and ket groupings picked from timings on this context, then
+    the same build timed again (results change only in the order of
+    additions, or within the mixed error)."""
+    import torch
+    out = {}
+    for prec in ("fp64", "mixed"):
+        jk.set_precision(prec)
+        for _ in range(max(1, a.warmup)):
+            jk.jk(P)
+        ms0 = _time(lambda: jk.jk(P), a.steps)
+        t0 = time.perf_counter()
+        tun = jk.autotune(P, reps=1)
+        tune_s = time.perf_counter() - t0
+        for _ in range(max(1, a.warmup)):
+            jk.jk(P)
+        ms1 = _time(lambda: jk.jk(P), a.steps)
+        J1, K1 = jk.jk(P)
+        torch.cuda.synchronize()
+        dK = float((K1 - K).abs().max())
+        inv = sum(1 for v in abi_tuning(jk)["exchange"].values() if len(v) > 2 and v[2])
+        out[prec] = {"default_ms": ms0, "tuned_ms": ms1, "autotune_s": tune_s, "max_abs_dK_vs_fp64": dK,
+                     "exchange_launches_by_second_shell": inv}
+        print("tuned %s: default %.1f ms -> tuned %.1f ms (autotune %.1f s, %d launches grouped by d) dK=%.1e" % (
+            prec, ms0, ms1, tune_s, inv, dK), file=sys.stderr, flush=True)
+    jk.set_precision(a.precision)
+    return out
+
+
+def abi_tuning(jk):
+    from paper_2406_14920_amd import abi
+    return abi.eri_get_tuning(jk.ctx)
+
+
 def bench_tm62(a):
     """Transition-metal-like workload (1336 functions, exponents to 2e5):
     FP64 and mixed J+K time and the mixed error against FP64."""
@@ -207,10 +242,19 @@ def bench_grad(a):
     g = jk.grad(P)
     ms = _time(lambda: jk.grad(P), max(1, min(a.steps, 3)))
     g = jk.grad(P).cpu().numpy()
+    jk.set_precision("mixed_all")
+    jk.grad(P)
+    ms_m = _time(lambda: jk.grad(P), max(1, min(a.steps, 3)))
+    gm = jk.grad(P).cpu().numpy()
     jk.close()
-    print("grad mol20: %.1f ms |sum g|=%.1e" % (ms, np.abs(g.sum(0)).max()), file=sys.stderr, flush=True)
+    print("grad mol20: %.1f ms |sum g|=%.1e; mixed %.1f ms max|dg|=%.1e |sum g|=%.1e" % (
+        ms, np.abs(g.sum(0)).max(), ms_m, np.abs(gm - g).max(), np.abs(gm.sum(0)).max()),
+        file=sys.stderr, flush=True)
     return {"workload": "mol20: 20 atoms, mol40 shell set, 420 spherical bf, Schwarz 1e-11", "ms": ms,
-            "max_abs_sum_over_atoms": float(np.abs(g.sum(0)).max()), "dtype": "f64"}
+            "max_abs_sum_over_atoms": float(np.abs(g.sum(0)).max()), "dtype": "f64",
+            "mixed": {"ms": ms_m, "max_abs_dg_vs_fp64": float(np.abs(gm - g).max()),
+                      "max_abs_sum_over_atoms": float(np.abs(gm.sum(0)).max()),
+                      "fp32_share": "Coulomb J-engine launches (raised bra order <= 6), tau_mix 1e-5"}}
 
 
 def bench_potential(a, n_mm: int = 20000):
@@ -265,7 +309,8 @@ def bench_scf(a):
     nocc = int(round(-nuc[:, 3].sum())) // 2
     jk = JK.from_molecule(mol)
     be = scf.GPUBackend(jk, nuc)
-    out = {"workload": "mol40 closed-shell SCF, %d electrons, 840 spherical bf, level shift 0.3" % (2 * nocc)}
+    out = {"workload": "mol40 closed-shell SCF, %d electrons, 840 spherical bf, level shift 0.3, "
+                       "overlap eigenvalues below 1e-6 dropped" % (2 * nocc)}
     for mode in ("fp64", "dynamic"):
         t0 = time.perf_counter()
         r = scf.rhf(be, nuc, nocc, mode=mode, max_iter=50, conv=1e-8, grad_conv=1e-5, level_shift=0.3)
@@ -335,6 +380,7 @@ def bench_batch(a):
     b = Batch(jks)
     b.jk(Ps)
     ms_batch = _time(lambda: b.jk(Ps), max(1, a.steps))
+    lat = np.array(b.latency())
     ms_seq = _time(lambda: [jk.jk(P) for jk, P in zip(jks, Ps)], max(1, min(a.steps, 3)))
     b.close()
     for jk in jks:
@@ -344,8 +390,12 @@ def bench_batch(a):
     return {"workload": "64 molecules of 5-30 atoms (mol40 shell set), FP64", "molecules": len(mols),
             "nbf_range": [min(m.nbf for m in mols), max(m.nbf for m in mols)],
             "ms_per_batch": ms_batch, "ms_per_batch_one_by_one": ms_seq,
-            "eris_per_s_batch": eris / (ms_batch / 1e3), "per_molecule_latency_ms_batch": ms_batch,
-            "launch": "direct launches on 8 concurrent streams (graph recording switched off)"}
+            "eris_per_s_batch": eris / (ms_batch / 1e3),
+            "per_molecule_latency_ms": {"min": float(lat.min()), "median": float(np.median(lat)),
+                                        "p90": float(np.percentile(lat, 90)), "max": float(lat.max())},
+            "latency_of": "last timed call, from its start to each molecule's completion (HIP events)",
+            "launch": "direct launches on 8 concurrent streams, largest molecule first onto the least-loaded "
+                      "stream (graph recording switched off)"}
 
 
 def main():
@@ -445,6 +495,7 @@ def main():
     if not a.no_extras:
         out["compare"] = compare_precision(jk, P, J, K, a, st)
         out["prim_thresh_0"] = bench_prim0(jk, P, J, K, a, st)
+        out["tuned"] = bench_tuned(jk, P, J, K, a)
     jk.close()
     if not a.no_extras:
         out["tm62"] = bench_tm62(a)

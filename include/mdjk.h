@@ -233,8 +233,13 @@ int build_jk_static(eri_ctx *ctx, const double *P, double *J, double *K);
  * pair derivative of SI eq. si_pair_derivative (SI eq. si_dj_formula);
  * exchange part: derivative integrals of every canonical quartet on all four
  * centres (the fourth by translational invariance).  Same screening as
- * build_jk; always double precision.  Per-atom sums are formed in a fixed
- * order, so repeated calls give identical results.
+ * build_jk.  Precision: under ERI_MIXED_ALL (and where the autotuner chose
+ * an FP32 share of a J-engine launch under ERI_MIXED) the Coulomb part's
+ * J-engine launches of raised bra order <= 6 take the FP32 share by the same
+ * density-weighted tile rule as build_jk, accumulated in FP64; the exchange
+ * part, the pair-derivative contraction and every sum are FP64 (FP32 vector
+ * arithmetic has no rate advantage over FP64 on this target).  Per-atom sums
+ * are formed in a fixed order, so repeated calls give identical results.
  * P: device nbf*nbf.  grad: device [natom*3] or NULL; E: device [1] or NULL
  * (then a double-precision J and K build is done first); not both NULL.
  * Asynchronous. */
@@ -354,6 +359,14 @@ int eri_set_tuning(eri_ctx *ctx, const eri_tuning_t *in);
 typedef struct eri_batch eri_batch;
 int eri_batch_create(eri_ctx *const *ctxs, int32_t n, void *stream, eri_batch **out);
 int eri_batch_build_jk(eri_batch *b, const double *const *P, double *const *J, double *const *K);
+/* Per-molecule latency of the last eri_batch_build_jk: ms[i] = device time
+ * from the start of that call on the batch stream to the end of molecule i's
+ * build (HIP events on its batch stream), for the first n molecules.
+ * Molecules are issued largest first (by the spherical ERIs of their unique
+ * quartets), each onto the least-loaded of the batch streams.  Synchronises
+ * with those events.  ERI_ESTATE before the first batch build. */
+int eri_batch_latency(eri_batch *b, float *ms, int32_t n);
+
 int eri_batch_destroy(eri_batch *b);
 
 /* Message of the last error on this thread ("" if none). */

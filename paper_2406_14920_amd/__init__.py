@@ -220,9 +220,9 @@ class JK:
 
 
 class Batch:
-    """Many JK contexts built together from one recorded HIP graph
-    (eri_batch_*).  Output tensors are allocated once and reused, so repeated
-    calls replay the same graph."""
+    """Many JK contexts built together (eri_batch_*): every molecule's build
+    forked from the batch stream onto one of a few streams, largest first,
+    and joined back.  Output tensors are allocated once and reused."""
 
     def __init__(self, jks, stream=None):
         import torch
@@ -244,6 +244,11 @@ class Batch:
         with torch.cuda.stream(self.stream):
             abi.eri_batch_build_jk(self.handle, list(Ps), self.J, self.K)
         return self.J, self.K
+
+    def latency(self):
+        """Per-molecule completion times (ms) of the last jk() call, from
+        its start on the batch stream (eri_batch_latency)."""
+        return abi.eri_batch_latency(self.handle, len(self.jks))
 
     def close(self):
         if getattr(self, "handle", None):

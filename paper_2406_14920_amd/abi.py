@@ -68,7 +68,7 @@ EXPORTS = ["eri_default_opts", "eri_setup", "eri_nbf", "eri_set_geometry", "eri_
            "eri_last_error", "eri_batch_create", "eri_batch_build_jk", "eri_batch_destroy",
            "eri_autotune", "eri_tuning", "build_jk_static", "eri_set_omega", "eri_get_tuning",
            "eri_set_tuning", "eri_potential", "eri_potential_grad", "eri_set_density_screen",
-           "eri_one_electron", "eri_grid_density", "eri_grid_matrix"]
+           "eri_one_electron", "eri_grid_density", "eri_grid_matrix", "eri_batch_latency"]
 
 _lib = None
 
@@ -111,6 +111,7 @@ def load(path: str = LIB_PATH):
     L.eri_batch_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int32, vp, ctypes.POINTER(vp)]
     L.eri_batch_build_jk.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp)]
     L.eri_batch_destroy.argtypes = [vp]
+    L.eri_batch_latency.argtypes = [vp, ctypes.POINTER(ctypes.c_float), ctypes.c_int32]
     L.eri_autotune.argtypes = [vp, vp, ctypes.c_int32]
     ip = ctypes.POINTER(ctypes.c_int32)
     L.eri_tuning.argtypes = [vp, ip, ip, ctypes.c_int32, ip]
@@ -331,3 +332,10 @@ def eri_tuning(ctx: int) -> dict:
 
 def eri_last_error() -> str:
     return load().eri_last_error().decode()
+
+
+def eri_batch_latency(batch: int, n: int) -> list:
+    """Per-molecule completion times (ms) of the last batch build."""
+    arr = (ctypes.c_float * max(n, 1))()
+    _check(load().eri_batch_latency(ctypes.c_void_p(batch), arr, int(n)))
+    return [float(arr[i]) for i in range(n)]

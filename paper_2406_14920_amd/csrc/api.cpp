@@ -1212,31 +1212,51 @@ void run_grad(eri_ctx *c, double *grad)
     hipStream_t st = c->st;
     const int nc = c->nbf_cart;
     ensure_grad(c);
+    // mixed precision: the J-engine launches take the FP32 share that
+    // build_jk's J-engine launches take (every launch under ERI_MIXED_ALL,
+    // the autotuner's choice under ERI_MIXED), with the same density-weighted
+    // tile rule; raised bra orders above 6 and the exchange part stay FP64
+    const int prec = c->opts.precision;
+    const bool mixed = prec != ERI_FP64;
+    if (mixed) {
+        ensure_mixed(c);
+        launch_density_bounds(c->wk.Pc, nc, c->d_l.p, c->d_coff.p, c->nshell, c->d_Pm.p, c->d_cp.p, c->d_Q.p,
+                              (int)c->cp.size(), c->d_QD.p, st);
+    }
     // Coulomb: Hermite density, J-engine with the bra order raised by one
     for (int Y = 0; Y < kPairClasses; ++Y)
         launch_hermite_density(kPairL[Y][0], kPairL[Y][1], c->d_cp.p + c->cp_base[Y], c->ncp[Y], c->d_pp.p,
-                               c->wk.Pc, nc, c->wk.Dt + c->dt_off[Y], nullptr, c->pp_base[Y], st);
+                               c->wk.Pc, nc, c->wk.Dt + c->dt_off[Y], mixed ? c->d_Dtf.p + c->dt_off[Y] : nullptr,
+                               c->pp_base[Y], st);
     launch_fill_zero(c->d_Jh1.p, (int64_t)c->d_Jh1.n, st);
     for (int X = 0; X < kPairClasses; ++X) {
         if (c->npp[X] == 0) continue;
         for (int Y = 0; Y < kPairClasses; ++Y) {
             if (c->ncp[Y] == 0) continue;
-            JArgs a = j_args(c, X, Y, false);
+            JArgs a = j_args(c, X, Y, mixed);
             // every ket chunk stores its sums; they are added to Jh1 in chunk
-            // order, so repeated gradients are bitwise identical
+            // order (the FP64 share first), so repeated gradients are bitwise
+            // identical
             a.kchunk = c->gchunk[X][Y];
             const int nch = (c->ncp[Y] + a.kchunk - 1) / a.kchunk;
             const int lx = kPairL[X][0] + kPairL[X][1] + 1, ly = kPairL[Y][0] + kPairL[Y][1];
             a.Jh = c->d_jhpart.p;
             a.jh_part = (int64_t)c->npp[X] * nherm(lx);
-            timed(c, st, cls_name("jeng_grad", kPairL[X][0], kPairL[X][1], kPairL[Y][0], kPairL[Y][1]), -1, 0, 0,
-                  [&] {
-                      if (!launch_jeng(lx, ly, a, false, st)) {
-                          set_err(ERI_ESTATE, "no J-engine kernel for orders (%d,%d)", lx, ly);
-                          throw HipError{ERI_ESTATE};
-                      }
-                      launch_jh_reduce(c->d_jhpart.p, nch, a.jh_part, c->d_Jh1.p + c->jh1_off[X], a.jh_part, st);
-                  });
+            const bool split = mixed && lx <= 6 && (prec == ERI_MIXED_ALL || c->jsplit[X][Y]);
+            for (int part = split ? 1 : 0; part <= (split ? 2 : 0); ++part) {
+                a.mode = part;
+                timed(c, st,
+                      cls_name("jeng_grad", kPairL[X][0], kPairL[X][1], kPairL[Y][0], kPairL[Y][1]) +
+                          (part == 0 ? "" : (part == 1 ? "/d" : "/s")),
+                      -1, 0, 0, [&] {
+                          if (!launch_jeng(lx, ly, a, part == 2, st)) {
+                              set_err(ERI_ESTATE, "no J-engine kernel for orders (%d,%d)", lx, ly);
+                              throw HipError{ERI_ESTATE};
+                          }
+                          launch_jh_reduce(c->d_jhpart.p, nch, a.jh_part, c->d_Jh1.p + c->jh1_off[X], a.jh_part,
+                                           st);
+                      });
+            }
         }
     }
     for (int X = 0; X < kPairClasses; ++X) {
@@ -2129,6 +2149,11 @@ struct eri_batch {
     hipGraphExec_t exec = nullptr;
     std::vector<const double *> P;
     std::vector<double *> J, K;
+    // direct launches: issue order (largest first) and lane of every molecule,
+    // timing events of the last call (start, then one per molecule)
+    std::vector<int> order, lane_of;
+    std::vector<hipEvent_t> tev;
+    bool timed_once = false;
 };
 
 namespace {
@@ -2231,6 +2256,21 @@ int eri_batch_create(eri_ctx *const *ctxs, int32_t n, void *stream, eri_batch **
         for (auto &s : b->lanes) HIPCHK(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
         b->evs.resize(1 + b->lanes.size());
         for (auto &e : b->evs) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        b->tev.resize(1 + (size_t)n);
+        for (auto &e : b->tev) HIPCHK(hipEventCreate(&e));
+        // largest molecules first, each onto the least-loaded lane (cost: the
+        // spherical ERIs its unique quartets represent)
+        b->order.resize(n);
+        for (int i = 0; i < n; ++i) b->order[i] = i;
+        std::stable_sort(b->order.begin(), b->order.end(),
+                         [&](int x, int y) { return ctxs[x]->eris_sph > ctxs[y]->eris_sph; });
+        b->lane_of.assign(n, 0);
+        std::vector<double> load(b->lanes.size(), 0.0);
+        for (int i : b->order) {
+            const size_t k = (size_t)(std::min_element(load.begin(), load.end()) - load.begin());
+            b->lane_of[i] = (int)k;
+            load[k] += ctxs[i]->eris_sph;
+        }
     } catch (const HipError &e) {
         return e.code;
     }
@@ -2264,19 +2304,38 @@ int eri_batch_build_jk(eri_batch *b, const double *const *P, double *const *J, d
             // the same fork/join, launched directly: every molecule on one of
             // the batch's streams, all joined back into the batch stream
             HIPCHK(hipEventRecord(b->evs[0], b->st));
+            HIPCHK(hipEventRecord(b->tev[0], b->st));
             for (auto &s : b->lanes) HIPCHK(hipStreamWaitEvent(s, b->evs[0], 0));
-            for (size_t i = 0; i < n; ++i) {
+            for (const int i : b->order) {
                 eri_ctx *c = b->ctxs[i];
                 const hipStream_t saved = c->st;
-                c->st = b->lanes[i % b->lanes.size()];
+                c->st = b->lanes[b->lane_of[i]];
                 const int rc = build_jk(c, P[i], J[i], K[i]);
                 c->st = saved;
                 if (rc) return rc;
+                HIPCHK(hipEventRecord(b->tev[1 + i], b->lanes[b->lane_of[i]]));
             }
+            b->timed_once = true;
             for (size_t k = 0; k < b->lanes.size(); ++k) {
                 HIPCHK(hipEventRecord(b->evs[1 + k], b->lanes[k]));
                 HIPCHK(hipStreamWaitEvent(b->st, b->evs[1 + k], 0));
             }
+        }
+    } catch (const HipError &e) {
+        return e.code;
+    }
+    return ERI_OK;
+}
+
+int eri_batch_latency(eri_batch *b, float *ms, int32_t n)
+{
+    if (!batch_ok(b)) return set_err(ERI_ESTATE, "invalid batch");
+    if (!ms || n < 0) return set_err(ERI_EINVAL, "ms is NULL or n negative");
+    if (!b->timed_once) return set_err(ERI_ESTATE, "no batch build has run with direct launches yet");
+    try {
+        for (int32_t i = 0; i < n && i < (int32_t)b->ctxs.size(); ++i) {
+            HIPCHK(hipEventSynchronize(b->tev[1 + i]));
+            HIPCHK(hipEventElapsedTime(&ms[i], b->tev[0], b->tev[1 + i]));
         }
     } catch (const HipError &e) {
         return e.code;
@@ -2291,6 +2350,7 @@ int eri_batch_destroy(eri_batch *b)
     (void)hipStreamSynchronize(b->st);
     batch_release_graph(b);
     for (auto &e : b->evs) (void)hipEventDestroy(e);
+    for (auto &e : b->tev) (void)hipEventDestroy(e);
     for (auto &s : b->lanes) (void)hipStreamDestroy(s);
     b->magic = 0;
     delete b;

@@ -98,9 +98,12 @@ def nuclear_repulsion(nuclei) -> float:
 def rhf(backend, nuclei, nocc: int, mode: str = "fp64", conv: float = 1e-9, grad_conv: float = 1e-6,
         max_iter: int = 100, ratio: float = 1e-2, tau_min: float = 1e-9, tau_max: float = 1e-3,
         fp64_below: float = 1e-5, tau_dens: float = 1e-12, rebuild_every: int = 6, diis: int = 8,
-        lindep: float = 1e-8, level_shift: float = 0.0) -> SCFResult:
+        lindep: float = 1e-6, level_shift: float = 0.0) -> SCFResult:
     """Closed-shell SCF (see the module docstring); nuclei rows x, y, z, q
-    with q = -Z (their repulsion uses the charges as given).  level_shift
+    with q = -Z (their repulsion uses the charges as given).  Overlap
+    eigenvalues below lindep are dropped from the orthogonalised basis (near
+    linear dependence would otherwise amplify rounding noise in the orbital
+    gradient by 1/lindep).  level_shift
     raises the virtual orbitals of the extrapolated Fock matrix by that many
     hartree before it is diagonalised (F + shift (S - S P S / 2)), which damps
     oscillating iterations and leaves the converged solution unchanged."""

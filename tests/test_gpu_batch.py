@@ -209,3 +209,29 @@ def test_autotune_cache_roundtrip(tmp_path):
     assert "c5/fp64" in store and store["c5/fp64"]["exchange"]
     jk1.close()
     jk2.close()
+
+
+def test_batch_latency_per_molecule():
+    """Per-molecule completion times of a batch call: one per molecule,
+    positive, none after the call's end (measured on the host around it)."""
+    import time
+    torch = _torch()
+    from paper_2406_14920_amd import JK, Batch
+    mols = [synth.small_cluster(n, 100 + n) for n in (2, 5, 3, 6)]
+    jks = [JK.from_molecule(m) for m in mols]
+    Ps = [torch.tensor(m.P, dtype=torch.float64, device="cuda") for m in mols]
+    b = Batch(jks)
+    b.jk(Ps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.jk(Ps)
+    torch.cuda.synchronize()
+    wall_ms = (time.perf_counter() - t0) * 1e3
+    lat = b.latency()
+    assert len(lat) == len(mols)
+    assert all(0.0 < v <= wall_ms + 1.0 for v in lat), (lat, wall_ms)
+    for jk, P, J, K in zip(jks, Ps, b.J, b.K):
+        J0, K0 = jk.jk(P)
+        _close(J, J0, "J batch")
+        _close(K, K0, "K batch")
+    b.close()
