@@ -64,7 +64,11 @@ extern "C" {
 #define ERI_EINVAL (-1) /* bad argument: null pointer, l outside 0..3, nprim < 1,
                            exponent <= 0 or not finite, atom index out of range,
                            negative threshold, unknown precision */
-#define ERI_ENOMEM (-2) /* device or host allocation failed */
+#define ERI_ENOMEM (-2) /* device or host allocation failed, or the library's device
+                           buffers would pass the byte cap that the environment
+                           variable ERI_MAX_DEVICE_BYTES sets (read at every
+                           allocation; unset or 0: no cap).  A failed call leaves
+                           no half-built context; a context stays usable. */
 #define ERI_EHIP   (-3) /* HIP runtime error; the message carries hipGetErrorString */
 #define ERI_ESTATE (-4) /* null/destroyed context or an inconsistent request */
 

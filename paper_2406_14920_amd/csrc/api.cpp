@@ -15,10 +15,12 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <array>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -167,6 +169,18 @@ double dfact(int n)
     return r;
 }
 
+// Device bytes held by the library's buffers in this process, and the cap
+// that the environment variable ERI_MAX_DEVICE_BYTES may set (read at every
+// allocation; unset or 0: none) so that tests can drive the out-of-memory
+// paths without exhausting the device.
+std::atomic<unsigned long long> g_dev_bytes{0};
+
+unsigned long long dev_cap()
+{
+    const char *s = std::getenv("ERI_MAX_DEVICE_BYTES");
+    return s ? std::strtoull(s, nullptr, 10) : 0ull;
+}
+
 template <typename T>
 struct DevBuf {
     T *p = nullptr;
@@ -174,8 +188,17 @@ struct DevBuf {
     void alloc(size_t count)
     {
         release();
+        if (count) {
+            const unsigned long long bytes = (unsigned long long)count * sizeof(T), cap = dev_cap();
+            if (cap && g_dev_bytes.load() + bytes > cap) {
+                set_err(ERI_ENOMEM, "device allocation of %llu bytes would pass ERI_MAX_DEVICE_BYTES=%llu (%llu held)",
+                        bytes, cap, (unsigned long long)g_dev_bytes.load());
+                throw HipError{ERI_ENOMEM};
+            }
+            HIPCHK(hipMalloc((void **)&p, count * sizeof(T)));
+            g_dev_bytes += bytes;
+        }
         n = count;
-        if (count) HIPCHK(hipMalloc((void **)&p, count * sizeof(T)));
     }
     void upload(const std::vector<T> &h)
     {
@@ -184,7 +207,10 @@ struct DevBuf {
     }
     void release()
     {
-        if (p) (void)hipFree(p);
+        if (p) {
+            (void)hipFree(p);
+            g_dev_bytes -= (unsigned long long)n * sizeof(T);
+        }
         p = nullptr;
         n = 0;
     }
