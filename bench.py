@@ -105,6 +105,12 @@ def cpu_baseline(mol, target_s: float = 15.0):
             "sample_seconds": dt}
 
 
+def _xsteps(a) -> int:
+    """Timed repetitions of the side measurements (the headline keeps
+    --steps): at most 3, so that the default run stays within minutes."""
+    return max(1, min(a.steps, 3))
+
+
 def _time(fn, steps):
     import torch
     torch.cuda.synchronize()
@@ -124,7 +130,7 @@ def compare_precision(jk, P, J, K, a, st):
     jk.set_precision(other)
     for _ in range(max(1, a.warmup)):
         J1, K1 = jk.jk(P)
-    ms = _time(lambda: jk.jk(P), a.steps)
+    ms = _time(lambda: jk.jk(P), _xsteps(a))
     J1, K1 = jk.jk(P)
     torch.cuda.synchronize()
     s2 = jk.stats()
@@ -149,7 +155,7 @@ def bench_prim0(jk0, P, J, K, a, st):
     jk = JK.from_molecule(mol, prim_thresh=0.0)
     for _ in range(max(1, a.warmup)):
         jk.jk(P)
-    ms = _time(lambda: jk.jk(P), a.steps)
+    ms = _time(lambda: jk.jk(P), _xsteps(a))
     J0, K0 = jk.jk(P)
     torch.cuda.synchronize()
     s0 = jk.stats()
@@ -176,13 +182,13 @@ def bench_tuned(jk, P, J, K, a):
         jk.set_precision(prec)
         for _ in range(max(1, a.warmup)):
             jk.jk(P)
-        ms0 = _time(lambda: jk.jk(P), a.steps)
+        ms0 = _time(lambda: jk.jk(P), _xsteps(a))
         t0 = time.perf_counter()
         tun = jk.autotune(P, reps=1)
         tune_s = time.perf_counter() - t0
         for _ in range(max(1, a.warmup)):
             jk.jk(P)
-        ms1 = _time(lambda: jk.jk(P), a.steps)
+        ms1 = _time(lambda: jk.jk(P), _xsteps(a))
         J1, K1 = jk.jk(P)
         torch.cuda.synchronize()
         dK = float((K1 - K).abs().max())
@@ -215,7 +221,7 @@ def bench_tm62(a):
         jk.set_precision(prec)
         for _ in range(max(1, a.warmup)):
             jk.jk(P)
-        ms = _time(lambda: jk.jk(P), max(1, min(a.steps, 5)))
+        ms = _time(lambda: jk.jk(P), _xsteps(a))
         J, K = jk.jk(P)
         torch.cuda.synchronize()
         res[prec] = (ms, J, K)
@@ -240,11 +246,11 @@ def bench_grad(a):
     jk = JK.from_molecule(mol)
     P = torch.tensor(mol.P, dtype=torch.float64, device="cuda")
     g = jk.grad(P)
-    ms = _time(lambda: jk.grad(P), max(1, min(a.steps, 3)))
+    ms = _time(lambda: jk.grad(P), 1)
     g = jk.grad(P).cpu().numpy()
     jk.set_precision("mixed_all")
     jk.grad(P)
-    ms_m = _time(lambda: jk.grad(P), max(1, min(a.steps, 3)))
+    ms_m = _time(lambda: jk.grad(P), 1)
     gm = jk.grad(P).cpu().numpy()
     jk.close()
     print("grad mol20: %.1f ms |sum g|=%.1e; mixed %.1f ms max|dg|=%.1e |sum g|=%.1e" % (
@@ -381,9 +387,9 @@ def bench_batch(a):
     eris = sum(jk.stats()["eris_sph"] for jk in jks)
     b = Batch(jks)
     b.jk(Ps)
-    ms_batch = _time(lambda: b.jk(Ps), max(1, a.steps))
+    ms_batch = _time(lambda: b.jk(Ps), _xsteps(a))
     lat = np.array(b.latency())
-    ms_seq = _time(lambda: [jk.jk(P) for jk, P in zip(jks, Ps)], max(1, min(a.steps, 3)))
+    ms_seq = _time(lambda: [jk.jk(P) for jk, P in zip(jks, Ps)], _xsteps(a))
     b.close()
     for jk in jks:
         jk.close()
@@ -411,7 +417,10 @@ def main():
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a device-to-device copy of BYTES bytes five times (counter calibration) and exit")
     ap.add_argument("--no-extras", action="store_true",
-                    help="skip the other-precision comparison, the 20-atom gradient and the 64-molecule batch")
+                    help="skip the side measurements (other precision, tm62, gradient, potential, SCF, grid, batch)")
+    ap.add_argument("--only", default=None,
+                    choices=["tm62", "grad", "potential", "scf", "grid", "batch"],
+                    help="run only this side measurement, print its JSON and exit (for profiling one family)")
     a = ap.parse_args()
     if a.gpus != 1:
         print("bench.py measures one GPU: the library has no multi-GPU path; run with --gpus 1",
@@ -428,6 +437,11 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes": a.copy_probe}), flush=True)
+        return
+    if a.only:
+        fn = {"tm62": bench_tm62, "grad": bench_grad, "potential": bench_potential, "scf": bench_scf,
+              "grid": bench_grid, "batch": bench_batch}[a.only]
+        print(json.dumps({a.only: fn(a)}), flush=True)
         return
     from paper_2406_14920_amd import JK, abi, synth
 
