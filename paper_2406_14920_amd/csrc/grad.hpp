@@ -67,6 +67,19 @@ __host__ __device__ constexpr int box_max_ext(int la, int lb)
     return m;
 }
 
+// largest Hermite box of a pair class grown by one along every axis
+__host__ __device__ constexpr int box_max_grown(int la, int lb)
+{
+    int m = 0;
+    for (int ca = 0; ca < ncart(la); ++ca)
+        for (int cb = 0; cb < ncart(lb); ++cb) {
+            const int v = (cart_x(la, ca) + cart_x(lb, cb) + 2) * (cart_y(la, ca) + cart_y(lb, cb) + 2) *
+                          (cart_z(la, ca) + cart_z(lb, cb) + 2);
+            if (v > m) m = v;
+        }
+    return m;
+}
+
 __device__ __forceinline__ double dcoef(const double *E, int DI, int DJ, int i, int j, int t, double a2)
 {
     double v = a2 * E[(i + 1) * DI + j * DJ + t];
@@ -225,68 +238,53 @@ __global__ __launch_bounds__(64) void kg_wave(KGArgs g)
                             }
                             const double *Ex = sEb, *Ey = sEb + C::EBD, *Ez = sEb + 2 * C::EBD;
                             const int ex_ = ax + bx, ey_ = ay + by, ez_ = az + bz;
-                            // d/dA: boxes extended by one along the derivative axis, each
-                            // walked in one flat loop of the class's largest extended box
-                            constexpr int BBM = box_max_ext(LA, LB);
-                            for (int k = 0; k < 3; ++k) {
-                                double s = 0.0;
-                                const int mx = ex_ + 1 + (k == 0), my = ey_ + 1 + (k == 1), mz = ez_ + 1 + (k == 2);
-                                const int nbox = mx * my * mz;
-                                int tx = 0, ty = 0, tz = 0;
-                                for (int st = 0; st < BBM; ++st) {
-                                    if (st < nbox) {
-                                        const double fx = k == 0 ? dcoef(Ex, C::EBI, C::EBJ, ax, bx, tx, a2)
-                                                                 : Ex[ax * C::EBI + bx * C::EBJ + tx];
-                                        const double fy = k == 1 ? dcoef(Ey, C::EBI, C::EBJ, ay, by, ty, a2)
-                                                                 : Ey[ay * C::EBI + by * C::EBJ + ty];
-                                        const double fz = k == 2 ? dcoef(Ez, C::EBI, C::EBJ, az, bz, tz, a2)
-                                                                 : Ez[az * C::EBI + bz * C::EBJ + tz];
-                                        const double *xr = sX + herm_idx_rt(tx, ty, tz);
-                                        double acc = 0.0;
+                            const int ox = ax * C::EBI + bx * C::EBJ, oy = ay * C::EBI + by * C::EBJ,
+                                      oz = az * C::EBI + bz * C::EBJ;
+                            // One pass over the lane's Hermite box grown by one along
+                            // every axis: each index t gets its weighted ket sum
+                            //     z_t = sum_c w_c X_t(c)
+                            // once, shared by the three d/dA terms (derivative
+                            // coefficient along k times E along the other two) and the
+                            // three (d/dA + d/dB) terms (E at t - 1_k).  E vanishes past
+                            // the box, so indices beyond it along two axes carry no term
+                            // and are skipped.  Walked as one flat loop of the class's
+                            // largest grown box.
+                            constexpr int UBM = box_max_grown(LA, LB);
+                            const int mx = ex_ + 2, my = ey_ + 2, mz = ez_ + 2, nbox = mx * my * mz;
+                            int tx = 0, ty = 0, tz = 0;
+                            for (int st = 0; st < UBM; ++st) {
+                                if (st < nbox && (tx > ex_) + (ty > ey_) + (tz > ez_) <= 1) {
+                                    const double *xr = sX + herm_idx_rt(tx, ty, tz);
+                                    double z = 0.0;
 #pragma unroll
-                                        for (int c = 0; c < CDCH; ++c) acc += wv[c] * xr[c * NHX];
-                                        s += fx * fy * fz * acc;
-                                    }
-                                    if (++tz == mz) {
-                                        tz = 0;
-                                        if (++ty == my) {
-                                            ty = 0;
-                                            ++tx;
-                                        }
-                                    }
-                                }
-                                gA[k] += s;
-                            }
-                            // (d/dA + d/dB) by the index shift, d/dC from Xc
-                            {
-                                constexpr int BM = box_max(LA, LB, 0, NAB);
-                                const int mx = ex_ + 1, my = ey_ + 1, mz = ez_ + 1, nbox = mx * my * mz;
-                                int tx = 0, ty = 0, tz = 0;
-                                for (int st = 0; st < BM; ++st) {
-                                    if (st < nbox) {
-                                        const double e = Ex[ax * C::EBI + bx * C::EBJ + tx] *
-                                                         Ey[ay * C::EBI + by * C::EBJ + ty] *
-                                                         Ez[az * C::EBI + bz * C::EBJ + tz];
+                                    for (int c = 0; c < CDCH; ++c) z += wv[c] * xr[c * NHX];
+                                    const double e0 = Ex[ox + tx], e1 = Ey[oy + ty], e2 = Ez[oz + tz];
+                                    const double d0 = dcoef(Ex, C::EBI, C::EBJ, ax, bx, tx, a2);
+                                    const double d1 = dcoef(Ey, C::EBI, C::EBJ, ay, by, ty, a2);
+                                    const double d2 = dcoef(Ez, C::EBI, C::EBJ, az, bz, tz, a2);
+                                    gA[0] += d0 * e1 * e2 * z;
+                                    gA[1] += e0 * d1 * e2 * z;
+                                    gA[2] += e0 * e1 * d2 * z;
+                                    if (tx > 0) gS[0] += Ex[ox + tx - 1] * e1 * e2 * z;
+                                    if (ty > 0) gS[1] += e0 * Ey[oy + ty - 1] * e2 * z;
+                                    if (tz > 0) gS[2] += e0 * e1 * Ez[oz + tz - 1] * z;
+                                    if (tx <= ex_ && ty <= ey_ && tz <= ez_) {  // d/dC from Xc
                                         const int it = herm_idx_rt(tx, ty, tz);
-                                        const int sh[3] = {herm_idx_rt(tx + 1, ty, tz), herm_idx_rt(tx, ty + 1, tz),
-                                                           herm_idx_rt(tx, ty, tz + 1)};
-                                        for (int k = 0; k < 3; ++k) {
-                                            double as = 0.0, ac = 0.0;
+                                        const double e = e0 * e1 * e2;
 #pragma unroll
-                                            for (int c = 0; c < CDCH; ++c) {
-                                                as += wv[c] * sX[c * NHX + sh[k]];
-                                                ac += wv[c] * sXc[(k * CDCH + c) * NHC + it];
-                                            }
-                                            gS[k] += e * as;
+                                        for (int k = 0; k < 3; ++k) {
+                                            double ac = 0.0;
+#pragma unroll
+                                            for (int c = 0; c < CDCH; ++c) ac += wv[c] * sXc[(k * CDCH + c) * NHC + it];
                                             gC[k] += e * ac;
                                         }
                                     }
-                                    if (++tz == mz) {
-                                        tz = 0;
-                                        if (++ty == my) {
-                                            ty = 0;
-                                            ++tx;
-                                        }
+                                }
+                                if (++tz == mz) {
+                                    tz = 0;
+                                    if (++ty == my) {
+                                        ty = 0;
+                                        ++tx;
                                     }
                                 }
                             }
