@@ -131,7 +131,7 @@ int jeng_default_chunk(int lx, int ly, int npp, int ncp)
 }
 
 // ---------------------------------------------------------------------------
-// Boys table: F_m(i h) for m < kBoysNM.  For each grid point the top order
+// Boys table: F_m(i h) for m < kBoysNM, then e^{-i h}.  For each grid point the top order
 // (m = 60) is summed from its Kummer series e^{-T} sum_k (2T)^k/(2m+1)...(2m+2k+1)
 // in long double, then every lower order follows from the downward recursion
 // F_m = (2T F_{m+1} + e^{-T})/(2m+1), which is stable.
@@ -142,7 +142,7 @@ const std::vector<double> &boys_table()
     static std::once_flag once;
     std::call_once(once, [] {
         const int top = 60;
-        tab.assign((size_t)kBoysNG * kBoysNM, 0.0);
+        tab.assign((size_t)kBoysNG * kBoysNC, 0.0);
         for (int i = 0; i < kBoysNG; ++i) {
             long double T = (long double)i * (long double)kBoysH;
             long double eT = expl(-T);
@@ -155,8 +155,9 @@ const std::vector<double> &boys_table()
             long double F = eT * sum;
             for (int m = top - 1; m >= 0; --m) {
                 F = (2.0L * T * F + eT) / (long double)(2 * m + 1);
-                if (m < kBoysNM) tab[(size_t)i * kBoysNM + m] = (double)F;
+                if (m < kBoysNM) tab[(size_t)i * kBoysNC + m] = (double)F;
             }
+            tab[(size_t)i * kBoysNC + kBoysNM] = (double)eT;
         }
     });
     return tab;

@@ -110,15 +110,34 @@ static_assert(sizeof(CPair) == 32, "CPair must be 32 bytes");
 
 // ---------------------------------------------------------------------------
 // Boys function table: F_m(T_i) on T_i = i*h, i = 0..kBoysNG-1, m = 0..kBoysNM-1,
-// row-major [i][m].  Taylor expansion around the nearest grid point
-// (dF_m/dT = -F_{m+1}) with kBoysK terms, then downward recursion; beyond
-// kBoysTmax the asymptotic F_0 = sqrt(pi/T)/2 and upward recursion.
+// row-major [i][m] with row stride kBoysNC; column kBoysNM of a row holds
+// e^{-T_i}.  Taylor expansion around the nearest grid point (dF_m/dT =
+// -F_{m+1}) with kBoysK terms, then downward recursion with
+// e^{-T} = e^{-T_i} e^{T_i - T} (the last factor a Taylor polynomial, the step
+// being at most h/2); beyond kBoysTmax the asymptotic F_0 = sqrt(pi/T)/2 and
+// upward recursion.
 // ---------------------------------------------------------------------------
 constexpr double kBoysH = 0.1;
 constexpr double kBoysTmax = 40.0;
 constexpr int kBoysNG = 402;
 constexpr int kBoysK = 8;
 constexpr int kBoysNM = 24;  // orders available in the table (m + kBoysK - 1 < kBoysNM)
+constexpr int kBoysNC = kBoysNM + 1;  // row stride: the orders, then e^{-T_i}
+
+// e^x for |x| <= h/2 = 0.05: degree-8 Taylor polynomial, relative error
+// below 0.05^9/9! ~ 5e-18
+__device__ __forceinline__ double exp_small(double x)
+{
+    double s = 1.0 / 40320.0;
+    s = 1.0 / 5040.0 + x * s;
+    s = 1.0 / 720.0 + x * s;
+    s = 1.0 / 120.0 + x * s;
+    s = 1.0 / 24.0 + x * s;
+    s = 1.0 / 6.0 + x * s;
+    s = 0.5 + x * s;
+    s = 1.0 + x * s;
+    return 1.0 + x * s;
+}
 
 // All orders 0..M for a compile-time M.
 template <int M>
@@ -127,13 +146,13 @@ __device__ __forceinline__ void boys_all(double T, double *F, const double *__re
     if (T < kBoysTmax) {
         int i = (int)(T * (1.0 / kBoysH) + 0.5);
         double x = (double)i * kBoysH - T;  // step from the grid point, |x| <= h/2
-        const double *row = tab + i * kBoysNM + M;
+        const double *row = tab + i * kBoysNC + M;
         double s = row[kBoysK - 1];
 #pragma unroll
         for (int k = kBoysK - 2; k >= 0; --k) s = row[k] + s * x * (1.0 / (k + 1));
         F[M] = s;
         if (M > 0) {
-            double e = exp(-T);
+            const double e = tab[i * kBoysNC + kBoysNM] * exp_small(x);
             double T2 = 2.0 * T;
 #pragma unroll
             for (int m = M - 1; m >= 0; --m) F[m] = (T2 * F[m + 1] + e) * (1.0 / (2 * m + 1));
@@ -156,7 +175,7 @@ __device__ __forceinline__ double boys_one(int m, double T, const double *__rest
     if (T < kBoysTmax) {
         int i = (int)(T * (1.0 / kBoysH) + 0.5);
         double x = (double)i * kBoysH - T;
-        const double *row = tab + i * kBoysNM + m;
+        const double *row = tab + i * kBoysNC + m;
         double s = row[kBoysK - 1];
 #pragma unroll
         for (int k = kBoysK - 2; k >= 0; --k) s = row[k] + s * x * (1.0 / (k + 1));

@@ -120,7 +120,9 @@ __device__ __forceinline__ void quartet_fs(const PrimPair &pb, const PrimPair &p
                                            double om2)
 {
     double p = pb.p, q = pk.p;
-    double rpq = 1.0 / (p + q);
+    // 1/sqrt(p+q) once; 1/(pq) from the stored 1/(2p), 1/(2q): no division
+    const double rs = rsqrt(p + q);
+    const double rpq = rs * rs;
     double alpha = p * q * rpq;
     const double dx = pb.P[0] - pk.P[0];
     const double dy = pb.P[1] - pk.P[1];
@@ -128,7 +130,7 @@ __device__ __forceinline__ void quartet_fs(const PrimPair &pb, const PrimPair &p
     X = (T)dx;
     Y = (T)dy;
     Z = (T)dz;
-    double pref = kTwoPi52 * pb.K * pk.K / (p * q) * sqrt(rpq);
+    double pref = kTwoPi52 * pb.K * pk.K * (4.0 * pb.o2p * pk.o2p) * rs;
     longrange_scale(om2, alpha, pref);
     double Tb = alpha * (dx * dx + dy * dy + dz * dz);
     double F[L + 1];
@@ -163,12 +165,13 @@ __device__ __forceinline__ void quartet_fs_scaled(const PrimPair &pb, const Prim
                                                   float &Y, float &Z, float &r, double om2)
 {
     const double p = pb.p, q = pk.p;
-    const double rpq = 1.0 / (p + q);
+    const double rs = rsqrt(p + q);
+    const double rpq = rs * rs;
     double alpha = p * q * rpq;
     const double dx = pb.P[0] - pk.P[0];
     const double dy = pb.P[1] - pk.P[1];
     const double dz = pb.P[2] - pk.P[2];
-    double s = kTwoPi52 / (p * q) * sqrt(rpq);
+    double s = kTwoPi52 * (4.0 * pb.o2p * pk.o2p) * rs;
     double w = -q * rpq;
     if (om2 > 0.0) {
         const double s0 = om2 / (alpha + om2);

@@ -41,13 +41,14 @@ __device__ __forceinline__ QuartetGeo quartet_geo(const PrimPair &pb, const Prim
 {
     QuartetGeo g;
     double p = pb.p, q = pk.p;
-    double rpq = 1.0 / (p + q);
+    const double rs = rsqrt(p + q);  // 1/(pq) from the stored 1/(2p), 1/(2q)
+    double rpq = rs * rs;
     g.alpha = p * q * rpq;
     g.X = pb.P[0] - pk.P[0];
     g.Y = pb.P[1] - pk.P[1];
     g.Z = pb.P[2] - pk.P[2];
     g.T = g.alpha * (g.X * g.X + g.Y * g.Y + g.Z * g.Z);
-    g.pref0 = kTwoPi52 / (p * q) * sqrt(rpq);
+    g.pref0 = kTwoPi52 * (4.0 * pb.o2p * pk.o2p) * rs;
     g.w = -q * rpq;
     if (om2 > 0.0) {  // long-range operator (eq. eri_longrange_formula)
         const double s0 = om2 / (g.alpha + om2);
@@ -65,13 +66,14 @@ __device__ __forceinline__ QuartetGeo quartet_geo(const PrimPair &pb, const Prim
 // The fields of a ket primitive pair that a quartet needs, loaded one by one
 // (a loop-carried copy of the whole record would live in scratch memory).
 struct PairLite {
-    double p, K, q, P0, P1, P2;
+    double p, K, q, P0, P1, P2, o2p;
 };
 
 __device__ __forceinline__ PairLite pair_lite(const PrimPair *__restrict__ r)
 {
     PairLite x;
     x.p = r->p;
+    x.o2p = r->o2p;
     x.K = r->K;
     x.q = r->q;
     x.P0 = r->P[0];
@@ -84,13 +86,14 @@ __device__ __forceinline__ QuartetGeo quartet_geo(const PrimPair &pb, const Pair
 {
     QuartetGeo g;
     double p = pb.p, q = pk.p;
-    double rpq = 1.0 / (p + q);
+    const double rs = rsqrt(p + q);
+    double rpq = rs * rs;
     g.alpha = p * q * rpq;
     g.X = pb.P[0] - pk.P0;
     g.Y = pb.P[1] - pk.P1;
     g.Z = pb.P[2] - pk.P2;
     g.T = g.alpha * (g.X * g.X + g.Y * g.Y + g.Z * g.Z);
-    g.pref0 = kTwoPi52 / (p * q) * sqrt(rpq);
+    g.pref0 = kTwoPi52 * (4.0 * pb.o2p * pk.o2p) * rs;
     g.w = -q * rpq;
     if (om2 > 0.0) {  // long-range operator (eq. eri_longrange_formula)
         const double s0 = om2 / (g.alpha + om2);

@@ -223,3 +223,24 @@ def test_mixed_precision_gradient(case):
     assert np.abs(gm.sum(0)).max() <= 1e-9
     if case == "mol4":
         assert np.abs(gm - oracle.grad(mol)).max() <= 1e-6
+
+
+def test_mol20_rows_vs_oracle():
+    """The 20-atom gradient workload at full size against the oracle's rows
+    for atoms 0, 9 and 19 (tests/golden/mol20_grad_rows.json, written by
+    tests/golden/make_grad_rows.py from the oracle alone; Schwarz 1e-11, no
+    primitive screen on either side): 1e-10 max|g| + 1e-12."""
+    import json
+    import os
+    torch = _torch()
+    path = os.path.join(os.path.dirname(__file__), "golden", "mol20_grad_rows.json")
+    ref = json.load(open(path))
+    mol = synth.mol20()
+    jk = _ctx(mol, tau=ref["schwarz_thresh"], tau_prim=ref["prim_thresh"])
+    P = torch.tensor(mol.P, dtype=torch.float64, device="cuda")
+    g = jk.grad(P).cpu().numpy()
+    scale = np.abs(g).max()
+    for atom, row in ref["rows"].items():
+        d = np.abs(g[int(atom)] - np.array(row)).max()
+        print("  atom %s max|d| %.2e (scale %.2e)" % (atom, d, scale), flush=True)
+        assert d <= 1e-10 * scale + 1e-12, (atom, g[int(atom)], row)
