@@ -137,10 +137,11 @@ def compare_precision(jk, P, J, K, a, st):
     jk.set_precision(a.precision)
     dJ = float((J1 - J0).abs().max())
     dK = float((K1 - K0).abs().max())
+    dE = abs(float(jk.energy(P, J1, K1)) - float(jk.energy(P, J0, K0)))
     mixed_st = s2 if other == "mixed" else st
-    print("compare %s: %.1f ms dJ=%.2e dK=%.2e" % (other, ms, dJ, dK), file=sys.stderr, flush=True)
+    print("compare %s: %.1f ms dJ=%.2e dK=%.2e dE=%.2e" % (other, ms, dJ, dK, dE), file=sys.stderr, flush=True)
     return {"precision": other, "ms_per_step": ms, "value": st["eris_sph"] / (ms / 1e3),
-            "max_abs_dJ_vs_fp64": dJ, "max_abs_dK_vs_fp64": dK,
+            "max_abs_dJ_vs_fp64": dJ, "max_abs_dK_vs_fp64": dK, "abs_dE_vs_fp64": dE,
             "fp32_quartet_fraction": mixed_st["n_quartets_fp32"] / max(1, st["n_quartets"]),
             "mixed_thresh": 1e-5}
 
