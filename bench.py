@@ -375,9 +375,18 @@ def bench_grid(a):
             "points_per_s_density": pts.shape[0] / (ms_rho * 1e-3), "integrated_electrons": n_el}
 
 
+def _lat(b):
+    lat = np.array(b.latency())
+    return {"min": float(lat.min()), "median": float(np.median(lat)), "p90": float(np.percentile(lat, 90)),
+            "max": float(lat.max())}
+
+
 def bench_batch(a):
-    """64 molecules of 5-30 atoms built as one batch (molecules on concurrent
-    streams), against the same molecules built one after another."""
+    """64 molecules of 5-30 atoms built as one batch: queue mode (one
+    launch per kernel over every molecule's blocks) and streams
+    mode (molecules on concurrent streams), against the same molecules built
+    one after another; and mol40 alone as a batch of one in queue mode
+    against its own build_jk."""
     import torch
     from paper_2406_14920_amd import JK, Batch, synth
     mols = synth.batch64()
@@ -386,25 +395,48 @@ def bench_batch(a):
     setup_s = time.perf_counter() - t0
     Ps = [torch.tensor(m.P, dtype=torch.float64, device="cuda") for m in mols]
     eris = sum(jk.stats()["eris_sph"] for jk in jks)
-    b = Batch(jks)
+    b = Batch(jks, mode="queue")
+    t0 = time.perf_counter()
     b.jk(Ps)
-    ms_batch = _time(lambda: b.jk(Ps), _xsteps(a))
-    lat = np.array(b.latency())
+    torch.cuda.synchronize()
+    plan_s = time.perf_counter() - t0
+    info = b.queue_info()
+    ms_queue = _time(lambda: b.jk(Ps), _xsteps(a))
+    lat_queue = _lat(b)
+    b.set_mode("streams")
+    b.jk(Ps)
+    ms_streams = _time(lambda: b.jk(Ps), _xsteps(a))
+    lat_streams = _lat(b)
     ms_seq = _time(lambda: [jk.jk(P) for jk, P in zip(jks, Ps)], _xsteps(a))
     b.close()
     for jk in jks:
         jk.close()
-    print("batch64: batch %.1f ms, one by one %.1f ms (setup %.1fs)" % (ms_batch, ms_seq, setup_s),
+    print("batch64: queue %.1f ms, streams %.1f ms, one by one %.1f ms (setup %.1fs, first queue call %.1fs)"
+          % (ms_queue, ms_streams, ms_seq, setup_s, plan_s), file=sys.stderr, flush=True)
+    m40 = synth.mol40()
+    jk40 = JK.from_molecule(m40)
+    P40 = torch.tensor(m40.P, dtype=torch.float64, device="cuda")
+    b1 = Batch([jk40], mode="queue")
+    b1.jk([P40])
+    ms40_queue = _time(lambda: b1.jk([P40]), _xsteps(a))
+    info40 = b1.queue_info()
+    ms40_direct = _time(lambda: jk40.jk(P40), _xsteps(a))
+    b1.close()
+    jk40.close()
+    print("mol40: queue (batch of one) %.1f ms, build_jk %.1f ms" % (ms40_queue, ms40_direct),
           file=sys.stderr, flush=True)
     return {"workload": "64 molecules of 5-30 atoms (mol40 shell set), FP64", "molecules": len(mols),
             "nbf_range": [min(m.nbf for m in mols), max(m.nbf for m in mols)],
-            "ms_per_batch": ms_batch, "ms_per_batch_one_by_one": ms_seq,
-            "eris_per_s_batch": eris / (ms_batch / 1e3),
-            "per_molecule_latency_ms": {"min": float(lat.min()), "median": float(np.median(lat)),
-                                        "p90": float(np.percentile(lat, 90)), "max": float(lat.max())},
+            "ms_per_batch": ms_queue, "eris_per_s_batch": eris / (ms_queue / 1e3),
+            "launch": "queue mode: one launch per kernel over the blocks of all 64 molecules, "
+                      "launches with the most work per block first",
+            "queue_plan": {"launches": info["launches"], "items": info["items"], "first_call_s": plan_s},
+            "per_molecule_latency_ms": lat_queue,
+            "ms_per_batch_streams": ms_streams, "per_molecule_latency_ms_streams": lat_streams,
+            "ms_per_batch_one_by_one": ms_seq,
             "latency_of": "last timed call, from its start to each molecule's completion (HIP events)",
-            "launch": "direct launches on 8 concurrent streams, largest molecule first onto the least-loaded "
-                      "stream (graph recording switched off)"}
+            "mol40_as_batch_of_one": {"queue_ms": ms40_queue, "build_jk_ms": ms40_direct,
+                                      "queue_launches": info40["launches"], "queue_items": info40["items"]}}
 
 
 def main():

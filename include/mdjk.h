@@ -352,23 +352,48 @@ int eri_set_tuning(eri_ctx *ctx, const eri_tuning_t *in);
  * before the work queued after it.  The contexts stay owned by the caller and
  * must outlive the batch.
  * eri_batch_build_jk: P, J, K are host arrays of n device pointers
- * (nbf_i x nbf_i each, as in build_jk; none NULL).  Every molecule's build
- * is forked from the batch stream onto one of up to 8 batch streams and
- * joined back, so molecules run concurrently.  (The library also holds a
- * path that records the whole batch into one HIP graph and replays it; it is
- * switched off in this build after host-side crashes of the recorded batch
- * on the MI355X runtime.)  Results equal those of build_jk on each context
- * (up to the order of floating-point atomic additions).  Asynchronous on the
- * batch stream. */
+ * (nbf_i x nbf_i each, as in build_jk; none NULL).  Results equal those of
+ * build_jk on each context (up to the order of floating-point atomic
+ * additions).  Asynchronous on the batch stream.  Two ways to run it
+ * (eri_batch_set_mode):
+ *  - ERI_BATCH_QUEUE (the default; used when every context is in ERI_FP64,
+ *    else the batch runs as ERI_BATCH_STREAMS): the J-engine and exchange
+ *    work of all molecules runs as ONE launch per kernel (angular class):
+ *    the blocks every molecule's own launch would have had become the items
+ *    of a device-side work list, the launches with the most work per block
+ *    first, and workgroup b runs item b, so the hardware dispatcher hands
+ *    the long items out first and fills the tail with the short ones (the
+ *    paper's kernels are one launch per class and molecule, section
+ *    "Implementation").  The plan
+ *    (argument tables and item lists, on the device) is made on the first
+ *    call and again after any context changes (precision, geometry, screen,
+ *    tuning): that call allocates and copies; later calls launch kernels
+ *    only, all on the batch stream, so a call after the first can be
+ *    captured into a HIP graph.
+ *  - ERI_BATCH_STREAMS: every molecule's build_jk is forked from the batch
+ *    stream onto one of up to 8 batch streams and joined back, so molecules
+ *    run concurrently.
+ * (The library also holds a path that records the streams form into one HIP
+ * graph itself; it is switched off in this build after host-side crashes of
+ * that recording on the MI355X runtime.) */
 typedef struct eri_batch eri_batch;
 int eri_batch_create(eri_ctx *const *ctxs, int32_t n, void *stream, eri_batch **out);
 int eri_batch_build_jk(eri_batch *b, const double *const *P, double *const *J, double *const *K);
+#define ERI_BATCH_QUEUE   0
+#define ERI_BATCH_STREAMS 1
+/* Select how eri_batch_build_jk runs (ERI_EINVAL for another value). */
+int eri_batch_set_mode(eri_batch *b, int32_t mode);
+/* Launches per queue build and the items (blocks) they run in total, of the
+ * current plan.  ERI_ESTATE before the first queue build. */
+int eri_batch_queue_info(eri_batch *b, int32_t *launches, int64_t *items);
 /* Per-molecule latency of the last eri_batch_build_jk: ms[i] = device time
  * from the start of that call on the batch stream to the end of molecule i's
  * build (HIP events on its batch stream), for the first n molecules.
  * Molecules are issued largest first (by the spherical ERIs of their unique
- * quartets), each onto the least-loaded of the batch streams.  Synchronises
- * with those events.  ERI_ESTATE before the first batch build. */
+ * quartets), in the streams mode each onto the least-loaded of the batch
+ * streams; in the queue mode every molecule finishes after the shared
+ * batch launches, with its output transforms.  Synchronises with those
+ * events.  ERI_ESTATE before the first batch build. */
 int eri_batch_latency(eri_batch *b, float *ms, int32_t n);
 
 int eri_batch_destroy(eri_batch *b);

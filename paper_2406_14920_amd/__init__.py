@@ -220,17 +220,23 @@ class JK:
 
 
 class Batch:
-    """Many JK contexts built together (eri_batch_*): every molecule's build
-    forked from the batch stream onto one of a few streams, largest first,
-    and joined back.  Output tensors are allocated once and reused."""
+    """Many JK contexts built together (eri_batch_*).  mode "queue" (the
+    default; double-precision contexts): one launch per kernel for the whole
+    batch, whose workgroups run the blocks of every molecule's launch from a
+    device-side work list, most work first; mode "streams": every molecule's build forked from the batch
+    stream onto one of a few streams, largest first, and joined back.
+    Output tensors are allocated once and reused."""
 
-    def __init__(self, jks, stream=None):
+    MODES = {"queue": abi.ERI_BATCH_QUEUE, "streams": abi.ERI_BATCH_STREAMS}
+
+    def __init__(self, jks, stream=None, mode: str = "queue"):
         import torch
         self.jks = list(jks)
         if stream is None:
             stream = torch.cuda.current_stream()
         self.stream = stream
         self.handle = abi.eri_batch_create([j.ctx for j in self.jks], int(stream.cuda_stream))
+        self.set_mode(mode)
         self.J = [torch.empty((j.nbf, j.nbf), dtype=torch.float64, device="cuda") for j in self.jks]
         self.K = [torch.empty((j.nbf, j.nbf), dtype=torch.float64, device="cuda") for j in self.jks]
 
@@ -249,6 +255,16 @@ class Batch:
         """Per-molecule completion times (ms) of the last jk() call, from
         its start on the batch stream (eri_batch_latency)."""
         return abi.eri_batch_latency(self.handle, len(self.jks))
+
+    def set_mode(self, mode: str):
+        if mode not in self.MODES:
+            raise ValueError("mode must be one of %s" % sorted(self.MODES))
+        abi.eri_batch_set_mode(self.handle, self.MODES[mode])
+        self.mode = mode
+
+    def queue_info(self) -> dict:
+        """Launches per build and work items of the current queue plan."""
+        return abi.eri_batch_queue_info(self.handle)
 
     def close(self):
         if getattr(self, "handle", None):

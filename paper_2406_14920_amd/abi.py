@@ -68,7 +68,11 @@ EXPORTS = ["eri_default_opts", "eri_setup", "eri_nbf", "eri_set_geometry", "eri_
            "eri_last_error", "eri_batch_create", "eri_batch_build_jk", "eri_batch_destroy",
            "eri_autotune", "eri_tuning", "build_jk_static", "eri_set_omega", "eri_get_tuning",
            "eri_set_tuning", "eri_potential", "eri_potential_grad", "eri_set_density_screen",
-           "eri_one_electron", "eri_grid_density", "eri_grid_matrix", "eri_batch_latency"]
+           "eri_one_electron", "eri_grid_density", "eri_grid_matrix", "eri_batch_latency",
+           "eri_batch_set_mode", "eri_batch_queue_info"]
+
+ERI_BATCH_QUEUE = 0
+ERI_BATCH_STREAMS = 1
 
 _lib = None
 
@@ -112,6 +116,8 @@ def load(path: str = LIB_PATH):
     L.eri_batch_build_jk.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp)]
     L.eri_batch_destroy.argtypes = [vp]
     L.eri_batch_latency.argtypes = [vp, ctypes.POINTER(ctypes.c_float), ctypes.c_int32]
+    L.eri_batch_set_mode.argtypes = [vp, ctypes.c_int32]
+    L.eri_batch_queue_info.argtypes = [vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64)]
     L.eri_autotune.argtypes = [vp, vp, ctypes.c_int32]
     ip = ctypes.POINTER(ctypes.c_int32)
     L.eri_tuning.argtypes = [vp, ip, ip, ctypes.c_int32, ip]
@@ -339,3 +345,15 @@ def eri_batch_latency(batch: int, n: int) -> list:
     arr = (ctypes.c_float * max(n, 1))()
     _check(load().eri_batch_latency(ctypes.c_void_p(batch), arr, int(n)))
     return [float(arr[i]) for i in range(n)]
+
+
+def eri_batch_set_mode(batch: int, mode: int) -> None:
+    _check(load().eri_batch_set_mode(ctypes.c_void_p(batch), int(mode)))
+
+
+def eri_batch_queue_info(batch: int) -> dict:
+    """Launches and work items of the batch's current queue plan."""
+    n = ctypes.c_int32()
+    m = ctypes.c_int64()
+    _check(load().eri_batch_queue_info(ctypes.c_void_p(batch), ctypes.byref(n), ctypes.byref(m)))
+    return {"launches": int(n.value), "items": int(m.value)}

@@ -20,11 +20,12 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(os.path.dirname(HERE), "_build")
 LIB = os.path.join(HERE, "libmdjk.so")
 
-SOURCES = ["k_small.hip", "k_wave_0.hip", "k_wave_1.hip", "k_wave_2.hip", "k_wave_3.hip",
-           "k_wave_4.hip", "k_wave_5.hip", "k_pair_0.hip", "k_pair_1.hip", "k_pair_2.hip", "k_pair_3.hip", "k_pair_4.hip", "k_pair_5.hip",
-           "k_pair_6.hip", "k_pair_7.hip", "eprod.hip", "jeng.hip", "jeng_reg_0.hip", "jeng_reg_1.hip", "jeng_reg_2.hip",
-           "jeng_reg_3.hip", "kg_0.hip", "kg_1.hip", "kg_2.hip", "kg_3.hip", "grad.hip", "setup.hip", "count.hip", "potential.hip", "grid.hip",
-           "api.cpp"]
+SOURCES = ["jeng_reg_0.hip", "jeng_reg_1.hip", "jeng_reg_2.hip", "jeng_reg_3.hip", "jeng_reg_q_0.hip",
+           "jeng_reg_q_1.hip", "jeng_reg_q_2.hip", "jeng_reg_q_3.hip", "k_pair_6.hip", "k_small.hip", "k_wave_0.hip",
+           "k_wave_1.hip", "k_wave_2.hip", "k_wave_3.hip", "k_wave_4.hip", "k_wave_5.hip", "k_pair_0.hip",
+           "k_pair_1.hip", "k_pair_2.hip", "k_pair_3.hip", "k_pair_4.hip", "k_pair_5.hip", "k_pair_7.hip",
+           "eprod.hip", "jeng.hip", "kg_0.hip", "kg_1.hip", "kg_2.hip", "kg_3.hip", "grad.hip", "setup.hip",
+           "count.hip", "potential.hip", "grid.hip", "api.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-munsafe-fp-atomics",

@@ -34,6 +34,7 @@
 #include "grid.hpp"
 #include "launch.hpp"
 #include "md_common.hpp"
+#include "queue.hpp"
 
 using namespace md;
 
@@ -959,7 +960,8 @@ JArgs j_args(const eri_ctx *c, int X, int Y, bool mixed)
 }
 
 
-void run_j(eri_ctx *c, bool mixed, hipStream_t st)
+// Hermite density of every ket class, Hermite J cleared.
+void j_prologue(eri_ctx *c, bool mixed, hipStream_t st)
 {
     const int nc = c->nbf_cart;
     for (int Y = 0; Y < kPairClasses; ++Y)
@@ -969,6 +971,11 @@ void run_j(eri_ctx *c, bool mixed, hipStream_t st)
                                    mixed ? c->d_Dtf.p + c->dt_off[Y] : nullptr, c->pp_base[Y], st);
         });
     timed(c, st, "fill_zero", -1, 0, 0, [&] { launch_fill_zero(c->wk.Jh, (int64_t)c->d_Jh.n, st); });
+}
+
+// The J-engine launches of every (bra class, ket class).
+void j_classes(eri_ctx *c, bool mixed, hipStream_t st)
+{
     for (int X = 0; X < kPairClasses; ++X) {
         if (c->npp[X] == 0) continue;
         for (int Y = 0; Y < kPairClasses; ++Y) {
@@ -985,6 +992,12 @@ void run_j(eri_ctx *c, bool mixed, hipStream_t st)
             }
         }
     }
+}
+
+// Hermite J to Cartesian J, added into the accumulator.
+void j_epilogue(eri_ctx *c, hipStream_t st)
+{
+    const int nc = c->nbf_cart;
     for (int X = 0; X < kPairClasses; ++X)
         timed(c, st, cls_name("herm2cart", kPairL[X][0], kPairL[X][1], 0, 0), -1, 0, 0, [&] {
             launch_hermite_to_cart(kPairL[X][0], kPairL[X][1], c->d_cp.p + c->cp_base[X], c->ncp[X], c->d_pp.p,
@@ -1065,6 +1078,13 @@ KPArgs kp_args(const KArgs &a, const int4 *chunks)
     return p;
 }
 
+
+void run_j(eri_ctx *c, bool mixed, hipStream_t st)
+{
+    j_prologue(c, mixed, st);
+    j_classes(c, mixed, st);
+    j_epilogue(c, st);
+}
 
 // Range-walking wave classes on stA, bra-shared and small classes on stB.
 void run_k(eri_ctx *c, bool mixed, hipStream_t stA, hipStream_t stB)
@@ -2181,6 +2201,26 @@ struct eri_batch {
     std::vector<int> order, lane_of;
     std::vector<hipEvent_t> tev;
     bool timed_once = false;
+    // queue launches (double-precision batches): one persistent launch per
+    // kernel instantiation over the blocks of every molecule
+    struct QGroup {
+        QueueLaunchFn fn;
+        const char *kind;
+        size_t tab_off;   // bytes into d_qtab
+        size_t item_off;  // into d_qitems
+        int nitems, entries;
+    };
+    int32_t mode = ERI_BATCH_QUEUE;
+    // queue builds fork from the batch stream as build_jk does: J-engine
+    // launches on qaux[0], bra-shared and small exchange launches on qaux[1],
+    // range-walking exchange launches on the batch stream
+    hipStream_t qaux[2] = {nullptr, nullptr};
+    hipEvent_t qev[3] = {nullptr, nullptr, nullptr};  // fork, join J, join small K
+    std::vector<QGroup> qg;
+    DevBuf<unsigned char> d_qtab;
+    DevBuf<int4> d_qitems;
+    std::vector<uint64_t> qgens;
+    bool qplanned = false;
 };
 
 namespace {
@@ -2258,7 +2298,160 @@ void batch_record(eri_batch *b)
     for (size_t i = 0; i < n; ++i) b->gens[i] = b->ctxs[i]->gen;
 }
 
+// Queue plan: every molecule's J-engine and exchange launches (as build_jk
+// would issue them in double precision) are recorded instead of issued and
+// grouped by kernel; each group becomes one launch whose items are the
+// blocks of its molecules' launches, the launches with the most work per
+// block first.  Rebuilt whenever a context changes.
+void batch_plan_queue(eri_batch *b)
+{
+    b->qplanned = false;
+    std::vector<eri_batch::QGroup> groups;
+    std::vector<std::vector<std::pair<int, QueueRec>>> members;
+    std::map<QueueLaunchFn, size_t> index;
+    std::vector<QueueRec> recs;
+    for (const int i : b->order) {
+        eri_ctx *c = b->ctxs[(size_t)i];
+        recs.clear();
+        const bool prof = c->profile;
+        c->profile = false;
+        queue_sink() = &recs;
+        try {
+            j_classes(c, false, nullptr);
+            run_k(c, false, nullptr, nullptr);
+        } catch (...) {
+            queue_sink() = nullptr;
+            c->profile = prof;
+            throw;
+        }
+        queue_sink() = nullptr;
+        c->profile = prof;
+        for (const QueueRec &r : recs) {
+            if (!r.fn) {
+                set_err(ERI_ESTATE, "queue launches serve double-precision builds only (molecule %d)", i);
+                throw HipError{ERI_ESTATE};
+            }
+            auto it = index.find(r.fn);
+            if (it == index.end()) {
+                it = index.emplace(r.fn, groups.size()).first;
+                groups.push_back(eri_batch::QGroup{r.fn, r.kind, 0, 0, 0, 0});
+                members.emplace_back();
+            }
+            members[it->second].emplace_back(i, r);
+        }
+    }
+    std::vector<unsigned char> tab;
+    std::vector<int4> items;
+    for (size_t g = 0; g < groups.size(); ++g) {
+        auto &m = members[g];
+        std::stable_sort(m.begin(), m.end(), [](const std::pair<int, QueueRec> &x, const std::pair<int, QueueRec> &y) {
+            return x.second.work > y.second.work;
+        });
+        eri_batch::QGroup &q = groups[g];
+        tab.resize((tab.size() + 255) / 256 * 256);
+        q.tab_off = tab.size();
+        q.item_off = items.size();
+        int64_t count = 0;
+        for (size_t e = 0; e < m.size(); ++e) {
+            const QueueRec &r = m[e].second;
+            tab.insert(tab.end(), r.args, r.args + r.asize);
+            count += (int64_t)r.gx * r.gy;
+            if (count > (int64_t)INT32_MAX) {
+                set_err(ERI_EINVAL, "batch too large for one queue launch (%s: more than 2^31 blocks)", q.kind);
+                throw HipError{ERI_EINVAL};
+            }
+            for (int by = 0; by < r.gy; ++by)
+                for (int bx = 0; bx < r.gx; ++bx) items.push_back(make_int4((int)e, bx, by, r.gx));
+        }
+        q.nitems = (int)count;
+        q.entries = (int)m.size();
+    }
+    b->d_qtab.alloc(0);
+    b->d_qtab.upload(tab);
+    b->d_qitems.upload(items);
+    b->qg = std::move(groups);
+    b->qgens.resize(b->ctxs.size());
+    for (size_t i = 0; i < b->ctxs.size(); ++i) b->qgens[i] = b->ctxs[i]->gen;
+    b->qplanned = true;
+}
+
+bool batch_queue_ready(const eri_batch *b)
+{
+    if (!b->qplanned) return false;
+    for (size_t i = 0; i < b->ctxs.size(); ++i)
+        if (b->qgens[i] != b->ctxs[i]->gen) return false;
+    return true;
+}
+
+// One batch build with queue launches: every molecule's density transforms
+// on the batch stream, the batch J-engine and exchange launches forked onto
+// three streams as in build_jk and joined back, every molecule's output
+// transforms on the batch stream.
+void batch_build_queue(eri_batch *b, const double *const *P, double *const *J, double *const *K)
+{
+    if (!batch_queue_ready(b)) batch_plan_queue(b);
+    const hipStream_t st = b->st;
+    // under stream capture the timing events are left out (the build is then
+    // a chain of kernel launches only)
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    HIPCHK(hipStreamIsCapturing(st, &cap));
+    const bool timing = cap == hipStreamCaptureStatusNone;
+    if (timing) HIPCHK(hipEventRecord(b->tev[0], st));
+    for (const int i : b->order) {
+        eri_ctx *c = b->ctxs[(size_t)i];
+        const bool prof = c->profile;
+        c->profile = false;
+        const int nc = c->nbf_cart;
+        launch_p_to_cart(P[i], c->nbf, c->wk.Pc, nc, shell_map(c), c->opts.spherical, st);
+        if (c->tau_dens > 0.0)
+            launch_density_bounds(c->wk.Pc, nc, c->d_l.p, c->d_coff.p, c->nshell, c->d_Pm.p, c->d_cp.p, c->d_Q.p,
+                                  (int)c->cp.size(), c->d_QD.p, st);
+        c->built_mixed = false;
+        c->mix_counts_ok = false;
+        launch_fill_zero(c->wk.Jacc, (int64_t)nc * nc, st);
+        launch_fill_zero(c->wk.Kacc, (int64_t)nc * nc, st);
+        j_prologue(c, false, st);
+        c->profile = prof;
+    }
+    HIPCHK(hipEventRecord(b->qev[0], st));
+    HIPCHK(hipStreamWaitEvent(b->qaux[0], b->qev[0], 0));
+    HIPCHK(hipStreamWaitEvent(b->qaux[1], b->qev[0], 0));
+    for (const eri_batch::QGroup &q : b->qg) {
+        const bool jeng = std::strncmp(q.kind, "jeng", 4) == 0;
+        const bool kside = std::strcmp(q.kind, "k_small") == 0 || std::strcmp(q.kind, "k_pair") == 0;
+        const hipStream_t s = jeng ? b->qaux[0] : (kside ? b->qaux[1] : st);
+        q.fn(b->d_qtab.p + q.tab_off, b->d_qitems.p + q.item_off, q.nitems, s);
+    }
+    HIPCHK(hipEventRecord(b->qev[1], b->qaux[0]));
+    HIPCHK(hipEventRecord(b->qev[2], b->qaux[1]));
+    HIPCHK(hipStreamWaitEvent(st, b->qev[1], 0));
+    HIPCHK(hipStreamWaitEvent(st, b->qev[2], 0));
+    for (const int i : b->order) {
+        eri_ctx *c = b->ctxs[(size_t)i];
+        const bool prof = c->profile;
+        c->profile = false;
+        const int nc = c->nbf_cart;
+        const ShellMap m = shell_map(c);
+        j_epilogue(c, st);
+        launch_acc_to_out(c->wk.Jacc, nc, J[i], c->nbf, m, c->opts.spherical, st);
+        launch_acc_to_out(c->wk.Kacc, nc, K[i], c->nbf, m, c->opts.spherical, st);
+        c->profile = prof;
+        if (timing) HIPCHK(hipEventRecord(b->tev[1 + (size_t)i], st));
+    }
+    HIPCHK(hipGetLastError());
+}
+
 }  // namespace
+
+namespace md {
+
+std::vector<QueueRec> *&queue_sink()
+{
+    static thread_local std::vector<QueueRec> *sink = nullptr;
+    return sink;
+}
+
+}  // namespace md
 
 extern "C" {
 
@@ -2270,6 +2463,10 @@ int eri_batch_create(eri_ctx *const *ctxs, int32_t n, void *stream, eri_batch **
     if (!ctxs || n <= 0) return set_err(ERI_EINVAL, "no contexts (n=%d)", n);
     for (int i = 0; i < n; ++i)
         if (!ctx_ok(ctxs[i])) return set_err(ERI_ESTATE, "context %d invalid", i);
+    for (int i = 1; i < n; ++i)
+        if (ctxs[i]->device != ctxs[0]->device)
+            return set_err(ERI_EINVAL, "context %d is on device %d, context 0 on device %d", i, ctxs[i]->device,
+                           ctxs[0]->device);
     std::unique_ptr<eri_batch> b(new (std::nothrow) eri_batch);
     if (!b) return set_err(ERI_ENOMEM, "host allocation failed");
     try {
@@ -2285,6 +2482,8 @@ int eri_batch_create(eri_ctx *const *ctxs, int32_t n, void *stream, eri_batch **
         for (auto &e : b->evs) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
         b->tev.resize(1 + (size_t)n);
         for (auto &e : b->tev) HIPCHK(hipEventCreate(&e));
+        for (auto &s : b->qaux) HIPCHK(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+        for (auto &e : b->qev) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
         // largest molecules first, each onto the least-loaded lane (cost: the
         // spherical ERIs its unique quartets represent)
         b->order.resize(n);
@@ -2315,6 +2514,19 @@ int eri_batch_build_jk(eri_batch *b, const double *const *P, double *const *J, d
         if (!P[i] || !J[i] || !K[i]) return set_err(ERI_EINVAL, "null P/J/K for molecule %zu", i);
     }
     try {
+        bool queue = b->mode == ERI_BATCH_QUEUE;
+        for (size_t i = 0; queue && i < n; ++i)
+            if (b->ctxs[i]->opts.precision != ERI_FP64) queue = false;
+        if (queue) {
+            hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+            HIPCHK(hipStreamIsCapturing(b->st, &cap));
+            if (cap != hipStreamCaptureStatusNone && !batch_queue_ready(b))
+                return set_err(ERI_ESTATE, "batch queue plan must be made before stream capture (run one build "
+                                           "outside the capture after each context change)");
+            batch_build_queue(b, P, J, K);
+            if (cap == hipStreamCaptureStatusNone) b->timed_once = true;
+            return ERI_OK;
+        }
         if (kBatchGraphs) {
             bool same = b->exec != nullptr && b->P.size() == n;
             for (size_t i = 0; same && i < n; ++i)
@@ -2354,6 +2566,26 @@ int eri_batch_build_jk(eri_batch *b, const double *const *P, double *const *J, d
     return ERI_OK;
 }
 
+int eri_batch_set_mode(eri_batch *b, int32_t mode)
+{
+    if (!batch_ok(b)) return set_err(ERI_ESTATE, "invalid batch");
+    if (mode != ERI_BATCH_QUEUE && mode != ERI_BATCH_STREAMS) return set_err(ERI_EINVAL, "unknown batch mode %d", mode);
+    b->mode = mode;
+    return ERI_OK;
+}
+
+int eri_batch_queue_info(eri_batch *b, int32_t *launches, int64_t *items)
+{
+    if (!batch_ok(b)) return set_err(ERI_ESTATE, "invalid batch");
+    if (!launches || !items) return set_err(ERI_EINVAL, "null output");
+    if (!b->qplanned) return set_err(ERI_ESTATE, "no queue build has run on this batch yet");
+    *launches = (int32_t)b->qg.size();
+    int64_t s = 0;
+    for (const auto &q : b->qg) s += q.nitems;
+    *items = s;
+    return ERI_OK;
+}
+
 int eri_batch_latency(eri_batch *b, float *ms, int32_t n)
 {
     if (!batch_ok(b)) return set_err(ERI_ESTATE, "invalid batch");
@@ -2379,6 +2611,10 @@ int eri_batch_destroy(eri_batch *b)
     for (auto &e : b->evs) (void)hipEventDestroy(e);
     for (auto &e : b->tev) (void)hipEventDestroy(e);
     for (auto &s : b->lanes) (void)hipStreamDestroy(s);
+    for (auto &e : b->qev)
+        if (e) (void)hipEventDestroy(e);
+    for (auto &s : b->qaux)
+        if (s) (void)hipStreamDestroy(s);
     b->magic = 0;
     delete b;
     return ERI_OK;

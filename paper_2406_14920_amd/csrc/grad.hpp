@@ -33,6 +33,14 @@
 
 namespace md {
 
+// LDS bytes of kg_wave's tables with a ket chunk of c components (the
+// natom x 3 partials come on top)
+__host__ __device__ constexpr int kg_lds_bytes(int L, int NR0, int EBD, int EKD, int NHX, int NHC, int ND_, int c)
+{
+    return 8 * (NR0 + (L + 2) + 3 * (L + 2) * ((L + 1) / 2 + 1) + 3 * EBD + 3 * EKD + c * NHX + 3 * c * NHC + ND_) +
+           4 * nherm(L + 1);
+}
+
 template <int LA, int LB, int LC, int LD>
 struct KGCfg {
     static constexpr int NA = ncart(LA), NB = ncart(LB), NC = ncart(LC), ND = ncart(LD);
@@ -41,12 +49,18 @@ struct KGCfg {
     static constexpr int L2 = L + 2;                 // dense R table side (orders up to L+1)
     static constexpr int NR0 = L2 * L2 * L2;
     static constexpr int NHX = nherm(LAB + 1), NHC = nherm(LAB);
-    static constexpr int CDCH = NCD < 16 ? NCD : 16;
     static constexpr int NABCH = (NAB + 63) / 64;
     // 1D tables [i][j][t]: bra i <= LA+1, j <= LB, t <= LAB+1; ket i <= LC+1, j <= LD, t <= LCD+1
     static constexpr int EBJ = LAB + 2, EBI = (LB + 1) * EBJ, EBD = (LA + 2) * EBI;
     static constexpr int EKJ = LCD + 2, EKI = (LD + 1) * EKJ, EKD = (LC + 2) * EKI;
     static constexpr int ND_ = NA * NC + NA * ND + NB * NC + NB * ND;
+    // ket components per chunk: the largest of 16, 8, 4 whose tables fit in
+    // 40 KB of LDS, so that four of these one-wave workgroups share a compute
+    // unit (one per SIMD; the largest classes hold 256 VGPRs, one wave per SIMD)
+    static constexpr int CDCH0 = kg_lds_bytes(L, NR0, EBD, EKD, NHX, NHC, ND_, 16) <= 40960  ? 16
+                                 : kg_lds_bytes(L, NR0, EBD, EKD, NHX, NHC, ND_, 8) <= 40960 ? 8
+                                                                                             : 4;
+    static constexpr int CDCH = NCD < CDCH0 ? NCD : CDCH0;
     static constexpr int RANGE = 4;
 };
 

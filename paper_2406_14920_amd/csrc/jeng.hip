@@ -11,6 +11,7 @@
 // build R in LDS with one wavefront per bra primitive pair.
 #include "kern_args.hpp"
 #include "md_device.hpp"
+#include "queue.hpp"
 #include "wave_r.hpp"
 
 namespace md {
@@ -108,11 +109,11 @@ __device__ __forceinline__ int count_kets(const double *__restrict__ Q, int n, d
 // threshold.  Single-precision tiles are summed per ket pair in T and added to
 // a double-precision accumulator.
 template <int LX, int LY, typename T>
-__global__ __launch_bounds__(64) void jeng_small(JArgs a)
+__device__ __forceinline__ void jeng_small_run(const JArgs &a, int blk_x, int blk_y)
 {
     constexpr int L = LX + LY, NX = nherm(LX), NY = nherm(LY);
     constexpr bool F32 = sizeof(T) == 4;
-    const int g = blockIdx.x * 64 + threadIdx.x;
+    const int g = blk_x * 64 + threadIdx.x;
     const bool valid = g < a.nbp;
     const int gi = valid ? g : a.nbp - 1;
     const PrimPair pb = a.pp[a.pbase + gi];
@@ -122,7 +123,7 @@ __global__ __launch_bounds__(64) void jeng_small(JArgs a)
     const int nvmax = __builtin_amdgcn_readfirstlane(wave_max(nv));
     const double qmax = uniform_d(wave_max(qi));
     const double Qw = (a.mode || a.tau_dens > 0.0) ? uniform_d(wave_max(Qi)) : 0.0;
-    const int j0 = blockIdx.y * a.kchunk;
+    const int j0 = blk_y * a.kchunk;
     const int j1 = min(min(a.nket, j0 + a.kchunk), nvmax);
     const T *__restrict__ Dt = pick<T>(a.Dt, a.Dtf);
 
@@ -192,11 +193,28 @@ __global__ __launch_bounds__(64) void jeng_small(JArgs a)
             double v;
             if constexpr (F32) v = Jh[P] * cw[herm_t(P) + herm_u(P) + herm_v(P)]; else v = Jt[P];
             if (a.jh_part > 0)
-                a.Jh[(int64_t)blockIdx.y * a.jh_part + (int64_t)g * NX + P] = v;
+                a.Jh[(int64_t)blk_y * a.jh_part + (int64_t)g * NX + P] = v;
             else
                 unsafeAtomicAdd(&a.Jh[(int64_t)g * NX + P], v);
         });
     }
+}
+
+template <int LX, int LY, typename T>
+__global__ __launch_bounds__(64) void jeng_small(JArgs a)
+{
+    jeng_small_run<LX, LY, T>(a, blockIdx.x, blockIdx.y);
+}
+
+// batch form (double precision): workgroup b runs block (items[b].y, items[b].z)
+// of the launch whose arguments are tab[items[b].x]
+template <int LX, int LY>
+__global__ __launch_bounds__(64) void jeng_small_q(const JArgs *__restrict__ tab, const int4 *__restrict__ items)
+{
+    const int4 it = items[blockIdx.x];
+    JArgs a = tab[it.x];
+    globalize(a);
+    jeng_small_run<LX, LY, double>(a, it.y, it.z);
 }
 
 // ---------------------------------------------------------------------------
@@ -204,7 +222,7 @@ __global__ __launch_bounds__(64) void jeng_small(JArgs a)
 // ---------------------------------------------------------------------------
 // Mixed mode: the tile is (bra primitive pair, ket pair j).
 template <int LX, int LY, typename T>
-__global__ __launch_bounds__(64) void jeng_wave(JArgs a)
+__device__ __forceinline__ void jeng_wave_run(const JArgs &a, int blk_x, int blk_y)
 {
     constexpr int L = LX + LY, L1 = L + 1, NX = nherm(LX), NY = nherm(LY);
     __shared__ T sR0[L1 * L1 * L1];
@@ -214,12 +232,12 @@ __global__ __launch_bounds__(64) void jeng_wave(JArgs a)
     __shared__ T sDq[NY];  // single precision: r^|Q| times the scaled Hermite density
     const int lane = threadIdx.x;
     herm_table_lds(sHerm, nherm(L), lane);
-    const int g = blockIdx.x;
+    const int g = blk_x;
     const PrimPair pb = a.pp[a.pbase + g];
     const double Qi = a.Qbra[a.owner[g]];
     const double qi = pb.q;
     const int nv = count_kets(a.Qket, a.nket, Qi, a.tau);
-    const int j0 = blockIdx.y * a.kchunk;
+    const int j0 = blk_y * a.kchunk;
     const int j1 = min(min(a.nket, j0 + a.kchunk), nv);
     if (j1 <= j0 && a.jh_part == 0) return;  // (per-chunk stores still write their zeros)
 
@@ -289,10 +307,27 @@ __global__ __launch_bounds__(64) void jeng_wave(JArgs a)
                 for (int k = 0; k < n; ++k) v *= c;
             }
             if (a.jh_part > 0)
-                a.Jh[(int64_t)blockIdx.y * a.jh_part + (int64_t)g * NX + lane + 64 * r] = v;
+                a.Jh[(int64_t)blk_y * a.jh_part + (int64_t)g * NX + lane + 64 * r] = v;
             else
                 unsafeAtomicAdd(&a.Jh[(int64_t)g * NX + lane + 64 * r], v);
         }
+}
+
+template <int LX, int LY, typename T>
+__global__ __launch_bounds__(64) void jeng_wave(JArgs a)
+{
+    jeng_wave_run<LX, LY, T>(a, blockIdx.x, blockIdx.y);
+}
+
+// batch form (double precision): workgroup b runs block (items[b].y, items[b].z)
+// of the launch whose arguments are tab[items[b].x]
+template <int LX, int LY>
+__global__ __launch_bounds__(64) void jeng_wave_q(const JArgs *__restrict__ tab, const int4 *__restrict__ items)
+{
+    const int4 it = items[blockIdx.x];
+    JArgs a = tab[it.x];
+    globalize(a);
+    jeng_wave_run<LX, LY, double>(a, it.y, it.z);
 }
 
 // out[i] += sum over the chunks c = 0, 1, ... of part[c * stride + i], in that
@@ -413,13 +448,24 @@ void jeng_launch_t(const JArgs &a, hipStream_t st)
         return;
     const int nch = (a.nket + a.kchunk - 1) / a.kchunk;
     if (a.nbp <= 0 || nch <= 0) return;
-    if constexpr (LX + LY <= kJengRegMaxL) {
-        dim3 grid((a.nbp + 63) / 64, nch);
-        hipLaunchKernelGGL((jeng_small<LX, LY, T>), grid, dim3(64), 0, st, a);
-    } else {
-        dim3 grid(a.nbp, nch);
-        hipLaunchKernelGGL((jeng_wave<LX, LY, T>), grid, dim3(64), 0, st, a);
+    constexpr bool SMALL = LX + LY <= kJengRegMaxL;
+    const dim3 grid(SMALL ? (a.nbp + 63) / 64 : a.nbp, nch);
+    if (queue_sink()) {  // a batch plan (builds only: bra order at most 6, double precision)
+        QueueLaunchFn fn = nullptr;
+        if constexpr (LX <= 6 && sizeof(T) == 8) {
+            if constexpr (SMALL)
+                fn = &queue_launch<JArgs, jeng_small_q<LX, LY>, 64>;
+            else
+                fn = &queue_launch<JArgs, jeng_wave_q<LX, LY>, 64>;
+        }
+        queue_record(fn, a, (int)grid.x, nch, (double)(a.kchunk < a.nket ? a.kchunk : a.nket),
+                     SMALL ? "jeng_small" : "jeng_wave");
+        return;
     }
+    if constexpr (SMALL)
+        hipLaunchKernelGGL((jeng_small<LX, LY, T>), grid, dim3(64), 0, st, a);
+    else
+        hipLaunchKernelGGL((jeng_wave<LX, LY, T>), grid, dim3(64), 0, st, a);
 }
 
 // Bra orders up to 7 serve the gradient (the bra order raised by one), which

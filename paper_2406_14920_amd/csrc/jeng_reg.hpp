@@ -7,6 +7,7 @@
 #pragma once
 #include "kern_args.hpp"
 #include "md_device.hpp"
+#include "queue.hpp"
 
 namespace md {
 
@@ -65,12 +66,12 @@ __device__ __forceinline__ void jeng_quartet_stream(const T *G, const T *px, con
 // Mixed mode: tile (wavefront of bra pairs, ket pair j) as in jeng_small;
 // single-precision tiles are summed per ket pair and added in double.
 template <int LX, int LY, typename T>
-__global__ __launch_bounds__(64) void jeng_reg(JArgs a)
+__device__ __forceinline__ void jeng_reg_run(const JArgs &a, int blk_x, int blk_y)
 {
     constexpr int L = LX + LY, NX = nherm(LX), NY = nherm(LY);
     constexpr bool F32 = sizeof(T) == 4;
     constexpr bool DQMEM = NY > 20;  // ket density read at use instead of held in registers
-    const int g = blockIdx.x * 64 + threadIdx.x;
+    const int g = blk_x * 64 + threadIdx.x;
     const bool valid = g < a.nbp;
     const int gi = valid ? g : a.nbp - 1;
     const PrimPair pb = a.pp[a.pbase + gi];
@@ -96,7 +97,7 @@ __global__ __launch_bounds__(64) void jeng_reg(JArgs a)
         const uint32_t hi32 = __builtin_amdgcn_readfirstlane((uint32_t)(bq >> 32));
         qmax = __longlong_as_double(((uint64_t)hi32 << 32) | lo32);
     }
-    const int j0 = blockIdx.y * a.kchunk;
+    const int j0 = blk_y * a.kchunk;
     const int j1 = min(min(a.nket, j0 + a.kchunk), nvmax);
 
     const T *__restrict__ Dt = pick<T>(a.Dt, a.Dtf);
@@ -162,11 +163,28 @@ __global__ __launch_bounds__(64) void jeng_reg(JArgs a)
             double v;
             if constexpr (F32) v = Jh[P] * cw[herm_t(P) + herm_u(P) + herm_v(P)]; else v = Jt[P];
             if (a.jh_part > 0)
-                a.Jh[(int64_t)blockIdx.y * a.jh_part + (int64_t)g * NX + P] = v;
+                a.Jh[(int64_t)blk_y * a.jh_part + (int64_t)g * NX + P] = v;
             else
                 unsafeAtomicAdd(&a.Jh[(int64_t)g * NX + P], v);
         });
     }
+}
+
+template <int LX, int LY, typename T>
+__global__ __launch_bounds__(64) void jeng_reg(JArgs a)
+{
+    jeng_reg_run<LX, LY, T>(a, blockIdx.x, blockIdx.y);
+}
+
+// batch form (double precision): workgroup b runs block (items[b].y, items[b].z)
+// of the launch whose arguments are tab[items[b].x]
+template <int LX, int LY>
+__global__ __launch_bounds__(64) void jeng_reg_q(const JArgs *__restrict__ tab, const int4 *__restrict__ items)
+{
+    const int4 it = items[blockIdx.x];
+    JArgs a = tab[it.x];
+    globalize(a);
+    jeng_reg_run<LX, LY, double>(a, it.y, it.z);
 }
 
 // register J-engine is used where its live set (Hermite J, Boys values,
@@ -177,12 +195,32 @@ __host__ __device__ constexpr bool jeng_reg_ok(int lx, int ly)
     return lx + ly >= 6 && nherm(lx) + 4 * (lx + ly + 1) + (nherm(ly) <= 20 ? nherm(ly) : 0) <= 116;
 }
 
+// The queue forms are instantiated in translation units of their own
+// (jeng_reg_q_*.hip), which compile in parallel with the direct ones.
+QueueLaunchFn jeng_reg_queue_fn_0(int lx, int ly);
+QueueLaunchFn jeng_reg_queue_fn_1(int lx, int ly);
+QueueLaunchFn jeng_reg_queue_fn_2(int lx, int ly);
+QueueLaunchFn jeng_reg_queue_fn_3(int lx, int ly);
+inline QueueLaunchFn jeng_reg_queue_fn(int lx, int ly)
+{
+    QueueLaunchFn f = jeng_reg_queue_fn_0(lx, ly);
+    if (!f) f = jeng_reg_queue_fn_1(lx, ly);
+    if (!f) f = jeng_reg_queue_fn_2(lx, ly);
+    if (!f) f = jeng_reg_queue_fn_3(lx, ly);
+    return f;
+}
+
 template <int LX, int LY>
 void jeng_reg_launch_t(const JArgs &a, bool fp32, hipStream_t st)
 {
     const int nch = (a.nket + a.kchunk - 1) / a.kchunk;
     if (a.nbp <= 0 || nch <= 0) return;
     dim3 grid((a.nbp + 63) / 64, nch);
+    if (queue_sink()) {  // a batch plan: a wavefront of bra pairs against one ket chunk per block
+        queue_record(fp32 ? nullptr : jeng_reg_queue_fn(LX, LY), a, (int)grid.x, nch,
+                     (double)(a.kchunk < a.nket ? a.kchunk : a.nket), "jeng_reg");
+        return;
+    }
     if (fp32)
         hipLaunchKernelGGL((jeng_reg<LX, LY, float>), grid, dim3(64), 0, st, a);
     else

@@ -1,0 +1,18 @@
+// jeng_reg_q_2.hip -- queue forms (batch launches) of the register J-engine
+// classes of jeng_reg_2.hip.
+#include "jeng_reg.hpp"
+
+namespace md {
+
+QueueLaunchFn jeng_reg_queue_fn_2(int lx, int ly)
+{
+    if (lx == 5 && ly == 3) return &queue_launch<JArgs, jeng_reg_q<5, 3>, 64>;
+    if (lx == 0 && ly == 6) return &queue_launch<JArgs, jeng_reg_q<0, 6>, 64>;
+    if (lx == 2 && ly == 4) return &queue_launch<JArgs, jeng_reg_q<2, 4>, 64>;
+    if (lx == 6 && ly == 0) return &queue_launch<JArgs, jeng_reg_q<6, 0>, 64>;
+    if (lx == 3 && ly == 6) return &queue_launch<JArgs, jeng_reg_q<3, 6>, 64>;
+    if (lx == 5 && ly == 4) return &queue_launch<JArgs, jeng_reg_q<5, 4>, 64>;
+    return nullptr;
+}
+
+}  // namespace md

@@ -18,6 +18,7 @@
 #pragma once
 #include "kern_args.hpp"
 #include "md_device.hpp"
+#include "queue.hpp"
 
 namespace md {
 
@@ -59,7 +60,7 @@ struct KPairCfg {
 };
 
 template <int LA, int LB, int LC, int LD, typename T>
-__global__ __launch_bounds__(64) void k_pair(KPArgs a)
+__device__ __forceinline__ void k_pair_run(const KPArgs &a, int blk_x)
 {
     using C = KPairCfg<LA, LB, LC, LD, T>;
     constexpr int NA = C::NA, NB = C::NB, NC = C::NC, ND = C::ND, NCD = C::NCD;
@@ -69,7 +70,7 @@ __global__ __launch_bounds__(64) void k_pair(KPArgs a)
     constexpr int SB = ob.off[C::NAB], SK = ok.off[NCD];
 
     const int lane = threadIdx.x;
-    const int4 ch = a.chunks[blockIdx.x];
+    const int4 ch = a.chunks[blk_x];
     const bool valid = lane < ch.z;
     const int64_t wl = a.prefix[ch.x] + ch.y + (valid ? lane : 0);  // the lane's work item
     int r = ch.x;
@@ -307,10 +308,31 @@ __global__ __launch_bounds__(64) void k_pair(KPArgs a)
     });
 }
 
+template <int LA, int LB, int LC, int LD, typename T>
+__global__ __launch_bounds__(64) void k_pair(KPArgs a)
+{
+    k_pair_run<LA, LB, LC, LD, T>(a, blockIdx.x);
+}
+
+// batch form (double precision): workgroup b runs block (items[b].y, items[b].z)
+// of the launch whose arguments are tab[items[b].x]
+template <int LA, int LB, int LC, int LD>
+__global__ __launch_bounds__(64) void k_pair_q(const KPArgs *__restrict__ tab, const int4 *__restrict__ items)
+{
+    const int4 it = items[blockIdx.x];
+    KPArgs a = tab[it.x];
+    globalize(a);
+    k_pair_run<LA, LB, LC, LD, double>(a, it.y);
+}
+
 template <int LA, int LB, int LC, int LD>
 void launch_k_pair_t(const KPArgs &a, int nchunks, bool fp32, hipStream_t st)
 {
     if (nchunks <= 0) return;
+    if (queue_sink()) {  // a batch plan: one chunk of up to 64 quartets per block
+        queue_record(fp32 ? nullptr : &queue_launch<KPArgs, k_pair_q<LA, LB, LC, LD>, 64>, a, nchunks, 1, 1.0, "k_pair");
+        return;
+    }
     if (fp32)
         hipLaunchKernelGGL((k_pair<LA, LB, LC, LD, float>), dim3((unsigned)nchunks), dim3(64), 0, st, a);
     else

@@ -15,11 +15,12 @@
 #include "class_lists.hpp"
 #include "kern_args.hpp"
 #include "md_device.hpp"
+#include "queue.hpp"
 
 namespace md {
 
 template <int LA, int LB, int LC, int LD, typename T>
-__global__ __launch_bounds__(128) void k_small(KArgs a)
+__device__ __forceinline__ void k_small_run(const KArgs &a, int blk_x)
 {
     constexpr int NA = ncart(LA), NB = ncart(LB), NC = ncart(LC), ND = ncart(LD);
     constexpr int L = LA + LB + LC + LD, LAB = LA + LB;
@@ -28,7 +29,7 @@ __global__ __launch_bounds__(128) void k_small(KArgs a)
 
     // every lane of a wavefront stays to the end (the digestion sums across
     // lanes); lanes past the work list evaluate nothing
-    const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t w = (int64_t)blk_x * 128 + threadIdx.x;
     const bool valid = w < a.nwork;
     const int64_t wc = valid ? w : a.nwork - 1;
     const int r = k_find_row(a.prefix, a.nrows, wc);
@@ -260,6 +261,23 @@ __global__ __launch_bounds__(128) void k_small(KArgs a)
     }
 }
 
+template <int LA, int LB, int LC, int LD, typename T>
+__global__ __launch_bounds__(128) void k_small(KArgs a)
+{
+    k_small_run<LA, LB, LC, LD, T>(a, blockIdx.x);
+}
+
+// batch form (double precision): workgroup b runs block (items[b].y, items[b].z)
+// of the launch whose arguments are tab[items[b].x]
+template <int LA, int LB, int LC, int LD>
+__global__ __launch_bounds__(128) void k_small_q(const KArgs *__restrict__ tab, const int4 *__restrict__ items)
+{
+    const int4 it = items[blockIdx.x];
+    KArgs a = tab[it.x];
+    globalize(a);
+    k_small_run<LA, LB, LC, LD, double>(a, it.y);
+}
+
 bool launch_k_small(int la, int lb, int lc, int ld, const KArgs &a, bool fp32, hipStream_t st)
 {
     const int threads = 128;
@@ -267,7 +285,10 @@ bool launch_k_small(int la, int lb, int lc, int ld, const KArgs &a, bool fp32, h
     if (a.nwork <= 0) return true;
 #define MD_CASE(A_, B_, C_, D_)                                                        \
     if (la == A_ && lb == B_ && lc == C_ && ld == D_) {                                \
-        if (fp32)                                                                      \
+        if (queue_sink())                                                              \
+            queue_record(fp32 ? nullptr : &queue_launch<KArgs, k_small_q<A_, B_, C_, D_>, 128>, a, (int)blocks, 1, 1.0, \
+                         "k_small");                                                   \
+        else if (fp32)                                                                 \
             hipLaunchKernelGGL((k_small<A_, B_, C_, D_, float>), dim3((unsigned)blocks), dim3(threads), 0, st, a); \
         else                                                                           \
             hipLaunchKernelGGL((k_small<A_, B_, C_, D_, double>), dim3((unsigned)blocks), dim3(threads), 0, st, a); \

@@ -120,7 +120,7 @@ __device__ __forceinline__ void flush_tiles(double *sK, const CPair &A, const CP
 }
 
 template <int LA, int LB, int LC, int LD, typename T>
-__global__ __launch_bounds__(64) void k_wave(KArgs a)
+__device__ __forceinline__ void k_wave_run(const KArgs &a, int blk_x, int grid_x)
 {
     using C = WaveCfg<LA, LB, LC, LD, T>;
     constexpr int NA = C::NA, NB = C::NB, NC = C::NC, ND = C::ND;
@@ -162,7 +162,7 @@ __global__ __launch_bounds__(64) void k_wave(KArgs a)
     }
 
     const int n = a.ld;
-    for (int64_t w0 = (int64_t)blockIdx.x * C::RANGE; w0 < a.nwork; w0 += (int64_t)gridDim.x * C::RANGE) {
+    for (int64_t w0 = (int64_t)blk_x * C::RANGE; w0 < a.nwork; w0 += (int64_t)grid_x * C::RANGE) {
         const int64_t w1 = (w0 + C::RANGE < a.nwork) ? w0 + C::RANGE : a.nwork;
         int row = k_find_row(a.prefix, a.nrows, w0);
         int jk = (int)(w0 - a.prefix[row]);
@@ -322,6 +322,23 @@ __global__ __launch_bounds__(64) void k_wave(KArgs a)
     }
 }
 
+template <int LA, int LB, int LC, int LD, typename T>
+__global__ __launch_bounds__(64) void k_wave(KArgs a)
+{
+    k_wave_run<LA, LB, LC, LD, T>(a, blockIdx.x, gridDim.x);
+}
+
+// batch form (double precision): workgroup b runs block (items[b].y, items[b].z)
+// of the launch whose arguments are tab[items[b].x]
+template <int LA, int LB, int LC, int LD>
+__global__ __launch_bounds__(64) void k_wave_q(const KArgs *__restrict__ tab, const int4 *__restrict__ items)
+{
+    const int4 it = items[blockIdx.x];
+    KArgs a = tab[it.x];
+    globalize(a);
+    k_wave_run<LA, LB, LC, LD, double>(a, it.y, it.w);
+}
+
 // Ket-first form for the classes whose block fits in LDS.  Per primitive
 // quartet, for each ket component cd (a compile-time round in which every
 // lane takes the same path), lane k owning the bra Hermite index t forms
@@ -335,7 +352,7 @@ __global__ __launch_bounds__(64) void k_wave(KArgs a)
 // The lane then digests its block row at once (digestion is linear in the
 // block), so no block buffer is needed and large blocks fit too.
 template <int LA, int LB, int LC, int LD, typename T>
-__global__ __launch_bounds__(64) void k_wave_x(KArgs a)
+__device__ __forceinline__ void k_wave_x_run(const KArgs &a, int blk_x, int grid_x)
 {
     using C = WaveCfg<LA, LB, LC, LD, T>;
     constexpr int NA = C::NA, NB = C::NB, NC = C::NC, ND = C::ND;
@@ -399,7 +416,7 @@ __global__ __launch_bounds__(64) void k_wave_x(KArgs a)
     }
 
     const int n = a.ld;
-    for (int64_t w0 = (int64_t)blockIdx.x * C::RANGE; w0 < a.nwork; w0 += (int64_t)gridDim.x * C::RANGE) {
+    for (int64_t w0 = (int64_t)blk_x * C::RANGE; w0 < a.nwork; w0 += (int64_t)grid_x * C::RANGE) {
         const int64_t w1 = (w0 + C::RANGE < a.nwork) ? w0 + C::RANGE : a.nwork;
         int row = k_find_row(a.prefix, a.nrows, w0);
         int jk = (int)(w0 - a.prefix[row]);
@@ -624,6 +641,23 @@ __global__ __launch_bounds__(64) void k_wave_x(KArgs a)
     }
 }
 
+template <int LA, int LB, int LC, int LD, typename T>
+__global__ __launch_bounds__(64) void k_wave_x(KArgs a)
+{
+    k_wave_x_run<LA, LB, LC, LD, T>(a, blockIdx.x, gridDim.x);
+}
+
+// batch form (double precision): workgroup b runs block (items[b].y, items[b].z)
+// of the launch whose arguments are tab[items[b].x]
+template <int LA, int LB, int LC, int LD>
+__global__ __launch_bounds__(64) void k_wave_x_q(const KArgs *__restrict__ tab, const int4 *__restrict__ items)
+{
+    const int4 it = items[blockIdx.x];
+    KArgs a = tab[it.x];
+    globalize(a);
+    k_wave_x_run<LA, LB, LC, LD, double>(a, it.y, it.w);
+}
+
 template <int LA, int LB, int LC, int LD>
 void launch_k_wave_t(const KArgs &a, bool fp32, hipStream_t st)
 {
@@ -632,6 +666,16 @@ void launch_k_wave_t(const KArgs &a, bool fp32, hipStream_t st)
     const int64_t cap = a.grid_cap > 0 ? a.grid_cap : 32768;
     const int64_t blocks = ranges < cap ? ranges : cap;
     if (blocks <= 0) return;
+    if (queue_sink()) {  // a batch plan: each block walks ranges/blocks ranges
+        QueueLaunchFn fn;
+        if constexpr (C::KETFIRST)
+            fn = &queue_launch<KArgs, k_wave_x_q<LA, LB, LC, LD>, 64>;
+        else
+            fn = &queue_launch<KArgs, k_wave_q<LA, LB, LC, LD>, 64>;
+        queue_record(fp32 ? nullptr : fn, a, (int)blocks, 1,
+                     (double)ranges / (double)blocks, C::KETFIRST ? "k_wave_x" : "k_wave");
+        return;
+    }
     if constexpr (!C::KETFIRST) {
         if (fp32)
             hipLaunchKernelGGL((k_wave<LA, LB, LC, LD, float>), dim3((unsigned)blocks), dim3(64), 0, st, a);

@@ -235,3 +235,112 @@ def test_batch_latency_per_molecule():
         _close(J, J0, "J batch")
         _close(K, K0, "K batch")
     b.close()
+
+
+def test_batch_queue_launches_match_standalone():
+    """Queue mode (the default for double-precision batches): one
+    launch per kernel for all molecules.  Every molecule's J and K equal its
+    own build_jk on repeated calls with eager work between; the plan is
+    remade after a context changes (a moved molecule, a density screen)."""
+    torch = _torch()
+    from paper_2406_14920_amd import JK, Batch
+    xyz = [[0.0, 0.0, 0.0], [1.9, 0.4, -0.3], [-0.7, 1.6, 0.9]]
+    specs = [(0, 0, 3), (0, 0, 1), (0, 1, 2), (0, 2, 1), (0, 3, 1),
+             (1, 0, 2), (1, 1, 1), (1, 3, 2),
+             (2, 0, 1), (2, 2, 2), (2, 3, 1)]
+    fshell = synth.custom(xyz, specs, seed=11, tau=1e-12, exp_range=(0.08, 60.0), name="f3")
+    mols = _mols(7) + [fshell]
+    print("  sizes:", [m.nbf for m in mols], flush=True)
+    jks = [JK.from_molecule(m) for m in mols]
+    Ps = [torch.tensor(m.P, dtype=torch.float64, device="cuda") for m in mols]
+    ref = [tuple(t.clone() for t in jk.jk(P)) for jk, P in zip(jks, Ps)]
+    torch.cuda.synchronize()
+    b = Batch(jks)
+    assert b.mode == "queue"
+    for rep in range(3):
+        J, K = b.jk(Ps)
+        torch.cuda.synchronize()
+        for i in range(len(mols)):
+            _close(J[i], ref[i][0], "J rep %d mol %d" % (rep, i))
+            _close(K[i], ref[i][1], "K rep %d mol %d" % (rep, i))
+        junk = torch.randn(256, 256, device="cuda", dtype=torch.float64)
+        (junk @ junk).sum().item()
+        for t in J + K:
+            t.fill_(7.0)
+    info = b.queue_info()
+    print("  queue plan:", info, flush=True)
+    assert 0 < info["launches"] <= 200 and info["items"] > 0
+    lat = b.latency()
+    assert len(lat) == len(mols) and all(x > 0.0 for x in lat)
+    # a moved molecule and a density-weighted screen on another: new plan
+    xyz = np.asarray(mols[1].xyz) + np.array([0.05, -0.1, 0.02])
+    jks[1].set_geometry(xyz)
+    jks[3].set_density_screen(1e-12)
+    ref2 = [tuple(t.clone() for t in jk.jk(P)) for jk, P in zip(jks, Ps)]
+    J, K = b.jk(Ps)
+    torch.cuda.synchronize()
+    for i in range(len(mols)):
+        _close(J[i], ref2[i][0], "J after change mol %d" % i)
+        _close(K[i], ref2[i][1], "K after change mol %d" % i)
+    # the streams form on the same batch gives the same results
+    b.set_mode("streams")
+    J, K = b.jk(Ps)
+    torch.cuda.synchronize()
+    for i in range(len(mols)):
+        _close(J[i], ref2[i][0], "J streams mol %d" % i)
+        _close(K[i], ref2[i][1], "K streams mol %d" % i)
+    with pytest.raises(ValueError):
+        b.set_mode("fused")
+    b.close()
+    for jk in jks:
+        jk.close()
+
+
+def test_batch_queue_graph_replays():
+    """A queue-mode batch build after the first is a chain of kernel launches
+    on the batch stream: captured into a HIP graph (torch's capture on that
+    stream) and replayed three times with eager work between, every replay
+    equals the eager build and follows new densities written into the same
+    tensors."""
+    torch = _torch()
+    from paper_2406_14920_amd import JK, Batch
+    mols = _mols(5)
+    jks = [JK.from_molecule(m) for m in mols]
+    Ps = [torch.tensor(m.P, dtype=torch.float64, device="cuda") for m in mols]
+    s = torch.cuda.Stream()
+    b = Batch(jks, stream=s)
+    with torch.cuda.stream(s):
+        J, K = b.jk(Ps)
+    torch.cuda.synchronize()
+    eager = [(j.clone(), k.clone()) for j, k in zip(J, K)]
+    print("  eager done", flush=True)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        b.jk(Ps)
+    torch.cuda.synchronize()
+    print("  captured", flush=True)
+    for rep in range(3):
+        for t in J + K:
+            t.fill_(-3.0)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for i in range(len(mols)):
+            _close(J[i], eager[i][0], "J replay %d mol %d" % (rep, i))
+            _close(K[i], eager[i][1], "K replay %d mol %d" % (rep, i))
+        junk = torch.randn(300, 300, device="cuda", dtype=torch.float64)
+        (junk @ junk).sum().item()
+        print("  replay %d ok" % rep, flush=True)
+    # new densities in the same tensors: the replay follows them
+    for P in Ps:
+        P.mul_(0.5)
+    torch.cuda.synchronize()
+    g.replay()
+    torch.cuda.synchronize()
+    for i in range(len(mols)):
+        _close(J[i], 0.5 * eager[i][0], "J new density mol %d" % i)
+        _close(K[i], 0.5 * eager[i][1], "K new density mol %d" % i)
+    del g
+    b.close()
+    for jk in jks:
+        jk.close()
