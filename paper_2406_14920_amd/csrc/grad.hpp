@@ -33,38 +33,6 @@
 
 namespace md {
 
-// LDS bytes of kg_wave's tables with a ket chunk of c components (the
-// natom x 3 partials come on top)
-__host__ __device__ constexpr int kg_lds_bytes(int L, int NR0, int EBD, int EKD, int NHX, int NHC, int ND_, int c)
-{
-    return 8 * (NR0 + (L + 2) + 3 * (L + 2) * ((L + 1) / 2 + 1) + 3 * EBD + 3 * EKD + c * NHX + 3 * c * NHC + ND_) +
-           4 * nherm(L + 1);
-}
-
-template <int LA, int LB, int LC, int LD>
-struct KGCfg {
-    static constexpr int NA = ncart(LA), NB = ncart(LB), NC = ncart(LC), ND = ncart(LD);
-    static constexpr int NAB = NA * NB, NCD = NC * ND;
-    static constexpr int L = LA + LB + LC + LD, LAB = LA + LB, LCD = LC + LD;
-    static constexpr int L2 = L + 2;                 // dense R table side (orders up to L+1)
-    static constexpr int NR0 = L2 * L2 * L2;
-    static constexpr int NHX = nherm(LAB + 1), NHC = nherm(LAB);
-    static constexpr int NABCH = (NAB + 63) / 64;
-    // 1D tables [i][j][t]: bra i <= LA+1, j <= LB, t <= LAB+1; ket i <= LC+1, j <= LD, t <= LCD+1
-    static constexpr int EBJ = LAB + 2, EBI = (LB + 1) * EBJ, EBD = (LA + 2) * EBI;
-    static constexpr int EKJ = LCD + 2, EKI = (LD + 1) * EKJ, EKD = (LC + 2) * EKI;
-    static constexpr int ND_ = NA * NC + NA * ND + NB * NC + NB * ND;
-    // ket components per chunk: the largest of 16, 8, 4 whose tables fit in
-    // 40 KB of LDS, so that four of these one-wave workgroups share a compute
-    // unit (one per SIMD; the largest classes hold 256 VGPRs, one wave per SIMD)
-    static constexpr int CDCH0 = kg_lds_bytes(L, NR0, EBD, EKD, NHX, NHC, ND_, 16) <= 40960  ? 16
-                                 : kg_lds_bytes(L, NR0, EBD, EKD, NHX, NHC, ND_, 8) <= 40960 ? 8
-                                                                                             : 4;
-    static constexpr int CDCH = NCD < CDCH0 ? NCD : CDCH0;
-    static constexpr int RANGE = 4;
-};
-
-// Derivative coefficient along one axis: 2a E^{i+1,j}_t - i E^{i-1,j}_t.
 // largest Hermite box of a pair class with one axis extended by one (the
 // derivative boxes), over all components and axes
 __host__ __device__ constexpr int box_max_ext(int la, int lb)
@@ -94,6 +62,40 @@ __host__ __device__ constexpr int box_max_grown(int la, int lb)
     return m;
 }
 
+// LDS bytes of kg_wave's tables with a ket chunk of c components (the
+// natom x 3 partials come on top)
+__host__ __device__ constexpr int kg_lds_bytes(int L, int NR0, int EBD, int EKD, int NHX, int NHC, int ND_, int KBM,
+                                               int c)
+{
+    return 8 * (NR0 + (L + 2) + 3 * (L + 2) * ((L + 1) / 2 + 1) + 3 * EBD + 3 * EKD + c * NHX + 3 * c * NHC + ND_) +
+           4 * nherm(L + 1) + 12 * 4 * c * KBM;
+}
+
+template <int LA, int LB, int LC, int LD>
+struct KGCfg {
+    static constexpr int NA = ncart(LA), NB = ncart(LB), NC = ncart(LC), ND = ncart(LD);
+    static constexpr int NAB = NA * NB, NCD = NC * ND;
+    static constexpr int L = LA + LB + LC + LD, LAB = LA + LB, LCD = LC + LD;
+    static constexpr int L2 = L + 2;                 // dense R table side (orders up to L+1)
+    static constexpr int NR0 = L2 * L2 * L2;
+    static constexpr int NHX = nherm(LAB + 1), NHC = nherm(LAB);
+    static constexpr int NABCH = (NAB + 63) / 64;
+    // 1D tables [i][j][t]: bra i <= LA+1, j <= LB, t <= LAB+1; ket i <= LC+1, j <= LD, t <= LCD+1
+    static constexpr int EBJ = LAB + 2, EBI = (LB + 1) * EBJ, EBD = (LA + 2) * EBI;
+    static constexpr int EKJ = LCD + 2, EKI = (LD + 1) * EKJ, EKD = (LC + 2) * EKI;
+    static constexpr int ND_ = NA * NC + NA * ND + NB * NC + NB * ND;
+    static constexpr int KBM = box_max_ext(LC, LD);  // longest ket coefficient list
+    // ket components per chunk: the largest of 16, 8, 4 whose tables fit in
+    // 40 KB of LDS, so that four of these one-wave workgroups share a compute
+    // unit (one per SIMD; the largest classes hold 256 VGPRs, one wave per SIMD)
+    static constexpr int CDCH0 = kg_lds_bytes(L, NR0, EBD, EKD, NHX, NHC, ND_, KBM, 16) <= 40960  ? 16
+                                 : kg_lds_bytes(L, NR0, EBD, EKD, NHX, NHC, ND_, KBM, 8) <= 40960 ? 8
+                                                                                                  : 4;
+    static constexpr int CDCH = NCD < CDCH0 ? NCD : CDCH0;
+    static constexpr int RANGE = 4;
+};
+
+// Derivative coefficient along one axis: 2a E^{i+1,j}_t - i E^{i-1,j}_t.
 __device__ __forceinline__ double dcoef(const double *E, int DI, int DJ, int i, int j, int t, double a2)
 {
     double v = a2 * E[(i + 1) * DI + j * DJ + t];
@@ -118,6 +120,11 @@ __global__ __launch_bounds__(64) void kg_wave(KGArgs g)
     __shared__ double sX[CDCH * NHX];
     __shared__ double sXc[3 * CDCH * NHC];
     __shared__ double sD[C::ND_];
+    // ket coefficient lists of a chunk, [kq][c][k]: kq 0 the ket E product,
+    // kq 1..3 its derivative along x, y, z; coefficient (sign included) and
+    // R offset of box point k, zero past the box
+    __shared__ double sEc[4 * CDCH * C::KBM];
+    __shared__ int sEo[4 * CDCH * C::KBM];
     extern __shared__ double sG[];  // natom x 3
 
     const int lane = threadIdx.x;
@@ -190,47 +197,52 @@ __global__ __launch_bounds__(64) void kg_wave(KGArgs g)
 
                     for (int cd0 = 0; cd0 < NCD; cd0 += CDCH) {
                         const int ncd = (cd0 + CDCH < NCD) ? CDCH : NCD - cd0;
-                        // ket-contracted intermediates of this chunk
-                        for (int o = lane; o < ncd * (NHX + 3 * NHC); o += 64) {
-                            int c, t, kdir;
-                            if (o < ncd * NHX) { c = o / NHX; t = o % NHX; kdir = -1; }
-                            else { const int r = o - ncd * NHX; kdir = r / (ncd * NHC); c = (r / NHC) % ncd; t = r % NHC; }
-                            const int cd = cd0 + c;
+                        // ket coefficient lists of this chunk: for component cd and
+                        // kq (0: E^{cd}, 1..3: its derivative along x, y, z) the
+                        // coefficients (-1)^{|s|} Ed_s over the (extended) ket box and
+                        // the R offsets of the box points, padded to KBM with zeros
+                        for (int o = lane; o < 4 * ncd * C::KBM; o += 64) {
+                            const int k = o % C::KBM, c = (o / C::KBM) % ncd, kq = o / (C::KBM * ncd);
+                            const int kdir = kq - 1, cd = cd0 + c;
                             int cx, cy, cz, dx, dy, dz;
                             cart_rt(LC, cd / ND, cx, cy, cz);
                             cart_rt(LD, cd % ND, dx, dy, dz);
-                            const int code = c_herm.tuv[t];
-                            const int tx = code & 0xff, ty = (code >> 8) & 0xff, tz = code >> 16;
                             const int mx = cx + dx + 1 + (kdir == 0), my = cy + dy + 1 + (kdir == 1),
                                       mz = cz + dz + 1 + (kdir == 2);
-                            const double *Ex = sEk, *Ey = sEk + C::EKD, *Ez = sEk + 2 * C::EKD;
-                            double acc = 0.0;
-                            // one flat loop over the (possibly extended) ket box, trip
-                            // count the class's largest box for every lane
-                            constexpr int KBM = box_max_ext(LC, LD);
-                            const int nbox = mx * my * mz;
-                            int sx = 0, sy = 0, sz = 0;
-                            for (int st = 0; st < KBM; ++st) {
-                                if (st < nbox) {
-                                    const double ex = kdir == 0 ? dcoef(Ex, C::EKI, C::EKJ, cx, dx, sx, c2)
-                                                                : Ex[cx * C::EKI + dx * C::EKJ + sx];
-                                    const double ey = kdir == 1 ? dcoef(Ey, C::EKI, C::EKJ, cy, dy, sy, c2)
-                                                                : Ey[cy * C::EKI + dy * C::EKJ + sy];
-                                    const double ez = kdir == 2 ? dcoef(Ez, C::EKI, C::EKJ, cz, dz, sz, c2)
-                                                                : Ez[cz * C::EKI + dz * C::EKJ + sz];
-                                    const double sg = ((sx + sy + sz) & 1) ? -1.0 : 1.0;
-                                    acc += sg * ex * ey * ez * sR0[((tx + sx) * L2 + ty + sy) * L2 + tz + sz];
-                                }
-                                if (++sz == mz) {
-                                    sz = 0;
-                                    if (++sy == my) {
-                                        sy = 0;
-                                        ++sx;
-                                    }
-                                }
+                            double coef = 0.0;
+                            int off = 0;
+                            if (k < mx * my * mz) {
+                                const int sx = k / (my * mz), sy = (k / mz) % my, sz = k % mz;
+                                const double *Ex = sEk, *Ey = sEk + C::EKD, *Ez = sEk + 2 * C::EKD;
+                                const double ex = kdir == 0 ? dcoef(Ex, C::EKI, C::EKJ, cx, dx, sx, c2)
+                                                            : Ex[cx * C::EKI + dx * C::EKJ + sx];
+                                const double ey = kdir == 1 ? dcoef(Ey, C::EKI, C::EKJ, cy, dy, sy, c2)
+                                                            : Ey[cy * C::EKI + dy * C::EKJ + sy];
+                                const double ez = kdir == 2 ? dcoef(Ez, C::EKI, C::EKJ, cz, dz, sz, c2)
+                                                            : Ez[cz * C::EKI + dz * C::EKJ + sz];
+                                coef = ((sx + sy + sz) & 1) ? -ex * ey * ez : ex * ey * ez;
+                                off = (sx * L2 + sy) * L2 + sz;
                             }
-                            if (kdir < 0) sX[c * NHX + t] = acc;
-                            else sXc[(kdir * CDCH + c) * NHC + t] = acc;
+                            sEc[(kq * CDCH + c) * C::KBM + k] = coef;
+                            sEo[(kq * CDCH + c) * C::KBM + k] = off;
+                        }
+                        __syncthreads();
+                        // ket-contracted intermediates of this chunk: one dot product
+                        // of a coefficient list with R around t per output (the
+                        // padding adds zeros times R_t, inside the table)
+                        for (int o = lane; o < ncd * (NHX + 3 * NHC); o += 64) {
+                            int c, t, kq;
+                            if (o < ncd * NHX) { c = o / NHX; t = o % NHX; kq = 0; }
+                            else { const int r = o - ncd * NHX; kq = 1 + r / (ncd * NHC); c = (r / NHC) % ncd; t = r % NHC; }
+                            const int code = c_herm.tuv[t];
+                            const int tb = ((code & 0xff) * L2 + ((code >> 8) & 0xff)) * L2 + (code >> 16);
+                            const double *ec = sEc + (kq * CDCH + c) * C::KBM;
+                            const int *eo = sEo + (kq * CDCH + c) * C::KBM;
+                            double acc = 0.0;
+#pragma unroll
+                            for (int k = 0; k < C::KBM; ++k) acc += ec[k] * sR0[tb + eo[k]];
+                            if (kq == 0) sX[c * NHX + t] = acc;
+                            else sXc[((kq - 1) * CDCH + c) * NHC + t] = acc;
                         }
                         __syncthreads();
 
