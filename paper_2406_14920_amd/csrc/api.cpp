@@ -308,6 +308,7 @@ struct eri_ctx {
     DevBuf<double> d_xyz;
     DevBuf<double4> d_psph, d_bsph;
     DevBuf<double> d_Jh1, d_pg, d_kpart, d_Jtmp, d_Ktmp, d_jhpart;
+    DevBuf<double> d_gred;  // chunk sums of the fixed-order gradient reduction
     int gchunk[kPairClasses][kPairClasses] = {};  // J-engine ket chunk of the gradient launches
     std::vector<int> kg_blocks;   // per exchange launch
     std::vector<int64_t> kg_off;  // first partial of each launch
@@ -1339,7 +1340,10 @@ void run_grad(eri_ctx *c, double *grad)
             throw HipError{ERI_ESTATE};
         }
     }
-    launch_grad_reduce(c->d_cp.p, (int)c->cp.size(), c->d_pg.p, c->d_kpart.p, c->kg_total, c->natom, grad, st);
+    const size_t nred = (size_t)grad_reduce_chunks((int)c->cp.size(), c->kg_total) * 3 * c->natom;
+    if (c->d_gred.n < nred) c->d_gred.alloc(nred);
+    launch_grad_reduce(c->d_cp.p, (int)c->cp.size(), c->d_pg.p, c->d_kpart.p, c->kg_total, c->natom, grad,
+                       c->d_gred.p, st);
 }
 
 // V = sum_C q_C (m|1/|r - C||n): Hermite potential of every primitive pair
@@ -1417,7 +1421,9 @@ void run_potential_grad(eri_ctx *c, const double *chg, int nchg, double *gatom, 
             g.pg = c->d_pg.p + 6 * (size_t)c->cp_base[X];
             launch_jgrad(la, lb, g, st);
         }
-        launch_grad_reduce(c->d_cp.p, (int)c->cp.size(), c->d_pg.p, nullptr, 0, c->natom, gatom, st);
+        const size_t nred = (size_t)grad_reduce_chunks((int)c->cp.size(), 0) * 3 * c->natom;
+        if (c->d_gred.n < nred) c->d_gred.alloc(nred);
+        launch_grad_reduce(c->d_cp.p, (int)c->cp.size(), c->d_pg.p, nullptr, 0, c->natom, gatom, c->d_gred.p, st);
     }
     if (gchg && nchg > 0) {
         launch_fill_zero(gchg, 3 * (int64_t)nchg, st);

@@ -86,24 +86,50 @@ __global__ __launch_bounds__(64) void jgrad_pair(JGArgs g)
     }
 }
 
-// grad[atom][k] = sum over contracted pairs (in order) of their Coulomb
-// centre terms + sum over exchange workgroup partials (in order).
-__global__ void grad_reduce(const CPair *__restrict__ cp, int ncp, const double *__restrict__ pg,
-                            const double *__restrict__ kpart, int64_t nkblocks, int natom,
-                            double *__restrict__ grad)
+// grad[atom][k] = the exchange workgroup partials and the contracted pairs'
+// Coulomb centre terms, summed in a fixed order in two steps: workgroup ch
+// sums the rows of chunk ch (kGradRowsK partial rows, or kGradRowsP pairs)
+// column by column into part[ch], then one thread per column adds the
+// chunks in order.  Repeated calls give identical bits.
+constexpr int kGradRowsK = 256, kGradRowsP = 256;
+
+int grad_reduce_chunks(int ncp, int64_t nkblocks)
 {
-    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= 3 * natom) return;
-    const int atom = idx / 3, k = idx % 3;
-    double s = 0.0;
-    for (int p = 0; p < ncp; ++p) {
-        const CPair c = cp[p];
-        if (c.at1 == atom) s += pg[(int64_t)p * 6 + k];
-        if (c.at2 == atom) s += pg[(int64_t)p * 6 + 3 + k];
+    return (int)((nkblocks + kGradRowsK - 1) / kGradRowsK) + (ncp + kGradRowsP - 1) / kGradRowsP;
+}
+
+__global__ __launch_bounds__(256) void grad_chunk_sums(const CPair *__restrict__ cp, int ncp,
+                                                       const double *__restrict__ pg,
+                                                       const double *__restrict__ kpart, int64_t nkblocks,
+                                                       int natom, int nkc, double *__restrict__ part)
+{
+    const int n3 = 3 * natom, ch = blockIdx.x;
+    for (int col = threadIdx.x; col < n3; col += blockDim.x) {
+        double s = 0.0;
+        if (ch < nkc) {
+            const int64_t b0 = (int64_t)ch * kGradRowsK;
+            const int64_t b1 = b0 + kGradRowsK < nkblocks ? b0 + kGradRowsK : nkblocks;
+            for (int64_t b = b0; b < b1; ++b) s += kpart[b * n3 + col];
+        } else {
+            const int atom = col / 3, k = col % 3;
+            const int p0 = (ch - nkc) * kGradRowsP, p1 = p0 + kGradRowsP < ncp ? p0 + kGradRowsP : ncp;
+            for (int p = p0; p < p1; ++p) {
+                const CPair c = cp[p];
+                if (c.at1 == atom) s += pg[(int64_t)p * 6 + k];
+                if (c.at2 == atom) s += pg[(int64_t)p * 6 + 3 + k];
+            }
+        }
+        part[(int64_t)ch * n3 + col] = s;
     }
-    double t = 0.0;
-    for (int64_t b = 0; b < nkblocks; ++b) t += kpart[b * 3 * natom + idx];
-    grad[idx] = s + t;
+}
+
+__global__ void grad_chunk_final(const double *__restrict__ part, int nch, int n3, double *__restrict__ grad)
+{
+    const int col = blockIdx.x * blockDim.x + threadIdx.x;
+    if (col >= n3) return;
+    double s = 0.0;
+    for (int ch = 0; ch < nch; ++ch) s += part[(int64_t)ch * n3 + col];
+    grad[col] = s;
 }
 
 // E = sum_ij P_ij (J_ij / 2 - K_ij / 4), one workgroup, fixed-order tree.
@@ -136,11 +162,15 @@ void launch_jgrad(int la, int lb, const JGArgs &g, hipStream_t st)
 }
 
 void launch_grad_reduce(const CPair *cp, int ncp, const double *pg, const double *kpart, int64_t nkblocks,
-                        int natom, double *grad, hipStream_t st)
+                        int natom, double *grad, double *part, hipStream_t st)
 {
     const int n = 3 * natom;
-    hipLaunchKernelGGL(grad_reduce, dim3((unsigned)((n + 63) / 64)), dim3(64), 0, st, cp, ncp, pg, kpart,
-                       nkblocks, natom, grad);
+    const int nkc = (int)((nkblocks + kGradRowsK - 1) / kGradRowsK);
+    const int nch = grad_reduce_chunks(ncp, nkblocks);
+    if (nch > 0)
+        hipLaunchKernelGGL(grad_chunk_sums, dim3((unsigned)nch), dim3(256), 0, st, cp, ncp, pg, kpart, nkblocks,
+                           natom, nkc, part);
+    hipLaunchKernelGGL(grad_chunk_final, dim3((unsigned)((n + 63) / 64)), dim3(64), 0, st, part, nch, n, grad);
 }
 
 void launch_energy(const double *P, const double *J, const double *K, int64_t n2, double *E, hipStream_t st)

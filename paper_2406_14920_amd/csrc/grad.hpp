@@ -21,7 +21,9 @@
 //     X^{cd}_t   = sum_s (-1)^{|s|} E^{cd}_s R_{t+s},          t in H(LAB+1)
 //     Xc^{cd,k}_t = sum_s (-1)^{|s|} Ed^{C,k}_{cd,s} R_{t+s},  t in H(LAB)
 // are built cooperatively for a chunk of ket components, and lane ab
-// contracts them with its bra coefficients and the weights.  Gradient
+// contracts them with its bra coefficients and the weights (when one chunk
+// holds every ket component the intermediates are first summed over the ket
+// primitive pairs, so the contraction runs once per bra primitive pair).  Gradient
 // contributions are summed per workgroup in LDS by one lane in work order and
 // written as per-workgroup partials, which a final kernel adds in a fixed
 // order (deterministic).
@@ -109,6 +111,12 @@ __global__ __launch_bounds__(64) void kg_wave(KGArgs g)
     using C = KGCfg<LA, LB, LC, LD>;
     constexpr int NA = C::NA, NB = C::NB, NC = C::NC, ND = C::ND, NAB = C::NAB, NCD = C::NCD;
     constexpr int L = C::L, L2 = C::L2, CDCH = C::CDCH, NHX = C::NHX, NHC = C::NHC;
+    // all ket components in one chunk: the ket-contracted intermediates are
+    // linear in the ket primitive pairs' contributions and the bra terms depend
+    // on the bra primitive pair only, so the intermediates are summed over the
+    // ket primitive pairs and the bra contraction runs once per bra primitive
+    // pair (as the forward kernel's ket-first form does)
+    constexpr bool KACC = NCD <= CDCH;
     const KArgs &a = g.k;
 
     __shared__ double sR0[C::NR0];
@@ -170,82 +178,9 @@ __global__ __launch_bounds__(64) void kg_wave(KGArgs g)
 
             double gA[3] = {0.0, 0.0, 0.0}, gS[3] = {0.0, 0.0, 0.0}, gC[3] = {0.0, 0.0, 0.0};
             const double qk0 = a.pp[B.poff].q;
-            for (int ip = 0; ip < A.np; ++ip) {
-                const PrimPair pb = a.pp[A.poff + ip];
-                if (pb.q * qk0 < a.tau_prim) break;
-                for (int kp = 0; kp < B.np; ++kp) {
-                    const PrimPair pk = a.pp[B.poff + kp];
-                    if (pb.q * pk.q < a.tau_prim) break;
-                    const QuartetGeo geo = quartet_geo(pb, pk, a.om2);
-                    wave_boys<L + 1>(geo, a.boys, sF, lane);
-                    wave_hpoly<L + 1>(geo, sH, lane);
-                    if (lane >= 8 && lane < 11) {
-                        const int k = lane - 8;
-                        const double pa = k == 0 ? pb.PA[0] : (k == 1 ? pb.PA[1] : pb.PA[2]);
-                        const double pbb = k == 0 ? pb.PB[0] : (k == 1 ? pb.PB[1] : pb.PB[2]);
-                        etab_lds<LA + 1, LB>(pa, pbb, pb.o2p, sEb + k * C::EBD);
-                    } else if (lane >= 16 && lane < 19) {
-                        const int k = lane - 16;
-                        const double pa = k == 0 ? pk.PA[0] : (k == 1 ? pk.PA[1] : pk.PA[2]);
-                        const double pbb = k == 0 ? pk.PB[0] : (k == 1 ? pk.PB[1] : pk.PB[2]);
-                        etab_lds<LC + 1, LD>(pa, pbb, pk.o2p, sEk + k * C::EKD);
-                    }
-                    __syncthreads();
-                    wave_r0h<L + 1>(sF, sH, sHerm, sR0, lane);
-                    __syncthreads();
-                    const double a2 = 2.0 * pb.a, c2 = 2.0 * pk.a;
-
-                    for (int cd0 = 0; cd0 < NCD; cd0 += CDCH) {
-                        const int ncd = (cd0 + CDCH < NCD) ? CDCH : NCD - cd0;
-                        // ket coefficient lists of this chunk: for component cd and
-                        // kq (0: E^{cd}, 1..3: its derivative along x, y, z) the
-                        // coefficients (-1)^{|s|} Ed_s over the (extended) ket box and
-                        // the R offsets of the box points, padded to KBM with zeros
-                        for (int o = lane; o < 4 * ncd * C::KBM; o += 64) {
-                            const int k = o % C::KBM, c = (o / C::KBM) % ncd, kq = o / (C::KBM * ncd);
-                            const int kdir = kq - 1, cd = cd0 + c;
-                            int cx, cy, cz, dx, dy, dz;
-                            cart_rt(LC, cd / ND, cx, cy, cz);
-                            cart_rt(LD, cd % ND, dx, dy, dz);
-                            const int mx = cx + dx + 1 + (kdir == 0), my = cy + dy + 1 + (kdir == 1),
-                                      mz = cz + dz + 1 + (kdir == 2);
-                            double coef = 0.0;
-                            int off = 0;
-                            if (k < mx * my * mz) {
-                                const int sx = k / (my * mz), sy = (k / mz) % my, sz = k % mz;
-                                const double *Ex = sEk, *Ey = sEk + C::EKD, *Ez = sEk + 2 * C::EKD;
-                                const double ex = kdir == 0 ? dcoef(Ex, C::EKI, C::EKJ, cx, dx, sx, c2)
-                                                            : Ex[cx * C::EKI + dx * C::EKJ + sx];
-                                const double ey = kdir == 1 ? dcoef(Ey, C::EKI, C::EKJ, cy, dy, sy, c2)
-                                                            : Ey[cy * C::EKI + dy * C::EKJ + sy];
-                                const double ez = kdir == 2 ? dcoef(Ez, C::EKI, C::EKJ, cz, dz, sz, c2)
-                                                            : Ez[cz * C::EKI + dz * C::EKJ + sz];
-                                coef = ((sx + sy + sz) & 1) ? -ex * ey * ez : ex * ey * ez;
-                                off = (sx * L2 + sy) * L2 + sz;
-                            }
-                            sEc[(kq * CDCH + c) * C::KBM + k] = coef;
-                            sEo[(kq * CDCH + c) * C::KBM + k] = off;
-                        }
-                        __syncthreads();
-                        // ket-contracted intermediates of this chunk: one dot product
-                        // of a coefficient list with R around t per output (the
-                        // padding adds zeros times R_t, inside the table)
-                        for (int o = lane; o < ncd * (NHX + 3 * NHC); o += 64) {
-                            int c, t, kq;
-                            if (o < ncd * NHX) { c = o / NHX; t = o % NHX; kq = 0; }
-                            else { const int r = o - ncd * NHX; kq = 1 + r / (ncd * NHC); c = (r / NHC) % ncd; t = r % NHC; }
-                            const int code = c_herm.tuv[t];
-                            const int tb = ((code & 0xff) * L2 + ((code >> 8) & 0xff)) * L2 + (code >> 16);
-                            const double *ec = sEc + (kq * CDCH + c) * C::KBM;
-                            const int *eo = sEo + (kq * CDCH + c) * C::KBM;
-                            double acc = 0.0;
-#pragma unroll
-                            for (int k = 0; k < C::KBM; ++k) acc += ec[k] * sR0[tb + eo[k]];
-                            if (kq == 0) sX[c * NHX + t] = acc;
-                            else sXc[((kq - 1) * CDCH + c) * NHC + t] = acc;
-                        }
-                        __syncthreads();
-
+            // bra contraction of the chunk [cd0, cd0 + ncd) held in sX, sXc: lane ab
+            // adds its weighted terms into gA, gS, gC
+            auto bra_pass = [&](int cd0, int ncd, double a2) {
                         for (int r = 0; r < C::NABCH; ++r) {
                             const int ab = r * 64 + lane;
                             if (ab >= NAB) continue;
@@ -315,8 +250,96 @@ __global__ __launch_bounds__(64) void kg_wave(KGArgs g)
                                 }
                             }
                         }
-                        __syncthreads();
+            };
+            for (int ip = 0; ip < A.np; ++ip) {
+                const PrimPair pb = a.pp[A.poff + ip];
+                if (pb.q * qk0 < a.tau_prim) break;
+                if constexpr (KACC) {  // ket sums of this bra primitive pair start at zero
+                    for (int o = lane; o < NCD * NHX; o += 64) sX[o] = 0.0;
+                    for (int o = lane; o < 3 * CDCH * NHC; o += 64) sXc[o] = 0.0;
+                }
+                for (int kp = 0; kp < B.np; ++kp) {
+                    const PrimPair pk = a.pp[B.poff + kp];
+                    if (pb.q * pk.q < a.tau_prim) break;
+                    const QuartetGeo geo = quartet_geo(pb, pk, a.om2);
+                    wave_boys<L + 1>(geo, a.boys, sF, lane);
+                    wave_hpoly<L + 1>(geo, sH, lane);
+                    if (lane >= 8 && lane < 11) {
+                        const int k = lane - 8;
+                        const double pa = k == 0 ? pb.PA[0] : (k == 1 ? pb.PA[1] : pb.PA[2]);
+                        const double pbb = k == 0 ? pb.PB[0] : (k == 1 ? pb.PB[1] : pb.PB[2]);
+                        etab_lds<LA + 1, LB>(pa, pbb, pb.o2p, sEb + k * C::EBD);
+                    } else if (lane >= 16 && lane < 19) {
+                        const int k = lane - 16;
+                        const double pa = k == 0 ? pk.PA[0] : (k == 1 ? pk.PA[1] : pk.PA[2]);
+                        const double pbb = k == 0 ? pk.PB[0] : (k == 1 ? pk.PB[1] : pk.PB[2]);
+                        etab_lds<LC + 1, LD>(pa, pbb, pk.o2p, sEk + k * C::EKD);
                     }
+                    __syncthreads();
+                    wave_r0h<L + 1>(sF, sH, sHerm, sR0, lane);
+                    __syncthreads();
+                    const double a2 = 2.0 * pb.a, c2 = 2.0 * pk.a;
+
+                    for (int cd0 = 0; cd0 < NCD; cd0 += CDCH) {
+                        const int ncd = (cd0 + CDCH < NCD) ? CDCH : NCD - cd0;
+                        // ket coefficient lists of this chunk: for component cd and
+                        // kq (0: E^{cd}, 1..3: its derivative along x, y, z) the
+                        // coefficients (-1)^{|s|} Ed_s over the (extended) ket box and
+                        // the R offsets of the box points, padded to KBM with zeros
+                        for (int o = lane; o < 4 * ncd * C::KBM; o += 64) {
+                            const int k = o % C::KBM, c = (o / C::KBM) % ncd, kq = o / (C::KBM * ncd);
+                            const int kdir = kq - 1, cd = cd0 + c;
+                            int cx, cy, cz, dx, dy, dz;
+                            cart_rt(LC, cd / ND, cx, cy, cz);
+                            cart_rt(LD, cd % ND, dx, dy, dz);
+                            const int mx = cx + dx + 1 + (kdir == 0), my = cy + dy + 1 + (kdir == 1),
+                                      mz = cz + dz + 1 + (kdir == 2);
+                            double coef = 0.0;
+                            int off = 0;
+                            if (k < mx * my * mz) {
+                                const int sx = k / (my * mz), sy = (k / mz) % my, sz = k % mz;
+                                const double *Ex = sEk, *Ey = sEk + C::EKD, *Ez = sEk + 2 * C::EKD;
+                                const double ex = kdir == 0 ? dcoef(Ex, C::EKI, C::EKJ, cx, dx, sx, c2)
+                                                            : Ex[cx * C::EKI + dx * C::EKJ + sx];
+                                const double ey = kdir == 1 ? dcoef(Ey, C::EKI, C::EKJ, cy, dy, sy, c2)
+                                                            : Ey[cy * C::EKI + dy * C::EKJ + sy];
+                                const double ez = kdir == 2 ? dcoef(Ez, C::EKI, C::EKJ, cz, dz, sz, c2)
+                                                            : Ez[cz * C::EKI + dz * C::EKJ + sz];
+                                coef = ((sx + sy + sz) & 1) ? -ex * ey * ez : ex * ey * ez;
+                                off = (sx * L2 + sy) * L2 + sz;
+                            }
+                            sEc[(kq * CDCH + c) * C::KBM + k] = coef;
+                            sEo[(kq * CDCH + c) * C::KBM + k] = off;
+                        }
+                        __syncthreads();
+                        // ket-contracted intermediates of this chunk: one dot product
+                        // of a coefficient list with R around t per output (the
+                        // padding adds zeros times R_t, inside the table)
+                        for (int o = lane; o < ncd * (NHX + 3 * NHC); o += 64) {
+                            int c, t, kq;
+                            if (o < ncd * NHX) { c = o / NHX; t = o % NHX; kq = 0; }
+                            else { const int r = o - ncd * NHX; kq = 1 + r / (ncd * NHC); c = (r / NHC) % ncd; t = r % NHC; }
+                            const int code = c_herm.tuv[t];
+                            const int tb = ((code & 0xff) * L2 + ((code >> 8) & 0xff)) * L2 + (code >> 16);
+                            const double *ec = sEc + (kq * CDCH + c) * C::KBM;
+                            const int *eo = sEo + (kq * CDCH + c) * C::KBM;
+                            double acc = 0.0;
+#pragma unroll
+                            for (int k = 0; k < C::KBM; ++k) acc += ec[k] * sR0[tb + eo[k]];
+                            double &dst = kq == 0 ? sX[c * NHX + t] : sXc[((kq - 1) * CDCH + c) * NHC + t];
+                            if constexpr (KACC) dst += acc; else dst = acc;
+                        }
+                        __syncthreads();
+
+                        if constexpr (!KACC) {
+                            bra_pass(cd0, ncd, a2);
+                            __syncthreads();
+                        }
+                    }
+                }
+                if constexpr (KACC) {  // one bra contraction per bra primitive pair
+                    bra_pass(0, NCD, 2.0 * pb.a);
+                    __syncthreads();
                 }
             }
             // wave sums (fixed butterfly), then one lane adds the four centres in order

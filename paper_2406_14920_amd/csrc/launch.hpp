@@ -65,8 +65,12 @@ bool launch_kg_1(int la, int lb, int lc, int ld, const KGArgs &g, int blocks, hi
 bool launch_kg_2(int la, int lb, int lc, int ld, const KGArgs &g, int blocks, hipStream_t st);
 bool launch_kg_3(int la, int lb, int lc, int ld, const KGArgs &g, int blocks, hipStream_t st);
 void launch_jgrad(int la, int lb, const JGArgs &g, hipStream_t st);
+// Fixed-order sum of the exchange partials and Coulomb pair terms into
+// grad (natom x 3); part holds grad_reduce_chunks(ncp, nkblocks) x 3 natom
+// doubles of scratch.
+int grad_reduce_chunks(int ncp, int64_t nkblocks);
 void launch_grad_reduce(const CPair *cp, int ncp, const double *pg, const double *kpart, int64_t nkblocks,
-                        int natom, double *grad, hipStream_t st);
+                        int natom, double *grad, double *part, hipStream_t st);
 void launch_energy(const double *P, const double *J, const double *K, int64_t n2, double *E, hipStream_t st);
 
 // grid.hip: bounding spheres of 64-point blocks; density (and gradient, if
