@@ -1244,7 +1244,7 @@ void ensure_grad(eri_ctx *c)
         const auto &w = c->kwork[wi];
         // small classes: a lane per quartet (64 per workgroup step); others a
         // workgroup per kKgRange quartets
-        const int per = is_k_small(kPairL[w.X][0], kPairL[w.X][1], kPairL[w.Y][0], kPairL[w.Y][1]) ? 64 : kKgRange;
+        const int per = kg_small_class(kPairL[w.X][0], kPairL[w.X][1], kPairL[w.Y][0], kPairL[w.Y][1]) ? 64 : kKgRange;
         const int64_t ranges = (w.nwork + per - 1) / per;
         c->kg_blocks[wi] = (int)std::min<int64_t>(ranges, kKgMaxBlocks);
         c->kg_off[wi] = c->kg_total;

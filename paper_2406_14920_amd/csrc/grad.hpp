@@ -30,6 +30,7 @@
 #pragma once
 #include "class_lists.hpp"
 #include "kern_args.hpp"
+#include "launch.hpp"
 #include "md_device.hpp"
 #include "wave_r.hpp"
 
@@ -87,12 +88,15 @@ struct KGCfg {
     static constexpr int EKJ = LCD + 2, EKI = (LD + 1) * EKJ, EKD = (LC + 2) * EKI;
     static constexpr int ND_ = NA * NC + NA * ND + NB * NC + NB * ND;
     static constexpr int KBM = box_max_ext(LC, LD);  // longest ket coefficient list
-    // ket components per chunk: the largest of 16, 8, 4 whose tables fit in
-    // 40 KB of LDS, so that four of these one-wave workgroups share a compute
-    // unit (one per SIMD; the largest classes hold 256 VGPRs, one wave per SIMD)
-    static constexpr int CDCH0 = kg_lds_bytes(L, NR0, EBD, EKD, NHX, NHC, ND_, KBM, 16) <= 40960  ? 16
-                                 : kg_lds_bytes(L, NR0, EBD, EKD, NHX, NHC, ND_, KBM, 8) <= 40960 ? 8
-                                                                                                  : 4;
+    // ket components per chunk: all of them (up to 24) if their tables fit in
+    // 40 KB of LDS, else the largest of 16, 8, 4 that fits, so that four of
+    // these one-wave workgroups share a compute unit (one per SIMD; the
+    // largest classes hold 256 VGPRs, one wave per SIMD)
+    static constexpr bool ALL = NCD <= 24 && kg_lds_bytes(L, NR0, EBD, EKD, NHX, NHC, ND_, KBM, NCD) <= 40960;
+    static constexpr int CDCH0 = ALL ? NCD
+                                 : kg_lds_bytes(L, NR0, EBD, EKD, NHX, NHC, ND_, KBM, 16) <= 40960 ? 16
+                                 : kg_lds_bytes(L, NR0, EBD, EKD, NHX, NHC, ND_, KBM, 8) <= 40960  ? 8
+                                                                                                   : 4;
     static constexpr int CDCH = NCD < CDCH0 ? NCD : CDCH0;
     static constexpr int RANGE = 4;
 };
@@ -620,16 +624,10 @@ void launch_kg_small_t(const KGArgs &g, int blocks, hipStream_t st)
 
 namespace md {
 
-// the lane-per-quartet kernel serves the classes the energy path serves the
-// same way (all their blocks fit in registers)
 template <int LA, int LB, int LC, int LD>
 constexpr bool kg_use_small()
 {
-    bool r = false;
-#define MD_IS(A_, B_, C_, D_) r = r || (LA == A_ && LB == B_ && LC == C_ && LD == D_);
-    MD_K_SMALL_LIST(MD_IS)
-#undef MD_IS
-    return r;
+    return kg_small_class(LA, LB, LC, LD);
 }
 
 template <int LA, int LB, int LC, int LD>

@@ -65,6 +65,19 @@ bool launch_kg_1(int la, int lb, int lc, int ld, const KGArgs &g, int blocks, hi
 bool launch_kg_2(int la, int lb, int lc, int ld, const KGArgs &g, int blocks, hipStream_t st);
 bool launch_kg_3(int la, int lb, int lc, int ld, const KGArgs &g, int blocks, hipStream_t st);
 void launch_jgrad(int la, int lb, const JGArgs &g, hipStream_t st);
+// Exchange-gradient classes served by the lane-per-quartet kernel kg_small
+// (every table in registers); the others use the wavefront kernel kg_wave.
+// The larger lane-per-quartet classes spill kilobytes per lane and run
+// faster as wavefronts summing over the ket primitive pairs (timed per class).
+__host__ __device__ constexpr bool kg_small_class(int la, int lb, int lc, int ld)
+{
+    return (la == 0 && lb == 0 && lc == 0 && ld == 0) || (la == 1 && lb == 0 && lc == 0 && ld == 0) ||
+           (la == 1 && lb == 0 && lc == 1 && ld == 0) || (la == 1 && lb == 1 && lc == 0 && ld == 0) ||
+           (la == 1 && lb == 1 && lc == 1 && ld == 0) || (la == 2 && lb == 0 && lc == 0 && ld == 0) ||
+           (la == 2 && lb == 0 && lc == 1 && ld == 0) || (la == 2 && lb == 0 && lc == 1 && ld == 1) ||
+           (la == 2 && lb == 0 && lc == 2 && ld == 0) || (la == 3 && lb == 0 && lc == 0 && ld == 0);
+}
+
 // Fixed-order sum of the exchange partials and Coulomb pair terms into
 // grad (natom x 3); part holds grad_reduce_chunks(ncp, nkblocks) x 3 natom
 // doubles of scratch.
