@@ -89,10 +89,12 @@ struct KGCfg {
     static constexpr int ND_ = NA * NC + NA * ND + NB * NC + NB * ND;
     static constexpr int KBM = box_max_ext(LC, LD);  // longest ket coefficient list
     // ket components per chunk: all of them (up to 24) if their tables fit in
-    // 40 KB of LDS, else the largest of 16, 8, 4 that fits, so that four of
-    // these one-wave workgroups share a compute unit (one per SIMD; the
-    // largest classes hold 256 VGPRs, one wave per SIMD)
-    static constexpr bool ALL = NCD <= 24 && kg_lds_bytes(L, NR0, EBD, EKD, NHX, NHC, ND_, KBM, NCD) <= 40960;
+    // 48 KB of LDS (three workgroups per compute unit; one chunk lets the
+    // intermediates be summed over the ket primitive pairs, worth more than
+    // the fourth workgroup), else the largest of 16, 8, 4 whose tables fit in
+    // 40 KB, so that four of these one-wave workgroups share a compute unit
+    // (one per SIMD; the largest classes hold 256 VGPRs, one wave per SIMD)
+    static constexpr bool ALL = NCD <= 24 && kg_lds_bytes(L, NR0, EBD, EKD, NHX, NHC, ND_, KBM, NCD) <= 49152;
     static constexpr int CDCH0 = ALL ? NCD
                                  : kg_lds_bytes(L, NR0, EBD, EKD, NHX, NHC, ND_, KBM, 16) <= 40960 ? 16
                                  : kg_lds_bytes(L, NR0, EBD, EKD, NHX, NHC, ND_, KBM, 8) <= 40960  ? 8
