@@ -99,10 +99,33 @@ def cpu_baseline(mol, target_s: float = 15.0):
     oracle.quartet_batch(B, q, tau_prim)
     dt = time.perf_counter() - t
     eris = float(np.sum(nsph[q[:, 0]] * nsph[q[:, 1]] * nsph[q[:, 2]] * nsph[q[:, 3]]))
-    return {"value": eris / dt, "unit": "ERIs/s", "cores": oracle.num_threads(), "kind": "oracle",
+    threads = oracle.num_threads()
+    # one thread on a sub-sample of about 3 s
+    k1 = max(2000, int(k * min(1.0, 3.0 / max(target_s, 1e-3)) / max(threads, 1)))
+    q1 = q[:k1]
+    oracle.set_threads(1)
+    try:
+        t = time.perf_counter()
+        oracle.quartet_batch(B, q1, tau_prim)
+        dt1 = time.perf_counter() - t
+    finally:
+        oracle.set_threads(threads)
+    eris1 = float(np.sum(nsph[q1[:, 0]] * nsph[q1[:, 1]] * nsph[q1[:, 2]] * nsph[q1[:, 3]]))
+    return {"value": eris / dt, "unit": "ERIs/s", "cores": threads, "kind": "oracle",
             "sample": "%d uniformly drawn kept shell quartets of mol40 (each evaluated once, "
                       "spherical blocks), %.1f s" % (k, dt),
-            "sample_seconds": dt}
+            "sample_seconds": dt, "cpu_model": _cpu_model(),
+            "single_thread": {"value": eris1 / dt1, "unit": "ERIs/s", "quartets": k1, "seconds": dt1}}
+
+
+def _cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def _xsteps(a) -> int:

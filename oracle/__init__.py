@@ -87,6 +87,7 @@ def lib():
         L.oracle_quartet_batch.argtypes = bas + [dp, ip] + qp + [ctypes.c_int64, ip]
         L.oracle_quartet_batch.restype = ctypes.c_double
         L.oracle_num_threads.restype = ctypes.c_int
+        L.oracle_set_threads.argtypes = [ctypes.c_int]
         L.oracle_vmatrix.argtypes = bas + [dp, ip, ip, ctypes.c_int32, ctypes.c_int32, dp, dp]
         L.oracle_vgrad.argtypes = bas + [dp, ip, ip, ctypes.c_int32, ctypes.c_int32, dp, dp, dp, dp]
         L.oracle_prim_vblock.argtypes = [ctypes.c_int, ctypes.c_int, dp, dp, ctypes.c_int32, dp, dp]
@@ -499,6 +500,11 @@ def quartet_batch(B: "OBasis", quartets, tau_prim: float) -> float:
 
 def num_threads() -> int:
     return int(lib().oracle_num_threads())
+
+
+def set_threads(n: int) -> None:
+    """Threads of the oracle's parallel loops from now on (timing only)."""
+    lib().oracle_set_threads(int(n))
 
 
 sph_matrix = _basis.sph_matrix

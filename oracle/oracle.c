@@ -943,6 +943,17 @@ double oracle_quartet_batch(int32_t nshell, int32_t natom, const int32_t *atom, 
     return total;
 }
 
+/* Threads of the parallel loops that follow (timing only; the results do
+ * not depend on it). */
+void oracle_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 int oracle_num_threads(void)
 {
 #ifdef _OPENMP
