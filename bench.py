@@ -431,11 +431,26 @@ def bench_batch(a):
     ms_streams = _time(lambda: b.jk(Ps), _xsteps(a))
     lat_streams = _lat(b)
     ms_seq = _time(lambda: [jk.jk(P) for jk, P in zip(jks, Ps)], _xsteps(a))
+    # FP32-mixed batch in queue mode against the FP64 results
+    b.set_mode("queue")
+    J64, K64 = b.jk(Ps)
+    J64 = [t.clone() for t in J64]
+    K64 = [t.clone() for t in K64]
+    for jk in jks:
+        jk.set_precision("mixed")
+    b.jk(Ps)
+    ms_mixed = _time(lambda: b.jk(Ps), _xsteps(a))
+    lat_mixed = _lat(b)
+    Jm, Km = b.jk(Ps)
+    torch.cuda.synchronize()
+    dj = max(float((x - y).abs().max()) for x, y in zip(Jm, J64))
+    dk = max(float((x - y).abs().max()) for x, y in zip(Km, K64))
     b.close()
     for jk in jks:
         jk.close()
-    print("batch64: queue %.1f ms, streams %.1f ms, one by one %.1f ms (setup %.1fs, first queue call %.1fs)"
-          % (ms_queue, ms_streams, ms_seq, setup_s, plan_s), file=sys.stderr, flush=True)
+    print("batch64: queue %.1f ms, streams %.1f ms, one by one %.1f ms, mixed (queue) %.1f ms "
+          "(setup %.1fs, first queue call %.1fs)" % (ms_queue, ms_streams, ms_seq, ms_mixed, setup_s, plan_s),
+          file=sys.stderr, flush=True)
     m40 = synth.mol40()
     jk40 = JK.from_molecule(m40)
     P40 = torch.tensor(m40.P, dtype=torch.float64, device="cuda")
@@ -457,6 +472,9 @@ def bench_batch(a):
             "per_molecule_latency_ms": lat_queue,
             "ms_per_batch_streams": ms_streams, "per_molecule_latency_ms_streams": lat_streams,
             "ms_per_batch_one_by_one": ms_seq,
+            "mixed": {"ms_per_batch": ms_mixed, "eris_per_s": eris / (ms_mixed / 1e3), "launch": "queue mode",
+                      "per_molecule_latency_ms": lat_mixed, "max_abs_dJ_vs_fp64": dj, "max_abs_dK_vs_fp64": dk,
+                      "mixed_thresh": 1e-5},
             "latency_of": "last timed call, from its start to each molecule's completion (HIP events)",
             "mol40_as_batch_of_one": {"queue_ms": ms40_queue, "build_jk_ms": ms40_direct,
                                       "queue_launches": info40["launches"], "queue_items": info40["items"]}}

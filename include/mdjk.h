@@ -356,9 +356,10 @@ int eri_set_tuning(eri_ctx *ctx, const eri_tuning_t *in);
  * build_jk on each context (up to the order of floating-point atomic
  * additions).  Asynchronous on the batch stream.  Two ways to run it
  * (eri_batch_set_mode):
- *  - ERI_BATCH_QUEUE (the default; used when every context is in ERI_FP64,
- *    else the batch runs as ERI_BATCH_STREAMS): the J-engine and exchange
- *    work of all molecules runs as ONE launch per kernel (angular class):
+ *  - ERI_BATCH_QUEUE (the default): the J-engine and exchange work of all
+ *    molecules runs as ONE launch per kernel (angular class and arithmetic
+ *    type; under ERI_MIXED* a class's double- and single-precision shares
+ *    are two kernels, as in build_jk):
  *    the blocks every molecule's own launch would have had become the items
  *    of a device-side work list, the launches with the most work per block
  *    first, and workgroup b runs item b, so the hardware dispatcher hands

@@ -221,7 +221,7 @@ class JK:
 
 class Batch:
     """Many JK contexts built together (eri_batch_*).  mode "queue" (the
-    default; double-precision contexts): one launch per kernel for the whole
+    default): one launch per kernel (and arithmetic type) for the whole
     batch, whose workgroups run the blocks of every molecule's launch from a
     device-side work list, most work first; mode "streams": every molecule's build forked from the batch
     stream onto one of a few streams, largest first, and joined back.

@@ -2305,7 +2305,9 @@ void batch_record(eri_batch *b)
 }
 
 // Queue plan: every molecule's J-engine and exchange launches (as build_jk
-// would issue them in double precision) are recorded instead of issued and
+// would issue them, in its precision mode: under ERI_MIXED* the double- and
+// single-precision shares are separate launches of different kernels) are
+// recorded instead of issued and
 // grouped by kernel; each group becomes one launch whose items are the
 // blocks of its molecules' launches, the launches with the most work per
 // block first.  Rebuilt whenever a context changes.
@@ -2319,12 +2321,17 @@ void batch_plan_queue(eri_batch *b)
     for (const int i : b->order) {
         eri_ctx *c = b->ctxs[(size_t)i];
         recs.clear();
+        const bool mixed = c->opts.precision != ERI_FP64;
+        if (mixed) {
+            ensure_mixed(c);  // single-precision Hermite products, made on the context stream
+            HIPCHK(hipStreamSynchronize(c->st));
+        }
         const bool prof = c->profile;
         c->profile = false;
         queue_sink() = &recs;
         try {
-            j_classes(c, false, nullptr);
-            run_k(c, false, nullptr, nullptr);
+            j_classes(c, mixed, nullptr);
+            run_k(c, mixed, nullptr, nullptr);
         } catch (...) {
             queue_sink() = nullptr;
             c->profile = prof;
@@ -2334,7 +2341,7 @@ void batch_plan_queue(eri_batch *b)
         c->profile = prof;
         for (const QueueRec &r : recs) {
             if (!r.fn) {
-                set_err(ERI_ESTATE, "queue launches serve double-precision builds only (molecule %d)", i);
+                set_err(ERI_ESTATE, "no batch form of a %s launch (molecule %d)", r.kind, i);
                 throw HipError{ERI_ESTATE};
             }
             auto it = index.find(r.fn);
@@ -2408,15 +2415,16 @@ void batch_build_queue(eri_batch *b, const double *const *P, double *const *J, d
         const bool prof = c->profile;
         c->profile = false;
         const int nc = c->nbf_cart;
+        const bool mixed = c->opts.precision != ERI_FP64;
         launch_p_to_cart(P[i], c->nbf, c->wk.Pc, nc, shell_map(c), c->opts.spherical, st);
-        if (c->tau_dens > 0.0)
+        if (mixed || c->tau_dens > 0.0)
             launch_density_bounds(c->wk.Pc, nc, c->d_l.p, c->d_coff.p, c->nshell, c->d_Pm.p, c->d_cp.p, c->d_Q.p,
                                   (int)c->cp.size(), c->d_QD.p, st);
-        c->built_mixed = false;
+        c->built_mixed = mixed;
         c->mix_counts_ok = false;
         launch_fill_zero(c->wk.Jacc, (int64_t)nc * nc, st);
         launch_fill_zero(c->wk.Kacc, (int64_t)nc * nc, st);
-        j_prologue(c, false, st);
+        j_prologue(c, mixed, st);
         c->profile = prof;
     }
     HIPCHK(hipEventRecord(b->qev[0], st));
@@ -2520,10 +2528,7 @@ int eri_batch_build_jk(eri_batch *b, const double *const *P, double *const *J, d
         if (!P[i] || !J[i] || !K[i]) return set_err(ERI_EINVAL, "null P/J/K for molecule %zu", i);
     }
     try {
-        bool queue = b->mode == ERI_BATCH_QUEUE;
-        for (size_t i = 0; queue && i < n; ++i)
-            if (b->ctxs[i]->opts.precision != ERI_FP64) queue = false;
-        if (queue) {
+        if (b->mode == ERI_BATCH_QUEUE) {
             hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
             HIPCHK(hipStreamIsCapturing(b->st, &cap));
             if (cap != hipStreamCaptureStatusNone && !batch_queue_ready(b))

@@ -206,15 +206,15 @@ __global__ __launch_bounds__(64) void jeng_small(JArgs a)
     jeng_small_run<LX, LY, T>(a, blockIdx.x, blockIdx.y);
 }
 
-// batch form (double precision): workgroup b runs block (items[b].y, items[b].z)
-// of the launch whose arguments are tab[items[b].x]
-template <int LX, int LY>
+// batch form: workgroup b runs block (items[b].y, items[b].z) of the
+// launch whose arguments are tab[items[b].x]
+template <int LX, int LY, typename T>
 __global__ __launch_bounds__(64) void jeng_small_q(const JArgs *__restrict__ tab, const int4 *__restrict__ items)
 {
     const int4 it = items[blockIdx.x];
     JArgs a = tab[it.x];
     globalize(a);
-    jeng_small_run<LX, LY, double>(a, it.y, it.z);
+    jeng_small_run<LX, LY, T>(a, it.y, it.z);
 }
 
 // ---------------------------------------------------------------------------
@@ -319,15 +319,15 @@ __global__ __launch_bounds__(64) void jeng_wave(JArgs a)
     jeng_wave_run<LX, LY, T>(a, blockIdx.x, blockIdx.y);
 }
 
-// batch form (double precision): workgroup b runs block (items[b].y, items[b].z)
-// of the launch whose arguments are tab[items[b].x]
-template <int LX, int LY>
+// batch form: workgroup b runs block (items[b].y, items[b].z) of the
+// launch whose arguments are tab[items[b].x]
+template <int LX, int LY, typename T>
 __global__ __launch_bounds__(64) void jeng_wave_q(const JArgs *__restrict__ tab, const int4 *__restrict__ items)
 {
     const int4 it = items[blockIdx.x];
     JArgs a = tab[it.x];
     globalize(a);
-    jeng_wave_run<LX, LY, double>(a, it.y, it.z);
+    jeng_wave_run<LX, LY, T>(a, it.y, it.z);
 }
 
 // out[i] += sum over the chunks c = 0, 1, ... of part[c * stride + i], in that
@@ -450,13 +450,13 @@ void jeng_launch_t(const JArgs &a, hipStream_t st)
     if (a.nbp <= 0 || nch <= 0) return;
     constexpr bool SMALL = LX + LY <= kJengRegMaxL;
     const dim3 grid(SMALL ? (a.nbp + 63) / 64 : a.nbp, nch);
-    if (queue_sink()) {  // a batch plan (builds only: bra order at most 6, double precision)
+    if (queue_sink()) {  // a batch plan (builds only: bra order at most 6)
         QueueLaunchFn fn = nullptr;
-        if constexpr (LX <= 6 && sizeof(T) == 8) {
+        if constexpr (LX <= 6) {
             if constexpr (SMALL)
-                fn = &queue_launch<JArgs, jeng_small_q<LX, LY>, 64>;
+                fn = &queue_launch<JArgs, jeng_small_q<LX, LY, T>, 64>;
             else
-                fn = &queue_launch<JArgs, jeng_wave_q<LX, LY>, 64>;
+                fn = &queue_launch<JArgs, jeng_wave_q<LX, LY, T>, 64>;
         }
         queue_record(fn, a, (int)grid.x, nch, (double)(a.kchunk < a.nket ? a.kchunk : a.nket),
                      SMALL ? "jeng_small" : "jeng_wave");

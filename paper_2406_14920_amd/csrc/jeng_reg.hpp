@@ -176,15 +176,15 @@ __global__ __launch_bounds__(64) void jeng_reg(JArgs a)
     jeng_reg_run<LX, LY, T>(a, blockIdx.x, blockIdx.y);
 }
 
-// batch form (double precision): workgroup b runs block (items[b].y, items[b].z)
-// of the launch whose arguments are tab[items[b].x]
-template <int LX, int LY>
+// batch form: workgroup b runs block (items[b].y, items[b].z) of the
+// launch whose arguments are tab[items[b].x]
+template <int LX, int LY, typename T>
 __global__ __launch_bounds__(64) void jeng_reg_q(const JArgs *__restrict__ tab, const int4 *__restrict__ items)
 {
     const int4 it = items[blockIdx.x];
     JArgs a = tab[it.x];
     globalize(a);
-    jeng_reg_run<LX, LY, double>(a, it.y, it.z);
+    jeng_reg_run<LX, LY, T>(a, it.y, it.z);
 }
 
 // register J-engine is used where its live set (Hermite J, Boys values,
@@ -197,16 +197,16 @@ __host__ __device__ constexpr bool jeng_reg_ok(int lx, int ly)
 
 // The queue forms are instantiated in translation units of their own
 // (jeng_reg_q_*.hip), which compile in parallel with the direct ones.
-QueueLaunchFn jeng_reg_queue_fn_0(int lx, int ly);
-QueueLaunchFn jeng_reg_queue_fn_1(int lx, int ly);
-QueueLaunchFn jeng_reg_queue_fn_2(int lx, int ly);
-QueueLaunchFn jeng_reg_queue_fn_3(int lx, int ly);
-inline QueueLaunchFn jeng_reg_queue_fn(int lx, int ly)
+QueueLaunchFn jeng_reg_queue_fn_0(int lx, int ly, bool fp32);
+QueueLaunchFn jeng_reg_queue_fn_1(int lx, int ly, bool fp32);
+QueueLaunchFn jeng_reg_queue_fn_2(int lx, int ly, bool fp32);
+QueueLaunchFn jeng_reg_queue_fn_3(int lx, int ly, bool fp32);
+inline QueueLaunchFn jeng_reg_queue_fn(int lx, int ly, bool fp32)
 {
-    QueueLaunchFn f = jeng_reg_queue_fn_0(lx, ly);
-    if (!f) f = jeng_reg_queue_fn_1(lx, ly);
-    if (!f) f = jeng_reg_queue_fn_2(lx, ly);
-    if (!f) f = jeng_reg_queue_fn_3(lx, ly);
+    QueueLaunchFn f = jeng_reg_queue_fn_0(lx, ly, fp32);
+    if (!f) f = jeng_reg_queue_fn_1(lx, ly, fp32);
+    if (!f) f = jeng_reg_queue_fn_2(lx, ly, fp32);
+    if (!f) f = jeng_reg_queue_fn_3(lx, ly, fp32);
     return f;
 }
 
@@ -217,7 +217,7 @@ void jeng_reg_launch_t(const JArgs &a, bool fp32, hipStream_t st)
     if (a.nbp <= 0 || nch <= 0) return;
     dim3 grid((a.nbp + 63) / 64, nch);
     if (queue_sink()) {  // a batch plan: a wavefront of bra pairs against one ket chunk per block
-        queue_record(fp32 ? nullptr : jeng_reg_queue_fn(LX, LY), a, (int)grid.x, nch,
+        queue_record(jeng_reg_queue_fn(LX, LY, fp32), a, (int)grid.x, nch,
                      (double)(a.kchunk < a.nket ? a.kchunk : a.nket), "jeng_reg");
         return;
     }

@@ -4,14 +4,26 @@
 
 namespace md {
 
-QueueLaunchFn jeng_reg_queue_fn_2(int lx, int ly)
+QueueLaunchFn jeng_reg_queue_fn_2(int lx, int ly, bool fp32)
 {
-    if (lx == 5 && ly == 3) return &queue_launch<JArgs, jeng_reg_q<5, 3>, 64>;
-    if (lx == 0 && ly == 6) return &queue_launch<JArgs, jeng_reg_q<0, 6>, 64>;
-    if (lx == 2 && ly == 4) return &queue_launch<JArgs, jeng_reg_q<2, 4>, 64>;
-    if (lx == 6 && ly == 0) return &queue_launch<JArgs, jeng_reg_q<6, 0>, 64>;
-    if (lx == 3 && ly == 6) return &queue_launch<JArgs, jeng_reg_q<3, 6>, 64>;
-    if (lx == 5 && ly == 4) return &queue_launch<JArgs, jeng_reg_q<5, 4>, 64>;
+    if (lx == 5 && ly == 3)
+        return fp32 ? &queue_launch<JArgs, jeng_reg_q<5, 3, float>, 64>
+                    : &queue_launch<JArgs, jeng_reg_q<5, 3, double>, 64>;
+    if (lx == 0 && ly == 6)
+        return fp32 ? &queue_launch<JArgs, jeng_reg_q<0, 6, float>, 64>
+                    : &queue_launch<JArgs, jeng_reg_q<0, 6, double>, 64>;
+    if (lx == 2 && ly == 4)
+        return fp32 ? &queue_launch<JArgs, jeng_reg_q<2, 4, float>, 64>
+                    : &queue_launch<JArgs, jeng_reg_q<2, 4, double>, 64>;
+    if (lx == 6 && ly == 0)
+        return fp32 ? &queue_launch<JArgs, jeng_reg_q<6, 0, float>, 64>
+                    : &queue_launch<JArgs, jeng_reg_q<6, 0, double>, 64>;
+    if (lx == 3 && ly == 6)
+        return fp32 ? &queue_launch<JArgs, jeng_reg_q<3, 6, float>, 64>
+                    : &queue_launch<JArgs, jeng_reg_q<3, 6, double>, 64>;
+    if (lx == 5 && ly == 4)
+        return fp32 ? &queue_launch<JArgs, jeng_reg_q<5, 4, float>, 64>
+                    : &queue_launch<JArgs, jeng_reg_q<5, 4, double>, 64>;
     return nullptr;
 }
 

@@ -314,15 +314,15 @@ __global__ __launch_bounds__(64) void k_pair(KPArgs a)
     k_pair_run<LA, LB, LC, LD, T>(a, blockIdx.x);
 }
 
-// batch form (double precision): workgroup b runs block (items[b].y, items[b].z)
-// of the launch whose arguments are tab[items[b].x]
-template <int LA, int LB, int LC, int LD>
+// batch form: workgroup b runs block (items[b].y, items[b].z) of the
+// launch whose arguments are tab[items[b].x]
+template <int LA, int LB, int LC, int LD, typename T>
 __global__ __launch_bounds__(64) void k_pair_q(const KPArgs *__restrict__ tab, const int4 *__restrict__ items)
 {
     const int4 it = items[blockIdx.x];
     KPArgs a = tab[it.x];
     globalize(a);
-    k_pair_run<LA, LB, LC, LD, double>(a, it.y);
+    k_pair_run<LA, LB, LC, LD, T>(a, it.y);
 }
 
 template <int LA, int LB, int LC, int LD>
@@ -330,7 +330,9 @@ void launch_k_pair_t(const KPArgs &a, int nchunks, bool fp32, hipStream_t st)
 {
     if (nchunks <= 0) return;
     if (queue_sink()) {  // a batch plan: one chunk of up to 64 quartets per block
-        queue_record(fp32 ? nullptr : &queue_launch<KPArgs, k_pair_q<LA, LB, LC, LD>, 64>, a, nchunks, 1, 1.0, "k_pair");
+        queue_record(fp32 ? &queue_launch<KPArgs, k_pair_q<LA, LB, LC, LD, float>, 64>
+                          : &queue_launch<KPArgs, k_pair_q<LA, LB, LC, LD, double>, 64>,
+                     a, nchunks, 1, 1.0, "k_pair");
         return;
     }
     if (fp32)

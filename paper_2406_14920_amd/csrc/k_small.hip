@@ -267,15 +267,15 @@ __global__ __launch_bounds__(128) void k_small(KArgs a)
     k_small_run<LA, LB, LC, LD, T>(a, blockIdx.x);
 }
 
-// batch form (double precision): workgroup b runs block (items[b].y, items[b].z)
-// of the launch whose arguments are tab[items[b].x]
-template <int LA, int LB, int LC, int LD>
+// batch form: workgroup b runs block (items[b].y, items[b].z) of the
+// launch whose arguments are tab[items[b].x]
+template <int LA, int LB, int LC, int LD, typename T>
 __global__ __launch_bounds__(128) void k_small_q(const KArgs *__restrict__ tab, const int4 *__restrict__ items)
 {
     const int4 it = items[blockIdx.x];
     KArgs a = tab[it.x];
     globalize(a);
-    k_small_run<LA, LB, LC, LD, double>(a, it.y);
+    k_small_run<LA, LB, LC, LD, T>(a, it.y);
 }
 
 bool launch_k_small(int la, int lb, int lc, int ld, const KArgs &a, bool fp32, hipStream_t st)
@@ -286,7 +286,9 @@ bool launch_k_small(int la, int lb, int lc, int ld, const KArgs &a, bool fp32, h
 #define MD_CASE(A_, B_, C_, D_)                                                        \
     if (la == A_ && lb == B_ && lc == C_ && ld == D_) {                                \
         if (queue_sink())                                                              \
-            queue_record(fp32 ? nullptr : &queue_launch<KArgs, k_small_q<A_, B_, C_, D_>, 128>, a, (int)blocks, 1, 1.0, \
+            queue_record(fp32 ? &queue_launch<KArgs, k_small_q<A_, B_, C_, D_, float>, 128>             \
+                              : &queue_launch<KArgs, k_small_q<A_, B_, C_, D_, double>, 128>,            \
+                         a, (int)blocks, 1, 1.0,                                       \
                          "k_small");                                                   \
         else if (fp32)                                                                 \
             hipLaunchKernelGGL((k_small<A_, B_, C_, D_, float>), dim3((unsigned)blocks), dim3(threads), 0, st, a); \

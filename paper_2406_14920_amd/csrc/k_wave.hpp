@@ -328,15 +328,15 @@ __global__ __launch_bounds__(64) void k_wave(KArgs a)
     k_wave_run<LA, LB, LC, LD, T>(a, blockIdx.x, gridDim.x);
 }
 
-// batch form (double precision): workgroup b runs block (items[b].y, items[b].z)
-// of the launch whose arguments are tab[items[b].x]
-template <int LA, int LB, int LC, int LD>
+// batch form: workgroup b runs block (items[b].y, items[b].z) of the
+// launch whose arguments are tab[items[b].x]
+template <int LA, int LB, int LC, int LD, typename T>
 __global__ __launch_bounds__(64) void k_wave_q(const KArgs *__restrict__ tab, const int4 *__restrict__ items)
 {
     const int4 it = items[blockIdx.x];
     KArgs a = tab[it.x];
     globalize(a);
-    k_wave_run<LA, LB, LC, LD, double>(a, it.y, it.w);
+    k_wave_run<LA, LB, LC, LD, T>(a, it.y, it.w);
 }
 
 // Ket-first form for the classes whose block fits in LDS.  Per primitive
@@ -647,15 +647,15 @@ __global__ __launch_bounds__(64) void k_wave_x(KArgs a)
     k_wave_x_run<LA, LB, LC, LD, T>(a, blockIdx.x, gridDim.x);
 }
 
-// batch form (double precision): workgroup b runs block (items[b].y, items[b].z)
-// of the launch whose arguments are tab[items[b].x]
-template <int LA, int LB, int LC, int LD>
+// batch form: workgroup b runs block (items[b].y, items[b].z) of the
+// launch whose arguments are tab[items[b].x]
+template <int LA, int LB, int LC, int LD, typename T>
 __global__ __launch_bounds__(64) void k_wave_x_q(const KArgs *__restrict__ tab, const int4 *__restrict__ items)
 {
     const int4 it = items[blockIdx.x];
     KArgs a = tab[it.x];
     globalize(a);
-    k_wave_x_run<LA, LB, LC, LD, double>(a, it.y, it.w);
+    k_wave_x_run<LA, LB, LC, LD, T>(a, it.y, it.w);
 }
 
 template <int LA, int LB, int LC, int LD>
@@ -669,10 +669,12 @@ void launch_k_wave_t(const KArgs &a, bool fp32, hipStream_t st)
     if (queue_sink()) {  // a batch plan: each block walks ranges/blocks ranges
         QueueLaunchFn fn;
         if constexpr (C::KETFIRST)
-            fn = &queue_launch<KArgs, k_wave_x_q<LA, LB, LC, LD>, 64>;
+            fn = fp32 ? &queue_launch<KArgs, k_wave_x_q<LA, LB, LC, LD, float>, 64>
+                      : &queue_launch<KArgs, k_wave_x_q<LA, LB, LC, LD, double>, 64>;
         else
-            fn = &queue_launch<KArgs, k_wave_q<LA, LB, LC, LD>, 64>;
-        queue_record(fp32 ? nullptr : fn, a, (int)blocks, 1,
+            fn = fp32 ? &queue_launch<KArgs, k_wave_q<LA, LB, LC, LD, float>, 64>
+                      : &queue_launch<KArgs, k_wave_q<LA, LB, LC, LD, double>, 64>;
+        queue_record(fn, a, (int)blocks, 1,
                      (double)ranges / (double)blocks, C::KETFIRST ? "k_wave_x" : "k_wave");
         return;
     }

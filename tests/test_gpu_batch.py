@@ -99,8 +99,8 @@ def test_batch_rerecords_on_change():
 
 
 def test_batch_direct_launches_match_standalone():
-    """Batches as they run now: every molecule's build launched on one of the
-    batch's streams, joined back; repeated calls with eager work between."""
+    """Streams mode: every molecule's build launched on one of the batch's
+    streams, joined back; repeated calls with eager work between."""
     torch = _torch()
     from paper_2406_14920_amd import JK, Batch
     mols = _mols(6)
@@ -110,7 +110,7 @@ def test_batch_direct_launches_match_standalone():
     Ps = [torch.tensor(m.P, dtype=torch.float64, device="cuda") for m in mols]
     ref = [tuple(t.clone() for t in jk.jk(P)) for jk, P in zip(jks, Ps)]
     torch.cuda.synchronize()
-    b = Batch(jks)
+    b = Batch(jks, mode="streams")
     for rep in range(2):
         J, K = b.jk(Ps)
         torch.cuda.synchronize()
@@ -341,6 +341,48 @@ def test_batch_queue_graph_replays():
         _close(J[i], 0.5 * eager[i][0], "J new density mol %d" % i)
         _close(K[i], 0.5 * eager[i][1], "K new density mol %d" % i)
     del g
+    b.close()
+    for jk in jks:
+        jk.close()
+
+
+@pytest.mark.parametrize("members", ["mixed", "mixed_all"])
+def test_batch_queue_mixed_precision_members(members):
+    """Queue mode with mixed-precision members: their double- and
+    single-precision shares run as separate batch kernels, with the same
+    precision tiles as their own build_jk, so each molecule's J and K equal
+    its own build (atomic order only); a member switched back to FP64 remakes
+    the plan."""
+    torch = _torch()
+    from paper_2406_14920_amd import JK, Batch
+    mols = _mols(6)
+    jks = [JK.from_molecule(m) for m in mols]
+    for i in (1, 3, 4):
+        jks[i].set_precision(members)
+    Ps = [torch.tensor(m.P, dtype=torch.float64, device="cuda") for m in mols]
+    ref = [tuple(t.clone() for t in jk.jk(P)) for jk, P in zip(jks, Ps)]
+    torch.cuda.synchronize()
+    b = Batch(jks)
+    assert b.mode == "queue"
+    for rep in range(2):
+        J, K = b.jk(Ps)
+        torch.cuda.synchronize()
+        for i in range(len(mols)):
+            _close(J[i], ref[i][0], "J rep %d mol %d" % (rep, i))
+            _close(K[i], ref[i][1], "K rep %d mol %d" % (rep, i))
+        junk = torch.randn(256, 256, device="cuda", dtype=torch.float64)
+        (junk @ junk).sum().item()
+    launches_mixed = b.queue_info()["launches"]
+    jks[3].set_precision("fp64")
+    ref3 = tuple(t.clone() for t in jks[3].jk(Ps[3]))
+    J, K = b.jk(Ps)
+    torch.cuda.synchronize()
+    _close(J[3], ref3[0], "J after switch")
+    _close(K[3], ref3[1], "K after switch")
+    for i in (0, 1, 2, 4, 5):
+        _close(J[i], ref[i][0], "J after switch mol %d" % i)
+        _close(K[i], ref[i][1], "K after switch mol %d" % i)
+    assert launches_mixed > 0 and b.queue_info()["launches"] > 0
     b.close()
     for jk in jks:
         jk.close()
