@@ -418,7 +418,8 @@ def bench_batch(a):
     setup_s = time.perf_counter() - t0
     Ps = [torch.tensor(m.P, dtype=torch.float64, device="cuda") for m in mols]
     eris = sum(jk.stats()["eris_sph"] for jk in jks)
-    b = Batch(jks, mode="queue")
+    s = torch.cuda.Stream()
+    b = Batch(jks, stream=s, mode="queue")
     t0 = time.perf_counter()
     b.jk(Ps)
     torch.cuda.synchronize()
@@ -426,6 +427,16 @@ def bench_batch(a):
     info = b.queue_info()
     ms_queue = _time(lambda: b.jk(Ps), _xsteps(a))
     lat_queue = _lat(b)
+    # the same build captured once into a HIP graph and replayed
+    Jq = [t.clone() for t in b.J]
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        b.jk(Ps)
+    g.replay()
+    torch.cuda.synchronize()
+    ms_graph = _time(g.replay, _xsteps(a))
+    graph_dj = max(float((x - y).abs().max()) for x, y in zip(b.J, Jq))
+    del g
     b.set_mode("streams")
     b.jk(Ps)
     ms_streams = _time(lambda: b.jk(Ps), _xsteps(a))
@@ -448,8 +459,8 @@ def bench_batch(a):
     b.close()
     for jk in jks:
         jk.close()
-    print("batch64: queue %.1f ms, streams %.1f ms, one by one %.1f ms, mixed (queue) %.1f ms "
-          "(setup %.1fs, first queue call %.1fs)" % (ms_queue, ms_streams, ms_seq, ms_mixed, setup_s, plan_s),
+    print("batch64: queue %.1f ms (graph replay %.1f ms), streams %.1f ms, one by one %.1f ms, mixed (queue) %.1f ms "
+          "(setup %.1fs, first queue call %.1fs)" % (ms_queue, ms_graph, ms_streams, ms_seq, ms_mixed, setup_s, plan_s),
           file=sys.stderr, flush=True)
     m40 = synth.mol40()
     jk40 = JK.from_molecule(m40)
@@ -469,6 +480,7 @@ def bench_batch(a):
             "launch": "queue mode: one launch per kernel over the blocks of all 64 molecules, "
                       "launches with the most work per block first",
             "queue_plan": {"launches": info["launches"], "items": info["items"], "first_call_s": plan_s},
+            "ms_per_batch_graph_replay": ms_graph, "graph_replay_max_abs_dJ_vs_eager": graph_dj,
             "per_molecule_latency_ms": lat_queue,
             "ms_per_batch_streams": ms_streams, "per_molecule_latency_ms_streams": lat_streams,
             "ms_per_batch_one_by_one": ms_seq,
