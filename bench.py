@@ -609,7 +609,8 @@ def main():
         out["batch64"] = bench_batch(a)
     if not a.no_cpu:
         cb = cpu_baseline(mol)
-        out["cpu_baseline"] = {k: cb[k] for k in ("value", "unit", "cores", "kind", "sample")}
+        out["cpu_baseline"] = {k: cb[k] for k in ("value", "unit", "cores", "kind", "sample", "cpu_model",
+                                                  "single_thread")}
     print(json.dumps(out), flush=True)
 
 
