@@ -2430,11 +2430,15 @@ void batch_build_queue(eri_batch *b, const double *const *P, double *const *J, d
     HIPCHK(hipEventRecord(b->qev[0], st));
     HIPCHK(hipStreamWaitEvent(b->qaux[0], b->qev[0], 0));
     HIPCHK(hipStreamWaitEvent(b->qaux[1], b->qev[0], 0));
+    // at most 2^24 items per launch, so that items x lanes stays below the
+    // 2^32 work-items of one launch
+    constexpr int kMaxItems = 1 << 24;
     for (const eri_batch::QGroup &q : b->qg) {
         const bool jeng = std::strncmp(q.kind, "jeng", 4) == 0;
         const bool kside = std::strcmp(q.kind, "k_small") == 0 || std::strcmp(q.kind, "k_pair") == 0;
         const hipStream_t s = jeng ? b->qaux[0] : (kside ? b->qaux[1] : st);
-        q.fn(b->d_qtab.p + q.tab_off, b->d_qitems.p + q.item_off, q.nitems, s);
+        for (int off = 0; off < q.nitems; off += kMaxItems)
+            q.fn(b->d_qtab.p + q.tab_off, b->d_qitems.p + q.item_off + off, std::min(kMaxItems, q.nitems - off), s);
     }
     HIPCHK(hipEventRecord(b->qev[1], b->qaux[0]));
     HIPCHK(hipEventRecord(b->qev[2], b->qaux[1]));
