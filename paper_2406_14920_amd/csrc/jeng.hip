@@ -232,6 +232,11 @@ __device__ __forceinline__ void jeng_wave_run(const JArgs &a, int blk_x, int blk
     __shared__ T sDq[NY];  // single precision: r^|Q| times the scaled Hermite density
     const int lane = threadIdx.x;
     herm_table_lds(sHerm, nherm(L), lane);
+    // per-lane R^0 term plan (L <= 9), visible after the first barrier
+    __shared__ uint32_t sPlan[R0Plan<L, T>::OK ? R0Plan<L, T>::NT * 64 : 1];
+    R0Plan<L, T> r0p;
+    r0p.code = sPlan;
+    if constexpr (R0Plan<L, T>::OK) r0_plan_build<L, T>(r0p, lane);
     const int g = blk_x;
     const PrimPair pb = a.pp[a.pbase + g];
     const double Qi = a.Qbra[a.owner[g]];
@@ -277,7 +282,10 @@ __device__ __forceinline__ void jeng_wave_run(const JArgs &a, int blk_x, int blk
                 dt = sDq;
             }
             __syncthreads();
-            wave_r0h<L, T>(sF, sH, sHerm, sR0, lane);
+            if constexpr (R0Plan<L, T>::OK)
+                wave_r0h_plan<L, T>(r0p, sF, sH, sR0, lane);
+            else
+                wave_r0h<L, T>(sF, sH, sHerm, sR0, lane);
             __syncthreads();
 #pragma unroll
             for (int r = 0; r < 2; ++r) {

@@ -139,6 +139,15 @@ __device__ __forceinline__ void k_wave_run(const KArgs &a, int blk_x, int grid_x
 
     const int lane = threadIdx.x;
     herm_table_lds(sHerm, nherm(L), lane);
+    // per-lane R^0 term plan (L <= 9), visible after the first barrier; only
+    // where the workgroup's LDS stays within 20 KB (eight workgroups per CU)
+    constexpr int LDS0 = (int)sizeof(T) * (C::NR0 + L + 1 + HPolyDims<L>::N + 3 * C::EBD + C::SK + C::NV) +
+                         16 * C::ND_ + 4 * nherm(L);
+    constexpr bool PLAN = R0Plan<L, T>::OK && LDS0 + R0Plan<L, T>::NT * 256 <= 20480;
+    __shared__ uint32_t sPlan[PLAN ? R0Plan<L, T>::NT * 64 : 1];
+    R0Plan<L, T> r0p;
+    r0p.code = sPlan;
+    if constexpr (PLAN) r0_plan_build<L, T>(r0p, lane);
     for (int o = lane; o < C::ND_; o += 64) sK[o] = 0.0;  // cleared again by every flush
 
     // the bra components this lane owns: their boxes and 1D table offsets
@@ -229,7 +238,10 @@ __device__ __forceinline__ void k_wave_run(const KArgs &a, int blk_x, int grid_x
                     const T *ek = pick<T>(a.eprod_ket, a.eprodf_ket) + (int64_t)(B.poff + kp - a.pbase_ket) * C::SK;
                     for (int o = lane; o < C::SK; o += 64) sEk[o] = ek[o];
                     __syncthreads();
-                    wave_r0h<L, T>(sF, sH, sHerm, sR0, lane);
+                    if constexpr (PLAN)
+                        wave_r0h_plan<L, T>(r0p, sF, sH, sR0, lane);
+                    else
+                        wave_r0h<L, T>(sF, sH, sHerm, sR0, lane);
                     __syncthreads();
 
                     static_for<0, C::NABCH>([&](auto chc) {
@@ -383,6 +395,16 @@ __device__ __forceinline__ void k_wave_x_run(const KArgs &a, int blk_x, int grid
 
     const int lane = threadIdx.x;
     herm_table_lds(sHerm, nherm(L), lane);
+    // per-lane R^0 term plan (the classes with L <= 9), visible after the
+    // first barrier of the quartet loop; only where the workgroup's LDS stays
+    // within 20 KB (eight workgroups per CU)
+    constexpr int LDS0 = (int)sizeof(T) * (NRX + NBAT * (L + 1) + HPolyDims<L>::N + 3 * C::EBD + C::SK) +
+                         8 * (NBAT * 6 + 2 * C::ND_) + 4 * nherm(L);
+    constexpr bool PLAN = R0Plan<L, T>::OK && LDS0 + R0Plan<L, T>::NT * 256 <= 20480;
+    __shared__ uint32_t sPlan[PLAN ? R0Plan<L, T>::NT * 64 : 1];
+    R0Plan<L, T> r0p;
+    r0p.code = sPlan;
+    if constexpr (PLAN) r0_plan_build<L, T, ST, SU>(r0p, lane);
     for (int o = lane; o < C::ND_; o += 64) sK[o] = 0.0;  // cleared again by every flush
 
     // bra Hermite indices this lane owns in the ket rounds
@@ -519,7 +541,10 @@ __device__ __forceinline__ void k_wave_x_run(const KArgs &a, int blk_x, int grid
                         const T *ek = pick<T>(a.eprod_ket, a.eprodf_ket) + (int64_t)(B.poff + kp - a.pbase_ket) * C::SK;
                         for (int o = lane; o < C::SK; o += 64) sEk[o] = ek[o];
                         __syncthreads();
-                        wave_r0h<L, T, ST, SU>(sFb + (kp - kb) * (L + 1), sH, sHerm, sR0, lane);
+                        if constexpr (PLAN)
+                            wave_r0h_plan<L, T, ST, SU>(r0p, sFb + (kp - kb) * (L + 1), sH, sR0, lane);
+                        else
+                            wave_r0h<L, T, ST, SU>(sFb + (kp - kb) * (L + 1), sH, sHerm, sR0, lane);
                         __syncthreads();
 
                         T rp[LCD + 1];  // r^|s| of the scaled single-precision form

@@ -318,7 +318,10 @@ __device__ __forceinline__ void wave_hpoly(const QuartetGeo &g, T *sH, int lane)
     const double gx = f * g.X, gy = f * g.Y, gz = f * g.Z;  // values, not a runtime-indexed member
     for (int i = lane; i < HPolyDims<L>::N; i += 64) {
         const int axis = i / ((L + 1) * H), t = (i / H) % (L + 1), a = i % H;
-        if (2 * a > t) continue;
+        if (2 * a > t) {  // no such term: a zero the planned R^0 sums can point at
+            sH[i] = T(0);
+            continue;
+        }
         double x = gx;
         if (axis == 1) x = gy;
         if (axis == 2) x = gz;
@@ -340,6 +343,45 @@ __host__ __device__ constexpr int r0_terms_max(int k0, int k1)
     return m;
 }
 
+// Hermite indices of R^0 of order L in the order the wavefront builds them:
+// by number of closed-form terms, largest first, so that each round of 64
+// lanes holds entries of similar term counts and the flat walk's trip count
+// (the round's largest) wastes few slots; tm[r] is that count for round r,
+// off[r] the first term slot of round r in a plan.
+template <int L>
+struct R0Rounds {
+    static constexpr int NH = nherm(L), NR = (NH + 63) / 64;
+    int perm[NH], tm[NR], off[NR + 1], tmax;
+    constexpr R0Rounds() : perm(), tm(), off(), tmax(0)
+    {
+        int n[NH] = {}, nmax = 0;
+        for (int k = 0; k < NH; ++k) {
+            n[k] = (herm_t(k) / 2 + 1) * (herm_u(k) / 2 + 1) * (herm_v(k) / 2 + 1);
+            if (n[k] > nmax) nmax = n[k];
+        }
+        int i = 0;  // stable, by descending term count
+        for (int c = nmax; c >= 1; --c)
+            for (int k = 0; k < NH; ++k)
+                if (n[k] == c) perm[i++] = k;
+        off[0] = 0;
+        for (int r = 0; r < NR; ++r) {
+            tm[r] = 0;
+            for (int q = r * 64; q < NH && q < r * 64 + 64; ++q)
+                if (n[perm[q]] > tm[r]) tm[r] = n[perm[q]];
+            off[r + 1] = off[r] + tm[r];
+            if (tm[r] > tmax) tmax = tm[r];
+        }
+    }
+};
+
+// Hermite index of lane slot q = 64 r + lane in build order (constant table).
+template <int L>
+__device__ __forceinline__ int r0_perm(int q)
+{
+    static constexpr R0Rounds<L> RR{};
+    return RR.perm[q];
+}
+
 // Phase 2 (after the barrier that publishes sF, sH and sHerm): dense R^0
 // into sR0 at t ST + u SU + v (by default the cube (L+1)^3).  No barrier inside.  Each lane walks the (a, b, c) terms of its
 // entry in one flat loop whose trip count is the round's largest term
@@ -352,10 +394,10 @@ __device__ __forceinline__ void wave_r0h(const T *sF, const T *sH, const int *sH
     const T *hx = sH, *hy = sH + L1 * H, *hz = sH + 2 * L1 * H;
     static_for<0, (NH + 63) / 64>([&](auto rc) {
         constexpr int r = decltype(rc)::value;
-        constexpr int TM = r0_terms_max(r * 64, (r * 64 + 64 < NH) ? r * 64 + 64 : NH);
-        const int k = r * 64 + lane;
-        if (k < NH) {
-            const int code = sHerm[k];
+        constexpr int TM = R0Rounds<L>().tm[r];
+        const int q = r * 64 + lane;
+        if (q < NH) {
+            const int code = sHerm[r0_perm<L>(q)];
             const int t = code & 0xff, u = (code >> 8) & 0xff, v = code >> 16;
             const int nb = u / 2 + 1, nc = v / 2 + 1, nterm = (t / 2 + 1) * nb * nc;
             const T *px = hx + t * H, *py = hy + u * H, *pz = hz + v * H;
@@ -376,6 +418,94 @@ __device__ __forceinline__ void wave_r0h(const T *sF, const T *sH, const int *sH
             sR0[t * ST + u * SU + v] = acc;
         }
     });
+}
+
+// The same closed form with the term walk planned once per kernel: for the
+// entry of lane slot 64 r + lane (build order, R0Rounds) and each of the
+// round's term slots j, one word in LDS (code[(off_r + j) 64 + lane]) packs
+// the offsets of the term's x, y and z Hermite-polynomial entries and of its
+// G value, 8 bits each (slots past the entry's term count point at a zero
+// polynomial entry), so that each term costs five LDS reads, the field
+// extractions and three multiply-adds instead of the flat loop's index
+// bookkeeping.  The offsets are in bytes while one axis row of sH takes at
+// most 256 bytes, else in elements; used for L <= 9 (the plan takes 5 KB of
+// LDS or less).  Same terms in the same order as wave_r0h, so the same sums.
+template <int L, typename T>
+struct R0Plan {
+    static constexpr int H = HPolyDims<L>::H, NH = nherm(L), NR = (NH + 63) / 64;
+    static constexpr bool OK = L >= 2 && L <= 9;
+    static constexpr bool BYTES = (L + 1) * H * (int)sizeof(T) <= 256;  // offsets in bytes, else in elements
+    static constexpr int NT = R0Rounds<L>().off[NR], TMAX = R0Rounds<L>().tmax;
+    uint32_t *code;  // LDS, NT x 64 words
+    int out[NR];     // R^0 index t ST + u SU + v of the lane's entry, -1 if none
+};
+
+template <int L, typename T, int ST = (L + 1) * (L + 1), int SU = L + 1>
+__device__ __forceinline__ void r0_plan_build(R0Plan<L, T> &p, int lane)
+{
+    using P = R0Plan<L, T>;
+    constexpr R0Rounds<L> RR{};
+    constexpr int H = P::H, B = P::BYTES ? (int)sizeof(T) : 1;
+    constexpr uint32_t ZERO = (uint32_t)((H - 1) * B);  // x entry (t = 0, a = H - 1): zero
+#pragma unroll
+    for (int r = 0; r < P::NR; ++r) {
+        const int q = r * 64 + lane;
+        int t = 0, u = 0, v = 0;
+        const bool ok = q < P::NH;
+        if (ok) {
+            const int code = c_herm.tuv[r0_perm<L>(q)];
+            t = code & 0xff;
+            u = (code >> 8) & 0xff;
+            v = code >> 16;
+        }
+        p.out[r] = ok ? t * ST + u * SU + v : -1;
+        const int nb = u / 2 + 1, nc = v / 2 + 1, nterm = ok ? (t / 2 + 1) * nb * nc : 0;
+        int a = 0, b = 0, c = 0;
+#pragma unroll
+        for (int j = 0; j < P::TMAX; ++j) {
+            if (j < RR.tm[r]) {
+                uint32_t w = ZERO;
+                if (j < nterm)
+                    w = (uint32_t)((t * H + a) * B) | ((uint32_t)((u * H + b) * B) << 8) |
+                        ((uint32_t)((v * H + c) * B) << 16) | ((uint32_t)((t + u + v - a - b - c) * B) << 24);
+                p.code[(RR.off[r] + j) * 64 + lane] = w;
+                if (++c == nc) {
+                    c = 0;
+                    if (++b == nb) {
+                        b = 0;
+                        ++a;
+                    }
+                }
+            }
+        }
+    }
+}
+
+template <int L, typename T, int ST = (L + 1) * (L + 1), int SU = L + 1>
+__device__ __forceinline__ void wave_r0h_plan(const R0Plan<L, T> &p, const T *sF, const T *sH, T *sR0, int lane)
+{
+    using P = R0Plan<L, T>;
+    constexpr R0Rounds<L> RR{};
+    constexpr int ROW = (L + 1) * P::H;
+    const char *hx = (const char *)sH, *hy = (const char *)(sH + ROW), *hz = (const char *)(sH + 2 * ROW);
+    const char *f = (const char *)sF;
+    constexpr uint32_t M = P::BYTES ? 1u : (uint32_t)sizeof(T);
+#pragma unroll
+    for (int r = 0; r < P::NR; ++r) {
+        T acc = T(0);
+#pragma unroll
+        for (int j = 0; j < P::TMAX; ++j) {
+            if (j < RR.tm[r]) {
+                const uint32_t w = p.code[(RR.off[r] + j) * 64 + lane];
+                const T x = *(const T *)(hx + (w & 0xffu) * M);
+                const T y = *(const T *)(hy + ((w >> 8) & 0xffu) * M);
+                const T z = *(const T *)(hz + ((w >> 16) & 0xffu) * M);
+                const T g = *(const T *)(f + (w >> 24) * M);
+                acc += x * y * z * g;
+            }
+        }
+        if (p.out[r] >= 0) sR0[p.out[r]] = acc;
+    }
 }
 
 // One axis of the 1D Hermite tables built in registers (eq. E_recursion, in
