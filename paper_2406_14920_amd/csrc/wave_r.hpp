@@ -325,8 +325,15 @@ __device__ __forceinline__ void wave_hpoly(const QuartetGeo &g, T *sH, int lane)
         double x = gx;
         if (axis == 1) x = gy;
         if (axis == 2) x = gz;
+        // c x^m, m = t - 2a <= L, by binary powering over the bits of m (the
+        // same steps for every lane instead of a loop of m multiplications)
+        const int m = t - 2 * a;
         double v = c_hcoef.c[t][a];
-        for (int k = 0; k < t - 2 * a; ++k) v *= x;
+#pragma unroll
+        for (int bit = 1; bit <= L; bit <<= 1) {
+            if (m & bit) v *= x;
+            x *= x;
+        }
         sH[i] = (T)v;
     }
 }
