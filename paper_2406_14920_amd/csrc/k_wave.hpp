@@ -508,10 +508,9 @@ __device__ __forceinline__ void k_wave_x_run(const KArgs &a, int blk_x, int grid
                             const PairLite pq = pair_lite(a.pp + B.poff + kq);
                             const QuartetGeo gq = quartet_geo(pb, pq, a.om2);
                             const double F = boys_one(m, gq.T, a.boys);
-                            double sc = sizeof(T) == 4 ? gq.pref0 : gq.pref;
+                            const double sc = sizeof(T) == 4 ? gq.pref0 : gq.pref;
                             const double m2a = sizeof(T) == 4 ? gq.w : -2.0 * gq.alpha;
-                            for (int k = 0; k < m; ++k) sc *= m2a;
-                            sFb[(kq - kb) * (L + 1) + m] = (T)(sc * F);
+                            sFb[(kq - kb) * (L + 1) + m] = (T)(sc * pow_small<L>(m2a, m) * F);
                             if (m == 0) {
                                 double *o = sGeo + (kq - kb) * 6;
                                 o[0] = gq.X;

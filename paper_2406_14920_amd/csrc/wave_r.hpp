@@ -111,15 +111,28 @@ __device__ __forceinline__ QuartetGeo quartet_geo(const PrimPair &pb, const Pair
 // Phase 1 (no barrier inside): lane m <= L writes sF[m] = pref (-2 alpha)^m F_m
 // (single precision: the scaled G~_m = pref0 w^m F_m).  F_m and the scale are
 // formed in double precision; the product is stored as T.
+// x^n for 0 <= n <= NMAX by binary powering: the same steps for every lane
+// (a loop of n multiplications runs to the wavefront's largest n).
+template <int NMAX, typename V>
+__device__ __forceinline__ V pow_small(V x, int n)
+{
+    V v = V(1);
+#pragma unroll
+    for (int bit = 1; bit <= NMAX; bit <<= 1) {
+        if (n & bit) v *= x;
+        x *= x;
+    }
+    return v;
+}
+
 template <int L, typename T>
 __device__ __forceinline__ void wave_boys(const QuartetGeo &g, const double *__restrict__ btab,
                                           T *sF, int lane)
 {
     if (lane <= L) {
         double F = boys_one(lane, g.T, btab);
-        double s = sizeof(T) == 4 ? g.pref0 : g.pref, m2a = sizeof(T) == 4 ? g.w : -2.0 * g.alpha;
-        for (int m = 0; m < lane; ++m) s *= m2a;
-        sF[lane] = (T)(s * F);
+        const double s = sizeof(T) == 4 ? g.pref0 : g.pref, m2a = sizeof(T) == 4 ? g.w : -2.0 * g.alpha;
+        sF[lane] = (T)(s * pow_small<L>(m2a, lane) * F);
     }
 }
 
