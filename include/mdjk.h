@@ -375,7 +375,7 @@ int eri_set_tuning(eri_ctx *ctx, const eri_tuning_t *in);
  *    stream onto one of up to 8 batch streams and joined back, so molecules
  *    run concurrently.
  * (The library also holds a path that records the streams form into one HIP
- * graph itself; it is switched off in this build after host-side crashes of
+ * graph itself; it is switched off in this library after host-side crashes of
  * that recording on the MI355X runtime.) */
 typedef struct eri_batch eri_batch;
 int eri_batch_create(eri_ctx *const *ctxs, int32_t n, void *stream, eri_batch **out);
