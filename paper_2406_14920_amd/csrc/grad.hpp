@@ -143,6 +143,17 @@ __global__ __launch_bounds__(64) void kg_wave(KGArgs g)
 
     const int lane = threadIdx.x;
     herm_table_lds(sHerm, nherm(L + 1), lane);
+    // per-lane R^0 term plan (orders up to 9), visible after the first
+    // barrier; only where it leaves the workgroups per CU that LDS allows
+    // unchanged, with 1 KB to spare for the atom partials (at most eight one-wave
+    // workgroups are resident anyway)
+    constexpr int LDSK = kg_lds_bytes(L, C::NR0, C::EBD, C::EKD, NHX, NHC, C::ND_, C::KBM, CDCH) + 512;
+    constexpr int WGK = 163840 / LDSK < 8 ? 163840 / LDSK : 8;
+    constexpr bool PLAN = R0Plan<L + 1, double>::OK && 163840 / (LDSK + R0Plan<L + 1, double>::NT * 256 + 1024) >= WGK;
+    __shared__ uint32_t sPlan[PLAN ? R0Plan<L + 1, double>::NT * 64 : 1];
+    R0Plan<L + 1, double> r0p;
+    r0p.code = sPlan;
+    if constexpr (PLAN) r0_plan_build<L + 1, double, L2 * L2, L2>(r0p, lane);
     const int na3 = 3 * g.natom;
     for (int o = lane; o < na3; o += 64) sG[o] = 0.0;
     // every entry finite from the start: the chunk loops below run to CDCH
@@ -282,7 +293,10 @@ __global__ __launch_bounds__(64) void kg_wave(KGArgs g)
                         etab_lds<LC + 1, LD>(pa, pbb, pk.o2p, sEk + k * C::EKD);
                     }
                     __syncthreads();
-                    wave_r0h<L + 1>(sF, sH, sHerm, sR0, lane);
+                    if constexpr (PLAN)
+                        wave_r0h_plan<L + 1, double, L2 * L2, L2>(r0p, sF, sH, sR0, lane);
+                    else
+                        wave_r0h<L + 1>(sF, sH, sHerm, sR0, lane);
                     __syncthreads();
                     const double a2 = 2.0 * pb.a, c2 = 2.0 * pk.a;
 
