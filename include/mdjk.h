@@ -369,8 +369,9 @@ int eri_set_tuning(eri_ctx *ctx, const eri_tuning_t *in);
  *    (argument tables and item lists, on the device) is made on the first
  *    call and again after any context changes (precision, geometry, screen,
  *    tuning): that call allocates and copies; later calls launch kernels
- *    only, all on the batch stream, so a call after the first can be
- *    captured into a HIP graph.
+ *    only (on the batch stream and on streams forked from it and joined
+ *    back, as in build_jk), so a call after the first can be captured into
+ *    a HIP graph.
  *  - ERI_BATCH_STREAMS: every molecule's build_jk is forked from the batch
  *    stream onto one of up to 8 batch streams and joined back, so molecules
  *    run concurrently.

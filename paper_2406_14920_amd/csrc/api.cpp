@@ -344,8 +344,8 @@ struct eri_ctx {
     // streams the J work and the bra-shared / small exchange launches fork
     // onto, joined back into the context stream by events
     bool recording = false;  // inside a batch graph recording: no internal fork
-    hipStream_t aux[2] = {nullptr, nullptr};
-    hipEvent_t ev_fork = nullptr, ev_kzero = nullptr, ev_join[2] = {nullptr, nullptr};
+    hipStream_t aux[3] = {nullptr, nullptr, nullptr};
+    hipEvent_t ev_fork = nullptr, ev_kzero = nullptr, ev_join[3] = {nullptr, nullptr, nullptr};
     std::map<std::string, Acc> prof;
 
     // stats
@@ -1087,8 +1087,9 @@ void run_j(eri_ctx *c, bool mixed, hipStream_t st)
     j_epilogue(c, st);
 }
 
-// Range-walking wave classes on stA, bra-shared and small classes on stB.
-void run_k(eri_ctx *c, bool mixed, hipStream_t stA, hipStream_t stB)
+// Range-walking wave classes on stA, lane-per-quartet classes on stB,
+// bra-shared classes on stC.
+void run_k(eri_ctx *c, bool mixed, hipStream_t stA, hipStream_t stB, hipStream_t stC)
 {
     for (const auto &w : c->kwork) {
         if (w.nwork == 0) continue;
@@ -1104,7 +1105,7 @@ void run_k(eri_ctx *c, bool mixed, hipStream_t stA, hipStream_t stB)
             if (w.choff >= 0) {
                 const KPArgs p = kp_args(a, c->d_chunks.p + w.choff);
                 const int nch = w.nchunks;
-                hipStream_t st = stB;
+                hipStream_t st = stC;
                 timed(c, st, cls_name("kp", la, lb, lc, ld) + sfx, 0, wi, part, [&] {
                     ok = launch_k_pair_0(la, lb, lc, ld, p, nch, f32, st) || launch_k_pair_1(la, lb, lc, ld, p, nch, f32, st) ||
                          launch_k_pair_2(la, lb, lc, ld, p, nch, f32, st) || launch_k_pair_3(la, lb, lc, ld, p, nch, f32, st) ||
@@ -1599,8 +1600,9 @@ int build_jk(eri_ctx *ctx, const double *P, double *J, double *K)
         }
         ctx->built_mixed = mixed;
         ctx->mix_counts_ok = false;
-        // J on its own stream, K split over the context stream and a second
-        // one; all accumulate with atomics, so the three run concurrently.
+        // J on its own stream, K split over the context stream (range-walking
+        // kernels) and two more (lane-per-quartet and bra-shared kernels); all
+        // accumulate with atomics, so the four run concurrently.
         // While profiling, everything stays on the context stream so that
         // each kernel's events bracket it alone.
         const bool fork = !ctx->profile && !ctx->recording;
@@ -1618,9 +1620,13 @@ int build_jk(eri_ctx *ctx, const double *P, double *J, double *K)
             launch_fill_zero(ctx->wk.Kacc, (int64_t)nc * nc, st);
             HIPCHK(hipEventRecord(ctx->ev_kzero, st));
             HIPCHK(hipStreamWaitEvent(sK, ctx->ev_kzero, 0));
-            run_k(ctx, mixed, st, sK);
+            hipStream_t sP = fork ? ctx->aux[2] : st;
+            HIPCHK(hipStreamWaitEvent(sP, ctx->ev_kzero, 0));
+            run_k(ctx, mixed, st, sK, sP);
             HIPCHK(hipEventRecord(ctx->ev_join[1], sK));
+            HIPCHK(hipEventRecord(ctx->ev_join[2], sP));
             HIPCHK(hipStreamWaitEvent(st, ctx->ev_join[1], 0));
+            HIPCHK(hipStreamWaitEvent(st, ctx->ev_join[2], 0));
             launch_acc_to_out(ctx->wk.Kacc, nc, K, ctx->nbf, m, ctx->opts.spherical, st);
         }
         if (J) HIPCHK(hipStreamWaitEvent(st, ctx->ev_join[0], 0));
@@ -1930,7 +1936,7 @@ int eri_destroy(eri_ctx *ctx)
             (void)hipStreamSynchronize(x);
             (void)hipStreamDestroy(x);
         }
-    for (hipEvent_t e : {ctx->ev_fork, ctx->ev_kzero, ctx->ev_join[0], ctx->ev_join[1]})
+    for (hipEvent_t e : {ctx->ev_fork, ctx->ev_kzero, ctx->ev_join[0], ctx->ev_join[1], ctx->ev_join[2]})
         if (e) (void)hipEventDestroy(e);
     for (auto &r : ctx->pending) {
         (void)hipEventDestroy(r.a);
@@ -2218,10 +2224,11 @@ struct eri_batch {
     };
     int32_t mode = ERI_BATCH_QUEUE;
     // queue builds fork from the batch stream as build_jk does: J-engine
-    // launches on qaux[0], bra-shared and small exchange launches on qaux[1],
-    // range-walking exchange launches on the batch stream
-    hipStream_t qaux[2] = {nullptr, nullptr};
-    hipEvent_t qev[3] = {nullptr, nullptr, nullptr};  // fork, join J, join small K
+    // launches on qaux[0], lane-per-quartet exchange launches on qaux[1],
+    // bra-shared exchange launches on qaux[2], range-walking exchange
+    // launches on the batch stream
+    hipStream_t qaux[3] = {nullptr, nullptr, nullptr};
+    hipEvent_t qev[4] = {nullptr, nullptr, nullptr, nullptr};  // fork, join J, join small K, join bra-shared K
     std::vector<QGroup> qg;
     DevBuf<unsigned char> d_qtab;
     DevBuf<int4> d_qitems;
@@ -2331,7 +2338,7 @@ void batch_plan_queue(eri_batch *b)
         queue_sink() = &recs;
         try {
             j_classes(c, mixed, nullptr);
-            run_k(c, mixed, nullptr, nullptr);
+            run_k(c, mixed, nullptr, nullptr, nullptr);
         } catch (...) {
             queue_sink() = nullptr;
             c->profile = prof;
@@ -2398,7 +2405,7 @@ bool batch_queue_ready(const eri_batch *b)
 
 // One batch build with queue launches: every molecule's density transforms
 // on the batch stream, the batch J-engine and exchange launches forked onto
-// three streams as in build_jk and joined back, every molecule's output
+// four streams as in build_jk and joined back, every molecule's output
 // transforms on the batch stream.
 void batch_build_queue(eri_batch *b, const double *const *P, double *const *J, double *const *K)
 {
@@ -2430,20 +2437,25 @@ void batch_build_queue(eri_batch *b, const double *const *P, double *const *J, d
     HIPCHK(hipEventRecord(b->qev[0], st));
     HIPCHK(hipStreamWaitEvent(b->qaux[0], b->qev[0], 0));
     HIPCHK(hipStreamWaitEvent(b->qaux[1], b->qev[0], 0));
+    HIPCHK(hipStreamWaitEvent(b->qaux[2], b->qev[0], 0));
     // at most 2^24 items per launch, so that items x lanes stays below the
     // 2^32 work-items of one launch
     constexpr int kMaxItems = 1 << 24;
     for (const eri_batch::QGroup &q : b->qg) {
         const bool jeng = std::strncmp(q.kind, "jeng", 4) == 0;
-        const bool kside = std::strcmp(q.kind, "k_small") == 0 || std::strcmp(q.kind, "k_pair") == 0;
-        const hipStream_t s = jeng ? b->qaux[0] : (kside ? b->qaux[1] : st);
+        const hipStream_t s = jeng ? b->qaux[0]
+                              : std::strcmp(q.kind, "k_small") == 0 ? b->qaux[1]
+                              : std::strcmp(q.kind, "k_pair") == 0  ? b->qaux[2]
+                                                                    : st;
         for (int off = 0; off < q.nitems; off += kMaxItems)
             q.fn(b->d_qtab.p + q.tab_off, b->d_qitems.p + q.item_off + off, std::min(kMaxItems, q.nitems - off), s);
     }
     HIPCHK(hipEventRecord(b->qev[1], b->qaux[0]));
     HIPCHK(hipEventRecord(b->qev[2], b->qaux[1]));
+    HIPCHK(hipEventRecord(b->qev[3], b->qaux[2]));
     HIPCHK(hipStreamWaitEvent(st, b->qev[1], 0));
     HIPCHK(hipStreamWaitEvent(st, b->qev[2], 0));
+    HIPCHK(hipStreamWaitEvent(st, b->qev[3], 0));
     for (const int i : b->order) {
         eri_ctx *c = b->ctxs[(size_t)i];
         const bool prof = c->profile;
