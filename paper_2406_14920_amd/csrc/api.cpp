@@ -1272,12 +1272,24 @@ void run_grad(eri_ctx *c, double *grad)
         launch_density_bounds(c->wk.Pc, nc, c->d_l.p, c->d_coff.p, c->nshell, c->d_Pm.p, c->d_cp.p, c->d_Q.p,
                               (int)c->cp.size(), c->d_QD.p, st);
     }
+    // The Coulomb part runs on one internal stream and the exchange classes
+    // are spread over the context stream and two more (each class writes
+    // partials of its own, reduced in a fixed order at the end, so the
+    // result does not depend on the interleaving); joined back before the
+    // reduction.  While profiling, everything stays on the context stream.
+    const bool fork = !c->profile && !c->recording;
+    const hipStream_t sJ = fork ? c->aux[0] : st;
+    const hipStream_t sK[3] = {st, fork ? c->aux[1] : st, fork ? c->aux[2] : st};
+    if (fork) {
+        HIPCHK(hipEventRecord(c->ev_fork, st));
+        for (const hipStream_t s : {c->aux[0], c->aux[1], c->aux[2]}) HIPCHK(hipStreamWaitEvent(s, c->ev_fork, 0));
+    }
     // Coulomb: Hermite density, J-engine with the bra order raised by one
     for (int Y = 0; Y < kPairClasses; ++Y)
         launch_hermite_density(kPairL[Y][0], kPairL[Y][1], c->d_cp.p + c->cp_base[Y], c->ncp[Y], c->d_pp.p,
                                c->wk.Pc, nc, c->wk.Dt + c->dt_off[Y], mixed ? c->d_Dtf.p + c->dt_off[Y] : nullptr,
-                               c->pp_base[Y], st);
-    launch_fill_zero(c->d_Jh1.p, (int64_t)c->d_Jh1.n, st);
+                               c->pp_base[Y], sJ);
+    launch_fill_zero(c->d_Jh1.p, (int64_t)c->d_Jh1.n, sJ);
     for (int X = 0; X < kPairClasses; ++X) {
         if (c->npp[X] == 0) continue;
         for (int Y = 0; Y < kPairClasses; ++Y) {
@@ -1294,16 +1306,16 @@ void run_grad(eri_ctx *c, double *grad)
             const bool split = mixed && lx <= 6 && (prec == ERI_MIXED_ALL || c->jsplit[X][Y]);
             for (int part = split ? 1 : 0; part <= (split ? 2 : 0); ++part) {
                 a.mode = part;
-                timed(c, st,
+                timed(c, sJ,
                       cls_name("jeng_grad", kPairL[X][0], kPairL[X][1], kPairL[Y][0], kPairL[Y][1]) +
                           (part == 0 ? "" : (part == 1 ? "/d" : "/s")),
                       -1, 0, 0, [&] {
-                          if (!launch_jeng(lx, ly, a, part == 2, st)) {
+                          if (!launch_jeng(lx, ly, a, part == 2, sJ)) {
                               set_err(ERI_ESTATE, "no J-engine kernel for orders (%d,%d)", lx, ly);
                               throw HipError{ERI_ESTATE};
                           }
                           launch_jh_reduce(c->d_jhpart.p, nch, a.jh_part, c->d_Jh1.p + c->jh1_off[X], a.jh_part,
-                                           st);
+                                           sJ);
                       });
             }
         }
@@ -1318,13 +1330,19 @@ void run_grad(eri_ctx *c, double *grad)
         g.D = c->wk.Pc;
         g.ld = nc;
         g.pg = c->d_pg.p + 6 * (size_t)c->cp_base[X];
-        timed(c, st, cls_name("jgrad", kPairL[X][0], kPairL[X][1], 0, 0), -1, 0, 0,
-              [&] { launch_jgrad(kPairL[X][0], kPairL[X][1], g, st); });
+        timed(c, sJ, cls_name("jgrad", kPairL[X][0], kPairL[X][1], 0, 0), -1, 0, 0,
+              [&] { launch_jgrad(kPairL[X][0], kPairL[X][1], g, sJ); });
     }
-    // exchange: every canonical quartet, all four centres
+    // exchange: every canonical quartet, all four centres; each class goes,
+    // in class order, to the stream with the least model work so far
+    double load[3] = {0.0, 0.0, 0.0};
     for (size_t wi = 0; wi < c->kwork.size(); ++wi) {
         const auto &w = c->kwork[wi];
         if (w.nwork == 0) continue;
+        int si = 0;
+        for (int k = 1; k < 3; ++k)
+            if (load[k] < load[si]) si = k;
+        const hipStream_t sk = sK[si];
         KGArgs g{};
         g.k = k_args(c, w, false);
         g.partial = c->d_kpart.p + (size_t)c->kg_off[wi] * 3 * c->natom;
@@ -1332,13 +1350,21 @@ void run_grad(eri_ctx *c, double *grad)
         const int la = kPairL[w.X][0], lb = kPairL[w.X][1], lc = kPairL[w.Y][0], ld = kPairL[w.Y][1];
         const int nb = c->kg_blocks[wi];
         bool ok = false;
-        timed(c, st, cls_name("kgrad", la, lb, lc, ld), -1, 0, 0, [&] {
-            ok = launch_kg_0(la, lb, lc, ld, g, nb, st) || launch_kg_1(la, lb, lc, ld, g, nb, st) ||
-                 launch_kg_2(la, lb, lc, ld, g, nb, st) || launch_kg_3(la, lb, lc, ld, g, nb, st);
+        timed(c, sk, cls_name("kgrad", la, lb, lc, ld), -1, 0, 0, [&] {
+            ok = launch_kg_0(la, lb, lc, ld, g, nb, sk) || launch_kg_1(la, lb, lc, ld, g, nb, sk) ||
+                 launch_kg_2(la, lb, lc, ld, g, nb, sk) || launch_kg_3(la, lb, lc, ld, g, nb, sk);
         });
         if (!ok) {
             set_err(ERI_ESTATE, "no exchange-gradient kernel for class (%d%d|%d%d)", la, lb, lc, ld);
             throw HipError{ERI_ESTATE};
+        }
+        const double prim = wi < c->kprim.size() ? (double)c->kprim[wi] : (double)w.nwork;
+        load[si] += prim * fl_k_prim(la, lb, lc, ld) + (double)w.nwork * fl_k_digest(la, lb, lc, ld);
+    }
+    if (fork) {
+        for (int k = 0; k < 3; ++k) {
+            HIPCHK(hipEventRecord(c->ev_join[k], c->aux[k]));
+            HIPCHK(hipStreamWaitEvent(st, c->ev_join[k], 0));
         }
     }
     const size_t nred = (size_t)grad_reduce_chunks((int)c->cp.size(), c->kg_total) * 3 * c->natom;
