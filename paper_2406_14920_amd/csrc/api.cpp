@@ -307,6 +307,7 @@ struct eri_ctx {
     bool grid_ready = false;
     DevBuf<double> d_xyz;
     DevBuf<double4> d_psph, d_bsph;
+    DevBuf<double> d_gpart;  // per-stream density partials of eri_grid_density
     DevBuf<double> d_Jh1, d_pg, d_kpart, d_Jtmp, d_Ktmp, d_jhpart;
     DevBuf<double> d_gred;  // chunk sums of the fixed-order gradient reduction
     int gchunk[kPairClasses][kPairClasses] = {};  // J-engine ket chunk of the gradient launches
@@ -1819,12 +1820,47 @@ int eri_grid_density(eri_ctx *ctx, const double *P, const double *pts, int64_t n
         grid_prepare(ctx, pts, npts);
         launch_fill_zero(rho, npts, st);
         if (grad) launch_fill_zero(grad, 3 * npts, st);
-        for (int X = 0; X < kPairClasses; ++X)
-            timed(ctx, st, cls_name("grid_rho", kPairL[X][0], kPairL[X][1], 0, 0), -1, 0, 0, [&] {
+        // The pair classes add into the points class by class.  They run on
+        // the context stream (into rho, grad) and three internal ones (each
+        // into a zeroed partial of its own), each class to the stream with
+        // the least pair work so far; after the join the partials are added
+        // in stream order, so the result is reproducible bit for bit.  Not
+        // forked while profiling, or when the partials would pass 1 GiB.
+        const int64_t w = grad ? 4 : 1;  // doubles per point
+        const bool fork = !ctx->profile && !ctx->recording && 3 * w * npts * (int64_t)sizeof(double) <= (1ll << 30);
+        double *part = nullptr;
+        if (fork) {
+            if (ctx->d_gpart.n < (size_t)(3 * w * npts)) ctx->d_gpart.alloc((size_t)(3 * w * npts));
+            part = ctx->d_gpart.p;
+            launch_fill_zero(part, 3 * w * npts, st);
+            HIPCHK(hipEventRecord(ctx->ev_fork, st));
+            for (int k = 0; k < 3; ++k) HIPCHK(hipStreamWaitEvent(ctx->aux[k], ctx->ev_fork, 0));
+        }
+        double load[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int X = 0; X < kPairClasses; ++X) {
+            if (ctx->ncp[X] == 0) continue;
+            int si = 0;
+            if (fork)
+                for (int k = 1; k < 4; ++k)
+                    if (load[k] < load[si]) si = k;
+            load[si] += (double)ctx->ncp[X] * ncart(kPairL[X][0]) * ncart(kPairL[X][1]);
+            const hipStream_t sg = si == 0 ? st : ctx->aux[si - 1];
+            double *r = si == 0 ? rho : part + (int64_t)(si - 1) * npts;
+            double *g = !grad ? nullptr : (si == 0 ? grad : part + 3 * npts + (int64_t)(si - 1) * 3 * npts);
+            timed(ctx, sg, cls_name("grid_rho", kPairL[X][0], kPairL[X][1], 0, 0), -1, 0, 0, [&] {
                 launch_grid_rho(kPairL[X][0], kPairL[X][1], ctx->d_cp.p + ctx->cp_base[X], ctx->ncp[X], ctx->d_pp.p,
                                 ctx->d_psph.p + ctx->cp_base[X], ctx->d_xyz.p, ctx->wk.Pc, nc, pts, npts,
-                                ctx->d_bsph.p, rho, grad, st);
+                                ctx->d_bsph.p, r, g, sg);
             });
+        }
+        if (fork) {
+            for (int k = 0; k < 3; ++k) {
+                HIPCHK(hipEventRecord(ctx->ev_join[k], ctx->aux[k]));
+                HIPCHK(hipStreamWaitEvent(st, ctx->ev_join[k], 0));
+            }
+            launch_jh_reduce(part, 3, npts, rho, npts, st);
+            if (grad) launch_jh_reduce(part + 3 * npts, 3, 3 * npts, grad, 3 * npts, st);
+        }
         HIPCHK(hipGetLastError());
     } catch (const HipError &e) {
         return e.code;
@@ -1846,12 +1882,38 @@ int eri_grid_matrix(eri_ctx *ctx, const double *pts, int64_t npts, const double 
         launch_fill_zero(ctx->wk.Jacc, (int64_t)nc * nc, st);
         if (npts > 0) {
             grid_prepare(ctx, pts, npts);
-            for (int X = 0; X < kPairClasses; ++X)
-                timed(ctx, st, cls_name("grid_vmat", kPairL[X][0], kPairL[X][1], 0, 0), -1, 0, 0, [&] {
+            // every contracted pair stores its own block, so the pair classes
+            // run concurrently on the context stream and three internal ones
+            // (each class to the stream with the least pair-block work so
+            // far), joined back before the output transform; while
+            // profiling, everything stays on the context stream
+            const bool fork = !ctx->profile && !ctx->recording;
+            const hipStream_t ss[4] = {st, fork ? ctx->aux[0] : st, fork ? ctx->aux[1] : st,
+                                       fork ? ctx->aux[2] : st};
+            if (fork) {
+                HIPCHK(hipEventRecord(ctx->ev_fork, st));
+                for (int k = 0; k < 3; ++k) HIPCHK(hipStreamWaitEvent(ctx->aux[k], ctx->ev_fork, 0));
+            }
+            double load[4] = {0.0, 0.0, 0.0, 0.0};
+            for (int X = 0; X < kPairClasses; ++X) {
+                if (ctx->ncp[X] == 0) continue;
+                int si = 0;
+                for (int k = 1; k < 4; ++k)
+                    if (load[k] < load[si]) si = k;
+                const hipStream_t sg = ss[si];
+                load[si] += (double)ctx->ncp[X] * ncart(kPairL[X][0]) * ncart(kPairL[X][1]);
+                timed(ctx, sg, cls_name("grid_vmat", kPairL[X][0], kPairL[X][1], 0, 0), -1, 0, 0, [&] {
                     launch_grid_vmat(kPairL[X][0], kPairL[X][1], ctx->d_cp.p + ctx->cp_base[X], ctx->ncp[X],
                                      ctx->d_pp.p, ctx->d_psph.p + ctx->cp_base[X], ctx->d_xyz.p, pts, npts,
-                                     ctx->d_bsph.p, v0, v1, ctx->wk.Jacc, nc, st);
+                                     ctx->d_bsph.p, v0, v1, ctx->wk.Jacc, nc, sg);
                 });
+            }
+            if (fork) {
+                for (int k = 0; k < 3; ++k) {
+                    HIPCHK(hipEventRecord(ctx->ev_join[k], ctx->aux[k]));
+                    HIPCHK(hipStreamWaitEvent(st, ctx->ev_join[k], 0));
+                }
+            }
         }
         launch_acc_to_out(ctx->wk.Jacc, nc, V, ctx->nbf, shell_map(ctx), ctx->opts.spherical, st);
         HIPCHK(hipGetLastError());
